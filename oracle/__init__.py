@@ -1,0 +1,140 @@
+"""CPU oracle for exact triangle counting. TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package. The GPU library never imports, links or
+calls it, and it imports nothing from the GPU package: the two share no code.
+
+Contents
+  * ``tc_oracle.cpp`` (built into ``liboracle.so``): the forward algorithm and
+    definition-level per-vertex / per-edge counts; see that file's header.
+  * ``dense``: brute force over vertex triples, trace(A^3)/6 and the matrix
+    formulation (Algorithm 3) on dense matrices, for small graphs.
+  * ``stages``: plain numpy definitions of the intermediate products of the
+    GPU pipeline (canonical simple graph, degree-rank order, oriented CSR,
+    per-edge buckets), for stage-level parity.
+  * ``mlp``: float64 numpy forward/backward of the kernel-selector MLP.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+ORDER_DEG_ID = 0     # (degree, id) ascending
+ORDER_PAPER = 1      # degree descending, id ascending (the paper's literal filter)
+ORDER_ID = 2         # plain id order
+
+
+def build() -> str:
+    """Compile tc_oracle.cpp into liboracle.so (g++ -O3, OpenMP)."""
+    src = os.path.join(_HERE, "tc_oracle.cpp")
+    tmp = _SO + ".tmp"
+    subprocess.check_call(["g++", "-O3", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", tmp, src])
+    os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    lib = ctypes.CDLL(_SO)
+    vp = ctypes.c_void_p
+    lib.oracle_graph_build.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(vp)]
+    lib.oracle_graph_build.restype = ctypes.c_int
+    lib.oracle_graph_free.argtypes = [vp]
+    lib.oracle_graph_num_edges.argtypes = [vp]
+    lib.oracle_graph_num_edges.restype = ctypes.c_int64
+    lib.oracle_graph_edges.argtypes = [vp, vp]
+    lib.oracle_graph_degrees.argtypes = [vp, vp]
+    lib.oracle_count_forward.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
+    lib.oracle_count_forward.restype = ctypes.c_uint64
+    lib.oracle_vertex_triangles.argtypes = [vp, vp, ctypes.c_int64, vp, ctypes.c_int]
+    lib.oracle_oriented_edge_counts.argtypes = [vp, vp, ctypes.c_int]
+    lib.oracle_edge_support.argtypes = [vp, vp, ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+class VertexRangeError(ValueError):
+    pass
+
+
+class Graph:
+    """The simple undirected graph denoted by an edge list (loops dropped, repeats merged)."""
+
+    def __init__(self, edges: np.ndarray, n: int, threads: int = 0):
+        e = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+        self.n = int(n)
+        self.threads = threads
+        lib = _load()
+        h = ctypes.c_void_p()
+        st = lib.oracle_graph_build(e.ctypes.data if e.size else None, e.shape[0], self.n, threads,
+                                    ctypes.byref(h))
+        if st == 2:
+            raise VertexRangeError("vertex id outside [0, n)")
+        if st != 0:
+            raise ValueError("invalid argument")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _load().oracle_graph_free(h)
+            self._h = None
+
+    @property
+    def m(self) -> int:
+        return int(_load().oracle_graph_num_edges(self._h))
+
+    def edges(self) -> np.ndarray:
+        out = np.empty((self.m, 2), dtype=np.int32)
+        if self.m:
+            _load().oracle_graph_edges(self._h, out.ctypes.data)
+        return out
+
+    def degrees(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.int32)
+        if self.n:
+            _load().oracle_graph_degrees(self._h, out.ctypes.data)
+        return out
+
+    def count(self, order: int = ORDER_DEG_ID, per_vertex: bool = False):
+        """Forward algorithm. Returns T, or (T, t) with per_vertex."""
+        t = np.zeros(self.n, dtype=np.uint64) if per_vertex else None
+        T = int(_load().oracle_count_forward(self._h, order, t.ctypes.data if per_vertex and self.n else None,
+                                             self.threads))
+        return (T, t) if per_vertex else T
+
+    def vertex_triangles(self, vs) -> np.ndarray:
+        vs = np.ascontiguousarray(vs, dtype=np.int32)
+        out = np.zeros(vs.shape[0], dtype=np.uint64)
+        if vs.size:
+            _load().oracle_vertex_triangles(self._h, vs.ctypes.data, vs.shape[0], out.ctypes.data, self.threads)
+        return out
+
+    def oriented_edge_counts(self) -> np.ndarray:
+        out = np.zeros(self.m, dtype=np.uint32)
+        if self.m:
+            _load().oracle_oriented_edge_counts(self._h, out.ctypes.data, self.threads)
+        return out
+
+    def edge_support(self) -> np.ndarray:
+        out = np.zeros(self.m, dtype=np.uint32)
+        if self.m:
+            _load().oracle_edge_support(self._h, out.ctypes.data, self.threads)
+        return out
+
+
+def count_triangles(edges: np.ndarray, n: int, per_vertex: bool = False, threads: int = 0,
+                    order: int = ORDER_DEG_ID):
+    """T (and t[v] with per_vertex) of the simple graph denoted by ``edges``."""
+    return Graph(edges, n, threads).count(order=order, per_vertex=per_vertex)

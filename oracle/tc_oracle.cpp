@@ -1,0 +1,272 @@
+/*
+ * CPU oracle for exact triangle counting. TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the tests, the package's smoke check and the benchmark's CPU-baseline
+ * leg may load this library. It shares no code, header or helper with the GPU
+ * library: it is a plain, slow, obviously correct restatement of what the
+ * paper's method computes, in the paper's order of steps.
+ *
+ * Problem (Section 3): exact triangle count of an undirected simple graph.
+ * Input pairs are unordered; self-loops are dropped and repeated pairs count
+ * once (the dataset table of Section 5 counts de-duplicated edges).
+ *
+ *   T    = number of vertex triples {a,b,c} with all three edges present
+ *   t[v] = number of triangles that contain v
+ *
+ * Functions:
+ *  - oracle_count_forward: the forward algorithm (Section 3.2, "TC using set
+ *    intersection", Algorithm 2; orientation by degree order, Section 4.2):
+ *    keep each edge once, directed along a strict total order of the
+ *    vertices, and intersect the two out-neighbour lists of every kept edge.
+ *  - oracle_vertex_triangles: t[v] by definition, the number of edges among
+ *    the neighbours of v. Written independently of the forward algorithm.
+ *  - oracle_oriented_edge_counts: per kept edge (a -> b), the number of
+ *    common neighbours w that follow both a and b in the (degree, id) order.
+ *    This is the per-edge intersection size of Section 3.2.
+ *  - oracle_edge_support: per edge, the number of triangles through it
+ *    (the per-edge triangle support used by k-truss, Section 1).
+ *
+ * Integers only; every count is accumulated in uint64_t, so there is no
+ * rounding anywhere.
+ */
+#include <omp.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+#include <algorithm>
+#include <parallel/algorithm>
+#include <vector>
+
+namespace {
+
+struct Graph {
+    int32_t n = 0;
+    int64_t m = 0;
+    std::vector<uint64_t> keys;       // canonical pairs (min << 32 | max), sorted, unique
+    std::vector<int32_t> deg;         // degree in the simple graph
+    std::vector<int64_t> adj_off;     // symmetric adjacency, rows sorted by id
+    std::vector<int32_t> adj;
+};
+
+int pick_threads(int threads) { return threads > 0 ? threads : omp_get_max_threads(); }
+
+// (degree, id) ascending: the strict total order used to orient edges.
+inline bool precedes_deg_id(const Graph& g, int32_t a, int32_t b) {
+    return g.deg[a] < g.deg[b] || (g.deg[a] == g.deg[b] && a < b);
+}
+// The paper's literal filter keeps e(u,v) with d(u) > d(v), ties to the
+// smaller id: degree descending, id ascending.
+inline bool precedes_paper(const Graph& g, int32_t a, int32_t b) {
+    return g.deg[a] > g.deg[b] || (g.deg[a] == g.deg[b] && a < b);
+}
+inline bool precedes(const Graph& g, int mode, int32_t a, int32_t b) {
+    if (mode == 1) return precedes_paper(g, a, b);
+    if (mode == 2) return a < b;
+    return precedes_deg_id(g, a, b);
+}
+
+// Size of the intersection of two ascending lists (two-pointer merge).
+inline uint64_t merge_count(const int32_t* a, int64_t na, const int32_t* b, int64_t nb) {
+    uint64_t c = 0;
+    int64_t i = 0, j = 0;
+    while (i < na && j < nb) {
+        if (a[i] < b[j]) ++i;
+        else if (a[i] > b[j]) ++j;
+        else { ++c; ++i; ++j; }
+    }
+    return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+/* Status codes: 0 ok, 1 invalid argument, 2 vertex id outside [0, n). */
+int oracle_graph_build(const int32_t* edges, int64_t num_edges, int32_t n, int threads, void** out) {
+    if (!out || num_edges < 0 || n < 0 || (num_edges > 0 && !edges)) return 1;
+    *out = nullptr;
+    for (int64_t i = 0; i < 2 * num_edges; ++i)
+        if (edges[i] < 0 || edges[i] >= n) return 2;
+    Graph* g = new Graph;
+    g->n = n;
+    // Canonicalise: unordered pair -> (min, max); self-loops dropped.
+    g->keys.reserve((size_t)num_edges);
+    for (int64_t i = 0; i < num_edges; ++i) {
+        uint32_t a = (uint32_t)edges[2 * i], b = (uint32_t)edges[2 * i + 1];
+        if (a == b) continue;
+        if (a > b) std::swap(a, b);
+        g->keys.push_back(((uint64_t)a << 32) | b);
+    }
+    // De-duplicate: sort, then keep one of each run of equal pairs.
+    omp_set_num_threads(pick_threads(threads));
+    __gnu_parallel::sort(g->keys.begin(), g->keys.end());
+    g->keys.erase(std::unique(g->keys.begin(), g->keys.end()), g->keys.end());
+    g->m = (int64_t)g->keys.size();
+    // Degrees and the symmetric adjacency (rows ascending by id).
+    g->deg.assign((size_t)n, 0);
+    for (uint64_t k : g->keys) { g->deg[k >> 32]++; g->deg[(uint32_t)k]++; }
+    g->adj_off.assign((size_t)n + 1, 0);
+    for (int32_t v = 0; v < n; ++v) g->adj_off[v + 1] = g->adj_off[v] + g->deg[v];
+    g->adj.resize((size_t)(2 * g->m));
+    std::vector<int64_t> fill(g->adj_off.begin(), g->adj_off.end() - 1);
+    for (uint64_t k : g->keys) {
+        int32_t a = (int32_t)(k >> 32), b = (int32_t)(uint32_t)k;
+        g->adj[fill[a]++] = b;
+        g->adj[fill[b]++] = a;
+    }
+#pragma omp parallel for schedule(dynamic, 1024) num_threads(pick_threads(threads))
+    for (int32_t v = 0; v < n; ++v)
+        std::sort(g->adj.begin() + g->adj_off[v], g->adj.begin() + g->adj_off[v + 1]);
+    *out = g;
+    return 0;
+}
+
+void oracle_graph_free(void* h) { delete (Graph*)h; }
+
+int64_t oracle_graph_num_edges(const void* h) { return ((const Graph*)h)->m; }
+
+/* Canonical pairs (a < b), ascending, as int32 [m][2]. */
+void oracle_graph_edges(const void* h, int32_t* out) {
+    const Graph* g = (const Graph*)h;
+    for (int64_t i = 0; i < g->m; ++i) {
+        out[2 * i] = (int32_t)(g->keys[i] >> 32);
+        out[2 * i + 1] = (int32_t)(uint32_t)g->keys[i];
+    }
+}
+
+void oracle_graph_degrees(const void* h, int32_t* out) {
+    const Graph* g = (const Graph*)h;
+    for (int32_t v = 0; v < g->n; ++v) out[v] = g->deg[v];
+}
+
+/*
+ * Forward algorithm (Section 3.2, Algorithm 2; filter of Section 4.2).
+ *   order_mode 0: orient along (degree, id) ascending (the reading used by
+ *                 the GPU path), 1: the paper's literal filter (degree
+ *                 descending, id ascending), 2: plain id order.
+ * Every strict total order finds each triangle exactly once, at the edge
+ * joining its two smallest vertices, so T and t do not depend on the mode.
+ * per_vertex (length n, may be NULL) receives t[v].
+ */
+uint64_t oracle_count_forward(const void* h, int order_mode, uint64_t* per_vertex, int threads) {
+    const Graph* g = (const Graph*)h;
+    const int32_t n = g->n;
+    // Form the filtered edge list: each edge once, from the earlier to the later endpoint.
+    std::vector<int64_t> off((size_t)n + 1, 0);
+    for (uint64_t k : g->keys) {
+        int32_t a = (int32_t)(k >> 32), b = (int32_t)(uint32_t)k;
+        off[(precedes(*g, order_mode, a, b) ? a : b) + 1]++;
+    }
+    for (int32_t v = 0; v < n; ++v) off[v + 1] += off[v];
+    std::vector<int32_t> out_adj((size_t)g->m);
+    std::vector<int64_t> fill(off.begin(), off.end() - 1);
+    for (uint64_t k : g->keys) {
+        int32_t a = (int32_t)(k >> 32), b = (int32_t)(uint32_t)k;
+        if (precedes(*g, order_mode, a, b)) out_adj[fill[a]++] = b;
+        else out_adj[fill[b]++] = a;
+    }
+    // Out-lists sorted by vertex id (keys are ascending, but sort to be explicit).
+#pragma omp parallel for schedule(dynamic, 1024) num_threads(pick_threads(threads))
+    for (int32_t v = 0; v < n; ++v) std::sort(out_adj.begin() + off[v], out_adj.begin() + off[v + 1]);
+    if (per_vertex)
+        for (int32_t v = 0; v < n; ++v) per_vertex[v] = 0;
+    // Intersect the two out-lists of every kept edge; reduce the counts.
+    uint64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : total) num_threads(pick_threads(threads))
+    for (int32_t u = 0; u < n; ++u) {
+        const int32_t* nu = out_adj.data() + off[u];
+        const int64_t du = off[u + 1] - off[u];
+        for (int64_t p = 0; p < du; ++p) {
+            int32_t v = nu[p];
+            const int32_t* nv = out_adj.data() + off[v];
+            const int64_t dv = off[v + 1] - off[v];
+            if (!per_vertex) {
+                total += merge_count(nu, du, nv, dv);
+                continue;
+            }
+            int64_t i = 0, j = 0;
+            while (i < du && j < dv) {
+                if (nu[i] < nv[j]) ++i;
+                else if (nu[i] > nv[j]) ++j;
+                else {
+                    ++total;
+#pragma omp atomic
+                    per_vertex[u]++;
+#pragma omp atomic
+                    per_vertex[v]++;
+#pragma omp atomic
+                    per_vertex[nu[i]]++;
+                    ++i; ++j;
+                }
+            }
+        }
+    }
+    return total;
+}
+
+/*
+ * t[v] for the k vertices vs[0..k): by definition, the number of edges whose
+ * two endpoints are both neighbours of v. Neighbours of v are marked in a
+ * byte map; each edge {a,b} with a, b in N(v) is seen twice (from a and b).
+ */
+void oracle_vertex_triangles(const void* h, const int32_t* vs, int64_t k, uint64_t* out, int threads) {
+    const Graph* g = (const Graph*)h;
+#pragma omp parallel num_threads(pick_threads(threads))
+    {
+        std::vector<uint8_t> mark((size_t)g->n, 0);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t q = 0; q < k; ++q) {
+            int32_t v = vs[q];
+            for (int64_t p = g->adj_off[v]; p < g->adj_off[v + 1]; ++p) mark[g->adj[p]] = 1;
+            uint64_t twice = 0;
+            for (int64_t p = g->adj_off[v]; p < g->adj_off[v + 1]; ++p) {
+                int32_t a = g->adj[p];
+                for (int64_t r = g->adj_off[a]; r < g->adj_off[a + 1]; ++r) twice += mark[g->adj[r]];
+            }
+            for (int64_t p = g->adj_off[v]; p < g->adj_off[v + 1]; ++p) mark[g->adj[p]] = 0;
+            out[q] = twice / 2;
+        }
+    }
+}
+
+/*
+ * Per-edge intersection sizes for the (degree, id) orientation. For the
+ * canonical pair i (a < b, ascending order of oracle_graph_edges), out[i] =
+ * |{ w : w ~ a, w ~ b, a < w and b < w in (degree, id) order }|, the size of
+ * N+(x) intersected with N+(y) for the kept edge x -> y on {a, b}.
+ */
+void oracle_oriented_edge_counts(const void* h, uint32_t* out, int threads) {
+    const Graph* g = (const Graph*)h;
+#pragma omp parallel for schedule(dynamic, 4096) num_threads(pick_threads(threads))
+    for (int64_t i = 0; i < g->m; ++i) {
+        int32_t a = (int32_t)(g->keys[i] >> 32), b = (int32_t)(uint32_t)g->keys[i];
+        const int32_t* na = g->adj.data() + g->adj_off[a];
+        const int32_t* nb = g->adj.data() + g->adj_off[b];
+        int64_t da = g->adj_off[a + 1] - g->adj_off[a], db = g->adj_off[b + 1] - g->adj_off[b];
+        uint32_t c = 0;
+        int64_t x = 0, y = 0;
+        while (x < da && y < db) {
+            if (na[x] < nb[y]) ++x;
+            else if (na[x] > nb[y]) ++y;
+            else {
+                int32_t w = na[x];
+                if (precedes_deg_id(*g, a, w) && precedes_deg_id(*g, b, w)) ++c;
+                ++x; ++y;
+            }
+        }
+        out[i] = c;
+    }
+}
+
+/* Per-edge triangle support |N(a) intersected with N(b)| for canonical pair i. */
+void oracle_edge_support(const void* h, uint32_t* out, int threads) {
+    const Graph* g = (const Graph*)h;
+#pragma omp parallel for schedule(dynamic, 4096) num_threads(pick_threads(threads))
+    for (int64_t i = 0; i < g->m; ++i) {
+        int32_t a = (int32_t)(g->keys[i] >> 32), b = (int32_t)(uint32_t)g->keys[i];
+        out[i] = (uint32_t)merge_count(g->adj.data() + g->adj_off[a], g->adj_off[a + 1] - g->adj_off[a],
+                                       g->adj.data() + g->adj_off[b], g->adj_off[b + 1] - g->adj_off[b]);
+    }
+}
+
+}  // extern "C"
