@@ -1,0 +1,190 @@
+#!/usr/bin/env python
+"""Benchmark: exact triangle counting on one MI355X.
+
+One step = one full pass of the counting path over one resident graph:
+validate/canonicalise, degree order, orient, radix sort -> CSR, de-duplicate,
+degree-pair buckets, kernel selection, tiles, intersection, reduction, count
+read back to the host. The input edge list is in HBM before timing starts.
+
+Default workload: R-MAT scale 20, edge factor 16 (a, b, c, d = 0.57, 0.19, 0.19,
+0.05), 16,777,216 raw draws over 1,048,576 vertices (random vertex permutation,
+random direction); the counted graph is its symmetrised, loop-free,
+de-duplicated version. Metric: Gedges/s = m / step time, m = unique undirected
+edges (= oriented edges intersected).
+
+Prints one JSON line (rank 0).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "rmat20": dict(kind="rmat", scale=20, edge_factor=16, seed=1),
+    "rmat18": dict(kind="rmat", scale=18, edge_factor=16, seed=1),
+    "rmat22": dict(kind="rmat", scale=22, edge_factor=16, seed=1),
+    "rmat24": dict(kind="rmat", scale=24, edge_factor=16, seed=1),
+    "er4096": dict(kind="er", n=4096, m=32768, seed=1804),
+    "rgg23": dict(kind="rgg", n=1 << 23, avg_degree=32.0, seed=5),
+}
+
+
+def make_graph(name):
+    import graphgen
+    w = WORKLOADS[name]
+    if w["kind"] == "rmat":
+        return graphgen.rmat(w["scale"], w["edge_factor"], seed=w["seed"]), 1 << w["scale"], w
+    if w["kind"] == "er":
+        return graphgen.erdos_renyi(w["n"], w["m"], seed=w["seed"]), w["n"], w
+    return graphgen.rgg(w["n"], w["avg_degree"], seed=w["seed"]), w["n"], w
+
+
+def algorithmic_bytes(tc, d_edges, n, stats):
+    """Compulsory global reads of each intersection kernel for this graph.
+
+    Per in-edge e = (u -> v) with a non-empty tail: 8 B (its entry) + 4 B per
+    tail element; per tile (v, chunk of in-edges): 16 B of descriptors and
+    offsets + 4 B per element of N+(v). The same figure holds for every
+    strategy (each must read the tail and N+(v) at least once).
+    """
+    import numpy as np
+    rank, off, col = tc.build_csr(d_edges, n)
+    off = off.cpu().numpy().astype(np.int64)
+    col = col.cpu().numpy().astype(np.int64)
+    m = col.shape[0]
+    dplus = np.diff(off)
+    src = np.repeat(np.arange(n, dtype=np.int64), dplus)
+    tail = off[src + 1] - np.arange(m) - 1
+    active = (tail > 0) & (dplus[col] > 0)
+    din = np.bincount(col[active], minlength=n)
+    li = np.minimum(14, np.floor(np.log2(np.maximum(din, 1)))).astype(np.int64)
+    lo = np.minimum(15, np.floor(np.log2(np.maximum(dplus, 1)))).astype(np.int64)
+    bucket = np.where((din > 0) & (dplus > 0), 16 * li + lo, 255)
+    kern = np.asarray(stats["bucket_kernel"], dtype=np.int64)[bucket]
+    chunk = np.asarray(stats["bucket_chunk"], dtype=np.int64)[bucket]
+    tiles = np.where(bucket != 255, (din + chunk - 1) // np.maximum(chunk, 1), 0)
+    out = {}
+    ek = kern[col[active]]
+    for k, name in enumerate(("merge", "bsearch", "bitmap")):
+        e_bytes = int((8 + 4 * tail[active][ek == k]).sum())
+        t_bytes = int((tiles[kern == k] * (16 + 4 * dplus[kern == k])).sum())
+        out[name] = e_bytes + t_bytes
+    S = int((dplus[col]).sum())
+    balg = 4 * (m + S) + 16 * m + 8 * (n + 1)   # merge-formulation minimum
+    return out, balg, int(tail[active].sum())
+
+
+def cpu_baseline(edges, n, m):
+    """The CPU oracle (forward algorithm, OpenMP) on the same graph, whole."""
+    import oracle
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    t0 = time.perf_counter()
+    g = oracle.Graph(edges, n, threads=threads)
+    T = g.count()
+    dt = time.perf_counter() - t0
+    return {"value": m / dt / 1e9, "unit": "Gedges/s", "cores": threads, "kind": "oracle",
+            "sample": f"whole graph (canonicalise + CSR + count), {dt:.2f} s", "T": T}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
+    ap.add_argument("--select", default="heuristic", choices=["heuristic", "learned", "merge", "bsearch", "bitmap"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the oracle equality check")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import __graft_entry__
+    __graft_entry__._ensure_built()
+    import paper_1804_06926_amd as tc
+
+    sel = {"heuristic": tc.SELECT_HEURISTIC, "learned": tc.SELECT_LEARNED, "merge": tc.FORCE_MERGE,
+           "bsearch": tc.FORCE_BSEARCH, "bitmap": tc.FORCE_BITMAP}[args.select]
+    print(f"[bench] workload={args.workload} generating", file=sys.stderr, flush=True)
+    edges, n, spec = make_graph(args.workload)
+    d_edges = torch.from_numpy(edges).to("cuda:0")
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        T = tc.count_triangles(d_edges, n, select=sel)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done T={T}", file=sys.stderr, flush=True)
+
+    stage_sum = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        T, st = tc.count_triangles(d_edges, n, select=sel, timing=True)
+        for k, v in st.items():
+            stage_sum[k] = stage_sum.get(k, 0.0) + v
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / max(args.steps, 1)
+    stages = {k: v / max(args.steps, 1) for k, v in stage_sum.items()}
+    stats = tc.last_stats("cuda:0")
+    m = stats["m"]
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step T={T} m={m}", file=sys.stderr, flush=True)
+
+    kbytes, balg, tail_sum = algorithmic_bytes(tc, d_edges, n, stats)
+    isect = {k: stages.get(f"isect_{k}", 0.0) for k in ("merge", "bsearch", "bitmap")}
+    dom = max(isect, key=isect.get)
+    dom_ms = isect[dom]
+    achieved = kbytes[dom] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    isect_ms = sum(isect.values())
+
+    result = {
+        "metric": "Gedges/s intersected (end to end, exact count)",
+        "value": m / (ms_per_step * 1e-3) / 1e9,
+        "unit": "Gedges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, **{k: v for k, v in spec.items() if k != "kind"},
+                   "generator": spec["kind"], "raw_pairs": int(edges.shape[0]), "n": n, "m": m,
+                   "triangles": T, "select": args.select},
+        "roofline": {"bound": "hbm", "kernel": f"k_isect_{dom}", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes": kbytes[dom], "avg_launch_ms": dom_ms},
+        "stages_ms": stages,
+        "intersect_gedges_per_s": m / (isect_ms * 1e-3) / 1e9 if isect_ms > 0 else None,
+        "tail_elements": tail_sum,
+        "effective_gbps_merge_formulation": balg / (isect_ms * 1e-3) / 1e9 if isect_ms > 0 else None,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cb = cpu_baseline(edges, n, m)
+        if not args.no_check:
+            assert cb["T"] == T, f"GPU count {T} != oracle {cb['T']}"
+        cb.pop("T")
+        result["cpu_baseline"] = cb
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,171 @@
+/*
+ * tc.h - exact triangle counting on one MI355X (gfx950), C ABI.
+ *
+ * The library implements the intersection-based formulation of exact
+ * triangle counting (Wang, Wang, Yang, Owens, "A Comparative Study on Exact
+ * Triangle Counting Algorithms on the GPU", HPGP 2016; Section 3.2 and
+ * Algorithm 2, with the edge-list optimisations of Section 4.2):
+ *   1. canonicalise the input pairs, drop self-loops and repeats;
+ *   2. keep every undirected edge once, directed from the lower to the higher
+ *      vertex in (degree, id) order (the degree filter of Section 4.2);
+ *   3. build the filtered CSR (the "induced subgraph" of Section 4.2) with a
+ *      device radix sort;
+ *   4. intersect the two out-neighbour lists of every kept edge; the sizes
+ *      sum to the triangle count (Algorithm 2, Reduce).
+ *
+ * Conventions for every entry point
+ *   - Pointers prefixed d_ are device pointers on the context's device;
+ *     h_ pointers are host pointers. The caller owns every buffer.
+ *   - Inputs are never modified. The library allocates no device memory per
+ *     call: scratch space is the caller's workspace, sized by
+ *     tc_workspace_size().
+ *   - Edge lists are int32 pairs, row-major [num_edges][2], in any order and
+ *     direction. Self-loops and repeated pairs are accepted and ignored.
+ *   - Every call returns a status. Host-detectable errors (null pointers,
+ *     negative sizes, small workspace) return before any launch. A vertex id
+ *     outside [0, num_vertices) is detected on the device and reported as
+ *     TC_ERR_VERTEX_RANGE after the stream is synchronised; outputs are
+ *     then left unspecified (host outputs are not written).
+ *   - Calls on one context are serialised on its stream; a context is not
+ *     thread-safe.
+ *   - Limits: num_vertices < 2^31, num_edges < 2^31.
+ */
+#ifndef TC_MI355X_TC_H
+#define TC_MI355X_TC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tc_status {
+    TC_OK = 0,
+    TC_ERR_INVALID_ARG = 1,   /* null pointer, negative size, bad option */
+    TC_ERR_VERTEX_RANGE = 2,  /* an edge names a vertex outside [0, num_vertices) */
+    TC_ERR_WORKSPACE = 3,     /* workspace smaller than tc_workspace_size() */
+    TC_ERR_HIP = 4,           /* a HIP runtime call failed; see tc_last_error() */
+    TC_ERR_UNSUPPORTED = 5    /* size beyond the documented limits */
+} tc_status;
+
+/* Which intersection strategy handles each degree-pair bucket. Every choice
+ * gives the same exact counts; only the time differs. */
+typedef enum tc_select {
+    TC_SELECT_HEURISTIC = 0,  /* fixed thresholds on the bucket's degrees */
+    TC_SELECT_LEARNED = 1,    /* the context's trained selector network */
+    TC_FORCE_MERGE = 2,       /* merge-path for every bucket */
+    TC_FORCE_BSEARCH = 3,     /* binary search for every bucket */
+    TC_FORCE_BITMAP = 4       /* LDS bitmap for every bucket */
+} tc_select;
+
+/* Option flags. */
+#define TC_F_STAGE_TIMING 0x1u  /* record per-stage times (tc_stage_times) */
+
+typedef struct tc_options {
+    int32_t select;           /* a tc_select value */
+    uint32_t flags;           /* TC_F_* bits */
+    int32_t reserved[6];      /* must be zero */
+} tc_options;
+
+typedef struct tc_ctx tc_ctx;
+
+/* Create a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream). */
+tc_status tc_create(tc_ctx** ctx, int device, void* hip_stream);
+tc_status tc_destroy(tc_ctx* ctx);
+
+/* Bytes of device workspace that a call with these sizes needs. The value
+ * depends only on the arguments, so one workspace serves every call with
+ * equal or smaller sizes. */
+tc_status tc_workspace_size(int64_t num_edges, int32_t num_vertices, const tc_options* opts, size_t* bytes);
+
+/*
+ * Exact triangle count T of the undirected simple graph denoted by the edge
+ * list (Algorithm 2: Count = Reduce(IntersectList)).
+ *   h_count       out: T (host).
+ *   d_per_vertex  out, optional (NULL): uint64[num_vertices], t[v] = number
+ *                 of triangles containing v (original ids).
+ */
+tc_status tc_count_triangles(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                             void* d_workspace, size_t workspace_bytes, const tc_options* opts,
+                             uint64_t* h_count, uint64_t* d_per_vertex);
+
+/*
+ * Per-edge intersection sizes (the IntersectList of Algorithm 2). For each
+ * kept edge (u -> v), u before v in (degree, id) order, writes
+ *   d_out_edges[i] = {u, v} (original ids) and
+ *   d_out_counts[i] = |N+(u) intersected with N+(v)|, the triangles whose two
+ *   lowest vertices are u and v.
+ * Edges come in CSR order (by rank of u, then rank of v). Capacity of both
+ * outputs: num_edges entries. h_num_out receives the number m of kept edges;
+ * h_count receives T (= sum of the counts).
+ */
+tc_status tc_edge_counts(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                         void* d_workspace, size_t workspace_bytes, const tc_options* opts,
+                         int32_t* d_out_edges, uint32_t* d_out_counts, int64_t* h_num_out, uint64_t* h_count);
+
+/*
+ * The filtered CSR of Section 4.2 ("induced subgraph"): vertices relabelled
+ * by rank in (degree, id) order, each undirected edge kept once from the
+ * lower to the higher rank, rows ascending.
+ *   d_rank     out: int32[num_vertices], rank of each original vertex.
+ *   d_offsets  out: int64[num_vertices + 1] row offsets over ranks.
+ *   d_col      out: int32[num_edges] capacity, column ranks.
+ *   h_num_out  out: number m of kept edges.
+ */
+tc_status tc_build_csr(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                       void* d_workspace, size_t workspace_bytes, const tc_options* opts, int32_t* d_rank,
+                       int64_t* d_offsets, int32_t* d_col, int64_t* h_num_out);
+
+/*
+ * The library's device radix sort (the CSR builder of step 3), exposed for
+ * reuse: stable ascending sort of `count` uint64 keys on bits [bit_lo,
+ * bit_hi), 8 bits per pass. d_keys holds the input and receives the result;
+ * d_keys_alt is caller scratch of the same size. Workspace: at least
+ * tc_radix_sort_workspace_size(count) bytes.
+ */
+size_t tc_radix_sort_workspace_size(int64_t count);
+tc_status tc_radix_sort_u64(tc_ctx* ctx, uint64_t* d_keys, uint64_t* d_keys_alt, int64_t count, int32_t bit_lo,
+                            int32_t bit_hi, void* d_workspace, size_t workspace_bytes);
+
+/*
+ * Work statistics of the last successful counting call on the context.
+ * Buckets are the degree-pair classes of the dynamic grouping (Section 4.2):
+ * for a middle vertex v with d_in in-edges whose tail is non-empty and
+ * d_out = |N+(v)|, bucket = 16 * min(14, floor(log2 d_in)) + min(15,
+ * floor(log2 d_out)); bucket 255 holds the vertices with no work.
+ */
+typedef struct tc_stats {
+    uint64_t num_edges_kept;          /* m: unique undirected edges */
+    uint64_t num_pairs_valid;         /* loop-free in-range input pairs */
+    uint32_t num_tiles;               /* intersection tiles */
+    uint32_t tile_begin[4];           /* tile range per strategy: merge, bsearch, bitmap */
+    uint32_t bucket_vertices[256];
+    uint64_t bucket_in_edges[256];
+    uint64_t bucket_out_edges[256];
+    uint64_t bucket_work[256];        /* sum over v of d_in(v) * d_out(v) */
+    uint8_t bucket_kernel[256];       /* 0 merge, 1 bsearch, 2 bitmap */
+    uint16_t bucket_chunk[256];       /* in-edges per tile */
+    uint8_t bucket_group[256];        /* lanes per in-edge (merge, bsearch) */
+} tc_stats;
+
+tc_status tc_last_stats(const tc_ctx* ctx, tc_stats* out);
+
+/*
+ * Per-stage device times (milliseconds) of the last call made with
+ * TC_F_STAGE_TIMING, and their names. Returns the number of stages written
+ * (at most `cap`).
+ */
+int32_t tc_stage_times(const tc_ctx* ctx, float* ms, int32_t cap);
+const char* tc_stage_name(int32_t stage);
+
+const char* tc_status_string(tc_status status);
+/* Text of the last error recorded on the context (empty if none). */
+const char* tc_last_error(const tc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_MI355X_TC_H */

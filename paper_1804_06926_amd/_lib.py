@@ -1,0 +1,265 @@
+"""ctypes binding of libtc_mi355x.so. Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(HERE, "libtc_mi355x.so")
+
+SELECT_HEURISTIC, SELECT_LEARNED, FORCE_MERGE, FORCE_BSEARCH, FORCE_BITMAP = 0, 1, 2, 3, 4
+F_STAGE_TIMING = 0x1
+
+_STATUS = {0: "ok", 1: "invalid argument", 2: "vertex id out of range", 3: "workspace too small",
+           4: "HIP runtime error", 5: "unsupported size"}
+
+_lib = None
+_lock = threading.Lock()
+_ctxs = {}          # (device, stream handle) -> tc_ctx*
+_workspaces = {}    # device -> uint8 tensor
+
+
+class TCError(RuntimeError):
+    def __init__(self, status: int, detail: str = ""):
+        self.status = status
+        msg = _STATUS.get(status, f"status {status}")
+        super().__init__(f"{msg}: {detail}" if detail else msg)
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("select", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 6)]
+
+
+def library_path() -> str:
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        raise RuntimeError(f"HIP library not built ({_SO}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(_SO)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sz = ctypes.c_size_t
+    lib.tc_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]
+    lib.tc_destroy.argtypes = [vp]
+    lib.tc_workspace_size.argtypes = [i64, i32, ctypes.POINTER(Options), ctypes.POINTER(sz)]
+    lib.tc_count_triangles.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options),
+                                       ctypes.POINTER(ctypes.c_uint64), vp]
+    lib.tc_edge_counts.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp,
+                                   ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_uint64)]
+    lib.tc_build_csr.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp, vp,
+                                 ctypes.POINTER(i64)]
+    lib.tc_radix_sort_workspace_size.argtypes = [i64]
+    lib.tc_radix_sort_workspace_size.restype = sz
+    lib.tc_radix_sort_u64.argtypes = [vp, vp, vp, i64, i32, i32, vp, sz]
+    lib.tc_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
+    lib.tc_stage_times.restype = i32
+    lib.tc_stage_name.argtypes = [i32]
+    lib.tc_stage_name.restype = ctypes.c_char_p
+    lib.tc_last_error.argtypes = [vp]
+    lib.tc_last_error.restype = ctypes.c_char_p
+    for f in ("tc_create", "tc_destroy", "tc_workspace_size", "tc_count_triangles", "tc_edge_counts",
+              "tc_build_csr", "tc_radix_sort_u64"):
+        getattr(lib, f).restype = ctypes.c_int
+    _ = u32
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ctx(device):
+    torch = _torch()
+    dev = torch.device(device)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    stream = torch.cuda.current_stream(idx).cuda_stream
+    key = (idx, stream)
+    with _lock:
+        h = _ctxs.get(key)
+        if h is None:
+            lib = _load()
+            p = ctypes.c_void_p()
+            st = lib.tc_create(ctypes.byref(p), idx, ctypes.c_void_p(stream))
+            if st != 0:
+                raise TCError(st, "tc_create")
+            h = p
+            _ctxs[key] = h
+    return h, idx
+
+
+def _check(st: int, ctx) -> None:
+    if st != 0:
+        detail = _load().tc_last_error(ctx).decode() if ctx else ""
+        raise TCError(st, detail)
+
+
+def _options(select: int, timing: bool) -> Options:
+    o = Options()
+    o.select = select
+    o.flags = F_STAGE_TIMING if timing else 0
+    return o
+
+
+def workspace_size(num_edges: int, num_vertices: int, select: int = SELECT_HEURISTIC) -> int:
+    out = ctypes.c_size_t()
+    o = _options(select, False)
+    st = _load().tc_workspace_size(num_edges, num_vertices, ctypes.byref(o), ctypes.byref(out))
+    _check(st, None)
+    return int(out.value)
+
+
+def _workspace(idx: int, nbytes: int, workspace=None):
+    torch = _torch()
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < nbytes:
+            raise TCError(3, "given workspace too small")
+        return workspace
+    ws = _workspaces.get(idx)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=f"cuda:{idx}")
+        _workspaces[idx] = ws
+    return ws
+
+
+def _edges_arg(edges):
+    torch = _torch()
+    if not (isinstance(edges, torch.Tensor) and edges.is_cuda):
+        raise TypeError("edges must be a CUDA (HIP) torch tensor")
+    if edges.dtype != torch.int32 or edges.dim() != 2 or edges.shape[1] != 2 or not edges.is_contiguous():
+        raise TypeError("edges must be a contiguous int32 tensor of shape [E, 2]")
+    return edges
+
+
+def _timings(ctx):
+    lib = _load()
+    buf = (ctypes.c_float * 32)()
+    k = lib.tc_stage_times(ctx, buf, 32)
+    return {lib.tc_stage_name(i).decode(): float(buf[i]) for i in range(k)}
+
+
+def stage_names():
+    lib = _load()
+    out, i = [], 0
+    while True:
+        s = lib.tc_stage_name(i).decode()
+        if not s:
+            return out
+        out.append(s)
+        i += 1
+
+
+def count_triangles(edges, num_vertices: int, per_vertex: bool = False, select: int = SELECT_HEURISTIC,
+                    workspace=None, timing: bool = False):
+    """Exact triangle count of the graph denoted by ``edges`` (int32 [E, 2] on the GPU).
+
+    Returns T (int), or (T, t) with per_vertex, t a uint64 tensor [num_vertices]
+    on the same device (int64 holding the uint64 t[v] = triangles containing v). With timing, a dict of
+    per-stage device milliseconds is appended to the result.
+    """
+    torch = _torch()
+    e = _edges_arg(edges)
+    ctx, idx = _ctx(e.device)
+    E = e.shape[0]
+    o = _options(select, timing)
+    nbytes = workspace_size(E, num_vertices, select)
+    ws = _workspace(idx, nbytes, workspace)
+    # t[v] < 2^63, so the uint64 results are held in an int64 tensor
+    pv = torch.empty(num_vertices, dtype=torch.int64, device=e.device) if per_vertex else None
+    count = ctypes.c_uint64()
+    st = _load().tc_count_triangles(ctx, e.data_ptr() if E else None, E, num_vertices, ws.data_ptr(),
+                                    ws.numel(), ctypes.byref(o), ctypes.byref(count),
+                                    pv.data_ptr() if pv is not None and num_vertices else None)
+    _check(st, ctx)
+    res = [int(count.value)]
+    if per_vertex:
+        res.append(pv)
+    if timing:
+        res.append(_timings(ctx))
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def edge_counts(edges, num_vertices: int, select: int = SELECT_HEURISTIC, workspace=None):
+    """Per-edge intersection sizes: (pairs int32 [m, 2] original ids (u before v), counts uint32 [m], T)."""
+    torch = _torch()
+    e = _edges_arg(edges)
+    ctx, idx = _ctx(e.device)
+    E = e.shape[0]
+    o = _options(select, False)
+    ws = _workspace(idx, workspace_size(E, num_vertices, select), workspace)
+    pairs = torch.empty((max(E, 1), 2), dtype=torch.int32, device=e.device)
+    counts = torch.empty(max(E, 1), dtype=torch.int32, device=e.device)   # uint32 counts < 2^31
+    m = ctypes.c_int64()
+    T = ctypes.c_uint64()
+    st = _load().tc_edge_counts(ctx, e.data_ptr() if E else None, E, num_vertices, ws.data_ptr(), ws.numel(),
+                                ctypes.byref(o), pairs.data_ptr(), counts.data_ptr(), ctypes.byref(m),
+                                ctypes.byref(T))
+    _check(st, ctx)
+    k = int(m.value)
+    return pairs[:k], counts[:k], int(T.value)
+
+
+def build_csr(edges, num_vertices: int, workspace=None):
+    """The degree-ordered CSR: (rank int32 [n], offsets int64 [n+1], col int32 [m])."""
+    torch = _torch()
+    e = _edges_arg(edges)
+    ctx, idx = _ctx(e.device)
+    E = e.shape[0]
+    o = _options(SELECT_HEURISTIC, False)
+    ws = _workspace(idx, workspace_size(E, num_vertices), workspace)
+    rank = torch.empty(max(num_vertices, 1), dtype=torch.int32, device=e.device)
+    off = torch.empty(num_vertices + 1, dtype=torch.int64, device=e.device)
+    col = torch.empty(max(E, 1), dtype=torch.int32, device=e.device)
+    m = ctypes.c_int64()
+    st = _load().tc_build_csr(ctx, e.data_ptr() if E else None, E, num_vertices, ws.data_ptr(), ws.numel(),
+                              ctypes.byref(o), rank.data_ptr(), off.data_ptr(), col.data_ptr(), ctypes.byref(m))
+    _check(st, ctx)
+    return rank[:num_vertices], off, col[:int(m.value)]
+
+
+def radix_sort_u64(keys, bit_lo: int = 0, bit_hi: int = 64):
+    """Sort a uint64 (or int64 bit-pattern) CUDA tensor in place on bits [bit_lo, bit_hi)."""
+    torch = _torch()
+    if not (isinstance(keys, torch.Tensor) and keys.is_cuda and keys.element_size() == 8 and keys.is_contiguous()):
+        raise TypeError("keys must be a contiguous 64-bit CUDA tensor")
+    ctx, idx = _ctx(keys.device)
+    n = keys.numel()
+    lib = _load()
+    nbytes = int(lib.tc_radix_sort_workspace_size(n))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=keys.device)
+    alt = torch.empty_like(keys)
+    st = lib.tc_radix_sort_u64(ctx, keys.data_ptr(), alt.data_ptr(), n, bit_lo, bit_hi, ws.data_ptr(), nbytes)
+    _check(st, ctx)
+    return keys
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("num_edges_kept", ctypes.c_uint64), ("num_pairs_valid", ctypes.c_uint64),
+                ("num_tiles", ctypes.c_uint32), ("tile_begin", ctypes.c_uint32 * 4),
+                ("bucket_vertices", ctypes.c_uint32 * 256), ("bucket_in_edges", ctypes.c_uint64 * 256),
+                ("bucket_out_edges", ctypes.c_uint64 * 256), ("bucket_work", ctypes.c_uint64 * 256),
+                ("bucket_kernel", ctypes.c_uint8 * 256), ("bucket_chunk", ctypes.c_uint16 * 256),
+                ("bucket_group", ctypes.c_uint8 * 256)]
+
+
+def last_stats(device="cuda:0") -> dict:
+    """Work statistics of the last counting call on the current stream's context."""
+    import numpy as np
+    ctx, _ = _ctx(device)
+    s = Stats()
+    lib = _load()
+    lib.tc_last_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(Stats)]
+    lib.tc_last_stats.restype = ctypes.c_int
+    _check(lib.tc_last_stats(ctx, ctypes.byref(s)), ctx)
+    out = {"m": int(s.num_edges_kept), "m_valid": int(s.num_pairs_valid), "num_tiles": int(s.num_tiles),
+           "tile_begin": list(s.tile_begin)}
+    for f in ("bucket_vertices", "bucket_in_edges", "bucket_out_edges", "bucket_work", "bucket_kernel",
+              "bucket_chunk", "bucket_group"):
+        out[f] = np.ctypeslib.as_array(getattr(s, f)).copy()
+    return out

@@ -1,0 +1,305 @@
+// C ABI of the library (declared in include/tc.h).
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "internal.h"
+#include "pipeline.h"
+#include "tc.h"
+
+struct tc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t events[tcx::NSTAGE + 1] = {};
+    float stage_ms[tcx::NSTAGE] = {};
+    int have_times = 0;
+    std::string last_error;
+    tcx::Ctrl* h_ctrl = nullptr;          // pinned host copy of the control block
+    uint8_t* d_learned = nullptr;         // device [256] kernel per bucket from the selector network
+    int learned_ready = 0;
+    uint16_t* d_chunk = nullptr;          // device [256] tile-size overrides (0 = default)
+    uint8_t* d_group = nullptr;           // device [256] lanes-per-edge overrides (0 = default)
+    int grid_override[tcx::NKERNEL] = {0, 0, 0};
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+tc_status hip_fail(tc_ctx* ctx, hipError_t e, const char* what) {
+    if (ctx) {
+        char buf[256];
+        snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
+        ctx->last_error = buf;
+    }
+    return TC_ERR_HIP;
+}
+
+tc_status arg_fail(tc_ctx* ctx, tc_status st, const char* what) {
+    if (ctx) ctx->last_error = what;
+    return st;
+}
+
+bool options_ok(const tc_options* o) {
+    if (!o) return true;
+    if (o->select < TC_SELECT_HEURISTIC || o->select > TC_FORCE_BITMAP) return false;
+    for (int i = 0; i < 6; ++i)
+        if (o->reserved[i]) return false;
+    return true;
+}
+
+constexpr int64_t kMaxEdges = (int64_t)0x7FFFFFFF;
+
+// Common checks and the run of the pipeline; returns with the control block
+// copied to ctx->h_ctrl on success.
+tc_status run(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* ws, size_t ws_bytes,
+              const tc_options* opts, tcx::RunArgs& ra) {
+    if (!ctx) return TC_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    if (E < 0 || n < 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "negative size");
+    if (E > kMaxEdges) return arg_fail(ctx, TC_ERR_UNSUPPORTED, "num_edges must be < 2^31");
+    if (!options_ok(opts)) return arg_fail(ctx, TC_ERR_INVALID_ARG, "bad options");
+    if (E > 0 && !d_edges) return arg_fail(ctx, TC_ERR_INVALID_ARG, "null edge list");
+    if (((uintptr_t)d_edges & 7u) != 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "edge list must be 8-byte aligned");
+    if (E > 0 && n == 0) return arg_fail(ctx, TC_ERR_VERTEX_RANGE, "edges given for an empty vertex set");
+    const tcx::Layout L = tcx::make_layout(E, n);
+    if (E > 0) {
+        if (!ws) return arg_fail(ctx, TC_ERR_INVALID_ARG, "null workspace");
+        if (ws_bytes < L.total) return arg_fail(ctx, TC_ERR_WORKSPACE, "workspace too small");
+    }
+    DeviceGuard guard(ctx->device);
+    const int sel = opts ? opts->select : TC_SELECT_HEURISTIC;
+    if (sel == TC_SELECT_LEARNED && !ctx->learned_ready)
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "no selector network loaded or trained");
+    const bool timing = opts && (opts->flags & TC_F_STAGE_TIMING);
+    ra.stream = ctx->stream;
+    ra.ws = ws;
+    ra.edges = d_edges;
+    ra.E = E;
+    ra.n = n;
+    ra.select = sel;
+    ra.learned = ctx->learned_ready ? ctx->d_learned : nullptr;
+    ra.chunk_override = ctx->d_chunk;
+    ra.group_override = ctx->d_group;
+    ra.grid_override = ctx->grid_override;
+    ra.events = timing ? ctx->events : nullptr;
+    if (E == 0) {
+        memset(ctx->h_ctrl, 0, sizeof(tcx::Ctrl));
+        if (ra.per_vertex && n > 0) {
+            hipError_t e = hipMemsetAsync(ra.per_vertex, 0, sizeof(uint64_t) * (size_t)n, ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+            if (e != hipSuccess) return hip_fail(ctx, e, "zero per-vertex output");
+        }
+        ctx->have_times = 0;
+        return TC_OK;
+    }
+    tcx::RunResult rr;
+    hipError_t e = tcx::run_pipeline(ra, &rr);
+    if (e != hipSuccess) return hip_fail(ctx, e, "launch");
+    e = hipMemcpyAsync(ctx->h_ctrl, rr.ctrl_dev, sizeof(tcx::Ctrl), hipMemcpyDeviceToHost, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "read control block");
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "synchronise");
+    ctx->have_times = 0;
+    if (timing) {
+        for (int s = 0; s < tcx::NSTAGE; ++s) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ctx->events[s], ctx->events[s + 1]) != hipSuccess) ms = -1.f;
+            ctx->stage_ms[s] = ms;
+        }
+        ctx->have_times = 1;
+    }
+    if (ctx->h_ctrl->err & 1u) return arg_fail(ctx, TC_ERR_VERTEX_RANGE, "vertex id outside [0, num_vertices)");
+    return TC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tc_status tc_create(tc_ctx** out, int device, void* hip_stream) {
+    if (!out) return TC_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return TC_ERR_INVALID_ARG;
+    tc_ctx* ctx = new tc_ctx;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    DeviceGuard guard(device);
+    hipError_t e = hipHostMalloc((void**)&ctx->h_ctrl, sizeof(tcx::Ctrl), hipHostMallocDefault);
+    for (int i = 0; e == hipSuccess && i <= tcx::NSTAGE; ++i) e = hipEventCreate(&ctx->events[i]);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_learned, tcx::NBUCKET);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_chunk, sizeof(uint16_t) * tcx::NBUCKET);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_group, tcx::NBUCKET);
+    if (e == hipSuccess) e = hipMemset(ctx->d_chunk, 0, sizeof(uint16_t) * tcx::NBUCKET);
+    if (e == hipSuccess) e = hipMemset(ctx->d_group, 0, tcx::NBUCKET);
+    if (e != hipSuccess) {
+        tc_destroy(ctx);
+        return TC_ERR_HIP;
+    }
+    *out = ctx;
+    return TC_OK;
+}
+
+tc_status tc_destroy(tc_ctx* ctx) {
+    if (!ctx) return TC_ERR_INVALID_ARG;
+    {
+        DeviceGuard guard(ctx->device);
+        for (int i = 0; i <= tcx::NSTAGE; ++i)
+            if (ctx->events[i]) (void)hipEventDestroy(ctx->events[i]);
+        if (ctx->h_ctrl) (void)hipHostFree(ctx->h_ctrl);
+        if (ctx->d_learned) (void)hipFree(ctx->d_learned);
+        if (ctx->d_chunk) (void)hipFree(ctx->d_chunk);
+        if (ctx->d_group) (void)hipFree(ctx->d_group);
+    }
+    delete ctx;
+    return TC_OK;
+}
+
+tc_status tc_workspace_size(int64_t num_edges, int32_t num_vertices, const tc_options* opts, size_t* bytes) {
+    if (!bytes || num_edges < 0 || num_vertices < 0 || !options_ok(opts)) return TC_ERR_INVALID_ARG;
+    if (num_edges > kMaxEdges) return TC_ERR_UNSUPPORTED;
+    *bytes = tcx::make_layout(num_edges, num_vertices).total;
+    return TC_OK;
+}
+
+tc_status tc_count_triangles(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                             void* d_workspace, size_t workspace_bytes, const tc_options* opts, uint64_t* h_count,
+                             uint64_t* d_per_vertex) {
+    if (!h_count) return arg_fail(ctx, TC_ERR_INVALID_ARG, "null count output");
+    tcx::RunArgs ra = {};
+    ra.per_vertex = d_per_vertex;
+    tc_status st = run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, opts, ra);
+    if (st == TC_OK) *h_count = ctx->h_ctrl->total;
+    return st;
+}
+
+tc_status tc_edge_counts(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                         void* d_workspace, size_t workspace_bytes, const tc_options* opts, int32_t* d_out_edges,
+                         uint32_t* d_out_counts, int64_t* h_num_out, uint64_t* h_count) {
+    if (!h_num_out || !h_count || (num_edges > 0 && (!d_out_edges || !d_out_counts)))
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "null output");
+    tcx::RunArgs ra = {};
+    ra.per_edge_counts = d_out_counts;
+    ra.per_edge_pairs = d_out_edges;
+    tc_status st = run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, opts, ra);
+    if (st == TC_OK) {
+        *h_num_out = ctx->h_ctrl->m;
+        *h_count = ctx->h_ctrl->total;
+    }
+    return st;
+}
+
+tc_status tc_build_csr(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                       void* d_workspace, size_t workspace_bytes, const tc_options* opts, int32_t* d_rank,
+                       int64_t* d_offsets, int32_t* d_col, int64_t* h_num_out) {
+    if (!h_num_out || !d_offsets || (num_vertices > 0 && !d_rank) || (num_edges > 0 && !d_col))
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "null output");
+    tcx::RunArgs ra = {};
+    ra.csr_rank = d_rank;
+    ra.csr_off = d_offsets;
+    ra.csr_col = d_col;
+    if (num_edges == 0) {
+        // every vertex is isolated: identity ranks and empty rows
+        if (!ctx) return TC_ERR_INVALID_ARG;
+        if (num_vertices < 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "negative size");
+        DeviceGuard guard(ctx->device);
+        hipError_t e = hipMemsetAsync(d_offsets, 0, sizeof(int64_t) * ((size_t)num_vertices + 1), ctx->stream);
+        if (e == hipSuccess && num_vertices > 0) {
+            int32_t* h = new int32_t[num_vertices];
+            for (int32_t i = 0; i < num_vertices; ++i) h[i] = i;
+            e = hipMemcpyAsync(d_rank, h, sizeof(int32_t) * (size_t)num_vertices, hipMemcpyHostToDevice, ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+            delete[] h;
+        } else if (e == hipSuccess) {
+            e = hipStreamSynchronize(ctx->stream);
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "empty CSR");
+        *h_num_out = 0;
+        return TC_OK;
+    }
+    tc_status st = run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, opts, ra);
+    if (st == TC_OK) *h_num_out = ctx->h_ctrl->m;
+    return st;
+}
+
+size_t tc_radix_sort_workspace_size(int64_t count) {
+    return count > 0 ? tcx::radix_temp_bytes((size_t)count) : 0;
+}
+
+tc_status tc_radix_sort_u64(tc_ctx* ctx, uint64_t* d_keys, uint64_t* d_keys_alt, int64_t count, int32_t bit_lo,
+                            int32_t bit_hi, void* d_workspace, size_t workspace_bytes) {
+    if (!ctx) return TC_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    if (count < 0 || bit_lo < 0 || bit_hi > 64 || bit_lo > bit_hi) return arg_fail(ctx, TC_ERR_INVALID_ARG, "bad range");
+    if (count > kMaxEdges) return arg_fail(ctx, TC_ERR_UNSUPPORTED, "count must be < 2^31");
+    if (count == 0 || bit_lo == bit_hi) return TC_OK;
+    if (!d_keys || !d_keys_alt || !d_workspace) return arg_fail(ctx, TC_ERR_INVALID_ARG, "null pointer");
+    if (workspace_bytes < tcx::radix_temp_bytes((size_t)count))
+        return arg_fail(ctx, TC_ERR_WORKSPACE, "workspace too small");
+    DeviceGuard guard(ctx->device);
+    const int alt = tcx::radix_sort_u64(d_keys, d_keys_alt, nullptr, nullptr, nullptr, (size_t)count, bit_lo, bit_hi,
+                                        d_workspace, ctx->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && alt)
+        e = hipMemcpyAsync(d_keys, d_keys_alt, sizeof(uint64_t) * (size_t)count, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "radix sort");
+    return TC_OK;
+}
+
+tc_status tc_last_stats(const tc_ctx* ctx, tc_stats* out) {
+    if (!ctx || !out) return TC_ERR_INVALID_ARG;
+    const tcx::Ctrl& c = *ctx->h_ctrl;
+    memset(out, 0, sizeof(*out));
+    out->num_edges_kept = c.m;
+    out->num_pairs_valid = c.m_valid;
+    out->num_tiles = c.ntiles;
+    for (int k = 0; k <= tcx::NKERNEL; ++k) out->tile_begin[k] = c.tile_begin[k];
+    for (int b = 0; b < tcx::NBUCKET; ++b) {
+        out->bucket_vertices[b] = c.bucket_nv[b];
+        out->bucket_in_edges[b] = c.bucket_in[b];
+        out->bucket_out_edges[b] = c.bucket_out[b];
+        out->bucket_work[b] = c.bucket_work[b];
+        out->bucket_kernel[b] = c.choice[b];
+        out->bucket_chunk[b] = c.chunk[b];
+        out->bucket_group[b] = c.group[b];
+    }
+    return TC_OK;
+}
+
+int32_t tc_stage_times(const tc_ctx* ctx, float* ms, int32_t cap) {
+    if (!ctx || !ms || !ctx->have_times) return 0;
+    int32_t k = cap < tcx::NSTAGE ? cap : tcx::NSTAGE;
+    for (int32_t i = 0; i < k; ++i) ms[i] = ctx->stage_ms[i];
+    return k;
+}
+
+const char* tc_stage_name(int32_t stage) { return tcx::stage_name(stage); }
+
+const char* tc_status_string(tc_status s) {
+    switch (s) {
+        case TC_OK: return "ok";
+        case TC_ERR_INVALID_ARG: return "invalid argument";
+        case TC_ERR_VERTEX_RANGE: return "vertex id out of range";
+        case TC_ERR_WORKSPACE: return "workspace too small";
+        case TC_ERR_HIP: return "HIP runtime error";
+        case TC_ERR_UNSUPPORTED: return "unsupported size";
+    }
+    return "unknown status";
+}
+
+const char* tc_last_error(const tc_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+// Internal host-side launchers shared between the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tcx {
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---- prims.hip
+void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+void fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
+size_t scan_temp_bytes();
+void scan_exclusive_sum_u32(const uint32_t* in, uint32_t* out, size_t len, void* temp, hipStream_t s);
+void scan_inclusive_max_u32(const uint32_t* in, uint32_t* out, size_t len, void* temp, hipStream_t s);
+void scan_exclusive_sum_u64(const uint64_t* in, uint64_t* out, size_t len, void* temp, hipStream_t s);
+size_t radix_temp_bytes(size_t cap);
+// Stable LSD sort of keys on bits [bit_lo, bit_hi), 8 bits per pass, optional
+// uint32 payload. The count is read from d_count on the device (nullptr: cap).
+// Returns 1 when the sorted data ended up in the *_alt buffers.
+int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s);
+
+// ---- control block shared by all stages (device memory, zeroed per call)
+constexpr int NBUCKET = 256;          // degree-pair buckets; 255 = no work
+constexpr int BUCKET_NONE = 255;
+constexpr int NKERNEL = 3;            // 0 merge-path, 1 binary search, 2 LDS bitmap
+enum { KER_MERGE = 0, KER_BSEARCH = 1, KER_BITMAP = 2 };
+
+struct Ctrl {
+    uint64_t total;                   // triangle count
+    uint32_t err;                     // bit 0: vertex id out of range
+    uint32_t m_valid;                 // oriented, loop-free pairs before de-duplication
+    uint32_t m;                       // unique oriented edges
+    uint32_t ntiles;                  // tiles emitted
+    uint32_t tile_begin[NKERNEL + 1]; // tile range per intersection kernel
+    uint32_t tile_next[NKERNEL];      // work-queue cursors
+    uint32_t pad0[3];
+    uint32_t bucket_nv[NBUCKET];      // vertices per bucket
+    uint64_t bucket_in[NBUCKET];      // sum of in-degrees (non-empty tails) per bucket
+    uint64_t bucket_out[NBUCKET];     // sum of out-degrees per bucket
+    uint64_t bucket_work[NBUCKET];    // sum of d-(v) * d+(v) per bucket
+    uint8_t choice[NBUCKET];          // kernel per bucket
+    uint8_t slot[NBUCKET];            // bucket -> position in (kernel, bucket) order
+    uint16_t chunk[NBUCKET];          // in-edges per tile, per bucket
+    uint8_t group[NBUCKET];           // lanes per in-edge for the edge-centric kernels
+    uint8_t pad1[NBUCKET - 0];
+};
+
+}  // namespace tcx

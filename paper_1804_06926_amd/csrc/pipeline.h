@@ -1,0 +1,53 @@
+// Host-side interface of the counting pipeline.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace tcx {
+
+enum { SEL_HEURISTIC = 0, SEL_LEARNED = 1, SEL_FORCE_MERGE = 2, SEL_FORCE_BSEARCH = 3, SEL_FORCE_BITMAP = 4 };
+
+constexpr int NSTAGE = 11;
+
+struct Layout {
+    size_t ctrl, deg, rank, inv, vbucket, pos_of, vlist, cursor, seg, tstart, off, rowend, pv;
+    size_t keysA, keysB, col, src, tiles, partial, scan_tmp, radix_tmp;
+    size_t tile_cap;
+    size_t total;
+};
+
+Layout make_layout(int64_t E, int32_t n);
+
+struct RunArgs {
+    hipStream_t stream;
+    void* ws;
+    const int32_t* edges;
+    int64_t E;
+    int32_t n;
+    int select;
+    const uint8_t* learned;          // device [256] kernel per bucket, or null
+    const uint16_t* chunk_override;  // device [256] or null
+    const uint8_t* group_override;   // device [256] or null
+    const int* grid_override;        // host [3] or null
+    uint64_t* per_vertex;            // device [n] or null (original ids)
+    uint32_t* per_edge_counts;       // device [E] or null (CSR order)
+    int32_t* per_edge_pairs;         // device [E][2] or null
+    int32_t* csr_rank;               // device [n] or null (CSR export)
+    int64_t* csr_off;                // device [n+1]
+    int32_t* csr_col;                // device [E]
+    hipEvent_t* events;              // NSTAGE + 1 events, or null
+};
+
+struct RunResult {
+    Ctrl* ctrl_dev;
+};
+
+hipError_t run_pipeline(const RunArgs& r, RunResult* out);
+int stage_count();
+const char* stage_name(int s);
+
+}  // namespace tcx

@@ -1,0 +1,318 @@
+// Device primitives: fills, three-phase scans and an LSD radix sort of 64-bit keys.
+//
+// The radix sort is the CSR builder of the method's "induced subgraph" step
+// (Section 4.2, optimisations for edge list generation): edges are sorted
+// by (source, destination) so every row of the filtered graph is contiguous
+// and ascending. Keys are sorted 8 bits per pass; a pass is a per-tile digit
+// histogram, an exclusive scan of the digit-major histogram, and a stable
+// scatter that ranks equal digits inside each wave with ballots.
+#include "common.h"
+#include "internal.h"
+
+namespace tcx {
+
+// ------------------------------------------------------------------ fills
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* p, T v, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = v;
+}
+
+static unsigned grid_for(size_t n, unsigned cap = 8192) {
+    size_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(n)), dim3(256), 0, s, p, v, n);
+}
+void fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_fill<uint64_t>, dim3(grid_for(n)), dim3(256), 0, s, p, v, n);
+}
+
+// ------------------------------------------------------------------ scans
+// Three phases over a fixed number of blocks: per-block reduction, a scan of
+// the block partials in one block, then each block scans its chunk with its
+// partial as the carry-in. Works in place (out == in).
+constexpr int SCAN_NT = 256;
+constexpr int SCAN_MAX_BLOCKS = 1024;
+
+struct OpSum {
+    template <typename T> __device__ static T apply(T a, T b) { return a + b; }
+    template <typename T> __device__ static T ident() { return T(0); }
+};
+struct OpMax {
+    template <typename T> __device__ static T apply(T a, T b) { return a > b ? a : b; }
+    template <typename T> __device__ static T ident() { return T(0); }
+};
+
+template <typename Op, typename T>
+__device__ T block_reduce(T v, T* scratch) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = Op::apply(v, (T)__shfl_xor(v, o, WAVE));
+    if (lane_id() == 0) scratch[wave_id()] = v;
+    __syncthreads();
+    T r = Op::template ident<T>();
+    for (int i = 0; i < SCAN_NT / WAVE; ++i) r = Op::apply(r, scratch[i]);
+    __syncthreads();
+    return r;
+}
+
+template <typename Op, typename T>
+__device__ T block_scan_inclusive(T v, T* scratch, T* total) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const T t = (T)__shfl_up(v, o, WAVE);
+        if (l >= o) v = Op::apply(v, t);
+    }
+    if (l == WAVE - 1) scratch[wave_id()] = v;
+    __syncthreads();
+    T base = Op::template ident<T>(), all = Op::template ident<T>();
+    for (int i = 0; i < SCAN_NT / WAVE; ++i) {
+        if (i < wave_id()) base = Op::apply(base, scratch[i]);
+        all = Op::apply(all, scratch[i]);
+    }
+    __syncthreads();
+    *total = all;
+    return Op::apply(base, v);
+}
+
+template <typename Op, typename T>
+__global__ __launch_bounds__(SCAN_NT) void k_scan_reduce(const T* in, size_t len, size_t chunk, T* partial) {
+    __shared__ T scratch[SCAN_NT / WAVE];
+    const size_t b0 = (size_t)blockIdx.x * chunk;
+    const size_t b1 = b0 + chunk < len ? b0 + chunk : len;
+    T acc = Op::template ident<T>();
+    for (size_t i = b0 + threadIdx.x; i < b1; i += SCAN_NT) acc = Op::apply(acc, in[i]);
+    acc = block_reduce<Op>(acc, scratch);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// Exclusive scan of up to SCAN_MAX_BLOCKS partials in one block; partial[nb] = total.
+template <typename Op, typename T>
+__global__ __launch_bounds__(SCAN_NT) void k_scan_partials(T* partial, int nb) {
+    __shared__ T scratch[SCAN_NT / WAVE];
+    constexpr int PER = SCAN_MAX_BLOCKS / SCAN_NT;
+    T v[PER];
+    T local = Op::template ident<T>();
+    for (int k = 0; k < PER; ++k) {
+        const int i = threadIdx.x * PER + k;
+        v[k] = i < nb ? partial[i] : Op::template ident<T>();
+        local = Op::apply(local, v[k]);
+    }
+    T total;
+    T inc = block_scan_inclusive<Op>(local, scratch, &total);
+    // exclusive base for this thread = inclusive of previous thread
+    T prev = (T)__shfl_up(inc, 1, WAVE);
+    __shared__ T wave_last[SCAN_NT / WAVE];
+    if (lane_id() == WAVE - 1) wave_last[wave_id()] = inc;
+    __syncthreads();
+    if (lane_id() == 0) prev = wave_id() == 0 ? Op::template ident<T>() : wave_last[wave_id() - 1];
+    T run = prev;
+    for (int k = 0; k < PER; ++k) {
+        const int i = threadIdx.x * PER + k;
+        if (i < nb) partial[i] = run;
+        run = Op::apply(run, v[k]);
+    }
+    if (threadIdx.x == 0) partial[nb] = total;
+}
+
+template <typename Op, typename T, bool INCLUSIVE>
+__global__ __launch_bounds__(SCAN_NT) void k_scan_down(const T* in, T* out, size_t len, size_t chunk,
+                                                       const T* partial) {
+    __shared__ T scratch[SCAN_NT / WAVE];
+    const size_t b0 = (size_t)blockIdx.x * chunk;
+    const size_t b1 = b0 + chunk < len ? b0 + chunk : len;
+    T carry = partial[blockIdx.x];
+    for (size_t base = b0; base < b1; base += SCAN_NT) {
+        const size_t i = base + threadIdx.x;
+        const T v = i < b1 ? in[i] : Op::template ident<T>();
+        T total;
+        const T inc = block_scan_inclusive<Op>(v, scratch, &total);
+        if (i < b1) {
+            if (INCLUSIVE) {
+                out[i] = Op::apply(carry, inc);
+            } else {
+                out[i] = Op::apply(carry, inc) - v;   // exclusive form is only used with OpSum
+            }
+        }
+        carry = Op::apply(carry, total);
+    }
+}
+
+size_t scan_temp_bytes() { return sizeof(uint64_t) * (SCAN_MAX_BLOCKS + 1); }
+
+template <typename Op, typename T, bool INCLUSIVE>
+static void scan_impl(const T* in, T* out, size_t len, void* temp, hipStream_t s) {
+    if (len == 0) return;
+    int nb = (int)((len + 8191) / 8192);
+    if (nb > SCAN_MAX_BLOCKS) nb = SCAN_MAX_BLOCKS;
+    if (nb < 1) nb = 1;
+    size_t chunk = (len + nb - 1) / nb;
+    chunk = (chunk + SCAN_NT - 1) / SCAN_NT * SCAN_NT;
+    nb = (int)((len + chunk - 1) / chunk);
+    T* partial = (T*)temp;
+    hipLaunchKernelGGL((k_scan_reduce<Op, T>), dim3(nb), dim3(SCAN_NT), 0, s, in, len, chunk, partial);
+    hipLaunchKernelGGL((k_scan_partials<Op, T>), dim3(1), dim3(SCAN_NT), 0, s, partial, nb);
+    hipLaunchKernelGGL((k_scan_down<Op, T, INCLUSIVE>), dim3(nb), dim3(SCAN_NT), 0, s, in, out, len, chunk,
+                       (const T*)partial);
+}
+
+void scan_exclusive_sum_u32(const uint32_t* in, uint32_t* out, size_t len, void* temp, hipStream_t s) {
+    scan_impl<OpSum, uint32_t, false>(in, out, len, temp, s);
+}
+void scan_inclusive_max_u32(const uint32_t* in, uint32_t* out, size_t len, void* temp, hipStream_t s) {
+    scan_impl<OpMax, uint32_t, true>(in, out, len, temp, s);
+}
+void scan_exclusive_sum_u64(const uint64_t* in, uint64_t* out, size_t len, void* temp, hipStream_t s) {
+    scan_impl<OpSum, uint64_t, false>(in, out, len, temp, s);
+}
+
+// ------------------------------------------------------------------ radix sort
+constexpr int RS_NT = 256;
+constexpr int RS_WAVES = RS_NT / WAVE;
+constexpr int RS_ITEMS = 8;                     // per lane
+constexpr int RS_TILE = RS_NT * RS_ITEMS;       // 2048 keys per tile
+constexpr int RS_WAVE_SPAN = WAVE * RS_ITEMS;   // 512 keys per wave, striped by lane
+
+__device__ __forceinline__ uint32_t rs_count(const uint32_t* d_count, uint32_t cap) {
+    const uint32_t c = d_count ? *d_count : cap;
+    return c < cap ? c : cap;
+}
+
+// Per-tile digit counts, written digit-major: hist[d * ntiles + tile].
+__global__ __launch_bounds__(RS_NT) void k_radix_hist(const uint64_t* __restrict__ keys, const uint32_t* d_count,
+                                                      uint32_t cap, int shift, uint32_t* __restrict__ hist,
+                                                      uint32_t ntiles) {
+    __shared__ uint32_t wcnt[RS_WAVES][256];
+    for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t n = rs_count(d_count, cap);
+    const int w = wave_id(), l = lane_id();
+    const uint32_t base = blockIdx.x * RS_TILE + w * RS_WAVE_SPAN;
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint32_t i = base + it * WAVE + l;
+        const bool valid = i < n;
+        const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & 255u : 0u;
+        const uint64_t peers = match_digit8(d, __ballot(valid));
+        if (valid && (peers & lanes_below()) == 0) wcnt[w][d] += (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    const int d = threadIdx.x;
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < RS_WAVES; ++k) t += wcnt[k][d];
+    hist[(size_t)d * ntiles + blockIdx.x] = t;
+}
+
+template <bool HAS_VAL>
+__global__ __launch_bounds__(RS_NT) void k_radix_scatter(const uint64_t* __restrict__ kin,
+                                                         const uint32_t* __restrict__ vin,
+                                                         uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                         const uint32_t* d_count, uint32_t cap, int shift,
+                                                         const uint32_t* __restrict__ hist_scan, uint32_t ntiles) {
+    __shared__ uint32_t wcnt[RS_WAVES][256];
+    __shared__ uint32_t lstart[256];
+    __shared__ uint32_t gbase[256];
+    __shared__ uint32_t scratch[RS_WAVES];
+    __shared__ uint64_t skey[RS_TILE];
+    __shared__ uint32_t sval[HAS_VAL ? RS_TILE : 1];
+    for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t n = rs_count(d_count, cap);
+    const int w = wave_id(), l = lane_id();
+    const uint32_t tile0 = blockIdx.x * RS_TILE;
+    const uint32_t base = tile0 + w * RS_WAVE_SPAN;
+    uint64_t k[RS_ITEMS];
+    uint32_t v[RS_ITEMS];
+    uint32_t loc[RS_ITEMS];   // digit | (rank within (wave, digit)) << 8
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint32_t i = base + it * WAVE + l;
+        const bool valid = i < n;
+        k[it] = valid ? kin[i] : 0ull;
+        if (HAS_VAL) v[it] = valid ? vin[i] : 0u;
+        const uint32_t d = (uint32_t)(k[it] >> shift) & 255u;
+        const uint64_t peers = match_digit8(d, __ballot(valid));
+        const uint32_t r = (uint32_t)__popcll(peers & lanes_below());
+        const uint32_t prev = wcnt[w][d];
+        __builtin_amdgcn_wave_barrier();
+        if (valid && r == 0) wcnt[w][d] = prev + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        loc[it] = d | ((prev + r) << 8);
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;
+        uint32_t run = 0;
+#pragma unroll
+        for (int q = 0; q < RS_WAVES; ++q) {
+            const uint32_t c = wcnt[q][d];
+            wcnt[q][d] = run;
+            run += c;
+        }
+        const uint32_t excl = block_exclusive_scan<RS_NT>(run, scratch);
+        lstart[d] = excl;
+        gbase[d] = hist_scan[(size_t)d * ntiles + blockIdx.x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint32_t i = base + it * WAVE + l;
+        if (i < n) {
+            const uint32_t d = loc[it] & 255u;
+            const uint32_t p = lstart[d] + wcnt[w][d] + (loc[it] >> 8);
+            skey[p] = k[it];
+            if (HAS_VAL) sval[p] = v[it];
+        }
+    }
+    __syncthreads();
+    const uint32_t tile_n = n > tile0 ? (n - tile0 < (uint32_t)RS_TILE ? n - tile0 : (uint32_t)RS_TILE) : 0u;
+    for (uint32_t j = threadIdx.x; j < tile_n; j += RS_NT) {
+        const uint64_t key = skey[j];
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint32_t pos = gbase[d] + (j - lstart[d]);
+        if (pos < n) {   // always true when the histogram scan is consistent
+            kout[pos] = key;
+            if (HAS_VAL) vout[pos] = sval[j];
+        }
+    }
+}
+
+size_t radix_temp_bytes(size_t cap) {
+    const size_t ntiles = (cap + RS_TILE - 1) / RS_TILE + 1;
+    return align_up(sizeof(uint32_t) * 256 * ntiles, 256) + align_up(scan_temp_bytes(), 256);
+}
+
+int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s) {
+    if (cap == 0 || bit_hi <= bit_lo) return 0;
+    const uint32_t ntiles = (uint32_t)((cap + RS_TILE - 1) / RS_TILE);
+    uint32_t* hist = (uint32_t*)temp;
+    void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * ((cap + RS_TILE - 1) / RS_TILE + 1), 256);
+    uint64_t* kin = keys;
+    uint64_t* kout = keys_alt;
+    uint32_t* vin = vals;
+    uint32_t* vout = vals_alt;
+    int passes = 0;
+    for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(RS_NT), 0, s, kin, d_count, (uint32_t)cap, shift, hist,
+                           ntiles);
+        scan_exclusive_sum_u32(hist, hist, (size_t)256 * ntiles, scan_tmp, s);
+        if (vals) {
+            hipLaunchKernelGGL(k_radix_scatter<true>, dim3(ntiles), dim3(RS_NT), 0, s, kin, vin, kout, vout, d_count,
+                               (uint32_t)cap, shift, hist, ntiles);
+        } else {
+            hipLaunchKernelGGL(k_radix_scatter<false>, dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr, kout, nullptr,
+                               d_count, (uint32_t)cap, shift, hist, ntiles);
+        }
+        uint64_t* tk = kin; kin = kout; kout = tk;
+        uint32_t* tv = vin; vin = vout; vout = tv;
+    }
+    return passes & 1;   // 1: result is in keys_alt / vals_alt
+}
+
+}  // namespace tcx
