@@ -58,7 +58,7 @@ def _load():
     lib.oracle_count_forward.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
     lib.oracle_count_forward.restype = ctypes.c_uint64
     lib.oracle_vertex_triangles.argtypes = [vp, vp, ctypes.c_int64, vp, ctypes.c_int]
-    lib.oracle_oriented_edge_counts.argtypes = [vp, vp, ctypes.c_int]
+    lib.oracle_oriented_edge_counts.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
     lib.oracle_edge_support.argtypes = [vp, vp, ctypes.c_int]
     _lib = lib
     return lib
@@ -121,10 +121,16 @@ class Graph:
             _load().oracle_vertex_triangles(self._h, vs.ctypes.data, vs.shape[0], out.ctypes.data, self.threads)
         return out
 
-    def oriented_edge_counts(self) -> np.ndarray:
+    def oriented_edge_counts(self, degree: str = "simple") -> np.ndarray:
+        """Per canonical edge, |N+(x) n N+(y)| for the (degree, id) orientation.
+
+        degree="simple": degree in the simple graph; degree="input": number of
+        input pairs at the vertex (self-loops dropped, repeats counted).
+        """
         out = np.zeros(self.m, dtype=np.uint32)
+        mode = {"simple": 0, "input": 1}[degree]
         if self.m:
-            _load().oracle_oriented_edge_counts(self._h, out.ctypes.data, self.threads)
+            _load().oracle_oriented_edge_counts(self._h, mode, out.ctypes.data, self.threads)
         return out
 
     def edge_support(self) -> np.ndarray:

@@ -44,10 +44,22 @@ def degree_order(deg: np.ndarray) -> np.ndarray:
     return rank
 
 
-def oriented_csr(edges: np.ndarray, n: int):
-    """(rank, offsets int64[n+1], col int64[m], src int64[m]) of the degree-ordered graph."""
+def input_degrees(edges: np.ndarray, n: int) -> np.ndarray:
+    """Number of input pairs at each vertex, self-loops dropped, repeated pairs counted."""
+    e = np.asarray(edges, dtype=np.int64).reshape(-1, 2)
+    e = e[e[:, 0] != e[:, 1]]
+    return (np.bincount(e[:, 0], minlength=n) + np.bincount(e[:, 1], minlength=n)).astype(np.int64)
+
+
+def oriented_csr(edges: np.ndarray, n: int, degree: str = "simple"):
+    """(rank, offsets int64[n+1], col int64[m], src int64[m]) of the degree-ordered graph.
+
+    degree="simple" orders by the simple graph's degrees, degree="input" by the
+    number of input pairs at each vertex (identical when the input has no repeats).
+    """
     pairs = simple_graph(edges, n)
-    rank = degree_order(degrees(pairs, n))
+    deg = degrees(pairs, n) if degree == "simple" else input_degrees(edges, n)
+    rank = degree_order(deg)
     ra, rb = rank[pairs[:, 0]], rank[pairs[:, 1]]
     src, dst = np.minimum(ra, rb), np.maximum(ra, rb)
     o = np.lexsort((dst, src))

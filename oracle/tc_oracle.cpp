@@ -44,6 +44,7 @@ struct Graph {
     int64_t m = 0;
     std::vector<uint64_t> keys;       // canonical pairs (min << 32 | max), sorted, unique
     std::vector<int32_t> deg;         // degree in the simple graph
+    std::vector<int64_t> deg_input;   // input pairs incident to v (loops dropped, repeats counted)
     std::vector<int64_t> adj_off;     // symmetric adjacency, rows sorted by id
     std::vector<int32_t> adj;
 };
@@ -53,6 +54,10 @@ int pick_threads(int threads) { return threads > 0 ? threads : omp_get_max_threa
 // (degree, id) ascending: the strict total order used to orient edges.
 inline bool precedes_deg_id(const Graph& g, int32_t a, int32_t b) {
     return g.deg[a] < g.deg[b] || (g.deg[a] == g.deg[b] && a < b);
+}
+// The same order with the degree counted over the input pairs (repeats included).
+inline bool precedes_input_deg_id(const Graph& g, int32_t a, int32_t b) {
+    return g.deg_input[a] < g.deg_input[b] || (g.deg_input[a] == g.deg_input[b] && a < b);
 }
 // The paper's literal filter keeps e(u,v) with d(u) > d(v), ties to the
 // smaller id: degree descending, id ascending.
@@ -91,9 +96,12 @@ int oracle_graph_build(const int32_t* edges, int64_t num_edges, int32_t n, int t
     g->n = n;
     // Canonicalise: unordered pair -> (min, max); self-loops dropped.
     g->keys.reserve((size_t)num_edges);
+    g->deg_input.assign((size_t)n, 0);
     for (int64_t i = 0; i < num_edges; ++i) {
         uint32_t a = (uint32_t)edges[2 * i], b = (uint32_t)edges[2 * i + 1];
         if (a == b) continue;
+        g->deg_input[a]++;
+        g->deg_input[b]++;
         if (a > b) std::swap(a, b);
         g->keys.push_back(((uint64_t)a << 32) | b);
     }
@@ -234,8 +242,11 @@ void oracle_vertex_triangles(const void* h, const int32_t* vs, int64_t k, uint64
  * canonical pair i (a < b, ascending order of oracle_graph_edges), out[i] =
  * |{ w : w ~ a, w ~ b, a < w and b < w in (degree, id) order }|, the size of
  * N+(x) intersected with N+(y) for the kept edge x -> y on {a, b}.
+ * degree_mode 0: degree in the simple graph; 1: number of input pairs at the
+ * vertex (self-loops dropped, repeated pairs counted). The two agree on
+ * inputs without repeats.
  */
-void oracle_oriented_edge_counts(const void* h, uint32_t* out, int threads) {
+void oracle_oriented_edge_counts(const void* h, int degree_mode, uint32_t* out, int threads) {
     const Graph* g = (const Graph*)h;
 #pragma omp parallel for schedule(dynamic, 4096) num_threads(pick_threads(threads))
     for (int64_t i = 0; i < g->m; ++i) {
@@ -250,7 +261,9 @@ void oracle_oriented_edge_counts(const void* h, uint32_t* out, int threads) {
             else if (na[x] > nb[y]) ++y;
             else {
                 int32_t w = na[x];
-                if (precedes_deg_id(*g, a, w) && precedes_deg_id(*g, b, w)) ++c;
+                const bool after_a = degree_mode ? precedes_input_deg_id(*g, a, w) : precedes_deg_id(*g, a, w);
+                const bool after_b = degree_mode ? precedes_input_deg_id(*g, b, w) : precedes_deg_id(*g, b, w);
+                if (after_a && after_b) ++c;
                 ++x; ++y;
             }
         }

@@ -119,7 +119,8 @@ def test_per_edge_counts_match_oracle(tc, sel):
     n = 1 << 13
     e = _dirty(graphgen.rmat(13, 16, seed=21), n, 21)
     g = oracle.Graph(e, n)
-    ref = g.oriented_edge_counts()
+    # the input has repeated pairs: the GPU orders by input-pair degree
+    ref = g.oriented_edge_counts(degree="input")
     ref_keys = _canon_keys(g.edges())
     pairs, counts, T = tc.edge_counts(dev(e), n, select=_sel(tc, sel))
     pairs = pairs.cpu().numpy()
@@ -130,8 +131,8 @@ def test_per_edge_counts_match_oracle(tc, sel):
     np.testing.assert_array_equal(keys[o], ref_keys)
     np.testing.assert_array_equal(counts[o], ref.astype(np.int64))
     assert T == g.count() == int(counts.sum())
-    # orientation: u before v in (degree, id) order
-    deg = g.degrees()
+    # orientation: u before v in (input degree, id) order
+    deg = stages.input_degrees(e, n)
     u, v = pairs[:, 0], pairs[:, 1]
     assert np.all((deg[u] < deg[v]) | ((deg[u] == deg[v]) & (u < v)))
 
@@ -140,7 +141,7 @@ def test_csr_export_matches_definition(tc):
     n = 1 << 12
     e = _dirty(graphgen.rmat(12, 16, seed=5), n, 5)
     rank, off, col = tc.build_csr(dev(e), n)
-    r_rank, r_off, r_col, _ = stages.oriented_csr(e, n)
+    r_rank, r_off, r_col, _ = stages.oriented_csr(e, n, degree="input")
     np.testing.assert_array_equal(rank.cpu().numpy(), r_rank)
     np.testing.assert_array_equal(off.cpu().numpy(), r_off)
     np.testing.assert_array_equal(col.cpu().numpy(), r_col)
@@ -160,6 +161,20 @@ def test_radix_sort_is_stable_and_exact(tc, count, bits):
     digit = (u >> np.uint64(lo)) & np.uint64((1 << (hi - lo)) - 1 if hi - lo < 64 else 0xFFFFFFFFFFFFFFFF)
     ref = keys[np.argsort(digit, kind="stable")]
     np.testing.assert_array_equal(d.cpu().numpy(), ref)
+
+
+def test_per_edge_counts_clean_input_simple_degree(tc):
+    """Without repeated pairs, input degree and simple degree coincide."""
+    n = 1 << 12
+    g0 = oracle.Graph(graphgen.rmat(12, 8, seed=31), n)
+    e = graphgen.shuffle_edges(g0.edges(), 4)
+    g = oracle.Graph(e, n)
+    ref = g.oriented_edge_counts(degree="simple")
+    pairs, counts, T = tc.edge_counts(dev(e), n)
+    keys = _canon_keys(pairs.cpu().numpy())
+    o = np.argsort(keys)
+    np.testing.assert_array_equal(keys[o], _canon_keys(g.edges()))
+    np.testing.assert_array_equal(counts.cpu().numpy()[o].astype(np.int64), ref.astype(np.int64))
 
 
 def test_rmat20_all_kernels_agree_per_edge(tc):

@@ -209,6 +209,24 @@ def test_oriented_edge_counts_match_sets_and_sum_to_T():
     np.testing.assert_array_equal(c, ref[o])
 
 
+def test_oriented_counts_input_degree_mode():
+    e, n = _rmat_small(10, 8)
+    dirty = np.concatenate([e, e[: e.shape[0] // 4, ::-1]]).astype(np.int32)
+    g = oracle.Graph(dirty, n)
+    c = g.oriented_edge_counts(degree="input")
+    assert int(c.sum()) == g.count()
+    rank, off, col, src = stages.oriented_csr(dirty, n, degree="input")
+    ref = stages.oriented_counts(off, col, src)
+    inv = np.empty(n, dtype=np.int64)
+    inv[rank] = np.arange(n)
+    a, b = inv[src], inv[col]
+    o = np.argsort((np.minimum(a, b) << 32) | np.maximum(a, b))
+    np.testing.assert_array_equal(c, ref[o])
+    # clean input: both degree definitions agree
+    g2 = oracle.Graph(e, n)
+    assert np.array_equal(g2.oriented_edge_counts("simple"), oracle.Graph(g2.edges(), n).oriented_edge_counts("input"))
+
+
 def test_edge_support():
     e, n = _rmat_small(9, 10)
     g = oracle.Graph(e, n)
