@@ -36,8 +36,10 @@ struct Ctrl {
     uint32_t m;                       // unique oriented edges
     uint32_t ntiles;                  // tiles emitted
     uint32_t tile_begin[NKERNEL + 1]; // tile range per intersection kernel
-    uint32_t tile_next[NKERNEL];      // work-queue cursors
+    uint32_t m_active;                // in-edges with work (non-empty tail, d+(v) > 0)
     uint32_t pad0[3];
+    uint32_t bstart[NBUCKET];         // first / one-past-last position of each bucket
+    uint32_t bend[NBUCKET];           //   in the (kernel, bucket)-ordered vertex list
     uint32_t bucket_nv[NBUCKET];      // vertices per bucket
     uint64_t bucket_in[NBUCKET];      // sum of in-degrees (non-empty tails) per bucket
     uint64_t bucket_out[NBUCKET];     // sum of out-degrees per bucket
@@ -46,7 +48,13 @@ struct Ctrl {
     uint8_t slot[NBUCKET];            // bucket -> position in (kernel, bucket) order
     uint16_t chunk[NBUCKET];          // in-edges per tile, per bucket
     uint8_t group[NBUCKET];           // lanes per in-edge for the edge-centric kernels
-    uint8_t pad1[NBUCKET - 0];
+    uint8_t pad1[NBUCKET];
 };
+
+// Tiles: low word = position i in the ordered vertex list; high word = chunk
+// index j of vertex i's in-edges, or TILE_MULTI | g for the g vertices
+// starting at position i (whole in-edge lists).
+constexpr uint32_t TILE_MULTI = 0x80000000u;
+constexpr int SEG_MAX = 256;          // vertices per multi-vertex tile
 
 }  // namespace tcx

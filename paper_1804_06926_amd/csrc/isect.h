@@ -8,23 +8,28 @@
 
 namespace tcx {
 
-constexpr int CHUNK_MAX = 512;   // in-edges per bitmap tile (LDS-resident tail table)
+constexpr int CHUNK_MAX = 512;   // in-edges per tile (LDS-resident entry table)
 
 struct IsectArgs {
-    Ctrl* ctrl;
-    const uint32_t* off;        // [n+1] CSR row offsets (ranks)
+    Ctrl* ctrl;                 // control block: tile ranges, tile shapes, the total
+    const uint32_t* off;       // [n+1] CSR row offsets (ranks)
     const uint32_t* col;        // [m]   CSR columns, rows ascending
     const uint32_t* src;        // [m]   row of each edge
-    const uint64_t* csc;        // [in-edges] e | row_end(u) << 32, grouped by (kernel, bucket, v)
-    const uint32_t* seg_start;  // [n+1] start of each vertex's in-edge segment (bucket order)
-    const uint32_t* vlist;      // [n]   vertices in bucket order
+    const uint64_t* csc;        // [m_active] v << 32 | e, grouped by v
+    const uint32_t* inoff;      // [n+1] start of each vertex's in-edges in csc
+    const uint32_t* vlist;      // [n]   vertices in (kernel, bucket) order
     const uint8_t* vbucket;     // [n]   bucket of each vertex
-    const uint64_t* tiles;      // [ntiles] vertex position | chunk << 32
+    const uint64_t* tiles;      // [ntiles] position | (chunk or TILE_MULTI | count) << 32
     uint32_t* per_edge;         // [m] or null: c_e in CSR edge order
     uint64_t* per_vertex;       // [n] or null: t[] in rank space
 };
 
 int isect_blocks_per_cu(int ker);
-void launch_isect(int ker, const IsectArgs& a, int grid, hipStream_t s);
+size_t isect_partials_bytes();
+// One intersection kernel over its tile range; per-block partial counts go to
+// partials (isect_partials_bytes() of workspace shared by the three kernels).
+void launch_isect(int ker, const IsectArgs& a, int grid, uint64_t* partials, hipStream_t s);
+// ctrl->total = sum of all partial counts.
+void launch_reduce_total(uint64_t* partials, Ctrl* ctrl, hipStream_t s);
 
 }  // namespace tcx

@@ -6,15 +6,18 @@
 // position p of row u, a common neighbour w of N+(u) and N+(v) must rank above
 // v, so only the tail of row u after p can match:
 //     c_e = | row_u[p+1 ..] intersected with N+(v) |  =  | N+(u) intersected with N+(v) |.
-// Work is grouped by the middle vertex v: a tile is v together with a chunk
-// of its in-edges (entries e | row_end(u) << 32). Three interchangeable
-// strategies compute the same c_e for every in-edge of a tile:
+// Work is grouped by the middle vertex v. A tile is either one vertex v with a
+// chunk of its in-edges, or several vertices of one bucket with all their
+// in-edges. Three interchangeable strategies compute the same c_e for every
+// in-edge of a tile:
 //   merge   : merge-path split of (tail, N+(v)) across a group of lanes
 //   bsearch : binary search of each element of the shorter list in the other
-//   bitmap  : N+(v) staged once per tile as an LDS bitmap; tails streamed
+//   bitmap  : N+(v) staged once per vertex as an LDS bitmap; tails streamed
 //             through it (long tails by a whole wave, short ones by one lane)
 // Each hit adds 1 to the exact 64-bit triangle count; optional outputs are
 // the per-edge counts c_e and per-vertex counts t[u], t[v], t[w].
+// Tiles are dealt to blocks round-robin (no shared work counter); each block
+// writes its partial count and one reduction adds them in a fixed order.
 #include "common.h"
 #include "internal.h"
 #include "isect.h"
@@ -26,29 +29,50 @@ constexpr int BM_WORDS = 4096;            // 131072-bit window (16 KiB)
 constexpr uint32_t BM_BITS = BM_WORDS * 32u;
 constexpr int STAGE_MAX = 4096;           // N+(v) staged in LDS by merge/bsearch when it fits
 constexpr uint32_t LONG_TAIL = 32;        // bitmap kernel: tails this long go to a whole wave
+constexpr int PARTIALS_PER_KERNEL = 4096; // max blocks per intersection launch
 
-struct TileView {
-    uint32_t v, e0, e1, b0, b1;
+struct Segs {
+    uint32_t v[SEG_MAX];
+    uint32_t e0[SEG_MAX];
+    uint32_t pref[SEG_MAX + 1];
+    uint32_t scratch[IS_NT / WAVE];
 };
 
-__device__ __forceinline__ bool next_tile(const IsectArgs& a, int ker, uint32_t* s_tile, TileView* tv) {
-    if (threadIdx.x == 0) *s_tile = a.ctrl->tile_begin[ker] + atomicAdd(&a.ctrl->tile_next[ker], 1u);
-    __syncthreads();
-    const uint32_t t = *s_tile;
-    __syncthreads();
-    if (t >= a.ctrl->tile_begin[ker + 1]) return false;
+// Decode tile t into segments (v, first in-edge, count); returns the count.
+// Called by the whole block; contains barriers.
+__device__ uint32_t load_tile(const IsectArgs& a, uint32_t t, Segs& S) {
     const uint64_t d = a.tiles[t];
-    const uint32_t i = (uint32_t)d, j = (uint32_t)(d >> 32);
-    const uint32_t v = a.vlist[i];
-    const uint32_t K = a.ctrl->chunk[a.vbucket[v]];
-    const uint32_t s0 = a.seg_start[i], s1 = a.seg_start[i + 1];
-    tv->v = v;
-    tv->e0 = s0 + j * K;
-    tv->e1 = tv->e0 + K < s1 ? tv->e0 + K : s1;
-    tv->b0 = a.off[v];
-    tv->b1 = a.off[v + 1];
-    return true;
+    const uint32_t i = (uint32_t)d, h = (uint32_t)(d >> 32);
+    uint32_t nseg, cnt = 0;
+    if (h & TILE_MULTI) {
+        nseg = h & ~TILE_MULTI;
+        if (threadIdx.x < nseg) {
+            const uint32_t v = a.vlist[i + threadIdx.x];
+            S.v[threadIdx.x] = v;
+            S.e0[threadIdx.x] = a.inoff[v];
+            cnt = a.inoff[v + 1] - a.inoff[v];
+        }
+    } else {
+        nseg = 1;
+        if (threadIdx.x == 0) {
+            const uint32_t v = a.vlist[i];
+            const uint32_t K = a.ctrl->chunk[a.vbucket[v]];
+            const uint32_t e0 = a.inoff[v] + h * K;
+            const uint32_t end = a.inoff[v + 1];
+            S.v[0] = v;
+            S.e0[0] = e0;
+            cnt = (e0 + K < end ? e0 + K : end) - e0;
+        }
+    }
+    uint32_t total;
+    const uint32_t excl = block_exclusive_scan<IS_NT>(cnt, S.scratch, &total);
+    if (threadIdx.x < nseg) S.pref[threadIdx.x] = excl;
+    if (threadIdx.x == 0) S.pref[nseg] = total;
+    __syncthreads();
+    return nseg;
 }
+
+__device__ __forceinline__ uint32_t tail_end(const IsectArgs& a, uint32_t e) { return a.off[a.src[e] + 1]; }
 
 __device__ __forceinline__ void edge_done(const IsectArgs& a, uint32_t e, uint32_t v, uint32_t c) {
     if (a.per_edge) a.per_edge[e] = c;
@@ -62,7 +86,7 @@ __device__ __forceinline__ void hit_vertex(const IsectArgs& a, uint32_t w) {
     if (a.per_vertex) atomicAdd((unsigned long long*)&a.per_vertex[w], 1ull);
 }
 
-__device__ __forceinline__ void block_flush_total(const IsectArgs& a, uint64_t acc) {
+__device__ __forceinline__ void block_partial(uint64_t acc, uint64_t* partials) {
     __shared__ uint64_t red[IS_NT / WAVE];
     acc = wave_sum_u64(acc);
     if (lane_id() == 0) red[wave_id()] = acc;
@@ -70,122 +94,123 @@ __device__ __forceinline__ void block_flush_total(const IsectArgs& a, uint64_t a
     if (threadIdx.x == 0) {
         uint64_t s = 0;
         for (int i = 0; i < IS_NT / WAVE; ++i) s += red[i];
-        if (s) atomicAdd((unsigned long long*)&a.ctrl->total, (unsigned long long)s);
+        partials[blockIdx.x] = s;
     }
 }
 
 // ------------------------------------------------------------------ LDS bitmap
-__global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a) {
+__global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* partials) {
     __shared__ uint32_t bm[BM_WORDS];
     __shared__ uint32_t s_start[CHUNK_MAX];
     __shared__ uint32_t s_end[CHUNK_MAX];
     __shared__ uint16_t s_long[CHUNK_MAX];
     __shared__ uint16_t s_short[CHUNK_MAX];
-    __shared__ uint32_t s_nlong, s_nshort, s_long_next, s_tile;
+    __shared__ uint32_t s_nlong, s_nshort, s_long_next;
+    __shared__ Segs S;
     for (int i = threadIdx.x; i < BM_WORDS; i += IS_NT) bm[i] = 0;
     const int l = lane_id();
     uint64_t acc = 0;
-    TileView tv;
-    while (next_tile(a, KER_BITMAP, &s_tile, &tv)) {
-        const uint32_t ne = tv.e1 - tv.e0;
-        const uint32_t nb = tv.b1 - tv.b0;
-        if (threadIdx.x == 0) { s_nlong = 0; s_nshort = 0; s_long_next = 0; }
-        __syncthreads();
-        for (uint32_t k = threadIdx.x; k < ne; k += IS_NT) {
-            const uint64_t ent = a.csc[tv.e0 + k];
-            const uint32_t s = (uint32_t)ent + 1u, e = (uint32_t)(ent >> 32);
-            s_start[k] = s;
-            s_end[k] = e;
-            if (e - s >= LONG_TAIL) s_long[atomicAdd(&s_nlong, 1u)] = (uint16_t)k;
-            else s_short[atomicAdd(&s_nshort, 1u)] = (uint16_t)k;
-        }
-        const uint32_t lo = a.col[tv.b0], hi = a.col[tv.b1 - 1];
-        const uint32_t base = lo & ~31u;
-        const uint32_t nwin = (hi - base) / BM_BITS + 1;
-        __syncthreads();
-        const uint32_t nlong = s_nlong, nshort = s_nshort;
-        for (uint32_t win = 0; win < nwin; ++win) {
-            const uint32_t wlo = base + win * BM_BITS;
-            for (uint32_t j = threadIdx.x; j < nb; j += IS_NT) {
-                const uint32_t x = a.col[tv.b0 + j];
-                if (x >= wlo && x - wlo < BM_BITS) atomicOr(&bm[(x - wlo) >> 5], 1u << ((x - wlo) & 31u));
-            }
+    const uint32_t t_end = a.ctrl->tile_begin[KER_BITMAP + 1];
+    for (uint32_t t = a.ctrl->tile_begin[KER_BITMAP] + blockIdx.x; t < t_end; t += gridDim.x) {
+        const uint32_t nseg = load_tile(a, t, S);
+        for (uint32_t sg = 0; sg < nseg; ++sg) {
+            const uint32_t v = S.v[sg];
+            const uint32_t e0 = S.e0[sg];
+            const uint32_t ne = S.pref[sg + 1] - S.pref[sg];
+            const uint32_t b0 = a.off[v], b1 = a.off[v + 1];
+            const uint32_t nb = b1 - b0;
+            if (threadIdx.x == 0) { s_nlong = 0; s_nshort = 0; s_long_next = 0; }
             __syncthreads();
-            // long tails: one wave per in-edge, lanes stride the tail
-            if (nwin == 1) {
-                while (true) {
-                    uint32_t q = 0;
-                    if (l == 0) q = atomicAdd(&s_long_next, 1u);
-                    q = __shfl(q, 0, WAVE);
-                    if (q >= nlong) break;
-                    const uint32_t k = s_long[q];
-                    const uint32_t s = s_start[k], e = s_end[k];
-                    uint32_t c = 0;
-                    for (uint32_t p = s + l; p < e; p += WAVE) {
-                        const uint32_t x = a.col[p] - wlo;
-                        if (x < BM_BITS && ((bm[x >> 5] >> (x & 31u)) & 1u)) {
-                            ++c;
-                            hit_vertex(a, x + wlo);
+            for (uint32_t k = threadIdx.x; k < ne; k += IS_NT) {
+                const uint32_t e = (uint32_t)a.csc[e0 + k];
+                const uint32_t s = e + 1u, end = tail_end(a, e);
+                s_start[k] = s;
+                s_end[k] = end;
+                if (end - s >= LONG_TAIL) s_long[atomicAdd(&s_nlong, 1u)] = (uint16_t)k;
+                else s_short[atomicAdd(&s_nshort, 1u)] = (uint16_t)k;
+            }
+            const uint32_t lo = a.col[b0], hi = a.col[b1 - 1];
+            const uint32_t base = lo & ~31u;
+            const uint32_t nwin = (hi - base) / BM_BITS + 1;
+            __syncthreads();
+            const uint32_t nlong = s_nlong, nshort = s_nshort;
+            for (uint32_t win = 0; win < nwin; ++win) {
+                const uint32_t wlo = base + win * BM_BITS;
+                for (uint32_t j = threadIdx.x; j < nb; j += IS_NT) {
+                    const uint32_t x = a.col[b0 + j] - wlo;
+                    if (x < BM_BITS) atomicOr(&bm[x >> 5], 1u << (x & 31u));
+                }
+                __syncthreads();
+                if (nwin == 1) {
+                    // long tails: one wave per in-edge, lanes stride the tail
+                    while (true) {
+                        uint32_t q = 0;
+                        if (l == 0) q = atomicAdd(&s_long_next, 1u);
+                        q = __shfl(q, 0, WAVE);
+                        if (q >= nlong) break;
+                        const uint32_t k = s_long[q];
+                        const uint32_t s = s_start[k], e = s_end[k];
+                        uint32_t c = 0;
+                        for (uint32_t p = s + l; p < e; p += WAVE) {
+                            const uint32_t x = a.col[p] - wlo;
+                            if (x < BM_BITS && ((bm[x >> 5] >> (x & 31u)) & 1u)) {
+                                ++c;
+                                hit_vertex(a, x + wlo);
+                            }
+                        }
+                        c = wave_sum(c);
+                        acc += (l == 0) ? c : 0u;
+                        if (l == 0) edge_done(a, s - 1u, v, c);
+                    }
+                    // short tails: one lane per in-edge
+                    for (uint32_t q = threadIdx.x; q < nshort; q += IS_NT) {
+                        const uint32_t k = s_short[q];
+                        const uint32_t s = s_start[k], e = s_end[k];
+                        uint32_t c = 0;
+                        for (uint32_t p = s; p < e; ++p) {
+                            const uint32_t x = a.col[p] - wlo;
+                            if (x < BM_BITS && ((bm[x >> 5] >> (x & 31u)) & 1u)) {
+                                ++c;
+                                hit_vertex(a, x + wlo);
+                            }
+                        }
+                        acc += c;
+                        edge_done(a, s - 1u, v, c);
+                    }
+                } else {
+                    // N+(v) spans more than one window: one lane per in-edge; the
+                    // per-edge output accumulates over the windows
+                    for (uint32_t k = threadIdx.x; k < ne; k += IS_NT) {
+                        const uint32_t s = s_start[k], e = s_end[k];
+                        uint32_t c = 0;
+                        for (uint32_t p = s; p < e; ++p) {
+                            const uint32_t x = a.col[p] - wlo;
+                            if (x < BM_BITS && ((bm[x >> 5] >> (x & 31u)) & 1u)) {
+                                ++c;
+                                hit_vertex(a, x + wlo);
+                            }
+                        }
+                        acc += c;
+                        if (a.per_edge) a.per_edge[s - 1u] = (win ? a.per_edge[s - 1u] : 0u) + c;
+                        if (a.per_vertex && c) {
+                            atomicAdd((unsigned long long*)&a.per_vertex[a.src[s - 1u]], (unsigned long long)c);
+                            atomicAdd((unsigned long long*)&a.per_vertex[v], (unsigned long long)c);
                         }
                     }
-                    c = wave_sum(c);
-                    acc += (l == 0) ? c : 0u;
-                    if (l == 0) edge_done(a, s - 1u, tv.v, c);
                 }
-                // short tails: one lane per in-edge
-                for (uint32_t q = threadIdx.x; q < nshort; q += IS_NT) {
-                    const uint32_t k = s_short[q];
-                    const uint32_t s = s_start[k], e = s_end[k];
-                    uint32_t c = 0;
-                    for (uint32_t p = s; p < e; ++p) {
-                        const uint32_t x = a.col[p] - wlo;
-                        if (x < BM_BITS && ((bm[x >> 5] >> (x & 31u)) & 1u)) {
-                            ++c;
-                            hit_vertex(a, x + wlo);
-                        }
-                    }
-                    acc += c;
-                    edge_done(a, s - 1u, tv.v, c);
+                __syncthreads();
+                for (uint32_t j = threadIdx.x; j < nb; j += IS_NT) {
+                    const uint32_t x = a.col[b0 + j] - wlo;
+                    if (x < BM_BITS) bm[x >> 5] = 0u;
                 }
-            } else {
-                // several windows (N+(v) spans more than 2^17 ranks): one lane per
-                // in-edge; the per-edge output accumulates across windows
-                for (uint32_t k = threadIdx.x; k < ne; k += IS_NT) {
-                    const uint32_t s = s_start[k], e = s_end[k];
-                    uint32_t c = 0;
-                    for (uint32_t p = s; p < e; ++p) {
-                        const uint32_t x = a.col[p] - wlo;
-                        if (x < BM_BITS && ((bm[x >> 5] >> (x & 31u)) & 1u)) {
-                            ++c;
-                            hit_vertex(a, x + wlo);
-                        }
-                    }
-                    acc += c;
-                    // accumulate the per-edge count across windows in place
-                    if (a.per_edge) a.per_edge[s - 1u] = (win ? a.per_edge[s - 1u] : 0u) + c;
-                    if (a.per_vertex && c) {
-                        atomicAdd((unsigned long long*)&a.per_vertex[a.src[s - 1u]], (unsigned long long)c);
-                        atomicAdd((unsigned long long*)&a.per_vertex[tv.v], (unsigned long long)c);
-                    }
-                }
+                __syncthreads();
             }
-            __syncthreads();
-            for (uint32_t j = threadIdx.x; j < nb; j += IS_NT) {
-                const uint32_t x = a.col[tv.b0 + j];
-                if (x >= wlo && x - wlo < BM_BITS) bm[(x - wlo) >> 5] = 0u;
-            }
-            __syncthreads();
         }
     }
-    block_flush_total(a, acc);
+    block_partial(acc, partials);
 }
 
 // ------------------------------------------------------------------ shared helpers for edge-centric kernels
-// N+(v) is staged in LDS when it fits; otherwise it is read from global memory.
-struct ListRef {
-    const uint32_t* p;
-};
-
 // Number of elements of A taken in the first d outputs of the merge of A and
 // B, A first on ties (merge-path split, Green et al. / Odeh et al.).
 __device__ __forceinline__ uint32_t merge_split(const uint32_t* A, uint32_t na, const uint32_t* B, uint32_t nb,
@@ -200,63 +225,6 @@ __device__ __forceinline__ uint32_t merge_split(const uint32_t* A, uint32_t na, 
     return lo;
 }
 
-// ------------------------------------------------------------------ merge path
-__global__ __launch_bounds__(IS_NT) void k_isect_merge(IsectArgs a) {
-    __shared__ uint32_t sb[STAGE_MAX];
-    __shared__ uint32_t s_tile;
-    uint64_t acc = 0;
-    TileView tv;
-    while (next_tile(a, KER_MERGE, &s_tile, &tv)) {
-        const uint32_t nb = tv.b1 - tv.b0;
-        const bool staged = nb <= (uint32_t)STAGE_MAX;
-        if (staged)
-            for (uint32_t j = threadIdx.x; j < nb; j += IS_NT) sb[j] = a.col[tv.b0 + j];
-        __syncthreads();
-        const uint32_t* B = staged ? sb : a.col + tv.b0;
-        const uint32_t g = a.ctrl->group[a.vbucket[tv.v]];          // lanes per in-edge (power of 2)
-        const uint32_t gi = threadIdx.x / g, gl = threadIdx.x % g;  // group index, lane in group
-        const uint32_t ngroups = IS_NT / g;
-        const uint32_t ne = tv.e1 - tv.e0;
-        const uint32_t rounds = (ne + ngroups - 1) / ngroups;
-        for (uint32_t r = 0; r < rounds; ++r) {
-            const uint32_t k = r * ngroups + gi;
-            uint32_t c = 0, e = 0;
-            if (k < ne) {
-                const uint64_t ent = a.csc[tv.e0 + k];
-                e = (uint32_t)ent;
-                const uint32_t s = e + 1u, end = (uint32_t)(ent >> 32);
-                const uint32_t* A = a.col + s;
-                const uint32_t na = end - s;
-                const uint32_t tot = na + nb;
-                const uint32_t d0 = (uint32_t)(((uint64_t)tot * gl) / g);
-                const uint32_t d1 = (uint32_t)(((uint64_t)tot * (gl + 1u)) / g);
-                uint32_t i = merge_split(A, na, B, nb, d0);
-                uint32_t jb = d0 - i;
-                for (uint32_t step = d0; step < d1; ++step) {
-                    if (i < na && (jb >= nb || A[i] <= B[jb])) {
-                        if (jb < nb && A[i] == B[jb]) {
-                            ++c;
-                            hit_vertex(a, A[i]);
-                        }
-                        ++i;
-                    } else {
-                        ++jb;
-                    }
-                }
-            }
-            // reduce within the group of g lanes (g divides the wave)
-            for (uint32_t o = g >> 1; o > 0; o >>= 1) c += __shfl_xor(c, (int)o, WAVE);
-            if (k < ne && gl == 0) {
-                acc += c;
-                edge_done(a, e, tv.v, c);
-            }
-        }
-        __syncthreads();
-    }
-    block_flush_total(a, acc);
-}
-
-// ------------------------------------------------------------------ binary search
 __device__ __forceinline__ bool contains(const uint32_t* L, uint32_t n, uint32_t x) {
     uint32_t lo = 0, hi = n;
     while (lo < hi) {
@@ -267,59 +235,109 @@ __device__ __forceinline__ bool contains(const uint32_t* L, uint32_t n, uint32_t
     return lo < n && L[lo] == x;
 }
 
-__global__ __launch_bounds__(IS_NT) void k_isect_bsearch(IsectArgs a) {
+// Segment holding flattened in-edge q (largest sg with pref[sg] <= q).
+__device__ __forceinline__ uint32_t find_seg(const Segs& S, uint32_t nseg, uint32_t q) {
+    uint32_t lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (S.pref[mid] <= q) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One in-edge by a group of g lanes: merge path (MERGE) or binary search.
+template <bool MERGE>
+__device__ __forceinline__ uint32_t isect_edge(const IsectArgs& a, const uint32_t* A, uint32_t na, const uint32_t* B,
+                                               uint32_t nb, uint32_t g, uint32_t gl) {
+    uint32_t c = 0;
+    if (MERGE) {
+        const uint32_t tot = na + nb;
+        const uint32_t d0 = (uint32_t)(((uint64_t)tot * gl) / g);
+        const uint32_t d1 = (uint32_t)(((uint64_t)tot * (gl + 1u)) / g);
+        uint32_t i = merge_split(A, na, B, nb, d0);
+        uint32_t j = d0 - i;
+        for (uint32_t step = d0; step < d1; ++step) {
+            if (i < na && (j >= nb || A[i] <= B[j])) {
+                if (j < nb && A[i] == B[j]) {
+                    ++c;
+                    hit_vertex(a, A[i]);
+                }
+                ++i;
+            } else {
+                ++j;
+            }
+        }
+    } else if (na <= nb) {
+        for (uint32_t q = gl; q < na; q += g) {
+            const uint32_t x = A[q];
+            if (contains(B, nb, x)) {
+                ++c;
+                hit_vertex(a, x);
+            }
+        }
+    } else {
+        for (uint32_t q = gl; q < nb; q += g) {
+            const uint32_t x = B[q];
+            if (contains(A, na, x)) {
+                ++c;
+                hit_vertex(a, x);
+            }
+        }
+    }
+    return c;
+}
+
+template <bool MERGE>
+__global__ __launch_bounds__(IS_NT) void k_isect_edges(IsectArgs a, uint64_t* partials) {
     __shared__ uint32_t sb[STAGE_MAX];
-    __shared__ uint32_t s_tile;
+    __shared__ Segs S;
+    constexpr int KER = MERGE ? KER_MERGE : KER_BSEARCH;
     uint64_t acc = 0;
-    TileView tv;
-    while (next_tile(a, KER_BSEARCH, &s_tile, &tv)) {
-        const uint32_t nb = tv.b1 - tv.b0;
-        const bool staged = nb <= (uint32_t)STAGE_MAX;
+    const uint32_t t_end = a.ctrl->tile_begin[KER + 1];
+    for (uint32_t t = a.ctrl->tile_begin[KER] + blockIdx.x; t < t_end; t += gridDim.x) {
+        const uint32_t nseg = load_tile(a, t, S);
+        const uint32_t v0 = S.v[0];
+        const uint32_t nb0 = a.off[v0 + 1] - a.off[v0];
+        const bool staged = nseg == 1 && nb0 <= (uint32_t)STAGE_MAX;
         if (staged)
-            for (uint32_t j = threadIdx.x; j < nb; j += IS_NT) sb[j] = a.col[tv.b0 + j];
+            for (uint32_t j = threadIdx.x; j < nb0; j += IS_NT) sb[j] = a.col[a.off[v0] + j];
         __syncthreads();
-        const uint32_t* B = staged ? sb : a.col + tv.b0;
-        const uint32_t g = a.ctrl->group[a.vbucket[tv.v]];
-        const uint32_t gi = threadIdx.x / g, gl = threadIdx.x % g;
+        const uint32_t g = a.ctrl->group[a.vbucket[v0]];            // lanes per in-edge (power of 2)
+        const uint32_t gi = threadIdx.x / g, gl = threadIdx.x % g;  // group index, lane in group
         const uint32_t ngroups = IS_NT / g;
-        const uint32_t ne = tv.e1 - tv.e0;
+        const uint32_t ne = S.pref[nseg];
         const uint32_t rounds = (ne + ngroups - 1) / ngroups;
         for (uint32_t r = 0; r < rounds; ++r) {
-            const uint32_t k = r * ngroups + gi;
-            uint32_t c = 0, e = 0;
-            if (k < ne) {
-                const uint64_t ent = a.csc[tv.e0 + k];
-                e = (uint32_t)ent;
-                const uint32_t s = e + 1u, end = (uint32_t)(ent >> 32);
-                const uint32_t* A = a.col + s;
-                const uint32_t na = end - s;
-                if (na <= nb) {
-                    for (uint32_t q = gl; q < na; q += g) {
-                        const uint32_t x = A[q];
-                        if (contains(B, nb, x)) {
-                            ++c;
-                            hit_vertex(a, x);
-                        }
-                    }
-                } else {
-                    for (uint32_t q = gl; q < nb; q += g) {
-                        const uint32_t x = B[q];
-                        if (contains(A, na, x)) {
-                            ++c;
-                            hit_vertex(a, x);
-                        }
-                    }
-                }
+            const uint32_t q = r * ngroups + gi;
+            uint32_t c = 0, e = 0, v = 0;
+            if (q < ne) {
+                const uint32_t sg = nseg == 1 ? 0u : find_seg(S, nseg, q);
+                v = S.v[sg];
+                e = (uint32_t)a.csc[S.e0[sg] + (q - S.pref[sg])];
+                const uint32_t s = e + 1u, end = tail_end(a, e);
+                const uint32_t* B = staged ? sb : a.col + a.off[v];
+                const uint32_t nb = a.off[v + 1] - a.off[v];
+                c = isect_edge<MERGE>(a, a.col + s, end - s, B, nb, g, gl);
             }
+            // reduce within the group of g lanes (g divides the wave)
             for (uint32_t o = g >> 1; o > 0; o >>= 1) c += __shfl_xor(c, (int)o, WAVE);
-            if (k < ne && gl == 0) {
+            if (q < ne && gl == 0) {
                 acc += c;
-                edge_done(a, e, tv.v, c);
+                edge_done(a, e, v, c);
             }
         }
         __syncthreads();
     }
-    block_flush_total(a, acc);
+    block_partial(acc, partials);
+}
+
+// Sum of the per-block partial counts of all three kernels, in a fixed order.
+__global__ __launch_bounds__(IS_NT) void k_reduce_total(const uint64_t* __restrict__ partials, uint32_t count,
+                                                        Ctrl* ctrl) {
+    uint64_t acc = 0;
+    for (uint32_t i = threadIdx.x; i < count; i += IS_NT) acc += partials[i];
+    block_partial(acc, &ctrl->total);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -336,20 +354,25 @@ static int num_cu() {
     return g_num_cu;
 }
 
-int isect_blocks_per_cu(int ker) {
+int isect_blocks_per_cu(int ker) { return ker == KER_BITMAP ? 6 : 8; }
+
+size_t isect_partials_bytes() { return sizeof(uint64_t) * NKERNEL * PARTIALS_PER_KERNEL; }
+
+void launch_isect(int ker, const IsectArgs& a, int grid, uint64_t* partials, hipStream_t s) {
+    if (grid <= 0) grid = num_cu() * isect_blocks_per_cu(ker);
+    if (grid > PARTIALS_PER_KERNEL) grid = PARTIALS_PER_KERNEL;
+    uint64_t* p = partials + (size_t)ker * PARTIALS_PER_KERNEL;
+    fill_u64(p, 0ull, PARTIALS_PER_KERNEL, s);
     switch (ker) {
-        case KER_BITMAP: return 6;
-        default: return 8;
+        case KER_MERGE: hipLaunchKernelGGL(k_isect_edges<true>, dim3(grid), dim3(IS_NT), 0, s, a, p); break;
+        case KER_BSEARCH: hipLaunchKernelGGL(k_isect_edges<false>, dim3(grid), dim3(IS_NT), 0, s, a, p); break;
+        default: hipLaunchKernelGGL(k_isect_bitmap, dim3(grid), dim3(IS_NT), 0, s, a, p); break;
     }
 }
 
-void launch_isect(int ker, const IsectArgs& a, int grid, hipStream_t s) {
-    if (grid <= 0) grid = num_cu() * isect_blocks_per_cu(ker);
-    switch (ker) {
-        case KER_MERGE: hipLaunchKernelGGL(k_isect_merge, dim3(grid), dim3(IS_NT), 0, s, a); break;
-        case KER_BSEARCH: hipLaunchKernelGGL(k_isect_bsearch, dim3(grid), dim3(IS_NT), 0, s, a); break;
-        default: hipLaunchKernelGGL(k_isect_bitmap, dim3(grid), dim3(IS_NT), 0, s, a); break;
-    }
+void launch_reduce_total(uint64_t* partials, Ctrl* ctrl, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_total, dim3(1), dim3(IS_NT), 0, s, partials, (uint32_t)(NKERNEL * PARTIALS_PER_KERNEL),
+                       ctrl);
 }
 
 }  // namespace tcx

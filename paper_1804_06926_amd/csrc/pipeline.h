@@ -11,11 +11,11 @@ namespace tcx {
 
 enum { SEL_HEURISTIC = 0, SEL_LEARNED = 1, SEL_FORCE_MERGE = 2, SEL_FORCE_BSEARCH = 3, SEL_FORCE_BITMAP = 4 };
 
-constexpr int NSTAGE = 11;
+constexpr int NSTAGE = 12;
 
 struct Layout {
-    size_t ctrl, deg, rank, inv, vbucket, pos_of, vlist, cursor, seg, tstart, off, rowend, pv;
-    size_t keysA, keysB, col, src, tiles, partial, scan_tmp, radix_tmp;
+    size_t ctrl, deg, rank, inv, vbucket, vlist, tstart, off, inoff, rowend, pv;
+    size_t vkeysA, vkeysB, keysA, keysB, col, src, tiles, partial, isect_partials, scan_tmp, radix_tmp;
     size_t tile_cap;
     size_t total;
 };

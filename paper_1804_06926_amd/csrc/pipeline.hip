@@ -3,17 +3,20 @@
 //
 // Stages (Algorithm 2; Section 4.2 for the filter, the induced subgraph and
 // dynamic grouping):
-//   degree    validate ids, canonicalise, count incidences (self-loops dropped)
+//   degree    validate ids, count input pairs per vertex (self-loops dropped)
 //   rank      sort vertices by (degree, id): rank = position
-//   orient    keep each pair once as (rank lo, rank hi), compacted
+//   orient    each pair as (rank lo, rank hi); loops / bad ids -> sentinel
 //   sort      radix sort of the oriented pairs -> rows contiguous, ascending
-//   csr       drop repeated pairs, emit col/src and row offsets
-//   bucket    per middle vertex v: (in-edges with a non-empty tail, |N+(v)|)
+//   csr       drop repeats and sentinels, emit col/src, row offsets
+//   csc       in-edges (u -> v) with a non-empty tail of row u, grouped by v
+//             (stable radix sort on v), in-offsets from the group boundaries
+//   bucket    per middle vertex v: (in-edges with work, |N+(v)|) -> bucket
 //   select    choose the intersection strategy and tile shape per bucket
-//   group     order vertices by (strategy, bucket); lay out in-edge segments
-//             and tiles; scatter in-edges into their segments
+//   group     order vertices by (strategy, bucket); emit tiles
 //   isect     the three intersection kernels, each over its tile range
 //   finish    map per-vertex / per-edge outputs back to original ids
+// No stage relies on atomics to one address: compaction and grouping go
+// through sorts and scans, so every intermediate array is deterministic.
 #include <string.h>
 
 #include "common.h"
@@ -62,44 +65,53 @@ __global__ __launch_bounds__(NT) void k_rank(const uint64_t* __restrict__ sorted
 }
 
 // ------------------------------------------------------------------ orient (filter by degree order)
-// Pairs become (lo rank << nb) | hi rank; loops and invalid ids are dropped.
-// Compaction: one atomic per wave reserves room for the wave's valid pairs.
+// Pair -> (lo rank << nb) | hi rank. Loops and invalid ids become the all-ones
+// sentinel on 2*nb bits, which exceeds every valid key (lo rank <= n - 2).
 __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, uint64_t E, int32_t n,
-                                               const uint32_t* __restrict__ rank, int nb,
-                                               uint64_t* __restrict__ keys, Ctrl* ctrl) {
-    const uint64_t stride = (uint64_t)gridDim.x * NT;
-    const uint64_t first = (uint64_t)blockIdx.x * NT + (threadIdx.x & ~(uint64_t)(WAVE - 1));
-    for (uint64_t wbase = first; wbase < E; wbase += stride) {
-        const uint64_t i = wbase + lane_id();
-        bool valid = false;
-        uint64_t key = 0;
-        if (i < E) {
-            const int2 e = edges[i];
-            if (e.x >= 0 && e.x < n && e.y >= 0 && e.y < n && e.x != e.y) {
-                const uint32_t a = rank[e.x], b = rank[e.y];
-                const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-                key = ((uint64_t)lo << nb) | hi;
-                valid = true;
-            }
+                                               const uint32_t* __restrict__ rank, int nb, uint64_t sentinel,
+                                               uint64_t* __restrict__ keys) {
+    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < E; i += (uint64_t)gridDim.x * NT) {
+        const int2 e = edges[i];
+        uint64_t key = sentinel;
+        if (e.x >= 0 && e.x < n && e.y >= 0 && e.y < n && e.x != e.y) {
+            const uint32_t a = rank[e.x], b = rank[e.y];
+            const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+            key = ((uint64_t)lo << nb) | hi;
         }
-        const uint64_t mask = __ballot(valid);
-        uint32_t base = 0;
-        if (lane_id() == 0 && mask) base = atomicAdd(&ctrl->m_valid, (uint32_t)__popcll(mask));
-        base = __shfl(base, 0, WAVE);
-        if (valid) keys[base + __popcll(mask & lanes_below())] = key;
+        keys[i] = key;
     }
 }
 
 // ------------------------------------------------------------------ unique + CSR
 constexpr int UQ_MAX_BLOCKS = 1024;
 
-__global__ __launch_bounds__(NT) void k_unique_count(const uint64_t* __restrict__ keys, const Ctrl* ctrl,
+struct Chunking {
+    uint32_t nblk, chunk;
+};
+
+static Chunking chunking(uint64_t len) {
+    uint32_t nblk = (uint32_t)((len + 8191) / 8192);
+    if (nblk > (uint32_t)UQ_MAX_BLOCKS) nblk = UQ_MAX_BLOCKS;
+    if (nblk < 1) nblk = 1;
+    uint32_t chunk = (uint32_t)((len + nblk - 1) / nblk);
+    chunk = (chunk + NT - 1) / NT * NT;
+    if (chunk == 0) chunk = NT;
+    nblk = (uint32_t)((len + chunk - 1) / chunk);
+    if (nblk < 1) nblk = 1;
+    return {nblk, chunk};
+}
+
+__device__ __forceinline__ bool keep_key(const uint64_t* keys, uint64_t i, uint64_t sentinel) {
+    const uint64_t k = keys[i];
+    return k != sentinel && (i == 0 || k != keys[i - 1]);
+}
+
+__global__ __launch_bounds__(NT) void k_unique_count(const uint64_t* __restrict__ keys, uint64_t E, uint64_t sentinel,
                                                      uint32_t chunk, uint32_t* __restrict__ partial, uint32_t nblk) {
-    const uint32_t mv = ctrl->m_valid;
     const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
-    const uint64_t b1 = b0 + chunk < mv ? b0 + chunk : mv;
+    const uint64_t b1 = b0 + chunk < E ? b0 + chunk : E;
     uint32_t c = 0;
-    for (uint64_t i = b0 + threadIdx.x; i < b1; i += NT) c += (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+    for (uint64_t i = b0 + threadIdx.x; i < b1; i += NT) c += keep_key(keys, i, sentinel) ? 1u : 0u;
     c = wave_sum(c);
     __shared__ uint32_t red[NT / WAVE];
     if (lane_id() == 0) red[wave_id()] = c;
@@ -112,20 +124,21 @@ __global__ __launch_bounds__(NT) void k_unique_count(const uint64_t* __restrict_
     }
 }
 
-__global__ __launch_bounds__(NT) void k_unique_write(const uint64_t* __restrict__ keys, Ctrl* ctrl, uint32_t chunk,
-                                                     const uint32_t* __restrict__ partial, uint32_t nblk, int nb,
-                                                     uint32_t* __restrict__ col, uint32_t* __restrict__ src,
-                                                     uint32_t* __restrict__ rowend) {
+// Keeps the first of every run of equal keys; rowend[s] = number of kept keys
+// up to and including the last key of row s.
+__global__ __launch_bounds__(NT) void k_unique_write(const uint64_t* __restrict__ keys, uint64_t E, uint64_t sentinel,
+                                                     Ctrl* ctrl, uint32_t chunk, const uint32_t* __restrict__ partial,
+                                                     uint32_t nblk, int nb, uint32_t* __restrict__ col,
+                                                     uint32_t* __restrict__ src, uint32_t* __restrict__ rowend) {
     __shared__ uint32_t scratch[NT / WAVE];
-    const uint32_t mv = ctrl->m_valid;
     const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
-    const uint64_t b1 = b0 + chunk < mv ? b0 + chunk : mv;
-    const uint64_t lowmask = (nb >= 64) ? ~0ull : ((1ull << nb) - 1ull);
+    const uint64_t b1 = b0 + chunk < E ? b0 + chunk : E;
+    const uint64_t lowmask = (1ull << nb) - 1ull;
     uint32_t carry = partial[blockIdx.x];
     if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->m = partial[nblk];
     for (uint64_t base = b0; base < b1; base += NT) {
         const uint64_t i = base + threadIdx.x;
-        const bool valid = i < b1;
+        const bool valid = i < b1 && keys[i] != sentinel;
         uint64_t key = 0;
         uint32_t keep = 0;
         if (valid) {
@@ -141,23 +154,41 @@ __global__ __launch_bounds__(NT) void k_unique_write(const uint64_t* __restrict_
                 col[pos] = (uint32_t)(key & lowmask);
                 src[pos] = s;
             }
-            if (i + 1 == mv || (uint32_t)(keys[i + 1] >> nb) != s) rowend[s] = pos + keep;
+            // the sentinel's row differs from every valid row
+            if (i + 1 == E || (uint32_t)(keys[i + 1] >> nb) != s) rowend[s] = pos + keep;
         }
         carry += total;
     }
 }
 
-// ------------------------------------------------------------------ buckets
-__global__ __launch_bounds__(NT) void k_indeg(const uint32_t* __restrict__ col, const uint32_t* __restrict__ src,
-                                              const uint32_t* __restrict__ off, const Ctrl* ctrl,
-                                              uint32_t* __restrict__ indeg) {
+// ------------------------------------------------------------------ CSC (in-edges grouped by v)
+// Key = v << 32 | e for in-edges with work; others get v = n and sort last.
+__global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ col, const uint32_t* __restrict__ src,
+                                                 const uint32_t* __restrict__ off, const Ctrl* ctrl, int32_t n,
+                                                 uint64_t* __restrict__ keys) {
     const uint32_t m = ctrl->m;
     for (uint64_t e = (uint64_t)blockIdx.x * NT + threadIdx.x; e < m; e += (uint64_t)gridDim.x * NT) {
-        const uint32_t s = src[e];
-        if (e + 1 < off[s + 1]) atomicAdd(&indeg[col[e]], 1u);
+        const uint32_t v = col[e];
+        const bool work = (e + 1 < off[src[e] + 1]) && (off[v + 1] > off[v]);
+        keys[e] = ((uint64_t)(work ? v : (uint32_t)n) << 32) | (uint32_t)e;
     }
 }
 
+// inend[v] = one past the last in-edge of v in the sorted order; m_active.
+__global__ __launch_bounds__(NT) void k_csc_bounds(const uint64_t* __restrict__ keys, Ctrl* ctrl, int32_t n,
+                                                   uint32_t* __restrict__ inend) {
+    const uint32_t m = ctrl->m;
+    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < m; i += (uint64_t)gridDim.x * NT) {
+        const uint32_t v = (uint32_t)(keys[i] >> 32);
+        const uint32_t vn = i + 1 < m ? (uint32_t)(keys[i + 1] >> 32) : (uint32_t)n;
+        if (v < (uint32_t)n && vn != v) {
+            inend[v] = (uint32_t)(i + 1);
+            if (vn == (uint32_t)n) ctrl->m_active = (uint32_t)(i + 1);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ buckets
 __device__ __forceinline__ uint32_t bucket_of(uint32_t din, uint32_t dout) {
     if (din == 0 || dout == 0) return BUCKET_NONE;
     const uint32_t li = min(14, floor_log2(din));
@@ -165,14 +196,14 @@ __device__ __forceinline__ uint32_t bucket_of(uint32_t din, uint32_t dout) {
     return 16u * li + lo;
 }
 
-__global__ __launch_bounds__(NT) void k_vbucket(const uint32_t* __restrict__ off, const uint32_t* __restrict__ indeg,
+__global__ __launch_bounds__(NT) void k_vbucket(const uint32_t* __restrict__ off, const uint32_t* __restrict__ inoff,
                                                 int32_t n, uint8_t* __restrict__ vbucket, Ctrl* ctrl) {
     __shared__ uint32_t s_nv[NBUCKET];
     __shared__ unsigned long long s_in[NBUCKET], s_out[NBUCKET], s_work[NBUCKET];
     for (int b = threadIdx.x; b < NBUCKET; b += NT) { s_nv[b] = 0; s_in[b] = 0; s_out[b] = 0; s_work[b] = 0; }
     __syncthreads();
     for (int64_t v = (int64_t)blockIdx.x * NT + threadIdx.x; v < n; v += (int64_t)gridDim.x * NT) {
-        const uint32_t din = indeg[v], dout = off[v + 1] - off[v];
+        const uint32_t din = inoff[v + 1] - inoff[v], dout = off[v + 1] - off[v];
         const uint32_t b = bucket_of(din, dout);
         vbucket[v] = (uint8_t)b;
         if (b != BUCKET_NONE) {
@@ -217,13 +248,13 @@ __global__ __launch_bounds__(NBUCKET) void k_select(Ctrl* ctrl, int mode, const 
     else if (mode == SEL_FORCE_BITMAP) ch = KER_BITMAP;
     else if (mode == SEL_LEARNED && learned) ch = learned[b] < NKERNEL ? learned[b] : heuristic_choice(b);
     else ch = heuristic_choice(b);
-    const int lo = b & 15;
+    const int lo = b & 15, li = b >> 4;
     // tile shape: in-edges per tile and lanes per in-edge
     uint32_t chunk = (ch == KER_BITMAP) ? 256u : 128u;
     uint32_t group = lo >= 9 ? 64u : (lo >= 3 ? (1u << (lo - 3)) : 1u);
     if (chunk_override && chunk_override[b]) chunk = chunk_override[b];
     if (group_override && group_override[b]) group = group_override[b];
-    if (ch == KER_BITMAP && chunk > (uint32_t)CHUNK_MAX) chunk = CHUNK_MAX;
+    if (chunk > (uint32_t)CHUNK_MAX) chunk = CHUNK_MAX;
     if (chunk < 16u) chunk = 16u;
     if (group > 64u || (group & (group - 1u))) group = 64u;
     if (group < 1u) group = 1u;
@@ -231,13 +262,23 @@ __global__ __launch_bounds__(NBUCKET) void k_select(Ctrl* ctrl, int mode, const 
     ctrl->chunk[b] = (uint16_t)chunk;
     ctrl->group[b] = (uint8_t)group;
     // slot order: (kernel, heavier tiles first); the empty bucket last
-    const int li = b >> 4;
     const uint32_t key = (b == BUCKET_NONE) ? 0xFFFFFFFFu : ((uint32_t)ch << 16) | (uint32_t)(255 - (16 * lo + li));
     s_key[b] = key;
     __syncthreads();
     uint32_t r = 0;
     for (int q = 0; q < NBUCKET; ++q) r += (s_key[q] < key || (s_key[q] == key && q < b)) ? 1u : 0u;
     ctrl->slot[b] = (uint8_t)r;
+}
+
+// Vertices per multi-vertex tile for bucket b (1 = chunks of single vertices).
+__device__ __forceinline__ uint32_t tile_group(const Ctrl* ctrl, uint32_t b) {
+    const uint32_t li = b >> 4;
+    if (li >= 14) return 1u;
+    const uint32_t maxin = 2u << li;   // in-degrees of the bucket are below this
+    const uint32_t K = ctrl->chunk[b];
+    if (2u * maxin > K) return 1u;
+    const uint32_t g = K / maxin;
+    return g > (uint32_t)SEG_MAX ? (uint32_t)SEG_MAX : g;
 }
 
 __global__ __launch_bounds__(NT) void k_vkeys_slot(const uint8_t* __restrict__ vbucket, int32_t n, const Ctrl* ctrl,
@@ -247,21 +288,38 @@ __global__ __launch_bounds__(NT) void k_vkeys_slot(const uint8_t* __restrict__ v
 }
 
 __global__ __launch_bounds__(NT) void k_vpos(const uint64_t* __restrict__ sorted, int32_t n,
-                                             const uint8_t* __restrict__ vbucket, const uint32_t* __restrict__ indeg,
-                                             const Ctrl* ctrl, uint32_t* __restrict__ vlist,
-                                             uint32_t* __restrict__ pos_of, uint32_t* __restrict__ seg,
-                                             uint32_t* __restrict__ ntile) {
+                                             const uint8_t* __restrict__ vbucket, Ctrl* ctrl,
+                                             uint32_t* __restrict__ vlist) {
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
         const uint32_t v = (uint32_t)sorted[i];
-        const uint32_t b = vbucket[v];
+        const uint32_t slot = (uint32_t)(sorted[i] >> 32);
         vlist[i] = v;
-        pos_of[v] = (uint32_t)i;
-        const uint32_t din = b == BUCKET_NONE ? 0u : indeg[v];
-        const uint32_t K = ctrl->chunk[b];
-        seg[i] = din;
-        ntile[i] = din ? (din + K - 1) / K : 0u;
+        const uint32_t b = vbucket[v];
+        if (i == 0 || (uint32_t)(sorted[i - 1] >> 32) != slot) ctrl->bstart[b] = (uint32_t)i;
+        if (i == n - 1 || (uint32_t)(sorted[i + 1] >> 32) != slot) ctrl->bend[b] = (uint32_t)(i + 1);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) { seg[n] = 0; ntile[n] = 0; }
+}
+
+__global__ __launch_bounds__(NT) void k_ntiles(const uint32_t* __restrict__ vlist, const uint8_t* __restrict__ vbucket,
+                                               const uint32_t* __restrict__ inoff, int32_t n, const Ctrl* ctrl,
+                                               uint32_t* __restrict__ ntile) {
+    for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
+        const uint32_t v = vlist[i];
+        const uint32_t b = vbucket[v];
+        uint32_t t = 0;
+        if (b != BUCKET_NONE) {
+            const uint32_t g = tile_group(ctrl, b);
+            if (g > 1) {
+                t = ((uint32_t)i - ctrl->bstart[b]) % g == 0 ? 1u : 0u;
+            } else {
+                const uint32_t din = inoff[v + 1] - inoff[v];
+                const uint32_t K = ctrl->chunk[b];
+                t = (din + K - 1) / K;
+            }
+        }
+        ntile[i] = t;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ntile[n] = 0;
 }
 
 __global__ __launch_bounds__(NT) void k_emit_tiles(const uint32_t* __restrict__ vlist,
@@ -277,28 +335,21 @@ __global__ __launch_bounds__(NT) void k_emit_tiles(const uint32_t* __restrict__ 
             kprev = bp == BUCKET_NONE ? NKERNEL : ctrl->choice[bp];
         }
         const uint32_t t0 = tstart[i], t1 = tstart[i + 1];
-        for (uint32_t t = t0; t < t1 && t < tile_cap; ++t) tiles[t] = (uint64_t)(uint32_t)i | ((uint64_t)(t - t0) << 32);
+        if (t1 > t0 && b != BUCKET_NONE) {
+            const uint32_t g = tile_group(ctrl, b);
+            if (g > 1) {
+                const uint32_t cnt = min(g, ctrl->bend[b] - (uint32_t)i);
+                if (t0 < tile_cap) tiles[t0] = (uint64_t)(uint32_t)i | ((uint64_t)(TILE_MULTI | cnt) << 32);
+            } else {
+                for (uint32_t t = t0; t < t1 && t < tile_cap; ++t)
+                    tiles[t] = (uint64_t)(uint32_t)i | ((uint64_t)(t - t0) << 32);
+            }
+        }
         for (int k = kprev + 1; k <= kk; ++k) ctrl->tile_begin[k] = t0;
         if (i == n - 1) {
             for (int k = kk + 1; k <= NKERNEL; ++k) ctrl->tile_begin[k] = tstart[n];
             ctrl->ntiles = tstart[n];
         }
-    }
-}
-
-__global__ __launch_bounds__(NT) void k_csc(const uint32_t* __restrict__ col, const uint32_t* __restrict__ src,
-                                            const uint32_t* __restrict__ off, const Ctrl* ctrl,
-                                            const uint8_t* __restrict__ vbucket, const uint32_t* __restrict__ pos_of,
-                                            const uint32_t* __restrict__ seg_start, uint32_t* __restrict__ cursor,
-                                            uint64_t* __restrict__ csc, uint64_t cap) {
-    const uint32_t m = ctrl->m;
-    for (uint64_t e = (uint64_t)blockIdx.x * NT + threadIdx.x; e < m; e += (uint64_t)gridDim.x * NT) {
-        const uint32_t end = off[src[e] + 1];
-        if (e + 1 >= end) continue;
-        const uint32_t v = col[e];
-        if (vbucket[v] == BUCKET_NONE) continue;
-        const uint32_t slot = seg_start[pos_of[v]] + atomicAdd(&cursor[v], 1u);
-        if (slot < cap) csc[slot] = (uint64_t)e | ((uint64_t)end << 32);
     }
 }
 
@@ -342,14 +393,14 @@ Layout make_layout(int64_t E, int32_t n) {
     L.rank = take(4 * nn);
     L.inv = take(4 * nn);
     L.vbucket = take(nn);
-    L.pos_of = take(4 * nn);
     L.vlist = take(4 * nn);
-    L.cursor = take(4 * nn);
-    L.seg = take(4 * (nn + 1));
     L.tstart = take(4 * (nn + 1));
     L.off = take(4 * (nn + 1));
+    L.inoff = take(4 * (nn + 1));
     L.rowend = take(4 * nn);
     L.pv = take(8 * nn);
+    L.vkeysA = take(8 * nn);
+    L.vkeysB = take(8 * nn);
     L.keysA = take(8 * kcap);
     L.keysB = take(8 * kcap);
     L.col = take(4 * ee);
@@ -357,6 +408,7 @@ Layout make_layout(int64_t E, int32_t n) {
     L.tile_cap = ee / 16 + nn + 1;
     L.tiles = take(8 * L.tile_cap);
     L.partial = take(4 * (UQ_MAX_BLOCKS + 1));
+    L.isect_partials = take(isect_partials_bytes());
     L.scan_tmp = take(scan_temp_bytes());
     L.radix_tmp = take(radix_temp_bytes(kcap));
     L.total = o;
@@ -366,7 +418,7 @@ Layout make_layout(int64_t E, int32_t n) {
 // ------------------------------------------------------------------ the pipeline
 int stage_count() { return NSTAGE; }
 const char* stage_name(int s) {
-    static const char* names[NSTAGE] = {"degree", "rank", "orient", "sort", "csr", "bucket",
+    static const char* names[NSTAGE] = {"degree", "rank", "orient", "sort", "csr", "csc", "bucket",
                                         "group", "isect_merge", "isect_bsearch", "isect_bitmap", "finish"};
     return (s >= 0 && s < NSTAGE) ? names[s] : "";
 }
@@ -382,14 +434,14 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     uint32_t* rank = (uint32_t*)(ws + L.rank);
     uint32_t* inv = (uint32_t*)(ws + L.inv);
     uint8_t* vbucket = (uint8_t*)(ws + L.vbucket);
-    uint32_t* pos_of = (uint32_t*)(ws + L.pos_of);
     uint32_t* vlist = (uint32_t*)(ws + L.vlist);
-    uint32_t* cursor = (uint32_t*)(ws + L.cursor);
-    uint32_t* seg = (uint32_t*)(ws + L.seg);
     uint32_t* tstart = (uint32_t*)(ws + L.tstart);
     uint32_t* off = (uint32_t*)(ws + L.off);
+    uint32_t* inoff = (uint32_t*)(ws + L.inoff);
     uint32_t* rowend = (uint32_t*)(ws + L.rowend);
     uint64_t* pv = (uint64_t*)(ws + L.pv);
+    uint64_t* vkeysA = (uint64_t*)(ws + L.vkeysA);
+    uint64_t* vkeysB = (uint64_t*)(ws + L.vkeysB);
     uint64_t* keysA = (uint64_t*)(ws + L.keysA);
     uint64_t* keysB = (uint64_t*)(ws + L.keysB);
     uint32_t* col = (uint32_t*)(ws + L.col);
@@ -402,46 +454,43 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     const size_t kcap = (size_t)(E > n ? E : n);
 
     auto mark = [&](int stage) {
-        if (r.events) hipEventRecord(r.events[stage], s);
+        if (r.events) (void)hipEventRecord(r.events[stage], s);
     };
     mark(0);
-    // ---- degree
+    // ---- degree: input pairs per vertex
     fill_u32((uint32_t*)ctrl, 0u, sizeof(Ctrl) / 4, s);
     fill_u32(deg, 0u, (size_t)n, s);
     hipLaunchKernelGGL(k_degree, dim3(grid_for((size_t)E)), dim3(NT), 0, s, edges, (uint64_t)E, n, deg, ctrl);
     mark(1);
-    // ---- rank: sort (degree, id); degrees of a multigraph are < 2E + 1
-    hipLaunchKernelGGL(k_vertex_keys, dim3(grid_for((size_t)n)), dim3(NT), 0, s, deg, n, keysA);
+    // ---- rank: sort (degree, id); degrees are below 2E + 1
+    hipLaunchKernelGGL(k_vertex_keys, dim3(grid_for((size_t)n)), dim3(NT), 0, s, deg, n, vkeysA);
     {
         const int dbits = bits_for((uint64_t)2 * (uint64_t)E + 1);
-        const int alt = radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)n, 32, 32 + dbits,
+        const int alt = radix_sort_u64(vkeysA, vkeysB, nullptr, nullptr, nullptr, (size_t)n, 32, 32 + dbits,
                                        radix_tmp, s);
-        hipLaunchKernelGGL(k_rank, dim3(grid_for((size_t)n)), dim3(NT), 0, s, alt ? keysB : keysA, n, rank, inv);
+        hipLaunchKernelGGL(k_rank, dim3(grid_for((size_t)n)), dim3(NT), 0, s, alt ? vkeysB : vkeysA, n, rank, inv);
     }
     mark(2);
     // ---- orient
-    const int nb = bits_for((uint64_t)n);
-    hipLaunchKernelGGL(k_orient, dim3(grid_for((size_t)E)), dim3(NT), 0, s, edges, (uint64_t)E, n, rank, nb, keysA,
-                       ctrl);
+    const int nb = bits_for((uint64_t)n) > 0 ? bits_for((uint64_t)n) : 1;
+    const uint64_t sentinel = (2 * nb >= 64) ? ~0ull : ((1ull << (2 * nb)) - 1ull);
+    hipLaunchKernelGGL(k_orient, dim3(grid_for((size_t)E)), dim3(NT), 0, s, edges, (uint64_t)E, n, rank, nb, sentinel,
+                       keysA);
     mark(3);
     // ---- sort oriented pairs
-    const int alt = radix_sort_u64(keysA, keysB, nullptr, nullptr, &ctrl->m_valid, (size_t)E, 0, 2 * nb, radix_tmp, s);
+    const int alt = radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)E, 0, 2 * nb, radix_tmp, s);
     uint64_t* sorted = alt ? keysB : keysA;
+    uint64_t* other = alt ? keysA : keysB;
     mark(4);
     // ---- unique + CSR
     {
-        uint32_t nblk = (uint32_t)((E + 8191) / 8192);
-        if (nblk > (uint32_t)UQ_MAX_BLOCKS) nblk = UQ_MAX_BLOCKS;
-        if (nblk < 1) nblk = 1;
-        uint32_t chunk = (uint32_t)(((uint64_t)E + nblk - 1) / nblk);
-        chunk = (chunk + NT - 1) / NT * NT;
-        nblk = (uint32_t)(((uint64_t)E + chunk - 1) / chunk);
-        if (nblk < 1) nblk = 1;
-        hipLaunchKernelGGL(k_unique_count, dim3(nblk), dim3(NT), 0, s, sorted, ctrl, chunk, partial, nblk);
-        scan_exclusive_sum_u32(partial, partial, (size_t)nblk + 1, scan_tmp, s);
+        const Chunking c = chunking((uint64_t)E);
+        hipLaunchKernelGGL(k_unique_count, dim3(c.nblk), dim3(NT), 0, s, sorted, (uint64_t)E, sentinel, c.chunk,
+                           partial, c.nblk);
+        scan_exclusive_sum_u32(partial, partial, (size_t)c.nblk + 1, scan_tmp, s);
         fill_u32(rowend, 0u, (size_t)n, s);
-        hipLaunchKernelGGL(k_unique_write, dim3(nblk), dim3(NT), 0, s, sorted, ctrl, chunk, partial, nblk, nb, col,
-                           src, rowend);
+        hipLaunchKernelGGL(k_unique_write, dim3(c.nblk), dim3(NT), 0, s, sorted, (uint64_t)E, sentinel, ctrl, c.chunk,
+                           partial, c.nblk, nb, col, src, rowend);
         fill_u32(off, 0u, 1, s);
         scan_inclusive_max_u32(rowend, off + 1, (size_t)n, scan_tmp, s);
     }
@@ -452,31 +501,35 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         out->ctrl_dev = ctrl;
         return hipGetLastError();
     }
-    // ---- buckets (deg is reused for in-degrees)
-    fill_u32(deg, 0u, (size_t)n, s);
-    hipLaunchKernelGGL(k_indeg, dim3(grid_for((size_t)E)), dim3(NT), 0, s, col, src, off, ctrl, deg);
-    hipLaunchKernelGGL(k_vbucket, dim3(grid_for((size_t)n, 2048)), dim3(NT), 0, s, off, deg, n, vbucket, ctrl);
+    // ---- CSC: in-edges with work grouped by v (the sorted pair keys are free now)
+    hipLaunchKernelGGL(k_csc_keys, dim3(grid_for((size_t)E)), dim3(NT), 0, s, col, src, off, ctrl, n, other);
+    const int nbv = bits_for((uint64_t)n + 1);
+    const int alt2 = radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, 32, 32 + nbv, radix_tmp, s);
+    uint64_t* csc = alt2 ? sorted : other;
+    fill_u32(rowend, 0u, (size_t)n, s);
+    hipLaunchKernelGGL(k_csc_bounds, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, n, rowend);
+    fill_u32(inoff, 0u, 1, s);
+    scan_inclusive_max_u32(rowend, inoff + 1, (size_t)n, scan_tmp, s);
+    mark(6);
+    // ---- buckets + selection
+    hipLaunchKernelGGL(k_vbucket, dim3(grid_for((size_t)n, 2048)), dim3(NT), 0, s, off, inoff, n, vbucket, ctrl);
     hipLaunchKernelGGL(k_select, dim3(1), dim3(NBUCKET), 0, s, ctrl, r.select, r.learned, r.chunk_override,
                        r.group_override);
-    mark(6);
-    // ---- group: order vertices by (kernel, bucket), segments, tiles, in-edge scatter
-    hipLaunchKernelGGL(k_vkeys_slot, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vbucket, n, ctrl, keysA);
+    mark(7);
+    // ---- group: order vertices by (kernel, bucket); tiles
+    hipLaunchKernelGGL(k_vkeys_slot, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vbucket, n, ctrl, vkeysA);
     {
-        const int a2 = radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)n, 32, 40, radix_tmp, s);
-        hipLaunchKernelGGL(k_vpos, dim3(grid_for((size_t)n)), dim3(NT), 0, s, a2 ? keysB : keysA, n, vbucket, deg,
-                           ctrl, vlist, pos_of, seg, tstart);
+        const int a3 = radix_sort_u64(vkeysA, vkeysB, nullptr, nullptr, nullptr, (size_t)n, 32, 40, radix_tmp, s);
+        hipLaunchKernelGGL(k_vpos, dim3(grid_for((size_t)n)), dim3(NT), 0, s, a3 ? vkeysB : vkeysA, n, vbucket, ctrl,
+                           vlist);
     }
-    scan_exclusive_sum_u32(seg, seg, (size_t)n + 1, scan_tmp, s);
+    hipLaunchKernelGGL(k_ntiles, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vlist, vbucket, inoff, n, ctrl, tstart);
     scan_exclusive_sum_u32(tstart, tstart, (size_t)n + 1, scan_tmp, s);
     hipLaunchKernelGGL(k_emit_tiles, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vlist, vbucket, tstart, n, ctrl,
                        tiles, (uint64_t)L.tile_cap);
-    fill_u32(cursor, 0u, (size_t)n, s);
-    uint64_t* csc = keysA;   // the vertex keys are no longer needed
-    hipLaunchKernelGGL(k_csc, dim3(grid_for((size_t)E)), dim3(NT), 0, s, col, src, off, ctrl, vbucket, pos_of, seg,
-                       cursor, csc, (uint64_t)kcap);
     if (r.per_edge_counts) fill_u32(r.per_edge_counts, 0u, (size_t)E, s);
     if (r.per_vertex) fill_u64(pv, 0ull, (size_t)n, s);
-    mark(7);
+    mark(8);
     // ---- intersections
     IsectArgs ia;
     ia.ctrl = ctrl;
@@ -484,18 +537,20 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     ia.col = col;
     ia.src = src;
     ia.csc = csc;
-    ia.seg_start = seg;
+    ia.inoff = inoff;
     ia.vlist = vlist;
     ia.vbucket = vbucket;
     ia.tiles = tiles;
     ia.per_edge = r.per_edge_counts;
     ia.per_vertex = r.per_vertex ? pv : nullptr;
+    uint64_t* partials = (uint64_t*)(ws + L.isect_partials);
     const int order[NKERNEL] = {KER_MERGE, KER_BSEARCH, KER_BITMAP};
     for (int q = 0; q < NKERNEL; ++q) {
         const int k = order[q];
-        launch_isect(k, ia, r.grid_override ? r.grid_override[k] : 0, s);
-        mark(8 + q);
+        launch_isect(k, ia, r.grid_override ? r.grid_override[k] : 0, partials, s);
+        mark(9 + q);
     }
+    launch_reduce_total(partials, ctrl, s);
     // ---- finish
     if (r.per_vertex)
         hipLaunchKernelGGL(k_map_pv, dim3(grid_for((size_t)n)), dim3(NT), 0, s, pv, inv, n, r.per_vertex);

@@ -184,7 +184,8 @@ __device__ __forceinline__ uint32_t rs_count(const uint32_t* d_count, uint32_t c
 
 // Per-tile digit counts, written digit-major: hist[d * ntiles + tile].
 __global__ __launch_bounds__(RS_NT) void k_radix_hist(const uint64_t* __restrict__ keys, const uint32_t* d_count,
-                                                      uint32_t cap, int shift, uint32_t* __restrict__ hist,
+                                                      uint32_t cap, int shift, uint32_t dmask,
+                                                      uint32_t* __restrict__ hist,
                                                       uint32_t ntiles) {
     __shared__ uint32_t wcnt[RS_WAVES][256];
     for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const uint64_t* __restrict
     for (int it = 0; it < RS_ITEMS; ++it) {
         const uint32_t i = base + it * WAVE + l;
         const bool valid = i < n;
-        const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & 255u : 0u;
+        const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & dmask : 0u;
         const uint64_t peers = match_digit8(d, __ballot(valid));
         if (valid && (peers & lanes_below()) == 0) wcnt[w][d] += (uint32_t)__popcll(peers);
     }
@@ -213,6 +214,7 @@ __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const uint64_t* __restr
                                                          const uint32_t* __restrict__ vin,
                                                          uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          const uint32_t* d_count, uint32_t cap, int shift,
+                                                         uint32_t dmask,
                                                          const uint32_t* __restrict__ hist_scan, uint32_t ntiles) {
     __shared__ uint32_t wcnt[RS_WAVES][256];
     __shared__ uint32_t lstart[256];
@@ -235,7 +237,7 @@ __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const uint64_t* __restr
         const bool valid = i < n;
         k[it] = valid ? kin[i] : 0ull;
         if (HAS_VAL) v[it] = valid ? vin[i] : 0u;
-        const uint32_t d = (uint32_t)(k[it] >> shift) & 255u;
+        const uint32_t d = (uint32_t)(k[it] >> shift) & dmask;
         const uint64_t peers = match_digit8(d, __ballot(valid));
         const uint32_t r = (uint32_t)__popcll(peers & lanes_below());
         const uint32_t prev = wcnt[w][d];
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const uint64_t* __restr
     const uint32_t tile_n = n > tile0 ? (n - tile0 < (uint32_t)RS_TILE ? n - tile0 : (uint32_t)RS_TILE) : 0u;
     for (uint32_t j = threadIdx.x; j < tile_n; j += RS_NT) {
         const uint64_t key = skey[j];
-        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint32_t d = (uint32_t)(key >> shift) & dmask;
         const uint32_t pos = gbase[d] + (j - lstart[d]);
         if (pos < n) {   // always true when the histogram scan is consistent
             kout[pos] = key;
@@ -299,15 +301,17 @@ int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t*
     uint32_t* vout = vals_alt;
     int passes = 0;
     for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(RS_NT), 0, s, kin, d_count, (uint32_t)cap, shift, hist,
-                           ntiles);
+        const int dbits = bit_hi - shift < 8 ? bit_hi - shift : 8;   // the last digit may be narrower
+        const uint32_t dmask = (1u << dbits) - 1u;
+        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(RS_NT), 0, s, kin, d_count, (uint32_t)cap, shift, dmask,
+                           hist, ntiles);
         scan_exclusive_sum_u32(hist, hist, (size_t)256 * ntiles, scan_tmp, s);
         if (vals) {
             hipLaunchKernelGGL(k_radix_scatter<true>, dim3(ntiles), dim3(RS_NT), 0, s, kin, vin, kout, vout, d_count,
-                               (uint32_t)cap, shift, hist, ntiles);
+                               (uint32_t)cap, shift, dmask, hist, ntiles);
         } else {
             hipLaunchKernelGGL(k_radix_scatter<false>, dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr, kout, nullptr,
-                               d_count, (uint32_t)cap, shift, hist, ntiles);
+                               d_count, (uint32_t)cap, shift, dmask, hist, ntiles);
         }
         uint64_t* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
