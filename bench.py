@@ -34,6 +34,7 @@ WORKLOADS = {
     "rmat22": dict(kind="rmat", scale=22, edge_factor=16, seed=1),
     "rmat24": dict(kind="rmat", scale=24, edge_factor=16, seed=1),
     "er4096": dict(kind="er", n=4096, m=32768, seed=1804),
+    "uniform20": dict(kind="uniform", n=1 << 20, pairs=16 << 20, seed=7),
     "rgg23": dict(kind="rgg", n=1 << 23, avg_degree=32.0, seed=5),
 }
 
@@ -45,6 +46,10 @@ def make_graph(name):
         return graphgen.rmat(w["scale"], w["edge_factor"], seed=w["seed"]), 1 << w["scale"], w
     if w["kind"] == "er":
         return graphgen.erdos_renyi(w["n"], w["m"], seed=w["seed"]), w["n"], w
+    if w["kind"] == "uniform":
+        import numpy as np
+        rng = np.random.Generator(np.random.PCG64(w["seed"]))
+        return rng.integers(0, w["n"], size=(w["pairs"], 2), dtype=np.int32), w["n"], w
     return graphgen.rgg(w["n"], w["avg_degree"], seed=w["seed"]), w["n"], w
 
 

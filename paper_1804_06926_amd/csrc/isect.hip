@@ -28,7 +28,7 @@ constexpr int IS_NT = 256;
 constexpr int BM_WORDS = 4096;            // 131072-bit window (16 KiB)
 constexpr uint32_t BM_BITS = BM_WORDS * 32u;
 constexpr int STAGE_MAX = 4096;           // N+(v) staged in LDS by merge/bsearch when it fits
-constexpr uint32_t LONG_TAIL = 32;        // bitmap kernel: tails this long go to a whole wave
+constexpr int UNROLL = 8;                 // bitmap kernel: tail loads in flight per lane
 constexpr int PARTIALS_PER_KERNEL = 4096; // max blocks per intersection launch
 
 struct Segs {
@@ -102,13 +102,11 @@ __device__ __forceinline__ void block_partial(uint64_t acc, uint64_t* partials) 
 __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* partials) {
     __shared__ uint32_t bm[BM_WORDS];
     __shared__ uint32_t s_start[CHUNK_MAX];
-    __shared__ uint32_t s_end[CHUNK_MAX];
-    __shared__ uint16_t s_long[CHUNK_MAX];
-    __shared__ uint16_t s_short[CHUNK_MAX];
-    __shared__ uint32_t s_nlong, s_nshort, s_long_next;
+    __shared__ uint32_t s_pref[CHUNK_MAX + 1];
+    __shared__ uint32_t s_cnt[CHUNK_MAX];
     __shared__ Segs S;
     for (int i = threadIdx.x; i < BM_WORDS; i += IS_NT) bm[i] = 0;
-    const int l = lane_id();
+    const bool need_cnt = a.per_edge || a.per_vertex;
     uint64_t acc = 0;
     const uint32_t t_end = a.ctrl->tile_begin[KER_BITMAP + 1];
     for (uint32_t t = a.ctrl->tile_begin[KER_BITMAP] + blockIdx.x; t < t_end; t += gridDim.x) {
@@ -119,21 +117,31 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
             const uint32_t ne = S.pref[sg + 1] - S.pref[sg];
             const uint32_t b0 = a.off[v], b1 = a.off[v + 1];
             const uint32_t nb = b1 - b0;
-            if (threadIdx.x == 0) { s_nlong = 0; s_nshort = 0; s_long_next = 0; }
-            __syncthreads();
-            for (uint32_t k = threadIdx.x; k < ne; k += IS_NT) {
-                const uint32_t e = (uint32_t)a.csc[e0 + k];
-                const uint32_t s = e + 1u, end = tail_end(a, e);
-                s_start[k] = s;
-                s_end[k] = end;
-                if (end - s >= LONG_TAIL) s_long[atomicAdd(&s_nlong, 1u)] = (uint16_t)k;
-                else s_short[atomicAdd(&s_nshort, 1u)] = (uint16_t)k;
+            // entry table: tail start and exclusive prefix of tail lengths
+            // (ne <= CHUNK_MAX = 2 * IS_NT, so two scans cover it)
+            uint32_t carry = 0;
+#pragma unroll
+            for (int h = 0; h < CHUNK_MAX / IS_NT; ++h) {
+                const uint32_t k = h * IS_NT + threadIdx.x;
+                uint32_t len = 0;
+                if (k < ne) {
+                    const uint32_t e = (uint32_t)a.csc[e0 + k];
+                    const uint32_t s = e + 1u;
+                    len = tail_end(a, e) - s;
+                    s_start[k] = s;
+                    if (need_cnt) s_cnt[k] = 0;
+                }
+                uint32_t total;
+                const uint32_t excl = block_exclusive_scan<IS_NT>(len, S.scratch, &total);
+                if (k < ne) s_pref[k] = carry + excl;
+                carry += total;
             }
+            if (threadIdx.x == 0) s_pref[ne] = carry;
+            const uint32_t L = carry;   // tail elements of this vertex's in-edges in the tile
             const uint32_t lo = a.col[b0], hi = a.col[b1 - 1];
             const uint32_t base = lo & ~31u;
             const uint32_t nwin = (hi - base) / BM_BITS + 1;
             __syncthreads();
-            const uint32_t nlong = s_nlong, nshort = s_nshort;
             for (uint32_t win = 0; win < nwin; ++win) {
                 const uint32_t wlo = base + win * BM_BITS;
                 for (uint32_t j = threadIdx.x; j < nb; j += IS_NT) {
@@ -141,60 +149,33 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                     if (x < BM_BITS) atomicOr(&bm[x >> 5], 1u << (x & 31u));
                 }
                 __syncthreads();
-                if (nwin == 1) {
-                    // long tails: one wave per in-edge, lanes stride the tail
-                    while (true) {
-                        uint32_t q = 0;
-                        if (l == 0) q = atomicAdd(&s_long_next, 1u);
-                        q = __shfl(q, 0, WAVE);
-                        if (q >= nlong) break;
-                        const uint32_t k = s_long[q];
-                        const uint32_t s = s_start[k], e = s_end[k];
-                        uint32_t c = 0;
-                        for (uint32_t p = s + l; p < e; p += WAVE) {
-                            const uint32_t x = a.col[p] - wlo;
-                            if (x < BM_BITS && ((bm[x >> 5] >> (x & 31u)) & 1u)) {
-                                ++c;
-                                hit_vertex(a, x + wlo);
+                // all tails of the tile as one flat item range; UNROLL independent
+                // loads per lane keep enough requests in flight
+                for (uint32_t r0 = 0; r0 < L; r0 += IS_NT * UNROLL) {
+                    uint32_t xs[UNROLL], ks[UNROLL];
+#pragma unroll
+                    for (int j = 0; j < UNROLL; ++j) {
+                        const uint32_t q = r0 + j * IS_NT + threadIdx.x;
+                        uint32_t k = 0;
+                        if (ne > 1) {   // entry holding item q: last k with pref[k] <= q
+                            uint32_t lo2 = 0, hi2 = ne - 1;
+                            while (lo2 < hi2) {
+                                const uint32_t mid = (lo2 + hi2 + 1) >> 1;
+                                if (s_pref[mid] <= q) lo2 = mid;
+                                else hi2 = mid - 1;
                             }
+                            k = lo2;
                         }
-                        c = wave_sum(c);
-                        acc += (l == 0) ? c : 0u;
-                        if (l == 0) edge_done(a, s - 1u, v, c);
+                        ks[j] = k;
+                        xs[j] = q < L ? a.col[s_start[k] + (q - s_pref[k])] - wlo : 0xFFFFFFFFu;
                     }
-                    // short tails: one lane per in-edge
-                    for (uint32_t q = threadIdx.x; q < nshort; q += IS_NT) {
-                        const uint32_t k = s_short[q];
-                        const uint32_t s = s_start[k], e = s_end[k];
-                        uint32_t c = 0;
-                        for (uint32_t p = s; p < e; ++p) {
-                            const uint32_t x = a.col[p] - wlo;
-                            if (x < BM_BITS && ((bm[x >> 5] >> (x & 31u)) & 1u)) {
-                                ++c;
-                                hit_vertex(a, x + wlo);
-                            }
-                        }
-                        acc += c;
-                        edge_done(a, s - 1u, v, c);
-                    }
-                } else {
-                    // N+(v) spans more than one window: one lane per in-edge; the
-                    // per-edge output accumulates over the windows
-                    for (uint32_t k = threadIdx.x; k < ne; k += IS_NT) {
-                        const uint32_t s = s_start[k], e = s_end[k];
-                        uint32_t c = 0;
-                        for (uint32_t p = s; p < e; ++p) {
-                            const uint32_t x = a.col[p] - wlo;
-                            if (x < BM_BITS && ((bm[x >> 5] >> (x & 31u)) & 1u)) {
-                                ++c;
-                                hit_vertex(a, x + wlo);
-                            }
-                        }
-                        acc += c;
-                        if (a.per_edge) a.per_edge[s - 1u] = (win ? a.per_edge[s - 1u] : 0u) + c;
-                        if (a.per_vertex && c) {
-                            atomicAdd((unsigned long long*)&a.per_vertex[a.src[s - 1u]], (unsigned long long)c);
-                            atomicAdd((unsigned long long*)&a.per_vertex[v], (unsigned long long)c);
+#pragma unroll
+                    for (int j = 0; j < UNROLL; ++j) {
+                        const uint32_t x = xs[j];
+                        if (x < BM_BITS && ((bm[x >> 5] >> (x & 31u)) & 1u)) {
+                            ++acc;
+                            if (need_cnt) atomicAdd(&s_cnt[ks[j]], 1u);
+                            hit_vertex(a, x + wlo);
                         }
                     }
                 }
@@ -205,6 +186,9 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                 }
                 __syncthreads();
             }
+            if (need_cnt)
+                for (uint32_t k = threadIdx.x; k < ne; k += IS_NT) edge_done(a, s_start[k] - 1u, v, s_cnt[k]);
+            __syncthreads();
         }
     }
     block_partial(acc, partials);
