@@ -28,7 +28,8 @@
  *     then left unspecified (host outputs are not written).
  *   - Calls on one context are serialised on its stream; a context is not
  *     thread-safe.
- *   - Limits: num_vertices < 2^31, num_edges < 2^31.
+ *   - Limits: num_vertices < 2^31, num_edges < 2^31 - 2^20 (TC_ERR_UNSUPPORTED
+ *     beyond).
  */
 #ifndef TC_MI355X_TC_H
 #define TC_MI355X_TC_H

@@ -59,7 +59,8 @@ bool options_ok(const tc_options* o) {
     return true;
 }
 
-constexpr int64_t kMaxEdges = (int64_t)0x7FFFFFFF;
+// 2E endpoints are indexed with 32-bit positions, with room for one sort tile
+constexpr int64_t kMaxEdges = ((int64_t)1 << 31) - ((int64_t)1 << 20);
 
 // Common checks and the run of the pipeline; returns with the control block
 // copied to ctx->h_ctrl on success.
@@ -68,7 +69,7 @@ tc_status run(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* w
     if (!ctx) return TC_ERR_INVALID_ARG;
     ctx->last_error.clear();
     if (E < 0 || n < 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "negative size");
-    if (E > kMaxEdges) return arg_fail(ctx, TC_ERR_UNSUPPORTED, "num_edges must be < 2^31");
+    if (E > kMaxEdges) return arg_fail(ctx, TC_ERR_UNSUPPORTED, "num_edges must be below 2^31 - 2^20");
     if (!options_ok(opts)) return arg_fail(ctx, TC_ERR_INVALID_ARG, "bad options");
     if (E > 0 && !d_edges) return arg_fail(ctx, TC_ERR_INVALID_ARG, "null edge list");
     if (((uintptr_t)d_edges & 7u) != 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "edge list must be 8-byte aligned");

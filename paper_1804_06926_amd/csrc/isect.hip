@@ -150,21 +150,25 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                 }
                 __syncthreads();
                 // all tails of the tile as one flat item range; UNROLL independent
-                // loads per lane keep enough requests in flight
+                // loads per lane keep enough requests in flight. Each of a thread's
+                // UNROLL item streams keeps a cursor to the entry holding its item
+                // (items only move forward), advanced by an exponential search.
+                uint32_t ks[UNROLL];
+#pragma unroll
+                for (int j = 0; j < UNROLL; ++j) ks[j] = 0;
                 for (uint32_t r0 = 0; r0 < L; r0 += IS_NT * UNROLL) {
-                    uint32_t xs[UNROLL], ks[UNROLL];
+                    uint32_t xs[UNROLL];
 #pragma unroll
                     for (int j = 0; j < UNROLL; ++j) {
                         const uint32_t q = r0 + j * IS_NT + threadIdx.x;
-                        uint32_t k = 0;
-                        if (ne > 1) {   // entry holding item q: last k with pref[k] <= q
-                            uint32_t lo2 = 0, hi2 = ne - 1;
-                            while (lo2 < hi2) {
-                                const uint32_t mid = (lo2 + hi2 + 1) >> 1;
-                                if (s_pref[mid] <= q) lo2 = mid;
-                                else hi2 = mid - 1;
+                        uint32_t k = ks[j];
+                        if (q < L && s_pref[k + 1] <= q) {   // last k with pref[k] <= q
+                            uint32_t step = 1;
+                            while (k + step < ne && s_pref[k + step] <= q) { k += step; step <<= 1; }
+                            while (step > 1) {
+                                step >>= 1;
+                                if (k + step < ne && s_pref[k + step] <= q) k += step;
                             }
-                            k = lo2;
                         }
                         ks[j] = k;
                         xs[j] = q < L ? a.col[s_start[k] + (q - s_pref[k])] - wlo : 0xFFFFFFFFu;

@@ -36,23 +36,36 @@ static unsigned grid_for(size_t n, unsigned cap = 16384) {
 }
 
 // ------------------------------------------------------------------ degree
-__global__ __launch_bounds__(NT) void k_degree(const int2* __restrict__ edges, uint64_t E, int32_t n,
-                                               uint32_t* __restrict__ deg, Ctrl* ctrl) {
+// Degrees come from sorting the 2E endpoints (device-wide atomics would
+// serialise on hub vertices): loop-free valid pairs contribute both ends,
+// everything else the sentinel n, which sorts last.
+__global__ __launch_bounds__(NT) void k_endpoints(const int2* __restrict__ edges, uint64_t E, int32_t n,
+                                                  uint32_t* __restrict__ keys, Ctrl* ctrl) {
     bool bad = false;
     for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < E; i += (uint64_t)gridDim.x * NT) {
         const int2 e = edges[i];
-        if (e.x < 0 || e.x >= n || e.y < 0 || e.y >= n) { bad = true; continue; }
-        if (e.x == e.y) continue;
-        atomicAdd(&deg[e.x], 1u);
-        atomicAdd(&deg[e.y], 1u);
+        const bool in_range = e.x >= 0 && e.x < n && e.y >= 0 && e.y < n;
+        bad |= !in_range;
+        const bool ok = in_range && e.x != e.y;
+        keys[2 * i] = ok ? (uint32_t)e.x : (uint32_t)n;
+        keys[2 * i + 1] = ok ? (uint32_t)e.y : (uint32_t)n;
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, 1u);
 }
 
-__global__ __launch_bounds__(NT) void k_vertex_keys(const uint32_t* __restrict__ deg, int32_t n,
+// dend[v] = one past the last occurrence of v among the sorted endpoints.
+__global__ __launch_bounds__(NT) void k_endpoint_bounds(const uint32_t* __restrict__ keys, uint64_t len, int32_t n,
+                                                        uint32_t* __restrict__ dend) {
+    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < len; i += (uint64_t)gridDim.x * NT) {
+        const uint32_t v = keys[i];
+        if (v < (uint32_t)n && (i + 1 == len || keys[i + 1] != v)) dend[v] = (uint32_t)(i + 1);
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_vertex_keys(const uint32_t* __restrict__ dstart, int32_t n,
                                                     uint64_t* __restrict__ keys) {
     for (int64_t v = (int64_t)blockIdx.x * NT + threadIdx.x; v < n; v += (int64_t)gridDim.x * NT)
-        keys[v] = ((uint64_t)deg[v] << 32) | (uint32_t)v;
+        keys[v] = ((uint64_t)(dstart[v + 1] - dstart[v]) << 32) | (uint32_t)v;
 }
 
 __global__ __launch_bounds__(NT) void k_rank(const uint64_t* __restrict__ sorted, int32_t n,
@@ -232,8 +245,8 @@ __global__ __launch_bounds__(NT) void k_vbucket(const uint32_t* __restrict__ off
 // merge-path takes the rest.
 __device__ int heuristic_choice(int b) {
     const int li = b >> 4, lo = b & 15;   // floor log2 of in-degree and out-degree
-    if (li >= 3) return KER_BITMAP;
-    if (lo >= 5) return KER_BSEARCH;
+    if (li >= 6) return KER_BITMAP;       // >= 64 in-edges share one staged N+(v)
+    if (lo >= 4) return KER_BSEARCH;
     return KER_MERGE;
 }
 
@@ -389,7 +402,7 @@ Layout make_layout(int64_t E, int32_t n) {
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + (bytes ? bytes : 1), A); return r; };
     L.ctrl = take(sizeof(Ctrl));
-    L.deg = take(4 * nn);
+    L.deg = take(4 * (nn + 1));
     L.rank = take(4 * nn);
     L.inv = take(4 * nn);
     L.vbucket = take(nn);
@@ -410,7 +423,7 @@ Layout make_layout(int64_t E, int32_t n) {
     L.partial = take(4 * (UQ_MAX_BLOCKS + 1));
     L.isect_partials = take(isect_partials_bytes());
     L.scan_tmp = take(scan_temp_bytes());
-    L.radix_tmp = take(radix_temp_bytes(kcap));
+    L.radix_tmp = take(radix_temp_bytes(2 * ee > nn ? 2 * ee : nn));
     L.total = o;
     return L;
 }
@@ -457,10 +470,20 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         if (r.events) (void)hipEventRecord(r.events[stage], s);
     };
     mark(0);
-    // ---- degree: input pairs per vertex
+    // ---- degree: input pairs per vertex, from the sorted endpoints
     fill_u32((uint32_t*)ctrl, 0u, sizeof(Ctrl) / 4, s);
-    fill_u32(deg, 0u, (size_t)n, s);
-    hipLaunchKernelGGL(k_degree, dim3(grid_for((size_t)E)), dim3(NT), 0, s, edges, (uint64_t)E, n, deg, ctrl);
+    {
+        uint32_t* ep = (uint32_t*)keysA;       // 2E uint32 fit in E uint64
+        uint32_t* ep_alt = (uint32_t*)keysB;
+        hipLaunchKernelGGL(k_endpoints, dim3(grid_for((size_t)E)), dim3(NT), 0, s, edges, (uint64_t)E, n, ep, ctrl);
+        const int a0 = radix_sort_u32(ep, ep_alt, nullptr, nullptr, nullptr, (size_t)(2 * E), 0,
+                                      bits_for((uint64_t)n + 1), radix_tmp, s);
+        fill_u32(rowend, 0u, (size_t)n, s);
+        hipLaunchKernelGGL(k_endpoint_bounds, dim3(grid_for((size_t)(2 * E))), dim3(NT), 0, s, a0 ? ep_alt : ep,
+                           (uint64_t)(2 * E), n, rowend);
+        fill_u32(deg, 0u, 1, s);
+        scan_inclusive_max_u32(rowend, deg + 1, (size_t)n, scan_tmp, s);   // deg[] holds degree offsets
+    }
     mark(1);
     // ---- rank: sort (degree, id); degrees are below 2E + 1
     hipLaunchKernelGGL(k_vertex_keys, dim3(grid_for((size_t)n)), dim3(NT), 0, s, deg, n, vkeysA);

@@ -183,7 +183,8 @@ __device__ __forceinline__ uint32_t rs_count(const uint32_t* d_count, uint32_t c
 }
 
 // Per-tile digit counts, written digit-major: hist[d * ntiles + tile].
-__global__ __launch_bounds__(RS_NT) void k_radix_hist(const uint64_t* __restrict__ keys, const uint32_t* d_count,
+template <typename KeyT>
+__global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ keys, const uint32_t* d_count,
                                                       uint32_t cap, int shift, uint32_t dmask,
                                                       uint32_t* __restrict__ hist,
                                                       uint32_t ntiles) {
@@ -209,10 +210,10 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const uint64_t* __restrict
     hist[(size_t)d * ntiles + blockIdx.x] = t;
 }
 
-template <bool HAS_VAL>
-__global__ __launch_bounds__(RS_NT) void k_radix_scatter(const uint64_t* __restrict__ kin,
+template <typename KeyT, bool HAS_VAL>
+__global__ __launch_bounds__(RS_NT) void k_radix_scatter(const KeyT* __restrict__ kin,
                                                          const uint32_t* __restrict__ vin,
-                                                         uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                         KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          const uint32_t* d_count, uint32_t cap, int shift,
                                                          uint32_t dmask,
                                                          const uint32_t* __restrict__ hist_scan, uint32_t ntiles) {
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const uint64_t* __restr
     __shared__ uint32_t lstart[256];
     __shared__ uint32_t gbase[256];
     __shared__ uint32_t scratch[RS_WAVES];
-    __shared__ uint64_t skey[RS_TILE];
+    __shared__ KeyT skey[RS_TILE];
     __shared__ uint32_t sval[HAS_VAL ? RS_TILE : 1];
     for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
     __syncthreads();
@@ -228,14 +229,14 @@ __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const uint64_t* __restr
     const int w = wave_id(), l = lane_id();
     const uint32_t tile0 = blockIdx.x * RS_TILE;
     const uint32_t base = tile0 + w * RS_WAVE_SPAN;
-    uint64_t k[RS_ITEMS];
+    KeyT k[RS_ITEMS];
     uint32_t v[RS_ITEMS];
     uint32_t loc[RS_ITEMS];   // digit | (rank within (wave, digit)) << 8
 #pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
         const uint32_t i = base + it * WAVE + l;
         const bool valid = i < n;
-        k[it] = valid ? kin[i] : 0ull;
+        k[it] = valid ? kin[i] : KeyT(0);
         if (HAS_VAL) v[it] = valid ? vin[i] : 0u;
         const uint32_t d = (uint32_t)(k[it] >> shift) & dmask;
         const uint64_t peers = match_digit8(d, __ballot(valid));
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const uint64_t* __restr
     __syncthreads();
     const uint32_t tile_n = n > tile0 ? (n - tile0 < (uint32_t)RS_TILE ? n - tile0 : (uint32_t)RS_TILE) : 0u;
     for (uint32_t j = threadIdx.x; j < tile_n; j += RS_NT) {
-        const uint64_t key = skey[j];
+        const KeyT key = skey[j];
         const uint32_t d = (uint32_t)(key >> shift) & dmask;
         const uint32_t pos = gbase[d] + (j - lstart[d]);
         if (pos < n) {   // always true when the histogram scan is consistent
@@ -289,34 +290,45 @@ size_t radix_temp_bytes(size_t cap) {
     return align_up(sizeof(uint32_t) * 256 * ntiles, 256) + align_up(scan_temp_bytes(), 256);
 }
 
-int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s) {
+template <typename KeyT>
+static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
+                      size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s) {
     if (cap == 0 || bit_hi <= bit_lo) return 0;
     const uint32_t ntiles = (uint32_t)((cap + RS_TILE - 1) / RS_TILE);
     uint32_t* hist = (uint32_t*)temp;
     void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * ((cap + RS_TILE - 1) / RS_TILE + 1), 256);
-    uint64_t* kin = keys;
-    uint64_t* kout = keys_alt;
+    KeyT* kin = keys;
+    KeyT* kout = keys_alt;
     uint32_t* vin = vals;
     uint32_t* vout = vals_alt;
     int passes = 0;
     for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
         const int dbits = bit_hi - shift < 8 ? bit_hi - shift : 8;   // the last digit may be narrower
         const uint32_t dmask = (1u << dbits) - 1u;
-        hipLaunchKernelGGL(k_radix_hist, dim3(ntiles), dim3(RS_NT), 0, s, kin, d_count, (uint32_t)cap, shift, dmask,
-                           hist, ntiles);
+        hipLaunchKernelGGL(k_radix_hist<KeyT>, dim3(ntiles), dim3(RS_NT), 0, s, kin, d_count, (uint32_t)cap, shift,
+                           dmask, hist, ntiles);
         scan_exclusive_sum_u32(hist, hist, (size_t)256 * ntiles, scan_tmp, s);
         if (vals) {
-            hipLaunchKernelGGL(k_radix_scatter<true>, dim3(ntiles), dim3(RS_NT), 0, s, kin, vin, kout, vout, d_count,
-                               (uint32_t)cap, shift, dmask, hist, ntiles);
-        } else {
-            hipLaunchKernelGGL(k_radix_scatter<false>, dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr, kout, nullptr,
+            hipLaunchKernelGGL((k_radix_scatter<KeyT, true>), dim3(ntiles), dim3(RS_NT), 0, s, kin, vin, kout, vout,
                                d_count, (uint32_t)cap, shift, dmask, hist, ntiles);
+        } else {
+            hipLaunchKernelGGL((k_radix_scatter<KeyT, false>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr, kout,
+                               nullptr, d_count, (uint32_t)cap, shift, dmask, hist, ntiles);
         }
-        uint64_t* tk = kin; kin = kout; kout = tk;
+        KeyT* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
     }
     return passes & 1;   // 1: result is in keys_alt / vals_alt
+}
+
+int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s) {
+    return radix_sort<uint64_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s);
+}
+
+int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s) {
+    return radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s);
 }
 
 }  // namespace tcx

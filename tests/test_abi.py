@@ -47,7 +47,7 @@ def test_workspace_size_host_checks(lib):
     assert out.value > small
     assert lib.tc_workspace_size(-1, 100, ctypes.byref(o), ctypes.byref(out)) == 1
     assert lib.tc_workspace_size(10, -1, ctypes.byref(o), ctypes.byref(out)) == 1
-    assert lib.tc_workspace_size(1 << 31, 10, ctypes.byref(o), ctypes.byref(out)) == 5
+    assert lib.tc_workspace_size((1 << 31) - (1 << 19), 10, ctypes.byref(o), ctypes.byref(out)) == 5
     o.select = 9
     assert lib.tc_workspace_size(10, 10, ctypes.byref(o), ctypes.byref(out)) == 1
     o.select = 0
