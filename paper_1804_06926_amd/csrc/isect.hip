@@ -104,8 +104,11 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
     __shared__ uint32_t s_start[CHUNK_MAX];
     __shared__ uint32_t s_pref[CHUNK_MAX + 1];
     __shared__ uint32_t s_cnt[CHUNK_MAX];
+    __shared__ uint32_t s_base[CHUNK_MAX];
+    __shared__ unsigned long long s_mask[IS_NT / WAVE];
     __shared__ Segs S;
     for (int i = threadIdx.x; i < BM_WORDS; i += IS_NT) bm[i] = 0;
+    if (threadIdx.x < IS_NT / WAVE) s_mask[threadIdx.x] = 0ull;
     const bool need_cnt = a.per_edge || a.per_vertex;
     uint64_t acc = 0;
     const uint32_t t_end = a.ctrl->tile_begin[KER_BITMAP + 1];
@@ -133,7 +136,10 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                 }
                 uint32_t total;
                 const uint32_t excl = block_exclusive_scan<IS_NT>(len, S.scratch, &total);
-                if (k < ne) s_pref[k] = carry + excl;
+                if (k < ne) {
+                    s_pref[k] = carry + excl;
+                    s_base[k] = s_start[k] - (carry + excl);   // modular: base + q is the address
+                }
                 carry += total;
             }
             if (threadIdx.x == 0) s_pref[ne] = carry;
@@ -149,29 +155,42 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                     if (x < BM_BITS) atomicOr(&bm[x >> 5], 1u << (x & 31u));
                 }
                 __syncthreads();
-                // all tails of the tile as one flat item range; UNROLL independent
-                // loads per lane keep enough requests in flight. Each of a thread's
-                // UNROLL item streams keeps a cursor to the entry holding its item
-                // (items only move forward), advanced by an exponential search.
-                uint32_t ks[UNROLL];
-#pragma unroll
-                for (int j = 0; j < UNROLL; ++j) ks[j] = 0;
-                for (uint32_t r0 = 0; r0 < L; r0 += IS_NT * UNROLL) {
-                    uint32_t xs[UNROLL];
+                // All tails of the tile form one flat item range [0, L); item q of
+                // entry k lives at col[base[k] + q]. Wave w takes the contiguous
+                // quarter [q0, q1) and walks it in 64-item windows, UNROLL windows
+                // (one load per lane each) in flight per round. The entries that
+                // start inside a window are found from one read of pref per lane:
+                // their start offsets are OR-ed into a 64-bit mask, and a lane's
+                // entry is kb + (number of starts at or before its offset).
+                const uint32_t wv = (uint32_t)wave_id(), ln = (uint32_t)lane_id();
+                const uint32_t q0 = (uint32_t)(((uint64_t)L * wv) / (IS_NT / WAVE));
+                const uint32_t q1 = (uint32_t)(((uint64_t)L * (wv + 1)) / (IS_NT / WAVE));
+                uint32_t kb = 0;   // entry holding item q0: last k with pref[k] <= q0
+                if (q0 < q1) {
+                    uint32_t lo2 = 0, hi2 = ne - 1;
+                    while (lo2 < hi2) {
+                        const uint32_t mid = (lo2 + hi2 + 1) >> 1;
+                        if (s_pref[mid] <= q0) lo2 = mid;
+                        else hi2 = mid - 1;
+                    }
+                    kb = lo2;
+                }
+                const uint64_t upto = ln == 63 ? ~0ull : ((2ull << ln) - 1ull);   // bits 0..ln
+                for (uint32_t W = q0; W < q1; W += WAVE * UNROLL) {
+                    uint32_t xs[UNROLL], ks[UNROLL];
 #pragma unroll
                     for (int j = 0; j < UNROLL; ++j) {
-                        const uint32_t q = r0 + j * IS_NT + threadIdx.x;
-                        uint32_t k = ks[j];
-                        if (q < L && s_pref[k + 1] <= q) {   // last k with pref[k] <= q
-                            uint32_t step = 1;
-                            while (k + step < ne && s_pref[k + step] <= q) { k += step; step <<= 1; }
-                            while (step > 1) {
-                                step >>= 1;
-                                if (k + step < ne && s_pref[k + step] <= q) k += step;
-                            }
-                        }
+                        const uint32_t Wj = W + j * WAVE;
+                        const uint32_t kk = kb + 1u + ln;
+                        const uint32_t o = (kk < ne) ? s_pref[kk] - Wj : 64u;
+                        if (o < 64u) atomicOr(&s_mask[wv], 1ull << o);
+                        const uint64_t M = s_mask[wv];
+                        if (ln == 0) s_mask[wv] = 0ull;
+                        const uint32_t k = kb + (uint32_t)__popcll(M & upto);
+                        kb += (uint32_t)__popcll(M);
+                        const uint32_t q = Wj + ln;
                         ks[j] = k;
-                        xs[j] = q < L ? a.col[s_start[k] + (q - s_pref[k])] - wlo : 0xFFFFFFFFu;
+                        xs[j] = q < q1 ? a.col[s_base[k] + q] - wlo : 0xFFFFFFFFu;
                     }
 #pragma unroll
                     for (int j = 0; j < UNROLL; ++j) {
