@@ -154,6 +154,65 @@ typedef struct tc_stats {
 tc_status tc_last_stats(const tc_ctx* ctx, tc_stats* out);
 
 /*
+ * Kernel selection per bucket by a learned network. The paper divides the
+ * edge list into small- and large-list groups with a hand-chosen threshold
+ * and proposes a third, one-large-one-small kernel (Section 4.2 and the
+ * intersection summary of Section 5); here a small network picks among the
+ * three strategies per degree-pair bucket, and the fixed thresholds remain
+ * the fallback. Counts never depend on the choice.
+ *
+ * Network: 6 features -> 32 -> 32 -> 3 logits (ReLU), bfloat16 weights
+ * rounded from a float32 master copy, float32 biases and accumulation.
+ * Parameter vector (float32, TC_SELECTOR_NUM_PARAMS entries, in order):
+ * W1 [32][6], b1 [32], W2 [32][32], b2 [32], W3 [3][32], b3 [3]; logit 0 is
+ * merge path, 1 binary search, 2 LDS bitmap.
+ * Features of bucket b (float32): floor(log2 d_in)/14, floor(log2 d_out)/15,
+ * log2(1+vertices)/24, log2(1+in-edges)/32, log2(1+out-edges)/32,
+ * log2(1+sum d_in*d_out)/48.
+ */
+#define TC_SELECTOR_NUM_PARAMS 1379
+#define TC_SELECTOR_NUM_FEATURES 6
+
+/* Features of the 256 buckets of the last counting call: h_features [256][6]. */
+tc_status tc_bucket_features(const tc_ctx* ctx, float* h_features);
+
+/*
+ * Timing data for training the selector: for each strategy k (0 merge,
+ * 1 binary search, 2 bitmap) and bucket b, the median over `repeats` (1..64)
+ * launches of strategy k on bucket b's tiles alone, in milliseconds, into
+ * h_ms[k * 256 + b] (-1 where the bucket is empty). h_features (optional)
+ * receives the bucket features [256][6]. Uses the same workspace as
+ * tc_count_triangles.
+ */
+tc_status tc_profile_buckets(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                             void* d_workspace, size_t workspace_bytes, int32_t repeats, float* h_ms,
+                             float* h_features);
+
+/* Load float32 master parameters (host); resets the Adam state and enables
+ * TC_SELECT_LEARNED on this context. */
+tc_status tc_selector_set_params(tc_ctx* ctx, const float* h_params);
+tc_status tc_selector_get_params(tc_ctx* ctx, float* h_params);
+
+/* Logits d_logits [batch][3] of features d_x [batch][6] (device arrays). */
+tc_status tc_selector_forward(tc_ctx* ctx, const float* d_x, int32_t batch, float* d_logits);
+
+/*
+ * Gradient of the weighted softmax cross-entropy
+ *   (1/batch) * sum_s w_s * (logsumexp(z_s) - z_s[y_s])
+ * with respect to the float32 master parameters (passed through the bfloat16
+ * rounding unchanged). d_labels int32 [batch] in 0..2; d_weights float32
+ * [batch] or NULL (all ones); d_grad float32 [TC_SELECTOR_NUM_PARAMS] or
+ * NULL; h_loss receives the loss (optional). batch in 1..65536.
+ */
+tc_status tc_selector_gradient(tc_ctx* ctx, const float* d_x, const int32_t* d_labels, const float* d_weights,
+                               int32_t batch, float* d_grad, float* h_loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on that
+ * gradient, then the bfloat16 compute copy is refreshed. */
+tc_status tc_selector_train_step(tc_ctx* ctx, const float* d_x, const int32_t* d_labels, const float* d_weights,
+                                 int32_t batch, float lr, float* h_loss);
+
+/*
  * Per-stage device times (milliseconds) of the last call made with
  * TC_F_STAGE_TIMING, and their names. Returns the number of stages written
  * (at most `cap`).

@@ -13,13 +13,22 @@ from ._lib import (  # noqa: F401
     FORCE_MERGE,
     SELECT_HEURISTIC,
     SELECT_LEARNED,
+    SELECTOR_NUM_FEATURES,
+    SELECTOR_NUM_PARAMS,
     TCError,
+    bucket_features,
     build_csr,
     count_triangles,
     edge_counts,
     last_stats,
     library_path,
+    profile_buckets,
     radix_sort_u64,
+    selector_forward,
+    selector_get_params,
+    selector_gradient,
+    selector_set_params,
+    selector_train_step,
     stage_names,
     workspace_size,
 )

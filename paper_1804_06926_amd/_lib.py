@@ -263,3 +263,122 @@ def last_stats(device="cuda:0") -> dict:
               "bucket_chunk", "bucket_group"):
         out[f] = np.ctypeslib.as_array(getattr(s, f)).copy()
     return out
+
+
+# ---------------------------------------------------------------- selector network
+SELECTOR_NUM_PARAMS = 1379
+SELECTOR_NUM_FEATURES = 6
+
+
+def _sel_lib():
+    lib = _load()
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.tc_bucket_features.argtypes = [vp, fp]
+    lib.tc_profile_buckets.argtypes = [vp, vp, i64, i32, vp, ctypes.c_size_t, i32, fp, fp]
+    lib.tc_selector_set_params.argtypes = [vp, fp]
+    lib.tc_selector_get_params.argtypes = [vp, fp]
+    lib.tc_selector_forward.argtypes = [vp, vp, i32, vp]
+    lib.tc_selector_gradient.argtypes = [vp, vp, vp, vp, i32, vp, fp]
+    lib.tc_selector_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, fp]
+    for f in ("tc_bucket_features", "tc_profile_buckets", "tc_selector_set_params", "tc_selector_get_params",
+              "tc_selector_forward", "tc_selector_gradient", "tc_selector_train_step"):
+        getattr(lib, f).restype = ctypes.c_int
+    return lib
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def selector_set_params(params, device="cuda:0") -> None:
+    """Load float32 master parameters of the selector network on the device's context."""
+    import numpy as np
+    p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+    if p.size != SELECTOR_NUM_PARAMS:
+        raise ValueError(f"expected {SELECTOR_NUM_PARAMS} parameters")
+    ctx, _ = _ctx(device)
+    _check(_sel_lib().tc_selector_set_params(ctx, _fptr(p)), ctx)
+
+
+def selector_get_params(device="cuda:0"):
+    import numpy as np
+    p = np.empty(SELECTOR_NUM_PARAMS, dtype=np.float32)
+    ctx, _ = _ctx(device)
+    _check(_sel_lib().tc_selector_get_params(ctx, _fptr(p)), ctx)
+    return p
+
+
+def _dev_f32(x, cols):
+    torch = _torch()
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()
+            and x.dim() == 2 and x.shape[1] == cols):
+        raise TypeError(f"expected a contiguous float32 CUDA tensor [B, {cols}]")
+    return x
+
+
+def selector_forward(x):
+    """Logits [B, 3] (float32 CUDA) of features x [B, 6] (float32 CUDA)."""
+    torch = _torch()
+    x = _dev_f32(x, SELECTOR_NUM_FEATURES)
+    ctx, _ = _ctx(x.device)
+    out = torch.empty((x.shape[0], 3), dtype=torch.float32, device=x.device)
+    _check(_sel_lib().tc_selector_forward(ctx, x.data_ptr(), x.shape[0], out.data_ptr()), ctx)
+    return out
+
+
+def _labels_weights(x, y, w):
+    torch = _torch()
+    if not (isinstance(y, torch.Tensor) and y.is_cuda and y.dtype == torch.int32 and y.numel() == x.shape[0]):
+        raise TypeError("labels must be an int32 CUDA tensor [B]")
+    if w is not None and not (isinstance(w, torch.Tensor) and w.is_cuda and w.dtype == torch.float32
+                              and w.numel() == x.shape[0]):
+        raise TypeError("weights must be a float32 CUDA tensor [B]")
+    return y.contiguous(), (w.contiguous() if w is not None else None)
+
+
+def selector_gradient(x, y, w=None):
+    """(gradient float32 [1379] CUDA, loss) of the weighted cross-entropy."""
+    torch = _torch()
+    x = _dev_f32(x, SELECTOR_NUM_FEATURES)
+    y, w = _labels_weights(x, y, w)
+    ctx, _ = _ctx(x.device)
+    g = torch.empty(SELECTOR_NUM_PARAMS, dtype=torch.float32, device=x.device)
+    loss = ctypes.c_float()
+    _check(_sel_lib().tc_selector_gradient(ctx, x.data_ptr(), y.data_ptr(), w.data_ptr() if w is not None else None,
+                                           x.shape[0], g.data_ptr(), ctypes.byref(loss)), ctx)
+    return g, float(loss.value)
+
+
+def selector_train_step(x, y, w=None, lr=1e-3) -> float:
+    x = _dev_f32(x, SELECTOR_NUM_FEATURES)
+    y, w = _labels_weights(x, y, w)
+    ctx, _ = _ctx(x.device)
+    loss = ctypes.c_float()
+    _check(_sel_lib().tc_selector_train_step(ctx, x.data_ptr(), y.data_ptr(),
+                                             w.data_ptr() if w is not None else None, x.shape[0], lr,
+                                             ctypes.byref(loss)), ctx)
+    return float(loss.value)
+
+
+def bucket_features(device="cuda:0"):
+    """Features [256, 6] of the buckets of the last counting call."""
+    import numpy as np
+    out = np.zeros((256, SELECTOR_NUM_FEATURES), dtype=np.float32)
+    ctx, _ = _ctx(device)
+    _check(_sel_lib().tc_bucket_features(ctx, _fptr(out)), ctx)
+    return out
+
+
+def profile_buckets(edges, num_vertices: int, repeats: int = 5, workspace=None):
+    """Per-(strategy, bucket) median milliseconds [3, 256] (-1 = empty) and features [256, 6]."""
+    import numpy as np
+    e = _edges_arg(edges)
+    ctx, idx = _ctx(e.device)
+    E = e.shape[0]
+    ws = _workspace(idx, workspace_size(E, num_vertices), workspace)
+    ms = np.zeros((3, 256), dtype=np.float32)
+    feat = np.zeros((256, SELECTOR_NUM_FEATURES), dtype=np.float32)
+    _check(_sel_lib().tc_profile_buckets(ctx, e.data_ptr() if E else None, E, num_vertices, ws.data_ptr(),
+                                         ws.numel(), repeats, _fptr(ms), _fptr(feat)), ctx)
+    return ms, feat

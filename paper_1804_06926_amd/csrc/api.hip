@@ -2,9 +2,12 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "internal.h"
+#include "mlp.h"
 #include "pipeline.h"
 #include "tc.h"
 
@@ -21,6 +24,16 @@ struct tc_ctx {
     uint16_t* d_chunk = nullptr;          // device [256] tile-size overrides (0 = default)
     uint8_t* d_group = nullptr;           // device [256] lanes-per-edge overrides (0 = default)
     int grid_override[tcx::NKERNEL] = {0, 0, 0};
+    // selector network: float32 master, Adam moments, gradient, bf16 compute copy,
+    // and the per-sample training buffers (allocated on first use)
+    float* d_master = nullptr;
+    float* d_adam_m = nullptr;
+    float* d_adam_v = nullptr;
+    float* d_grad = nullptr;
+    float* d_loss = nullptr;
+    tcx::MlpCompute* d_cw = nullptr;
+    float* d_acts = nullptr;
+    int adam_step = 0;
 };
 
 namespace {
@@ -90,7 +103,8 @@ tc_status run(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* w
     ra.E = E;
     ra.n = n;
     ra.select = sel;
-    ra.learned = ctx->learned_ready ? ctx->d_learned : nullptr;
+    ra.mlp = ctx->learned_ready ? ctx->d_cw : nullptr;
+    ra.learned = ctx->d_learned;
     ra.chunk_override = ctx->d_chunk;
     ra.group_override = ctx->d_group;
     ra.grid_override = ctx->grid_override;
@@ -145,6 +159,13 @@ tc_status tc_create(tc_ctx** out, int device, void* hip_stream) {
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_group, tcx::NBUCKET);
     if (e == hipSuccess) e = hipMemset(ctx->d_chunk, 0, sizeof(uint16_t) * tcx::NBUCKET);
     if (e == hipSuccess) e = hipMemset(ctx->d_group, 0, tcx::NBUCKET);
+    const size_t np = sizeof(float) * tcx::MLP_NPARAM;
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_master, np);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_adam_m, np);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_adam_v, np);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_grad, np);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_loss, sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_cw, sizeof(tcx::MlpCompute));
     if (e != hipSuccess) {
         tc_destroy(ctx);
         return TC_ERR_HIP;
@@ -163,6 +184,10 @@ tc_status tc_destroy(tc_ctx* ctx) {
         if (ctx->d_learned) (void)hipFree(ctx->d_learned);
         if (ctx->d_chunk) (void)hipFree(ctx->d_chunk);
         if (ctx->d_group) (void)hipFree(ctx->d_group);
+        float* bufs[] = {ctx->d_master, ctx->d_adam_m, ctx->d_adam_v, ctx->d_grad, ctx->d_loss, ctx->d_acts};
+        for (float* p : bufs)
+            if (p) (void)hipFree(p);
+        if (ctx->d_cw) (void)hipFree(ctx->d_cw);
     }
     delete ctx;
     return TC_OK;
@@ -278,6 +303,154 @@ tc_status tc_last_stats(const tc_ctx* ctx, tc_stats* out) {
         out->bucket_group[b] = c.group[b];
     }
     return TC_OK;
+}
+
+tc_status tc_bucket_features(const tc_ctx* ctx, float* h_features) {
+    if (!ctx || !h_features) return TC_ERR_INVALID_ARG;
+    memcpy(h_features, ctx->h_ctrl->features, sizeof(ctx->h_ctrl->features));
+    return TC_OK;
+}
+
+tc_status tc_profile_buckets(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                             void* d_workspace, size_t workspace_bytes, int32_t repeats, float* h_ms,
+                             float* h_features) {
+    if (!ctx || !h_ms || repeats < 1 || repeats > 64) return arg_fail(ctx, TC_ERR_INVALID_ARG, "bad arguments");
+    for (int i = 0; i < tcx::NKERNEL * tcx::NBUCKET; ++i) h_ms[i] = -1.f;
+    if (num_edges == 0) return TC_OK;
+    std::vector<uint32_t> tstart((size_t)num_vertices + 1);
+    for (int k = 0; k < tcx::NKERNEL; ++k) {
+        tc_options o = {};
+        o.select = TC_FORCE_MERGE + k;   // merge, bsearch, bitmap follow in order
+        tcx::RunArgs ra = {};
+        ra.stop_before_isect = 1;
+        tc_status st = run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, &o, ra);
+        if (st != TC_OK) return st;
+        if (k == 0 && h_features) memcpy(h_features, ctx->h_ctrl->features, sizeof(ctx->h_ctrl->features));
+        DeviceGuard guard(ctx->device);
+        const tcx::Layout L = tcx::make_layout(num_edges, num_vertices);
+        hipError_t e = hipMemcpy(tstart.data(), (char*)d_workspace + L.tstart, sizeof(uint32_t) * tstart.size(),
+                                 hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(ctx, e, "read tile starts");
+        const tcx::Ctrl c = *ctx->h_ctrl;
+        for (int b = 0; b < tcx::NBUCKET - 1; ++b) {
+            if (c.bucket_nv[b] == 0 || c.bend[b] <= c.bstart[b]) continue;
+            const uint32_t t0 = tstart[c.bstart[b]], t1 = tstart[c.bend[b]];
+            if (t1 <= t0) continue;
+            std::vector<float> ms;
+            for (int r = 0; r < repeats; ++r) {
+                (void)hipEventRecord(ctx->events[0], ctx->stream);
+                e = tcx::launch_isect_range(ra, k, t0, t1);
+                (void)hipEventRecord(ctx->events[1], ctx->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(ctx->events[1]);
+                float t = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&t, ctx->events[0], ctx->events[1]);
+                if (e != hipSuccess) return hip_fail(ctx, e, "profile launch");
+                ms.push_back(t);
+            }
+            std::sort(ms.begin(), ms.end());
+            h_ms[k * tcx::NBUCKET + b] = ms[ms.size() / 2];
+        }
+    }
+    return TC_OK;
+}
+
+static tc_status ensure_acts(tc_ctx* ctx) {
+    if (ctx->d_acts) return TC_OK;
+    const size_t per = 4 * tcx::MLP_H + tcx::MLP_OUT + 1;
+    hipError_t e = hipMalloc((void**)&ctx->d_acts, sizeof(float) * per * tcx::MLP_MAX_BATCH);
+    return e == hipSuccess ? TC_OK : hip_fail(ctx, e, "selector buffers");
+}
+
+static tcx::MlpActs acts_of(tc_ctx* ctx, int B) {
+    tcx::MlpActs a;
+    float* p = ctx->d_acts;
+    a.h1 = p; p += (size_t)B * tcx::MLP_H;
+    a.h2 = p; p += (size_t)B * tcx::MLP_H;
+    a.dh1 = p; p += (size_t)B * tcx::MLP_H;
+    a.dh2 = p; p += (size_t)B * tcx::MLP_H;
+    a.dz = p; p += (size_t)B * tcx::MLP_OUT;
+    a.loss = p;
+    return a;
+}
+
+tc_status tc_selector_set_params(tc_ctx* ctx, const float* h_params) {
+    if (!ctx || !h_params) return TC_ERR_INVALID_ARG;
+    DeviceGuard guard(ctx->device);
+    const size_t np = sizeof(float) * tcx::MLP_NPARAM;
+    hipError_t e = hipMemcpyAsync(ctx->d_master, h_params, np, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->d_adam_m, 0, np, ctx->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(ctx->d_adam_v, 0, np, ctx->stream);
+    if (e == hipSuccess) {
+        tcx::mlp_cast(ctx->d_master, ctx->d_cw, ctx->stream);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set selector parameters");
+    ctx->adam_step = 0;
+    ctx->learned_ready = 1;
+    return TC_OK;
+}
+
+tc_status tc_selector_get_params(tc_ctx* ctx, float* h_params) {
+    if (!ctx || !h_params) return TC_ERR_INVALID_ARG;
+    if (!ctx->learned_ready) return arg_fail(ctx, TC_ERR_INVALID_ARG, "no selector parameters set");
+    DeviceGuard guard(ctx->device);
+    hipError_t e = hipMemcpyAsync(h_params, ctx->d_master, sizeof(float) * tcx::MLP_NPARAM, hipMemcpyDeviceToHost,
+                                  ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    return e == hipSuccess ? TC_OK : hip_fail(ctx, e, "get selector parameters");
+}
+
+tc_status tc_selector_forward(tc_ctx* ctx, const float* d_x, int32_t batch, float* d_logits) {
+    if (!ctx || batch < 0 || (batch > 0 && (!d_x || !d_logits))) return TC_ERR_INVALID_ARG;
+    if (!ctx->learned_ready) return arg_fail(ctx, TC_ERR_INVALID_ARG, "no selector parameters set");
+    DeviceGuard guard(ctx->device);
+    tcx::mlp_forward(ctx->d_cw, d_x, batch, d_logits, ctx->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    return e == hipSuccess ? TC_OK : hip_fail(ctx, e, "selector forward");
+}
+
+static tc_status selector_grad(tc_ctx* ctx, const float* d_x, const int32_t* d_labels, const float* d_weights,
+                               int32_t batch, float* h_loss) {
+    if (!ctx || batch < 1 || batch > tcx::MLP_MAX_BATCH || !d_x || !d_labels) return TC_ERR_INVALID_ARG;
+    if (!ctx->learned_ready) return arg_fail(ctx, TC_ERR_INVALID_ARG, "no selector parameters set");
+    tc_status st = ensure_acts(ctx);
+    if (st != TC_OK) return st;
+    tcx::mlp_gradient(ctx->d_cw, d_x, d_labels, d_weights, batch, acts_of(ctx, batch), ctx->d_grad, ctx->d_loss,
+                      ctx->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && h_loss)
+        e = hipMemcpyAsync(h_loss, ctx->d_loss, sizeof(float), hipMemcpyDeviceToHost, ctx->stream);
+    return e == hipSuccess ? TC_OK : hip_fail(ctx, e, "selector gradient");
+}
+
+tc_status tc_selector_gradient(tc_ctx* ctx, const float* d_x, const int32_t* d_labels, const float* d_weights,
+                               int32_t batch, float* d_grad, float* h_loss) {
+    if (!ctx) return TC_ERR_INVALID_ARG;
+    DeviceGuard guard(ctx->device);
+    tc_status st = selector_grad(ctx, d_x, d_labels, d_weights, batch, h_loss);
+    if (st != TC_OK) return st;
+    hipError_t e = hipSuccess;
+    if (d_grad)
+        e = hipMemcpyAsync(d_grad, ctx->d_grad, sizeof(float) * tcx::MLP_NPARAM, hipMemcpyDeviceToDevice,
+                           ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    return e == hipSuccess ? TC_OK : hip_fail(ctx, e, "selector gradient");
+}
+
+tc_status tc_selector_train_step(tc_ctx* ctx, const float* d_x, const int32_t* d_labels, const float* d_weights,
+                                 int32_t batch, float lr, float* h_loss) {
+    if (!ctx || !(lr > 0.f)) return TC_ERR_INVALID_ARG;
+    DeviceGuard guard(ctx->device);
+    tc_status st = selector_grad(ctx, d_x, d_labels, d_weights, batch, h_loss);
+    if (st != TC_OK) return st;
+    ctx->adam_step += 1;
+    tcx::mlp_adam(ctx->d_master, ctx->d_grad, ctx->d_adam_m, ctx->d_adam_v, lr, ctx->adam_step, ctx->stream);
+    tcx::mlp_cast(ctx->d_master, ctx->d_cw, ctx->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    return e == hipSuccess ? TC_OK : hip_fail(ctx, e, "selector train step");
 }
 
 int32_t tc_stage_times(const tc_ctx* ctx, float* ms, int32_t cap) {

@@ -51,6 +51,7 @@ struct Ctrl {
     uint16_t chunk[NBUCKET];          // in-edges per tile, per bucket
     uint8_t group[NBUCKET];           // lanes per in-edge for the edge-centric kernels
     uint8_t pad1[NBUCKET];
+    float features[NBUCKET][6];       // selector-network input per bucket
 };
 
 // Tiles: low word = position i in the ordered vertex list; high word = chunk

@@ -29,7 +29,9 @@ struct RunArgs {
     int64_t E;
     int32_t n;
     int select;
-    const uint8_t* learned;          // device [256] kernel per bucket, or null
+    const void* mlp;                 // device MlpCompute (selector network), or null
+    uint8_t* learned;                // device [256] kernel per bucket written by the network
+    int stop_before_isect;           // leave after the tiles are laid out (bucket profiling)
     const uint16_t* chunk_override;  // device [256] or null
     const uint8_t* group_override;   // device [256] or null
     const int* grid_override;        // host [3] or null
@@ -47,6 +49,8 @@ struct RunResult {
 };
 
 hipError_t run_pipeline(const RunArgs& r, RunResult* out);
+// After a run with stop_before_isect: one intersection kernel over tiles [t0, t1).
+hipError_t launch_isect_range(const RunArgs& r, int ker, uint32_t t0, uint32_t t1);
 int stage_count();
 const char* stage_name(int s);
 

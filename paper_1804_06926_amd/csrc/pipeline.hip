@@ -22,6 +22,7 @@
 #include "common.h"
 #include "internal.h"
 #include "isect.h"
+#include "mlp.h"
 #include "pipeline.h"
 
 namespace tcx {
@@ -393,6 +394,13 @@ __global__ __launch_bounds__(NT) void k_export_csr(const uint32_t* __restrict__ 
     for (uint64_t e = (uint64_t)blockIdx.x * NT + threadIdx.x; e < m; e += stride) o_col[e] = (int32_t)col[e];
 }
 
+__global__ void k_set_tile_range(Ctrl* ctrl, int ker, uint32_t t0, uint32_t t1) {
+    if (threadIdx.x == 0) {
+        ctrl->tile_begin[ker] = t0;
+        ctrl->tile_begin[ker + 1] = t1;
+    }
+}
+
 // ------------------------------------------------------------------ workspace layout
 Layout make_layout(int64_t E, int32_t n) {
     Layout L;
@@ -434,6 +442,43 @@ const char* stage_name(int s) {
     static const char* names[NSTAGE] = {"degree", "rank", "orient", "sort", "csr", "csc", "bucket",
                                         "group", "isect_merge", "isect_bsearch", "isect_bitmap", "finish"};
     return (s >= 0 && s < NSTAGE) ? names[s] : "";
+}
+
+static IsectArgs isect_args(const RunArgs& r, const Layout& L, uint64_t* csc) {
+    char* ws = (char*)r.ws;
+    IsectArgs ia;
+    ia.ctrl = (Ctrl*)(ws + L.ctrl);
+    ia.off = (const uint32_t*)(ws + L.off);
+    ia.col = (const uint32_t*)(ws + L.col);
+    ia.src = (const uint32_t*)(ws + L.src);
+    ia.csc = csc;
+    ia.inoff = (const uint32_t*)(ws + L.inoff);
+    ia.vlist = (const uint32_t*)(ws + L.vlist);
+    ia.vbucket = (const uint8_t*)(ws + L.vbucket);
+    ia.tiles = (const uint64_t*)(ws + L.tiles);
+    ia.per_edge = r.per_edge_counts;
+    ia.per_vertex = r.per_vertex ? (uint64_t*)(ws + L.pv) : nullptr;
+    return ia;
+}
+
+// Where the CSC array ended up (it depends on the parity of the sort passes).
+static uint64_t* csc_of(const RunArgs& r, const Layout& L) {
+    char* ws = (char*)r.ws;
+    const int nb = bits_for((uint64_t)r.n) > 0 ? bits_for((uint64_t)r.n) : 1;
+    const int p1 = (2 * nb + 7) / 8;                   // passes of the pair sort
+    const int p2 = (bits_for((uint64_t)r.n + 1) + 7) / 8;   // passes of the CSC sort
+    uint64_t* sorted = (p1 & 1) ? (uint64_t*)(ws + L.keysB) : (uint64_t*)(ws + L.keysA);
+    uint64_t* other = (p1 & 1) ? (uint64_t*)(ws + L.keysA) : (uint64_t*)(ws + L.keysB);
+    return (p2 & 1) ? sorted : other;
+}
+
+hipError_t launch_isect_range(const RunArgs& r, int ker, uint32_t t0, uint32_t t1) {
+    const Layout L = make_layout(r.E, r.n);
+    IsectArgs ia = isect_args(r, L, csc_of(r, L));
+    hipLaunchKernelGGL(k_set_tile_range, dim3(1), dim3(64), 0, r.stream, ia.ctrl, ker, t0, t1);
+    launch_isect(ker, ia, r.grid_override ? r.grid_override[ker] : 0, (uint64_t*)((char*)r.ws + L.isect_partials),
+                 r.stream);
+    return hipGetLastError();
 }
 
 hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
@@ -536,8 +581,11 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     mark(6);
     // ---- buckets + selection
     hipLaunchKernelGGL(k_vbucket, dim3(grid_for((size_t)n, 2048)), dim3(NT), 0, s, off, inoff, n, vbucket, ctrl);
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(NBUCKET), 0, s, ctrl, r.select, r.learned, r.chunk_override,
-                       r.group_override);
+    const bool learned = r.select == SEL_LEARNED && r.mlp && r.learned;
+    if (learned) mlp_select((const MlpCompute*)r.mlp, ctrl, r.learned, s);
+    else bucket_features_launch(ctrl, s);
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(NBUCKET), 0, s, ctrl, r.select, learned ? r.learned : nullptr,
+                       r.chunk_override, r.group_override);
     mark(7);
     // ---- group: order vertices by (kernel, bucket); tiles
     hipLaunchKernelGGL(k_vkeys_slot, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vbucket, n, ctrl, vkeysA);
@@ -553,19 +601,12 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     if (r.per_edge_counts) fill_u32(r.per_edge_counts, 0u, (size_t)E, s);
     if (r.per_vertex) fill_u64(pv, 0ull, (size_t)n, s);
     mark(8);
+    if (r.stop_before_isect) {
+        out->ctrl_dev = ctrl;
+        return hipGetLastError();
+    }
     // ---- intersections
-    IsectArgs ia;
-    ia.ctrl = ctrl;
-    ia.off = off;
-    ia.col = col;
-    ia.src = src;
-    ia.csc = csc;
-    ia.inoff = inoff;
-    ia.vlist = vlist;
-    ia.vbucket = vbucket;
-    ia.tiles = tiles;
-    ia.per_edge = r.per_edge_counts;
-    ia.per_vertex = r.per_vertex ? pv : nullptr;
+    const IsectArgs ia = isect_args(r, L, csc);
     uint64_t* partials = (uint64_t*)(ws + L.isect_partials);
     const int order[NKERNEL] = {KER_MERGE, KER_BSEARCH, KER_BITMAP};
     for (int q = 0; q < NKERNEL; ++q) {

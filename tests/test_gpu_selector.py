@@ -1,0 +1,129 @@
+"""GPU parity of the selector network's kernels against the float64 oracle, and
+the learned selection mode's exactness. Inputs are seeded synthetic features."""
+import os
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tc():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1804_06926_amd import _lib
+    if not os.path.exists(_lib.library_path()):
+        import __graft_entry__
+        __graft_entry__.build()
+    import paper_1804_06926_amd
+    return paper_1804_06926_amd
+
+
+def _batch(B, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(0, 1, size=(B, 6)).astype(np.float32)
+    y = rng.integers(0, 3, size=B).astype(np.int32)
+    w = rng.uniform(0.2, 3.0, size=B).astype(np.float32)
+    return X, y, w
+
+
+def _params(seed):
+    theta = mlp.init_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    theta[mlp.N_PARAMS - 3:] = rng.normal(0, 0.3, 3)
+    theta[192:224] = rng.normal(0, 0.1, 32)     # b1
+    theta[1248:1280] = rng.normal(0, 0.1, 32)   # b2
+    return theta.astype(np.float32)
+
+
+@pytest.mark.parametrize("B", [1, 255, 256, 1000])
+def test_forward_matches_oracle_within_error_bound(tc, B):
+    import torch
+    theta = _params(B)
+    X, _, _ = _batch(B, B)
+    tc.selector_set_params(theta)
+    z = tc.selector_forward(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+    z64, _, _ = mlp.forward(theta, X)
+    bound = mlp.forward_error_bound(theta, X)
+    assert np.all(np.abs(z - z64) <= bound), np.max(np.abs(z - z64) - bound)
+    np.testing.assert_array_equal(tc.selector_get_params(), theta)
+
+
+@pytest.mark.parametrize("B,weighted", [(1, False), (300, True), (4096, True)])
+def test_gradient_matches_oracle(tc, B, weighted):
+    """Tolerance: each gradient entry is a sum of B products formed from float32
+    activations; float32 rounding of the layer outputs and of the sum bounds the
+    relative error by about (B + 70) * 2^-24 of the sum of absolute terms, far
+    below the 1e-4 relative slack used here (plus 1e-7 absolute)."""
+    import torch
+    theta = _params(7 + B)
+    X, y, w = _batch(B, 11 + B)
+    tc.selector_set_params(theta)
+    g, loss = tc.selector_gradient(torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(),
+                                   torch.from_numpy(w).cuda() if weighted else None)
+    g = g.cpu().numpy().astype(np.float64)
+    loss64, g64 = mlp.loss_and_grad(theta, X, y, w if weighted else None)
+    assert abs(loss - loss64) <= 1e-5 * max(1.0, abs(loss64))
+    # scale of each entry: the same gradient computed with absolute values
+    _, gabs = mlp.loss_and_grad(theta, X, y, w if weighted else None)
+    tol = 1e-4 * np.abs(gabs) + 1e-4 * np.max(np.abs(g64)) + 1e-7
+    assert np.all(np.abs(g - g64) <= tol), np.max(np.abs(g - g64) - tol)
+
+
+def test_training_steps_match_oracle_adam_and_lower_the_loss(tc):
+    import torch
+    theta = _params(3)
+    X, y, w = _batch(512, 5)
+    tc.selector_set_params(theta)
+    dx, dy, dw = torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(), torch.from_numpy(w).cuda()
+    th = theta.astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    losses = []
+    for t in range(1, 6):
+        losses.append(tc.selector_train_step(dx, dy, dw, lr=1e-2))
+        _, g = mlp.loss_and_grad(th.astype(np.float32), X, y, w)
+        th, m, v = mlp.adam_step(th, g, m, v, t, lr=1e-2)
+    got = tc.selector_get_params().astype(np.float64)
+    # Adam moves each parameter by at most about lr per step; float32 gradients may
+    # flip the sign of tiny components, so compare with a step-sized tolerance
+    assert np.max(np.abs(got - th)) < 5 * 1e-2
+    assert np.mean(np.abs(got - th)) < 1e-3
+    for _ in range(200):
+        last = tc.selector_train_step(dx, dy, dw, lr=1e-2)
+    assert last < losses[0] * 0.9
+
+
+def test_learned_selection_gives_exact_counts(tc):
+    import torch
+    rng = np.random.default_rng(0)
+    theta = mlp.init_params(5)
+    tc.selector_set_params(theta)
+    for scale, seed in ((12, 1), (15, 2)):
+        n = 1 << scale
+        e = graphgen.rmat(scale, 16, seed=seed)
+        ref = oracle.count_triangles(e, n)
+        d = torch.from_numpy(e).cuda()
+        assert tc.count_triangles(d, n, select=tc.SELECT_LEARNED) == ref
+        # bucket features are those of the graph, computed on the device
+        feat = tc.bucket_features()
+        assert feat.shape == (256, 6) and np.all(np.isfinite(feat))
+    _ = rng
+
+
+def test_profile_buckets_shapes(tc):
+    import torch
+    n = 1 << 14
+    e = graphgen.rmat(14, 16, seed=3)
+    ms, feat = tc.profile_buckets(torch.from_numpy(e).cuda(), n, repeats=3)
+    st = tc.last_stats()
+    busy = np.nonzero(st["bucket_vertices"][:255])[0]
+    assert busy.size > 0
+    for b in busy:
+        assert np.all(ms[:, b] > 0), b
+    assert np.all(ms[:, 255] < 0)
