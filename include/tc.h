@@ -62,6 +62,7 @@ typedef enum tc_select {
 
 /* Option flags. */
 #define TC_F_STAGE_TIMING 0x1u  /* record per-stage times (tc_stage_times) */
+#define TC_F_NO_GRAPH 0x2u      /* batched counting: launch directly instead of replaying a captured graph */
 
 typedef struct tc_options {
     int32_t select;           /* a tc_select value */
@@ -105,6 +106,34 @@ tc_status tc_count_triangles(tc_ctx* ctx, const int32_t* d_edges, int64_t num_ed
 tc_status tc_edge_counts(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
                          void* d_workspace, size_t workspace_bytes, const tc_options* opts,
                          int32_t* d_out_edges, uint32_t* d_out_counts, int64_t* h_num_out, uint64_t* h_count);
+
+/*
+ * Batched counting of many graphs in one pass (not in the paper; its small-
+ * graph overhead remark in Section 5 motivates it). Graph g's pairs are
+ * d_edges[h_edge_offsets[g] .. h_edge_offsets[g+1]) with graph-local ids in
+ * [0, h_num_vertices[g]). The graphs are counted as one disjoint union:
+ * every triangle lies inside one graph, and each is attributed to its graph
+ * through its middle vertex, so h_counts[g] (host, uint64) is exact.
+ * By default the whole device work of a call is captured once as a HIP graph
+ * and replayed on later calls with the same sizes, edge pointer, workspace
+ * and selection mode (TC_F_NO_GRAPH launches directly). If the context's
+ * stream is the null stream, the work runs on a stream owned by the context.
+ * Workspace: tc_batch_workspace_size(total pairs, total vertices, graphs).
+ * An id outside its own graph's range yields TC_ERR_VERTEX_RANGE.
+ */
+tc_status tc_batch_workspace_size(int64_t total_edges, int64_t total_vertices, int32_t num_graphs,
+                                  const tc_options* opts, size_t* bytes);
+tc_status tc_count_triangles_batch(tc_ctx* ctx, const int32_t* d_edges, const int64_t* h_edge_offsets,
+                                   const int32_t* h_num_vertices, int32_t num_graphs, void* d_workspace,
+                                   size_t workspace_bytes, const tc_options* opts, uint64_t* h_counts);
+
+/*
+ * Tile shapes per degree-pair bucket (the autotuner's output): h_chunk[256]
+ * in-edges per tile (16..512; 0 = default), h_group[256] lanes per in-edge
+ * for merge path and binary search (power of two 1..64; 0 = default).
+ * NULL resets to the defaults. Shapes change speed only, never counts.
+ */
+tc_status tc_set_tile_shapes(tc_ctx* ctx, const uint16_t* h_chunk, const uint8_t* h_group);
 
 /*
  * The filtered CSR of Section 4.2 ("induced subgraph"): vertices relabelled
@@ -187,6 +216,13 @@ tc_status tc_bucket_features(const tc_ctx* ctx, float* h_features);
 tc_status tc_profile_buckets(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
                              void* d_workspace, size_t workspace_bytes, int32_t repeats, float* h_ms,
                              float* h_features);
+
+/* Like tc_profile_buckets, but each bucket is timed only with the strategy
+ * that opts->select chooses for it (the current tile shapes apply):
+ * h_ms[256], -1 where the bucket is empty. Used by the tile-shape autotuner. */
+tc_status tc_profile_selected(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                              void* d_workspace, size_t workspace_bytes, const tc_options* opts, int32_t repeats,
+                              float* h_ms);
 
 /* Load float32 master parameters (host); resets the Adam state and enables
  * TC_SELECT_LEARNED on this context. */

@@ -19,16 +19,19 @@ from ._lib import (  # noqa: F401
     bucket_features,
     build_csr,
     count_triangles,
+    count_triangles_batch,
     edge_counts,
     last_stats,
     library_path,
     profile_buckets,
+    profile_selected,
     radix_sort_u64,
     selector_forward,
     selector_get_params,
     selector_gradient,
     selector_set_params,
     selector_train_step,
+    set_tile_shapes,
     stage_names,
     workspace_size,
 )

@@ -382,3 +382,85 @@ def profile_buckets(edges, num_vertices: int, repeats: int = 5, workspace=None):
     _check(_sel_lib().tc_profile_buckets(ctx, e.data_ptr() if E else None, E, num_vertices, ws.data_ptr(),
                                          ws.numel(), repeats, _fptr(ms), _fptr(feat)), ctx)
     return ms, feat
+
+
+# ---------------------------------------------------------------- batched counting, tile shapes
+F_NO_GRAPH = 0x2
+
+
+def _batch_lib():
+    lib = _load()
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.tc_batch_workspace_size.argtypes = [i64, i64, i32, ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_size_t)]
+    lib.tc_count_triangles_batch.argtypes = [vp, vp, vp, vp, i32, vp, ctypes.c_size_t, ctypes.POINTER(Options), vp]
+    lib.tc_set_tile_shapes.argtypes = [vp, vp, vp]
+    lib.tc_profile_selected.argtypes = [vp, vp, i64, i32, vp, ctypes.c_size_t, ctypes.POINTER(Options), i32,
+                                        ctypes.POINTER(ctypes.c_float)]
+    for f in ("tc_batch_workspace_size", "tc_count_triangles_batch", "tc_set_tile_shapes", "tc_profile_selected"):
+        getattr(lib, f).restype = ctypes.c_int
+    return lib
+
+
+_batch_ws = {}
+
+
+def count_triangles_batch(edges, edge_offsets, num_vertices, select: int = SELECT_HEURISTIC, graph: bool = True,
+                          workspace=None):
+    """Exact triangle count of each graph of a batch (one pass over their disjoint union).
+
+    edges: int32 CUDA tensor [E, 2], graph g's pairs in rows
+    edge_offsets[g] .. edge_offsets[g+1] with ids local to the graph.
+    edge_offsets: int64 [G+1] host array; num_vertices: int32 [G] host array.
+    With graph=True the device work is captured once and replayed.
+    Returns a uint64 numpy array [G].
+    """
+    import numpy as np
+    torch = _torch()
+    e = _edges_arg(edges)
+    ctx, idx = _ctx(e.device)
+    eo = np.ascontiguousarray(edge_offsets, dtype=np.int64)
+    nv = np.ascontiguousarray(num_vertices, dtype=np.int32)
+    G = nv.size
+    if eo.size != G + 1:
+        raise ValueError("edge_offsets must have num_graphs + 1 entries")
+    lib = _batch_lib()
+    o = _options(select, False)
+    o.flags = 0 if graph else F_NO_GRAPH
+    nbytes = ctypes.c_size_t()
+    _check(lib.tc_batch_workspace_size(int(eo[-1]), int(nv.astype(np.int64).sum()), G, ctypes.byref(o),
+                                       ctypes.byref(nbytes)), None)
+    if workspace is None:
+        ws = _batch_ws.get(idx)
+        if ws is None or ws.numel() < nbytes.value:
+            ws = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=e.device)
+            _batch_ws[idx] = ws
+    else:
+        ws = workspace
+    counts = np.zeros(G, dtype=np.uint64)
+    _check(lib.tc_count_triangles_batch(ctx, e.data_ptr() if e.shape[0] else None, eo.ctypes.data, nv.ctypes.data, G,
+                                        ws.data_ptr(), ws.numel(), ctypes.byref(o), counts.ctypes.data), ctx)
+    return counts
+
+
+def set_tile_shapes(chunk=None, group=None, device="cuda:0") -> None:
+    """Per-bucket tile shapes: chunk[256] in-edges per tile, group[256] lanes per in-edge (0 = default)."""
+    import numpy as np
+    ctx, _ = _ctx(device)
+    c = None if chunk is None else np.ascontiguousarray(chunk, dtype=np.uint16)
+    g = None if group is None else np.ascontiguousarray(group, dtype=np.uint8)
+    _check(_batch_lib().tc_set_tile_shapes(ctx, c.ctypes.data if c is not None else None,
+                                           g.ctypes.data if g is not None else None), ctx)
+
+
+def profile_selected(edges, num_vertices: int, select: int = SELECT_HEURISTIC, repeats: int = 3, workspace=None):
+    """Per-bucket median milliseconds [256] with the strategy the mode selects (-1 = empty)."""
+    import numpy as np
+    e = _edges_arg(edges)
+    ctx, idx = _ctx(e.device)
+    E = e.shape[0]
+    ws = _workspace(idx, workspace_size(E, num_vertices), workspace)
+    ms = np.zeros(256, dtype=np.float32)
+    o = _options(select, False)
+    _check(_batch_lib().tc_profile_selected(ctx, e.data_ptr() if E else None, E, num_vertices, ws.data_ptr(),
+                                            ws.numel(), ctypes.byref(o), repeats, _fptr(ms)), ctx)
+    return ms

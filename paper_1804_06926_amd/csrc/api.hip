@@ -34,6 +34,19 @@ struct tc_ctx {
     tcx::MlpCompute* d_cw = nullptr;
     float* d_acts = nullptr;
     int adam_step = 0;
+    // batched counting: a stream for capture when the context's stream is the
+    // null stream, and the captured graph of the last batch shape
+    hipStream_t own_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    struct {
+        int64_t E, N;
+        int32_t G, select;
+        const void* edges;
+        const void* ws;
+    } graph_key = {};
+    uint64_t* h_counts_pinned = nullptr;
+    size_t h_counts_cap = 0;
 };
 
 namespace {
@@ -188,6 +201,10 @@ tc_status tc_destroy(tc_ctx* ctx) {
         for (float* p : bufs)
             if (p) (void)hipFree(p);
         if (ctx->d_cw) (void)hipFree(ctx->d_cw);
+        if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+        if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+        if (ctx->h_counts_pinned) (void)hipHostFree(ctx->h_counts_pinned);
     }
     delete ctx;
     return TC_OK;
@@ -305,9 +322,175 @@ tc_status tc_last_stats(const tc_ctx* ctx, tc_stats* out) {
     return TC_OK;
 }
 
+tc_status tc_batch_workspace_size(int64_t total_edges, int64_t total_vertices, int32_t num_graphs,
+                                  const tc_options* opts, size_t* bytes) {
+    if (!bytes || total_edges < 0 || total_vertices < 0 || num_graphs < 0 || !options_ok(opts))
+        return TC_ERR_INVALID_ARG;
+    if (total_edges > kMaxEdges || total_vertices >= ((int64_t)1 << 31)) return TC_ERR_UNSUPPORTED;
+    *bytes = tcx::make_batch_layout(total_edges, total_vertices, num_graphs).total;
+    return TC_OK;
+}
+
+tc_status tc_count_triangles_batch(tc_ctx* ctx, const int32_t* d_edges, const int64_t* h_edge_offsets,
+                                   const int32_t* h_num_vertices, int32_t num_graphs, void* d_workspace,
+                                   size_t workspace_bytes, const tc_options* opts, uint64_t* h_counts) {
+    if (!ctx) return TC_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    if (num_graphs < 0 || (num_graphs > 0 && (!h_edge_offsets || !h_num_vertices || !h_counts)))
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "null argument");
+    if (!options_ok(opts)) return arg_fail(ctx, TC_ERR_INVALID_ARG, "bad options");
+    if (num_graphs == 0) return TC_OK;
+    if (h_edge_offsets[0] != 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "edge_offsets[0] must be 0");
+    if (h_edge_offsets[num_graphs] == 0) {   // no pairs at all: every count is zero
+        for (int32_t g = 0; g < num_graphs; ++g) {
+            if (h_num_vertices[g] < 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "vertex counts must be >= 0");
+            h_counts[g] = 0;
+        }
+        return TC_OK;
+    }
+    int64_t N = 0;
+    std::vector<int64_t> voff((size_t)num_graphs + 1);
+    for (int32_t g = 0; g < num_graphs; ++g) {
+        if (h_edge_offsets[g + 1] < h_edge_offsets[g] || h_num_vertices[g] < 0)
+            return arg_fail(ctx, TC_ERR_INVALID_ARG, "edge offsets must not decrease; vertex counts >= 0");
+        voff[g] = N;
+        N += h_num_vertices[g];
+    }
+    voff[num_graphs] = N;
+    const int64_t E = h_edge_offsets[num_graphs];
+    if (E > kMaxEdges || N >= ((int64_t)1 << 31)) return arg_fail(ctx, TC_ERR_UNSUPPORTED, "batch too large");
+    if (E > 0 && !d_edges) return arg_fail(ctx, TC_ERR_INVALID_ARG, "null edge list");
+    if (((uintptr_t)d_edges & 7u) != 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "edge list must be 8-byte aligned");
+    const tcx::BatchLayout B = tcx::make_batch_layout(E, N, num_graphs);
+    if (!d_workspace || workspace_bytes < B.total) return arg_fail(ctx, TC_ERR_WORKSPACE, "workspace too small");
+    const int sel = opts ? opts->select : TC_SELECT_HEURISTIC;
+    if (sel == TC_SELECT_LEARNED && !ctx->learned_ready)
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "no selector network loaded or trained");
+    const bool capture = !(opts && (opts->flags & TC_F_NO_GRAPH));
+    DeviceGuard guard(ctx->device);
+    hipError_t e = hipSuccess;
+    hipStream_t s = ctx->stream;
+    if (!s) {   // the null stream cannot be captured: use the context's own stream
+        if (!ctx->own_stream) e = hipStreamCreate(&ctx->own_stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "create stream");
+        s = ctx->own_stream;
+    }
+    if ((size_t)num_graphs > ctx->h_counts_cap) {
+        if (ctx->h_counts_pinned) (void)hipHostFree(ctx->h_counts_pinned);
+        ctx->h_counts_pinned = nullptr;
+        ctx->h_counts_cap = 0;
+        e = hipHostMalloc((void**)&ctx->h_counts_pinned, sizeof(uint64_t) * (size_t)num_graphs, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(ctx, e, "pinned counts");
+        ctx->h_counts_cap = (size_t)num_graphs;
+    }
+    char* ws = (char*)d_workspace;
+    // graph descriptions go to the device outside any captured graph
+    e = hipMemcpyAsync(ws + B.eoff, h_edge_offsets, sizeof(int64_t) * ((size_t)num_graphs + 1),
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + B.voff, voff.data(), sizeof(int64_t) * voff.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + B.nv, h_num_vertices, sizeof(int32_t) * (size_t)num_graphs, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy graph offsets");
+
+    tcx::RunArgs ra = {};
+    ra.stream = s;
+    ra.ws = d_workspace;
+    ra.select = sel;
+    ra.mlp = ctx->learned_ready ? ctx->d_cw : nullptr;
+    ra.learned = ctx->d_learned;
+    ra.chunk_override = ctx->d_chunk;
+    ra.group_override = ctx->d_group;
+    ra.grid_override = ctx->grid_override;
+    tcx::BatchArgs ba = {d_edges, E, N, num_graphs};
+    const bool same = ctx->graph_exec && ctx->graph_key.E == E && ctx->graph_key.N == N &&
+                      ctx->graph_key.G == num_graphs && ctx->graph_key.select == sel &&
+                      ctx->graph_key.edges == d_edges && ctx->graph_key.ws == d_workspace;
+    if (capture && !same) {
+        if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+        if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+        ctx->graph_exec = nullptr;
+        ctx->graph = nullptr;
+        e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(ctx, e, "begin capture");
+        hipError_t le = tcx::run_batch(ba, ra);
+        e = hipStreamEndCapture(s, &ctx->graph);
+        if (le != hipSuccess) e = le;
+        if (e == hipSuccess) e = hipGraphInstantiate(&ctx->graph_exec, ctx->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return hip_fail(ctx, e, "capture batch");
+        ctx->graph_key = {E, N, num_graphs, sel, d_edges, d_workspace};
+    }
+    if (capture) e = hipGraphLaunch(ctx->graph_exec, s);
+    else e = tcx::run_batch(ba, ra);
+    if (e != hipSuccess) return hip_fail(ctx, e, "launch batch");
+    e = hipMemcpyAsync(ctx->h_ctrl, ws + B.pipe.ctrl, sizeof(tcx::Ctrl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->h_counts_pinned, ws + B.counts, sizeof(uint64_t) * (size_t)num_graphs,
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "read batch counts");
+    ctx->have_times = 0;
+    if (ctx->h_ctrl->err & 1u) return arg_fail(ctx, TC_ERR_VERTEX_RANGE, "vertex id outside its graph's range");
+    memcpy(h_counts, ctx->h_counts_pinned, sizeof(uint64_t) * (size_t)num_graphs);
+    return TC_OK;
+}
+
+tc_status tc_set_tile_shapes(tc_ctx* ctx, const uint16_t* h_chunk, const uint8_t* h_group) {
+    if (!ctx) return TC_ERR_INVALID_ARG;
+    DeviceGuard guard(ctx->device);
+    std::vector<uint16_t> c(tcx::NBUCKET, 0);
+    std::vector<uint8_t> g(tcx::NBUCKET, 0);
+    if (h_chunk) memcpy(c.data(), h_chunk, sizeof(uint16_t) * tcx::NBUCKET);
+    if (h_group) memcpy(g.data(), h_group, tcx::NBUCKET);
+    hipError_t e = hipMemcpy(ctx->d_chunk, c.data(), sizeof(uint16_t) * tcx::NBUCKET, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_group, g.data(), tcx::NBUCKET, hipMemcpyHostToDevice);
+    return e == hipSuccess ? TC_OK : hip_fail(ctx, e, "set tile shapes");
+}
+
 tc_status tc_bucket_features(const tc_ctx* ctx, float* h_features) {
     if (!ctx || !h_features) return TC_ERR_INVALID_ARG;
     memcpy(h_features, ctx->h_ctrl->features, sizeof(ctx->h_ctrl->features));
+    return TC_OK;
+}
+
+// Lay out the tiles under selection mode `select`, then time each busy bucket's
+// tiles alone with the kernel the mode chose for it (median of `repeats`).
+// ms_row(kernel) gives the output row for a kernel.
+static tc_status profile_pass(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* ws, size_t ws_bytes,
+                              int select, int32_t repeats, float* h_ms, bool row_per_kernel, float* h_features) {
+    tc_options o = {};
+    o.select = select;
+    tcx::RunArgs ra = {};
+    ra.stop_before_isect = 1;
+    tc_status st = run(ctx, d_edges, E, n, ws, ws_bytes, &o, ra);
+    if (st != TC_OK) return st;
+    if (h_features) memcpy(h_features, ctx->h_ctrl->features, sizeof(ctx->h_ctrl->features));
+    DeviceGuard guard(ctx->device);
+    const tcx::Layout L = tcx::make_layout(E, n);
+    std::vector<uint32_t> tstart((size_t)n + 1);
+    hipError_t e = hipMemcpy(tstart.data(), (char*)ws + L.tstart, sizeof(uint32_t) * tstart.size(),
+                             hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "read tile starts");
+    const tcx::Ctrl c = *ctx->h_ctrl;
+    for (int b = 0; b < tcx::NBUCKET - 1; ++b) {
+        if (c.bucket_nv[b] == 0 || c.bend[b] <= c.bstart[b]) continue;
+        const uint32_t t0 = tstart[c.bstart[b]], t1 = tstart[c.bend[b]];
+        if (t1 <= t0) continue;
+        const int k = c.choice[b];
+        std::vector<float> ms;
+        for (int r = 0; r < repeats; ++r) {
+            (void)hipEventRecord(ctx->events[0], ctx->stream);
+            e = tcx::launch_isect_range(ra, k, t0, t1);
+            (void)hipEventRecord(ctx->events[1], ctx->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(ctx->events[1]);
+            float t = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, ctx->events[0], ctx->events[1]);
+            if (e != hipSuccess) return hip_fail(ctx, e, "profile launch");
+            ms.push_back(t);
+        }
+        std::sort(ms.begin(), ms.end());
+        h_ms[(row_per_kernel ? k * tcx::NBUCKET : 0) + b] = ms[ms.size() / 2];
+    }
     return TC_OK;
 }
 
@@ -317,41 +500,23 @@ tc_status tc_profile_buckets(tc_ctx* ctx, const int32_t* d_edges, int64_t num_ed
     if (!ctx || !h_ms || repeats < 1 || repeats > 64) return arg_fail(ctx, TC_ERR_INVALID_ARG, "bad arguments");
     for (int i = 0; i < tcx::NKERNEL * tcx::NBUCKET; ++i) h_ms[i] = -1.f;
     if (num_edges == 0) return TC_OK;
-    std::vector<uint32_t> tstart((size_t)num_vertices + 1);
-    for (int k = 0; k < tcx::NKERNEL; ++k) {
-        tc_options o = {};
-        o.select = TC_FORCE_MERGE + k;   // merge, bsearch, bitmap follow in order
-        tcx::RunArgs ra = {};
-        ra.stop_before_isect = 1;
-        tc_status st = run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, &o, ra);
+    for (int k = 0; k < tcx::NKERNEL; ++k) {   // merge, bsearch, bitmap follow in order
+        tc_status st = profile_pass(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes,
+                                    TC_FORCE_MERGE + k, repeats, h_ms, true, k == 0 ? h_features : nullptr);
         if (st != TC_OK) return st;
-        if (k == 0 && h_features) memcpy(h_features, ctx->h_ctrl->features, sizeof(ctx->h_ctrl->features));
-        DeviceGuard guard(ctx->device);
-        const tcx::Layout L = tcx::make_layout(num_edges, num_vertices);
-        hipError_t e = hipMemcpy(tstart.data(), (char*)d_workspace + L.tstart, sizeof(uint32_t) * tstart.size(),
-                                 hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_fail(ctx, e, "read tile starts");
-        const tcx::Ctrl c = *ctx->h_ctrl;
-        for (int b = 0; b < tcx::NBUCKET - 1; ++b) {
-            if (c.bucket_nv[b] == 0 || c.bend[b] <= c.bstart[b]) continue;
-            const uint32_t t0 = tstart[c.bstart[b]], t1 = tstart[c.bend[b]];
-            if (t1 <= t0) continue;
-            std::vector<float> ms;
-            for (int r = 0; r < repeats; ++r) {
-                (void)hipEventRecord(ctx->events[0], ctx->stream);
-                e = tcx::launch_isect_range(ra, k, t0, t1);
-                (void)hipEventRecord(ctx->events[1], ctx->stream);
-                if (e == hipSuccess) e = hipEventSynchronize(ctx->events[1]);
-                float t = 0.f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&t, ctx->events[0], ctx->events[1]);
-                if (e != hipSuccess) return hip_fail(ctx, e, "profile launch");
-                ms.push_back(t);
-            }
-            std::sort(ms.begin(), ms.end());
-            h_ms[k * tcx::NBUCKET + b] = ms[ms.size() / 2];
-        }
     }
     return TC_OK;
+}
+
+tc_status tc_profile_selected(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                              void* d_workspace, size_t workspace_bytes, const tc_options* opts, int32_t repeats,
+                              float* h_ms) {
+    if (!ctx || !h_ms || repeats < 1 || repeats > 64 || !options_ok(opts))
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "bad arguments");
+    for (int i = 0; i < tcx::NBUCKET; ++i) h_ms[i] = -1.f;
+    if (num_edges == 0) return TC_OK;
+    return profile_pass(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes,
+                        opts ? opts->select : TC_SELECT_HEURISTIC, repeats, h_ms, false, nullptr);
 }
 
 static tc_status ensure_acts(tc_ctx* ctx) {

@@ -22,6 +22,7 @@ struct IsectArgs {
     const uint64_t* tiles;      // [ntiles] position | (chunk or TILE_MULTI | count) << 32
     uint32_t* per_edge;         // [m] or null: c_e in CSR edge order
     uint64_t* per_vertex;       // [n] or null: t[] in rank space
+    uint64_t* per_middle;       // [n] or null: triangles whose middle vertex is v (rank space)
 };
 
 int isect_blocks_per_cu(int ker);

@@ -74,8 +74,10 @@ __device__ uint32_t load_tile(const IsectArgs& a, uint32_t t, Segs& S) {
 
 __device__ __forceinline__ uint32_t tail_end(const IsectArgs& a, uint32_t e) { return a.off[a.src[e] + 1]; }
 
-__device__ __forceinline__ void edge_done(const IsectArgs& a, uint32_t e, uint32_t v, uint32_t c) {
+__device__ __forceinline__ void edge_done(const IsectArgs& a, uint32_t e, uint32_t v, uint32_t c,
+                                          bool middle = true) {
     if (a.per_edge) a.per_edge[e] = c;
+    if (middle && a.per_middle && c) atomicAdd((unsigned long long*)&a.per_middle[v], (unsigned long long)c);
     if (a.per_vertex && c) {
         atomicAdd((unsigned long long*)&a.per_vertex[a.src[e]], (unsigned long long)c);
         atomicAdd((unsigned long long*)&a.per_vertex[v], (unsigned long long)c);
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
     __shared__ Segs S;
     for (int i = threadIdx.x; i < BM_WORDS; i += IS_NT) bm[i] = 0;
     if (threadIdx.x < IS_NT / WAVE) s_mask[threadIdx.x] = 0ull;
-    const bool need_cnt = a.per_edge || a.per_vertex;
+    const bool need_cnt = a.per_edge || a.per_vertex || a.per_middle;
     uint64_t acc = 0;
     const uint32_t t_end = a.ctrl->tile_begin[KER_BITMAP + 1];
     for (uint32_t t = a.ctrl->tile_begin[KER_BITMAP] + blockIdx.x; t < t_end; t += gridDim.x) {
@@ -209,8 +211,19 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                 }
                 __syncthreads();
             }
-            if (need_cnt)
-                for (uint32_t k = threadIdx.x; k < ne; k += IS_NT) edge_done(a, s_start[k] - 1u, v, s_cnt[k]);
+            if (need_cnt) {
+                uint32_t seg_hits = 0;
+                for (uint32_t k = threadIdx.x; k < ne; k += IS_NT) {
+                    edge_done(a, s_start[k] - 1u, v, s_cnt[k], false);
+                    seg_hits += s_cnt[k];
+                }
+                if (a.per_middle) {   // one update per vertex and tile
+                    uint32_t total;
+                    (void)block_exclusive_scan<IS_NT>(seg_hits, S.scratch, &total);
+                    if (threadIdx.x == 0 && total)
+                        atomicAdd((unsigned long long*)&a.per_middle[v], (unsigned long long)total);
+                }
+            }
             __syncthreads();
         }
     }

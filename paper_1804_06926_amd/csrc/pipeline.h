@@ -36,6 +36,8 @@ struct RunArgs {
     const uint8_t* group_override;   // device [256] or null
     const int* grid_override;        // host [3] or null
     uint64_t* per_vertex;            // device [n] or null (original ids)
+    uint64_t* per_middle;            // device [n] or null (original ids): triangles with v in the middle
+                                     // (exclusive with per_vertex: both use the same scratch)
     uint32_t* per_edge_counts;       // device [E] or null (CSR order)
     int32_t* per_edge_pairs;         // device [E][2] or null
     int32_t* csr_rank;               // device [n] or null (CSR export)
@@ -49,6 +51,24 @@ struct RunResult {
 };
 
 hipError_t run_pipeline(const RunArgs& r, RunResult* out);
+
+// ---- batched counting (batch.hip)
+struct BatchLayout {
+    Layout pipe;   // the union graph's pipeline workspace comes first
+    size_t union_edges, eoff, voff, nv, middle, counts;
+    size_t total;
+};
+BatchLayout make_batch_layout(int64_t E, int64_t N, int32_t G);
+
+struct BatchArgs {
+    const int32_t* edges;   // device [E][2], graph-local ids, graphs in order
+    int64_t E;              // total pairs
+    int64_t N;              // total vertices
+    int32_t G;              // graphs
+};
+// Enqueue the whole batched count (graph offsets already in the workspace).
+// r carries the stream, workspace and selection; its graph fields are set here.
+hipError_t run_batch(const BatchArgs& b, RunArgs& r);
 // After a run with stop_before_isect: one intersection kernel over tiles [t0, t1).
 hipError_t launch_isect_range(const RunArgs& r, int ker, uint32_t t0, uint32_t t1);
 int stage_count();

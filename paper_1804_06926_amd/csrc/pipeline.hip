@@ -458,6 +458,7 @@ static IsectArgs isect_args(const RunArgs& r, const Layout& L, uint64_t* csc) {
     ia.tiles = (const uint64_t*)(ws + L.tiles);
     ia.per_edge = r.per_edge_counts;
     ia.per_vertex = r.per_vertex ? (uint64_t*)(ws + L.pv) : nullptr;
+    ia.per_middle = r.per_middle ? (uint64_t*)(ws + L.pv) : nullptr;
     return ia;
 }
 
@@ -599,7 +600,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     hipLaunchKernelGGL(k_emit_tiles, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vlist, vbucket, tstart, n, ctrl,
                        tiles, (uint64_t)L.tile_cap);
     if (r.per_edge_counts) fill_u32(r.per_edge_counts, 0u, (size_t)E, s);
-    if (r.per_vertex) fill_u64(pv, 0ull, (size_t)n, s);
+    if (r.per_vertex || r.per_middle) fill_u64(pv, 0ull, (size_t)n, s);
     mark(8);
     if (r.stop_before_isect) {
         out->ctrl_dev = ctrl;
@@ -618,6 +619,8 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     // ---- finish
     if (r.per_vertex)
         hipLaunchKernelGGL(k_map_pv, dim3(grid_for((size_t)n)), dim3(NT), 0, s, pv, inv, n, r.per_vertex);
+    else if (r.per_middle)
+        hipLaunchKernelGGL(k_map_pv, dim3(grid_for((size_t)n)), dim3(NT), 0, s, pv, inv, n, r.per_middle);
     if (r.per_edge_pairs)
         hipLaunchKernelGGL(k_map_edges, dim3(grid_for((size_t)E)), dim3(NT), 0, s, col, src, inv, ctrl,
                            (int2*)r.per_edge_pairs);

@@ -1,0 +1,148 @@
+"""Learned kernel selection: timing collection, labels, training, persistence.
+
+The counting path groups the middle vertices of the oriented graph into
+degree-pair buckets and runs one of three intersection strategies per bucket
+(merge path, binary search, LDS bitmap). This module trains the small
+network that picks the strategy:
+
+1. ``collect``: for each training graph, the library times every strategy on
+   every bucket's tiles alone (``profile_buckets``) and reports the bucket
+   features.
+2. ``make_labels``: the fastest strategy per bucket by median time; within
+   ``tie`` of the heuristic's time the heuristic's choice is kept.
+3. ``train``: full-batch Adam on the GPU with the library's own forward and
+   backward kernels (``selector_train_step``); samples are weighted by how
+   much time the choice can save.
+4. ``save`` / ``load``: float32 master parameters as JSON.
+
+The fixed-threshold heuristic (``heuristic_choice``) is the fallback and the
+baseline the learned choice is compared with.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+from . import _lib
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "selector_weights.json")
+KERNELS = ("merge", "bsearch", "bitmap")
+
+
+def heuristic_choice(bucket: int) -> int:
+    """The library's fixed thresholds (same rule as the device code)."""
+    li, lo = bucket >> 4, bucket & 15
+    if li >= 6:
+        return 2
+    if lo >= 4:
+        return 1
+    return 0
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-normal weights, zero biases (float32, 1379 entries)."""
+    rng = np.random.default_rng(seed)
+    shapes = [(32, 6), (32,), (32, 32), (32,), (3, 32), (3,)]
+    parts = []
+    for s in shapes:
+        if len(s) == 2:
+            parts.append(rng.normal(0.0, np.sqrt(2.0 / s[1]), size=s).ravel())
+        else:
+            parts.append(np.zeros(s))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def collect(graphs, repeats: int = 5, device: str = "cuda:0", log=None):
+    """Time every strategy on every busy bucket of each graph.
+
+    graphs: iterable of (name, edges int32 [E, 2] numpy, num_vertices).
+    Returns a dict of arrays: features [N, 6], times [N, 3] (ms), bucket [N],
+    graph [N] (index into names), and names.
+    """
+    import torch
+    feats, times, buckets, gids, names = [], [], [], [], []
+    for gi, (name, edges, n) in enumerate(graphs):
+        d = torch.from_numpy(np.ascontiguousarray(edges, dtype=np.int32)).to(device)
+        ms, feat = _lib.profile_buckets(d, n, repeats=repeats)
+        for b in range(255):
+            if np.all(ms[:, b] > 0):
+                feats.append(feat[b])
+                times.append(ms[:, b])
+                buckets.append(b)
+                gids.append(gi)
+        names.append(name)
+        if log:
+            log(f"[selector] collected {name}: {sum(1 for g in gids if g == gi)} buckets")
+        del d
+    return {"features": np.array(feats, dtype=np.float32).reshape(-1, 6),
+            "times": np.array(times, dtype=np.float64).reshape(-1, 3),
+            "bucket": np.array(buckets, dtype=np.int64), "graph": np.array(gids, dtype=np.int64),
+            "names": names}
+
+
+def make_labels(times: np.ndarray, buckets: np.ndarray, tie: float = 0.02) -> np.ndarray:
+    best = np.argmin(times, axis=1)
+    heur = np.array([heuristic_choice(int(b)) for b in buckets])
+    keep = times[np.arange(len(best)), heur] <= (1.0 + tie) * times[np.arange(len(best)), best]
+    return np.where(keep, heur, best).astype(np.int32)
+
+
+def sample_weights(times: np.ndarray) -> np.ndarray:
+    """Weight each bucket by the time at stake (slowest minus fastest), mean 1."""
+    stake = times.max(axis=1) - times.min(axis=1)
+    w = np.sqrt(stake + 1e-6)
+    return (w / w.mean()).astype(np.float32)
+
+
+def train(features, labels, weights=None, steps: int = 3000, lr: float = 3e-3, seed: int = 0,
+          device: str = "cuda:0", log=None):
+    """Full-batch Adam on the GPU. Returns (params, losses)."""
+    import torch
+    _lib.selector_set_params(init_params(seed), device)
+    x = torch.from_numpy(np.ascontiguousarray(features, dtype=np.float32)).to(device)
+    y = torch.from_numpy(np.ascontiguousarray(labels, dtype=np.int32)).to(device)
+    w = None if weights is None else torch.from_numpy(np.ascontiguousarray(weights, dtype=np.float32)).to(device)
+    losses = []
+    for step in range(steps):
+        losses.append(_lib.selector_train_step(x, y, w, lr=lr))
+        if log and (step % 500 == 0 or step == steps - 1):
+            log(f"[selector] step {step} loss {losses[-1]:.4f}")
+    return _lib.selector_get_params(device), losses
+
+
+def predict(features, device: str = "cuda:0") -> np.ndarray:
+    import torch
+    x = torch.from_numpy(np.ascontiguousarray(features, dtype=np.float32)).to(device)
+    return _lib.selector_forward(x).argmax(dim=1).cpu().numpy()
+
+
+def regret(times: np.ndarray, choices: np.ndarray) -> float:
+    """Sum over buckets of (time of the chosen strategy - best time), ms."""
+    idx = np.arange(times.shape[0])
+    return float(np.sum(times[idx, choices] - times.min(axis=1)))
+
+
+def save(path: str, params: np.ndarray, meta: dict | None = None) -> None:
+    doc = {"format": "tc-selector-v1", "num_params": int(params.size),
+           "params": [float(x) for x in np.asarray(params, dtype=np.float32)], "meta": meta or {}}
+    with open(path, "w") as f:
+        json.dump(doc, f)
+
+
+def load(path: str) -> np.ndarray:
+    with open(path) as f:
+        doc = json.load(f)
+    if doc.get("format") != "tc-selector-v1" or doc.get("num_params") != _lib.SELECTOR_NUM_PARAMS:
+        raise ValueError(f"{path}: not a selector parameter file")
+    return np.asarray(doc["params"], dtype=np.float32)
+
+
+def load_default(device: str = "cuda:0") -> bool:
+    """Load the packaged trained parameters into the device's context, if present."""
+    if not os.path.exists(DEFAULT_WEIGHTS):
+        return False
+    _lib.selector_set_params(load(DEFAULT_WEIGHTS), device)
+    return True

@@ -1,0 +1,129 @@
+"""Train the kernel-selector network on the GPU and evaluate it on held-out graphs.
+
+Training graphs: R-MAT scales 18-22 (edge factor 16) and Chung-Lu graphs
+(power-law exponent 2.1), all seeded apart from the benchmark and test graphs.
+Held-out graphs: R-MAT scale 24 and a random geometric graph on 2^23 vertices
+(average degree 32), plus any others named on the command line.
+
+Writes the float32 parameters (JSON, see selector.save) and a report with the
+per-graph regret of the learned choice, of the heuristic and of every single
+strategy, and the end-to-end step time of the learned and heuristic modes.
+
+    python -m paper_1804_06926_amd.train_selector --out selector_weights.json --report report.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def training_graphs(quick: bool):
+    import graphgen
+    scales = (16, 17, 18) if quick else (18, 19, 20, 21, 22)
+    for i, s in enumerate(scales):
+        yield f"rmat{s}_seed{101 + i}", graphgen.rmat(s, 16, seed=101 + i), 1 << s
+    sizes = ((1 << 16, 8 << 16), (1 << 17, 16 << 17)) if quick else \
+        ((1 << 17, 8 << 17), (1 << 18, 16 << 18), (1 << 19, 8 << 19), (1 << 20, 16 << 20), (1 << 21, 8 << 21))
+    for i, (n, E) in enumerate(sizes):
+        yield f"chunglu_n{n}_seed{201 + i}", graphgen.chung_lu(n, E, 2.1, seed=201 + i), n
+
+
+def heldout_graphs(quick: bool):
+    import graphgen
+    if quick:
+        yield "rmat19_seed1", graphgen.rmat(19, 16, seed=1), 1 << 19
+        yield "rgg_2^18", graphgen.rgg(1 << 18, 32.0, seed=5), 1 << 18
+    else:
+        yield "rmat24_seed1", graphgen.rmat(24, 16, seed=1), 1 << 24
+        yield "rgg_2^23", graphgen.rgg(1 << 23, 32.0, seed=5), 1 << 23
+
+
+def step_time(tc, d, n, select, steps=5):
+    import torch
+    tc.count_triangles(d, n, select=select)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        T = tc.count_triangles(d, n, select=select)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, T
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--report", required=True)
+    ap.add_argument("--repeats", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--quick", action="store_true", help="small graphs (for a smoke run)")
+    args = ap.parse_args(argv)
+
+    import torch
+
+    import paper_1804_06926_amd as tc
+    from paper_1804_06926_amd import selector
+
+    t0 = time.time()
+    data = selector.collect(training_graphs(args.quick), repeats=args.repeats, log=log)
+    y = selector.make_labels(data["times"], data["bucket"])
+    w = selector.sample_weights(data["times"])
+    log(f"[selector] {len(y)} training buckets; label counts {np.bincount(y, minlength=3).tolist()}")
+    params, losses = selector.train(data["features"], y, w, steps=args.steps, lr=args.lr, log=log)
+    pred = selector.predict(data["features"])
+    report = {"train": {"buckets": int(len(y)), "accuracy": float(np.mean(pred == y)),
+                        "loss_first": losses[0], "loss_last": losses[-1],
+                        "regret_learned_ms": selector.regret(data["times"], pred),
+                        "regret_heuristic_ms": selector.regret(
+                            data["times"], np.array([selector.heuristic_choice(int(b)) for b in data["bucket"]])),
+                        "graphs": data["names"]}}
+    selector.save(args.out, params, {"trained_on": data["names"], "steps": args.steps, "lr": args.lr,
+                                     "repeats": args.repeats})
+    log(f"[selector] saved {args.out}; train report {report['train']}")
+
+    report["heldout"] = []
+    for name, edges, n in heldout_graphs(args.quick):
+        log(f"[selector] held-out {name}")
+        d = torch.from_numpy(edges).cuda()
+        ms, feat = tc.profile_buckets(d, n, repeats=args.repeats)
+        busy = [b for b in range(255) if np.all(ms[:, b] > 0)]
+        times = ms[:, busy].T.astype(np.float64)
+        fx = feat[busy]
+        learned = selector.predict(fx)
+        heur = np.array([selector.heuristic_choice(b) for b in busy])
+        entry = {"graph": name, "buckets": len(busy),
+                 "regret_learned_ms": selector.regret(times, learned),
+                 "regret_heuristic_ms": selector.regret(times, heur),
+                 "best_total_ms": float(times.min(axis=1).sum())}
+        for k, kn in enumerate(selector.KERNELS):
+            entry[f"regret_all_{kn}_ms"] = selector.regret(times, np.full(len(busy), k))
+        tc.selector_set_params(params)
+        t_l, T_l = step_time(tc, d, n, tc.SELECT_LEARNED)
+        t_h, T_h = step_time(tc, d, n, tc.SELECT_HEURISTIC)
+        assert T_l == T_h, (T_l, T_h)
+        entry.update({"step_ms_learned": t_l, "step_ms_heuristic": t_h, "triangles": T_l})
+        report["heldout"].append(entry)
+        log(f"[selector] {entry}")
+        del d
+    report["wall_s"] = time.time() - t0
+    with open(args.report, "w") as f:
+        json.dump(report, f, indent=1)
+    log(f"[selector] report written to {args.report}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
