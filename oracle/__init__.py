@@ -60,6 +60,7 @@ def _load():
     lib.oracle_vertex_triangles.argtypes = [vp, vp, ctypes.c_int64, vp, ctypes.c_int]
     lib.oracle_oriented_edge_counts.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
     lib.oracle_edge_support.argtypes = [vp, vp, ctypes.c_int]
+    lib.oracle_pair_counts.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int, vp, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -131,6 +132,15 @@ class Graph:
         mode = {"simple": 0, "input": 1}[degree]
         if self.m:
             _load().oracle_oriented_edge_counts(self._h, mode, out.ctypes.data, self.threads)
+        return out
+
+    def pair_counts(self, pairs, degree: str = "simple") -> np.ndarray:
+        """oriented_edge_counts for the given pairs only (0 for a pair that is not an edge)."""
+        p = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        out = np.zeros(p.shape[0], dtype=np.uint32)
+        if p.size:
+            _load().oracle_pair_counts(self._h, p.ctypes.data, p.shape[0], {"simple": 0, "input": 1}[degree],
+                                       out.ctypes.data, self.threads)
         return out
 
     def edge_support(self) -> np.ndarray:

@@ -271,6 +271,39 @@ void oracle_oriented_edge_counts(const void* h, int degree_mode, uint32_t* out, 
     }
 }
 
+/*
+ * The oriented per-edge count of oracle_oriented_edge_counts for k given
+ * pairs (a_q, b_q) (any order; each must be an edge of the graph, else the
+ * count is 0): the number of common neighbours w after both a_q and b_q in
+ * (degree, id) order, degree_mode as above.
+ */
+void oracle_pair_counts(const void* h, const int32_t* pairs, int64_t k, int degree_mode, uint32_t* out,
+                        int threads) {
+    const Graph* g = (const Graph*)h;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(pick_threads(threads))
+    for (int64_t q = 0; q < k; ++q) {
+        const int32_t a = pairs[2 * q], b = pairs[2 * q + 1];
+        const int32_t* na = g->adj.data() + g->adj_off[a];
+        const int32_t* nb = g->adj.data() + g->adj_off[b];
+        const int64_t da = g->adj_off[a + 1] - g->adj_off[a], db = g->adj_off[b + 1] - g->adj_off[b];
+        if (!std::binary_search(na, na + da, b)) { out[q] = 0; continue; }
+        uint32_t c = 0;
+        int64_t x = 0, y = 0;
+        while (x < da && y < db) {
+            if (na[x] < nb[y]) ++x;
+            else if (na[x] > nb[y]) ++y;
+            else {
+                const int32_t w = na[x];
+                const bool after_a = degree_mode ? precedes_input_deg_id(*g, a, w) : precedes_deg_id(*g, a, w);
+                const bool after_b = degree_mode ? precedes_input_deg_id(*g, b, w) : precedes_deg_id(*g, b, w);
+                if (after_a && after_b) ++c;
+                ++x; ++y;
+            }
+        }
+        out[q] = c;
+    }
+}
+
 /* Per-edge triangle support |N(a) intersected with N(b)| for canonical pair i. */
 void oracle_edge_support(const void* h, uint32_t* out, int threads) {
     const Graph* g = (const Graph*)h;

@@ -227,6 +227,20 @@ def test_oriented_counts_input_degree_mode():
     assert np.array_equal(g2.oriented_edge_counts("simple"), oracle.Graph(g2.edges(), n).oriented_edge_counts("input"))
 
 
+def test_pair_counts_match_full_oriented_counts():
+    e, n = _rmat_small(11, 12)
+    dirty = np.concatenate([e, e[::5, ::-1]]).astype(np.int32)
+    g = oracle.Graph(dirty, n)
+    for mode in ("simple", "input"):
+        full = g.oriented_edge_counts(mode)
+        pe = g.edges()
+        rng = np.random.default_rng(1)
+        idx = rng.choice(g.m, 500, replace=False)
+        q = pe[idx][:, ::-1].copy()   # reversed order must not matter
+        np.testing.assert_array_equal(g.pair_counts(q, mode), full[idx])
+    assert g.pair_counts(np.array([[0, 0]]))[0] == 0
+
+
 def test_edge_support():
     e, n = _rmat_small(9, 10)
     g = oracle.Graph(e, n)
