@@ -15,7 +15,7 @@ struct IsectArgs {
     const uint32_t* off;       // [n+1] CSR row offsets (ranks)
     const uint32_t* col;        // [m]   CSR columns, rows ascending
     const uint32_t* src;        // [m]   row of each edge
-    const uint64_t* csc;        // [m_active] v << 32 | e, grouped by v
+    const uint64_t* csc;        // [m_active] tail start | tail end << 32, grouped by middle vertex
     const uint32_t* inoff;      // [n+1] start of each vertex's in-edges in csc
     const uint32_t* vlist;      // [n]   vertices in (kernel, bucket) order
     const uint8_t* vbucket;     // [n]   bucket of each vertex

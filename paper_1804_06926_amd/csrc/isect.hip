@@ -12,8 +12,8 @@
 // in-edge of a tile:
 //   merge   : merge-path split of (tail, N+(v)) across a group of lanes
 //   bsearch : binary search of each element of the shorter list in the other
-//   bitmap  : N+(v) staged once per vertex as an LDS bitmap; tails streamed
-//             through it (long tails by a whole wave, short ones by one lane)
+//   bitmap  : N+(v) staged once per vertex as an LDS bitmap; all tails of the
+//             tile streamed through it as one flat, coalesced item range
 // Each hit adds 1 to the exact 64-bit triangle count; optional outputs are
 // the per-edge counts c_e and per-vertex counts t[u], t[v], t[w].
 // Tiles are dealt to blocks round-robin (no shared work counter); each block
@@ -72,8 +72,6 @@ __device__ uint32_t load_tile(const IsectArgs& a, uint32_t t, Segs& S) {
     return nseg;
 }
 
-__device__ __forceinline__ uint32_t tail_end(const IsectArgs& a, uint32_t e) { return a.off[a.src[e] + 1]; }
-
 __device__ __forceinline__ void edge_done(const IsectArgs& a, uint32_t e, uint32_t v, uint32_t c,
                                           bool middle = true) {
     if (a.per_edge) a.per_edge[e] = c;
@@ -130,9 +128,9 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                 const uint32_t k = h * IS_NT + threadIdx.x;
                 uint32_t len = 0;
                 if (k < ne) {
-                    const uint32_t e = (uint32_t)a.csc[e0 + k];
-                    const uint32_t s = e + 1u;
-                    len = tail_end(a, e) - s;
+                    const uint64_t ent = a.csc[e0 + k];   // tail start | tail end << 32
+                    const uint32_t s = (uint32_t)ent;
+                    len = (uint32_t)(ent >> 32) - s;
                     s_start[k] = s;
                     if (need_cnt) s_cnt[k] = 0;
                 }
@@ -334,8 +332,9 @@ __global__ __launch_bounds__(IS_NT) void k_isect_edges(IsectArgs a, uint64_t* pa
             if (q < ne) {
                 const uint32_t sg = nseg == 1 ? 0u : find_seg(S, nseg, q);
                 v = S.v[sg];
-                e = (uint32_t)a.csc[S.e0[sg] + (q - S.pref[sg])];
-                const uint32_t s = e + 1u, end = tail_end(a, e);
+                const uint64_t ent = a.csc[S.e0[sg] + (q - S.pref[sg])];   // tail start | end << 32
+                const uint32_t s = (uint32_t)ent, end = (uint32_t)(ent >> 32);
+                e = s - 1u;
                 const uint32_t* B = staged ? sb : a.col + a.off[v];
                 const uint32_t nb = a.off[v + 1] - a.off[v];
                 c = isect_edge<MERGE>(a, a.col + s, end - s, B, nb, g, gl);

@@ -202,6 +202,18 @@ __global__ __launch_bounds__(NT) void k_csc_bounds(const uint64_t* __restrict__ 
     }
 }
 
+// In place, after the bounds are known: entry v << 32 | e becomes the tail
+// range of edge e, start (e + 1) | end << 32, so a kernel reads it in one load.
+__global__ __launch_bounds__(NT) void k_csc_expand(uint64_t* __restrict__ csc, const Ctrl* ctrl,
+                                                   const uint32_t* __restrict__ src,
+                                                   const uint32_t* __restrict__ off) {
+    const uint32_t ma = ctrl->m_active;
+    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < ma; i += (uint64_t)gridDim.x * NT) {
+        const uint32_t e = (uint32_t)csc[i];
+        csc[i] = (uint64_t)(e + 1u) | ((uint64_t)off[src[e] + 1] << 32);
+    }
+}
+
 // ------------------------------------------------------------------ buckets
 __device__ __forceinline__ uint32_t bucket_of(uint32_t din, uint32_t dout) {
     if (din == 0 || dout == 0) return BUCKET_NONE;
@@ -579,6 +591,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     hipLaunchKernelGGL(k_csc_bounds, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, n, rowend);
     fill_u32(inoff, 0u, 1, s);
     scan_inclusive_max_u32(rowend, inoff + 1, (size_t)n, scan_tmp, s);
+    hipLaunchKernelGGL(k_csc_expand, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, src, off);
     mark(6);
     // ---- buckets + selection
     hipLaunchKernelGGL(k_vbucket, dim3(grid_for((size_t)n, 2048)), dim3(NT), 0, s, off, inoff, n, vbucket, ctrl);
