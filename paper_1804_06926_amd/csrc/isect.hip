@@ -105,10 +105,10 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
     __shared__ uint32_t s_pref[CHUNK_MAX + 1];
     __shared__ uint32_t s_cnt[CHUNK_MAX];
     __shared__ uint32_t s_base[CHUNK_MAX];
-    __shared__ unsigned long long s_mask[IS_NT / WAVE];
+    __shared__ unsigned long long s_mask[IS_NT / WAVE][UNROLL];
     __shared__ Segs S;
     for (int i = threadIdx.x; i < BM_WORDS; i += IS_NT) bm[i] = 0;
-    if (threadIdx.x < IS_NT / WAVE) s_mask[threadIdx.x] = 0ull;
+    if (threadIdx.x < (IS_NT / WAVE) * UNROLL) (&s_mask[0][0])[threadIdx.x] = 0ull;
     const bool need_cnt = a.per_edge || a.per_vertex || a.per_middle;
     uint64_t acc = 0;
     const uint32_t t_end = a.ctrl->tile_begin[KER_BITMAP + 1];
@@ -177,21 +177,35 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                 }
                 const uint64_t upto = ln == 63 ? ~0ull : ((2ull << ln) - 1ull);   // bits 0..ln
                 for (uint32_t W = q0; W < q1; W += WAVE * UNROLL) {
+                    // entries holding the first item of each window, searched by
+                    // lanes 0..UNROLL-1 in parallel within [kb, ne)
+                    uint32_t kw = kb;
+                    if (ln < (uint32_t)UNROLL && W + ln * WAVE < q1) {
+                        const uint32_t qw = W + ln * WAVE;
+                        uint32_t lo2 = kb, hi2 = ne - 1;
+                        while (lo2 < hi2) {
+                            const uint32_t mid = (lo2 + hi2 + 1) >> 1;
+                            if (s_pref[mid] <= qw) lo2 = mid;
+                            else hi2 = mid - 1;
+                        }
+                        kw = lo2;
+                    }
                     uint32_t xs[UNROLL], ks[UNROLL];
 #pragma unroll
                     for (int j = 0; j < UNROLL; ++j) {
                         const uint32_t Wj = W + j * WAVE;
-                        const uint32_t kk = kb + 1u + ln;
+                        const uint32_t kbj = __shfl(kw, j, WAVE);
+                        const uint32_t kk = kbj + 1u + ln;
                         const uint32_t o = (kk < ne) ? s_pref[kk] - Wj : 64u;
-                        if (o < 64u) atomicOr(&s_mask[wv], 1ull << o);
-                        const uint64_t M = s_mask[wv];
-                        if (ln == 0) s_mask[wv] = 0ull;
-                        const uint32_t k = kb + (uint32_t)__popcll(M & upto);
-                        kb += (uint32_t)__popcll(M);
+                        if (o < 64u) atomicOr(&s_mask[wv][j], 1ull << o);
+                        const uint64_t M = s_mask[wv][j];
+                        if (ln == 0) s_mask[wv][j] = 0ull;
+                        const uint32_t k = kbj + (uint32_t)__popcll(M & upto);
                         const uint32_t q = Wj + ln;
                         ks[j] = k;
                         xs[j] = q < q1 ? a.col[s_base[k] + q] - wlo : 0xFFFFFFFFu;
                     }
+                    kb = __shfl(kw, UNROLL - 1, WAVE);   // searches of the next round start here
 #pragma unroll
                     for (int j = 0; j < UNROLL; ++j) {
                         const uint32_t x = xs[j];
