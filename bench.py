@@ -27,6 +27,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "Gedges/s intersected + HBM GB/s; learned/batched vs plain speedup, exact"
 
 WORKLOADS = {
     "rmat20": dict(kind="rmat", scale=20, edge_factor=16, seed=1),
@@ -36,6 +37,7 @@ WORKLOADS = {
     "er4096": dict(kind="er", n=4096, m=32768, seed=1804),
     "uniform20": dict(kind="uniform", n=1 << 20, pairs=16 << 20, seed=7),
     "rgg23": dict(kind="rgg", n=1 << 23, avg_degree=32.0, seed=5),
+    "clbatch": dict(kind="batch"),
 }
 
 
@@ -100,6 +102,54 @@ def cpu_baseline(edges, n, m):
             "sample": f"whole graph (canonicalise + CSR + count), {dt:.2f} s", "T": T}
 
 
+def batch_bench(args, tc, autotune, sel):
+    """4096 Chung-Lu graphs (gamma 2.1, draws log-uniform in [1e3, 1e6], n_g = E_g / 8):
+    one batched call (captured graph replayed) against 4096 separate calls."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    print("[bench] clbatch generating 4096 graphs", file=sys.stderr, flush=True)
+    edges, off, nv = graphgen.chung_lu_batch(4096)
+    d = torch.from_numpy(edges).to("cuda:0")
+    tuned = autotune.apply_cached(sel, "cuda:0")
+    for _ in range(max(args.warmup, 1)):
+        counts = tc.count_triangles_batch(d, off, nv, select=sel)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        counts = tc.count_triangles_batch(d, off, nv, select=sel)
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    m = tc.last_stats("cuda:0")["m"]
+    print(f"[bench] batched: {ms_batch:.2f} ms/step, union m={m}", file=sys.stderr, flush=True)
+    # the same graphs through 4096 plain calls (one warm pass, then one timed pass)
+    sep = np.zeros(nv.size, dtype=np.uint64)
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for g in range(nv.size):
+            sep[g] = tc.count_triangles(d[off[g]:off[g + 1]], int(nv[g]), select=sel)
+        torch.cuda.synchronize()
+        ms_sep = (time.perf_counter() - t1) * 1e3
+        print(f"[bench] separate pass {rep}: {ms_sep:.1f} ms", file=sys.stderr, flush=True)
+    assert np.array_equal(sep, counts), "batched and separate counts differ"
+    result = {
+        "metric": METRIC, "value": m / (ms_batch * 1e-3) / 1e9, "unit": "Gedges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batch, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "clbatch", "graphs": int(nv.size), "gamma": 2.1, "draws_loguniform": [1e3, 1e6],
+                   "raw_pairs": int(edges.shape[0]), "n": int(nv.astype(np.int64).sum()), "m": m,
+                   "triangles": int(counts.astype(np.int64).sum()), "select": args.select,
+                   "autotuned_tiles": bool(tuned)},
+        "roofline": None,
+        "batched_vs_separate": {"ms_batched": ms_batch, "ms_separate_4096_calls": ms_sep,
+                                "speedup": ms_sep / ms_batch},
+    }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,8 +172,16 @@ def main(argv=None):
     __graft_entry__._ensure_built()
     import paper_1804_06926_amd as tc
 
+    from paper_1804_06926_amd import autotune, selector
+    have_weights = selector.load_default("cuda:0")
+    if args.select == "learned" and not have_weights:
+        print("bench.py: --select learned needs trained selector weights "
+              f"({selector.DEFAULT_WEIGHTS})", file=sys.stderr)
+        return 2
     sel = {"heuristic": tc.SELECT_HEURISTIC, "learned": tc.SELECT_LEARNED, "merge": tc.FORCE_MERGE,
            "bsearch": tc.FORCE_BSEARCH, "bitmap": tc.FORCE_BITMAP}[args.select]
+    if args.workload == "clbatch":
+        return batch_bench(args, tc, autotune, sel)
     print(f"[bench] workload={args.workload} generating", file=sys.stderr, flush=True)
     edges, n, spec = make_graph(args.workload)
     d_edges = torch.from_numpy(edges).to("cuda:0")
@@ -157,7 +215,7 @@ def main(argv=None):
     isect_ms = sum(isect.values())
 
     result = {
-        "metric": "Gedges/s intersected (end to end, exact count)",
+        "metric": METRIC,
         "value": m / (ms_per_step * 1e-3) / 1e9,
         "unit": "Gedges/s",
         "n_gpus": 1,
@@ -180,6 +238,19 @@ def main(argv=None):
         "tail_elements": tail_sum,
         "effective_gbps_merge_formulation": balg / (isect_ms * 1e-3) / 1e9 if isect_ms > 0 else None,
     }
+    if have_weights and args.select == "heuristic":
+        # the learned selector against the heuristic on the same graph, counts equal
+        for _ in range(2):
+            T_l = tc.count_triangles(d_edges, n, select=tc.SELECT_LEARNED)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            T_l = tc.count_triangles(d_edges, n, select=tc.SELECT_LEARNED)
+        torch.cuda.synchronize()
+        ms_l = (time.perf_counter() - t1) * 1e3 / max(args.steps, 1)
+        assert T_l == T, (T_l, T)
+        result["learned_vs_heuristic"] = {"ms_per_step_learned": ms_l, "ms_per_step_heuristic": ms_per_step,
+                                          "speedup": ms_per_step / ms_l}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cb = cpu_baseline(edges, n, m)
