@@ -301,11 +301,20 @@ __device__ __forceinline__ uint32_t isect_edge(const IsectArgs& a, const uint32_
             }
         }
     } else if (na <= nb) {
-        for (uint32_t q = gl; q < na; q += g) {
-            const uint32_t x = A[q];
-            if (contains(B, nb, x)) {
-                ++c;
-                hit_vertex(a, x);
+        // tail elements are loaded four at a time (independent loads), then searched
+        for (uint32_t q0 = gl; q0 < na; q0 += 4u * g) {
+            uint32_t xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t q = q0 + (uint32_t)u * g;
+                xv[u] = q < na ? A[q] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (q0 + (uint32_t)u * g < na && contains(B, nb, xv[u])) {
+                    ++c;
+                    hit_vertex(a, xv[u]);
+                }
             }
         }
     } else {
@@ -323,6 +332,7 @@ __device__ __forceinline__ uint32_t isect_edge(const IsectArgs& a, const uint32_
 template <bool MERGE>
 __global__ __launch_bounds__(IS_NT) void k_isect_edges(IsectArgs a, uint64_t* partials) {
     __shared__ uint32_t sb[STAGE_MAX];
+    __shared__ uint32_t s_boff[SEG_MAX + 1];
     __shared__ Segs S;
     constexpr int KER = MERGE ? KER_MERGE : KER_BSEARCH;
     uint64_t acc = 0;
@@ -330,10 +340,26 @@ __global__ __launch_bounds__(IS_NT) void k_isect_edges(IsectArgs a, uint64_t* pa
     for (uint32_t t = a.ctrl->tile_begin[KER] + blockIdx.x; t < t_end; t += gridDim.x) {
         const uint32_t nseg = load_tile(a, t, S);
         const uint32_t v0 = S.v[0];
-        const uint32_t nb0 = a.off[v0 + 1] - a.off[v0];
-        const bool staged = nseg == 1 && nb0 <= (uint32_t)STAGE_MAX;
-        if (staged)
-            for (uint32_t j = threadIdx.x; j < nb0; j += IS_NT) sb[j] = a.col[a.off[v0] + j];
+        // stage the N+(v) lists of all the tile's vertices back to back when they fit
+        uint32_t dl = 0;
+        if (threadIdx.x < nseg) dl = a.off[S.v[threadIdx.x] + 1] - a.off[S.v[threadIdx.x]];
+        uint32_t TB;
+        const uint32_t bex = block_exclusive_scan<IS_NT>(dl, S.scratch, &TB);
+        if (threadIdx.x < nseg) s_boff[threadIdx.x] = bex;
+        if (threadIdx.x == 0) s_boff[nseg] = TB;
+        __syncthreads();
+        const bool staged = TB <= (uint32_t)STAGE_MAX;
+        if (staged) {
+            for (uint32_t j = threadIdx.x; j < TB; j += IS_NT) {
+                uint32_t lo2 = 0, hi2 = nseg - 1;   // segment holding list position j
+                while (lo2 < hi2) {
+                    const uint32_t mid = (lo2 + hi2 + 1) >> 1;
+                    if (s_boff[mid] <= j) lo2 = mid;
+                    else hi2 = mid - 1;
+                }
+                sb[j] = a.col[a.off[S.v[lo2]] + (j - s_boff[lo2])];
+            }
+        }
         __syncthreads();
         const uint32_t g = a.ctrl->group[a.vbucket[v0]];            // lanes per in-edge (power of 2)
         const uint32_t gi = threadIdx.x / g, gl = threadIdx.x % g;  // group index, lane in group
@@ -349,8 +375,8 @@ __global__ __launch_bounds__(IS_NT) void k_isect_edges(IsectArgs a, uint64_t* pa
                 const uint64_t ent = a.csc[S.e0[sg] + (q - S.pref[sg])];   // tail start | end << 32
                 const uint32_t s = (uint32_t)ent, end = (uint32_t)(ent >> 32);
                 e = s - 1u;
-                const uint32_t* B = staged ? sb : a.col + a.off[v];
-                const uint32_t nb = a.off[v + 1] - a.off[v];
+                const uint32_t* B = staged ? sb + s_boff[sg] : a.col + a.off[v];
+                const uint32_t nb = s_boff[sg + 1] - s_boff[sg];
                 c = isect_edge<MERGE>(a, a.col + s, end - s, B, nb, g, gl);
             }
             // reduce within the group of g lanes (g divides the wave)
