@@ -210,13 +210,42 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ k
     hist[(size_t)d * ntiles + blockIdx.x] = t;
 }
 
+// One block per digit d: exclusive scan, in place, of the digit's row of tile
+// counts hist[d * ntiles .. +ntiles); the row total goes to digit_tot[d].
+constexpr int RS_ROW_ITEMS = 8;
+__global__ __launch_bounds__(RS_NT) void k_radix_rowscan(uint32_t* __restrict__ hist, uint32_t ntiles,
+                                                         uint32_t* __restrict__ digit_tot) {
+    __shared__ uint32_t scratch[RS_WAVES];
+    uint32_t* row = hist + (size_t)blockIdx.x * ntiles;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < ntiles; base += RS_NT * RS_ROW_ITEMS) {
+        const uint32_t i0 = base + threadIdx.x * RS_ROW_ITEMS;
+        uint32_t v[RS_ROW_ITEMS], sum = 0;
+#pragma unroll
+        for (int k = 0; k < RS_ROW_ITEMS; ++k) {
+            v[k] = i0 + k < ntiles ? row[i0 + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t total;
+        uint32_t run = carry + block_exclusive_scan<RS_NT>(sum, scratch, &total);
+#pragma unroll
+        for (int k = 0; k < RS_ROW_ITEMS; ++k) {
+            if (i0 + k < ntiles) row[i0 + k] = run;
+            run += v[k];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
+}
+
 template <typename KeyT, bool HAS_VAL>
 __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const KeyT* __restrict__ kin,
                                                          const uint32_t* __restrict__ vin,
                                                          KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          const uint32_t* d_count, uint32_t cap, int shift,
                                                          uint32_t dmask,
-                                                         const uint32_t* __restrict__ hist_scan, uint32_t ntiles) {
+                                                         const uint32_t* __restrict__ hist_scan, uint32_t ntiles,
+                                                         const uint32_t* __restrict__ digit_tot) {
     __shared__ uint32_t wcnt[RS_WAVES][256];
     __shared__ uint32_t lstart[256];
     __shared__ uint32_t gbase[256];
@@ -259,7 +288,9 @@ __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const KeyT* __restrict_
         }
         const uint32_t excl = block_exclusive_scan<RS_NT>(run, scratch);
         lstart[d] = excl;
-        gbase[d] = hist_scan[(size_t)d * ntiles + blockIdx.x];
+        // digit base = keys with a smaller digit; plus this tile's offset in its digit row
+        const uint32_t dbase = block_exclusive_scan<RS_NT>(digit_tot[d], scratch);
+        gbase[d] = dbase + hist_scan[(size_t)d * ntiles + blockIdx.x];
     }
     __syncthreads();
 #pragma unroll
@@ -297,6 +328,7 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
     const uint32_t ntiles = (uint32_t)((cap + RS_TILE - 1) / RS_TILE);
     uint32_t* hist = (uint32_t*)temp;
     void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * ((cap + RS_TILE - 1) / RS_TILE + 1), 256);
+    uint32_t* digit_tot = (uint32_t*)scan_tmp;   // 256 digit totals
     KeyT* kin = keys;
     KeyT* kout = keys_alt;
     uint32_t* vin = vals;
@@ -307,13 +339,13 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
         const uint32_t dmask = (1u << dbits) - 1u;
         hipLaunchKernelGGL(k_radix_hist<KeyT>, dim3(ntiles), dim3(RS_NT), 0, s, kin, d_count, (uint32_t)cap, shift,
                            dmask, hist, ntiles);
-        scan_exclusive_sum_u32(hist, hist, (size_t)256 * ntiles, scan_tmp, s);
+        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(RS_NT), 0, s, hist, ntiles, digit_tot);
         if (vals) {
             hipLaunchKernelGGL((k_radix_scatter<KeyT, true>), dim3(ntiles), dim3(RS_NT), 0, s, kin, vin, kout, vout,
-                               d_count, (uint32_t)cap, shift, dmask, hist, ntiles);
+                               d_count, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot);
         } else {
             hipLaunchKernelGGL((k_radix_scatter<KeyT, false>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr, kout,
-                               nullptr, d_count, (uint32_t)cap, shift, dmask, hist, ntiles);
+                               nullptr, d_count, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot);
         }
         KeyT* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
