@@ -29,6 +29,7 @@ constexpr int BM_WORDS = 4096;            // 131072-bit window (16 KiB)
 constexpr uint32_t BM_BITS = BM_WORDS * 32u;
 constexpr int STAGE_MAX = 4096;           // N+(v) staged in LDS by merge/bsearch when it fits
 constexpr int UNROLL = 8;                 // bitmap kernel: tail loads in flight per lane
+constexpr int NV_MAX = 2048;              // bitmap kernel, per-vertex mode: N+(v) kept for t[w] gathering
 constexpr int PARTIALS_PER_KERNEL = 4096; // max blocks per intersection launch
 
 struct Segs {
@@ -99,7 +100,11 @@ __device__ __forceinline__ void block_partial(uint64_t acc, uint64_t* partials) 
 }
 
 // ------------------------------------------------------------------ LDS bitmap
+// PV: per-vertex counts requested; t[w] of the hits is gathered per tile in LDS.
+template <bool PV>
 __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* partials) {
+    __shared__ uint32_t s_nv[PV ? NV_MAX : 1];
+    __shared__ uint32_t s_wc[PV ? NV_MAX : 1];
     __shared__ uint32_t bm[BM_WORDS];
     __shared__ uint32_t s_start[CHUNK_MAX];
     __shared__ uint32_t s_pref[CHUNK_MAX + 1];
@@ -147,6 +152,12 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
             const uint32_t lo = a.col[b0], hi = a.col[b1 - 1];
             const uint32_t base = lo & ~31u;
             const uint32_t nwin = (hi - base) / BM_BITS + 1;
+            if (PV && nb <= (uint32_t)NV_MAX) {
+                for (uint32_t j = threadIdx.x; j < nb; j += IS_NT) {
+                    s_nv[j] = a.col[b0 + j];
+                    s_wc[j] = 0u;
+                }
+            }
             __syncthreads();
             for (uint32_t win = 0; win < nwin; ++win) {
                 const uint32_t wlo = base + win * BM_BITS;
@@ -212,7 +223,20 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                         if (x < BM_BITS && ((bm[x >> 5] >> (x & 31u)) & 1u)) {
                             ++acc;
                             if (need_cnt) atomicAdd(&s_cnt[ks[j]], 1u);
-                            hit_vertex(a, x + wlo);
+                            if (PV) {
+                                if (nb <= (uint32_t)NV_MAX) {   // t[w] gathered in LDS, flushed per vertex
+                                    uint32_t lo3 = 0, hi3 = nb - 1;
+                                    const uint32_t w = x + wlo;
+                                    while (lo3 < hi3) {
+                                        const uint32_t mid = (lo3 + hi3) >> 1;
+                                        if (s_nv[mid] < w) lo3 = mid + 1;
+                                        else hi3 = mid;
+                                    }
+                                    atomicAdd(&s_wc[lo3], 1u);
+                                } else {
+                                    hit_vertex(a, x + wlo);
+                                }
+                            }
                         }
                     }
                 }
@@ -222,6 +246,10 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                     if (x < BM_BITS) bm[x >> 5] = 0u;
                 }
                 __syncthreads();
+            }
+            if (PV && nb <= (uint32_t)NV_MAX) {
+                for (uint32_t j = threadIdx.x; j < nb; j += IS_NT)
+                    if (s_wc[j]) atomicAdd((unsigned long long*)&a.per_vertex[s_nv[j]], (unsigned long long)s_wc[j]);
             }
             if (need_cnt) {
                 uint32_t seg_hits = 0;
@@ -425,7 +453,10 @@ void launch_isect(int ker, const IsectArgs& a, int grid, uint64_t* partials, hip
     switch (ker) {
         case KER_MERGE: hipLaunchKernelGGL(k_isect_edges<true>, dim3(grid), dim3(IS_NT), 0, s, a, p); break;
         case KER_BSEARCH: hipLaunchKernelGGL(k_isect_edges<false>, dim3(grid), dim3(IS_NT), 0, s, a, p); break;
-        default: hipLaunchKernelGGL(k_isect_bitmap, dim3(grid), dim3(IS_NT), 0, s, a, p); break;
+        default:
+            if (a.per_vertex) hipLaunchKernelGGL(k_isect_bitmap<true>, dim3(grid), dim3(IS_NT), 0, s, a, p);
+            else hipLaunchKernelGGL(k_isect_bitmap<false>, dim3(grid), dim3(IS_NT), 0, s, a, p);
+            break;
     }
 }
 
