@@ -76,3 +76,53 @@ def apply_cached(select: int = _lib.SELECT_HEURISTIC, device: str = "cuda:0", pa
         return False
     _lib.set_tile_shapes(chunk=shapes, device=device)
     return True
+
+
+def main(argv=None):
+    """Tune on the disjoint union of the 4096-graph Chung-Lu batch (or an R-MAT graph)."""
+    import argparse
+    import sys
+    import time
+
+    import torch
+
+    root = os.path.dirname(HERE)
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import graphgen
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="clbatch", choices=["clbatch", "rmat20"])
+    ap.add_argument("--select", type=int, default=_lib.SELECT_HEURISTIC)
+    ap.add_argument("--out", default=DEFAULT_CACHE)
+    ap.add_argument("--repeats", type=int, default=3)
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    t0 = time.time()
+    if args.workload == "clbatch":
+        e, off, nv = graphgen.chung_lu_batch(4096)
+        base = np.zeros(nv.size, dtype=np.int64)
+        np.cumsum(nv[:-1].astype(np.int64), out=base[1:])
+        e = e + np.repeat(base, np.diff(off)).astype(np.int32)[:, None]
+        n = int(nv.astype(np.int64).sum())
+    else:
+        e, n = graphgen.rmat(20, 16, seed=1), 1 << 20
+    d = torch.from_numpy(np.ascontiguousarray(e, dtype=np.int32)).cuda()
+    log(f"[autotune] {args.workload}: E={e.shape[0]} n={n}")
+    if args.select == _lib.SELECT_LEARNED:
+        from . import selector
+        selector.load_default()
+    best, table = tune(d, n, select=args.select, repeats=args.repeats, log=log)
+    key = device_key(args.select)
+    save(best, key, args.out)
+    tot = {K: float(np.sum(table[i][table[i] > 0])) for i, K in enumerate(CANDIDATES)}
+    picked = float(sum(table[CANDIDATES.index(int(best[b])), b] for b in range(256) if best[b]))
+    log(f"[autotune] per-size totals (ms) {tot}; per-bucket best total {picked:.3f} ms; "
+        f"saved under {key} in {args.out} ({time.time() - t0:.0f} s)")
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
