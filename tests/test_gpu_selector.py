@@ -58,8 +58,9 @@ def test_forward_matches_oracle_within_error_bound(tc, B):
 def test_gradient_matches_oracle(tc, B, weighted):
     """Tolerance: each gradient entry is a sum of B products formed from float32
     activations; float32 rounding of the layer outputs and of the sum bounds the
-    relative error by about (B + 70) * 2^-24 of the sum of absolute terms, far
-    below the 1e-4 relative slack used here (plus 1e-7 absolute)."""
+    error by about (B + 70) * 2^-24 times the sum of absolute terms. That sum is
+    at most B * max|term| <= B times the largest gradient entry here, so the
+    slack 1e-4 * (|g| + max|g|) + 1e-7 covers B up to about 4096 with margin."""
     import torch
     theta = _params(7 + B)
     X, y, w = _batch(B, 11 + B)
@@ -69,9 +70,7 @@ def test_gradient_matches_oracle(tc, B, weighted):
     g = g.cpu().numpy().astype(np.float64)
     loss64, g64 = mlp.loss_and_grad(theta, X, y, w if weighted else None)
     assert abs(loss - loss64) <= 1e-5 * max(1.0, abs(loss64))
-    # scale of each entry: the same gradient computed with absolute values
-    _, gabs = mlp.loss_and_grad(theta, X, y, w if weighted else None)
-    tol = 1e-4 * np.abs(gabs) + 1e-4 * np.max(np.abs(g64)) + 1e-7
+    tol = 1e-4 * np.abs(g64) + 1e-4 * np.max(np.abs(g64)) + 1e-7
     assert np.all(np.abs(g - g64) <= tol), np.max(np.abs(g - g64) - tol)
 
 
@@ -127,3 +126,14 @@ def test_profile_buckets_shapes(tc):
     for b in busy:
         assert np.all(ms[:, b] > 0), b
     assert np.all(ms[:, 255] < 0)
+
+
+def test_device_heuristic_matches_host_rule(tc):
+    import torch
+    from paper_1804_06926_amd import selector
+    n = 1 << 16
+    e = graphgen.rmat(16, 16, seed=4)
+    tc.count_triangles(torch.from_numpy(e).cuda(), n, select=tc.SELECT_HEURISTIC)
+    st = tc.last_stats()
+    for b in range(255):
+        assert st["bucket_kernel"][b] == selector.heuristic_choice(b), b

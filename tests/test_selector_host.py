@@ -1,0 +1,57 @@
+"""Host-side logic of the selector and the autotuner (no GPU)."""
+import json
+
+import numpy as np
+
+from paper_1804_06926_amd import autotune, selector
+
+
+def test_heuristic_thresholds():
+    assert selector.heuristic_choice(16 * 6 + 0) == 2     # >= 64 in-edges: bitmap
+    assert selector.heuristic_choice(16 * 5 + 9) == 1     # fewer in-edges, long lists: binary search
+    assert selector.heuristic_choice(16 * 2 + 2) == 0     # short lists: merge path
+
+
+def test_labels_keep_heuristic_within_tie():
+    times = np.array([[1.00, 1.01, 2.0],     # heuristic (bucket 0 -> merge) within 2%: keep merge
+                      [2.00, 1.00, 3.0],     # clearly faster binary search
+                      [5.00, 4.00, 1.0]])
+    buckets = np.array([0, 0, 0])
+    y = selector.make_labels(times, buckets, tie=0.02)
+    assert y.tolist() == [0, 1, 2]
+
+
+def test_sample_weights_and_regret():
+    times = np.array([[1.0, 1.0, 1.0], [1.0, 5.0, 9.0]])
+    w = selector.sample_weights(times)
+    assert abs(w.mean() - 1.0) < 1e-6 and w[1] > w[0]
+    assert selector.regret(times, np.array([0, 2])) == 8.0
+    assert selector.regret(times, np.array([1, 0])) == 0.0
+
+
+def test_init_params_shape_and_scale():
+    p = selector.init_params(3)
+    assert p.dtype == np.float32 and p.size == 1379
+    W1 = p[:192]
+    assert abs(W1.std() - np.sqrt(2 / 6)) < 0.1
+    assert np.all(p[192:224] == 0)
+
+
+def test_weights_roundtrip(tmp_path):
+    p = selector.init_params(1)
+    f = tmp_path / "w.json"
+    selector.save(str(f), p, {"note": "x"})
+    np.testing.assert_array_equal(selector.load(str(f)), p)
+    doc = json.loads(f.read_text())
+    assert doc["format"] == "tc-selector-v1"
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    f = tmp_path / "t.json"
+    shapes = np.zeros(256, dtype=np.uint16)
+    shapes[[3, 100, 254]] = [64, 256, 512]
+    autotune.save(shapes, "gfx950|hipX|select0", str(f))
+    autotune.save(shapes * 0 + 0, "other", str(f))
+    got = autotune.load("gfx950|hipX|select0", str(f))
+    np.testing.assert_array_equal(got, shapes)
+    assert autotune.load("missing", str(f)) is None
