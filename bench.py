@@ -159,6 +159,8 @@ def main(argv=None):
     ap.add_argument("--select", default="heuristic", choices=["heuristic", "learned", "merge", "bsearch", "bitmap"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle equality check")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also run one device-to-device copy of MIB MiB (calibrates counter-based traffic)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -180,6 +182,12 @@ def main(argv=None):
         return 2
     sel = {"heuristic": tc.SELECT_HEURISTIC, "learned": tc.SELECT_LEARNED, "merge": tc.FORCE_MERGE,
            "bsearch": tc.FORCE_BSEARCH, "bitmap": tc.FORCE_BITMAP}[args.select]
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.int32, device="cuda:0")   # MiB of int32
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "clbatch":
         return batch_bench(args, tc, autotune, sel)
     print(f"[bench] workload={args.workload} generating", file=sys.stderr, flush=True)
