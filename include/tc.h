@@ -94,6 +94,21 @@ tc_status tc_count_triangles(tc_ctx* ctx, const int32_t* d_edges, int64_t num_ed
                              uint64_t* h_count, uint64_t* d_per_vertex);
 
 /*
+ * tc_count_triangles without any host synchronisation: the work is queued on
+ * the context's stream and the call returns. On completion
+ *   d_result[0] = T, d_result[1] = 0, or TC_ERR_VERTEX_RANGE when an id lies
+ *   outside [0, num_vertices) (then d_result[0] and d_per_vertex are
+ *   meaningless).
+ * d_result: uint64[2], device memory, 8-byte aligned. Host-detectable errors
+ * return before anything is queued. The workspace and outputs must stay
+ * untouched until the stream reaches the end of the call; calls queued on one
+ * stream may share a workspace. TC_F_STAGE_TIMING is rejected here.
+ */
+tc_status tc_count_triangles_async(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                                   void* d_workspace, size_t workspace_bytes, const tc_options* opts,
+                                   uint64_t* d_result, uint64_t* d_per_vertex);
+
+/*
  * Per-edge intersection sizes (the IntersectList of Algorithm 2). For each
  * kept edge (u -> v), u before v in (degree, id) order, writes
  *   d_out_edges[i] = {u, v} (original ids) and

@@ -19,6 +19,7 @@ from ._lib import (  # noqa: F401
     bucket_features,
     build_csr,
     count_triangles,
+    count_triangles_async,
     count_triangles_batch,
     edge_counts,
     last_stats,

@@ -49,6 +49,7 @@ def _load():
     lib.tc_workspace_size.argtypes = [i64, i32, ctypes.POINTER(Options), ctypes.POINTER(sz)]
     lib.tc_count_triangles.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options),
                                        ctypes.POINTER(ctypes.c_uint64), vp]
+    lib.tc_count_triangles_async.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp]
     lib.tc_edge_counts.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp,
                                    ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_uint64)]
     lib.tc_build_csr.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp, vp,
@@ -62,7 +63,8 @@ def _load():
     lib.tc_stage_name.restype = ctypes.c_char_p
     lib.tc_last_error.argtypes = [vp]
     lib.tc_last_error.restype = ctypes.c_char_p
-    for f in ("tc_create", "tc_destroy", "tc_workspace_size", "tc_count_triangles", "tc_edge_counts",
+    for f in ("tc_create", "tc_destroy", "tc_workspace_size", "tc_count_triangles", "tc_count_triangles_async",
+              "tc_edge_counts",
               "tc_build_csr", "tc_radix_sort_u64"):
         getattr(lib, f).restype = ctypes.c_int
     _ = u32
@@ -183,6 +185,34 @@ def count_triangles(edges, num_vertices: int, per_vertex: bool = False, select: 
     if timing:
         res.append(_timings(ctx))
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def count_triangles_async(edges, num_vertices: int, result=None, per_vertex=None, select: int = SELECT_HEURISTIC,
+                          workspace=None):
+    """Queue a count on torch's current stream without waiting for it.
+
+    Returns ``result``, an int64 tensor [2] on the device (allocated when not
+    given): after the stream reaches the call, result[0] = T and result[1] = 0,
+    or the status code of an out-of-range vertex id. ``per_vertex`` (optional,
+    int64 [num_vertices] on the device) receives t[v]. The workspace must not
+    be reused by other streams until the call has finished.
+    """
+    torch = _torch()
+    e = _edges_arg(edges)
+    ctx, idx = _ctx(e.device)
+    E = e.shape[0]
+    o = _options(select, False)
+    ws = _workspace(idx, workspace_size(E, num_vertices, select), workspace)
+    if result is None:
+        result = torch.empty(2, dtype=torch.int64, device=e.device)
+    if per_vertex is not None and (per_vertex.dtype != torch.int64 or per_vertex.numel() < num_vertices):
+        raise TypeError("per_vertex must be an int64 tensor with num_vertices entries")
+    st = _load().tc_count_triangles_async(ctx, e.data_ptr() if E else None, E, num_vertices, ws.data_ptr(),
+                                          ws.numel(), ctypes.byref(o), result.data_ptr(),
+                                          per_vertex.data_ptr() if per_vertex is not None and num_vertices
+                                          else None)
+    _check(st, ctx)
+    return result
 
 
 def edge_counts(edges, num_vertices: int, select: int = SELECT_HEURISTIC, workspace=None):

@@ -90,8 +90,10 @@ constexpr int64_t kMaxEdges = ((int64_t)1 << 31) - ((int64_t)1 << 20);
 
 // Common checks and the run of the pipeline; returns with the control block
 // copied to ctx->h_ctrl on success.
+// With d_result set, nothing waits for the device: T and the range status go
+// to d_result[0..1] on the stream.
 tc_status run(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* ws, size_t ws_bytes,
-              const tc_options* opts, tcx::RunArgs& ra) {
+              const tc_options* opts, tcx::RunArgs& ra, uint64_t* d_result = nullptr) {
     if (!ctx) return TC_ERR_INVALID_ARG;
     ctx->last_error.clear();
     if (E < 0 || n < 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "negative size");
@@ -110,6 +112,7 @@ tc_status run(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* w
     if (sel == TC_SELECT_LEARNED && !ctx->learned_ready)
         return arg_fail(ctx, TC_ERR_INVALID_ARG, "no selector network loaded or trained");
     const bool timing = opts && (opts->flags & TC_F_STAGE_TIMING);
+    if (d_result && timing) return arg_fail(ctx, TC_ERR_INVALID_ARG, "stage timing needs a synchronising call");
     ra.stream = ctx->stream;
     ra.ws = ws;
     ra.edges = d_edges;
@@ -122,6 +125,13 @@ tc_status run(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* w
     ra.group_override = ctx->d_group;
     ra.grid_override = ctx->grid_override;
     ra.events = timing ? ctx->events : nullptr;
+    if (E == 0 && d_result) {
+        tcx::fill_u64(d_result, 0ull, 2, ctx->stream);
+        if (ra.per_vertex && n > 0) tcx::fill_u64(ra.per_vertex, 0ull, (size_t)n, ctx->stream);
+        ctx->have_times = 0;
+        const hipError_t e = hipGetLastError();
+        return e == hipSuccess ? TC_OK : hip_fail(ctx, e, "queue zero result");
+    }
     if (E == 0) {
         memset(ctx->h_ctrl, 0, sizeof(tcx::Ctrl));
         if (ra.per_vertex && n > 0) {
@@ -135,6 +145,12 @@ tc_status run(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* w
     tcx::RunResult rr;
     hipError_t e = tcx::run_pipeline(ra, &rr);
     if (e != hipSuccess) return hip_fail(ctx, e, "launch");
+    if (d_result) {
+        tcx::publish_result(rr.ctrl_dev, d_result, (uint64_t)TC_ERR_VERTEX_RANGE, ctx->stream);
+        ctx->have_times = 0;
+        e = hipGetLastError();
+        return e == hipSuccess ? TC_OK : hip_fail(ctx, e, "queue result");
+    }
     e = hipMemcpyAsync(ctx->h_ctrl, rr.ctrl_dev, sizeof(tcx::Ctrl), hipMemcpyDeviceToHost, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "read control block");
     e = hipStreamSynchronize(ctx->stream);
@@ -226,6 +242,16 @@ tc_status tc_count_triangles(tc_ctx* ctx, const int32_t* d_edges, int64_t num_ed
     tc_status st = run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, opts, ra);
     if (st == TC_OK) *h_count = ctx->h_ctrl->total;
     return st;
+}
+
+tc_status tc_count_triangles_async(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                                   void* d_workspace, size_t workspace_bytes, const tc_options* opts,
+                                   uint64_t* d_result, uint64_t* d_per_vertex) {
+    if (!d_result) return arg_fail(ctx, TC_ERR_INVALID_ARG, "null result output");
+    if (((uintptr_t)d_result & 7u) != 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "result must be 8-byte aligned");
+    tcx::RunArgs ra = {};
+    ra.per_vertex = d_per_vertex;
+    return run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, opts, ra, d_result);
 }
 
 tc_status tc_edge_counts(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,

@@ -51,6 +51,8 @@ struct RunResult {
 };
 
 hipError_t run_pipeline(const RunArgs& r, RunResult* out);
+// Copies T and the range flag of a finished run to result[0..1] (device).
+void publish_result(const Ctrl* ctrl, uint64_t* result, uint64_t range_status, hipStream_t s);
 
 // ---- batched counting (batch.hip)
 struct BatchLayout {

@@ -413,6 +413,18 @@ __global__ void k_set_tile_range(Ctrl* ctrl, int ker, uint32_t t0, uint32_t t1) 
     }
 }
 
+// result[0] = T, result[1] = range_status when an id was out of range, else 0.
+__global__ void k_publish(const Ctrl* ctrl, uint64_t* result, uint64_t range_status) {
+    if (threadIdx.x == 0) {
+        result[0] = ctrl->total;
+        result[1] = (ctrl->err & 1u) ? range_status : 0ull;
+    }
+}
+
+void publish_result(const Ctrl* ctrl, uint64_t* result, uint64_t range_status, hipStream_t s) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, ctrl, result, range_status);
+}
+
 // ------------------------------------------------------------------ workspace layout
 Layout make_layout(int64_t E, int32_t n) {
     Layout L;

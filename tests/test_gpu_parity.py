@@ -108,6 +108,33 @@ def test_vertex_range_error(tc):
     assert tc.count_triangles(dev([[0, 1], [1, 2], [2, 0]]), 3) == 1
 
 
+def test_async_calls_queue_without_waiting(tc):
+    """Several asynchronous calls queued back to back on one stream and one
+    workspace, each with its own result slot, then one synchronisation: every
+    slot holds the oracle's T, the range status is reported on the device, and
+    an empty input gives zeros."""
+    import torch
+    cases = [(graphgen.rmat(s, 16, seed=40 + s), 1 << s) for s in (10, 13, 15)]
+    cases.append((graphgen.erdos_renyi(4096, 32768, seed=1804), 4096))
+    ws = torch.empty(max(tc.workspace_size(e.shape[0], n) for e, n in cases), dtype=torch.uint8, device="cuda:0")
+    res = torch.full((len(cases) + 2, 2), -1, dtype=torch.int64, device="cuda:0")
+    pv = torch.full((1 << 15,), -1, dtype=torch.int64, device="cuda:0")
+    dev_cases = [(dev(e), n) for e, n in cases]
+    for k, (d, n) in enumerate(dev_cases):
+        tc.count_triangles_async(d, n, result=res[k], per_vertex=pv if n == 1 << 15 else None, workspace=ws)
+    tc.count_triangles_async(dev([[0, 1], [1, 9]]), 5, result=res[len(cases)], workspace=ws)
+    tc.count_triangles_async(torch.zeros((0, 2), dtype=torch.int32, device="cuda:0"), 3, result=res[-1],
+                             workspace=ws)
+    torch.cuda.synchronize()
+    got = res.cpu().numpy()
+    for k, (e, n) in enumerate(cases):
+        assert got[k].tolist() == [oracle.count_triangles(e, n), 0], k
+    assert got[len(cases)][1] == 2
+    assert got[-1].tolist() == [0, 0]
+    _, ref_t = oracle.count_triangles(cases[2][0], cases[2][1], per_vertex=True)
+    np.testing.assert_array_equal(pv.cpu().numpy().astype(np.uint64), ref_t)
+
+
 def _canon_keys(pairs):
     a = pairs[:, 0].astype(np.int64)
     b = pairs[:, 1].astype(np.int64)
