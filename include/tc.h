@@ -109,6 +109,24 @@ tc_status tc_count_triangles_async(tc_ctx* ctx, const int32_t* d_edges, int64_t 
                                    uint64_t* d_result, uint64_t* d_per_vertex);
 
 /*
+ * Triangle-based graph measures named in Section 1 and, as a small extension
+ * of the method, at the end of Section 5: the local clustering coefficient
+ * (Watts and Strogatz) and the transitivity ratio.
+ *   d_coeff         out: double[num_vertices] (original ids),
+ *                   C(v) = t[v] / C(d(v), 2), with d(v) the degree in the
+ *                   simple graph; 0 when d(v) < 2.
+ *   d_per_vertex    out, optional (NULL): uint64 t[v] as in tc_count_triangles.
+ *   h_count         out: T.
+ *   h_wedges        out: number of wedges (paths of two edges), sum of C(d(v), 2).
+ *   h_transitivity  out: 3 T / wedges (0 without wedges).
+ * Both ratios are one correctly rounded double division of exact integers
+ * (the integers converted to double first).
+ */
+tc_status tc_clustering(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                        void* d_workspace, size_t workspace_bytes, const tc_options* opts, double* d_coeff,
+                        uint64_t* d_per_vertex, uint64_t* h_count, uint64_t* h_wedges, double* h_transitivity);
+
+/*
  * Per-edge intersection sizes (the IntersectList of Algorithm 2). For each
  * kept edge (u -> v), u before v in (degree, id) order, writes
  *   d_out_edges[i] = {u, v} (original ids) and

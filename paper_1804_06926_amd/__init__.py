@@ -18,6 +18,7 @@ from ._lib import (  # noqa: F401
     TCError,
     bucket_features,
     build_csr,
+    clustering,
     count_triangles,
     count_triangles_async,
     count_triangles_batch,

@@ -50,6 +50,9 @@ def _load():
     lib.tc_count_triangles.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options),
                                        ctypes.POINTER(ctypes.c_uint64), vp]
     lib.tc_count_triangles_async.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp]
+    lib.tc_clustering.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp,
+                                  ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                  ctypes.POINTER(ctypes.c_double)]
     lib.tc_edge_counts.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp,
                                    ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_uint64)]
     lib.tc_build_csr.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp, vp,
@@ -64,6 +67,7 @@ def _load():
     lib.tc_last_error.argtypes = [vp]
     lib.tc_last_error.restype = ctypes.c_char_p
     for f in ("tc_create", "tc_destroy", "tc_workspace_size", "tc_count_triangles", "tc_count_triangles_async",
+              "tc_clustering",
               "tc_edge_counts",
               "tc_build_csr", "tc_radix_sort_u64"):
         getattr(lib, f).restype = ctypes.c_int
@@ -213,6 +217,31 @@ def count_triangles_async(edges, num_vertices: int, result=None, per_vertex=None
                                           else None)
     _check(st, ctx)
     return result
+
+
+def clustering(edges, num_vertices: int, per_vertex: bool = False, select: int = SELECT_HEURISTIC, workspace=None):
+    """Local clustering coefficients and transitivity.
+
+    Returns (coeff float64 [num_vertices] on the device, T, wedges, transitivity),
+    with t (int64 [num_vertices], the uint64 per-vertex counts) appended when
+    per_vertex is set.
+    """
+    torch = _torch()
+    e = _edges_arg(edges)
+    ctx, idx = _ctx(e.device)
+    E = e.shape[0]
+    o = _options(select, False)
+    ws = _workspace(idx, workspace_size(E, num_vertices, select), workspace)
+    coeff = torch.empty(max(num_vertices, 1), dtype=torch.float64, device=e.device)[:num_vertices]
+    pv = torch.empty(num_vertices, dtype=torch.int64, device=e.device) if per_vertex else None
+    T, W, tr = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_double()
+    st = _load().tc_clustering(ctx, e.data_ptr() if E else None, E, num_vertices, ws.data_ptr(), ws.numel(),
+                               ctypes.byref(o), coeff.data_ptr() if num_vertices else None,
+                               pv.data_ptr() if pv is not None and num_vertices else None, ctypes.byref(T),
+                               ctypes.byref(W), ctypes.byref(tr))
+    _check(st, ctx)
+    res = (coeff, int(T.value), int(W.value), float(tr.value))
+    return res + (pv,) if per_vertex else res
 
 
 def edge_counts(edges, num_vertices: int, select: int = SELECT_HEURISTIC, workspace=None):

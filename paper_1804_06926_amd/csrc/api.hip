@@ -254,6 +254,29 @@ tc_status tc_count_triangles_async(tc_ctx* ctx, const int32_t* d_edges, int64_t 
     return run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, opts, ra, d_result);
 }
 
+tc_status tc_clustering(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                        void* d_workspace, size_t workspace_bytes, const tc_options* opts, double* d_coeff,
+                        uint64_t* d_per_vertex, uint64_t* h_count, uint64_t* h_wedges, double* h_transitivity) {
+    if (!h_count || !h_wedges || !h_transitivity || (num_vertices > 0 && !d_coeff))
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "null output");
+    tcx::RunArgs ra = {};
+    ra.clustering = d_coeff;
+    ra.per_vertex = d_per_vertex;
+    tc_status st = run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, opts, ra);
+    if (st != TC_OK) return st;
+    if (num_edges == 0 && num_vertices > 0) {   // no edges: every degree is zero
+        DeviceGuard guard(ctx->device);
+        hipError_t e = hipMemsetAsync(d_coeff, 0, sizeof(double) * (size_t)num_vertices, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "zero coefficients");
+    }
+    const uint64_t T = ctx->h_ctrl->total, W = ctx->h_ctrl->wedges;
+    *h_count = T;
+    *h_wedges = W;
+    *h_transitivity = W ? 3.0 * (double)T / (double)W : 0.0;
+    return TC_OK;
+}
+
 tc_status tc_edge_counts(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
                          void* d_workspace, size_t workspace_bytes, const tc_options* opts, int32_t* d_out_edges,
                          uint32_t* d_out_counts, int64_t* h_num_out, uint64_t* h_count) {

@@ -38,6 +38,7 @@ struct RunArgs {
     uint64_t* per_vertex;            // device [n] or null (original ids)
     uint64_t* per_middle;            // device [n] or null (original ids): triangles with v in the middle
                                      // (exclusive with per_vertex: both use the same scratch)
+    double* clustering;              // device [n] or null (original ids): t[v] / C(d(v), 2); sets ctrl->wedges
     uint32_t* per_edge_counts;       // device [E] or null (CSR order)
     int32_t* per_edge_pairs;         // device [E][2] or null
     int32_t* csr_rank;               // device [n] or null (CSR export)

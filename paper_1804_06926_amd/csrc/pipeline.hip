@@ -385,6 +385,56 @@ __global__ __launch_bounds__(NT) void k_map_pv(const uint64_t* __restrict__ pv, 
     for (int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x; r < n; r += (int64_t)gridDim.x * NT) out[inv[r]] = pv[r];
 }
 
+// ------------------------------------------------------------------ clustering epilogue
+// Local clustering coefficient C(v) = t[v] / C(d(v), 2) (zero when d(v) < 2)
+// and the number of wedges (paths of length two) sum_v C(d(v), 2), which with
+// T gives the transitivity 3T / wedges. d(v) is the simple-graph degree: the
+// out-degree of v's CSR row plus its in-degree over the kept edges.
+constexpr unsigned CL_MAX_BLOCKS = 4096;   // block partials live in the intersection partials
+
+__global__ __launch_bounds__(NT) void k_indeg(const uint32_t* __restrict__ col, const Ctrl* ctrl,
+                                              uint32_t* __restrict__ indeg) {
+    const uint32_t m = ctrl->m;
+    for (uint64_t e = (uint64_t)blockIdx.x * NT + threadIdx.x; e < m; e += (uint64_t)gridDim.x * NT)
+        atomicAdd(&indeg[col[e]], 1u);
+}
+
+__global__ __launch_bounds__(NT) void k_clustering(const uint64_t* __restrict__ t, const uint32_t* __restrict__ inv,
+                                                   const uint32_t* __restrict__ off,
+                                                   const uint32_t* __restrict__ indeg, int32_t n,
+                                                   double* __restrict__ coeff, uint64_t* __restrict__ partials) {
+    __shared__ uint64_t red[NT / WAVE];
+    uint64_t acc = 0;
+    for (int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x; r < n; r += (int64_t)gridDim.x * NT) {
+        const uint64_t d = (uint64_t)(off[r + 1] - off[r]) + indeg[r];
+        const uint64_t w = d < 2 ? 0ull : d * (d - 1) / 2;
+        acc += w;
+        coeff[inv[r]] = w ? (double)t[r] / (double)w : 0.0;
+    }
+    acc = wave_sum_u64(acc);
+    if (lane_id() == 0) red[wave_id()] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t s = 0;
+        for (int i = 0; i < NT / WAVE; ++i) s += red[i];
+        partials[blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_sum_wedges(const uint64_t* __restrict__ partials, unsigned count, Ctrl* ctrl) {
+    __shared__ uint64_t red[NT / WAVE];
+    uint64_t acc = 0;
+    for (unsigned i = threadIdx.x; i < count; i += NT) acc += partials[i];
+    acc = wave_sum_u64(acc);
+    if (lane_id() == 0) red[wave_id()] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t s = 0;
+        for (int i = 0; i < NT / WAVE; ++i) s += red[i];
+        ctrl->wedges = s;
+    }
+}
+
 __global__ __launch_bounds__(NT) void k_map_edges(const uint32_t* __restrict__ col, const uint32_t* __restrict__ src,
                                                   const uint32_t* __restrict__ inv, const Ctrl* ctrl,
                                                   int2* __restrict__ out) {
@@ -481,7 +531,7 @@ static IsectArgs isect_args(const RunArgs& r, const Layout& L, uint64_t* csc) {
     ia.vbucket = (const uint8_t*)(ws + L.vbucket);
     ia.tiles = (const uint64_t*)(ws + L.tiles);
     ia.per_edge = r.per_edge_counts;
-    ia.per_vertex = r.per_vertex ? (uint64_t*)(ws + L.pv) : nullptr;
+    ia.per_vertex = (r.per_vertex || r.clustering) ? (uint64_t*)(ws + L.pv) : nullptr;
     ia.per_middle = r.per_middle ? (uint64_t*)(ws + L.pv) : nullptr;
     return ia;
 }
@@ -625,7 +675,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     hipLaunchKernelGGL(k_emit_tiles, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vlist, vbucket, tstart, n, ctrl,
                        tiles, (uint64_t)L.tile_cap);
     if (r.per_edge_counts) fill_u32(r.per_edge_counts, 0u, (size_t)E, s);
-    if (r.per_vertex || r.per_middle) fill_u64(pv, 0ull, (size_t)n, s);
+    if (r.per_vertex || r.per_middle || r.clustering) fill_u64(pv, 0ull, (size_t)n, s);
     mark(8);
     if (r.stop_before_isect) {
         out->ctrl_dev = ctrl;
@@ -646,6 +696,13 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         hipLaunchKernelGGL(k_map_pv, dim3(grid_for((size_t)n)), dim3(NT), 0, s, pv, inv, n, r.per_vertex);
     else if (r.per_middle)
         hipLaunchKernelGGL(k_map_pv, dim3(grid_for((size_t)n)), dim3(NT), 0, s, pv, inv, n, r.per_middle);
+    if (r.clustering) {   // the degree offsets are dead by now: reuse them for the simple in-degree
+        fill_u32(deg, 0u, (size_t)n, s);
+        hipLaunchKernelGGL(k_indeg, dim3(grid_for((size_t)E)), dim3(NT), 0, s, col, ctrl, deg);
+        const unsigned g = grid_for((size_t)n, CL_MAX_BLOCKS);
+        hipLaunchKernelGGL(k_clustering, dim3(g), dim3(NT), 0, s, pv, inv, off, deg, n, r.clustering, partials);
+        hipLaunchKernelGGL(k_sum_wedges, dim3(1), dim3(NT), 0, s, partials, g, ctrl);
+    }
     if (r.per_edge_pairs)
         hipLaunchKernelGGL(k_map_edges, dim3(grid_for((size_t)E)), dim3(NT), 0, s, col, src, inv, ctrl,
                            (int2*)r.per_edge_pairs);

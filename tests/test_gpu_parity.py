@@ -135,6 +135,31 @@ def test_async_calls_queue_without_waiting(tc):
     np.testing.assert_array_equal(pv.cpu().numpy().astype(np.uint64), ref_t)
 
 
+@pytest.mark.parametrize("case", ["fig4", "k40", "wheel6", "friendship", "star", "rmat12_dirty", "chung_lu",
+                                  "rgg_16k", "isolated_tail"])
+def test_clustering_matches_oracle(tc, case):
+    """Each coefficient and the transitivity are one correctly rounded float64
+    division of the same exact integers on both sides, so they agree exactly."""
+    from oracle.measures import clustering
+    e, n = CASES[case]()
+    print(f"case={case} E={e.shape[0]} n={n}", flush=True)
+    r_coeff, r_T, r_W, r_tr, r_t = clustering(e, n)
+    coeff, T, W, tr, t = tc.clustering(dev(e), n, per_vertex=True)
+    assert (T, W, tr) == (r_T, r_W, r_tr)
+    np.testing.assert_array_equal(coeff.cpu().numpy(), r_coeff)
+    np.testing.assert_array_equal(t.cpu().numpy().astype(np.uint64), r_t)
+    # without the per-vertex output requested
+    coeff2, T2, W2, tr2 = tc.clustering(dev(e), n, select=tc.FORCE_BITMAP)
+    assert (T2, W2, tr2) == (r_T, r_W, r_tr)
+    np.testing.assert_array_equal(coeff2.cpu().numpy(), r_coeff)
+
+
+def test_clustering_empty(tc):
+    import torch
+    coeff, T, W, tr = tc.clustering(torch.zeros((0, 2), dtype=torch.int32, device="cuda:0"), 5)
+    assert (T, W, tr) == (0, 0, 0.0) and coeff.cpu().numpy().tolist() == [0.0] * 5
+
+
 def _canon_keys(pairs):
     a = pairs[:, 0].astype(np.int64)
     b = pairs[:, 1].astype(np.int64)
