@@ -141,6 +141,18 @@ tc_status tc_edge_counts(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges,
                          int32_t* d_out_edges, uint32_t* d_out_counts, int64_t* h_num_out, uint64_t* h_count);
 
 /*
+ * Edge support: for each kept edge, the number of triangles that contain it
+ * (Section 1: the triangles the counting algorithms enumerate are the input
+ * of k-truss decomposition). Same output layout as tc_edge_counts:
+ * d_out_edges[i] = {u, v} (original ids, u before v in (degree, id) order) and
+ * d_out_support[i] (uint32), CSR order, capacity num_edges entries each;
+ * h_num_out = m, h_count = T (the supports sum to 3T).
+ */
+tc_status tc_edge_support(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                          void* d_workspace, size_t workspace_bytes, const tc_options* opts,
+                          int32_t* d_out_edges, uint32_t* d_out_support, int64_t* h_num_out, uint64_t* h_count);
+
+/*
  * Batched counting of many graphs in one pass (not in the paper; its small-
  * graph overhead remark in Section 5 motivates it). Graph g's pairs are
  * d_edges[h_edge_offsets[g] .. h_edge_offsets[g+1]) with graph-local ids in

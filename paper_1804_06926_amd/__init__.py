@@ -23,6 +23,7 @@ from ._lib import (  # noqa: F401
     count_triangles_async,
     count_triangles_batch,
     edge_counts,
+    edge_support,
     last_stats,
     library_path,
     profile_buckets,

@@ -50,6 +50,8 @@ def _load():
     lib.tc_count_triangles.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options),
                                        ctypes.POINTER(ctypes.c_uint64), vp]
     lib.tc_count_triangles_async.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp]
+    lib.tc_edge_support.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp,
+                                    ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_uint64)]
     lib.tc_clustering.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp,
                                   ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                                   ctypes.POINTER(ctypes.c_double)]
@@ -67,7 +69,7 @@ def _load():
     lib.tc_last_error.argtypes = [vp]
     lib.tc_last_error.restype = ctypes.c_char_p
     for f in ("tc_create", "tc_destroy", "tc_workspace_size", "tc_count_triangles", "tc_count_triangles_async",
-              "tc_clustering",
+              "tc_clustering", "tc_edge_support",
               "tc_edge_counts",
               "tc_build_csr", "tc_radix_sort_u64"):
         getattr(lib, f).restype = ctypes.c_int
@@ -242,6 +244,27 @@ def clustering(edges, num_vertices: int, per_vertex: bool = False, select: int =
     _check(st, ctx)
     res = (coeff, int(T.value), int(W.value), float(tr.value))
     return res + (pv,) if per_vertex else res
+
+
+def edge_support(edges, num_vertices: int, select: int = SELECT_HEURISTIC, workspace=None):
+    """Triangles containing each kept edge: (pairs int32 [m, 2] original ids, support uint32 [m] held
+    in int32, T)."""
+    torch = _torch()
+    e = _edges_arg(edges)
+    ctx, idx = _ctx(e.device)
+    E = e.shape[0]
+    o = _options(select, False)
+    ws = _workspace(idx, workspace_size(E, num_vertices, select), workspace)
+    pairs = torch.empty((max(E, 1), 2), dtype=torch.int32, device=e.device)
+    sup = torch.empty(max(E, 1), dtype=torch.int32, device=e.device)
+    m = ctypes.c_int64()
+    T = ctypes.c_uint64()
+    st = _load().tc_edge_support(ctx, e.data_ptr() if E else None, E, num_vertices, ws.data_ptr(), ws.numel(),
+                                 ctypes.byref(o), pairs.data_ptr(), sup.data_ptr(), ctypes.byref(m),
+                                 ctypes.byref(T))
+    _check(st, ctx)
+    k = int(m.value)
+    return pairs[:k], sup[:k], int(T.value)
 
 
 def edge_counts(edges, num_vertices: int, select: int = SELECT_HEURISTIC, workspace=None):

@@ -293,6 +293,22 @@ tc_status tc_edge_counts(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges,
     return st;
 }
 
+tc_status tc_edge_support(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                          void* d_workspace, size_t workspace_bytes, const tc_options* opts, int32_t* d_out_edges,
+                          uint32_t* d_out_support, int64_t* h_num_out, uint64_t* h_count) {
+    if (!h_num_out || !h_count || (num_edges > 0 && (!d_out_edges || !d_out_support)))
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "null output");
+    tcx::RunArgs ra = {};
+    ra.support = d_out_support;
+    ra.per_edge_pairs = d_out_edges;
+    tc_status st = run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, opts, ra);
+    if (st == TC_OK) {
+        *h_num_out = ctx->h_ctrl->m;
+        *h_count = ctx->h_ctrl->total;
+    }
+    return st;
+}
+
 tc_status tc_build_csr(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
                        void* d_workspace, size_t workspace_bytes, const tc_options* opts, int32_t* d_rank,
                        int64_t* d_offsets, int32_t* d_col, int64_t* h_num_out) {

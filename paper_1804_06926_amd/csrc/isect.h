@@ -23,6 +23,7 @@ struct IsectArgs {
     uint32_t* per_edge;         // [m] or null: c_e in CSR edge order
     uint64_t* per_vertex;       // [n] or null: t[] in rank space
     uint64_t* per_middle;       // [n] or null: triangles whose middle vertex is v (rank space)
+    uint32_t* support;          // [m] or null: triangles containing each kept edge (CSR edge order)
 };
 
 int isect_blocks_per_cu(int ker);

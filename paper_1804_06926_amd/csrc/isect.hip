@@ -15,7 +15,9 @@
 //   bitmap  : N+(v) staged once per vertex as an LDS bitmap; all tails of the
 //             tile streamed through it as one flat, coalesced item range
 // Each hit adds 1 to the exact 64-bit triangle count; optional outputs are
-// the per-edge counts c_e and per-vertex counts t[u], t[v], t[w].
+// the per-edge counts c_e, the per-vertex counts t[u], t[v], t[w] and the
+// edge support (triangles per edge: a hit w adds 1 to edges uv, uw and vw;
+// uw is the tail element's own CSR position, vw the position of w in N+(v)).
 // Tiles are dealt to blocks round-robin (no shared work counter); each block
 // writes its partial count and one reduction adds them in a fixed order.
 #include "common.h"
@@ -76,6 +78,7 @@ __device__ uint32_t load_tile(const IsectArgs& a, uint32_t t, Segs& S) {
 __device__ __forceinline__ void edge_done(const IsectArgs& a, uint32_t e, uint32_t v, uint32_t c,
                                           bool middle = true) {
     if (a.per_edge) a.per_edge[e] = c;
+    if (a.support && c) atomicAdd(&a.support[e], c);
     if (middle && a.per_middle && c) atomicAdd((unsigned long long*)&a.per_middle[v], (unsigned long long)c);
     if (a.per_vertex && c) {
         atomicAdd((unsigned long long*)&a.per_vertex[a.src[e]], (unsigned long long)c);
@@ -85,6 +88,26 @@ __device__ __forceinline__ void edge_done(const IsectArgs& a, uint32_t e, uint32
 
 __device__ __forceinline__ void hit_vertex(const IsectArgs& a, uint32_t w) {
     if (a.per_vertex) atomicAdd((unsigned long long*)&a.per_vertex[w], 1ull);
+}
+
+// A hit w = col[ea] = col[eb]: ea is the edge (u, w) of the tail, eb the edge (v, w).
+__device__ __forceinline__ void hit(const IsectArgs& a, uint32_t w, uint32_t ea, uint32_t eb) {
+    hit_vertex(a, w);
+    if (a.support) {
+        atomicAdd(&a.support[ea], 1u);
+        atomicAdd(&a.support[eb], 1u);
+    }
+}
+
+// Position of x in the ascending list L[0..n), or n when absent.
+__device__ __forceinline__ uint32_t find_pos(const uint32_t* L, uint32_t n, uint32_t x) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (L[mid] < x) lo = mid + 1u;
+        else hi = mid;
+    }
+    return (lo < n && L[lo] == x) ? lo : n;
 }
 
 __device__ __forceinline__ void block_partial(uint64_t acc, uint64_t* partials) {
@@ -100,11 +123,12 @@ __device__ __forceinline__ void block_partial(uint64_t acc, uint64_t* partials) 
 }
 
 // ------------------------------------------------------------------ LDS bitmap
-// PV: per-vertex counts requested; t[w] of the hits is gathered per tile in LDS.
-template <bool PV>
+// GATHER: per-vertex counts or edge support requested; the hits per element
+// of N+(v) (for t[w] and the support of edge vw) are gathered in LDS.
+template <bool GATHER>
 __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* partials) {
-    __shared__ uint32_t s_nv[PV ? NV_MAX : 1];
-    __shared__ uint32_t s_wc[PV ? NV_MAX : 1];
+    __shared__ uint32_t s_nv[GATHER ? NV_MAX : 1];
+    __shared__ uint32_t s_wc[GATHER ? NV_MAX : 1];
     __shared__ uint32_t bm[BM_WORDS];
     __shared__ uint32_t s_start[CHUNK_MAX];
     __shared__ uint32_t s_pref[CHUNK_MAX + 1];
@@ -114,7 +138,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
     __shared__ Segs S;
     for (int i = threadIdx.x; i < BM_WORDS; i += IS_NT) bm[i] = 0;
     if (threadIdx.x < (IS_NT / WAVE) * UNROLL) (&s_mask[0][0])[threadIdx.x] = 0ull;
-    const bool need_cnt = a.per_edge || a.per_vertex || a.per_middle;
+    const bool need_cnt = a.per_edge || a.per_vertex || a.per_middle || a.support;
     uint64_t acc = 0;
     const uint32_t t_end = a.ctrl->tile_begin[KER_BITMAP + 1];
     for (uint32_t t = a.ctrl->tile_begin[KER_BITMAP] + blockIdx.x; t < t_end; t += gridDim.x) {
@@ -152,7 +176,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
             const uint32_t lo = a.col[b0], hi = a.col[b1 - 1];
             const uint32_t base = lo & ~31u;
             const uint32_t nwin = (hi - base) / BM_BITS + 1;
-            if (PV && nb <= (uint32_t)NV_MAX) {
+            if (GATHER && nb <= (uint32_t)NV_MAX) {
                 for (uint32_t j = threadIdx.x; j < nb; j += IS_NT) {
                     s_nv[j] = a.col[b0 + j];
                     s_wc[j] = 0u;
@@ -223,10 +247,12 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                         if (x < BM_BITS && ((bm[x >> 5] >> (x & 31u)) & 1u)) {
                             ++acc;
                             if (need_cnt) atomicAdd(&s_cnt[ks[j]], 1u);
-                            if (PV) {
-                                if (nb <= (uint32_t)NV_MAX) {   // t[w] gathered in LDS, flushed per vertex
+                            if (GATHER) {
+                                const uint32_t w = x + wlo;
+                                if (a.support)   // edge (u, w): the tail element's own position
+                                    atomicAdd(&a.support[s_base[ks[j]] + W + (uint32_t)j * WAVE + ln], 1u);
+                                if (nb <= (uint32_t)NV_MAX) {   // w's slot in N+(v), flushed per vertex
                                     uint32_t lo3 = 0, hi3 = nb - 1;
-                                    const uint32_t w = x + wlo;
                                     while (lo3 < hi3) {
                                         const uint32_t mid = (lo3 + hi3) >> 1;
                                         if (s_nv[mid] < w) lo3 = mid + 1;
@@ -234,7 +260,8 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                                     }
                                     atomicAdd(&s_wc[lo3], 1u);
                                 } else {
-                                    hit_vertex(a, x + wlo);
+                                    hit_vertex(a, w);
+                                    if (a.support) atomicAdd(&a.support[b0 + find_pos(a.col + b0, nb, w)], 1u);
                                 }
                             }
                         }
@@ -247,9 +274,13 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                 }
                 __syncthreads();
             }
-            if (PV && nb <= (uint32_t)NV_MAX) {
-                for (uint32_t j = threadIdx.x; j < nb; j += IS_NT)
-                    if (s_wc[j]) atomicAdd((unsigned long long*)&a.per_vertex[s_nv[j]], (unsigned long long)s_wc[j]);
+            if (GATHER && nb <= (uint32_t)NV_MAX) {
+                for (uint32_t j = threadIdx.x; j < nb; j += IS_NT) {
+                    const uint32_t c = s_wc[j];
+                    if (!c) continue;
+                    if (a.per_vertex) atomicAdd((unsigned long long*)&a.per_vertex[s_nv[j]], (unsigned long long)c);
+                    if (a.support) atomicAdd(&a.support[b0 + j], c);
+                }
             }
             if (need_cnt) {
                 uint32_t seg_hits = 0;
@@ -285,16 +316,6 @@ __device__ __forceinline__ uint32_t merge_split(const uint32_t* A, uint32_t na, 
     return lo;
 }
 
-__device__ __forceinline__ bool contains(const uint32_t* L, uint32_t n, uint32_t x) {
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (L[mid] < x) lo = mid + 1u;
-        else hi = mid;
-    }
-    return lo < n && L[lo] == x;
-}
-
 // Segment holding flattened in-edge q (largest sg with pref[sg] <= q).
 __device__ __forceinline__ uint32_t find_seg(const Segs& S, uint32_t nseg, uint32_t q) {
     uint32_t lo = 0, hi = nseg - 1;
@@ -307,9 +328,10 @@ __device__ __forceinline__ uint32_t find_seg(const Segs& S, uint32_t nseg, uint3
 }
 
 // One in-edge by a group of g lanes: merge path (MERGE) or binary search.
+// ea0, eb0: CSR positions of A[0] (the tail) and B[0] (N+(v)).
 template <bool MERGE>
 __device__ __forceinline__ uint32_t isect_edge(const IsectArgs& a, const uint32_t* A, uint32_t na, const uint32_t* B,
-                                               uint32_t nb, uint32_t g, uint32_t gl) {
+                                               uint32_t nb, uint32_t g, uint32_t gl, uint32_t ea0, uint32_t eb0) {
     uint32_t c = 0;
     if (MERGE) {
         const uint32_t tot = na + nb;
@@ -321,7 +343,7 @@ __device__ __forceinline__ uint32_t isect_edge(const IsectArgs& a, const uint32_
             if (i < na && (j >= nb || A[i] <= B[j])) {
                 if (j < nb && A[i] == B[j]) {
                     ++c;
-                    hit_vertex(a, A[i]);
+                    hit(a, A[i], ea0 + i, eb0 + j);
                 }
                 ++i;
             } else {
@@ -339,18 +361,23 @@ __device__ __forceinline__ uint32_t isect_edge(const IsectArgs& a, const uint32_
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                if (q0 + (uint32_t)u * g < na && contains(B, nb, xv[u])) {
-                    ++c;
-                    hit_vertex(a, xv[u]);
+                const uint32_t q = q0 + (uint32_t)u * g;
+                if (q < na) {
+                    const uint32_t p = find_pos(B, nb, xv[u]);
+                    if (p < nb) {
+                        ++c;
+                        hit(a, xv[u], ea0 + q, eb0 + p);
+                    }
                 }
             }
         }
     } else {
         for (uint32_t q = gl; q < nb; q += g) {
             const uint32_t x = B[q];
-            if (contains(A, na, x)) {
+            const uint32_t p = find_pos(A, na, x);
+            if (p < na) {
                 ++c;
-                hit_vertex(a, x);
+                hit(a, x, ea0 + p, eb0 + q);
             }
         }
     }
@@ -405,7 +432,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_edges(IsectArgs a, uint64_t* pa
                 e = s - 1u;
                 const uint32_t* B = staged ? sb + s_boff[sg] : a.col + a.off[v];
                 const uint32_t nb = s_boff[sg + 1] - s_boff[sg];
-                c = isect_edge<MERGE>(a, a.col + s, end - s, B, nb, g, gl);
+                c = isect_edge<MERGE>(a, a.col + s, end - s, B, nb, g, gl, s, a.off[v]);
             }
             // reduce within the group of g lanes (g divides the wave)
             for (uint32_t o = g >> 1; o > 0; o >>= 1) c += __shfl_xor(c, (int)o, WAVE);
@@ -454,7 +481,8 @@ void launch_isect(int ker, const IsectArgs& a, int grid, uint64_t* partials, hip
         case KER_MERGE: hipLaunchKernelGGL(k_isect_edges<true>, dim3(grid), dim3(IS_NT), 0, s, a, p); break;
         case KER_BSEARCH: hipLaunchKernelGGL(k_isect_edges<false>, dim3(grid), dim3(IS_NT), 0, s, a, p); break;
         default:
-            if (a.per_vertex) hipLaunchKernelGGL(k_isect_bitmap<true>, dim3(grid), dim3(IS_NT), 0, s, a, p);
+            if (a.per_vertex || a.support)
+                hipLaunchKernelGGL(k_isect_bitmap<true>, dim3(grid), dim3(IS_NT), 0, s, a, p);
             else hipLaunchKernelGGL(k_isect_bitmap<false>, dim3(grid), dim3(IS_NT), 0, s, a, p);
             break;
     }

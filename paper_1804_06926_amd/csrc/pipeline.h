@@ -40,6 +40,7 @@ struct RunArgs {
                                      // (exclusive with per_vertex: both use the same scratch)
     double* clustering;              // device [n] or null (original ids): t[v] / C(d(v), 2); sets ctrl->wedges
     uint32_t* per_edge_counts;       // device [E] or null (CSR order)
+    uint32_t* support;               // device [E] or null (CSR order): triangles containing each kept edge
     int32_t* per_edge_pairs;         // device [E][2] or null
     int32_t* csr_rank;               // device [n] or null (CSR export)
     int64_t* csr_off;                // device [n+1]

@@ -533,6 +533,7 @@ static IsectArgs isect_args(const RunArgs& r, const Layout& L, uint64_t* csc) {
     ia.per_edge = r.per_edge_counts;
     ia.per_vertex = (r.per_vertex || r.clustering) ? (uint64_t*)(ws + L.pv) : nullptr;
     ia.per_middle = r.per_middle ? (uint64_t*)(ws + L.pv) : nullptr;
+    ia.support = r.support;
     return ia;
 }
 
@@ -675,6 +676,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     hipLaunchKernelGGL(k_emit_tiles, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vlist, vbucket, tstart, n, ctrl,
                        tiles, (uint64_t)L.tile_cap);
     if (r.per_edge_counts) fill_u32(r.per_edge_counts, 0u, (size_t)E, s);
+    if (r.support) fill_u32(r.support, 0u, (size_t)E, s);
     if (r.per_vertex || r.per_middle || r.clustering) fill_u64(pv, 0ull, (size_t)n, s);
     mark(8);
     if (r.stop_before_isect) {

@@ -189,6 +189,25 @@ def test_per_edge_counts_match_oracle(tc, sel):
     assert np.all((deg[u] < deg[v]) | ((deg[u] == deg[v]) & (u < v)))
 
 
+@pytest.mark.parametrize("sel", SELECTS)
+@pytest.mark.parametrize("case", ["fig4", "k40", "wheel6", "friendship", "rmat12_dirty", "chung_lu", "rgg_16k",
+                                  "er_4096_32768"])
+def test_edge_support_matches_oracle(tc, case, sel):
+    """Support of every kept edge (triangles containing it) against the oracle,
+    matched by canonical pair: the edge set is unique, the order may differ."""
+    e, n = CASES[case]()
+    print(f"case={case} select={sel} E={e.shape[0]} n={n}", flush=True)
+    g = oracle.Graph(e, n)
+    ref = g.edge_support()
+    ref_keys = _canon_keys(g.edges())
+    pairs, sup, T = tc.edge_support(dev(e), n, select=_sel(tc, sel))
+    keys = _canon_keys(pairs.cpu().numpy())
+    o = np.argsort(keys)
+    np.testing.assert_array_equal(keys[o], ref_keys)
+    np.testing.assert_array_equal(sup.cpu().numpy()[o].astype(np.uint32), ref)
+    assert T == g.count() and int(ref.astype(np.int64).sum()) == 3 * T
+
+
 def test_csr_export_matches_definition(tc):
     n = 1 << 12
     e = _dirty(graphgen.rmat(12, 16, seed=5), n, 5)
