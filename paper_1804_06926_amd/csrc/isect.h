@@ -26,7 +26,9 @@ struct IsectArgs {
     uint32_t* support;          // [m] or null: triangles containing each kept edge (CSR edge order)
 };
 
-int isect_blocks_per_cu(int ker);
+// Blocks of one intersection kernel resident per CU (from the occupancy API);
+// gather: the variant with per-vertex or support outputs.
+int isect_blocks_per_cu(int ker, bool gather);
 size_t isect_partials_bytes();
 // One intersection kernel over its tile range; per-block partial counts go to
 // partials (isect_partials_bytes() of workspace shared by the three kernels).

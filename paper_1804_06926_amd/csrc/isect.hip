@@ -130,14 +130,13 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
     __shared__ uint32_t s_nv[GATHER ? NV_MAX : 1];
     __shared__ uint32_t s_wc[GATHER ? NV_MAX : 1];
     __shared__ uint32_t bm[BM_WORDS];
-    __shared__ uint32_t s_start[CHUNK_MAX];
     __shared__ uint32_t s_pref[CHUNK_MAX + 1];
     __shared__ uint32_t s_cnt[CHUNK_MAX];
-    __shared__ uint32_t s_base[CHUNK_MAX];
-    __shared__ unsigned long long s_mask[IS_NT / WAVE][UNROLL];
+    __shared__ uint32_t s_base[CHUNK_MAX + 1];   // entry ne is read (unused) by lanes past the end
+    __shared__ uint8_t s_flag[IS_NT / WAVE][UNROLL][WAVE];    // entry-start marks, one slot per item offset
     __shared__ Segs S;
     for (int i = threadIdx.x; i < BM_WORDS; i += IS_NT) bm[i] = 0;
-    if (threadIdx.x < (IS_NT / WAVE) * UNROLL) (&s_mask[0][0])[threadIdx.x] = 0ull;
+    for (int i = threadIdx.x; i < (IS_NT / WAVE) * UNROLL * WAVE; i += IS_NT) (&s_flag[0][0][0])[i] = 0;
     const bool need_cnt = a.per_edge || a.per_vertex || a.per_middle || a.support;
     uint64_t acc = 0;
     const uint32_t t_end = a.ctrl->tile_begin[KER_BITMAP + 1];
@@ -155,19 +154,18 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
 #pragma unroll
             for (int h = 0; h < CHUNK_MAX / IS_NT; ++h) {
                 const uint32_t k = h * IS_NT + threadIdx.x;
-                uint32_t len = 0;
+                uint32_t len = 0, st = 0;
                 if (k < ne) {
                     const uint64_t ent = a.csc[e0 + k];   // tail start | tail end << 32
-                    const uint32_t s = (uint32_t)ent;
-                    len = (uint32_t)(ent >> 32) - s;
-                    s_start[k] = s;
+                    st = (uint32_t)ent;
+                    len = (uint32_t)(ent >> 32) - st;
                     if (need_cnt) s_cnt[k] = 0;
                 }
                 uint32_t total;
                 const uint32_t excl = block_exclusive_scan<IS_NT>(len, S.scratch, &total);
                 if (k < ne) {
                     s_pref[k] = carry + excl;
-                    s_base[k] = s_start[k] - (carry + excl);   // modular: base + q is the address
+                    s_base[k] = st - (carry + excl);   // modular: base + q is the address; start = base + pref
                 }
                 carry += total;
             }
@@ -195,8 +193,12 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                 // quarter [q0, q1) and walks it in 64-item windows, UNROLL windows
                 // (one load per lane each) in flight per round. The entries that
                 // start inside a window are found from one read of pref per lane:
-                // their start offsets are OR-ed into a 64-bit mask, and a lane's
+                // each marks its start offset in a per-wave slot array, a ballot
+                // over the slots gives the 64-bit mask of starts, and a lane's
                 // entry is kb + (number of starts at or before its offset).
+                // Each phase runs over all UNROLL windows before the next, and
+                // loads are unconditional (out-of-range lanes read a valid
+                // address), so the loads of a round are issued back to back.
                 const uint32_t wv = (uint32_t)wave_id(), ln = (uint32_t)lane_id();
                 const uint32_t q0 = (uint32_t)(((uint64_t)L * wv) / (IS_NT / WAVE));
                 const uint32_t q1 = (uint32_t)(((uint64_t)L * (wv + 1)) / (IS_NT / WAVE));
@@ -225,28 +227,67 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                         }
                         kw = lo2;
                     }
-                    uint32_t xs[UNROLL], ks[UNROLL];
+                    uint32_t xs[UNROLL], ks[UNROLL], kj[UNROLL];
+#pragma unroll
+                    for (int j = 0; j < UNROLL; ++j) kj[j] = __shfl(kw, j, WAVE);
+                    // mark the starts: lane ln looks at entry kj + 1 + ln (pref is strictly
+                    // increasing, so the marked offsets are distinct and at least 1).
+                    // Entries past the last one read pref[ne] = L: a start at or after
+                    // item L moves only lanes whose items lie beyond q1 (unused).
+                    uint32_t o[UNROLL];
 #pragma unroll
                     for (int j = 0; j < UNROLL; ++j) {
-                        const uint32_t Wj = W + j * WAVE;
-                        const uint32_t kbj = __shfl(kw, j, WAVE);
-                        const uint32_t kk = kbj + 1u + ln;
-                        const uint32_t o = (kk < ne) ? s_pref[kk] - Wj : 64u;
-                        if (o < 64u) atomicOr(&s_mask[wv][j], 1ull << o);
-                        const uint64_t M = s_mask[wv][j];
-                        if (ln == 0) s_mask[wv][j] = 0ull;
-                        const uint32_t k = kbj + (uint32_t)__popcll(M & upto);
-                        const uint32_t q = Wj + ln;
-                        ks[j] = k;
-                        xs[j] = q < q1 ? a.col[s_base[k] + q] - wlo : 0xFFFFFFFFu;
+                        const uint32_t kk = kj[j] + 1u + ln;
+                        o[j] = s_pref[kk < ne ? kk : ne] - (W + j * WAVE);
                     }
+#pragma unroll
+                    for (int j = 0; j < UNROLL; ++j)
+                        if (o[j] < 64u) s_flag[wv][j][o[j]] = 1;
+                    // the lanes of the wave exchange marks through LDS: keep the
+                    // mark / read / clear phases in program order
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    uint32_t f[UNROLL];
+#pragma unroll
+                    for (int j = 0; j < UNROLL; ++j) f[j] = s_flag[wv][j][ln];
+#pragma unroll
+                    for (int j = 0; j < UNROLL; ++j) s_flag[wv][j][ln] = 0;   // each lane clears its own slot
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+                    for (int j = 0; j < UNROLL; ++j) {
+                        const uint64_t M = __ballot(f[j] != 0u);
+                        ks[j] = kj[j] + (uint32_t)__popcll(M & upto);
+                    }
+                    uint32_t ad[UNROLL];
+#pragma unroll
+                    for (int j = 0; j < UNROLL; ++j) {
+                        const uint32_t q = W + j * WAVE + ln;
+                        const uint32_t sb = s_base[ks[j]];
+                        ad[j] = q < q1 ? sb + q : b0;
+                    }
+#pragma unroll
+                    for (int j = 0; j < UNROLL; ++j) xs[j] = a.col[ad[j]];
+#pragma unroll
+                    for (int j = 0; j < UNROLL; ++j)
+                        xs[j] = (W + j * WAVE + ln < q1) ? xs[j] - wlo : 0xFFFFFFFFu;
                     kb = __shfl(kw, UNROLL - 1, WAVE);   // searches of the next round start here
+                    // membership tests: all bitmap words read first, then tested
+                    uint32_t wd[UNROLL];
+#pragma unroll
+                    for (int j = 0; j < UNROLL; ++j) wd[j] = bm[(xs[j] < BM_BITS ? xs[j] : 0u) >> 5];
+                    uint32_t hits = 0, hm = 0;
+#pragma unroll
+                    for (int j = 0; j < UNROLL; ++j) {
+                        const uint32_t h = xs[j] < BM_BITS ? (wd[j] >> (xs[j] & 31u)) & 1u : 0u;
+                        hits += h;
+                        hm |= h << j;
+                    }
+                    acc += hits;
+                    if (!need_cnt) continue;
 #pragma unroll
                     for (int j = 0; j < UNROLL; ++j) {
                         const uint32_t x = xs[j];
-                        if (x < BM_BITS && ((bm[x >> 5] >> (x & 31u)) & 1u)) {
-                            ++acc;
-                            if (need_cnt) atomicAdd(&s_cnt[ks[j]], 1u);
+                        if ((hm >> j) & 1u) {
+                            atomicAdd(&s_cnt[ks[j]], 1u);
                             if (GATHER) {
                                 const uint32_t w = x + wlo;
                                 if (a.support)   // edge (u, w): the tail element's own position
@@ -285,7 +326,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
             if (need_cnt) {
                 uint32_t seg_hits = 0;
                 for (uint32_t k = threadIdx.x; k < ne; k += IS_NT) {
-                    edge_done(a, s_start[k] - 1u, v, s_cnt[k], false);
+                    edge_done(a, s_base[k] + s_pref[k] - 1u, v, s_cnt[k], false);
                     seg_hits += s_cnt[k];
                 }
                 if (a.per_middle) {   // one update per vertex and tile
@@ -327,6 +368,54 @@ __device__ __forceinline__ uint32_t find_seg(const Segs& S, uint32_t nseg, uint3
     return lo;
 }
 
+// Elements X[q] (q = gl, gl + g, ...) of one list searched in the ascending
+// list Y (ny > 0) by a group of g lanes: four elements per lane at a time, as
+// four interleaved branch-free lower bounds (halving the range each step),
+// so that every step issues four independent loads. Returns the matches; a
+// match at X[q] = Y[p] is edge ex0 + q and edge ey0 + p.
+__device__ __forceinline__ uint32_t search_list(const IsectArgs& a, const uint32_t* X, uint32_t nx,
+                                                const uint32_t* Y, uint32_t ny, uint32_t g, uint32_t gl,
+                                                uint32_t ex0, uint32_t ey0) {
+    uint32_t c = 0;
+    if (ny == 0) return 0;
+    for (uint32_t q0 = gl; q0 < nx; q0 += 4u * g) {
+        uint32_t xv[4], bs[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t q = q0 + (uint32_t)u * g;
+            xv[u] = X[q < nx ? q : nx - 1u];
+            bs[u] = 0;
+        }
+        for (uint32_t len = ny; len > 1;) {
+            const uint32_t half = len >> 1;
+            uint32_t yv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) yv[u] = Y[bs[u] + half];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) bs[u] = yv[u] < xv[u] ? bs[u] + half : bs[u];
+            len -= half;
+        }
+        // bs = last position below x (or 0): the lower bound is bs or bs + 1
+        uint32_t y0[4], y1[4], lb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y0[u] = Y[bs[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            lb[u] = bs[u] + (y0[u] < xv[u] ? 1u : 0u);
+            y1[u] = Y[lb[u] < ny ? lb[u] : ny - 1u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t q = q0 + (uint32_t)u * g;
+            if (q < nx && lb[u] < ny && y1[u] == xv[u]) {
+                ++c;
+                hit(a, xv[u], ex0 + q, ey0 + lb[u]);
+            }
+        }
+    }
+    return c;
+}
+
 // One in-edge by a group of g lanes: merge path (MERGE) or binary search.
 // ea0, eb0: CSR positions of A[0] (the tail) and B[0] (N+(v)).
 template <bool MERGE>
@@ -351,35 +440,9 @@ __device__ __forceinline__ uint32_t isect_edge(const IsectArgs& a, const uint32_
             }
         }
     } else if (na <= nb) {
-        // tail elements are loaded four at a time (independent loads), then searched
-        for (uint32_t q0 = gl; q0 < na; q0 += 4u * g) {
-            uint32_t xv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t q = q0 + (uint32_t)u * g;
-                xv[u] = q < na ? A[q] : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t q = q0 + (uint32_t)u * g;
-                if (q < na) {
-                    const uint32_t p = find_pos(B, nb, xv[u]);
-                    if (p < nb) {
-                        ++c;
-                        hit(a, xv[u], ea0 + q, eb0 + p);
-                    }
-                }
-            }
-        }
+        c = search_list(a, A, na, B, nb, g, gl, ea0, eb0);   // tail elements searched in N+(v)
     } else {
-        for (uint32_t q = gl; q < nb; q += g) {
-            const uint32_t x = B[q];
-            const uint32_t p = find_pos(A, na, x);
-            if (p < na) {
-                ++c;
-                hit(a, x, ea0 + p, eb0 + q);
-            }
-        }
+        c = search_list(a, B, nb, A, na, g, gl, eb0, ea0);   // N+(v) searched in the tail
     }
     return c;
 }
@@ -430,9 +493,11 @@ __global__ __launch_bounds__(IS_NT) void k_isect_edges(IsectArgs a, uint64_t* pa
                 const uint64_t ent = a.csc[S.e0[sg] + (q - S.pref[sg])];   // tail start | end << 32
                 const uint32_t s = (uint32_t)ent, end = (uint32_t)(ent >> 32);
                 e = s - 1u;
-                const uint32_t* B = staged ? sb + s_boff[sg] : a.col + a.off[v];
                 const uint32_t nb = s_boff[sg + 1] - s_boff[sg];
-                c = isect_edge<MERGE>(a, a.col + s, end - s, B, nb, g, gl, s, a.off[v]);
+                const uint32_t bo = a.off[v];
+                // two call sites, so that each knows whether N+(v) is in LDS or in global memory
+                if (staged) c = isect_edge<MERGE>(a, a.col + s, end - s, sb + s_boff[sg], nb, g, gl, s, bo);
+                else c = isect_edge<MERGE>(a, a.col + s, end - s, a.col + bo, nb, g, gl, s, bo);
             }
             // reduce within the group of g lanes (g divides the wave)
             for (uint32_t o = g >> 1; o > 0; o >>= 1) c += __shfl_xor(c, (int)o, WAVE);
@@ -468,12 +533,31 @@ static int num_cu() {
     return g_num_cu;
 }
 
-int isect_blocks_per_cu(int ker) { return ker == KER_BITMAP ? 6 : 8; }
+// Persistent grids: as many blocks as the CUs hold at once (LDS and registers
+// decide), so that no block starts late and stretches the tail.
+static int resident_blocks(const void* fn) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, IS_NT, 0) != hipSuccess || b <= 0) b = 1;
+    return b;
+}
+
+int isect_blocks_per_cu(int ker, bool gather) {
+    static int cache[NKERNEL][2] = {};
+    int& c = cache[ker][gather ? 1 : 0];
+    if (!c) {
+        const void* fn = ker == KER_MERGE     ? (const void*)k_isect_edges<true>
+                         : ker == KER_BSEARCH ? (const void*)k_isect_edges<false>
+                         : gather             ? (const void*)k_isect_bitmap<true>
+                                              : (const void*)k_isect_bitmap<false>;
+        c = resident_blocks(fn);
+    }
+    return c;
+}
 
 size_t isect_partials_bytes() { return sizeof(uint64_t) * NKERNEL * PARTIALS_PER_KERNEL; }
 
 void launch_isect(int ker, const IsectArgs& a, int grid, uint64_t* partials, hipStream_t s) {
-    if (grid <= 0) grid = num_cu() * isect_blocks_per_cu(ker);
+    if (grid <= 0) grid = num_cu() * isect_blocks_per_cu(ker, a.per_vertex || a.support);
     if (grid > PARTIALS_PER_KERNEL) grid = PARTIALS_PER_KERNEL;
     uint64_t* p = partials + (size_t)ker * PARTIALS_PER_KERNEL;
     fill_u64(p, 0ull, PARTIALS_PER_KERNEL, s);
