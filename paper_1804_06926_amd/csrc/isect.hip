@@ -423,20 +423,30 @@ __device__ __forceinline__ uint32_t isect_edge(const IsectArgs& a, const uint32_
                                                uint32_t nb, uint32_t g, uint32_t gl, uint32_t ea0, uint32_t eb0) {
     uint32_t c = 0;
     if (MERGE) {
+        // The lane's diagonal range [d0, d1) of the merge path consumes the A
+        // elements [i0, i1); each A element is consumed by exactly one lane and
+        // counts when it equals the B head at that point, which (B ascending)
+        // is the first B element not below it. So the lane walks its A
+        // elements, four loaded at a time, with a monotone cursor into B that
+        // starts at the diagonal's B position d0 - i0.
         const uint32_t tot = na + nb;
         const uint32_t d0 = (uint32_t)(((uint64_t)tot * gl) / g);
         const uint32_t d1 = (uint32_t)(((uint64_t)tot * (gl + 1u)) / g);
-        uint32_t i = merge_split(A, na, B, nb, d0);
-        uint32_t j = d0 - i;
-        for (uint32_t step = d0; step < d1; ++step) {
-            if (i < na && (j >= nb || A[i] <= B[j])) {
-                if (j < nb && A[i] == B[j]) {
+        const uint32_t i0 = merge_split(A, na, B, nb, d0);
+        const uint32_t i1 = merge_split(A, na, B, nb, d1);
+        uint32_t j = d0 - i0;
+        for (uint32_t i = i0; i < i1; i += 4u) {
+            uint32_t av[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) av[u] = A[i + u < i1 ? i + u : i1 - 1u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (i + u >= i1) break;
+                while (j < nb && B[j] < av[u]) ++j;
+                if (j < nb && B[j] == av[u]) {
                     ++c;
-                    hit(a, A[i], ea0 + i, eb0 + j);
+                    hit(a, av[u], ea0 + i + u, eb0 + j);
                 }
-                ++i;
-            } else {
-                ++j;
             }
         }
     } else if (na <= nb) {
