@@ -194,11 +194,17 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ k
     const uint32_t n = rs_count(d_count, cap);
     const int w = wave_id(), l = lane_id();
     const uint32_t base = blockIdx.x * RS_TILE + w * RS_WAVE_SPAN;
+    uint32_t dg[RS_ITEMS];
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint32_t i = base + it * WAVE + l;
+        dg[it] = i < n ? (uint32_t)(keys[i] >> shift) & dmask : 0u;
+    }
 #pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
         const uint32_t i = base + it * WAVE + l;
         const bool valid = i < n;
-        const uint32_t d = valid ? (uint32_t)(keys[i] >> shift) & dmask : 0u;
+        const uint32_t d = dg[it];
         const uint64_t peers = match_digit8(d, __ballot(valid));
         if (valid && (peers & lanes_below()) == 0) wcnt[w][d] += (uint32_t)__popcll(peers);
     }
@@ -261,12 +267,18 @@ __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const KeyT* __restrict_
     KeyT k[RS_ITEMS];
     uint32_t v[RS_ITEMS];
     uint32_t loc[RS_ITEMS];   // digit | (rank within (wave, digit)) << 8
+    // all loads first, so that they are in flight together (the ranking below
+    // has wave barriers that no load may cross)
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint32_t i = base + it * WAVE + l;
+        k[it] = i < n ? kin[i] : KeyT(0);
+        if (HAS_VAL) v[it] = i < n ? vin[i] : 0u;
+    }
 #pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
         const uint32_t i = base + it * WAVE + l;
         const bool valid = i < n;
-        k[it] = valid ? kin[i] : KeyT(0);
-        if (HAS_VAL) v[it] = valid ? vin[i] : 0u;
         const uint32_t d = (uint32_t)(k[it] >> shift) & dmask;
         const uint64_t peers = match_digit8(d, __ballot(valid));
         const uint32_t r = (uint32_t)__popcll(peers & lanes_below());
