@@ -37,6 +37,7 @@ void fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s) {
 // partial as the carry-in. Works in place (out == in).
 constexpr int SCAN_NT = 256;
 constexpr int SCAN_MAX_BLOCKS = 1024;
+constexpr int SCAN_ITEMS = 8;   // elements per thread per step
 
 struct OpSum {
     template <typename T> __device__ static T apply(T a, T b) { return a + b; }
@@ -85,7 +86,16 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_reduce(const T* in, size_t len
     const size_t b0 = (size_t)blockIdx.x * chunk;
     const size_t b1 = b0 + chunk < len ? b0 + chunk : len;
     T acc = Op::template ident<T>();
-    for (size_t i = b0 + threadIdx.x; i < b1; i += SCAN_NT) acc = Op::apply(acc, in[i]);
+    for (size_t base = b0; base < b1; base += (size_t)SCAN_NT * SCAN_ITEMS) {
+        T v[SCAN_ITEMS];
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) {   // loads in flight together
+            const size_t i = base + (size_t)k * SCAN_NT + threadIdx.x;
+            v[k] = i < b1 ? in[i] : Op::template ident<T>();
+        }
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) acc = Op::apply(acc, v[k]);
+    }
     acc = block_reduce<Op>(acc, scratch);
     if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
@@ -126,16 +136,37 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_down(const T* in, T* out, size
     const size_t b0 = (size_t)blockIdx.x * chunk;
     const size_t b1 = b0 + chunk < len ? b0 + chunk : len;
     T carry = partial[blockIdx.x];
-    for (size_t base = b0; base < b1; base += SCAN_NT) {
-        const size_t i = base + threadIdx.x;
-        const T v = i < b1 ? in[i] : Op::template ident<T>();
+    // SCAN_ITEMS consecutive elements per thread: loaded together, scanned in
+    // registers, then one block scan of the thread totals per SCAN_NT * SCAN_ITEMS
+    for (size_t base = b0; base < b1; base += (size_t)SCAN_NT * SCAN_ITEMS) {
+        const size_t i0 = base + (size_t)threadIdx.x * SCAN_ITEMS;
+        T v[SCAN_ITEMS];
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) v[k] = i0 + k < b1 ? in[i0 + k] : Op::template ident<T>();
+        T run = Op::template ident<T>();
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) run = Op::apply(run, v[k]);
         T total;
-        const T inc = block_scan_inclusive<Op>(v, scratch, &total);
-        if (i < b1) {
-            if (INCLUSIVE) {
-                out[i] = Op::apply(carry, inc);
-            } else {
-                out[i] = Op::apply(carry, inc) - v;   // exclusive form is only used with OpSum
+        const T inc = block_scan_inclusive<Op>(run, scratch, &total);
+        // exclusive prefix of this thread's run within the block step
+        T acc;
+        {
+            const T prev_inc = (T)__shfl_up(inc, 1, WAVE);
+            __shared__ T wave_last[SCAN_NT / WAVE];
+            if (lane_id() == WAVE - 1) wave_last[wave_id()] = inc;
+            __syncthreads();
+            T before = Op::template ident<T>();
+            if (lane_id() != 0) before = prev_inc;
+            else if (wave_id() != 0) before = wave_last[wave_id() - 1];
+            __syncthreads();
+            acc = Op::apply(carry, before);
+        }
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k) {
+            if (i0 + k < b1) {
+                const T nxt = Op::apply(acc, v[k]);
+                out[i0 + k] = INCLUSIVE ? nxt : acc;
+                acc = nxt;
             }
         }
         carry = Op::apply(carry, total);
