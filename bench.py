@@ -55,6 +55,29 @@ def make_graph(name):
     return graphgen.rgg(w["n"], w["avg_degree"], seed=w["seed"]), w["n"], w
 
 
+def counted_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE passes scaled by a copy of known size), or None when
+    there is none for this workload or the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    src = os.path.join(ROOT, "paper_1804_06926_amd", "csrc", "isect.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ": " in line and not line.startswith(("|", "#", " ")):
+                k, v = line.strip().split(": ", 1)
+                fields[k] = v
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    key = f"{kernel}_traffic_bytes"
+    if fields.get("isect_source_sha256") != digest or key not in fields:
+        return None
+    return float(fields[key])
+
+
 def algorithmic_bytes(tc, d_edges, n, stats):
     """Compulsory global reads of each intersection kernel for this graph.
 
@@ -254,7 +277,8 @@ def main(argv=None):
                    "generator": spec["kind"], "raw_pairs": int(edges.shape[0]), "n": n, "m": m,
                    "triangles": T, "select": args.select},
         "roofline": {"bound": "hbm", "kernel": f"k_isect_{dom}", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": counted_traffic(f"k_isect_{dom}", args.workload),
                      "algorithmic_bytes": kbytes[dom], "avg_launch_ms": dom_ms},
         "stages_ms": stages,
         "intersect_gedges_per_s": m / (isect_ms * 1e-3) / 1e9 if isect_ms > 0 else None,
