@@ -97,8 +97,8 @@ tc_status tc_count_triangles(tc_ctx* ctx, const int32_t* d_edges, int64_t num_ed
  * tc_count_triangles without any host synchronisation: the work is queued on
  * the context's stream and the call returns. On completion
  *   d_result[0] = T, d_result[1] = 0, or TC_ERR_VERTEX_RANGE when an id lies
- *   outside [0, num_vertices) (then d_result[0] and d_per_vertex are
- *   meaningless).
+ *   outside [0, num_vertices), or TC_ERR_HIP when an internal bound check
+ *   failed (in both cases d_result[0] and d_per_vertex are meaningless).
  * d_result: uint64[2], device memory, 8-byte aligned. Host-detectable errors
  * return before anything is queued. The workspace and outputs must stay
  * untouched until the stream reaches the end of the call; calls queued on one

@@ -146,7 +146,7 @@ tc_status run(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* w
     hipError_t e = tcx::run_pipeline(ra, &rr);
     if (e != hipSuccess) return hip_fail(ctx, e, "launch");
     if (d_result) {
-        tcx::publish_result(rr.ctrl_dev, d_result, (uint64_t)TC_ERR_VERTEX_RANGE, ctx->stream);
+        tcx::publish_result(rr.ctrl_dev, d_result, (uint64_t)TC_ERR_VERTEX_RANGE, (uint64_t)TC_ERR_HIP, ctx->stream);
         ctx->have_times = 0;
         e = hipGetLastError();
         return e == hipSuccess ? TC_OK : hip_fail(ctx, e, "queue result");
@@ -165,6 +165,7 @@ tc_status run(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* w
         ctx->have_times = 1;
     }
     if (ctx->h_ctrl->err & 1u) return arg_fail(ctx, TC_ERR_VERTEX_RANGE, "vertex id outside [0, num_vertices)");
+    if (ctx->h_ctrl->err) return arg_fail(ctx, TC_ERR_HIP, "internal bound violated (tail length)");
     return TC_OK;
 }
 
@@ -496,6 +497,7 @@ tc_status tc_count_triangles_batch(tc_ctx* ctx, const int32_t* d_edges, const in
     if (e != hipSuccess) return hip_fail(ctx, e, "read batch counts");
     ctx->have_times = 0;
     if (ctx->h_ctrl->err & 1u) return arg_fail(ctx, TC_ERR_VERTEX_RANGE, "vertex id outside its graph's range");
+    if (ctx->h_ctrl->err) return arg_fail(ctx, TC_ERR_HIP, "internal bound violated (tail length)");
     memcpy(h_counts, ctx->h_counts_pinned, sizeof(uint64_t) * (size_t)num_graphs);
     return TC_OK;
 }

@@ -31,6 +31,7 @@ constexpr int BM_WORDS = 4096;            // 131072-bit window (16 KiB)
 constexpr uint32_t BM_BITS = BM_WORDS * 32u;
 constexpr int STAGE_MAX = 4096;           // N+(v) staged in LDS by merge/bsearch when it fits
 constexpr int UNROLL = 8;                 // bitmap kernel: tail loads in flight per lane
+constexpr uint32_t WT_MAX = 2048;         // bitmap kernel: 64-item windows per chunk of the item range
 constexpr int NV_MAX = 2048;              // bitmap kernel, per-vertex mode: N+(v) kept for t[w] gathering
 constexpr int PARTIALS_PER_KERNEL = 4096; // max blocks per intersection launch
 
@@ -129,13 +130,14 @@ template <bool GATHER>
 __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* partials) {
     __shared__ uint32_t s_nv[GATHER ? NV_MAX : 1];
     __shared__ uint32_t s_wc[GATHER ? NV_MAX : 1];
-    __shared__ uint32_t bm[BM_WORDS];
+    __shared__ uint32_t bm[BM_WORDS + 1];        // + one always-zero word for out-of-window positions
+    __shared__ uint16_t s_wst[WT_MAX];           // entry holding the first item of each window of a chunk
     __shared__ uint32_t s_pref[CHUNK_MAX + 1];
     __shared__ uint32_t s_cnt[CHUNK_MAX];
     __shared__ uint32_t s_base[CHUNK_MAX + 1];   // entry ne is read (unused) by lanes past the end
     __shared__ uint8_t s_flag[IS_NT / WAVE][UNROLL][WAVE];    // entry-start marks, one slot per item offset
     __shared__ Segs S;
-    for (int i = threadIdx.x; i < BM_WORDS; i += IS_NT) bm[i] = 0;
+    for (int i = threadIdx.x; i <= BM_WORDS; i += IS_NT) bm[i] = 0;
     for (int i = threadIdx.x; i < (IS_NT / WAVE) * UNROLL * WAVE; i += IS_NT) (&s_flag[0][0][0])[i] = 0;
     const bool need_cnt = a.per_edge || a.per_vertex || a.per_middle || a.support;
     uint64_t acc = 0;
@@ -189,124 +191,122 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                 }
                 __syncthreads();
                 // All tails of the tile form one flat item range [0, L); item q of
-                // entry k lives at col[base[k] + q]. Wave w takes the contiguous
-                // quarter [q0, q1) and walks it in 64-item windows, UNROLL windows
-                // (one load per lane each) in flight per round. The entries that
-                // start inside a window are found from one read of pref per lane:
-                // each marks its start offset in a per-wave slot array, a ballot
-                // over the slots gives the 64-bit mask of starts, and a lane's
-                // entry is kb + (number of starts at or before its offset).
-                // Each phase runs over all UNROLL windows before the next, and
-                // loads are unconditional (out-of-range lanes read a valid
-                // address), so the loads of a round are issued back to back.
+                // entry k lives at col[base[k] + q]. The range is cut into 64-item
+                // windows, taken in chunks of WT_MAX windows: per chunk a table gives
+                // the entry holding each window's first item, and wave w walks a
+                // contiguous, 64-aligned quarter of the chunk in rounds of UNROLL
+                // windows (one item per lane per window). A round runs in phases,
+                // each over all UNROLL windows: read the windows' first entries from
+                // the table; mark the entry starts inside each window (lane ln looks
+                // at entry first + 1 + ln and marks its start offset in a per-wave
+                // slot array); read the slots back as a ballot mask, so that a lane's
+                // entry is first + (starts at or before its offset); issue the tail
+                // loads, unconditional (lanes past the end read a valid address);
+                // test the bitmap.
                 const uint32_t wv = (uint32_t)wave_id(), ln = (uint32_t)lane_id();
-                const uint32_t q0 = (uint32_t)(((uint64_t)L * wv) / (IS_NT / WAVE));
-                const uint32_t q1 = (uint32_t)(((uint64_t)L * (wv + 1)) / (IS_NT / WAVE));
-                uint32_t kb = 0;   // entry holding item q0: last k with pref[k] <= q0
-                if (q0 < q1) {
-                    uint32_t lo2 = 0, hi2 = ne - 1;
-                    while (lo2 < hi2) {
-                        const uint32_t mid = (lo2 + hi2 + 1) >> 1;
-                        if (s_pref[mid] <= q0) lo2 = mid;
-                        else hi2 = mid - 1;
+                for (uint32_t c0 = 0; c0 < L; c0 += WT_MAX * WAVE) {
+                    const uint32_t c1 = L - c0 < WT_MAX * WAVE ? L : c0 + WT_MAX * WAVE;
+                    const uint32_t nwc = (c1 - c0 + WAVE - 1) / WAVE;   // windows in this chunk
+                    // window table: entry k covers items [pref[k], pref[k+1])
+                    for (uint32_t k = threadIdx.x; k < ne; k += IS_NT) {
+                        const uint32_t p0 = s_pref[k] > c0 ? s_pref[k] : c0;
+                        const uint32_t p1 = s_pref[k + 1] < c1 ? s_pref[k + 1] : c1;
+                        for (uint32_t w = (p0 - c0 + WAVE - 1) / WAVE; p0 < p1 && w * WAVE + c0 < p1; ++w)
+                            s_wst[w] = (uint16_t)k;
                     }
-                    kb = lo2;
-                }
-                const uint64_t upto = ln == 63 ? ~0ull : ((2ull << ln) - 1ull);   // bits 0..ln
-                for (uint32_t W = q0; W < q1; W += WAVE * UNROLL) {
-                    // entries holding the first item of each window, searched by
-                    // lanes 0..UNROLL-1 in parallel within [kb, ne)
-                    uint32_t kw = kb;
-                    if (ln < (uint32_t)UNROLL && W + ln * WAVE < q1) {
-                        const uint32_t qw = W + ln * WAVE;
-                        uint32_t lo2 = kb, hi2 = ne - 1;
-                        while (lo2 < hi2) {
-                            const uint32_t mid = (lo2 + hi2 + 1) >> 1;
-                            if (s_pref[mid] <= qw) lo2 = mid;
-                            else hi2 = mid - 1;
+                    __syncthreads();
+                    const uint32_t span = (c1 - c0 + WAVE - 1) / WAVE;   // windows, split over the waves
+                    const uint32_t q0 = c0 + WAVE * ((span * wv) / (IS_NT / WAVE));
+                    const uint32_t qe = c0 + WAVE * ((span * (wv + 1)) / (IS_NT / WAVE));
+                    const uint32_t q1 = qe < c1 ? qe : c1;
+                    for (uint32_t W = q0; W < q1; W += WAVE * UNROLL) {
+                        uint32_t xs[UNROLL], ks[UNROLL], kj[UNROLL];
+#pragma unroll
+                        for (int j = 0; j < UNROLL; ++j) {   // same address in all lanes: broadcast
+                            const uint32_t wi = (W - c0) / WAVE + (uint32_t)j;
+                            kj[j] = s_wst[wi < nwc ? wi : nwc - 1u];
                         }
-                        kw = lo2;
-                    }
-                    uint32_t xs[UNROLL], ks[UNROLL], kj[UNROLL];
+                        // mark the starts (pref is strictly increasing, so the marked offsets
+                        // are distinct and at least 1). Entries past the last one read
+                        // pref[ne] = L: a start at or after item L moves only lanes whose
+                        // items lie beyond q1 (unused).
+                        uint32_t o[UNROLL];
 #pragma unroll
-                    for (int j = 0; j < UNROLL; ++j) kj[j] = __shfl(kw, j, WAVE);
-                    // mark the starts: lane ln looks at entry kj + 1 + ln (pref is strictly
-                    // increasing, so the marked offsets are distinct and at least 1).
-                    // Entries past the last one read pref[ne] = L: a start at or after
-                    // item L moves only lanes whose items lie beyond q1 (unused).
-                    uint32_t o[UNROLL];
+                        for (int j = 0; j < UNROLL; ++j) {
+                            const uint32_t kk = kj[j] + 1u + ln;
+                            o[j] = s_pref[kk < ne ? kk : ne] - (W + j * WAVE);
+                        }
 #pragma unroll
-                    for (int j = 0; j < UNROLL; ++j) {
-                        const uint32_t kk = kj[j] + 1u + ln;
-                        o[j] = s_pref[kk < ne ? kk : ne] - (W + j * WAVE);
-                    }
+                        for (int j = 0; j < UNROLL; ++j)
+                            if (o[j] < 64u) s_flag[wv][j][o[j]] = 1;
+                        // the lanes of the wave exchange marks through LDS: keep the
+                        // mark / read / clear phases in program order
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        uint32_t f[UNROLL];
 #pragma unroll
-                    for (int j = 0; j < UNROLL; ++j)
-                        if (o[j] < 64u) s_flag[wv][j][o[j]] = 1;
-                    // the lanes of the wave exchange marks through LDS: keep the
-                    // mark / read / clear phases in program order
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    uint32_t f[UNROLL];
+                        for (int j = 0; j < UNROLL; ++j) f[j] = s_flag[wv][j][ln];
 #pragma unroll
-                    for (int j = 0; j < UNROLL; ++j) f[j] = s_flag[wv][j][ln];
+                        for (int j = 0; j < UNROLL; ++j) s_flag[wv][j][ln] = 0;   // each lane clears its own slot
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
-                    for (int j = 0; j < UNROLL; ++j) s_flag[wv][j][ln] = 0;   // each lane clears its own slot
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        for (int j = 0; j < UNROLL; ++j) {
+                            const uint64_t M = __ballot(f[j] != 0u);
+                            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(M >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u));
+                            ks[j] = kj[j] + below + (f[j] != 0u ? 1u : 0u);
+                        }
+                        uint32_t ad[UNROLL];
 #pragma unroll
-                    for (int j = 0; j < UNROLL; ++j) {
-                        const uint64_t M = __ballot(f[j] != 0u);
-                        ks[j] = kj[j] + (uint32_t)__popcll(M & upto);
-                    }
-                    uint32_t ad[UNROLL];
+                        for (int j = 0; j < UNROLL; ++j) {
+                            const uint32_t q = W + j * WAVE + ln;
+                            const uint32_t sb = s_base[ks[j]];
+                            ad[j] = q < q1 ? sb + q : b0;
+                        }
 #pragma unroll
-                    for (int j = 0; j < UNROLL; ++j) {
-                        const uint32_t q = W + j * WAVE + ln;
-                        const uint32_t sb = s_base[ks[j]];
-                        ad[j] = q < q1 ? sb + q : b0;
-                    }
+                        for (int j = 0; j < UNROLL; ++j) xs[j] = a.col[ad[j]];
 #pragma unroll
-                    for (int j = 0; j < UNROLL; ++j) xs[j] = a.col[ad[j]];
+                        for (int j = 0; j < UNROLL; ++j)
+                            xs[j] = (W + j * WAVE + ln < q1) ? xs[j] - wlo : 0xFFFFFFFFu;
+                        // membership: bit positions past the window map to the spare
+                        // always-zero word bm[BM_WORDS]
+                        uint32_t wd[UNROLL];
 #pragma unroll
-                    for (int j = 0; j < UNROLL; ++j)
-                        xs[j] = (W + j * WAVE + ln < q1) ? xs[j] - wlo : 0xFFFFFFFFu;
-                    kb = __shfl(kw, UNROLL - 1, WAVE);   // searches of the next round start here
-                    // membership tests: all bitmap words read first, then tested
-                    uint32_t wd[UNROLL];
+                        for (int j = 0; j < UNROLL; ++j) wd[j] = bm[(xs[j] < BM_BITS ? xs[j] : BM_BITS) >> 5];
+                        uint32_t hits = 0, hm = 0;
 #pragma unroll
-                    for (int j = 0; j < UNROLL; ++j) wd[j] = bm[(xs[j] < BM_BITS ? xs[j] : 0u) >> 5];
-                    uint32_t hits = 0, hm = 0;
+                        for (int j = 0; j < UNROLL; ++j) {
+                            const uint32_t h = (wd[j] >> (xs[j] & 31u)) & 1u;
+                            hits += h;
+                            hm |= h << j;
+                        }
+                        acc += hits;
+                        if (!need_cnt) continue;
 #pragma unroll
-                    for (int j = 0; j < UNROLL; ++j) {
-                        const uint32_t h = xs[j] < BM_BITS ? (wd[j] >> (xs[j] & 31u)) & 1u : 0u;
-                        hits += h;
-                        hm |= h << j;
-                    }
-                    acc += hits;
-                    if (!need_cnt) continue;
-#pragma unroll
-                    for (int j = 0; j < UNROLL; ++j) {
-                        const uint32_t x = xs[j];
-                        if ((hm >> j) & 1u) {
-                            atomicAdd(&s_cnt[ks[j]], 1u);
-                            if (GATHER) {
-                                const uint32_t w = x + wlo;
-                                if (a.support)   // edge (u, w): the tail element's own position
-                                    atomicAdd(&a.support[s_base[ks[j]] + W + (uint32_t)j * WAVE + ln], 1u);
-                                if (nb <= (uint32_t)NV_MAX) {   // w's slot in N+(v), flushed per vertex
-                                    uint32_t lo3 = 0, hi3 = nb - 1;
-                                    while (lo3 < hi3) {
-                                        const uint32_t mid = (lo3 + hi3) >> 1;
-                                        if (s_nv[mid] < w) lo3 = mid + 1;
-                                        else hi3 = mid;
+                        for (int j = 0; j < UNROLL; ++j) {
+                            const uint32_t x = xs[j];
+                            if ((hm >> j) & 1u) {
+                                atomicAdd(&s_cnt[ks[j]], 1u);
+                                if (GATHER) {
+                                    const uint32_t w = x + wlo;
+                                    if (a.support)   // edge (u, w): the tail element's own position
+                                        atomicAdd(&a.support[s_base[ks[j]] + W + (uint32_t)j * WAVE + ln], 1u);
+                                    if (nb <= (uint32_t)NV_MAX) {   // w's slot in N+(v), flushed per vertex
+                                        uint32_t lo3 = 0, hi3 = nb - 1;
+                                        while (lo3 < hi3) {
+                                            const uint32_t mid = (lo3 + hi3) >> 1;
+                                            if (s_nv[mid] < w) lo3 = mid + 1;
+                                            else hi3 = mid;
+                                        }
+                                        atomicAdd(&s_wc[lo3], 1u);
+                                    } else {
+                                        hit_vertex(a, w);
+                                        if (a.support) atomicAdd(&a.support[b0 + find_pos(a.col + b0, nb, w)], 1u);
                                     }
-                                    atomicAdd(&s_wc[lo3], 1u);
-                                } else {
-                                    hit_vertex(a, w);
-                                    if (a.support) atomicAdd(&a.support[b0 + find_pos(a.col + b0, nb, w)], 1u);
                                 }
                             }
                         }
                     }
+                    __syncthreads();   // the table is rebuilt for the next chunk
                 }
                 __syncthreads();
                 for (uint32_t j = threadIdx.x; j < nb; j += IS_NT) {

@@ -53,8 +53,10 @@ struct RunResult {
 };
 
 hipError_t run_pipeline(const RunArgs& r, RunResult* out);
-// Copies T and the range flag of a finished run to result[0..1] (device).
-void publish_result(const Ctrl* ctrl, uint64_t* result, uint64_t range_status, hipStream_t s);
+// Copies T and the status of a finished run to result[0..1] (device): range_status
+// for an id out of range, internal_status for a violated internal bound, else 0.
+void publish_result(const Ctrl* ctrl, uint64_t* result, uint64_t range_status, uint64_t internal_status,
+                    hipStream_t s);
 
 // ---- batched counting (batch.hip)
 struct BatchLayout {

@@ -17,6 +17,7 @@
 //   finish    map per-vertex / per-edge outputs back to original ids
 // No stage relies on atomics to one address: compaction and grouping go
 // through sorts and scans, so every intermediate array is deterministic.
+#include <math.h>
 #include <string.h>
 
 #include "common.h"
@@ -176,25 +177,39 @@ __global__ __launch_bounds__(NT) void k_unique_write(const uint64_t* __restrict_
 }
 
 // ------------------------------------------------------------------ CSC (in-edges grouped by v)
-// Key = v << 32 | e for in-edges with work; others get v = n and sort last.
+// Key of an in-edge e = (u -> v) with work: v in the bits above sh, then e, and
+// (packed form, lbits > 0) the tail length in the low lbits bits; others get
+// v = n and sort last. The tail length is below sqrt(2E): an out-neighbour w
+// of u has at least u's input degree, which is at least d+(u), so
+// d+(u)^2 <= sum of input degrees <= 2E. Packing it saves the later gather of
+// the row end of u. A length that does not fit sets error bit 1.
 __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ col, const uint32_t* __restrict__ src,
-                                                 const uint32_t* __restrict__ off, const Ctrl* ctrl, int32_t n,
-                                                 uint64_t* __restrict__ keys) {
+                                                 const uint32_t* __restrict__ off, Ctrl* ctrl, int32_t n,
+                                                 uint64_t* __restrict__ keys, int sh, int lbits) {
     const uint32_t m = ctrl->m;
+    bool bad = false;
     for (uint64_t e = (uint64_t)blockIdx.x * NT + threadIdx.x; e < m; e += (uint64_t)gridDim.x * NT) {
         const uint32_t v = col[e];
-        const bool work = (e + 1 < off[src[e] + 1]) && (off[v + 1] > off[v]);
-        keys[e] = ((uint64_t)(work ? v : (uint32_t)n) << 32) | (uint32_t)e;
+        const uint32_t end = off[src[e] + 1];
+        const bool work = (e + 1 < end) && (off[v + 1] > off[v]);
+        uint64_t low = e;
+        if (lbits > 0) {
+            const uint64_t len = work ? end - (e + 1) : 0u;
+            bad |= len >> lbits != 0;
+            low = (low << lbits) | (len & ((1ull << lbits) - 1ull));
+        }
+        keys[e] = ((uint64_t)(work ? v : (uint32_t)n) << sh) | low;
     }
+    if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, 2u);
 }
 
 // inend[v] = one past the last in-edge of v in the sorted order; m_active.
 __global__ __launch_bounds__(NT) void k_csc_bounds(const uint64_t* __restrict__ keys, Ctrl* ctrl, int32_t n,
-                                                   uint32_t* __restrict__ inend) {
+                                                   uint32_t* __restrict__ inend, int sh) {
     const uint32_t m = ctrl->m;
     for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < m; i += (uint64_t)gridDim.x * NT) {
-        const uint32_t v = (uint32_t)(keys[i] >> 32);
-        const uint32_t vn = i + 1 < m ? (uint32_t)(keys[i + 1] >> 32) : (uint32_t)n;
+        const uint32_t v = (uint32_t)(keys[i] >> sh);
+        const uint32_t vn = i + 1 < m ? (uint32_t)(keys[i + 1] >> sh) : (uint32_t)n;
         if (v < (uint32_t)n && vn != v) {
             inend[v] = (uint32_t)(i + 1);
             if (vn == (uint32_t)n) ctrl->m_active = (uint32_t)(i + 1);
@@ -202,15 +217,23 @@ __global__ __launch_bounds__(NT) void k_csc_bounds(const uint64_t* __restrict__ 
     }
 }
 
-// In place, after the bounds are known: entry v << 32 | e becomes the tail
-// range of edge e, start (e + 1) | end << 32, so a kernel reads it in one load.
+// In place, after the bounds are known: each key becomes the tail range of its
+// edge e, start (e + 1) | end << 32, so a kernel reads it in one load. Packed
+// keys carry the length; otherwise the row end of u is gathered.
 __global__ __launch_bounds__(NT) void k_csc_expand(uint64_t* __restrict__ csc, const Ctrl* ctrl,
                                                    const uint32_t* __restrict__ src,
-                                                   const uint32_t* __restrict__ off) {
+                                                   const uint32_t* __restrict__ off, int ebits, int lbits) {
     const uint32_t ma = ctrl->m_active;
+    const uint64_t emask = (1ull << ebits) - 1ull, lmask = (1ull << lbits) - 1ull;
     for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < ma; i += (uint64_t)gridDim.x * NT) {
-        const uint32_t e = (uint32_t)csc[i];
-        csc[i] = (uint64_t)(e + 1u) | ((uint64_t)off[src[e] + 1] << 32);
+        const uint64_t key = csc[i];
+        if (lbits > 0) {
+            const uint32_t e = (uint32_t)((key >> lbits) & emask);
+            csc[i] = (uint64_t)(e + 1u) | ((uint64_t)(e + 1u + (uint32_t)(key & lmask)) << 32);
+        } else {
+            const uint32_t e = (uint32_t)key;
+            csc[i] = (uint64_t)(e + 1u) | ((uint64_t)off[src[e] + 1] << 32);
+        }
     }
 }
 
@@ -464,15 +487,31 @@ __global__ void k_set_tile_range(Ctrl* ctrl, int ker, uint32_t t0, uint32_t t1) 
 }
 
 // result[0] = T, result[1] = range_status when an id was out of range, else 0.
-__global__ void k_publish(const Ctrl* ctrl, uint64_t* result, uint64_t range_status) {
+__global__ void k_publish(const Ctrl* ctrl, uint64_t* result, uint64_t range_status, uint64_t internal_status) {
     if (threadIdx.x == 0) {
         result[0] = ctrl->total;
-        result[1] = (ctrl->err & 1u) ? range_status : 0ull;
+        result[1] = (ctrl->err & 1u) ? range_status : (ctrl->err ? internal_status : 0ull);
     }
 }
 
-void publish_result(const Ctrl* ctrl, uint64_t* result, uint64_t range_status, hipStream_t s) {
-    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, ctrl, result, range_status);
+void publish_result(const Ctrl* ctrl, uint64_t* result, uint64_t range_status, uint64_t internal_status,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, ctrl, result, range_status, internal_status);
+}
+
+// Packed in-edge keys when v, e and the tail length fit in 64 bits.
+struct CscPacking {
+    int sh, ebits, lbits;
+};
+
+static CscPacking csc_packing(int64_t E, int32_t n) {
+    const uint64_t twoE = 2ull * (uint64_t)E;
+    uint64_t r = (uint64_t)sqrt((double)twoE);   // floor(sqrt(2E)), the bound on d+(u)
+    while (r * r > twoE) --r;
+    while ((r + 1) * (r + 1) <= twoE) ++r;
+    const int eb = bits_for((uint64_t)E), lb = bits_for(r + 1), vb = bits_for((uint64_t)n + 1);
+    if (vb + eb + lb <= 64) return {eb + lb, eb, lb};
+    return {32, 32, 0};
 }
 
 // ------------------------------------------------------------------ workspace layout
@@ -646,15 +685,19 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         return hipGetLastError();
     }
     // ---- CSC: in-edges with work grouped by v (the sorted pair keys are free now)
-    hipLaunchKernelGGL(k_csc_keys, dim3(grid_for((size_t)E)), dim3(NT), 0, s, col, src, off, ctrl, n, other);
     const int nbv = bits_for((uint64_t)n + 1);
-    const int alt2 = radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, 32, 32 + nbv, radix_tmp, s);
+    const CscPacking pk = csc_packing(E, n);
+    hipLaunchKernelGGL(k_csc_keys, dim3(grid_for((size_t)E)), dim3(NT), 0, s, col, src, off, ctrl, n, other, pk.sh,
+                       pk.lbits);
+    const int alt2 =
+        radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, pk.sh, pk.sh + nbv, radix_tmp, s);
     uint64_t* csc = alt2 ? sorted : other;
     fill_u32(rowend, 0u, (size_t)n, s);
-    hipLaunchKernelGGL(k_csc_bounds, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, n, rowend);
+    hipLaunchKernelGGL(k_csc_bounds, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, n, rowend, pk.sh);
     fill_u32(inoff, 0u, 1, s);
     scan_inclusive_max_u32(rowend, inoff + 1, (size_t)n, scan_tmp, s);
-    hipLaunchKernelGGL(k_csc_expand, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, src, off);
+    hipLaunchKernelGGL(k_csc_expand, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, src, off, pk.ebits,
+                       pk.lbits);
     mark(6);
     // ---- buckets + selection
     hipLaunchKernelGGL(k_vbucket, dim3(grid_for((size_t)n, 2048)), dim3(NT), 0, s, off, inoff, n, vbucket, ctrl);
