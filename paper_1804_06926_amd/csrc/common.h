@@ -9,7 +9,9 @@ namespace tcx {
 constexpr int WAVE = 64;
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
-__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x / WAVE); }
+// Uniform across the wave; readfirstlane lets the compiler keep values derived
+// from it in scalar registers.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)); }
 
 // Bit mask of the lanes below the calling lane.
 __device__ __forceinline__ uint64_t lanes_below() {

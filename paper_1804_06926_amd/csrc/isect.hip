@@ -32,6 +32,7 @@ constexpr uint32_t BM_BITS = BM_WORDS * 32u;
 constexpr int STAGE_MAX = 4096;           // N+(v) staged in LDS by merge/bsearch when it fits
 constexpr int UNROLL = 8;                 // bitmap kernel: tail loads in flight per lane
 constexpr uint32_t WT_MAX = 2048;         // bitmap kernel: 64-item windows per chunk of the item range
+constexpr uint32_t LONG_TAIL = 64;        // bitmap kernel: tails of at least one window are walked directly
 constexpr int NV_MAX = 2048;              // bitmap kernel, per-vertex mode: N+(v) kept for t[w] gathering
 constexpr int PARTIALS_PER_KERNEL = 4096; // max blocks per intersection launch
 
@@ -150,19 +151,42 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
             const uint32_t ne = S.pref[sg + 1] - S.pref[sg];
             const uint32_t b0 = a.off[v], b1 = a.off[v + 1];
             const uint32_t nb = b1 - b0;
-            // entry table: tail start and exclusive prefix of tail lengths
-            // (ne <= CHUNK_MAX = 2 * IS_NT, so two scans cover it)
-            uint32_t carry = 0;
+            // entry table: tail base and exclusive prefix of tail lengths, long
+            // tails (at least one window of items) first, then the short ones;
+            // entry order inside a vertex is free (ne <= CHUNK_MAX = 2 * IS_NT,
+            // so two block scans cover each pass)
+            uint32_t st_h[CHUNK_MAX / IS_NT], len_h[CHUNK_MAX / IS_NT], lb_h[CHUNK_MAX / IS_NT];
+            uint32_t nl = 0;   // long entries
 #pragma unroll
             for (int h = 0; h < CHUNK_MAX / IS_NT; ++h) {
                 const uint32_t k = h * IS_NT + threadIdx.x;
-                uint32_t len = 0, st = 0;
+                st_h[h] = len_h[h] = 0;
                 if (k < ne) {
                     const uint64_t ent = a.csc[e0 + k];   // tail start | tail end << 32
-                    st = (uint32_t)ent;
-                    len = (uint32_t)(ent >> 32) - st;
-                    if (need_cnt) s_cnt[k] = 0;
+                    st_h[h] = (uint32_t)ent;
+                    len_h[h] = (uint32_t)(ent >> 32) - st_h[h];
                 }
+                uint32_t total;
+                lb_h[h] = nl + block_exclusive_scan<IS_NT>(len_h[h] >= LONG_TAIL ? 1u : 0u, S.scratch, &total);
+                nl += total;
+            }
+#pragma unroll
+            for (int h = 0; h < CHUNK_MAX / IS_NT; ++h) {   // lengths and starts in entry order
+                const uint32_t k = h * IS_NT + threadIdx.x;
+                if (k < ne) {
+                    const uint32_t pos = len_h[h] >= LONG_TAIL ? lb_h[h] : nl + (k - lb_h[h]);
+                    s_pref[pos] = len_h[h];
+                    s_base[pos] = st_h[h];
+                    if (need_cnt) s_cnt[pos] = 0;
+                }
+            }
+            __syncthreads();
+            uint32_t carry = 0;
+#pragma unroll
+            for (int h = 0; h < CHUNK_MAX / IS_NT; ++h) {   // in place: each thread rewrites its own slots
+                const uint32_t k = h * IS_NT + threadIdx.x;
+                const uint32_t len = k < ne ? s_pref[k] : 0u;
+                const uint32_t st = k < ne ? s_base[k] : 0u;
                 uint32_t total;
                 const uint32_t excl = block_exclusive_scan<IS_NT>(len, S.scratch, &total);
                 if (k < ne) {
@@ -202,8 +226,11 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                 // slot array); read the slots back as a ballot mask, so that a lane's
                 // entry is first + (starts at or before its offset); issue the tail
                 // loads, unconditional (lanes past the end read a valid address);
-                // test the bitmap.
+                // test the bitmap. Rounds that lie inside the long tails (placed
+                // first) skip the marks: there an entry spans at least one window,
+                // so one compare with the next entry's start gives a lane's entry.
                 const uint32_t wv = (uint32_t)wave_id(), ln = (uint32_t)lane_id();
+                const uint32_t Llong = s_pref[nl];   // items of the long tails: [0, Llong)
                 for (uint32_t c0 = 0; c0 < L; c0 += WT_MAX * WAVE) {
                     const uint32_t c1 = L - c0 < WT_MAX * WAVE ? L : c0 + WT_MAX * WAVE;
                     const uint32_t nwc = (c1 - c0 + WAVE - 1) / WAVE;   // windows in this chunk
@@ -219,6 +246,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                     const uint32_t q0 = c0 + WAVE * ((span * wv) / (IS_NT / WAVE));
                     const uint32_t qe = c0 + WAVE * ((span * (wv + 1)) / (IS_NT / WAVE));
                     const uint32_t q1 = qe < c1 ? qe : c1;
+                    const uint32_t lim = Llong < q1 ? Llong : q1;   // rounds below lim see long tails only
                     for (uint32_t W = q0; W < q1; W += WAVE * UNROLL) {
                         uint32_t xs[UNROLL], ks[UNROLL], kj[UNROLL];
 #pragma unroll
@@ -226,65 +254,77 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                             const uint32_t wi = (W - c0) / WAVE + (uint32_t)j;
                             kj[j] = s_wst[wi < nwc ? wi : nwc - 1u];
                         }
-                        // mark the starts (pref is strictly increasing, so the marked offsets
-                        // are distinct and at least 1). Entries past the last one read
-                        // pref[ne] = L: a start at or after item L moves only lanes whose
-                        // items lie beyond q1 (unused).
-                        uint32_t o[UNROLL];
+                        if (W + WAVE * UNROLL <= lim) {
+                            // long tails only: an entry spans at least one window, so at most
+                            // one entry starts inside a window; a lane's entry is the window's
+                            // first entry, plus one at or after the next start
 #pragma unroll
-                        for (int j = 0; j < UNROLL; ++j) {
-                            const uint32_t kk = kj[j] + 1u + ln;
-                            o[j] = s_pref[kk < ne ? kk : ne] - (W + j * WAVE);
+                            for (int j = 0; j < UNROLL; ++j) {
+                                const uint32_t nx = s_pref[kj[j] + 1u];
+                                ks[j] = kj[j] + (W + j * WAVE + ln >= nx ? 1u : 0u);
+                            }
+                            uint32_t ad[UNROLL];
+#pragma unroll
+                            for (int j = 0; j < UNROLL; ++j) ad[j] = s_base[ks[j]] + W + j * WAVE + ln;
+#pragma unroll
+                            for (int j = 0; j < UNROLL; ++j) xs[j] = a.col[ad[j]] - wlo;
+                        } else {
+                            // mark the starts (pref is strictly increasing, so the marked offsets
+                            // are distinct and at least 1). Entries past the last one read
+                            // pref[ne] = L: a start at or after item L moves only lanes whose
+                            // items lie beyond q1 (unused).
+                            uint32_t o[UNROLL];
+    #pragma unroll
+                            for (int j = 0; j < UNROLL; ++j) {
+                                const uint32_t kk = kj[j] + 1u + ln;
+                                o[j] = s_pref[kk < ne ? kk : ne] - (W + j * WAVE);
+                            }
+    #pragma unroll
+                            for (int j = 0; j < UNROLL; ++j)
+                                if (o[j] < 64u) s_flag[wv][j][o[j]] = 1;
+                            // the lanes of the wave exchange marks through LDS: keep the
+                            // mark / read / clear phases in program order
+                            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                            uint32_t f[UNROLL];
+    #pragma unroll
+                            for (int j = 0; j < UNROLL; ++j) f[j] = s_flag[wv][j][ln];
+    #pragma unroll
+                            for (int j = 0; j < UNROLL; ++j) s_flag[wv][j][ln] = 0;   // each lane clears its own slot
+                            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    #pragma unroll
+                            for (int j = 0; j < UNROLL; ++j) {
+                                const uint64_t M = __ballot(f[j] != 0u);
+                                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                                    (uint32_t)(M >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u));
+                                ks[j] = kj[j] + below + (f[j] != 0u ? 1u : 0u);
+                            }
+                            uint32_t ad[UNROLL];
+    #pragma unroll
+                            for (int j = 0; j < UNROLL; ++j) {
+                                const uint32_t q = W + j * WAVE + ln;
+                                const uint32_t sb = s_base[ks[j]];
+                                ad[j] = q < q1 ? sb + q : b0;
+                            }
+    #pragma unroll
+                            for (int j = 0; j < UNROLL; ++j) xs[j] = a.col[ad[j]];
+    #pragma unroll
+                            for (int j = 0; j < UNROLL; ++j)
+                                xs[j] = (W + j * WAVE + ln < q1) ? xs[j] - wlo : 0xFFFFFFFFu;
                         }
-#pragma unroll
-                        for (int j = 0; j < UNROLL; ++j)
-                            if (o[j] < 64u) s_flag[wv][j][o[j]] = 1;
-                        // the lanes of the wave exchange marks through LDS: keep the
-                        // mark / read / clear phases in program order
-                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                        uint32_t f[UNROLL];
-#pragma unroll
-                        for (int j = 0; j < UNROLL; ++j) f[j] = s_flag[wv][j][ln];
-#pragma unroll
-                        for (int j = 0; j < UNROLL; ++j) s_flag[wv][j][ln] = 0;   // each lane clears its own slot
-                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-#pragma unroll
-                        for (int j = 0; j < UNROLL; ++j) {
-                            const uint64_t M = __ballot(f[j] != 0u);
-                            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                                (uint32_t)(M >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)M, 0u));
-                            ks[j] = kj[j] + below + (f[j] != 0u ? 1u : 0u);
-                        }
-                        uint32_t ad[UNROLL];
-#pragma unroll
-                        for (int j = 0; j < UNROLL; ++j) {
-                            const uint32_t q = W + j * WAVE + ln;
-                            const uint32_t sb = s_base[ks[j]];
-                            ad[j] = q < q1 ? sb + q : b0;
-                        }
-#pragma unroll
-                        for (int j = 0; j < UNROLL; ++j) xs[j] = a.col[ad[j]];
-#pragma unroll
-                        for (int j = 0; j < UNROLL; ++j)
-                            xs[j] = (W + j * WAVE + ln < q1) ? xs[j] - wlo : 0xFFFFFFFFu;
                         // membership: bit positions past the window map to the spare
                         // always-zero word bm[BM_WORDS]
                         uint32_t wd[UNROLL];
 #pragma unroll
                         for (int j = 0; j < UNROLL; ++j) wd[j] = bm[(xs[j] < BM_BITS ? xs[j] : BM_BITS) >> 5];
-                        uint32_t hits = 0, hm = 0;
+                        uint32_t hits = 0;
 #pragma unroll
-                        for (int j = 0; j < UNROLL; ++j) {
-                            const uint32_t h = (wd[j] >> (xs[j] & 31u)) & 1u;
-                            hits += h;
-                            hm |= h << j;
-                        }
+                        for (int j = 0; j < UNROLL; ++j) hits += (wd[j] >> (xs[j] & 31u)) & 1u;
                         acc += hits;
                         if (!need_cnt) continue;
 #pragma unroll
                         for (int j = 0; j < UNROLL; ++j) {
                             const uint32_t x = xs[j];
-                            if ((hm >> j) & 1u) {
+                            if ((wd[j] >> (x & 31u)) & 1u) {
                                 atomicAdd(&s_cnt[ks[j]], 1u);
                                 if (GATHER) {
                                     const uint32_t w = x + wlo;
