@@ -197,6 +197,8 @@ def main(argv=None):
     ap.add_argument("--select", default="heuristic", choices=["heuristic", "learned", "merge", "bsearch", "bitmap"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle equality check")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-selector comparison (profiling runs: one selection mode only)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (calibrates counter-based traffic)")
     args = ap.parse_args(argv)
@@ -285,7 +287,7 @@ def main(argv=None):
         "tail_elements": tail_sum,
         "effective_gbps_merge_formulation": balg / (isect_ms * 1e-3) / 1e9 if isect_ms > 0 else None,
     }
-    if have_weights and args.select == "heuristic":
+    if have_weights and args.select == "heuristic" and not args.no_learned:
         # the learned selector against the heuristic on the same graph, counts equal
         for _ in range(2):
             T_l = tc.count_triangles(d_edges, n, select=tc.SELECT_LEARNED)
