@@ -165,7 +165,7 @@ tc_status run(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* w
         ctx->have_times = 1;
     }
     if (ctx->h_ctrl->err & 1u) return arg_fail(ctx, TC_ERR_VERTEX_RANGE, "vertex id outside [0, num_vertices)");
-    if (ctx->h_ctrl->err) return arg_fail(ctx, TC_ERR_HIP, "internal bound violated (tail length or sort wait)");
+    if (ctx->h_ctrl->err) return arg_fail(ctx, TC_ERR_HIP, "internal bound violated (tail length)");
     return TC_OK;
 }
 
@@ -359,16 +359,12 @@ tc_status tc_radix_sort_u64(tc_ctx* ctx, uint64_t* d_keys, uint64_t* d_keys_alt,
         return arg_fail(ctx, TC_ERR_WORKSPACE, "workspace too small");
     DeviceGuard guard(ctx->device);
     const int alt = tcx::radix_sort_u64(d_keys, d_keys_alt, nullptr, nullptr, nullptr, (size_t)count, bit_lo, bit_hi,
-                                        d_workspace, ctx->stream, nullptr);
+                                        d_workspace, ctx->stream);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && alt)
         e = hipMemcpyAsync(d_keys, d_keys_alt, sizeof(uint64_t) * (size_t)count, hipMemcpyDeviceToDevice, ctx->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(&ctx->h_ctrl->err, tcx::radix_err_word(d_workspace, (size_t)count), sizeof(uint32_t),
-                           hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "radix sort");
-    if (ctx->h_ctrl->err) return arg_fail(ctx, TC_ERR_HIP, "internal bound violated (sort wait)");
     return TC_OK;
 }
 
@@ -501,7 +497,7 @@ tc_status tc_count_triangles_batch(tc_ctx* ctx, const int32_t* d_edges, const in
     if (e != hipSuccess) return hip_fail(ctx, e, "read batch counts");
     ctx->have_times = 0;
     if (ctx->h_ctrl->err & 1u) return arg_fail(ctx, TC_ERR_VERTEX_RANGE, "vertex id outside its graph's range");
-    if (ctx->h_ctrl->err) return arg_fail(ctx, TC_ERR_HIP, "internal bound violated (tail length or sort wait)");
+    if (ctx->h_ctrl->err) return arg_fail(ctx, TC_ERR_HIP, "internal bound violated (tail length)");
     memcpy(h_counts, ctx->h_counts_pinned, sizeof(uint64_t) * (size_t)num_graphs);
     return TC_OK;
 }

@@ -19,14 +19,11 @@ void scan_exclusive_sum_u64(const uint64_t* in, uint64_t* out, size_t len, void*
 size_t radix_temp_bytes(size_t cap);
 // Stable LSD sort of keys on bits [bit_lo, bit_hi), 8 bits per pass, optional
 // uint32 payload. The count is read from d_count on the device (nullptr: cap).
-// Returns 1 when the sorted data ended up in the *_alt buffers. err (device,
-// may be null: a word inside temp, see radix_err_word) receives bit 2 when a
-// look-back wait exceeded its bound.
+// Returns 1 when the sorted data ended up in the *_alt buffers.
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, uint32_t* err);
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s);
 int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, uint32_t* err);
-uint32_t* radix_err_word(void* temp, size_t cap);
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s);
 
 // ---- control block shared by all stages (device memory, zeroed per call)
 constexpr int NBUCKET = 256;          // degree-pair buckets; 255 = no work

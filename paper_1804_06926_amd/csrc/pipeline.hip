@@ -637,7 +637,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         uint32_t* ep_alt = (uint32_t*)keysB;
         hipLaunchKernelGGL(k_endpoints, dim3(grid_for((size_t)E)), dim3(NT), 0, s, edges, (uint64_t)E, n, ep, ctrl);
         const int a0 = radix_sort_u32(ep, ep_alt, nullptr, nullptr, nullptr, (size_t)(2 * E), 0,
-                                      bits_for((uint64_t)n + 1), radix_tmp, s, &ctrl->err);
+                                      bits_for((uint64_t)n + 1), radix_tmp, s);
         fill_u32(rowend, 0u, (size_t)n, s);
         hipLaunchKernelGGL(k_endpoint_bounds, dim3(grid_for((size_t)(2 * E))), dim3(NT), 0, s, a0 ? ep_alt : ep,
                            (uint64_t)(2 * E), n, rowend);
@@ -650,7 +650,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     {
         const int dbits = bits_for((uint64_t)2 * (uint64_t)E + 1);
         const int alt = radix_sort_u64(vkeysA, vkeysB, nullptr, nullptr, nullptr, (size_t)n, 32, 32 + dbits,
-                                       radix_tmp, s, &ctrl->err);
+                                       radix_tmp, s);
         hipLaunchKernelGGL(k_rank, dim3(grid_for((size_t)n)), dim3(NT), 0, s, alt ? vkeysB : vkeysA, n, rank, inv);
     }
     mark(2);
@@ -661,8 +661,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
                        keysA);
     mark(3);
     // ---- sort oriented pairs
-    const int alt = radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)E, 0, 2 * nb, radix_tmp, s,
-                                   &ctrl->err);
+    const int alt = radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)E, 0, 2 * nb, radix_tmp, s);
     uint64_t* sorted = alt ? keysB : keysA;
     uint64_t* other = alt ? keysA : keysB;
     mark(4);
@@ -691,8 +690,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     hipLaunchKernelGGL(k_csc_keys, dim3(grid_for((size_t)E)), dim3(NT), 0, s, col, src, off, ctrl, n, other, pk.sh,
                        pk.lbits);
     const int alt2 =
-        radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, pk.sh, pk.sh + nbv, radix_tmp, s,
-                       &ctrl->err);
+        radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, pk.sh, pk.sh + nbv, radix_tmp, s);
     uint64_t* csc = alt2 ? sorted : other;
     fill_u32(rowend, 0u, (size_t)n, s);
     hipLaunchKernelGGL(k_csc_bounds, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, n, rowend, pk.sh);
@@ -712,8 +710,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     // ---- group: order vertices by (kernel, bucket); tiles
     hipLaunchKernelGGL(k_vkeys_slot, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vbucket, n, ctrl, vkeysA);
     {
-        const int a3 = radix_sort_u64(vkeysA, vkeysB, nullptr, nullptr, nullptr, (size_t)n, 32, 40, radix_tmp, s,
-                                      &ctrl->err);
+        const int a3 = radix_sort_u64(vkeysA, vkeysB, nullptr, nullptr, nullptr, (size_t)n, 32, 40, radix_tmp, s);
         hipLaunchKernelGGL(k_vpos, dim3(grid_for((size_t)n)), dim3(NT), 0, s, a3 ? vkeysB : vkeysA, n, vbucket, ctrl,
                            vlist);
     }

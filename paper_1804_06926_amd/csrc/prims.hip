@@ -3,8 +3,9 @@
 // The radix sort is the CSR builder of the method's "induced subgraph" step
 // (Section 4.2, optimisations for edge list generation): edges are sorted
 // by (source, destination) so every row of the filtered graph is contiguous
-// and ascending. Keys are sorted 8 bits per pass, one kernel per pass (see
-// the radix sort section).
+// and ascending. Keys are sorted 8 bits per pass; a pass is a per-tile digit
+// histogram, an exclusive scan of the digit-major histogram, and a stable
+// scatter that ranks equal digits inside each wave with ballots.
 #include "common.h"
 #include "internal.h"
 
@@ -201,75 +202,98 @@ void scan_exclusive_sum_u64(const uint64_t* in, uint64_t* out, size_t len, void*
 }
 
 // ------------------------------------------------------------------ radix sort
-// LSD, 8-bit digits, one kernel per pass ("onesweep"): the digit totals of
-// all passes come from one read of the keys; in a pass, each tile of 2048 keys
-// takes a ticket in launch order, ranks its keys (ballot-matched digits,
-// stable), publishes its per-digit counts, and finds the keys of each digit in
-// all earlier tiles by looking back over their published counts (decoupled
-// look-back). A tile only waits for tiles with smaller tickets, which are
-// already running, and publishes its own counts before it waits, so every
-// wait ends; the wait is also bounded, and exceeding the bound sets err bit 2.
 constexpr int RS_NT = 256;
 constexpr int RS_WAVES = RS_NT / WAVE;
 constexpr int RS_ITEMS = 8;                     // per lane
 constexpr int RS_TILE = RS_NT * RS_ITEMS;       // 2048 keys per tile
 constexpr int RS_WAVE_SPAN = WAVE * RS_ITEMS;   // 512 keys per wave, striped by lane
-constexpr int RS_MAX_PASS = 8;
-constexpr uint64_t OS_AGG = 1ull << 62;         // status flag: the tile's own count
-constexpr uint64_t OS_PRE = 2ull << 62;         // status flag: inclusive count over tiles 0..t
-constexpr uint64_t OS_VAL = (1ull << 62) - 1ull;
-constexpr uint32_t OS_SPIN_MAX = 1u << 20;
 
 __device__ __forceinline__ uint32_t rs_count(const uint32_t* d_count, uint32_t cap) {
     const uint32_t c = d_count ? *d_count : cap;
     return c < cap ? c : cap;
 }
 
-// Digit totals of every pass: tot[p * 256 + d] (zeroed beforehand).
+// Per-tile digit counts, written digit-major: hist[d * ntiles + tile].
 template <typename KeyT>
-__global__ __launch_bounds__(RS_NT) void k_radix_totals(const KeyT* __restrict__ keys, const uint32_t* d_count,
-                                                        uint32_t cap, int bit_lo, int bit_hi,
-                                                        uint32_t* __restrict__ tot) {
-    __shared__ uint32_t h[RS_MAX_PASS * 256];
-    const int npass = (bit_hi - bit_lo + 7) / 8;
-    for (int i = threadIdx.x; i < npass * 256; i += RS_NT) h[i] = 0;
+__global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ keys, const uint32_t* d_count,
+                                                      uint32_t cap, int shift, uint32_t dmask,
+                                                      uint32_t* __restrict__ hist,
+                                                      uint32_t ntiles) {
+    __shared__ uint32_t wcnt[RS_WAVES][256];
+    for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const uint32_t n = rs_count(d_count, cap);
-    for (uint32_t i = blockIdx.x * RS_NT + threadIdx.x; i < n; i += gridDim.x * RS_NT) {
-        const KeyT k = keys[i];
-        for (int p = 0; p < npass; ++p) {
-            const int sh = bit_lo + 8 * p;
-            const int db = bit_hi - sh < 8 ? bit_hi - sh : 8;
-            atomicAdd(&h[p * 256 + ((uint32_t)(k >> sh) & ((1u << db) - 1u))], 1u);
-        }
+    const int w = wave_id(), l = lane_id();
+    const uint32_t base = blockIdx.x * RS_TILE + w * RS_WAVE_SPAN;
+    uint32_t dg[RS_ITEMS];
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint32_t i = base + it * WAVE + l;
+        dg[it] = i < n ? (uint32_t)(keys[i] >> shift) & dmask : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint32_t i = base + it * WAVE + l;
+        const bool valid = i < n;
+        const uint32_t d = dg[it];
+        const uint64_t peers = match_digit8(d, __ballot(valid));
+        if (valid && (peers & lanes_below()) == 0) wcnt[w][d] += (uint32_t)__popcll(peers);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < npass * 256; i += RS_NT)
-        if (h[i]) atomicAdd(&tot[i], h[i]);
+    const int d = threadIdx.x;
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < RS_WAVES; ++k) t += wcnt[k][d];
+    hist[(size_t)d * ntiles + blockIdx.x] = t;
+}
+
+// One block per digit d: exclusive scan, in place, of the digit's row of tile
+// counts hist[d * ntiles .. +ntiles); the row total goes to digit_tot[d].
+constexpr int RS_ROW_ITEMS = 8;
+__global__ __launch_bounds__(RS_NT) void k_radix_rowscan(uint32_t* __restrict__ hist, uint32_t ntiles,
+                                                         uint32_t* __restrict__ digit_tot) {
+    __shared__ uint32_t scratch[RS_WAVES];
+    uint32_t* row = hist + (size_t)blockIdx.x * ntiles;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < ntiles; base += RS_NT * RS_ROW_ITEMS) {
+        const uint32_t i0 = base + threadIdx.x * RS_ROW_ITEMS;
+        uint32_t v[RS_ROW_ITEMS], sum = 0;
+#pragma unroll
+        for (int k = 0; k < RS_ROW_ITEMS; ++k) {
+            v[k] = i0 + k < ntiles ? row[i0 + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t total;
+        uint32_t run = carry + block_exclusive_scan<RS_NT>(sum, scratch, &total);
+#pragma unroll
+        for (int k = 0; k < RS_ROW_ITEMS; ++k) {
+            if (i0 + k < ntiles) row[i0 + k] = run;
+            run += v[k];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
 }
 
 template <typename KeyT, bool HAS_VAL>
-__global__ __launch_bounds__(RS_NT) void k_radix_onesweep(const KeyT* __restrict__ kin,
-                                                          const uint32_t* __restrict__ vin,
-                                                          KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                          const uint32_t* d_count, uint32_t cap, int shift,
-                                                          uint32_t dmask, const uint32_t* __restrict__ tot,
-                                                          uint64_t* status, uint32_t* ticket, uint32_t* err) {
+__global__ __launch_bounds__(RS_NT) void k_radix_scatter(const KeyT* __restrict__ kin,
+                                                         const uint32_t* __restrict__ vin,
+                                                         KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                         const uint32_t* d_count, uint32_t cap, int shift,
+                                                         uint32_t dmask,
+                                                         const uint32_t* __restrict__ hist_scan, uint32_t ntiles,
+                                                         const uint32_t* __restrict__ digit_tot) {
     __shared__ uint32_t wcnt[RS_WAVES][256];
     __shared__ uint32_t lstart[256];
     __shared__ uint32_t gbase[256];
     __shared__ uint32_t scratch[RS_WAVES];
-    __shared__ uint32_t s_tile;
     __shared__ KeyT skey[RS_TILE];
     __shared__ uint32_t sval[HAS_VAL ? RS_TILE : 1];
     for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
-    if (threadIdx.x == 0) s_tile = atomicAdd(ticket, 1u);
     __syncthreads();
     const uint32_t n = rs_count(d_count, cap);
-    const uint32_t t = s_tile;
-    const uint32_t tile0 = t * RS_TILE;
-    if (tile0 >= n) return;   // no keys here, and none in any later ticket
     const int w = wave_id(), l = lane_id();
+    const uint32_t tile0 = blockIdx.x * RS_TILE;
     const uint32_t base = tile0 + w * RS_WAVE_SPAN;
     KeyT k[RS_ITEMS];
     uint32_t v[RS_ITEMS];
@@ -305,38 +329,11 @@ __global__ __launch_bounds__(RS_NT) void k_radix_onesweep(const KeyT* __restrict
             wcnt[q][d] = run;
             run += c;
         }
-        // publish this tile's count of digit d, then look back for the earlier tiles'
-        uint64_t* st = status + (size_t)t * 256 + d;
-        if (t == 0) {
-            __hip_atomic_store(st, OS_PRE | run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(st, OS_AGG | run, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        uint64_t before = 0;
-        if (t > 0) {
-            uint32_t j = t - 1, spins = 0;
-            for (;;) {
-                const uint64_t sv =
-                    __hip_atomic_load(status + (size_t)j * 256 + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if ((sv >> 62) == 0) {
-                    if (++spins > OS_SPIN_MAX) {
-                        atomicOr(err, 4u);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                before += sv & OS_VAL;
-                if ((sv & OS_PRE) || j == 0) break;
-                --j;
-            }
-            __hip_atomic_store(st, OS_PRE | (before + run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
         const uint32_t excl = block_exclusive_scan<RS_NT>(run, scratch);
         lstart[d] = excl;
-        // digit base = keys with a smaller digit (all tiles) + keys of digit d in earlier tiles
-        const uint32_t dbase = block_exclusive_scan<RS_NT>(d <= (int)dmask ? tot[d] : 0u, scratch);
-        gbase[d] = dbase + (uint32_t)before;
+        // digit base = keys with a smaller digit; plus this tile's offset in its digit row
+        const uint32_t dbase = block_exclusive_scan<RS_NT>(digit_tot[d], scratch);
+        gbase[d] = dbase + hist_scan[(size_t)d * ntiles + blockIdx.x];
     }
     __syncthreads();
 #pragma unroll
@@ -350,80 +347,63 @@ __global__ __launch_bounds__(RS_NT) void k_radix_onesweep(const KeyT* __restrict
         }
     }
     __syncthreads();
-    const uint32_t tile_n = n - tile0 < (uint32_t)RS_TILE ? n - tile0 : (uint32_t)RS_TILE;
+    const uint32_t tile_n = n > tile0 ? (n - tile0 < (uint32_t)RS_TILE ? n - tile0 : (uint32_t)RS_TILE) : 0u;
     for (uint32_t j = threadIdx.x; j < tile_n; j += RS_NT) {
         const KeyT key = skey[j];
         const uint32_t d = (uint32_t)(key >> shift) & dmask;
         const uint32_t pos = gbase[d] + (j - lstart[d]);
-        if (pos < n) {   // always true when the counts are consistent
+        if (pos < n) {   // always true when the histogram scan is consistent
             kout[pos] = key;
             if (HAS_VAL) vout[pos] = sval[j];
         }
     }
 }
 
-// Temporary layout: status [ntiles * 256] u64 | totals [RS_MAX_PASS * 256] u32 |
-// tickets [RS_MAX_PASS] u32 | error word.
-static size_t rs_status_bytes(size_t cap) {
-    const size_t ntiles = (cap + RS_TILE - 1) / RS_TILE + 1;
-    return align_up(sizeof(uint64_t) * 256 * ntiles, 256);
-}
-
 size_t radix_temp_bytes(size_t cap) {
-    return rs_status_bytes(cap) + align_up(sizeof(uint32_t) * (RS_MAX_PASS * 256 + RS_MAX_PASS + 1), 256);
-}
-
-uint32_t* radix_err_word(void* temp, size_t cap) {
-    return (uint32_t*)((char*)temp + rs_status_bytes(cap)) + RS_MAX_PASS * 256 + RS_MAX_PASS;
+    const size_t ntiles = (cap + RS_TILE - 1) / RS_TILE + 1;
+    return align_up(sizeof(uint32_t) * 256 * ntiles, 256) + align_up(scan_temp_bytes(), 256);
 }
 
 template <typename KeyT>
 static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                      size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, uint32_t* err) {
+                      size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s) {
     if (cap == 0 || bit_hi <= bit_lo) return 0;
     const uint32_t ntiles = (uint32_t)((cap + RS_TILE - 1) / RS_TILE);
-    const int npass = (bit_hi - bit_lo + 7) / 8;
-    uint64_t* status = (uint64_t*)temp;
-    uint32_t* tot = (uint32_t*)((char*)temp + rs_status_bytes(cap));
-    uint32_t* tickets = tot + RS_MAX_PASS * 256;
-    if (!err) err = tickets + RS_MAX_PASS;
-    fill_u32(tot, 0u, (size_t)RS_MAX_PASS * 256 + RS_MAX_PASS + (err == tickets + RS_MAX_PASS ? 1 : 0), s);
-    {
-        const unsigned g = ntiles < 2048u ? ntiles : 2048u;
-        hipLaunchKernelGGL(k_radix_totals<KeyT>, dim3(g), dim3(RS_NT), 0, s, keys, d_count, (uint32_t)cap, bit_lo,
-                           bit_hi, tot);
-    }
+    uint32_t* hist = (uint32_t*)temp;
+    void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * ((cap + RS_TILE - 1) / RS_TILE + 1), 256);
+    uint32_t* digit_tot = (uint32_t*)scan_tmp;   // 256 digit totals
     KeyT* kin = keys;
     KeyT* kout = keys_alt;
     uint32_t* vin = vals;
     uint32_t* vout = vals_alt;
-    for (int p = 0; p < npass; ++p) {
-        const int shift = bit_lo + 8 * p;
+    int passes = 0;
+    for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
         const int dbits = bit_hi - shift < 8 ? bit_hi - shift : 8;   // the last digit may be narrower
         const uint32_t dmask = (1u << dbits) - 1u;
-        fill_u64(status, 0ull, (size_t)ntiles * 256, s);
+        hipLaunchKernelGGL(k_radix_hist<KeyT>, dim3(ntiles), dim3(RS_NT), 0, s, kin, d_count, (uint32_t)cap, shift,
+                           dmask, hist, ntiles);
+        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(RS_NT), 0, s, hist, ntiles, digit_tot);
         if (vals) {
-            hipLaunchKernelGGL((k_radix_onesweep<KeyT, true>), dim3(ntiles), dim3(RS_NT), 0, s, kin, vin, kout, vout,
-                               d_count, (uint32_t)cap, shift, dmask, tot + p * 256, status, tickets + p, err);
+            hipLaunchKernelGGL((k_radix_scatter<KeyT, true>), dim3(ntiles), dim3(RS_NT), 0, s, kin, vin, kout, vout,
+                               d_count, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot);
         } else {
-            hipLaunchKernelGGL((k_radix_onesweep<KeyT, false>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr, kout,
-                               nullptr, d_count, (uint32_t)cap, shift, dmask, tot + p * 256, status, tickets + p,
-                               err);
+            hipLaunchKernelGGL((k_radix_scatter<KeyT, false>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr, kout,
+                               nullptr, d_count, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot);
         }
         KeyT* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
     }
-    return npass & 1;   // 1: result is in keys_alt / vals_alt
+    return passes & 1;   // 1: result is in keys_alt / vals_alt
 }
 
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, uint32_t* err) {
-    return radix_sort<uint64_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s, err);
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s) {
+    return radix_sort<uint64_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s);
 }
 
 int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, uint32_t* err) {
-    return radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s, err);
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s) {
+    return radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s);
 }
 
 }  // namespace tcx
