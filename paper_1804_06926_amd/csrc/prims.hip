@@ -231,14 +231,10 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ k
         const uint32_t i = base + it * WAVE + l;
         dg[it] = i < n ? (uint32_t)(keys[i] >> shift) & dmask : 0u;
     }
+    // counts only (no ranks): one LDS atomic per key into the wave's histogram
 #pragma unroll
-    for (int it = 0; it < RS_ITEMS; ++it) {
-        const uint32_t i = base + it * WAVE + l;
-        const bool valid = i < n;
-        const uint32_t d = dg[it];
-        const uint64_t peers = match_digit8(d, __ballot(valid));
-        if (valid && (peers & lanes_below()) == 0) wcnt[w][d] += (uint32_t)__popcll(peers);
-    }
+    for (int it = 0; it < RS_ITEMS; ++it)
+        if (base + it * WAVE + l < n) atomicAdd(&wcnt[w][dg[it]], 1u);
     __syncthreads();
     const int d = threadIdx.x;
     uint32_t t = 0;
