@@ -245,7 +245,7 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ k
 
 // One block per digit d: exclusive scan, in place, of the digit's row of tile
 // counts hist[d * ntiles .. +ntiles); the row total goes to digit_tot[d].
-constexpr int RS_ROW_ITEMS = 8;
+constexpr int RS_ROW_ITEMS = 32;
 __global__ __launch_bounds__(RS_NT) void k_radix_rowscan(uint32_t* __restrict__ hist, uint32_t ntiles,
                                                          uint32_t* __restrict__ digit_tot) {
     __shared__ uint32_t scratch[RS_WAVES];
