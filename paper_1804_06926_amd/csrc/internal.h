@@ -24,6 +24,9 @@ int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t*
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s);
 int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s);
+// The 256 per-digit key counts of the last pass of the latest sort with this
+// temp and cap (device memory inside temp).
+const uint32_t* radix_last_digit_totals(const void* temp, size_t cap);
 
 // ---- control block shared by all stages (device memory, zeroed per call)
 constexpr int NBUCKET = 256;          // degree-pair buckets; 255 = no work

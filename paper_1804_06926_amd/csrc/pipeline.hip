@@ -38,21 +38,106 @@ static unsigned grid_for(size_t n, unsigned cap = 16384) {
 }
 
 // ------------------------------------------------------------------ degree
-// Degrees come from sorting the 2E endpoints (device-wide atomics would
-// serialise on hub vertices): loop-free valid pairs contribute both ends,
-// everything else the sentinel n, which sorts last.
+// Input degree = loop-free valid pairs per vertex. Device-wide atomics would
+// serialise on hub vertices, so the 2E endpoints are first partitioned by
+// their high bits (one radix pass when n <= 2^22), and each bucket of 2^bw
+// vertices is then counted in an LDS histogram. Endpoints of loops and
+// invalid pairs are written as `sentinel`; with sentinel = n - 1 each block
+// also records how many it wrote, and they are taken off vertex n - 1 at the
+// end. Larger n falls back to a full sort of the endpoints (sentinel n, which
+// sorts last) and run boundaries.
+constexpr int DEG_MAX_BW = 14;        // LDS histogram of 2^14 counters (64 KB)
+constexpr unsigned DEG_EP_BLOCKS = 1024;
+
 __global__ __launch_bounds__(NT) void k_endpoints(const int2* __restrict__ edges, uint64_t E, int32_t n,
-                                                  uint32_t* __restrict__ keys, Ctrl* ctrl) {
+                                                  uint32_t sentinel, uint32_t* __restrict__ keys, Ctrl* ctrl,
+                                                  uint32_t* __restrict__ nsent) {
+    __shared__ uint32_t red[NT / WAVE];
     bool bad = false;
+    uint32_t sent = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < E; i += (uint64_t)gridDim.x * NT) {
         const int2 e = edges[i];
         const bool in_range = e.x >= 0 && e.x < n && e.y >= 0 && e.y < n;
         bad |= !in_range;
         const bool ok = in_range && e.x != e.y;
-        keys[2 * i] = ok ? (uint32_t)e.x : (uint32_t)n;
-        keys[2 * i + 1] = ok ? (uint32_t)e.y : (uint32_t)n;
+        keys[2 * i] = ok ? (uint32_t)e.x : sentinel;
+        keys[2 * i + 1] = ok ? (uint32_t)e.y : sentinel;
+        sent += ok ? 0u : 2u;
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, 1u);
+    sent = wave_sum(sent);
+    if (lane_id() == 0) red[wave_id()] = sent;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int k = 0; k < NT / WAVE; ++k) t += red[k];
+        nsent[blockIdx.x] = t;
+    }
+}
+
+// bstart[b] = first position of bucket b in the partitioned endpoints (the
+// exclusive scan of the last pass's digit counts); bstart[nb] = 2E.
+__global__ __launch_bounds__(NT) void k_bucket_starts(const uint32_t* __restrict__ digit_tot, uint32_t nb,
+                                                      uint32_t total, uint32_t* __restrict__ bstart) {
+    __shared__ uint32_t scratch[NT / WAVE];
+    const uint32_t d = threadIdx.x;
+    const uint32_t c = (digit_tot && d < nb) ? digit_tot[d] : 0u;
+    const uint32_t ex = block_exclusive_scan<NT>(c, scratch);
+    if (d < nb) bstart[d] = digit_tot ? ex : 0u;
+    if (d == 0) bstart[nb] = total;
+}
+
+// Block (bucket b, split sp) counts its share of bucket b in LDS. One split:
+// plain stores of every count of the bucket; several: atomic adds into the
+// zeroed degree array.
+__global__ __launch_bounds__(NT) void k_bucket_count(const uint32_t* __restrict__ ep,
+                                                     const uint32_t* __restrict__ bstart, int bw, uint32_t splits,
+                                                     int32_t n, uint32_t* __restrict__ deg) {
+    extern __shared__ uint32_t h[];
+    const uint32_t nh = 1u << bw, mask = nh - 1u;
+    const uint32_t b = blockIdx.x / splits, sp = blockIdx.x % splits;
+    for (uint32_t j = threadIdx.x; j < nh; j += NT) h[j] = 0;
+    __syncthreads();
+    const uint32_t s0 = bstart[b], s1 = bstart[b + 1];
+    const uint32_t len = s1 - s0;
+    const uint32_t a0 = s0 + (uint32_t)(((uint64_t)len * sp) / splits);
+    const uint32_t a1 = s0 + (uint32_t)(((uint64_t)len * (sp + 1)) / splits);
+    constexpr int U = 8;
+    for (uint32_t i0 = a0; i0 < a1; i0 += NT * U) {
+        uint32_t x[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {   // loads in flight together
+            const uint32_t i = i0 + k * NT + threadIdx.x;
+            x[k] = i < a1 ? ep[i] : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            if (x[k] != 0xFFFFFFFFu) atomicAdd(&h[x[k] & mask], 1u);
+    }
+    __syncthreads();
+    const uint64_t v0 = (uint64_t)b << bw;
+    for (uint32_t j = threadIdx.x; j < nh; j += NT) {
+        const uint64_t v = v0 + j;
+        if (v >= (uint64_t)n) break;
+        if (splits == 1) deg[v] = h[j];
+        else if (h[j]) atomicAdd(&deg[v], h[j]);
+    }
+}
+
+// deg[n - 1] -= the sentinel endpoints written by k_endpoints.
+__global__ __launch_bounds__(NT) void k_drop_sentinels(const uint32_t* __restrict__ nsent, uint32_t nblocks,
+                                                       int32_t n, uint32_t* __restrict__ deg) {
+    __shared__ uint32_t red[NT / WAVE];
+    uint32_t t = 0;
+    for (uint32_t i = threadIdx.x; i < nblocks; i += NT) t += nsent[i];
+    t = wave_sum(t);
+    if (lane_id() == 0) red[wave_id()] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int k = 0; k < NT / WAVE; ++k) s += red[k];
+        deg[n - 1] -= s;
+    }
 }
 
 // dend[v] = one past the last occurrence of v among the sorted endpoints.
@@ -64,10 +149,14 @@ __global__ __launch_bounds__(NT) void k_endpoint_bounds(const uint32_t* __restri
     }
 }
 
-__global__ __launch_bounds__(NT) void k_vertex_keys(const uint32_t* __restrict__ dstart, int32_t n,
+// Key (degree, id); OFFSETS: deg holds degree offsets [n + 1], else counts [n].
+template <bool OFFSETS>
+__global__ __launch_bounds__(NT) void k_vertex_keys(const uint32_t* __restrict__ deg, int32_t n,
                                                     uint64_t* __restrict__ keys) {
-    for (int64_t v = (int64_t)blockIdx.x * NT + threadIdx.x; v < n; v += (int64_t)gridDim.x * NT)
-        keys[v] = ((uint64_t)(dstart[v + 1] - dstart[v]) << 32) | (uint32_t)v;
+    for (int64_t v = (int64_t)blockIdx.x * NT + threadIdx.x; v < n; v += (int64_t)gridDim.x * NT) {
+        const uint32_t d = OFFSETS ? deg[v + 1] - deg[v] : deg[v];
+        keys[v] = ((uint64_t)d << 32) | (uint32_t)v;
+    }
 }
 
 __global__ __launch_bounds__(NT) void k_rank(const uint64_t* __restrict__ sorted, int32_t n,
@@ -542,6 +631,7 @@ Layout make_layout(int64_t E, int32_t n) {
     L.tile_cap = ee / 16 + nn + 1;
     L.tiles = take(8 * L.tile_cap);
     L.partial = take(4 * (UQ_MAX_BLOCKS + 1));
+    L.bstart = take(4 * 260);
     L.isect_partials = take(isect_partials_bytes());
     L.scan_tmp = take(scan_temp_bytes());
     L.radix_tmp = take(radix_temp_bytes(2 * ee > nn ? 2 * ee : nn));
@@ -632,21 +722,47 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     mark(0);
     // ---- degree: input pairs per vertex, from the sorted endpoints
     fill_u32((uint32_t*)ctrl, 0u, sizeof(Ctrl) / 4, s);
+    const int vbits = bits_for((uint64_t)n);               // vertex ids fit in vbits bits
+    const int bw = vbits - 8 > 12 ? vbits - 8 : (vbits < 12 ? vbits : 12);
+    const bool bucketed = bw <= DEG_MAX_BW;
     {
         uint32_t* ep = (uint32_t*)keysA;       // 2E uint32 fit in E uint64
         uint32_t* ep_alt = (uint32_t*)keysB;
-        hipLaunchKernelGGL(k_endpoints, dim3(grid_for((size_t)E)), dim3(NT), 0, s, edges, (uint64_t)E, n, ep, ctrl);
-        const int a0 = radix_sort_u32(ep, ep_alt, nullptr, nullptr, nullptr, (size_t)(2 * E), 0,
-                                      bits_for((uint64_t)n + 1), radix_tmp, s);
-        fill_u32(rowend, 0u, (size_t)n, s);
-        hipLaunchKernelGGL(k_endpoint_bounds, dim3(grid_for((size_t)(2 * E))), dim3(NT), 0, s, a0 ? ep_alt : ep,
-                           (uint64_t)(2 * E), n, rowend);
-        fill_u32(deg, 0u, 1, s);
-        scan_inclusive_max_u32(rowend, deg + 1, (size_t)n, scan_tmp, s);   // deg[] holds degree offsets
+        const unsigned eg = grid_for((size_t)E, DEG_EP_BLOCKS);
+        hipLaunchKernelGGL(k_endpoints, dim3(eg), dim3(NT), 0, s, edges, (uint64_t)E, n,
+                           bucketed ? (uint32_t)(n - 1) : (uint32_t)n, ep, ctrl, partial);
+        if (bucketed) {
+            // partition by bits [bw, vbits) (at most 8: one pass), then count per bucket
+            const uint32_t nb = 1u << (vbits - bw);
+            int a0 = 0;
+            if (vbits > bw)
+                a0 = radix_sort_u32(ep, ep_alt, nullptr, nullptr, nullptr, (size_t)(2 * E), bw, vbits, radix_tmp, s);
+            uint32_t* bst = (uint32_t*)(ws + L.bstart);
+            hipLaunchKernelGGL(k_bucket_starts, dim3(1), dim3(NT), 0, s,
+                               vbits > bw ? radix_last_digit_totals(radix_tmp, (size_t)(2 * E)) : nullptr, nb,
+                               (uint32_t)(2 * E), bst);
+            uint32_t splits = 1;
+            while (nb * splits < 256u && (uint64_t)splits * 65536u < (uint64_t)(2 * E) && splits < 64u) splits *= 2;
+            if (splits > 1) fill_u32(deg, 0u, (size_t)n, s);
+            hipLaunchKernelGGL(k_bucket_count, dim3(nb * splits), dim3(NT), sizeof(uint32_t) << bw, s,
+                               a0 ? ep_alt : ep, bst, bw, splits, n, deg);
+            hipLaunchKernelGGL(k_drop_sentinels, dim3(1), dim3(NT), 0, s, partial, eg, n, deg);
+        } else {
+            const int a0 = radix_sort_u32(ep, ep_alt, nullptr, nullptr, nullptr, (size_t)(2 * E), 0,
+                                          bits_for((uint64_t)n + 1), radix_tmp, s);
+            fill_u32(rowend, 0u, (size_t)n, s);
+            hipLaunchKernelGGL(k_endpoint_bounds, dim3(grid_for((size_t)(2 * E))), dim3(NT), 0, s, a0 ? ep_alt : ep,
+                               (uint64_t)(2 * E), n, rowend);
+            fill_u32(deg, 0u, 1, s);
+            scan_inclusive_max_u32(rowend, deg + 1, (size_t)n, scan_tmp, s);   // deg[] holds degree offsets
+        }
     }
     mark(1);
     // ---- rank: sort (degree, id); degrees are below 2E + 1
-    hipLaunchKernelGGL(k_vertex_keys, dim3(grid_for((size_t)n)), dim3(NT), 0, s, deg, n, vkeysA);
+    if (bucketed)
+        hipLaunchKernelGGL(k_vertex_keys<false>, dim3(grid_for((size_t)n)), dim3(NT), 0, s, deg, n, vkeysA);
+    else
+        hipLaunchKernelGGL(k_vertex_keys<true>, dim3(grid_for((size_t)n)), dim3(NT), 0, s, deg, n, vkeysA);
     {
         const int dbits = bits_for((uint64_t)2 * (uint64_t)E + 1);
         const int alt = radix_sort_u64(vkeysA, vkeysB, nullptr, nullptr, nullptr, (size_t)n, 32, 32 + dbits,

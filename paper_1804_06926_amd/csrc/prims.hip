@@ -245,7 +245,7 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ k
 
 // One block per digit d: exclusive scan, in place, of the digit's row of tile
 // counts hist[d * ntiles .. +ntiles); the row total goes to digit_tot[d].
-constexpr int RS_ROW_ITEMS = 32;
+constexpr int RS_ROW_ITEMS = 8;
 __global__ __launch_bounds__(RS_NT) void k_radix_rowscan(uint32_t* __restrict__ hist, uint32_t ntiles,
                                                          uint32_t* __restrict__ digit_tot) {
     __shared__ uint32_t scratch[RS_WAVES];
@@ -390,6 +390,11 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
         uint32_t* tv = vin; vin = vout; vout = tv;
     }
     return passes & 1;   // 1: result is in keys_alt / vals_alt
+}
+
+const uint32_t* radix_last_digit_totals(const void* temp, size_t cap) {
+    return (const uint32_t*)((const char*)temp +
+                             align_up(sizeof(uint32_t) * 256 * ((cap + RS_TILE - 1) / RS_TILE + 1), 256));
 }
 
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,

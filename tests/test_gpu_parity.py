@@ -63,6 +63,12 @@ CASES = {
     "chung_lu": lambda: (graphgen.chung_lu(20000, 160000, seed=4), 20000),
     "rgg_16k": lambda: (graphgen.rgg(1 << 14, avg_degree=24, seed=6), 1 << 14),
     "isolated_tail": lambda: (graphgen.complete(30), 5000),
+    # ids over 22 bits: the degree count uses its widest LDS buckets (2^14 vertices)
+    "sparse_22bit": lambda: (_dirty(graphgen.chung_lu(4_100_000, 2_000_000, seed=12), 4_100_000, 12), 4_100_000),
+    # ids over 12 bits: no partition pass, one bucket counted by several blocks
+    "dense_12bit": lambda: (graphgen.erdos_renyi(4000, 300_000, seed=13), 4000),
+    # ids over 13 bits: a one-bit partition, two buckets counted by several blocks each
+    "dense_13bit": lambda: (graphgen.erdos_renyi(6000, 400_000, seed=14), 6000),
 }
 
 SELECTS = ["heuristic", "merge", "bsearch", "bitmap"]
