@@ -24,6 +24,7 @@ struct IsectArgs {
     uint64_t* per_vertex;       // [n] or null: t[] in rank space
     uint64_t* per_middle;       // [n] or null: triangles whose middle vertex is v (rank space)
     uint32_t* support;          // [m] or null: triangles containing each kept edge (CSR edge order)
+    uint32_t col_narrow;        // 1 when col spans less than 4 GiB (32-bit byte offsets suffice)
 };
 
 // Blocks of one intersection kernel resident per CU (from the occupancy API);

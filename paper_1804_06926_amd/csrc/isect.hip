@@ -127,7 +127,15 @@ __device__ __forceinline__ void block_partial(uint64_t acc, uint64_t* partials) 
 // ------------------------------------------------------------------ LDS bitmap
 // GATHER: per-vertex counts or edge support requested; the hits per element
 // of N+(v) (for t[w] and the support of edge vw) are gathered in LDS.
-template <bool GATHER>
+// Element i of col. NARROW: the array is below 4 GiB, so a 32-bit byte offset
+// from the (scalar) base addresses it and no 64-bit address math is needed.
+template <bool NARROW>
+__device__ __forceinline__ uint32_t col_at(const uint32_t* col, uint32_t i) {
+    if (NARROW) return *(const uint32_t*)((const char*)col + (uint32_t)(i << 2));
+    return col[i];
+}
+
+template <bool GATHER, bool NARROW>
 __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* partials) {
     __shared__ uint32_t s_nv[GATHER ? NV_MAX : 1];
     __shared__ uint32_t s_wc[GATHER ? NV_MAX : 1];
@@ -267,7 +275,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
 #pragma unroll
                             for (int j = 0; j < UNROLL; ++j) ad[j] = s_base[ks[j]] + W + j * WAVE + ln;
 #pragma unroll
-                            for (int j = 0; j < UNROLL; ++j) xs[j] = a.col[ad[j]] - wlo;
+                            for (int j = 0; j < UNROLL; ++j) xs[j] = col_at<NARROW>(a.col, ad[j]) - wlo;
                         } else {
                             // mark the starts (pref is strictly increasing, so the marked offsets
                             // are distinct and at least 1). Entries past the last one read
@@ -306,7 +314,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                                 ad[j] = q < q1 ? sb + q : b0;
                             }
     #pragma unroll
-                            for (int j = 0; j < UNROLL; ++j) xs[j] = a.col[ad[j]];
+                            for (int j = 0; j < UNROLL; ++j) xs[j] = col_at<NARROW>(a.col, ad[j]);
     #pragma unroll
                             for (int j = 0; j < UNROLL; ++j)
                                 xs[j] = (W + j * WAVE + ln < q1) ? xs[j] - wlo : 0xFFFFFFFFu;
@@ -597,8 +605,8 @@ int isect_blocks_per_cu(int ker, bool gather) {
     if (!c) {
         const void* fn = ker == KER_MERGE     ? (const void*)k_isect_edges<true>
                          : ker == KER_BSEARCH ? (const void*)k_isect_edges<false>
-                         : gather             ? (const void*)k_isect_bitmap<true>
-                                              : (const void*)k_isect_bitmap<false>;
+                         : gather             ? (const void*)k_isect_bitmap<true, true>
+                                              : (const void*)k_isect_bitmap<false, true>;
         c = resident_blocks(fn);
     }
     return c;
@@ -614,11 +622,18 @@ void launch_isect(int ker, const IsectArgs& a, int grid, uint64_t* partials, hip
     switch (ker) {
         case KER_MERGE: hipLaunchKernelGGL(k_isect_edges<true>, dim3(grid), dim3(IS_NT), 0, s, a, p); break;
         case KER_BSEARCH: hipLaunchKernelGGL(k_isect_edges<false>, dim3(grid), dim3(IS_NT), 0, s, a, p); break;
-        default:
-            if (a.per_vertex || a.support)
-                hipLaunchKernelGGL(k_isect_bitmap<true>, dim3(grid), dim3(IS_NT), 0, s, a, p);
-            else hipLaunchKernelGGL(k_isect_bitmap<false>, dim3(grid), dim3(IS_NT), 0, s, a, p);
+        default: {
+            const bool narrow = a.col_narrow != 0;
+            if (a.per_vertex || a.support) {
+                if (narrow) hipLaunchKernelGGL((k_isect_bitmap<true, true>), dim3(grid), dim3(IS_NT), 0, s, a, p);
+                else hipLaunchKernelGGL((k_isect_bitmap<true, false>), dim3(grid), dim3(IS_NT), 0, s, a, p);
+            } else if (narrow) {
+                hipLaunchKernelGGL((k_isect_bitmap<false, true>), dim3(grid), dim3(IS_NT), 0, s, a, p);
+            } else {
+                hipLaunchKernelGGL((k_isect_bitmap<false, false>), dim3(grid), dim3(IS_NT), 0, s, a, p);
+            }
             break;
+        }
     }
 }
 

@@ -663,6 +663,7 @@ static IsectArgs isect_args(const RunArgs& r, const Layout& L, uint64_t* csc) {
     ia.per_vertex = (r.per_vertex || r.clustering) ? (uint64_t*)(ws + L.pv) : nullptr;
     ia.per_middle = r.per_middle ? (uint64_t*)(ws + L.pv) : nullptr;
     ia.support = r.support;
+    ia.col_narrow = r.E < ((int64_t)1 << 30) ? 1u : 0u;   // m <= E
     return ia;
 }
 
