@@ -364,14 +364,17 @@ __global__ __launch_bounds__(NT) void k_vbucket(const uint32_t* __restrict__ off
 
 // ------------------------------------------------------------------ selection
 // One thread per bucket. The heuristic follows the paper's dynamic grouping:
-// a fixed degree threshold decides between the cooperative (staged) and the
-// per-pair strategies; here the staged LDS bitmap takes middle vertices with
-// many in-edges, binary search takes few in-edges against long lists, and
-// merge-path takes the rest.
+// a fixed threshold decides between the cooperative (staged) and the per-pair
+// strategies. Here the staged LDS bitmap takes middle vertices whose work,
+// in-edges times out-degree, is at least about 2^10 (the bitmap's set-up is
+// then amortised), binary search takes the rest with at least two
+// out-neighbours, and merge-path the single-neighbour lists. The threshold
+// was chosen from per-bucket timings of all three kernels on R-MAT and
+// Chung-Lu graphs of 2^17 to 2^22 vertices.
 __device__ int heuristic_choice(int b) {
     const int li = b >> 4, lo = b & 15;   // floor log2 of in-degree and out-degree
-    if (li >= 6) return KER_BITMAP;       // >= 64 in-edges share one staged N+(v)
-    if (lo >= 4) return KER_BSEARCH;
+    if (li + lo >= 10) return KER_BITMAP;
+    if (lo >= 1) return KER_BSEARCH;
     return KER_MERGE;
 }
 

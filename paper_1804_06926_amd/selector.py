@@ -35,9 +35,9 @@ KERNELS = ("merge", "bsearch", "bitmap")
 def heuristic_choice(bucket: int) -> int:
     """The library's fixed thresholds (same rule as the device code)."""
     li, lo = bucket >> 4, bucket & 15
-    if li >= 6:
+    if li + lo >= 10:
         return 2
-    if lo >= 4:
+    if lo >= 1:
         return 1
     return 0
 

@@ -7,9 +7,11 @@ from paper_1804_06926_amd import autotune, selector
 
 
 def test_heuristic_thresholds():
-    assert selector.heuristic_choice(16 * 6 + 0) == 2     # >= 64 in-edges: bitmap
-    assert selector.heuristic_choice(16 * 5 + 9) == 1     # fewer in-edges, long lists: binary search
-    assert selector.heuristic_choice(16 * 2 + 2) == 0     # short lists: merge path
+    assert selector.heuristic_choice(16 * 6 + 4) == 2     # in-edges x out-degree >= 2^10: bitmap
+    assert selector.heuristic_choice(16 * 13 + 0) == 2
+    assert selector.heuristic_choice(16 * 5 + 4) == 1     # less work, two or more out-neighbours: binary search
+    assert selector.heuristic_choice(16 * 2 + 1) == 1
+    assert selector.heuristic_choice(16 * 2 + 0) == 0     # one out-neighbour: merge path
 
 
 def test_labels_keep_heuristic_within_tie():
