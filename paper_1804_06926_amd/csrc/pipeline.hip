@@ -364,17 +364,17 @@ __global__ __launch_bounds__(NT) void k_vbucket(const uint32_t* __restrict__ off
 
 // ------------------------------------------------------------------ selection
 // One thread per bucket. The heuristic follows the paper's dynamic grouping:
-// a fixed threshold decides between the cooperative (staged) and the per-pair
-// strategies. Here the staged LDS bitmap takes middle vertices whose work,
-// in-edges times out-degree, is at least about 2^10 (the bitmap's set-up is
-// then amortised), binary search takes the rest with at least two
-// out-neighbours, and merge-path the single-neighbour lists. The threshold
-// was chosen from per-bucket timings of all three kernels on R-MAT and
-// Chung-Lu graphs of 2^17 to 2^22 vertices.
+// fixed degree thresholds decide between the cooperative (staged) and the
+// per-pair strategies. Here the staged LDS bitmap takes middle vertices with
+// at least 64 in-edges, or at least 16 in-edges and 64 out-neighbours (the
+// bitmap's set-up is then amortised), binary search takes lists of at least
+// 16 out-neighbours, and merge-path the rest. The thresholds were chosen from
+// per-bucket timings of all three kernels on R-MAT and Chung-Lu graphs of
+// 2^17 to 2^22 vertices and on a batch of 4096 small Chung-Lu graphs.
 __device__ int heuristic_choice(int b) {
     const int li = b >> 4, lo = b & 15;   // floor log2 of in-degree and out-degree
-    if (li + lo >= 10) return KER_BITMAP;
-    if (lo >= 1) return KER_BSEARCH;
+    if (li >= 6 || (li >= 4 && lo >= 6)) return KER_BITMAP;
+    if (lo >= 4) return KER_BSEARCH;
     return KER_MERGE;
 }
 

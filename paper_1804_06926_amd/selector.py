@@ -35,9 +35,9 @@ KERNELS = ("merge", "bsearch", "bitmap")
 def heuristic_choice(bucket: int) -> int:
     """The library's fixed thresholds (same rule as the device code)."""
     li, lo = bucket >> 4, bucket & 15
-    if li + lo >= 10:
+    if li >= 6 or (li >= 4 and lo >= 6):
         return 2
-    if lo >= 1:
+    if lo >= 4:
         return 1
     return 0
 

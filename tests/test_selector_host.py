@@ -7,11 +7,11 @@ from paper_1804_06926_amd import autotune, selector
 
 
 def test_heuristic_thresholds():
-    assert selector.heuristic_choice(16 * 6 + 4) == 2     # in-edges x out-degree >= 2^10: bitmap
-    assert selector.heuristic_choice(16 * 13 + 0) == 2
-    assert selector.heuristic_choice(16 * 5 + 4) == 1     # less work, two or more out-neighbours: binary search
-    assert selector.heuristic_choice(16 * 2 + 1) == 1
-    assert selector.heuristic_choice(16 * 2 + 0) == 0     # one out-neighbour: merge path
+    assert selector.heuristic_choice(16 * 6 + 0) == 2     # >= 64 in-edges: bitmap
+    assert selector.heuristic_choice(16 * 4 + 6) == 2     # >= 16 in-edges and >= 64 out-neighbours: bitmap
+    assert selector.heuristic_choice(16 * 4 + 5) == 1     # fewer, long lists: binary search
+    assert selector.heuristic_choice(16 * 3 + 9) == 1
+    assert selector.heuristic_choice(16 * 2 + 2) == 0     # short lists: merge path
 
 
 def test_labels_keep_heuristic_within_tie():
