@@ -391,7 +391,7 @@ __global__ __launch_bounds__(NBUCKET) void k_select(Ctrl* ctrl, int mode, const 
     else ch = heuristic_choice(b);
     const int lo = b & 15, li = b >> 4;
     // tile shape: in-edges per tile and lanes per in-edge
-    uint32_t chunk = (ch == KER_BITMAP) ? 256u : 128u;
+    uint32_t chunk = 256u;
     uint32_t group = lo >= 9 ? 64u : (lo >= 3 ? (1u << (lo - 3)) : 1u);
     if (chunk_override && chunk_override[b]) chunk = chunk_override[b];
     if (group_override && group_override[b]) group = group_override[b];
