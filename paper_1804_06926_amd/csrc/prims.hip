@@ -213,49 +213,34 @@ __device__ __forceinline__ uint32_t rs_count(const uint32_t* d_count, uint32_t c
     return c < cap ? c : cap;
 }
 
-// Per-tile digit counts, written digit-major: hist[d * ntp + tile], ntp = the
-// tile count rounded up to tpb. A block takes tpb consecutive tiles, so each
-// digit's counts go out as one contiguous run (tpb = 8: 32 bytes) instead of
-// tpb scattered 4-byte writes.
-constexpr int RS_TPB = 8;
+// Per-tile digit counts, written digit-major: hist[d * ntiles + tile].
 template <typename KeyT>
 __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ keys, const uint32_t* d_count,
                                                       uint32_t cap, int shift, uint32_t dmask,
-                                                      uint32_t* __restrict__ hist, uint32_t ntp, int tpb) {
+                                                      uint32_t* __restrict__ hist,
+                                                      uint32_t ntiles) {
     __shared__ uint32_t wcnt[RS_WAVES][256];
     for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const uint32_t n = rs_count(d_count, cap);
-    const int w = wave_id(), l = lane_id(), d = threadIdx.x;
-    uint32_t c[RS_TPB];
-    uint32_t cum = 0;   // running total of digit d over the block's tiles so far
-    for (int tt = 0; tt < tpb; ++tt) {
-        const uint32_t base = (blockIdx.x * tpb + tt) * RS_TILE + w * RS_WAVE_SPAN;
-        uint32_t dg[RS_ITEMS];
+    const int w = wave_id(), l = lane_id();
+    const uint32_t base = blockIdx.x * RS_TILE + w * RS_WAVE_SPAN;
+    uint32_t dg[RS_ITEMS];
 #pragma unroll
-        for (int it = 0; it < RS_ITEMS; ++it) {
-            const uint32_t i = base + it * WAVE + l;
-            dg[it] = i < n ? (uint32_t)(keys[i] >> shift) & dmask : 0u;
-        }
-        // counts only (no ranks): one LDS atomic per key into the wave's histogram
-#pragma unroll
-        for (int it = 0; it < RS_ITEMS; ++it)
-            if (base + it * WAVE + l < n) atomicAdd(&wcnt[w][dg[it]], 1u);
-        __syncthreads();
-        uint32_t t = 0;
-#pragma unroll
-        for (int k = 0; k < RS_WAVES; ++k) t += wcnt[k][d];
-        c[tt < RS_TPB ? tt : 0] = t - cum;
-        cum = t;
-        __syncthreads();
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint32_t i = base + it * WAVE + l;
+        dg[it] = i < n ? (uint32_t)(keys[i] >> shift) & dmask : 0u;
     }
-    uint32_t* out = hist + (size_t)d * ntp + (size_t)blockIdx.x * tpb;
-    if (tpb == RS_TPB) {
-        ((uint4*)out)[0] = make_uint4(c[0], c[1], c[2], c[3]);
-        ((uint4*)out)[1] = make_uint4(c[4], c[5], c[6], c[7]);
-    } else {
-        for (int tt = 0; tt < tpb; ++tt) out[tt] = c[tt];
-    }
+    // counts only (no ranks): one LDS atomic per key into the wave's histogram
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it)
+        if (base + it * WAVE + l < n) atomicAdd(&wcnt[w][dg[it]], 1u);
+    __syncthreads();
+    const int d = threadIdx.x;
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < RS_WAVES; ++k) t += wcnt[k][d];
+    hist[(size_t)d * ntiles + blockIdx.x] = t;
 }
 
 // One block per digit d: exclusive scan, in place, of the digit's row of tile
@@ -292,125 +277,97 @@ __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const KeyT* __restrict_
                                                          KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          const uint32_t* d_count, uint32_t cap, int shift,
                                                          uint32_t dmask,
-                                                         const uint32_t* __restrict__ hist_scan, uint32_t ntp,
-                                                         int tpb, const uint32_t* __restrict__ digit_tot) {
+                                                         const uint32_t* __restrict__ hist_scan, uint32_t ntiles,
+                                                         const uint32_t* __restrict__ digit_tot) {
     __shared__ uint32_t wcnt[RS_WAVES][256];
     __shared__ uint32_t lstart[256];
     __shared__ uint32_t gbase[256];
     __shared__ uint32_t scratch[RS_WAVES];
     __shared__ KeyT skey[RS_TILE];
     __shared__ uint32_t sval[HAS_VAL ? RS_TILE : 1];
+    for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
     const uint32_t n = rs_count(d_count, cap);
     const int w = wave_id(), l = lane_id();
-    // per block: digit bases (keys with a smaller digit) and this block's tile
-    // offsets in each digit row, read as one contiguous run per digit
-    uint32_t hs[RS_TPB];
-    uint32_t dbase;
+    const uint32_t tile0 = blockIdx.x * RS_TILE;
+    const uint32_t base = tile0 + w * RS_WAVE_SPAN;
+    KeyT k[RS_ITEMS];
+    uint32_t v[RS_ITEMS];
+    uint32_t loc[RS_ITEMS];   // digit | (rank within (wave, digit)) << 8
+    // all loads first, so that they are in flight together (the ranking below
+    // has wave barriers that no load may cross)
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint32_t i = base + it * WAVE + l;
+        k[it] = i < n ? kin[i] : KeyT(0);
+        if (HAS_VAL) v[it] = i < n ? vin[i] : 0u;
+    }
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint32_t i = base + it * WAVE + l;
+        const bool valid = i < n;
+        const uint32_t d = (uint32_t)(k[it] >> shift) & dmask;
+        const uint64_t peers = match_digit8(d, __ballot(valid));
+        const uint32_t r = (uint32_t)__popcll(peers & lanes_below());
+        const uint32_t prev = wcnt[w][d];
+        __builtin_amdgcn_wave_barrier();
+        if (valid && r == 0) wcnt[w][d] = prev + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        loc[it] = d | ((prev + r) << 8);
+    }
+    __syncthreads();
     {
         const int d = threadIdx.x;
-        const uint32_t* row = hist_scan + (size_t)d * ntp + (size_t)blockIdx.x * tpb;
-        if (tpb == RS_TPB) {
-            const uint4 a = ((const uint4*)row)[0], b = ((const uint4*)row)[1];
-            hs[0] = a.x; hs[1] = a.y; hs[2] = a.z; hs[3] = a.w;
-            hs[4] = b.x; hs[5] = b.y; hs[6] = b.z; hs[7] = b.w;
-        } else {
-            for (int tt = 0; tt < RS_TPB; ++tt) hs[tt] = tt < tpb ? row[tt] : 0u;
+        uint32_t run = 0;
+#pragma unroll
+        for (int q = 0; q < RS_WAVES; ++q) {
+            const uint32_t c = wcnt[q][d];
+            wcnt[q][d] = run;
+            run += c;
         }
-        dbase = block_exclusive_scan<RS_NT>(digit_tot[d], scratch);
+        const uint32_t excl = block_exclusive_scan<RS_NT>(run, scratch);
+        lstart[d] = excl;
+        // digit base = keys with a smaller digit; plus this tile's offset in its digit row
+        const uint32_t dbase = block_exclusive_scan<RS_NT>(digit_tot[d], scratch);
+        gbase[d] = dbase + hist_scan[(size_t)d * ntiles + blockIdx.x];
     }
-    for (int tt = 0; tt < tpb; ++tt) {
-        const uint32_t tile0 = (blockIdx.x * tpb + tt) * RS_TILE;
-        if (tile0 >= n) break;   // uniform across the block
-        for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
-        __syncthreads();
-        const uint32_t base = tile0 + w * RS_WAVE_SPAN;
-        KeyT k[RS_ITEMS];
-        uint32_t v[RS_ITEMS];
-        uint32_t loc[RS_ITEMS];   // digit | (rank within (wave, digit)) << 8
-        // all loads first, so that they are in flight together (the ranking below
-        // has wave barriers that no load may cross)
+    __syncthreads();
 #pragma unroll
-        for (int it = 0; it < RS_ITEMS; ++it) {
-            const uint32_t i = base + it * WAVE + l;
-            k[it] = i < n ? kin[i] : KeyT(0);
-            if (HAS_VAL) v[it] = i < n ? vin[i] : 0u;
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint32_t i = base + it * WAVE + l;
+        if (i < n) {
+            const uint32_t d = loc[it] & 255u;
+            const uint32_t p = lstart[d] + wcnt[w][d] + (loc[it] >> 8);
+            skey[p] = k[it];
+            if (HAS_VAL) sval[p] = v[it];
         }
-#pragma unroll
-        for (int it = 0; it < RS_ITEMS; ++it) {
-            const uint32_t i = base + it * WAVE + l;
-            const bool valid = i < n;
-            const uint32_t d = (uint32_t)(k[it] >> shift) & dmask;
-            const uint64_t peers = match_digit8(d, __ballot(valid));
-            const uint32_t r = (uint32_t)__popcll(peers & lanes_below());
-            const uint32_t prev = wcnt[w][d];
-            __builtin_amdgcn_wave_barrier();
-            if (valid && r == 0) wcnt[w][d] = prev + (uint32_t)__popcll(peers);
-            __builtin_amdgcn_wave_barrier();
-            loc[it] = d | ((prev + r) << 8);
+    }
+    __syncthreads();
+    const uint32_t tile_n = n > tile0 ? (n - tile0 < (uint32_t)RS_TILE ? n - tile0 : (uint32_t)RS_TILE) : 0u;
+    for (uint32_t j = threadIdx.x; j < tile_n; j += RS_NT) {
+        const KeyT key = skey[j];
+        const uint32_t d = (uint32_t)(key >> shift) & dmask;
+        const uint32_t pos = gbase[d] + (j - lstart[d]);
+        if (pos < n) {   // always true when the histogram scan is consistent
+            kout[pos] = key;
+            if (HAS_VAL) vout[pos] = sval[j];
         }
-        __syncthreads();
-        {
-            const int d = threadIdx.x;
-            uint32_t run = 0;
-#pragma unroll
-            for (int q = 0; q < RS_WAVES; ++q) {
-                const uint32_t c = wcnt[q][d];
-                wcnt[q][d] = run;
-                run += c;
-            }
-            const uint32_t excl = block_exclusive_scan<RS_NT>(run, scratch);
-            lstart[d] = excl;
-            uint32_t h = hs[0];
-#pragma unroll
-            for (int q = 1; q < RS_TPB; ++q)
-                if (q == tt) h = hs[q];
-            gbase[d] = dbase + h;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int it = 0; it < RS_ITEMS; ++it) {
-            const uint32_t i = base + it * WAVE + l;
-            if (i < n) {
-                const uint32_t d = loc[it] & 255u;
-                const uint32_t p = lstart[d] + wcnt[w][d] + (loc[it] >> 8);
-                skey[p] = k[it];
-                if (HAS_VAL) sval[p] = v[it];
-            }
-        }
-        __syncthreads();
-        const uint32_t tile_n = n - tile0 < (uint32_t)RS_TILE ? n - tile0 : (uint32_t)RS_TILE;
-        for (uint32_t j = threadIdx.x; j < tile_n; j += RS_NT) {
-            const KeyT key = skey[j];
-            const uint32_t d = (uint32_t)(key >> shift) & dmask;
-            const uint32_t pos = gbase[d] + (j - lstart[d]);
-            if (pos < n) {   // always true when the histogram scan is consistent
-                kout[pos] = key;
-                if (HAS_VAL) vout[pos] = sval[j];
-            }
-        }
-        __syncthreads();   // LDS reused by the next tile
     }
 }
 
-// Histogram table: 256 digit rows of the tile count rounded up to RS_TPB.
-static size_t rs_hist_bytes(size_t cap) {
-    const size_t ntiles = (cap + RS_TILE - 1) / RS_TILE;
-    return align_up(sizeof(uint32_t) * 256 * (ntiles + RS_TPB), 256);
+size_t radix_temp_bytes(size_t cap) {
+    const size_t ntiles = (cap + RS_TILE - 1) / RS_TILE + 1;
+    return align_up(sizeof(uint32_t) * 256 * ntiles, 256) + align_up(scan_temp_bytes(), 256);
 }
-
-size_t radix_temp_bytes(size_t cap) { return rs_hist_bytes(cap) + align_up(scan_temp_bytes(), 256); }
 
 template <typename KeyT>
 static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                       size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s) {
     if (cap == 0 || bit_hi <= bit_lo) return 0;
     const uint32_t ntiles = (uint32_t)((cap + RS_TILE - 1) / RS_TILE);
-    // several tiles per block once there are enough blocks to fill the GPU
-    const int tpb = ntiles >= (uint32_t)RS_TPB * 1024u ? RS_TPB : 1;
-    const uint32_t ntp = (ntiles + tpb - 1) / tpb * tpb;
-    const uint32_t nblk = ntp / tpb;
     uint32_t* hist = (uint32_t*)temp;
-    uint32_t* digit_tot = (uint32_t*)((char*)temp + rs_hist_bytes(cap));   // 256 digit totals
+    void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * ((cap + RS_TILE - 1) / RS_TILE + 1), 256);
+    uint32_t* digit_tot = (uint32_t*)scan_tmp;   // 256 digit totals
     KeyT* kin = keys;
     KeyT* kout = keys_alt;
     uint32_t* vin = vals;
@@ -419,15 +376,15 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
     for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
         const int dbits = bit_hi - shift < 8 ? bit_hi - shift : 8;   // the last digit may be narrower
         const uint32_t dmask = (1u << dbits) - 1u;
-        hipLaunchKernelGGL(k_radix_hist<KeyT>, dim3(nblk), dim3(RS_NT), 0, s, kin, d_count, (uint32_t)cap, shift,
-                           dmask, hist, ntp, tpb);
-        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(RS_NT), 0, s, hist, ntp, digit_tot);
+        hipLaunchKernelGGL(k_radix_hist<KeyT>, dim3(ntiles), dim3(RS_NT), 0, s, kin, d_count, (uint32_t)cap, shift,
+                           dmask, hist, ntiles);
+        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(RS_NT), 0, s, hist, ntiles, digit_tot);
         if (vals) {
-            hipLaunchKernelGGL((k_radix_scatter<KeyT, true>), dim3(nblk), dim3(RS_NT), 0, s, kin, vin, kout, vout,
-                               d_count, (uint32_t)cap, shift, dmask, hist, ntp, tpb, digit_tot);
+            hipLaunchKernelGGL((k_radix_scatter<KeyT, true>), dim3(ntiles), dim3(RS_NT), 0, s, kin, vin, kout, vout,
+                               d_count, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot);
         } else {
-            hipLaunchKernelGGL((k_radix_scatter<KeyT, false>), dim3(nblk), dim3(RS_NT), 0, s, kin, nullptr, kout,
-                               nullptr, d_count, (uint32_t)cap, shift, dmask, hist, ntp, tpb, digit_tot);
+            hipLaunchKernelGGL((k_radix_scatter<KeyT, false>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr, kout,
+                               nullptr, d_count, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot);
         }
         KeyT* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
@@ -436,7 +393,8 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
 }
 
 const uint32_t* radix_last_digit_totals(const void* temp, size_t cap) {
-    return (const uint32_t*)((const char*)temp + rs_hist_bytes(cap));
+    return (const uint32_t*)((const char*)temp +
+                             align_up(sizeof(uint32_t) * 256 * ((cap + RS_TILE - 1) / RS_TILE + 1), 256));
 }
 
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,

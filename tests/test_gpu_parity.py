@@ -226,7 +226,7 @@ def test_csr_export_matches_definition(tc):
 
 @pytest.mark.parametrize("count,bits", [(c, b) for c in (1, 2047, 2048, 2049, 100003)
                                         for b in ((0, 64), (0, 20), (32, 45), (7, 13))]
-                         # past 2^24 keys a block takes 8 tiles; a ragged last block
+                         # a sort of more than 2^24 keys with a ragged last tile
                          + [(8 * 1024 * 2048 + 2048 * 5 + 77, (0, 64)), (8 * 1024 * 2048 + 2048 * 5 + 77, (7, 13))])
 def test_radix_sort_is_stable_and_exact(tc, count, bits):
     import torch
