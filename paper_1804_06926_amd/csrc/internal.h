@@ -63,5 +63,6 @@ struct Ctrl {
 // starting at position i (whole in-edge lists).
 constexpr uint32_t TILE_MULTI = 0x80000000u;
 constexpr int SEG_MAX = 256;          // vertices per multi-vertex tile
+constexpr int SEG_MAX_BITMAP = 32;    // vertices per multi-vertex tile of the bitmap kernel
 
 }  // namespace tcx

@@ -28,8 +28,8 @@ struct IsectArgs {
 };
 
 // Blocks of one intersection kernel resident per CU (from the occupancy API);
-// gather: the variant with per-vertex or support outputs.
-int isect_blocks_per_cu(int ker, bool gather);
+// mode: the bitmap kernel's output mode (0 for the edge kernels).
+int isect_blocks_per_cu(int ker, int mode);
 size_t isect_partials_bytes();
 // One intersection kernel over its tile range; per-block partial counts go to
 // partials (isect_partials_bytes() of workspace shared by the three kernels).

@@ -31,26 +31,30 @@ constexpr int BM_WORDS = 4096;            // 131072-bit window (16 KiB)
 constexpr uint32_t BM_BITS = BM_WORDS * 32u;
 constexpr int STAGE_MAX = 4096;           // N+(v) staged in LDS by merge/bsearch when it fits
 constexpr int UNROLL = 8;                 // bitmap kernel: tail loads in flight per lane
-constexpr uint32_t WT_MAX = 2048;         // bitmap kernel: 64-item windows per chunk of the item range
+constexpr uint32_t WT_MAX = 1024;         // bitmap kernel: 64-item windows per chunk of the item range
 constexpr uint32_t LONG_TAIL = 64;        // bitmap kernel: tails of at least one window are walked directly
 constexpr int NV_MAX = 2048;              // bitmap kernel, per-vertex mode: N+(v) kept for t[w] gathering
 constexpr int PARTIALS_PER_KERNEL = 4096; // max blocks per intersection launch
 
-struct Segs {
-    uint32_t v[SEG_MAX];
-    uint32_t e0[SEG_MAX];
-    uint32_t pref[SEG_MAX + 1];
+template <int N>
+struct SegsT {
+    uint32_t v[N];
+    uint32_t e0[N];
+    uint32_t pref[N + 1];
     uint32_t scratch[IS_NT / WAVE];
 };
+using Segs = SegsT<SEG_MAX>;
 
 // Decode tile t into segments (v, first in-edge, count); returns the count.
 // Called by the whole block; contains barriers.
-__device__ uint32_t load_tile(const IsectArgs& a, uint32_t t, Segs& S) {
+template <int N>
+__device__ uint32_t load_tile(const IsectArgs& a, uint32_t t, SegsT<N>& S) {
     const uint64_t d = a.tiles[t];
     const uint32_t i = (uint32_t)d, h = (uint32_t)(d >> 32);
     uint32_t nseg, cnt = 0;
     if (h & TILE_MULTI) {
         nseg = h & ~TILE_MULTI;
+        if (nseg > (uint32_t)N) nseg = N;   // the tile layout never makes more
         if (threadIdx.x < nseg) {
             const uint32_t v = a.vlist[i + threadIdx.x];
             S.v[threadIdx.x] = v;
@@ -125,8 +129,6 @@ __device__ __forceinline__ void block_partial(uint64_t acc, uint64_t* partials) 
 }
 
 // ------------------------------------------------------------------ LDS bitmap
-// GATHER: per-vertex counts or edge support requested; the hits per element
-// of N+(v) (for t[w] and the support of edge vw) are gathered in LDS.
 // Element i of col. NARROW: the array is below 4 GiB, so a 32-bit byte offset
 // from the (scalar) base addresses it and no 64-bit address math is needed.
 template <bool NARROW>
@@ -135,20 +137,27 @@ __device__ __forceinline__ uint32_t col_at(const uint32_t* col, uint32_t i) {
     return col[i];
 }
 
-template <bool GATHER, bool NARROW>
+// Outputs of a bitmap launch: T only; also per in-edge counts (per-edge or
+// per-middle-vertex outputs); or also gathered per-vertex counts or edge
+// support (the hits per element of N+(v), for t[w] and the support of edge
+// vw, are gathered in LDS). Each mode sizes its LDS to what it uses.
+enum { BM_COUNT = 0, BM_ENTRY = 1, BM_GATHER = 2 };
+
+template <int MODE, bool NARROW>
 __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* partials) {
+    constexpr bool GATHER = MODE == BM_GATHER;
+    constexpr bool need_cnt = MODE != BM_COUNT;
     __shared__ uint32_t s_nv[GATHER ? NV_MAX : 1];
     __shared__ uint32_t s_wc[GATHER ? NV_MAX : 1];
     __shared__ uint32_t bm[BM_WORDS + 1];        // + one always-zero word for out-of-window positions
     __shared__ uint16_t s_wst[WT_MAX];           // entry holding the first item of each window of a chunk
     __shared__ uint32_t s_pref[CHUNK_MAX + 1];
-    __shared__ uint32_t s_cnt[CHUNK_MAX];
+    __shared__ uint32_t s_cnt[need_cnt ? CHUNK_MAX : 1];
     __shared__ uint32_t s_base[CHUNK_MAX + 1];   // entry ne is read (unused) by lanes past the end
     __shared__ uint8_t s_flag[IS_NT / WAVE][UNROLL][WAVE];    // entry-start marks, one slot per item offset
-    __shared__ Segs S;
+    __shared__ SegsT<SEG_MAX_BITMAP> S;
     for (int i = threadIdx.x; i <= BM_WORDS; i += IS_NT) bm[i] = 0;
     for (int i = threadIdx.x; i < (IS_NT / WAVE) * UNROLL * WAVE; i += IS_NT) (&s_flag[0][0][0])[i] = 0;
-    const bool need_cnt = a.per_edge || a.per_vertex || a.per_middle || a.support;
     uint64_t acc = 0;
     const uint32_t t_end = a.ctrl->tile_begin[KER_BITMAP + 1];
     for (uint32_t t = a.ctrl->tile_begin[KER_BITMAP] + blockIdx.x; t < t_end; t += gridDim.x) {
@@ -185,7 +194,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                     const uint32_t pos = len_h[h] >= LONG_TAIL ? lb_h[h] : nl + (k - lb_h[h]);
                     s_pref[pos] = len_h[h];
                     s_base[pos] = st_h[h];
-                    if (need_cnt) s_cnt[pos] = 0;
+                    if (need_cnt) s_cnt[need_cnt ? pos : 0] = 0;
                 }
             }
             __syncthreads();
@@ -599,14 +608,30 @@ static int resident_blocks(const void* fn) {
     return b;
 }
 
-int isect_blocks_per_cu(int ker, bool gather) {
-    static int cache[NKERNEL][2] = {};
-    int& c = cache[ker][gather ? 1 : 0];
+static int bitmap_mode(const IsectArgs& a) {
+    if (a.per_vertex || a.support) return BM_GATHER;
+    if (a.per_edge || a.per_middle) return BM_ENTRY;
+    return BM_COUNT;
+}
+
+static const void* bitmap_fn(int mode, bool narrow) {
+    switch (mode) {
+        case BM_GATHER: return narrow ? (const void*)k_isect_bitmap<BM_GATHER, true>
+                                      : (const void*)k_isect_bitmap<BM_GATHER, false>;
+        case BM_ENTRY: return narrow ? (const void*)k_isect_bitmap<BM_ENTRY, true>
+                                     : (const void*)k_isect_bitmap<BM_ENTRY, false>;
+        default: return narrow ? (const void*)k_isect_bitmap<BM_COUNT, true>
+                               : (const void*)k_isect_bitmap<BM_COUNT, false>;
+    }
+}
+
+int isect_blocks_per_cu(int ker, int mode) {
+    static int cache[NKERNEL][3] = {};
+    int& c = cache[ker][mode];
     if (!c) {
         const void* fn = ker == KER_MERGE     ? (const void*)k_isect_edges<true>
                          : ker == KER_BSEARCH ? (const void*)k_isect_edges<false>
-                         : gather             ? (const void*)k_isect_bitmap<true, true>
-                                              : (const void*)k_isect_bitmap<false, true>;
+                                              : bitmap_fn(mode, true);
         c = resident_blocks(fn);
     }
     return c;
@@ -615,7 +640,8 @@ int isect_blocks_per_cu(int ker, bool gather) {
 size_t isect_partials_bytes() { return sizeof(uint64_t) * NKERNEL * PARTIALS_PER_KERNEL; }
 
 void launch_isect(int ker, const IsectArgs& a, int grid, uint64_t* partials, hipStream_t s) {
-    if (grid <= 0) grid = num_cu() * isect_blocks_per_cu(ker, a.per_vertex || a.support);
+    const int mode = ker == KER_BITMAP ? bitmap_mode(a) : 0;
+    if (grid <= 0) grid = num_cu() * isect_blocks_per_cu(ker, mode);
     if (grid > PARTIALS_PER_KERNEL) grid = PARTIALS_PER_KERNEL;
     uint64_t* p = partials + (size_t)ker * PARTIALS_PER_KERNEL;
     fill_u64(p, 0ull, PARTIALS_PER_KERNEL, s);
@@ -623,14 +649,16 @@ void launch_isect(int ker, const IsectArgs& a, int grid, uint64_t* partials, hip
         case KER_MERGE: hipLaunchKernelGGL(k_isect_edges<true>, dim3(grid), dim3(IS_NT), 0, s, a, p); break;
         case KER_BSEARCH: hipLaunchKernelGGL(k_isect_edges<false>, dim3(grid), dim3(IS_NT), 0, s, a, p); break;
         default: {
-            const bool narrow = a.col_narrow != 0;
-            if (a.per_vertex || a.support) {
-                if (narrow) hipLaunchKernelGGL((k_isect_bitmap<true, true>), dim3(grid), dim3(IS_NT), 0, s, a, p);
-                else hipLaunchKernelGGL((k_isect_bitmap<true, false>), dim3(grid), dim3(IS_NT), 0, s, a, p);
-            } else if (narrow) {
-                hipLaunchKernelGGL((k_isect_bitmap<false, true>), dim3(grid), dim3(IS_NT), 0, s, a, p);
+            const bool nw = a.col_narrow != 0;
+            if (mode == BM_GATHER) {
+                if (nw) hipLaunchKernelGGL((k_isect_bitmap<BM_GATHER, true>), dim3(grid), dim3(IS_NT), 0, s, a, p);
+                else hipLaunchKernelGGL((k_isect_bitmap<BM_GATHER, false>), dim3(grid), dim3(IS_NT), 0, s, a, p);
+            } else if (mode == BM_ENTRY) {
+                if (nw) hipLaunchKernelGGL((k_isect_bitmap<BM_ENTRY, true>), dim3(grid), dim3(IS_NT), 0, s, a, p);
+                else hipLaunchKernelGGL((k_isect_bitmap<BM_ENTRY, false>), dim3(grid), dim3(IS_NT), 0, s, a, p);
             } else {
-                hipLaunchKernelGGL((k_isect_bitmap<false, false>), dim3(grid), dim3(IS_NT), 0, s, a, p);
+                if (nw) hipLaunchKernelGGL((k_isect_bitmap<BM_COUNT, true>), dim3(grid), dim3(IS_NT), 0, s, a, p);
+                else hipLaunchKernelGGL((k_isect_bitmap<BM_COUNT, false>), dim3(grid), dim3(IS_NT), 0, s, a, p);
             }
             break;
         }

@@ -419,7 +419,8 @@ __device__ __forceinline__ uint32_t tile_group(const Ctrl* ctrl, uint32_t b) {
     const uint32_t K = ctrl->chunk[b];
     if (2u * maxin > K) return 1u;
     const uint32_t g = K / maxin;
-    return g > (uint32_t)SEG_MAX ? (uint32_t)SEG_MAX : g;
+    const uint32_t cap = ctrl->choice[b] == KER_BITMAP ? (uint32_t)SEG_MAX_BITMAP : (uint32_t)SEG_MAX;
+    return g > cap ? cap : g;
 }
 
 __global__ __launch_bounds__(NT) void k_vkeys_slot(const uint8_t* __restrict__ vbucket, int32_t n, const Ctrl* ctrl,
