@@ -141,6 +141,21 @@ tc_status tc_edge_counts(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges,
                          int32_t* d_out_edges, uint32_t* d_out_counts, int64_t* h_num_out, uint64_t* h_count);
 
 /*
+ * Triangle listing (Section 1: the counting algorithms also enumerate the
+ * triangles they count). Writes the T triangles to d_out as int32 triples of
+ * original ids (u, v, w), u before v before w in (degree, id) order: the
+ * triangles of each kept edge (u, v) are contiguous, edges in CSR order,
+ * the order inside an edge unspecified. capacity = triples d_out holds.
+ * h_count receives T in every case; when T > capacity the call returns
+ * TC_ERR_WORKSPACE and writes nothing to d_out (allocate T triples and call
+ * again). The workspace must hold tc_list_workspace_size() bytes.
+ */
+tc_status tc_list_workspace_size(int64_t num_edges, int32_t num_vertices, const tc_options* opts, size_t* bytes);
+tc_status tc_list_triangles(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                            void* d_workspace, size_t workspace_bytes, const tc_options* opts, int32_t* d_out,
+                            int64_t capacity, uint64_t* h_count);
+
+/*
  * Edge support: for each kept edge, the number of triangles that contain it
  * (Section 1: the triangles the counting algorithms enumerate are the input
  * of k-truss decomposition). Same output layout as tc_edge_counts:

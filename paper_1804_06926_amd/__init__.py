@@ -25,6 +25,7 @@ from ._lib import (  # noqa: F401
     edge_counts,
     edge_support,
     last_stats,
+    list_triangles,
     library_path,
     profile_buckets,
     profile_selected,

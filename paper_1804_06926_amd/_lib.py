@@ -50,6 +50,9 @@ def _load():
     lib.tc_count_triangles.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options),
                                        ctypes.POINTER(ctypes.c_uint64), vp]
     lib.tc_count_triangles_async.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp]
+    lib.tc_list_workspace_size.argtypes = [i64, i32, ctypes.POINTER(Options), ctypes.POINTER(sz)]
+    lib.tc_list_triangles.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, i64,
+                                      ctypes.POINTER(ctypes.c_uint64)]
     lib.tc_edge_support.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp,
                                     ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_uint64)]
     lib.tc_clustering.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp,
@@ -69,7 +72,7 @@ def _load():
     lib.tc_last_error.argtypes = [vp]
     lib.tc_last_error.restype = ctypes.c_char_p
     for f in ("tc_create", "tc_destroy", "tc_workspace_size", "tc_count_triangles", "tc_count_triangles_async",
-              "tc_clustering", "tc_edge_support",
+              "tc_clustering", "tc_edge_support", "tc_list_workspace_size", "tc_list_triangles",
               "tc_edge_counts",
               "tc_build_csr", "tc_radix_sort_u64"):
         getattr(lib, f).restype = ctypes.c_int
@@ -244,6 +247,32 @@ def clustering(edges, num_vertices: int, per_vertex: bool = False, select: int =
     _check(st, ctx)
     res = (coeff, int(T.value), int(W.value), float(tr.value))
     return res + (pv,) if per_vertex else res
+
+
+def list_triangles(edges, num_vertices: int, select: int = SELECT_HEURISTIC, workspace=None):
+    """All triangles as an int32 tensor [T, 3] of original ids (u, v, w), u before v before w in
+    (degree, id) order; grouped by the edge (u, v) in CSR order, unordered inside a group."""
+    torch = _torch()
+    e = _edges_arg(edges)
+    ctx, idx = _ctx(e.device)
+    E = e.shape[0]
+    o = _options(select, False)
+    nbytes = ctypes.c_size_t()
+    _check(_load().tc_list_workspace_size(E, num_vertices, ctypes.byref(o), ctypes.byref(nbytes)), None)
+    ws = _workspace(idx, int(nbytes.value), workspace)
+    T = ctypes.c_uint64()
+    cap = 0
+    out = None
+    for _ in range(2):   # the first call reports T when the capacity is short
+        out = torch.empty((max(cap, 1), 3), dtype=torch.int32, device=e.device)
+        st = _load().tc_list_triangles(ctx, e.data_ptr() if E else None, E, num_vertices, ws.data_ptr(), ws.numel(),
+                                       ctypes.byref(o), out.data_ptr(), cap, ctypes.byref(T))
+        if st == 3 and T.value > cap:
+            cap = int(T.value)
+            continue
+        _check(st, ctx)
+        break
+    return out[: int(T.value)]
 
 
 def edge_support(edges, num_vertices: int, select: int = SELECT_HEURISTIC, workspace=None):

@@ -294,6 +294,53 @@ tc_status tc_edge_counts(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges,
     return st;
 }
 
+tc_status tc_list_workspace_size(int64_t num_edges, int32_t num_vertices, const tc_options* opts, size_t* bytes) {
+    if (!bytes || num_edges < 0 || num_vertices < 0 || !options_ok(opts)) return TC_ERR_INVALID_ARG;
+    *bytes = tcx::make_layout(num_edges, num_vertices).total + tcx::list_extra_bytes(num_edges);
+    return TC_OK;
+}
+
+tc_status tc_list_triangles(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                            void* d_workspace, size_t workspace_bytes, const tc_options* opts, int32_t* d_out,
+                            int64_t capacity, uint64_t* h_count) {
+    if (!h_count || capacity < 0 || (capacity > 0 && !d_out))
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "null output or negative capacity");
+    if (num_edges < 0 || num_vertices < 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "negative size");
+    const size_t base = tcx::make_layout(num_edges, num_vertices).total;
+    if (num_edges > 0 && workspace_bytes < base + tcx::list_extra_bytes(num_edges))
+        return arg_fail(ctx, TC_ERR_WORKSPACE, "workspace below tc_list_workspace_size");
+    char* ws = (char*)d_workspace;
+    uint64_t* offs = (uint64_t*)(ws + base);
+    uint32_t* cnt = (uint32_t*)(ws + base + tcx::align_up(8 * ((size_t)num_edges + 1), 256));
+    // pass 1: the count and the per-edge counts
+    tcx::RunArgs ra = {};
+    ra.per_edge_counts = num_edges > 0 ? cnt : nullptr;
+    tc_status st = run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, opts, ra);
+    if (st != TC_OK) return st;
+    const uint64_t T = ctx->h_ctrl->total;
+    *h_count = T;
+    if (T == 0) return TC_OK;
+    if (T > (uint64_t)capacity) return arg_fail(ctx, TC_ERR_WORKSPACE, "output capacity below the triangle count");
+    // slot offsets per in-edge, then pass 2 writes the triangles
+    DeviceGuard guard(ctx->device);
+    const tcx::Layout L = tcx::make_layout(num_edges, num_vertices);
+    const tcx::Ctrl* dctrl = (const tcx::Ctrl*)(ws + L.ctrl);
+    const size_t m = ctx->h_ctrl->m;
+    tcx::widen_u32_u64(cnt, offs, dctrl, (size_t)num_edges, ctx->stream);
+    tcx::scan_exclusive_sum_u64(offs, offs, m, ws + L.scan_tmp, ctx->stream);
+    tcx::fill_u32(cnt, 0u, m, ctx->stream);
+    tcx::RunArgs r2 = ra;
+    r2.per_edge_counts = nullptr;
+    r2.events = nullptr;
+    r2.list_off = offs;
+    r2.list_cur = cnt;
+    r2.list_out = d_out;
+    hipError_t e = tcx::run_list_pass(r2);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "list triangles");
+    return TC_OK;
+}
+
 tc_status tc_edge_support(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
                           void* d_workspace, size_t workspace_bytes, const tc_options* opts, int32_t* d_out_edges,
                           uint32_t* d_out_support, int64_t* h_num_out, uint64_t* h_count) {

@@ -25,6 +25,12 @@ struct IsectArgs {
     uint64_t* per_middle;       // [n] or null: triangles whose middle vertex is v (rank space)
     uint32_t* support;          // [m] or null: triangles containing each kept edge (CSR edge order)
     uint32_t col_narrow;        // 1 when col spans less than 4 GiB (32-bit byte offsets suffice)
+    // triangle listing (second pass): triangle i of in-edge e goes to
+    // list_out[3 * (list_off[e] + i)], as original ids (u, v, w)
+    const uint64_t* list_off;   // [m] or null
+    uint32_t* list_cur;         // [m] zeroed: per-edge cursors of the edge-centric kernels
+    int32_t* list_out;          // [T][3]
+    const uint32_t* inv;        // [n] rank -> original id
 };
 
 // Blocks of one intersection kernel resident per CU (from the occupancy API);

@@ -96,13 +96,23 @@ __device__ __forceinline__ void hit_vertex(const IsectArgs& a, uint32_t w) {
     if (a.per_vertex) atomicAdd((unsigned long long*)&a.per_vertex[w], 1ull);
 }
 
-// A hit w = col[ea] = col[eb]: ea is the edge (u, w) of the tail, eb the edge (v, w).
-__device__ __forceinline__ void hit(const IsectArgs& a, uint32_t w, uint32_t ea, uint32_t eb) {
+// Triangle (u, v, w) of in-edge e = (u -> v) at list slot pos, original ids.
+__device__ __forceinline__ void list_write(const IsectArgs& a, uint64_t pos, uint32_t e, uint32_t w) {
+    int32_t* o = a.list_out + 3 * pos;
+    o[0] = (int32_t)a.inv[a.src[e]];
+    o[1] = (int32_t)a.inv[a.col[e]];
+    o[2] = (int32_t)a.inv[w];
+}
+
+// A hit w = col[ea] = col[eb] for in-edge ein: ea is the edge (u, w) of the
+// tail, eb the edge (v, w).
+__device__ __forceinline__ void hit(const IsectArgs& a, uint32_t w, uint32_t ea, uint32_t eb, uint32_t ein) {
     hit_vertex(a, w);
     if (a.support) {
         atomicAdd(&a.support[ea], 1u);
         atomicAdd(&a.support[eb], 1u);
     }
+    if (a.list_out) list_write(a, a.list_off[ein] + atomicAdd(&a.list_cur[ein], 1u), ein, w);
 }
 
 // Position of x in the ascending list L[0..n), or n when absent.
@@ -140,8 +150,9 @@ __device__ __forceinline__ uint32_t col_at(const uint32_t* col, uint32_t i) {
 // Outputs of a bitmap launch: T only; also per in-edge counts (per-edge or
 // per-middle-vertex outputs); or also gathered per-vertex counts or edge
 // support (the hits per element of N+(v), for t[w] and the support of edge
-// vw, are gathered in LDS). Each mode sizes its LDS to what it uses.
-enum { BM_COUNT = 0, BM_ENTRY = 1, BM_GATHER = 2 };
+// vw, are gathered in LDS); or the triangle list (the per-entry count is the
+// cursor of the entry's slots). Each mode sizes its LDS to what it uses.
+enum { BM_COUNT = 0, BM_ENTRY = 1, BM_GATHER = 2, BM_LIST = 3 };
 
 template <int MODE, bool NARROW>
 __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* partials) {
@@ -342,7 +353,11 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                         for (int j = 0; j < UNROLL; ++j) {
                             const uint32_t x = xs[j];
                             if ((wd[j] >> (x & 31u)) & 1u) {
-                                atomicAdd(&s_cnt[ks[j]], 1u);
+                                const uint32_t slot = atomicAdd(&s_cnt[ks[j]], 1u);
+                                if (MODE == BM_LIST) {
+                                    const uint32_t e = s_base[ks[j]] + s_pref[ks[j]] - 1u;
+                                    list_write(a, a.list_off[e] + slot, e, x + wlo);
+                                }
                                 if (GATHER) {
                                     const uint32_t w = x + wlo;
                                     if (a.support)   // edge (u, w): the tail element's own position
@@ -432,7 +447,7 @@ __device__ __forceinline__ uint32_t find_seg(const Segs& S, uint32_t nseg, uint3
 // match at X[q] = Y[p] is edge ex0 + q and edge ey0 + p.
 __device__ __forceinline__ uint32_t search_list(const IsectArgs& a, const uint32_t* X, uint32_t nx,
                                                 const uint32_t* Y, uint32_t ny, uint32_t g, uint32_t gl,
-                                                uint32_t ex0, uint32_t ey0) {
+                                                uint32_t ex0, uint32_t ey0, uint32_t ein) {
     uint32_t c = 0;
     if (ny == 0) return 0;
     for (uint32_t q0 = gl; q0 < nx; q0 += 4u * g) {
@@ -466,7 +481,7 @@ __device__ __forceinline__ uint32_t search_list(const IsectArgs& a, const uint32
             const uint32_t q = q0 + (uint32_t)u * g;
             if (q < nx && lb[u] < ny && y1[u] == xv[u]) {
                 ++c;
-                hit(a, xv[u], ex0 + q, ey0 + lb[u]);
+                hit(a, xv[u], ex0 + q, ey0 + lb[u], ein);
             }
         }
     }
@@ -474,7 +489,8 @@ __device__ __forceinline__ uint32_t search_list(const IsectArgs& a, const uint32
 }
 
 // One in-edge by a group of g lanes: merge path (MERGE) or binary search.
-// ea0, eb0: CSR positions of A[0] (the tail) and B[0] (N+(v)).
+// ea0, eb0: CSR positions of A[0] (the tail) and B[0] (N+(v)); the in-edge
+// itself sits just before its tail, at ea0 - 1.
 template <bool MERGE>
 __device__ __forceinline__ uint32_t isect_edge(const IsectArgs& a, const uint32_t* A, uint32_t na, const uint32_t* B,
                                                uint32_t nb, uint32_t g, uint32_t gl, uint32_t ea0, uint32_t eb0) {
@@ -502,14 +518,14 @@ __device__ __forceinline__ uint32_t isect_edge(const IsectArgs& a, const uint32_
                 while (j < nb && B[j] < av[u]) ++j;
                 if (j < nb && B[j] == av[u]) {
                     ++c;
-                    hit(a, av[u], ea0 + i + u, eb0 + j);
+                    hit(a, av[u], ea0 + i + u, eb0 + j, ea0 - 1u);
                 }
             }
         }
     } else if (na <= nb) {
-        c = search_list(a, A, na, B, nb, g, gl, ea0, eb0);   // tail elements searched in N+(v)
+        c = search_list(a, A, na, B, nb, g, gl, ea0, eb0, ea0 - 1u);   // tail elements searched in N+(v)
     } else {
-        c = search_list(a, B, nb, A, na, g, gl, eb0, ea0);   // N+(v) searched in the tail
+        c = search_list(a, B, nb, A, na, g, gl, eb0, ea0, ea0 - 1u);   // N+(v) searched in the tail
     }
     return c;
 }
@@ -609,6 +625,7 @@ static int resident_blocks(const void* fn) {
 }
 
 static int bitmap_mode(const IsectArgs& a) {
+    if (a.list_out) return BM_LIST;
     if (a.per_vertex || a.support) return BM_GATHER;
     if (a.per_edge || a.per_middle) return BM_ENTRY;
     return BM_COUNT;
@@ -616,6 +633,8 @@ static int bitmap_mode(const IsectArgs& a) {
 
 static const void* bitmap_fn(int mode, bool narrow) {
     switch (mode) {
+        case BM_LIST: return narrow ? (const void*)k_isect_bitmap<BM_LIST, true>
+                                    : (const void*)k_isect_bitmap<BM_LIST, false>;
         case BM_GATHER: return narrow ? (const void*)k_isect_bitmap<BM_GATHER, true>
                                       : (const void*)k_isect_bitmap<BM_GATHER, false>;
         case BM_ENTRY: return narrow ? (const void*)k_isect_bitmap<BM_ENTRY, true>
@@ -626,7 +645,7 @@ static const void* bitmap_fn(int mode, bool narrow) {
 }
 
 int isect_blocks_per_cu(int ker, int mode) {
-    static int cache[NKERNEL][3] = {};
+    static int cache[NKERNEL][4] = {};
     int& c = cache[ker][mode];
     if (!c) {
         const void* fn = ker == KER_MERGE     ? (const void*)k_isect_edges<true>
@@ -650,7 +669,10 @@ void launch_isect(int ker, const IsectArgs& a, int grid, uint64_t* partials, hip
         case KER_BSEARCH: hipLaunchKernelGGL(k_isect_edges<false>, dim3(grid), dim3(IS_NT), 0, s, a, p); break;
         default: {
             const bool nw = a.col_narrow != 0;
-            if (mode == BM_GATHER) {
+            if (mode == BM_LIST) {
+                if (nw) hipLaunchKernelGGL((k_isect_bitmap<BM_LIST, true>), dim3(grid), dim3(IS_NT), 0, s, a, p);
+                else hipLaunchKernelGGL((k_isect_bitmap<BM_LIST, false>), dim3(grid), dim3(IS_NT), 0, s, a, p);
+            } else if (mode == BM_GATHER) {
                 if (nw) hipLaunchKernelGGL((k_isect_bitmap<BM_GATHER, true>), dim3(grid), dim3(IS_NT), 0, s, a, p);
                 else hipLaunchKernelGGL((k_isect_bitmap<BM_GATHER, false>), dim3(grid), dim3(IS_NT), 0, s, a, p);
             } else if (mode == BM_ENTRY) {

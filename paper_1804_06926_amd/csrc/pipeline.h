@@ -46,6 +46,9 @@ struct RunArgs {
     int64_t* csr_off;                // device [n+1]
     int32_t* csr_col;                // device [E]
     hipEvent_t* events;              // NSTAGE + 1 events, or null
+    const uint64_t* list_off;        // triangle listing pass: device [m] slot offsets per in-edge, or null
+    uint32_t* list_cur;              //   device [m] zeroed cursors
+    int32_t* list_out;               //   device [T][3] output
 };
 
 struct RunResult {
@@ -75,6 +78,13 @@ struct BatchArgs {
 // Enqueue the whole batched count (graph offsets already in the workspace).
 // r carries the stream, workspace and selection; its graph fields are set here.
 hipError_t run_batch(const BatchArgs& b, RunArgs& r);
+// After a full run on the same workspace: the three intersection kernels again,
+// writing the triangle list (r.list_*).
+hipError_t run_list_pass(const RunArgs& r);
+// out[i] = in[i] for i < m (device count), widening.
+void widen_u32_u64(const uint32_t* in, uint64_t* out, const Ctrl* ctrl, size_t cap, hipStream_t s);
+// Extra workspace of tc_list_triangles after make_layout(E, n).total: slot offsets, counts / cursors.
+size_t list_extra_bytes(int64_t E);
 // After a run with stop_before_isect: one intersection kernel over tiles [t0, t1).
 hipError_t launch_isect_range(const RunArgs& r, int ker, uint32_t t0, uint32_t t1);
 int stage_count();

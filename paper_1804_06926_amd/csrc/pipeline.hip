@@ -667,6 +667,10 @@ static IsectArgs isect_args(const RunArgs& r, const Layout& L, uint64_t* csc) {
     ia.per_vertex = (r.per_vertex || r.clustering) ? (uint64_t*)(ws + L.pv) : nullptr;
     ia.per_middle = r.per_middle ? (uint64_t*)(ws + L.pv) : nullptr;
     ia.support = r.support;
+    ia.list_off = r.list_off;
+    ia.list_cur = r.list_cur;
+    ia.list_out = r.list_out;
+    ia.inv = (const uint32_t*)(ws + L.inv);
     ia.col_narrow = r.E < ((int64_t)1 << 30) ? 1u : 0u;   // m <= E
     return ia;
 }
@@ -680,6 +684,28 @@ static uint64_t* csc_of(const RunArgs& r, const Layout& L) {
     uint64_t* sorted = (p1 & 1) ? (uint64_t*)(ws + L.keysB) : (uint64_t*)(ws + L.keysA);
     uint64_t* other = (p1 & 1) ? (uint64_t*)(ws + L.keysA) : (uint64_t*)(ws + L.keysB);
     return (p2 & 1) ? sorted : other;
+}
+
+hipError_t run_list_pass(const RunArgs& r) {
+    const Layout L = make_layout(r.E, r.n);
+    const IsectArgs ia = isect_args(r, L, csc_of(r, L));
+    uint64_t* partials = (uint64_t*)((char*)r.ws + L.isect_partials);
+    for (int k = 0; k < NKERNEL; ++k) launch_isect(k, ia, r.grid_override ? r.grid_override[k] : 0, partials, r.stream);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(NT) void k_widen(const uint32_t* __restrict__ in, uint64_t* __restrict__ out,
+                                              const Ctrl* ctrl) {
+    const uint32_t m = ctrl->m;
+    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < m; i += (uint64_t)gridDim.x * NT) out[i] = in[i];
+}
+
+void widen_u32_u64(const uint32_t* in, uint64_t* out, const Ctrl* ctrl, size_t cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_widen, dim3(grid_for(cap)), dim3(NT), 0, s, in, out, ctrl);
+}
+
+size_t list_extra_bytes(int64_t E) {
+    return align_up(8 * ((size_t)E + 1), 256) + align_up(4 * ((size_t)E > 0 ? (size_t)E : 1), 256);
 }
 
 hipError_t launch_isect_range(const RunArgs& r, int ker, uint32_t t0, uint32_t t1) {

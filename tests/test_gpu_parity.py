@@ -214,6 +214,43 @@ def test_edge_support_matches_oracle(tc, case, sel):
     assert T == g.count() and int(ref.astype(np.int64).sum()) == 3 * T
 
 
+@pytest.mark.parametrize("sel", SELECTS)
+@pytest.mark.parametrize("case", ["fig4", "k40", "wheel6", "friendship", "tripartite", "rmat12_dirty", "chung_lu",
+                                  "rgg_16k", "er_4096_32768", "bipartite"])
+def test_list_triangles(tc, case, sel):
+    """The listed triples are exactly the triangles: as many as the oracle counts,
+    each one a triangle of the simple graph, no two the same; each ordered
+    u before v before w in (input degree, id) order and grouped by edge (u, v)."""
+    e, n = CASES[case]()
+    print(f"case={case} select={sel} E={e.shape[0]} n={n}", flush=True)
+    g = oracle.Graph(e, n)
+    T = g.count()
+    tri = tc.list_triangles(dev(e), n, select=_sel(tc, sel)).cpu().numpy().astype(np.int64)
+    assert tri.shape == (T, 3)
+    if T == 0:
+        return
+    keys = set(_canon_keys(g.edges()).tolist())
+    u, v, w = tri[:, 0], tri[:, 1], tri[:, 2]
+    for a_, b_ in ((u, v), (v, w), (u, w)):
+        assert (a_ != b_).all()
+        assert all(k in keys for k in _canon_keys(np.stack([a_, b_], 1)).tolist())
+    srt = np.sort(tri, axis=1)
+    assert np.unique(srt, axis=0).shape[0] == T
+    deg = stages.input_degrees(e, n).astype(np.int64)
+    ku, kv, kw = deg[u] * n + u, deg[v] * n + v, deg[w] * n + w
+    assert (ku < kv).all() and (kv < kw).all()
+    pair = u * n + v
+    change = np.nonzero(np.diff(pair))[0]
+    starts = np.concatenate([[0], change + 1])
+    assert np.unique(pair[starts]).shape[0] == starts.shape[0]   # each edge's triangles are contiguous
+
+
+def test_list_triangles_empty(tc):
+    import torch
+    assert tc.list_triangles(torch.zeros((0, 2), dtype=torch.int32, device="cuda:0"), 4).shape == (0, 3)
+    assert tc.list_triangles(dev(graphgen.star(20)), 21).shape == (0, 3)
+
+
 def test_csr_export_matches_definition(tc):
     n = 1 << 12
     e = _dirty(graphgen.rmat(12, 16, seed=5), n, 5)
