@@ -335,9 +335,13 @@ tc_status tc_list_triangles(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edg
     r2.list_off = offs;
     r2.list_cur = cnt;
     r2.list_out = d_out;
+    r2.list_cap = (uint64_t)capacity;
     hipError_t e = tcx::run_list_pass(r2);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&ctx->h_ctrl->err, &dctrl->err, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "list triangles");
+    if (ctx->h_ctrl->err) return arg_fail(ctx, TC_ERR_HIP, "internal: listing pass disagrees with the count");
     return TC_OK;
 }
 

@@ -29,7 +29,8 @@ struct IsectArgs {
     // list_out[3 * (list_off[e] + i)], as original ids (u, v, w)
     const uint64_t* list_off;   // [m] or null
     uint32_t* list_cur;         // [m] zeroed: per-edge cursors of the edge-centric kernels
-    int32_t* list_out;          // [T][3]
+    int32_t* list_out;          // [list_cap][3]
+    uint64_t list_cap;          // triples list_out holds; a slot beyond sets error bit 3
     const uint32_t* inv;        // [n] rank -> original id
 };
 

@@ -98,6 +98,10 @@ __device__ __forceinline__ void hit_vertex(const IsectArgs& a, uint32_t w) {
 
 // Triangle (u, v, w) of in-edge e = (u -> v) at list slot pos, original ids.
 __device__ __forceinline__ void list_write(const IsectArgs& a, uint64_t pos, uint32_t e, uint32_t w) {
+    if (pos >= a.list_cap) {   // only if the two passes disagree
+        atomicOr(&a.ctrl->err, 8u);
+        return;
+    }
     int32_t* o = a.list_out + 3 * pos;
     o[0] = (int32_t)a.inv[a.src[e]];
     o[1] = (int32_t)a.inv[a.col[e]];

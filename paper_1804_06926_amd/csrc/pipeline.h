@@ -48,7 +48,8 @@ struct RunArgs {
     hipEvent_t* events;              // NSTAGE + 1 events, or null
     const uint64_t* list_off;        // triangle listing pass: device [m] slot offsets per in-edge, or null
     uint32_t* list_cur;              //   device [m] zeroed cursors
-    int32_t* list_out;               //   device [T][3] output
+    int32_t* list_out;               //   device [list_cap][3] output
+    uint64_t list_cap;
 };
 
 struct RunResult {

@@ -670,6 +670,7 @@ static IsectArgs isect_args(const RunArgs& r, const Layout& L, uint64_t* csc) {
     ia.list_off = r.list_off;
     ia.list_cur = r.list_cur;
     ia.list_out = r.list_out;
+    ia.list_cap = r.list_cap;
     ia.inv = (const uint32_t*)(ws + L.inv);
     ia.col_narrow = r.E < ((int64_t)1 << 30) ? 1u : 0u;   // m <= E
     return ia;
