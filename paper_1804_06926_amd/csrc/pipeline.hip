@@ -40,13 +40,14 @@ static unsigned grid_for(size_t n, unsigned cap = 16384) {
 // ------------------------------------------------------------------ degree
 // Input degree = loop-free valid pairs per vertex. Device-wide atomics would
 // serialise on hub vertices, so the 2E endpoints are first partitioned by
-// their high bits (one radix pass when n <= 2^22), and each bucket of 2^bw
-// vertices is then counted in an LDS histogram. Endpoints of loops and
-// invalid pairs are written as `sentinel`; with sentinel = n - 1 each block
-// also records how many it wrote, and they are taken off vertex n - 1 at the
-// end. Larger n falls back to a full sort of the endpoints (sentinel n, which
-// sorts last) and run boundaries.
+// their high bits (one radix pass for ids of up to 22 bits, two up to 27), and
+// each bucket of 2^bw vertices is then counted in an LDS histogram. Endpoints
+// of loops and invalid pairs are written as `sentinel`; with sentinel = n - 1
+// each block also records how many it wrote, and they are taken off vertex
+// n - 1 at the end. Wider ids fall back to a full sort of the endpoints
+// (sentinel n, which sorts last) and run boundaries.
 constexpr int DEG_MAX_BW = 14;        // LDS histogram of 2^14 counters (64 KB)
+constexpr int DEG_MAX_BUCKET_BITS = 13;   // up to 8192 buckets (ids below 2^27)
 constexpr unsigned DEG_EP_BLOCKS = 1024;
 
 __global__ __launch_bounds__(NT) void k_endpoints(const int2* __restrict__ edges, uint64_t E, int32_t n,
@@ -75,16 +76,19 @@ __global__ __launch_bounds__(NT) void k_endpoints(const int2* __restrict__ edges
     }
 }
 
-// bstart[b] = first position of bucket b in the partitioned endpoints (the
-// exclusive scan of the last pass's digit counts); bstart[nb] = 2E.
-__global__ __launch_bounds__(NT) void k_bucket_starts(const uint32_t* __restrict__ digit_tot, uint32_t nb,
-                                                      uint32_t total, uint32_t* __restrict__ bstart) {
-    __shared__ uint32_t scratch[NT / WAVE];
-    const uint32_t d = threadIdx.x;
-    const uint32_t c = (digit_tot && d < nb) ? digit_tot[d] : 0u;
-    const uint32_t ex = block_exclusive_scan<NT>(c, scratch);
-    if (d < nb) bstart[d] = digit_tot ? ex : 0u;
-    if (d == 0) bstart[nb] = total;
+// bstart[b] = first position of bucket b (ids >> bw == b) in the endpoints,
+// which the partition left ordered by bucket; bstart[nb] = len.
+__global__ __launch_bounds__(NT) void k_bucket_starts(const uint32_t* __restrict__ ep, uint32_t len, int bw,
+                                                      uint32_t nb, uint32_t* __restrict__ bstart) {
+    for (uint32_t b = blockIdx.x * NT + threadIdx.x; b <= nb; b += gridDim.x * NT) {
+        uint32_t lo = 0, hi = len;
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if ((ep[mid] >> bw) < b) lo = mid + 1;
+            else hi = mid;
+        }
+        bstart[b] = b == nb ? len : lo;
+    }
 }
 
 // Block (bucket b, split sp) counts its share of bucket b in LDS. One split:
@@ -268,7 +272,9 @@ __global__ __launch_bounds__(NT) void k_unique_write(const uint64_t* __restrict_
 // ------------------------------------------------------------------ CSC (in-edges grouped by v)
 // Key of an in-edge e = (u -> v) with work: v in the bits above sh, then e, and
 // (packed form, lbits > 0) the tail length in the low lbits bits; others get
-// v = n and sort last. The tail length is below sqrt(2E): an out-neighbour w
+// v = n - 1 and sort last: the top-ranked vertex has no out-neighbours, so
+// none of its in-edges has work, and ids then need bits_for(n) bits, not
+// bits_for(n + 1) (one pass less when n is a power of two). The tail length is below sqrt(2E): an out-neighbour w
 // of u has at least u's input degree, which is at least d+(u), so
 // d+(u)^2 <= sum of input degrees <= 2E. Packing it saves the later gather of
 // the row end of u. A length that does not fit sets error bit 1.
@@ -287,7 +293,7 @@ __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ co
             bad |= len >> lbits != 0;
             low = (low << lbits) | (len & ((1ull << lbits) - 1ull));
         }
-        keys[e] = ((uint64_t)(work ? v : (uint32_t)n) << sh) | low;
+        keys[e] = ((uint64_t)(work ? v : (uint32_t)(n - 1)) << sh) | low;
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, 2u);
 }
@@ -296,12 +302,13 @@ __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ co
 __global__ __launch_bounds__(NT) void k_csc_bounds(const uint64_t* __restrict__ keys, Ctrl* ctrl, int32_t n,
                                                    uint32_t* __restrict__ inend, int sh) {
     const uint32_t m = ctrl->m;
+    const uint32_t last = (uint32_t)(n - 1);   // the group of in-edges without work
     for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < m; i += (uint64_t)gridDim.x * NT) {
         const uint32_t v = (uint32_t)(keys[i] >> sh);
-        const uint32_t vn = i + 1 < m ? (uint32_t)(keys[i + 1] >> sh) : (uint32_t)n;
-        if (v < (uint32_t)n && vn != v) {
+        const uint32_t vn = i + 1 < m ? (uint32_t)(keys[i + 1] >> sh) : last;
+        if (v < last && vn != v) {
             inend[v] = (uint32_t)(i + 1);
-            if (vn == (uint32_t)n) ctrl->m_active = (uint32_t)(i + 1);
+            if (vn == last) ctrl->m_active = (uint32_t)(i + 1);
         }
     }
 }
@@ -602,7 +609,7 @@ static CscPacking csc_packing(int64_t E, int32_t n) {
     uint64_t r = (uint64_t)sqrt((double)twoE);   // floor(sqrt(2E)), the bound on d+(u)
     while (r * r > twoE) --r;
     while ((r + 1) * (r + 1) <= twoE) ++r;
-    const int eb = bits_for((uint64_t)E), lb = bits_for(r + 1), vb = bits_for((uint64_t)n + 1);
+    const int eb = bits_for((uint64_t)E), lb = bits_for(r + 1), vb = bits_for((uint64_t)n);
     if (vb + eb + lb <= 64) return {eb + lb, eb, lb};
     return {32, 32, 0};
 }
@@ -635,7 +642,7 @@ Layout make_layout(int64_t E, int32_t n) {
     L.tile_cap = ee / 16 + nn + 1;
     L.tiles = take(8 * L.tile_cap);
     L.partial = take(4 * (UQ_MAX_BLOCKS + 1));
-    L.bstart = take(4 * 260);
+    L.bstart = take(4 * ((1u << DEG_MAX_BUCKET_BITS) + 4));
     L.isect_partials = take(isect_partials_bytes());
     L.scan_tmp = take(scan_temp_bytes());
     L.radix_tmp = take(radix_temp_bytes(2 * ee > nn ? 2 * ee : nn));
@@ -681,7 +688,7 @@ static uint64_t* csc_of(const RunArgs& r, const Layout& L) {
     char* ws = (char*)r.ws;
     const int nb = bits_for((uint64_t)r.n) > 0 ? bits_for((uint64_t)r.n) : 1;
     const int p1 = (2 * nb + 7) / 8;                   // passes of the pair sort
-    const int p2 = (bits_for((uint64_t)r.n + 1) + 7) / 8;   // passes of the CSC sort
+    const int p2 = (bits_for((uint64_t)r.n) + 7) / 8;   // passes of the CSC sort
     uint64_t* sorted = (p1 & 1) ? (uint64_t*)(ws + L.keysB) : (uint64_t*)(ws + L.keysA);
     uint64_t* other = (p1 & 1) ? (uint64_t*)(ws + L.keysA) : (uint64_t*)(ws + L.keysB);
     return (p2 & 1) ? sorted : other;
@@ -754,9 +761,10 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     mark(0);
     // ---- degree: input pairs per vertex, from the sorted endpoints
     fill_u32((uint32_t*)ctrl, 0u, sizeof(Ctrl) / 4, s);
+    // bucket width: one partition pass up to 22-bit ids, two (buckets of 2^14) up to 27 bits
     const int vbits = bits_for((uint64_t)n);               // vertex ids fit in vbits bits
-    const int bw = vbits - 8 > 12 ? vbits - 8 : (vbits < 12 ? vbits : 12);
-    const bool bucketed = bw <= DEG_MAX_BW;
+    const int bw = vbits <= 20 ? (vbits < 12 ? vbits : 12) : (vbits <= 22 ? vbits - 8 : DEG_MAX_BW);
+    const bool bucketed = vbits - bw <= DEG_MAX_BUCKET_BITS;
     {
         uint32_t* ep = (uint32_t*)keysA;       // 2E uint32 fit in E uint64
         uint32_t* ep_alt = (uint32_t*)keysB;
@@ -764,15 +772,14 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         hipLaunchKernelGGL(k_endpoints, dim3(eg), dim3(NT), 0, s, edges, (uint64_t)E, n,
                            bucketed ? (uint32_t)(n - 1) : (uint32_t)n, ep, ctrl, partial);
         if (bucketed) {
-            // partition by bits [bw, vbits) (at most 8: one pass), then count per bucket
+            // partition by bits [bw, vbits), then count per bucket
             const uint32_t nb = 1u << (vbits - bw);
             int a0 = 0;
             if (vbits > bw)
                 a0 = radix_sort_u32(ep, ep_alt, nullptr, nullptr, nullptr, (size_t)(2 * E), bw, vbits, radix_tmp, s);
             uint32_t* bst = (uint32_t*)(ws + L.bstart);
-            hipLaunchKernelGGL(k_bucket_starts, dim3(1), dim3(NT), 0, s,
-                               vbits > bw ? radix_last_digit_totals(radix_tmp, (size_t)(2 * E)) : nullptr, nb,
-                               (uint32_t)(2 * E), bst);
+            hipLaunchKernelGGL(k_bucket_starts, dim3(grid_for((size_t)nb + 1)), dim3(NT), 0, s, a0 ? ep_alt : ep,
+                               (uint32_t)(2 * E), bw, nb, bst);
             uint32_t splits = 1;
             while (nb * splits < 256u && (uint64_t)splits * 65536u < (uint64_t)(2 * E) && splits < 64u) splits *= 2;
             if (splits > 1) fill_u32(deg, 0u, (size_t)n, s);
@@ -833,7 +840,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         return hipGetLastError();
     }
     // ---- CSC: in-edges with work grouped by v (the sorted pair keys are free now)
-    const int nbv = bits_for((uint64_t)n + 1);
+    const int nbv = bits_for((uint64_t)n);   // in-edge groups: ids 0 .. n - 1 (n - 1 = no work)
     const CscPacking pk = csc_packing(E, n);
     hipLaunchKernelGGL(k_csc_keys, dim3(grid_for((size_t)E)), dim3(NT), 0, s, col, src, off, ctrl, n, other, pk.sh,
                        pk.lbits);

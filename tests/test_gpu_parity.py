@@ -65,6 +65,8 @@ CASES = {
     "isolated_tail": lambda: (graphgen.complete(30), 5000),
     # ids over 22 bits: the degree count uses its widest LDS buckets (2^14 vertices)
     "sparse_22bit": lambda: (_dirty(graphgen.chung_lu(4_100_000, 2_000_000, seed=12), 4_100_000, 12), 4_100_000),
+    # ids over 25 bits: two partition passes, buckets of 2^14 vertices
+    "sparse_25bit": lambda: (graphgen.chung_lu(20_000_000, 1_500_000, seed=15), 20_000_000),
     # ids over 12 bits: no partition pass, one bucket counted by several blocks
     "dense_12bit": lambda: (graphgen.erdos_renyi(4000, 300_000, seed=13), 4000),
     # ids over 13 bits: a one-bit partition, two buckets counted by several blocks each
