@@ -175,18 +175,37 @@ __global__ __launch_bounds__(NT) void k_rank(const uint64_t* __restrict__ sorted
 // ------------------------------------------------------------------ orient (filter by degree order)
 // Pair -> (lo rank << nb) | hi rank. Loops and invalid ids become the all-ones
 // sentinel on 2*nb bits, which exceeds every valid key (lo rank <= n - 2).
+// Eight pairs per thread per step, all loads issued before any is used: the
+// rank lookups are random gathers, so the kernel lives on memory-level
+// parallelism.
+constexpr int OR_U = 8;
 __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, uint64_t E, int32_t n,
                                                const uint32_t* __restrict__ rank, int nb, uint64_t sentinel,
                                                uint64_t* __restrict__ keys) {
-    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < E; i += (uint64_t)gridDim.x * NT) {
-        const int2 e = edges[i];
-        uint64_t key = sentinel;
-        if (e.x >= 0 && e.x < n && e.y >= 0 && e.y < n && e.x != e.y) {
-            const uint32_t a = rank[e.x], b = rank[e.y];
-            const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-            key = ((uint64_t)lo << nb) | hi;
+    const uint64_t stride = (uint64_t)gridDim.x * NT;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * NT + threadIdx.x; i0 < E; i0 += stride * OR_U) {
+        int2 ed[OR_U];
+#pragma unroll
+        for (int k = 0; k < OR_U; ++k) {
+            const uint64_t i = i0 + k * stride;
+            ed[k] = i < E ? edges[i] : make_int2(-1, -1);
         }
-        keys[i] = key;
+        uint32_t ra[OR_U], rb[OR_U];
+        bool ok[OR_U];
+#pragma unroll
+        for (int k = 0; k < OR_U; ++k) {
+            ok[k] = ed[k].x >= 0 && ed[k].x < n && ed[k].y >= 0 && ed[k].y < n && ed[k].x != ed[k].y;
+            ra[k] = rank[ok[k] ? ed[k].x : 0];
+            rb[k] = rank[ok[k] ? ed[k].y : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < OR_U; ++k) {
+            const uint64_t i = i0 + k * stride;
+            if (i < E) {
+                const uint32_t lo = ra[k] < rb[k] ? ra[k] : rb[k], hi = ra[k] < rb[k] ? rb[k] : ra[k];
+                keys[i] = ok[k] ? (((uint64_t)lo << nb) | hi) : sentinel;
+            }
+        }
     }
 }
 
@@ -283,17 +302,35 @@ __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ co
                                                  uint64_t* __restrict__ keys, int sh, int lbits) {
     const uint32_t m = ctrl->m;
     bool bad = false;
-    for (uint64_t e = (uint64_t)blockIdx.x * NT + threadIdx.x; e < m; e += (uint64_t)gridDim.x * NT) {
-        const uint32_t v = col[e];
-        const uint32_t end = off[src[e] + 1];
-        const bool work = (e + 1 < end) && (off[v + 1] > off[v]);
-        uint64_t low = e;
-        if (lbits > 0) {
-            const uint64_t len = work ? end - (e + 1) : 0u;
-            bad |= len >> lbits != 0;
-            low = (low << lbits) | (len & ((1ull << lbits) - 1ull));
+    const uint64_t stride = (uint64_t)gridDim.x * NT;
+    for (uint64_t e0 = (uint64_t)blockIdx.x * NT + threadIdx.x; e0 < m; e0 += stride * OR_U) {
+        uint32_t v[OR_U], u[OR_U];
+#pragma unroll
+        for (int k = 0; k < OR_U; ++k) {   // loads of all OR_U edges in flight together
+            const uint64_t e = e0 + k * stride;
+            v[k] = e < m ? col[e] : 0u;
+            u[k] = e < m ? src[e] : 0u;
         }
-        keys[e] = ((uint64_t)(work ? v : (uint32_t)(n - 1)) << sh) | low;
+        uint32_t end[OR_U], d0[OR_U], d1[OR_U];
+#pragma unroll
+        for (int k = 0; k < OR_U; ++k) {
+            end[k] = off[u[k] + 1];
+            d0[k] = off[v[k]];
+            d1[k] = off[v[k] + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < OR_U; ++k) {
+            const uint64_t e = e0 + k * stride;
+            if (e >= m) continue;
+            const bool work = (e + 1 < end[k]) && (d1[k] > d0[k]);
+            uint64_t low = e;
+            if (lbits > 0) {
+                const uint64_t len = work ? end[k] - (e + 1) : 0u;
+                bad |= len >> lbits != 0;
+                low = (low << lbits) | (len & ((1ull << lbits) - 1ull));
+            }
+            keys[e] = ((uint64_t)(work ? v[k] : (uint32_t)(n - 1)) << sh) | low;
+        }
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, 2u);
 }
@@ -812,7 +849,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     // ---- orient
     const int nb = bits_for((uint64_t)n) > 0 ? bits_for((uint64_t)n) : 1;
     const uint64_t sentinel = (2 * nb >= 64) ? ~0ull : ((1ull << (2 * nb)) - 1ull);
-    hipLaunchKernelGGL(k_orient, dim3(grid_for((size_t)E)), dim3(NT), 0, s, edges, (uint64_t)E, n, rank, nb, sentinel,
+    hipLaunchKernelGGL(k_orient, dim3(grid_for(((size_t)E + OR_U - 1) / OR_U)), dim3(NT), 0, s, edges, (uint64_t)E, n, rank, nb, sentinel,
                        keysA);
     mark(3);
     // ---- sort oriented pairs
@@ -842,7 +879,8 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     // ---- CSC: in-edges with work grouped by v (the sorted pair keys are free now)
     const int nbv = bits_for((uint64_t)n);   // in-edge groups: ids 0 .. n - 1 (n - 1 = no work)
     const CscPacking pk = csc_packing(E, n);
-    hipLaunchKernelGGL(k_csc_keys, dim3(grid_for((size_t)E)), dim3(NT), 0, s, col, src, off, ctrl, n, other, pk.sh,
+    hipLaunchKernelGGL(k_csc_keys, dim3(grid_for(((size_t)E + OR_U - 1) / OR_U)), dim3(NT), 0, s, col, src, off, ctrl,
+                       n, other, pk.sh,
                        pk.lbits);
     const int alt2 =
         radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, pk.sh, pk.sh + nbv, radix_tmp, s);
