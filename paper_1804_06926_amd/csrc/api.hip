@@ -165,7 +165,7 @@ tc_status run(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* w
         ctx->have_times = 1;
     }
     if (ctx->h_ctrl->err & 1u) return arg_fail(ctx, TC_ERR_VERTEX_RANGE, "vertex id outside [0, num_vertices)");
-    if (ctx->h_ctrl->err) return arg_fail(ctx, TC_ERR_HIP, "internal bound violated (tail length)");
+    if (ctx->h_ctrl->err) return arg_fail(ctx, TC_ERR_HIP, "internal bound violated");
     return TC_OK;
 }
 
@@ -548,7 +548,7 @@ tc_status tc_count_triangles_batch(tc_ctx* ctx, const int32_t* d_edges, const in
     if (e != hipSuccess) return hip_fail(ctx, e, "read batch counts");
     ctx->have_times = 0;
     if (ctx->h_ctrl->err & 1u) return arg_fail(ctx, TC_ERR_VERTEX_RANGE, "vertex id outside its graph's range");
-    if (ctx->h_ctrl->err) return arg_fail(ctx, TC_ERR_HIP, "internal bound violated (tail length)");
+    if (ctx->h_ctrl->err) return arg_fail(ctx, TC_ERR_HIP, "internal bound violated");
     memcpy(h_counts, ctx->h_counts_pinned, sizeof(uint64_t) * (size_t)num_graphs);
     return TC_OK;
 }

@@ -293,15 +293,14 @@ __global__ __launch_bounds__(NT) void k_unique_write(const uint64_t* __restrict_
 // (packed form, lbits > 0) the tail length in the low lbits bits; others get
 // v = n - 1 and sort last: the top-ranked vertex has no out-neighbours, so
 // none of its in-edges has work, and ids then need bits_for(n) bits, not
-// bits_for(n + 1) (one pass less when n is a power of two). The tail length is below sqrt(2E): an out-neighbour w
-// of u has at least u's input degree, which is at least d+(u), so
-// d+(u)^2 <= sum of input degrees <= 2E. Packing it saves the later gather of
-// the row end of u. A length that does not fit sets error bit 1.
+// bits_for(n + 1) (one pass less when n is a power of two). A length that
+// does not fit the packed field is stored as all ones, and the row end of u is
+// gathered for that entry later. Packing saves that gather for the others.
 __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ col, const uint32_t* __restrict__ src,
                                                  const uint32_t* __restrict__ off, Ctrl* ctrl, int32_t n,
                                                  uint64_t* __restrict__ keys, int sh, int lbits) {
     const uint32_t m = ctrl->m;
-    bool bad = false;
+    const uint64_t esc = (1ull << lbits) - 1ull;   // escape: length gathered at expansion
     const uint64_t stride = (uint64_t)gridDim.x * NT;
     for (uint64_t e0 = (uint64_t)blockIdx.x * NT + threadIdx.x; e0 < m; e0 += stride * OR_U) {
         uint32_t v[OR_U], u[OR_U];
@@ -326,13 +325,11 @@ __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ co
             uint64_t low = e;
             if (lbits > 0) {
                 const uint64_t len = work ? end[k] - (e + 1) : 0u;
-                bad |= len >> lbits != 0;
-                low = (low << lbits) | (len & ((1ull << lbits) - 1ull));
+                low = (low << lbits) | (len < esc ? len : esc);
             }
             keys[e] = ((uint64_t)(work ? v[k] : (uint32_t)(n - 1)) << sh) | low;
         }
     }
-    if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, 2u);
 }
 
 // inend[v] = one past the last in-edge of v in the sorted order; m_active.
@@ -362,7 +359,9 @@ __global__ __launch_bounds__(NT) void k_csc_expand(uint64_t* __restrict__ csc, c
         const uint64_t key = csc[i];
         if (lbits > 0) {
             const uint32_t e = (uint32_t)((key >> lbits) & emask);
-            csc[i] = (uint64_t)(e + 1u) | ((uint64_t)(e + 1u + (uint32_t)(key & lmask)) << 32);
+            const uint64_t len = key & lmask;
+            const uint32_t end = len != lmask ? e + 1u + (uint32_t)len : off[src[e] + 1];
+            csc[i] = (uint64_t)(e + 1u) | ((uint64_t)end << 32);
         } else {
             const uint32_t e = (uint32_t)key;
             csc[i] = (uint64_t)(e + 1u) | ((uint64_t)off[src[e] + 1] << 32);
@@ -636,7 +635,9 @@ void publish_result(const Ctrl* ctrl, uint64_t* result, uint64_t range_status, u
     hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, ctrl, result, range_status, internal_status);
 }
 
-// Packed in-edge keys when v, e and the tail length fit in 64 bits.
+// Packed in-edge keys: v, e, and the tail length in the bits left over (at
+// most what the bound d+(u) <= sqrt(2E) needs; lengths that do not fit are
+// escaped). Without room for at least 6 length bits, e alone is kept.
 struct CscPacking {
     int sh, ebits, lbits;
 };
@@ -646,8 +647,10 @@ static CscPacking csc_packing(int64_t E, int32_t n) {
     uint64_t r = (uint64_t)sqrt((double)twoE);   // floor(sqrt(2E)), the bound on d+(u)
     while (r * r > twoE) --r;
     while ((r + 1) * (r + 1) <= twoE) ++r;
-    const int eb = bits_for((uint64_t)E), lb = bits_for(r + 1), vb = bits_for((uint64_t)n);
-    if (vb + eb + lb <= 64) return {eb + lb, eb, lb};
+    const int eb = bits_for((uint64_t)E), vb = bits_for((uint64_t)n);
+    int lb = bits_for(r + 2);   // lengths below r + 1, plus the escape value
+    if (lb > 64 - vb - eb) lb = 64 - vb - eb;
+    if (lb >= 6) return {eb + lb, eb, lb};
     return {32, 32, 0};
 }
 

@@ -243,32 +243,57 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ k
     hist[(size_t)d * ntiles + blockIdx.x] = t;
 }
 
-// One block per digit d: exclusive scan, in place, of the digit's row of tile
-// counts hist[d * ntiles .. +ntiles); the row total goes to digit_tot[d].
+// Block (d, s): exclusive scan, in place, of segment s (RS_ROW_SEG tile counts)
+// of digit d's row hist[d * ntiles .. +ntiles). With one segment per row the
+// row total goes to digit_tot[d]; otherwise the segment total goes to
+// seg_tot[d * nseg + s] and k_radix_rowfix adds the carries.
 constexpr int RS_ROW_ITEMS = 8;
+constexpr uint32_t RS_ROW_SEG = 4 * RS_NT * RS_ROW_ITEMS;   // 8192 tile counts per segment
 __global__ __launch_bounds__(RS_NT) void k_radix_rowscan(uint32_t* __restrict__ hist, uint32_t ntiles,
-                                                         uint32_t* __restrict__ digit_tot) {
+                                                         uint32_t* __restrict__ digit_tot,
+                                                         uint32_t* __restrict__ seg_tot) {
     __shared__ uint32_t scratch[RS_WAVES];
     uint32_t* row = hist + (size_t)blockIdx.x * ntiles;
+    const uint32_t s0 = blockIdx.y * RS_ROW_SEG;
+    const uint32_t s1 = s0 + RS_ROW_SEG < ntiles ? s0 + RS_ROW_SEG : ntiles;
     uint32_t carry = 0;
-    for (uint32_t base = 0; base < ntiles; base += RS_NT * RS_ROW_ITEMS) {
+    for (uint32_t base = s0; base < s1; base += RS_NT * RS_ROW_ITEMS) {
         const uint32_t i0 = base + threadIdx.x * RS_ROW_ITEMS;
         uint32_t v[RS_ROW_ITEMS], sum = 0;
 #pragma unroll
         for (int k = 0; k < RS_ROW_ITEMS; ++k) {
-            v[k] = i0 + k < ntiles ? row[i0 + k] : 0u;
+            v[k] = i0 + k < s1 ? row[i0 + k] : 0u;
             sum += v[k];
         }
         uint32_t total;
         uint32_t run = carry + block_exclusive_scan<RS_NT>(sum, scratch, &total);
 #pragma unroll
         for (int k = 0; k < RS_ROW_ITEMS; ++k) {
-            if (i0 + k < ntiles) row[i0 + k] = run;
+            if (i0 + k < s1) row[i0 + k] = run;
             run += v[k];
         }
         carry += total;
     }
-    if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
+    if (threadIdx.x == 0) {
+        if (gridDim.y == 1) digit_tot[blockIdx.x] = carry;
+        else seg_tot[blockIdx.x * gridDim.y + blockIdx.y] = carry;
+    }
+}
+
+// Block (d, s): adds the totals of segments 0..s-1 to segment s; the last
+// segment's block also writes the row total.
+__global__ __launch_bounds__(RS_NT) void k_radix_rowfix(uint32_t* __restrict__ hist, uint32_t ntiles,
+                                                        const uint32_t* __restrict__ seg_tot,
+                                                        uint32_t* __restrict__ digit_tot) {
+    const uint32_t d = blockIdx.x, sg = blockIdx.y, nseg = gridDim.y;
+    uint32_t carry = 0;
+    for (uint32_t q = 0; q < sg; ++q) carry += seg_tot[d * nseg + q];
+    if (sg == nseg - 1 && threadIdx.x == 0) digit_tot[d] = carry + seg_tot[d * nseg + sg];
+    if (sg == 0 || carry == 0) return;
+    uint32_t* row = hist + (size_t)d * ntiles;
+    const uint32_t s0 = sg * RS_ROW_SEG;
+    const uint32_t s1 = s0 + RS_ROW_SEG < ntiles ? s0 + RS_ROW_SEG : ntiles;
+    for (uint32_t i = s0 + threadIdx.x; i < s1; i += RS_NT) row[i] += carry;
 }
 
 template <typename KeyT, bool HAS_VAL>
@@ -355,9 +380,17 @@ __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const KeyT* __restrict_
     }
 }
 
+// Temporary layout: histogram table [256][ntiles + 1] | digit totals [256] (in the
+// scan-temporary area) | segment totals [256][segments].
+static size_t rs_nseg(size_t cap) {
+    const size_t ntiles = (cap + RS_TILE - 1) / RS_TILE;
+    return (ntiles + RS_ROW_SEG - 1) / RS_ROW_SEG;
+}
+
 size_t radix_temp_bytes(size_t cap) {
     const size_t ntiles = (cap + RS_TILE - 1) / RS_TILE + 1;
-    return align_up(sizeof(uint32_t) * 256 * ntiles, 256) + align_up(scan_temp_bytes(), 256);
+    return align_up(sizeof(uint32_t) * 256 * ntiles, 256) + align_up(scan_temp_bytes(), 256) +
+           align_up(sizeof(uint32_t) * 256 * (rs_nseg(cap) + 1), 256);
 }
 
 template <typename KeyT>
@@ -368,6 +401,8 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
     uint32_t* hist = (uint32_t*)temp;
     void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * ((cap + RS_TILE - 1) / RS_TILE + 1), 256);
     uint32_t* digit_tot = (uint32_t*)scan_tmp;   // 256 digit totals
+    uint32_t* seg_tot = (uint32_t*)((char*)scan_tmp + align_up(scan_temp_bytes(), 256));
+    const uint32_t nseg = (uint32_t)rs_nseg(cap);
     KeyT* kin = keys;
     KeyT* kout = keys_alt;
     uint32_t* vin = vals;
@@ -378,7 +413,9 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
         const uint32_t dmask = (1u << dbits) - 1u;
         hipLaunchKernelGGL(k_radix_hist<KeyT>, dim3(ntiles), dim3(RS_NT), 0, s, kin, d_count, (uint32_t)cap, shift,
                            dmask, hist, ntiles);
-        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(RS_NT), 0, s, hist, ntiles, digit_tot);
+        hipLaunchKernelGGL(k_radix_rowscan, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, digit_tot, seg_tot);
+        if (nseg > 1)
+            hipLaunchKernelGGL(k_radix_rowfix, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, seg_tot, digit_tot);
         if (vals) {
             hipLaunchKernelGGL((k_radix_scatter<KeyT, true>), dim3(ntiles), dim3(RS_NT), 0, s, kin, vin, kout, vout,
                                d_count, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot);
