@@ -5,8 +5,10 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 calls it, and it imports nothing from the GPU package: the two share no code.
 
 Contents
-  * ``tc_oracle.cpp`` (built into ``liboracle.so``): the forward algorithm and
-    definition-level per-vertex / per-edge counts; see that file's header.
+  * ``tc_oracle.cpp`` (built into ``liboracle.so``): the forward algorithm,
+    definition-level per-vertex / per-edge counts, the matrix formulation
+    (Algorithm 3, row by row) and the full-list variant; see that file's
+    header.
   * ``dense``: brute force over vertex triples, trace(A^3)/6 and the matrix
     formulation (Algorithm 3) on dense matrices, for small graphs.
   * ``stages``: plain numpy definitions of the intermediate products of the
@@ -61,6 +63,10 @@ def _load():
     lib.oracle_oriented_edge_counts.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
     lib.oracle_edge_support.argtypes = [vp, vp, ctypes.c_int]
     lib.oracle_pair_counts.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int, vp, ctypes.c_int]
+    lib.oracle_full_sum.argtypes = [vp, ctypes.c_int]
+    lib.oracle_full_sum.restype = ctypes.c_uint64
+    lib.oracle_matrix_rows.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int]
+    lib.oracle_matrix_rows.restype = ctypes.c_uint64
     _lib = lib
     return lib
 
@@ -142,6 +148,24 @@ class Graph:
             _load().oracle_pair_counts(self._h, p.ctypes.data, p.shape[0], {"simple": 0, "input": 1}[degree],
                                        out.ctypes.data, self.threads)
         return out
+
+    def full_sum(self) -> int:
+        """Full-list variant: sum over the edges of |N(a) n N(b)| (= 3T)."""
+        return int(_load().oracle_full_sum(self._h, self.threads)) if self.m else 0
+
+    def matrix_sum(self, order: int = ORDER_DEG_ID, upper: bool = False, row_sums: bool = False):
+        """Algorithm 3 row by row: sum of C = A o (L U) (= 2T; T with upper).
+
+        order: ORDER_DEG_ID (rows by increasing nonzeros, ties by id) or
+        ORDER_ID (no permutation). With row_sums, also the per-row sums of C
+        (uint64, original ids).
+        """
+        if order not in (ORDER_DEG_ID, ORDER_ID):
+            raise ValueError("order must be ORDER_DEG_ID or ORDER_ID")
+        rs = np.zeros(self.n, dtype=np.uint64) if row_sums else None
+        s = int(_load().oracle_matrix_rows(self._h, order, 1 if upper else 0,
+                                           rs.ctypes.data if row_sums and self.n else None, self.threads))
+        return (s, rs) if row_sums else s
 
     def edge_support(self) -> np.ndarray:
         out = np.zeros(self.m, dtype=np.uint32)

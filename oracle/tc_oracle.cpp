@@ -25,6 +25,11 @@
  *    This is the per-edge intersection size of Section 3.2.
  *  - oracle_edge_support: per edge, the number of triangles through it
  *    (the per-edge triangle support used by k-truss, Section 1).
+ *  - oracle_matrix_rows: the matrix formulation (Section 3.3, Algorithm 3),
+ *    row by row: C = A o (L U) without forming L U, per-row sums of C.
+ *  - oracle_full_sum: the full-list variant of the intersection method
+ *    (each edge once, whole neighbour lists; Section 4.2 without the induced
+ *    subgraph): the sum of |N(a) intersected with N(b)| over the edges.
  *
  * Integers only; every count is accumulated in uint64_t, so there is no
  * rounding anywhere.
@@ -313,6 +318,80 @@ void oracle_edge_support(const void* h, uint32_t* out, int threads) {
         out[i] = (uint32_t)merge_count(g->adj.data() + g->adj_off[a], g->adj_off[a + 1] - g->adj_off[a],
                                        g->adj.data() + g->adj_off[b], g->adj_off[b + 1] - g->adj_off[b]);
     }
+}
+
+/*
+ * Full-list variant: the edge list is filtered (each undirected edge once,
+ * here the canonical pairs) but every intersection takes the whole
+ * neighbour lists, N(a) with N(b). A triangle is found once at each of its
+ * three edges, so the returned sum is 3T.
+ */
+uint64_t oracle_full_sum(const void* h, int threads) {
+    const Graph* g = (const Graph*)h;
+    uint64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : total) num_threads(pick_threads(threads))
+    for (int64_t i = 0; i < g->m; ++i) {
+        int32_t a = (int32_t)(g->keys[i] >> 32), b = (int32_t)(uint32_t)g->keys[i];
+        total += merge_count(g->adj.data() + g->adj_off[a], g->adj_off[a + 1] - g->adj_off[a],
+                             g->adj.data() + g->adj_off[b], g->adj_off[b + 1] - g->adj_off[b]);
+    }
+    return total;
+}
+
+/*
+ * Matrix formulation (Section 3.3, Algorithm 3), row by row:
+ *   1. order the rows (and columns) by increasing number of nonzeros, ties
+ *      by id (order_mode 0), or keep the id order (order_mode 2);
+ *   2. L holds the entries (i, k) with k before i in that order, U the
+ *      entries (k, j) with k before j, so that A = L + U;
+ *   3-4. row i of C = A o (L U): for every k in row i of L and every j in
+ *      row k of U, C(i, j) gains one if A(i, j) is set (a dense marker of
+ *      row i of A stands in for the Hadamard product; B = L U is not stored);
+ *   5. T = (1/2) sum C (the sum of C, as the worked example of Figure 4
+ *      states; the printed last line sums A).
+ * upper = 1 keeps only the entries of C above the diagonal (j after i; the
+ * first optimisation of the matrix implementation in Section 3.3): their
+ * sum is T itself.
+ * row_sums (length n, original ids, may be NULL) receives sum_j C(i, j);
+ * returns sum C.
+ */
+uint64_t oracle_matrix_rows(const void* h, int order_mode, int upper, uint64_t* row_sums, int threads) {
+    const Graph* g = (const Graph*)h;
+    const int32_t n = g->n;
+    std::vector<int64_t> pos((size_t)n);   // place of each vertex in the row order
+    {
+        std::vector<int32_t> perm((size_t)n);
+        for (int32_t v = 0; v < n; ++v) perm[v] = v;
+        if (order_mode == 0)
+            std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return g->deg[a] < g->deg[b]; });
+        for (int32_t q = 0; q < n; ++q) pos[perm[q]] = q;
+    }
+    uint64_t total = 0;
+#pragma omp parallel num_threads(pick_threads(threads))
+    {
+        std::vector<uint8_t> mask((size_t)n, 0);
+#pragma omp for schedule(dynamic, 256) reduction(+ : total)
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t a0 = g->adj_off[i], a1 = g->adj_off[i + 1];
+            for (int64_t p = a0; p < a1; ++p) {   // row i of A (cut to the upper triangle if asked)
+                const int32_t j = g->adj[p];
+                if (!upper || pos[j] > pos[i]) mask[j] = 1;
+            }
+            uint64_t row = 0;
+            for (int64_t p = a0; p < a1; ++p) {
+                const int32_t k = g->adj[p];
+                if (pos[k] >= pos[i]) continue;   // L(i, k) needs k before i
+                for (int64_t r = g->adj_off[k]; r < g->adj_off[k + 1]; ++r) {
+                    const int32_t j = g->adj[r];
+                    if (pos[j] > pos[k]) row += mask[j];   // U(k, j) needs k before j
+                }
+            }
+            for (int64_t p = a0; p < a1; ++p) mask[g->adj[p]] = 0;
+            if (row_sums) row_sums[i] = row;
+            total += row;
+        }
+    }
+    return total;
 }
 
 }  // extern "C"
