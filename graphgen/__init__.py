@@ -249,3 +249,33 @@ def friendship(k: int) -> np.ndarray:
 
 def star(k: int) -> np.ndarray:
     return np.stack([np.zeros(k, dtype=np.int64), 1 + np.arange(k)], 1).astype(np.int32)
+
+
+def spread_hubs(n: int = 1 << 21, background: int = 2_000_000, hubs: int = 64, pool: int = 8000,
+                pool_degree: int = 4000, spread_degree: int = 1000, seed: int = 21) -> np.ndarray:
+    """Hubs whose neighbourhoods reach across the whole vertex range.
+
+    A uniform background of ``background`` random pairs over n vertices (low
+    degrees, so their degree ranks spread over the range); ``hubs`` vertices
+    joined in a clique; each hub joined to ``pool_degree`` vertices of a shared
+    pool of ``pool`` vertices (many triangles through hub pairs) and to
+    ``spread_degree`` uniform random vertices. numpy PCG64(seed); repeats and
+    loops may occur (the counting path drops them). Random order and direction.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    bg = rng.integers(0, n, size=(background, 2), dtype=np.int64)
+    ids = rng.choice(n, size=hubs + pool, replace=False)
+    H, P = ids[:hubs], ids[hubs:]
+    i, j = np.triu_indices(hubs, 1)
+    clique = np.stack([H[i], H[j]], 1)
+    parts = [bg, clique]
+    for h in H:
+        nb = rng.choice(P, size=pool_degree, replace=False)
+        parts.append(np.stack([np.full(pool_degree, h), nb], 1))
+        sp = rng.integers(0, n, size=spread_degree, dtype=np.int64)
+        parts.append(np.stack([np.full(spread_degree, h), sp], 1))
+    e = np.concatenate(parts)
+    e = e[rng.permutation(e.shape[0])]
+    flip = rng.random(e.shape[0]) < 0.5
+    e[flip] = e[flip][:, ::-1]
+    return np.ascontiguousarray(e, dtype=np.int32)

@@ -168,6 +168,50 @@ tc_status tc_edge_support(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges
                           int32_t* d_out_edges, uint32_t* d_out_support, int64_t* h_num_out, uint64_t* h_count);
 
 /*
+ * The paper's other formulations of the same count, for comparison with the
+ * filtered one above. All run the same canonicalisation, degree order and
+ * filtered CSR, then stream, for every kept edge (u -> v), one list of u
+ * against one list of v through the same three intersection kernels (counts
+ * only, no per-edge or per-vertex outputs):
+ *   TC_FORM_FILTERED     N+(u) against N+(v): T (Section 4.2,
+ *                        "tc-intersection-filtered"; same as
+ *                        tc_count_triangles).
+ *   TC_FORM_FULL         N(u) against N(v), the whole neighbour lists over
+ *                        the half-filtered edge list (Section 4.2 without the
+ *                        induced subgraph, "tc-intersection-full" of the
+ *                        speedup figure of Section 5): each triangle is found
+ *                        at its three edges, so the sum is 3T.
+ *   TC_FORM_MATRIX       Algorithm 3 with the rows in (degree, id) order:
+ *                        C = A o (L U) and T = (1/2) sum C, where row v of C
+ *                        collects, over the rows u of L(v, :) (the in-
+ *                        neighbours of v), the U row of u (N+(u)) masked by
+ *                        the A row of v (N(v)); B = L U is never formed.
+ *                        The sum is sum C = 2T.
+ *   TC_FORM_MATRIX_UPPER the same with the mask cut to the upper triangle
+ *                        (Section 3.3, first optimisation of the matrix
+ *                        implementation): N+(u) against N+(v), sum T.
+ * h_count receives T; h_sum (optional, may be NULL) the sum of the hits
+ * before the division (3T, 2T or T). A sum that the multiple does not divide
+ * is reported as TC_ERR_HIP (internal bound violated). The workspace must
+ * hold tc_formulation_workspace_size() bytes (the full and matrix forms add
+ * the symmetric adjacency: 4 (n + 1) + 8 num_edges bytes, rounded up).
+ * Selection modes as for tc_count_triangles.
+ */
+typedef enum tc_formulation {
+    TC_FORM_FILTERED = 0,
+    TC_FORM_FULL = 1,
+    TC_FORM_MATRIX = 2,
+    TC_FORM_MATRIX_UPPER = 3
+} tc_formulation;
+
+tc_status tc_formulation_workspace_size(int64_t num_edges, int32_t num_vertices, const tc_options* opts,
+                                        int formulation, size_t* bytes);
+tc_status tc_count_triangles_formulation(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges,
+                                         int32_t num_vertices, void* d_workspace, size_t workspace_bytes,
+                                         const tc_options* opts, int formulation, uint64_t* h_count,
+                                         uint64_t* h_sum);
+
+/*
  * Batched counting of many graphs in one pass (not in the paper; its small-
  * graph overhead remark in Section 5 motivates it). Graph g's pairs are
  * d_edges[h_edge_offsets[g] .. h_edge_offsets[g+1]) with graph-local ids in

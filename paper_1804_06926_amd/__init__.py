@@ -21,6 +21,8 @@ from ._lib import (  # noqa: F401
     clustering,
     count_triangles,
     count_triangles_async,
+    count_triangles_formulation,
+    FORMULATIONS,
     count_triangles_batch,
     edge_counts,
     edge_support,

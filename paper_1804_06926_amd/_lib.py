@@ -50,6 +50,8 @@ def _load():
     lib.tc_count_triangles.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options),
                                        ctypes.POINTER(ctypes.c_uint64), vp]
     lib.tc_count_triangles_async.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, vp]
+    lib.tc_formulation_workspace_size.argtypes = [i64, i32, ctypes.POINTER(Options), i32, ctypes.POINTER(sz)]
+    lib.tc_count_triangles_formulation.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), i32, vp, vp]
     lib.tc_list_workspace_size.argtypes = [i64, i32, ctypes.POINTER(Options), ctypes.POINTER(sz)]
     lib.tc_list_triangles.argtypes = [vp, vp, i64, i32, vp, sz, ctypes.POINTER(Options), vp, i64,
                                       ctypes.POINTER(ctypes.c_uint64)]
@@ -194,6 +196,39 @@ def count_triangles(edges, num_vertices: int, per_vertex: bool = False, select: 
     if timing:
         res.append(_timings(ctx))
     return res[0] if len(res) == 1 else tuple(res)
+
+
+FORMULATIONS = {"filtered": 0, "full": 1, "matrix": 2, "matrix_upper": 3}
+
+
+def count_triangles_formulation(edges, num_vertices: int, formulation: str = "full",
+                                select: int = SELECT_HEURISTIC, workspace=None, timing: bool = False):
+    """T by one of the paper's formulations, with the sum of hits it divides.
+
+    formulation: "filtered" (N+(u) against N+(v), sum T), "full" (whole
+    neighbour lists over the half-filtered edges, sum 3T), "matrix"
+    (Algorithm 3, C = A o (L U), sum of C = 2T) or "matrix_upper" (the
+    matrix form with the mask cut to the upper triangle, sum T).
+    Returns (T, sum), plus a dict of per-stage milliseconds with timing.
+    """
+    if formulation not in FORMULATIONS:
+        raise ValueError(f"unknown formulation {formulation!r}")
+    f = FORMULATIONS[formulation]
+    e = _edges_arg(edges)
+    ctx, idx = _ctx(e.device)
+    E = e.shape[0]
+    o = _options(select, timing)
+    lib = _load()
+    nb = ctypes.c_size_t()
+    _check(lib.tc_formulation_workspace_size(E, num_vertices, ctypes.byref(o), f, ctypes.byref(nb)), None)
+    ws = _workspace(idx, nb.value, workspace)
+    count, total = ctypes.c_uint64(), ctypes.c_uint64()
+    st = lib.tc_count_triangles_formulation(ctx, e.data_ptr() if E else None, E, num_vertices, ws.data_ptr(),
+                                            ws.numel(), ctypes.byref(o), f, ctypes.byref(count), ctypes.byref(total))
+    _check(st, ctx)
+    if timing:
+        return int(count.value), int(total.value), _timings(ctx)
+    return int(count.value), int(total.value)
 
 
 def count_triangles_async(edges, num_vertices: int, result=None, per_vertex=None, select: int = SELECT_HEURISTIC,

@@ -103,9 +103,11 @@ tc_status run(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* w
     if (((uintptr_t)d_edges & 7u) != 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "edge list must be 8-byte aligned");
     if (E > 0 && n == 0) return arg_fail(ctx, TC_ERR_VERTEX_RANGE, "edges given for an empty vertex set");
     const tcx::Layout L = tcx::make_layout(E, n);
+    const bool sym = ra.formulation == tcx::FORM_FULL || ra.formulation == tcx::FORM_MATRIX;
     if (E > 0) {
         if (!ws) return arg_fail(ctx, TC_ERR_INVALID_ARG, "null workspace");
-        if (ws_bytes < L.total) return arg_fail(ctx, TC_ERR_WORKSPACE, "workspace too small");
+        if (ws_bytes < L.total + (sym ? tcx::sym_extra_bytes(E, n) : 0))
+            return arg_fail(ctx, TC_ERR_WORKSPACE, "workspace too small");
     }
     DeviceGuard guard(ctx->device);
     const int sel = opts ? opts->select : TC_SELECT_HEURISTIC;
@@ -253,6 +255,36 @@ tc_status tc_count_triangles_async(tc_ctx* ctx, const int32_t* d_edges, int64_t 
     tcx::RunArgs ra = {};
     ra.per_vertex = d_per_vertex;
     return run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, opts, ra, d_result);
+}
+
+tc_status tc_formulation_workspace_size(int64_t num_edges, int32_t num_vertices, const tc_options* opts,
+                                        int formulation, size_t* bytes) {
+    if (!bytes || num_edges < 0 || num_vertices < 0 || !options_ok(opts)) return TC_ERR_INVALID_ARG;
+    if (formulation < TC_FORM_FILTERED || formulation > TC_FORM_MATRIX_UPPER) return TC_ERR_INVALID_ARG;
+    if (num_edges > kMaxEdges) return TC_ERR_UNSUPPORTED;
+    const bool sym = formulation == TC_FORM_FULL || formulation == TC_FORM_MATRIX;
+    *bytes = tcx::make_layout(num_edges, num_vertices).total +
+             (sym ? tcx::sym_extra_bytes(num_edges, num_vertices) : 0);
+    return TC_OK;
+}
+
+tc_status tc_count_triangles_formulation(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges,
+                                         int32_t num_vertices, void* d_workspace, size_t workspace_bytes,
+                                         const tc_options* opts, int formulation, uint64_t* h_count,
+                                         uint64_t* h_sum) {
+    if (!h_count) return arg_fail(ctx, TC_ERR_INVALID_ARG, "null count output");
+    if (formulation < TC_FORM_FILTERED || formulation > TC_FORM_MATRIX_UPPER)
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "unknown formulation");
+    tcx::RunArgs ra = {};
+    ra.formulation = formulation;
+    tc_status st = run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, opts, ra);
+    if (st != TC_OK) return st;
+    const uint64_t sum = ctx->h_ctrl->total;
+    const uint64_t k = (uint64_t)tcx::form_multiple(formulation);
+    if (sum % k) return arg_fail(ctx, TC_ERR_HIP, "internal bound violated");
+    *h_count = sum / k;
+    if (h_sum) *h_sum = sum;
+    return TC_OK;
 }
 
 tc_status tc_clustering(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,

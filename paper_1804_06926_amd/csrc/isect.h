@@ -32,6 +32,10 @@ struct IsectArgs {
     int32_t* list_out;          // [list_cap][3]
     uint64_t list_cap;          // triples list_out holds; a slot beyond sets error bit 3
     const uint32_t* inv;        // [n] rank -> original id
+    // 1: the tails are whole rows that may reach below and above the middle
+    // list (the full-list and matrix formulations); the bitmap kernel then clips
+    // each tail to the window it is testing. Count only.
+    uint32_t clip;
 };
 
 // Blocks of one intersection kernel resident per CU (from the occupancy API);

@@ -156,19 +156,90 @@ __device__ __forceinline__ uint32_t col_at(const uint32_t* col, uint32_t i) {
 // support (the hits per element of N+(v), for t[w] and the support of edge
 // vw, are gathered in LDS); or the triangle list (the per-entry count is the
 // cursor of the entry's slots). Each mode sizes its LDS to what it uses.
-enum { BM_COUNT = 0, BM_ENTRY = 1, BM_GATHER = 2, BM_LIST = 3 };
+// BM_CLIP counts only, for tails that are whole rows: each tail and the middle
+// list are cut to the window being tested, and windows holding no element of
+// the middle list are skipped.
+enum { BM_COUNT = 0, BM_ENTRY = 1, BM_GATHER = 2, BM_LIST = 3, BM_CLIP = 4, BM_NMODE = 5 };
+
+constexpr int EH = CHUNK_MAX / IS_NT;   // entries of a vertex per thread
+
+// First position p in [p, e) of the ascending col whose value is at least x (e if none).
+template <bool NARROW>
+__device__ __forceinline__ uint32_t first_at_least(const uint32_t* col, uint32_t p, uint32_t e, uint64_t x) {
+    while (p < e) {
+        const uint32_t mid = p + ((e - p) >> 1);
+        if ((uint64_t)col_at<NARROW>(col, mid) < x) p = mid + 1u;
+        else e = mid;
+    }
+    return p;
+}
+
+// Entry table of one vertex's in-edges in a tile, in LDS: entry k streams
+// items [s_pref[k], s_pref[k + 1]) of a flat item range, item q at
+// col[s_base[k] + q] (s_base = start - s_pref, modular). Tails of at least
+// LONG_TAIL items come first, then the shorter non-empty ones; empty tails are
+// left out, so s_pref is strictly increasing. Thread t holds entries t and
+// t + IS_NT (start st_h, length len_h; length 0 past the vertex's entries).
+// Returns the entries kept; nl = long entries, L = total items. Whole block;
+// contains barriers.
+template <bool CNT>
+__device__ __forceinline__ uint32_t entry_table(const uint32_t (&st_h)[EH], const uint32_t (&len_h)[EH],
+                                                uint32_t* s_pref, uint32_t* s_base, uint32_t* s_cnt,
+                                                uint32_t* scratch, uint32_t& nl, uint32_t& L) {
+    uint32_t pos_h[EH];
+    uint32_t cl = 0, cs = 0;   // long and non-empty short entries of the earlier passes
+#pragma unroll
+    for (int h = 0; h < EH; ++h) {   // both counts in one scan: long in the high half
+        const uint32_t len = len_h[h];
+        const uint32_t f = len >= LONG_TAIL ? 0x10000u : (len ? 1u : 0u);
+        uint32_t total;
+        const uint32_t ex = block_exclusive_scan<IS_NT>(f, scratch, &total);
+        pos_h[h] = len >= LONG_TAIL ? cl + (ex >> 16) : cs + (ex & 0xFFFFu);
+        cl += total >> 16;
+        cs += total & 0xFFFFu;
+    }
+#pragma unroll
+    for (int h = 0; h < EH; ++h) {   // lengths and starts in table order
+        if (!len_h[h]) continue;
+        const uint32_t pos = len_h[h] >= LONG_TAIL ? pos_h[h] : cl + pos_h[h];
+        s_pref[pos] = len_h[h];
+        s_base[pos] = st_h[h];
+        if (CNT) s_cnt[pos] = 0;
+    }
+    __syncthreads();
+    const uint32_t nt = cl + cs;
+    uint32_t carry = 0;
+#pragma unroll
+    for (int h = 0; h < EH; ++h) {   // in place: each thread rewrites its own slots
+        const uint32_t k = h * IS_NT + threadIdx.x;
+        const uint32_t len = k < nt ? s_pref[k] : 0u;
+        const uint32_t st = k < nt ? s_base[k] : 0u;
+        uint32_t total;
+        const uint32_t excl = block_exclusive_scan<IS_NT>(len, scratch, &total);
+        if (k < nt) {
+            s_pref[k] = carry + excl;
+            s_base[k] = st - (carry + excl);
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) s_pref[nt] = carry;
+    nl = cl;
+    L = carry;
+    return nt;
+}
 
 template <int MODE, bool NARROW>
 __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* partials) {
     constexpr bool GATHER = MODE == BM_GATHER;
-    constexpr bool need_cnt = MODE != BM_COUNT;
+    constexpr bool CLIP = MODE == BM_CLIP;
+    constexpr bool need_cnt = MODE != BM_COUNT && !CLIP;
     __shared__ uint32_t s_nv[GATHER ? NV_MAX : 1];
     __shared__ uint32_t s_wc[GATHER ? NV_MAX : 1];
     __shared__ uint32_t bm[BM_WORDS + 1];        // + one always-zero word for out-of-window positions
     __shared__ uint16_t s_wst[WT_MAX];           // entry holding the first item of each window of a chunk
     __shared__ uint32_t s_pref[CHUNK_MAX + 1];
     __shared__ uint32_t s_cnt[need_cnt ? CHUNK_MAX : 1];
-    __shared__ uint32_t s_base[CHUNK_MAX + 1];   // entry ne is read (unused) by lanes past the end
+    __shared__ uint32_t s_base[CHUNK_MAX + 1];   // entry nt is read (unused) by lanes past the end
     __shared__ uint8_t s_flag[IS_NT / WAVE][UNROLL][WAVE];    // entry-start marks, one slot per item offset
     __shared__ SegsT<SEG_MAX_BITMAP> S;
     for (int i = threadIdx.x; i <= BM_WORDS; i += IS_NT) bm[i] = 0;
@@ -183,14 +254,10 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
             const uint32_t ne = S.pref[sg + 1] - S.pref[sg];
             const uint32_t b0 = a.off[v], b1 = a.off[v + 1];
             const uint32_t nb = b1 - b0;
-            // entry table: tail base and exclusive prefix of tail lengths, long
-            // tails (at least one window of items) first, then the short ones;
-            // entry order inside a vertex is free (ne <= CHUNK_MAX = 2 * IS_NT,
-            // so two block scans cover each pass)
-            uint32_t st_h[CHUNK_MAX / IS_NT], len_h[CHUNK_MAX / IS_NT], lb_h[CHUNK_MAX / IS_NT];
-            uint32_t nl = 0;   // long entries
+            // the vertex's entries (ne <= CHUNK_MAX = 2 * IS_NT: two per thread)
+            uint32_t st_h[EH], len_h[EH];
 #pragma unroll
-            for (int h = 0; h < CHUNK_MAX / IS_NT; ++h) {
+            for (int h = 0; h < EH; ++h) {
                 const uint32_t k = h * IS_NT + threadIdx.x;
                 st_h[h] = len_h[h] = 0;
                 if (k < ne) {
@@ -198,37 +265,10 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                     st_h[h] = (uint32_t)ent;
                     len_h[h] = (uint32_t)(ent >> 32) - st_h[h];
                 }
-                uint32_t total;
-                lb_h[h] = nl + block_exclusive_scan<IS_NT>(len_h[h] >= LONG_TAIL ? 1u : 0u, S.scratch, &total);
-                nl += total;
             }
-#pragma unroll
-            for (int h = 0; h < CHUNK_MAX / IS_NT; ++h) {   // lengths and starts in entry order
-                const uint32_t k = h * IS_NT + threadIdx.x;
-                if (k < ne) {
-                    const uint32_t pos = len_h[h] >= LONG_TAIL ? lb_h[h] : nl + (k - lb_h[h]);
-                    s_pref[pos] = len_h[h];
-                    s_base[pos] = st_h[h];
-                    if (need_cnt) s_cnt[need_cnt ? pos : 0] = 0;
-                }
-            }
-            __syncthreads();
-            uint32_t carry = 0;
-#pragma unroll
-            for (int h = 0; h < CHUNK_MAX / IS_NT; ++h) {   // in place: each thread rewrites its own slots
-                const uint32_t k = h * IS_NT + threadIdx.x;
-                const uint32_t len = k < ne ? s_pref[k] : 0u;
-                const uint32_t st = k < ne ? s_base[k] : 0u;
-                uint32_t total;
-                const uint32_t excl = block_exclusive_scan<IS_NT>(len, S.scratch, &total);
-                if (k < ne) {
-                    s_pref[k] = carry + excl;
-                    s_base[k] = st - (carry + excl);   // modular: base + q is the address; start = base + pref
-                }
-                carry += total;
-            }
-            if (threadIdx.x == 0) s_pref[ne] = carry;
-            const uint32_t L = carry;   // tail elements of this vertex's in-edges in the tile
+            // the table: once per vertex, or per window when the tails are clipped
+            uint32_t nt = 0, nl = 0, L = 0;
+            if (!CLIP) nt = entry_table<need_cnt>(st_h, len_h, s_pref, s_base, s_cnt, S.scratch, nl, L);
             const uint32_t lo = a.col[b0], hi = a.col[b1 - 1];
             const uint32_t base = lo & ~31u;
             const uint32_t nwin = (hi - base) / BM_BITS + 1;
@@ -239,9 +279,36 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                 }
             }
             __syncthreads();
+            uint32_t mnext = 0;   // clipped: first element of the middle list not yet in a window
             for (uint32_t win = 0; win < nwin; ++win) {
                 const uint32_t wlo = base + win * BM_BITS;
-                for (uint32_t j = threadIdx.x; j < nb; j += IS_NT) {
+                uint32_t j0 = 0, j1 = nb;   // elements of the middle list set in this window
+                if (CLIP) {
+                    const uint64_t whi = (uint64_t)wlo + BM_BITS;
+                    j0 = mnext;
+                    j1 = first_at_least<NARROW>(a.col, b0 + j0, b1, whi) - b0;
+                    mnext = j1;
+                    if (j1 == j0) continue;   // same for the whole block: nothing to match here
+                    // each tail cut to [wlo, whi); what lies above stays for the next windows
+                    uint32_t cs_h[EH], cl_h[EH];
+#pragma unroll
+                    for (int h = 0; h < EH; ++h) {
+                        uint32_t p = st_h[h];
+                        const uint32_t e = p + len_h[h];
+                        uint32_t e2 = e;
+                        if (p < e) {
+                            if (col_at<NARROW>(a.col, p) < wlo) p = first_at_least<NARROW>(a.col, p, e, wlo);
+                            if (p < e && (uint64_t)col_at<NARROW>(a.col, e - 1u) >= whi)
+                                e2 = first_at_least<NARROW>(a.col, p, e, whi);
+                        }
+                        cs_h[h] = p;
+                        cl_h[h] = e2 - p;
+                        st_h[h] = e2;
+                        len_h[h] = e - e2;
+                    }
+                    nt = entry_table<false>(cs_h, cl_h, s_pref, s_base, s_cnt, S.scratch, nl, L);
+                }
+                for (uint32_t j = j0 + threadIdx.x; j < j1; j += IS_NT) {
                     const uint32_t x = a.col[b0 + j] - wlo;
                     if (x < BM_BITS) atomicOr(&bm[x >> 5], 1u << (x & 31u));
                 }
@@ -267,7 +334,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                     const uint32_t c1 = L - c0 < WT_MAX * WAVE ? L : c0 + WT_MAX * WAVE;
                     const uint32_t nwc = (c1 - c0 + WAVE - 1) / WAVE;   // windows in this chunk
                     // window table: entry k covers items [pref[k], pref[k+1])
-                    for (uint32_t k = threadIdx.x; k < ne; k += IS_NT) {
+                    for (uint32_t k = threadIdx.x; k < nt; k += IS_NT) {
                         const uint32_t p0 = s_pref[k] > c0 ? s_pref[k] : c0;
                         const uint32_t p1 = s_pref[k + 1] < c1 ? s_pref[k + 1] : c1;
                         for (uint32_t w = (p0 - c0 + WAVE - 1) / WAVE; p0 < p1 && w * WAVE + c0 < p1; ++w)
@@ -303,13 +370,13 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                         } else {
                             // mark the starts (pref is strictly increasing, so the marked offsets
                             // are distinct and at least 1). Entries past the last one read
-                            // pref[ne] = L: a start at or after item L moves only lanes whose
+                            // pref[nt] = L: a start at or after item L moves only lanes whose
                             // items lie beyond q1 (unused).
                             uint32_t o[UNROLL];
     #pragma unroll
                             for (int j = 0; j < UNROLL; ++j) {
                                 const uint32_t kk = kj[j] + 1u + ln;
-                                o[j] = s_pref[kk < ne ? kk : ne] - (W + j * WAVE);
+                                o[j] = s_pref[kk < nt ? kk : nt] - (W + j * WAVE);
                             }
     #pragma unroll
                             for (int j = 0; j < UNROLL; ++j)
@@ -385,7 +452,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                     __syncthreads();   // the table is rebuilt for the next chunk
                 }
                 __syncthreads();
-                for (uint32_t j = threadIdx.x; j < nb; j += IS_NT) {
+                for (uint32_t j = j0 + threadIdx.x; j < j1; j += IS_NT) {
                     const uint32_t x = a.col[b0 + j] - wlo;
                     if (x < BM_BITS) bm[x >> 5] = 0u;
                 }
@@ -401,7 +468,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
             }
             if (need_cnt) {
                 uint32_t seg_hits = 0;
-                for (uint32_t k = threadIdx.x; k < ne; k += IS_NT) {
+                for (uint32_t k = threadIdx.x; k < nt; k += IS_NT) {
                     edge_done(a, s_base[k] + s_pref[k] - 1u, v, s_cnt[k], false);
                     seg_hits += s_cnt[k];
                 }
@@ -629,6 +696,7 @@ static int resident_blocks(const void* fn) {
 }
 
 static int bitmap_mode(const IsectArgs& a) {
+    if (a.clip) return BM_CLIP;   // whole-row tails: counts only
     if (a.list_out) return BM_LIST;
     if (a.per_vertex || a.support) return BM_GATHER;
     if (a.per_edge || a.per_middle) return BM_ENTRY;
@@ -643,13 +711,15 @@ static const void* bitmap_fn(int mode, bool narrow) {
                                       : (const void*)k_isect_bitmap<BM_GATHER, false>;
         case BM_ENTRY: return narrow ? (const void*)k_isect_bitmap<BM_ENTRY, true>
                                      : (const void*)k_isect_bitmap<BM_ENTRY, false>;
+        case BM_CLIP: return narrow ? (const void*)k_isect_bitmap<BM_CLIP, true>
+                                    : (const void*)k_isect_bitmap<BM_CLIP, false>;
         default: return narrow ? (const void*)k_isect_bitmap<BM_COUNT, true>
                                : (const void*)k_isect_bitmap<BM_COUNT, false>;
     }
 }
 
 int isect_blocks_per_cu(int ker, int mode) {
-    static int cache[NKERNEL][4] = {};
+    static int cache[NKERNEL][BM_NMODE] = {};
     int& c = cache[ker][mode];
     if (!c) {
         const void* fn = ker == KER_MERGE     ? (const void*)k_isect_edges<true>
@@ -679,6 +749,9 @@ void launch_isect(int ker, const IsectArgs& a, int grid, uint64_t* partials, hip
             } else if (mode == BM_GATHER) {
                 if (nw) hipLaunchKernelGGL((k_isect_bitmap<BM_GATHER, true>), dim3(grid), dim3(IS_NT), 0, s, a, p);
                 else hipLaunchKernelGGL((k_isect_bitmap<BM_GATHER, false>), dim3(grid), dim3(IS_NT), 0, s, a, p);
+            } else if (mode == BM_CLIP) {
+                if (nw) hipLaunchKernelGGL((k_isect_bitmap<BM_CLIP, true>), dim3(grid), dim3(IS_NT), 0, s, a, p);
+                else hipLaunchKernelGGL((k_isect_bitmap<BM_CLIP, false>), dim3(grid), dim3(IS_NT), 0, s, a, p);
             } else if (mode == BM_ENTRY) {
                 if (nw) hipLaunchKernelGGL((k_isect_bitmap<BM_ENTRY, true>), dim3(grid), dim3(IS_NT), 0, s, a, p);
                 else hipLaunchKernelGGL((k_isect_bitmap<BM_ENTRY, false>), dim3(grid), dim3(IS_NT), 0, s, a, p);

@@ -11,6 +11,15 @@ namespace tcx {
 
 enum { SEL_HEURISTIC = 0, SEL_LEARNED = 1, SEL_FORCE_MERGE = 2, SEL_FORCE_BSEARCH = 3, SEL_FORCE_BITMAP = 4 };
 
+// What each in-edge (u -> v) of the degree-ordered graph streams against which
+// list of its middle vertex v, and the multiple of T that the sum of the hits is:
+//   FILTERED     : tail of N+(u) after v  against N+(v)  -> T
+//   FULL         : N(u)                   against N(v)   -> 3T
+//   MATRIX       : U row of u = N+(u)     against A row of v = N(v)   -> 2T
+//   MATRIX_UPPER : N+(u)                  against N+(v)  -> T
+enum { FORM_FILTERED = 0, FORM_FULL = 1, FORM_MATRIX = 2, FORM_MATRIX_UPPER = 3, FORM_COUNT = 4 };
+inline int form_multiple(int f) { return f == FORM_FULL ? 3 : (f == FORM_MATRIX ? 2 : 1); }
+
 constexpr int NSTAGE = 12;
 
 struct Layout {
@@ -50,6 +59,8 @@ struct RunArgs {
     uint32_t* list_cur;              //   device [m] zeroed cursors
     int32_t* list_out;               //   device [list_cap][3] output
     uint64_t list_cap;
+    int formulation;                 // FORM_*; other than FORM_FILTERED: T only (no per-edge or
+                                     // per-vertex outputs), workspace make_layout + sym_extra_bytes
 };
 
 struct RunResult {
@@ -86,6 +97,9 @@ hipError_t run_list_pass(const RunArgs& r);
 void widen_u32_u64(const uint32_t* in, uint64_t* out, const Ctrl* ctrl, size_t cap, hipStream_t s);
 // Extra workspace of tc_list_triangles after make_layout(E, n).total: slot offsets, counts / cursors.
 size_t list_extra_bytes(int64_t E);
+// Extra workspace of the other formulations after make_layout(E, n).total: the
+// symmetric adjacency (row offsets and 2m columns).
+size_t sym_extra_bytes(int64_t E, int32_t n);
 // After a run with stop_before_isect: one intersection kernel over tiles [t0, t1).
 hipError_t launch_isect_range(const RunArgs& r, int ker, uint32_t t0, uint32_t t1);
 int stage_count();

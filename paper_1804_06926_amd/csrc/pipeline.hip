@@ -369,6 +369,62 @@ __global__ __launch_bounds__(NT) void k_csc_expand(uint64_t* __restrict__ csc, c
     }
 }
 
+// ------------------------------------------------------------------ the other formulations
+// All in-edges, grouped by v and, inside a group, in CSR order (so by u): key
+// v << sh | e, sorted on the v bits only (the sort is stable).
+__global__ __launch_bounds__(NT) void k_sym_keys(const uint32_t* __restrict__ col, const Ctrl* ctrl,
+                                                 uint64_t* __restrict__ keys, int sh) {
+    const uint32_t m = ctrl->m;
+    for (uint64_t e = (uint64_t)blockIdx.x * NT + threadIdx.x; e < m; e += (uint64_t)gridDim.x * NT)
+        keys[e] = ((uint64_t)col[e] << sh) | e;
+}
+
+// inend[v] = one past the last in-edge of v in the sorted order.
+__global__ __launch_bounds__(NT) void k_sym_bounds(const uint64_t* __restrict__ keys, const Ctrl* ctrl,
+                                                   uint32_t* __restrict__ inend, int sh) {
+    const uint32_t m = ctrl->m;
+    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < m; i += (uint64_t)gridDim.x * NT) {
+        const uint64_t v = keys[i] >> sh;
+        if (i + 1 == m || (keys[i + 1] >> sh) != v) inend[v] = (uint32_t)(i + 1);
+    }
+}
+
+// Row offsets of the symmetric adjacency: row v holds N-(v) (in-neighbours,
+// all ranked below v) and then N+(v), so fo[v] = inoff[v] + off[v].
+__global__ __launch_bounds__(NT) void k_sym_rows(const uint32_t* __restrict__ inoff, const uint32_t* __restrict__ off,
+                                                 int32_t n, uint32_t* __restrict__ fo) {
+    for (int64_t v = (int64_t)blockIdx.x * NT + threadIdx.x; v <= n; v += (int64_t)gridDim.x * NT)
+        fo[v] = inoff[v] + off[v];
+}
+
+// Per sorted in-edge i = (u -> v), edge e: (full rows) the two copies of the
+// edge in the symmetric adjacency, u at position i - inoff[v] of row v's lower
+// part (fo[v] + i - inoff[v] = off[v] + i) and v at position e - off[u] of row
+// u's upper part (fo[u] + indeg(u) + e - off[u] = inoff[u + 1] + e); then the
+// key becomes the range that the edge streams, start | end << 32.
+__global__ __launch_bounds__(NT) void k_sym_build(uint64_t* __restrict__ keys, const Ctrl* ctrl,
+                                                  const uint32_t* __restrict__ src, const uint32_t* __restrict__ col,
+                                                  const uint32_t* __restrict__ off, const uint32_t* __restrict__ inoff,
+                                                  uint32_t* __restrict__ fcol, int sh, int form) {
+    const uint32_t m = ctrl->m;
+    const uint64_t emask = (1ull << sh) - 1ull;
+    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < m; i += (uint64_t)gridDim.x * NT) {
+        const uint64_t key = keys[i];
+        const uint32_t v = (uint32_t)(key >> sh), e = (uint32_t)(key & emask);
+        const uint32_t u = src[e];
+        const uint32_t ua = off[u], ub = off[u + 1];
+        uint32_t st = ua, en = ub;   // MATRIX_UPPER: N+(u) in the oriented columns
+        if (form != FORM_MATRIX_UPPER) {
+            const uint32_t i0 = inoff[u], i1 = inoff[u + 1];
+            fcol[off[v] + (uint32_t)i] = u;
+            fcol[i1 + e] = v;
+            st = form == FORM_FULL ? i0 + ua : i1 + ua;   // whole row of u, or its upper part
+            en = i1 + ub;
+        }
+        keys[i] = (uint64_t)st | ((uint64_t)en << 32);
+    }
+}
+
 // ------------------------------------------------------------------ buckets
 __device__ __forceinline__ uint32_t bucket_of(uint32_t din, uint32_t dout) {
     if (din == 0 || dout == 0) return BUCKET_NONE;
@@ -698,12 +754,19 @@ const char* stage_name(int s) {
     return (s >= 0 && s < NSTAGE) ? names[s] : "";
 }
 
+// The symmetric adjacency of the other formulations, after the pipeline's own workspace.
+static uint32_t* sym_off(const RunArgs& r, const Layout& L) { return (uint32_t*)((char*)r.ws + L.total); }
+static uint32_t* sym_col(const RunArgs& r, const Layout& L) {
+    return (uint32_t*)((char*)r.ws + L.total + align_up(4 * ((size_t)r.n + 1), 256));
+}
+
 static IsectArgs isect_args(const RunArgs& r, const Layout& L, uint64_t* csc) {
     char* ws = (char*)r.ws;
+    const bool sym = r.formulation == FORM_FULL || r.formulation == FORM_MATRIX;
     IsectArgs ia;
     ia.ctrl = (Ctrl*)(ws + L.ctrl);
-    ia.off = (const uint32_t*)(ws + L.off);
-    ia.col = (const uint32_t*)(ws + L.col);
+    ia.off = sym ? sym_off(r, L) : (const uint32_t*)(ws + L.off);
+    ia.col = sym ? sym_col(r, L) : (const uint32_t*)(ws + L.col);
     ia.src = (const uint32_t*)(ws + L.src);
     ia.csc = csc;
     ia.inoff = (const uint32_t*)(ws + L.inoff);
@@ -719,7 +782,8 @@ static IsectArgs isect_args(const RunArgs& r, const Layout& L, uint64_t* csc) {
     ia.list_out = r.list_out;
     ia.list_cap = r.list_cap;
     ia.inv = (const uint32_t*)(ws + L.inv);
-    ia.col_narrow = r.E < ((int64_t)1 << 30) ? 1u : 0u;   // m <= E
+    ia.col_narrow = (sym ? 2 * r.E : r.E) < ((int64_t)1 << 30) ? 1u : 0u;   // m <= E
+    ia.clip = r.formulation != FORM_FILTERED ? 1u : 0u;
     return ia;
 }
 
@@ -750,6 +814,10 @@ __global__ __launch_bounds__(NT) void k_widen(const uint32_t* __restrict__ in, u
 
 void widen_u32_u64(const uint32_t* in, uint64_t* out, const Ctrl* ctrl, size_t cap, hipStream_t s) {
     hipLaunchKernelGGL(k_widen, dim3(grid_for(cap)), dim3(NT), 0, s, in, out, ctrl);
+}
+
+size_t sym_extra_bytes(int64_t E, int32_t n) {
+    return align_up(4 * ((size_t)n + 1), 256) + align_up(8 * ((size_t)E > 0 ? (size_t)E : 1), 256);
 }
 
 size_t list_extra_bytes(int64_t E) {
@@ -879,24 +947,46 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         out->ctrl_dev = ctrl;
         return hipGetLastError();
     }
-    // ---- CSC: in-edges with work grouped by v (the sorted pair keys are free now)
-    const int nbv = bits_for((uint64_t)n);   // in-edge groups: ids 0 .. n - 1 (n - 1 = no work)
-    const CscPacking pk = csc_packing(E, n);
-    hipLaunchKernelGGL(k_csc_keys, dim3(grid_for(((size_t)E + OR_U - 1) / OR_U)), dim3(NT), 0, s, col, src, off, ctrl,
-                       n, other, pk.sh,
-                       pk.lbits);
-    const int alt2 =
-        radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, pk.sh, pk.sh + nbv, radix_tmp, s);
-    uint64_t* csc = alt2 ? sorted : other;
-    fill_u32(rowend, 0u, (size_t)n, s);
-    hipLaunchKernelGGL(k_csc_bounds, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, n, rowend, pk.sh);
-    fill_u32(inoff, 0u, 1, s);
-    scan_inclusive_max_u32(rowend, inoff + 1, (size_t)n, scan_tmp, s);
-    hipLaunchKernelGGL(k_csc_expand, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, src, off, pk.ebits,
-                       pk.lbits);
+    const int nbv = bits_for((uint64_t)n);
+    uint64_t* csc;
+    const uint32_t* moff = off;   // offsets of the middle lists
+    if (r.formulation == FORM_FILTERED) {
+        // ---- CSC: in-edges with work grouped by v (the sorted pair keys are free now);
+        // in-edge groups: ids 0 .. n - 1 (n - 1 = no work)
+        const CscPacking pk = csc_packing(E, n);
+        hipLaunchKernelGGL(k_csc_keys, dim3(grid_for(((size_t)E + OR_U - 1) / OR_U)), dim3(NT), 0, s, col, src, off,
+                           ctrl, n, other, pk.sh, pk.lbits);
+        const int alt2 =
+            radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, pk.sh, pk.sh + nbv, radix_tmp, s);
+        csc = alt2 ? sorted : other;
+        fill_u32(rowend, 0u, (size_t)n, s);
+        hipLaunchKernelGGL(k_csc_bounds, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, n, rowend, pk.sh);
+        fill_u32(inoff, 0u, 1, s);
+        scan_inclusive_max_u32(rowend, inoff + 1, (size_t)n, scan_tmp, s);
+        hipLaunchKernelGGL(k_csc_expand, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, src, off, pk.ebits,
+                           pk.lbits);
+    } else {
+        // ---- all in-edges grouped by v; the symmetric adjacency; the streamed ranges
+        const int sh = bits_for((uint64_t)E) > 0 ? bits_for((uint64_t)E) : 1;
+        hipLaunchKernelGGL(k_sym_keys, dim3(grid_for((size_t)E)), dim3(NT), 0, s, col, ctrl, other, sh);
+        const int alt2 =
+            radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, sh, sh + nbv, radix_tmp, s);
+        csc = alt2 ? sorted : other;
+        fill_u32(rowend, 0u, (size_t)n, s);
+        hipLaunchKernelGGL(k_sym_bounds, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, rowend, sh);
+        fill_u32(inoff, 0u, 1, s);
+        scan_inclusive_max_u32(rowend, inoff + 1, (size_t)n, scan_tmp, s);
+        uint32_t* fo = sym_off(r, L);
+        if (r.formulation != FORM_MATRIX_UPPER) {
+            hipLaunchKernelGGL(k_sym_rows, dim3(grid_for((size_t)n + 1)), dim3(NT), 0, s, inoff, off, n, fo);
+            moff = fo;
+        }
+        hipLaunchKernelGGL(k_sym_build, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, src, col, off, inoff,
+                           sym_col(r, L), sh, r.formulation);
+    }
     mark(6);
     // ---- buckets + selection
-    hipLaunchKernelGGL(k_vbucket, dim3(grid_for((size_t)n, 2048)), dim3(NT), 0, s, off, inoff, n, vbucket, ctrl);
+    hipLaunchKernelGGL(k_vbucket, dim3(grid_for((size_t)n, 2048)), dim3(NT), 0, s, moff, inoff, n, vbucket, ctrl);
     const bool learned = r.select == SEL_LEARNED && r.mlp && r.learned;
     if (learned) mlp_select((const MlpCompute*)r.mlp, ctrl, r.learned, s);
     else bucket_features_launch(ctrl, s);

@@ -316,3 +316,52 @@ def test_rmat20_all_kernels_agree_per_edge(tc):
         else:
             np.testing.assert_array_equal(cur[0], base[0])
             np.testing.assert_array_equal(cur[1], base[1])
+
+
+# ---------------------------------------------------------------- the other formulations
+FORM_CASES = sorted(CASES) + ["spread_hubs", "rmat18"]
+_form_ref = {}
+
+
+def _form_case(case):
+    if case == "spread_hubs":
+        return graphgen.spread_hubs(), 1 << 21
+    if case == "rmat18":
+        return graphgen.rmat(18, 16, seed=9), 1 << 18
+    return CASES[case]()
+
+
+def _form_oracle(case, e, n):
+    """(T, full sum, sum of C, upper sum of C) from the oracle, once per case."""
+    if case not in _form_ref:
+        G = oracle.Graph(e, n)
+        _form_ref[case] = (G.count(), G.full_sum(), G.matrix_sum(), G.matrix_sum(upper=True))
+    return _form_ref[case]
+
+
+@pytest.mark.parametrize("sel", SELECTS)
+@pytest.mark.parametrize("case", FORM_CASES)
+def test_formulations_match_oracle(tc, case, sel):
+    """Full lists (sum 3T), Algorithm 3 (sum of C = 2T), its upper-triangle
+    form (T) and the filtered form, each against the oracle's own sums."""
+    e, n = _form_case(case)
+    T, full, mat, upper = _form_oracle(case, e, n)
+    d = dev(e)
+    for form, want in (("filtered", T), ("full", full), ("matrix", mat), ("matrix_upper", upper)):
+        print(f"case={case} select={sel} formulation={form} E={e.shape[0]} n={n}", flush=True)
+        got = tc.count_triangles_formulation(d, n, form, select=_sel(tc, sel))
+        assert got == (T, want), form
+
+
+def test_formulations_empty_and_errors(tc):
+    import torch
+    empty = torch.zeros((0, 2), dtype=torch.int32, device="cuda:0")
+    for form in tc.FORMULATIONS:
+        assert tc.count_triangles_formulation(empty, 4, form) == (0, 0)
+        assert tc.count_triangles_formulation(dev([[1, 1], [2, 2]]), 3, form) == (0, 0)
+        assert tc.count_triangles_formulation(dev([[0, 1], [1, 2], [2, 0]]), 3, form)[0] == 1
+        with pytest.raises(tc.TCError) as ei:
+            tc.count_triangles_formulation(dev([[0, 1], [1, 6]]), 4, form)
+        assert ei.value.status == 2
+    with pytest.raises(ValueError):
+        tc.count_triangles_formulation(dev([[0, 1]]), 2, "dense")
