@@ -110,7 +110,35 @@ def algorithmic_bytes(tc, d_edges, n, stats):
         out[name] = e_bytes + t_bytes
     S = int((dplus[col]).sum())
     balg = 4 * (m + S) + 16 * m + 8 * (n + 1)   # merge-formulation minimum
-    return out, balg, int(tail[active].sum())
+    # list elements each formulation streams over all kept edges (u -> v), before
+    # any window clipping: tails; whole rows N(u); rows N+(u)
+    deg = dplus + np.bincount(col, minlength=n)
+    elems = {"filtered": int(tail[active].sum()), "full": int(deg[src].sum()),
+             "matrix": int(dplus[src].sum()), "matrix_upper": int(dplus[src].sum())}
+    return out, balg, int(tail[active].sum()), elems
+
+
+def formulation_compare(tc, d_edges, n, T, steps, elems):
+    """The full-list and matrix formulations timed on the same graph; each
+    count asserted equal to the filtered one."""
+    import torch
+    out = {}
+    for form in ("full", "matrix", "matrix_upper"):
+        tc.count_triangles_formulation(d_edges, n, form)
+        torch.cuda.synchronize()
+        isect = {}
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            Tf, total, st = tc.count_triangles_formulation(d_edges, n, form, timing=True)
+            for k, v in st.items():
+                if k.startswith("isect_"):
+                    isect[k[6:]] = isect.get(k[6:], 0.0) + v / max(steps, 1)
+        torch.cuda.synchronize()
+        assert Tf == T, (form, Tf, T)
+        out[form] = {"ms_per_step": (time.perf_counter() - t0) * 1e3 / max(steps, 1),
+                     "isect_ms": sum(isect.values()), "isect_ms_by_kernel": isect, "sum": total,
+                     "streamed_elements": elems[form]}
+    return out
 
 
 def cpu_baseline(edges, n, m):
@@ -199,6 +227,8 @@ def main(argv=None):
     ap.add_argument("--no-check", action="store_true", help="skip the oracle equality check")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-selector comparison (profiling runs: one selection mode only)")
+    ap.add_argument("--formulations", action="store_true",
+                    help="also time the full-list and matrix formulations on the same graph")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one device-to-device copy of MIB MiB (calibrates counter-based traffic)")
     args = ap.parse_args(argv)
@@ -255,7 +285,7 @@ def main(argv=None):
     m = stats["m"]
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step T={T} m={m}", file=sys.stderr, flush=True)
 
-    kbytes, balg, tail_sum = algorithmic_bytes(tc, d_edges, n, stats)
+    kbytes, balg, tail_sum, elems = algorithmic_bytes(tc, d_edges, n, stats)
     isect = {k: stages.get(f"isect_{k}", 0.0) for k in ("merge", "bsearch", "bitmap")}
     dom = max(isect, key=isect.get)
     dom_ms = isect[dom]
@@ -300,6 +330,12 @@ def main(argv=None):
         assert T_l == T, (T_l, T)
         result["learned_vs_heuristic"] = {"ms_per_step_learned": ms_l, "ms_per_step_heuristic": ms_per_step,
                                           "speedup": ms_per_step / ms_l}
+    if args.formulations and args.select == "heuristic":
+        print("[bench] full-list and matrix formulations", file=sys.stderr, flush=True)
+        forms = formulation_compare(tc, d_edges, n, T, args.steps, elems)
+        forms["filtered"] = {"ms_per_step": ms_per_step, "isect_ms": isect_ms, "sum": T,
+                             "streamed_elements": elems["filtered"]}
+        result["formulations"] = forms
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         cb = cpu_baseline(edges, n, m)

@@ -174,6 +174,26 @@ __device__ __forceinline__ uint32_t first_at_least(const uint32_t* col, uint32_t
     return p;
 }
 
+// The same search by a whole wave, the same result in every lane: 64 probes
+// per step narrow the range 64-fold, so a list of d elements costs about
+// log64(d) dependent loads instead of log2(d).
+template <bool NARROW>
+__device__ __forceinline__ uint32_t wave_first_at_least(const uint32_t* col, uint32_t p, uint32_t e, uint64_t x) {
+    const uint32_t ln = (uint32_t)lane_id();
+    while (e - p > (uint32_t)WAVE) {
+        const uint32_t step = (e - p + WAVE - 1) / WAVE;
+        const uint32_t q = p + (ln + 1u) * step - 1u;   // last element of the lane's step
+        const bool below = q < e && (uint64_t)col_at<NARROW>(col, q) < x;
+        const uint32_t c = (uint32_t)__popcll(__ballot(below));   // steps wholly below x
+        const uint32_t np = p + c * step;
+        e = np + step < e ? np + step : e;
+        p = np;
+    }
+    const uint32_t q = p + ln;
+    const bool below = q < e && (uint64_t)col_at<NARROW>(col, q) < x;
+    return p + (uint32_t)__popcll(__ballot(below));
+}
+
 // Entry table of one vertex's in-edges in a tile, in LDS: entry k streams
 // items [s_pref[k], s_pref[k + 1]) of a flat item range, item q at
 // col[s_base[k] + q] (s_base = start - s_pref, modular). Tails of at least
@@ -279,6 +299,14 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                 }
             }
             __syncthreads();
+            // clipped tails: each entry keeps a cursor (st_h, with len_h left) and the
+            // value under it, so a window that holds none of its elements costs no load
+            uint64_t cv_h[EH];
+            if (CLIP) {
+#pragma unroll
+                for (int h = 0; h < EH; ++h)
+                    cv_h[h] = len_h[h] ? (uint64_t)col_at<NARROW>(a.col, st_h[h]) : ~0ull;
+            }
             uint32_t mnext = 0;   // clipped: first element of the middle list not yet in a window
             for (uint32_t win = 0; win < nwin; ++win) {
                 const uint32_t wlo = base + win * BM_BITS;
@@ -286,7 +314,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                 if (CLIP) {
                     const uint64_t whi = (uint64_t)wlo + BM_BITS;
                     j0 = mnext;
-                    j1 = first_at_least<NARROW>(a.col, b0 + j0, b1, whi) - b0;
+                    j1 = wave_first_at_least<NARROW>(a.col, b0 + j0, b1, whi) - b0;
                     mnext = j1;
                     if (j1 == j0) continue;   // same for the whole block: nothing to match here
                     // each tail cut to [wlo, whi); what lies above stays for the next windows
@@ -295,11 +323,12 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                     for (int h = 0; h < EH; ++h) {
                         uint32_t p = st_h[h];
                         const uint32_t e = p + len_h[h];
-                        uint32_t e2 = e;
-                        if (p < e) {
-                            if (col_at<NARROW>(a.col, p) < wlo) p = first_at_least<NARROW>(a.col, p, e, wlo);
-                            if (p < e && (uint64_t)col_at<NARROW>(a.col, e - 1u) >= whi)
-                                e2 = first_at_least<NARROW>(a.col, p, e, whi);
+                        uint32_t e2 = p;
+                        if (cv_h[h] < whi) {
+                            // elements below wlo belong to windows without middle elements
+                            if (cv_h[h] < wlo) p = first_at_least<NARROW>(a.col, p, e, wlo);
+                            e2 = first_at_least<NARROW>(a.col, p, e, whi);
+                            cv_h[h] = e2 < e ? (uint64_t)col_at<NARROW>(a.col, e2) : ~0ull;
                         }
                         cs_h[h] = p;
                         cl_h[h] = e2 - p;

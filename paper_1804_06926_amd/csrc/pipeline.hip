@@ -479,7 +479,7 @@ __device__ int heuristic_choice(int b) {
 
 __global__ __launch_bounds__(NBUCKET) void k_select(Ctrl* ctrl, int mode, const uint8_t* __restrict__ learned,
                                                     const uint16_t* __restrict__ chunk_override,
-                                                    const uint8_t* __restrict__ group_override) {
+                                                    const uint8_t* __restrict__ group_override, int whole_rows) {
     __shared__ uint32_t s_key[NBUCKET];
     const int b = threadIdx.x;
     int ch;
@@ -490,7 +490,9 @@ __global__ __launch_bounds__(NBUCKET) void k_select(Ctrl* ctrl, int mode, const 
     else ch = heuristic_choice(b);
     const int lo = b & 15, li = b >> 4;
     // tile shape: in-edges per tile and lanes per in-edge
-    uint32_t chunk = 256u;
+    // whole-row tails are cut per bitmap window: the largest chunks spread each
+    // window's set-up over the most in-edges
+    uint32_t chunk = (whole_rows && ch == KER_BITMAP) ? (uint32_t)CHUNK_MAX : 256u;
     uint32_t group = lo >= 9 ? 64u : (lo >= 3 ? (1u << (lo - 3)) : 1u);
     if (chunk_override && chunk_override[b]) chunk = chunk_override[b];
     if (group_override && group_override[b]) group = group_override[b];
@@ -991,7 +993,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     if (learned) mlp_select((const MlpCompute*)r.mlp, ctrl, r.learned, s);
     else bucket_features_launch(ctrl, s);
     hipLaunchKernelGGL(k_select, dim3(1), dim3(NBUCKET), 0, s, ctrl, r.select, learned ? r.learned : nullptr,
-                       r.chunk_override, r.group_override);
+                       r.chunk_override, r.group_override, r.formulation != FORM_FILTERED ? 1 : 0);
     mark(7);
     // ---- group: order vertices by (kernel, bucket); tiles
     hipLaunchKernelGGL(k_vkeys_slot, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vbucket, n, ctrl, vkeysA);

@@ -107,3 +107,32 @@ def test_chung_lu_batch_4096_sampled(tc):
     for g in sample:
         ref = oracle.count_triangles(e[off[g]:off[g + 1]], int(nv[g]))
         assert int(got[g]) == ref, g
+
+
+def test_formulations_rmat20_against_oracle(tc):
+    """The benchmark graph (R-MAT 20) through every formulation and strategy:
+    T equal to the oracle's, and the sums 3T (full lists), 2T (sum of C) and T."""
+    import torch
+    n = 1 << 20
+    e = graphgen.rmat(20, 16, seed=1)
+    print("[rmat20] oracle T", flush=True)
+    T = oracle.count_triangles(e, n)
+    d = torch.from_numpy(e).cuda()
+    for form, k in (("filtered", 1), ("full", 3), ("matrix", 2), ("matrix_upper", 1)):
+        for sel in (tc.SELECT_HEURISTIC, tc.FORCE_MERGE, tc.FORCE_BSEARCH, tc.FORCE_BITMAP):
+            print(f"[rmat20] formulation={form} select={sel}", flush=True)
+            assert tc.count_triangles_formulation(d, n, form, select=sel) == (T, k * T)
+
+
+def test_formulations_rmat24_sums(tc):
+    """R-MAT 24 (heuristic selection): every formulation's T equals the filtered
+    count (itself checked on samples above) and the sums are 3T, 2T and T."""
+    import torch
+    n = 1 << 24
+    e = graphgen.rmat(24, 16, seed=1)
+    d = torch.from_numpy(e).cuda()
+    print("[rmat24] filtered", flush=True)
+    T = tc.count_triangles(d, n)
+    for form, k in (("full", 3), ("matrix", 2), ("matrix_upper", 1)):
+        print(f"[rmat24] formulation={form}", flush=True)
+        assert tc.count_triangles_formulation(d, n, form) == (T, k * T)
