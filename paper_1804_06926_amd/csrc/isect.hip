@@ -446,7 +446,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
                         for (int j = 0; j < UNROLL; ++j) wd[j] = bm[(xs[j] < BM_BITS ? xs[j] : BM_BITS) >> 5];
                         uint32_t hits = 0;
 #pragma unroll
-                        for (int j = 0; j < UNROLL; ++j) hits += (wd[j] >> (xs[j] & 31u)) & 1u;
+                        for (int j = 0; j < UNROLL; ++j) hits += __builtin_amdgcn_ubfe(wd[j], xs[j], 1u);
                         acc += hits;
                         if (!need_cnt) continue;
 #pragma unroll
