@@ -58,9 +58,10 @@ struct Ctrl {
     float features[NBUCKET][6];       // selector-network input per bucket
 };
 
-// Tiles: low word = position i in the ordered vertex list; high word = chunk
-// index j of vertex i's in-edges, or TILE_MULTI | g for the g vertices
-// starting at position i (whole in-edge lists).
+// Tiles, 16 bytes each, decoded without further dependent loads where
+// possible: {v, first in-edge, in-edge count, 0} for a chunk of one vertex's
+// in-edges; {i, g, 0, TILE_MULTI} for the g vertices starting at position i of
+// the ordered vertex list (whole in-edge lists).
 constexpr uint32_t TILE_MULTI = 0x80000000u;
 constexpr int SEG_MAX = 256;          // vertices per multi-vertex tile
 constexpr int SEG_MAX_BITMAP = 32;    // vertices per multi-vertex tile of the bitmap kernel

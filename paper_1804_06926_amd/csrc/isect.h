@@ -19,7 +19,7 @@ struct IsectArgs {
     const uint32_t* inoff;      // [n+1] start of each vertex's in-edges in csc
     const uint32_t* vlist;      // [n]   vertices in (kernel, bucket) order
     const uint8_t* vbucket;     // [n]   bucket of each vertex
-    const uint64_t* tiles;      // [ntiles] position | (chunk or TILE_MULTI | count) << 32
+    const uint4* tiles;         // [ntiles] tile descriptors (see TILE_MULTI)
     uint32_t* per_edge;         // [m] or null: c_e in CSR edge order
     uint64_t* per_vertex;       // [n] or null: t[] in rank space
     uint64_t* per_middle;       // [n] or null: triangles whose middle vertex is v (rank space)

@@ -49,14 +49,13 @@ using Segs = SegsT<SEG_MAX>;
 // Called by the whole block; contains barriers.
 template <int N>
 __device__ uint32_t load_tile(const IsectArgs& a, uint32_t t, SegsT<N>& S) {
-    const uint64_t d = a.tiles[t];
-    const uint32_t i = (uint32_t)d, h = (uint32_t)(d >> 32);
+    const uint4 d = a.tiles[t];
     uint32_t nseg, cnt = 0;
-    if (h & TILE_MULTI) {
-        nseg = h & ~TILE_MULTI;
+    if (d.w & TILE_MULTI) {
+        nseg = d.y;
         if (nseg > (uint32_t)N) nseg = N;   // the tile layout never makes more
         if (threadIdx.x < nseg) {
-            const uint32_t v = a.vlist[i + threadIdx.x];
+            const uint32_t v = a.vlist[d.x + threadIdx.x];
             S.v[threadIdx.x] = v;
             S.e0[threadIdx.x] = a.inoff[v];
             cnt = a.inoff[v + 1] - a.inoff[v];
@@ -64,13 +63,9 @@ __device__ uint32_t load_tile(const IsectArgs& a, uint32_t t, SegsT<N>& S) {
     } else {
         nseg = 1;
         if (threadIdx.x == 0) {
-            const uint32_t v = a.vlist[i];
-            const uint32_t K = a.ctrl->chunk[a.vbucket[v]];
-            const uint32_t e0 = a.inoff[v] + h * K;
-            const uint32_t end = a.inoff[v + 1];
-            S.v[0] = v;
-            S.e0[0] = e0;
-            cnt = (e0 + K < end ? e0 + K : end) - e0;
+            S.v[0] = d.x;
+            S.e0[0] = d.y;
+            cnt = d.z;
         }
     }
     uint32_t total;

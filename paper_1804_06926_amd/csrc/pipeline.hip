@@ -570,8 +570,9 @@ __global__ __launch_bounds__(NT) void k_ntiles(const uint32_t* __restrict__ vlis
 
 __global__ __launch_bounds__(NT) void k_emit_tiles(const uint32_t* __restrict__ vlist,
                                                    const uint8_t* __restrict__ vbucket,
+                                                   const uint32_t* __restrict__ inoff,
                                                    const uint32_t* __restrict__ tstart, int32_t n, Ctrl* ctrl,
-                                                   uint64_t* __restrict__ tiles, uint64_t tile_cap) {
+                                                   uint4* __restrict__ tiles, uint64_t tile_cap) {
     for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT) {
         const uint32_t b = vbucket[vlist[i]];
         const int kk = b == BUCKET_NONE ? NKERNEL : ctrl->choice[b];
@@ -585,10 +586,15 @@ __global__ __launch_bounds__(NT) void k_emit_tiles(const uint32_t* __restrict__ 
             const uint32_t g = tile_group(ctrl, b);
             if (g > 1) {
                 const uint32_t cnt = min(g, ctrl->bend[b] - (uint32_t)i);
-                if (t0 < tile_cap) tiles[t0] = (uint64_t)(uint32_t)i | ((uint64_t)(TILE_MULTI | cnt) << 32);
+                if (t0 < tile_cap) tiles[t0] = make_uint4((uint32_t)i, cnt, 0u, TILE_MULTI);
             } else {
-                for (uint32_t t = t0; t < t1 && t < tile_cap; ++t)
-                    tiles[t] = (uint64_t)(uint32_t)i | ((uint64_t)(t - t0) << 32);
+                const uint32_t v = vlist[i];
+                const uint32_t K = ctrl->chunk[b];
+                const uint32_t e_beg = inoff[v], e_end = inoff[v + 1];
+                for (uint32_t t = t0; t < t1 && t < tile_cap; ++t) {
+                    const uint32_t e0 = e_beg + (t - t0) * K;
+                    tiles[t] = make_uint4(v, e0, (e0 + K < e_end ? e0 + K : e_end) - e0, 0u);
+                }
             }
         }
         for (int k = kprev + 1; k <= kk; ++k) ctrl->tile_begin[k] = t0;
@@ -741,7 +747,7 @@ Layout make_layout(int64_t E, int32_t n) {
     L.col = take(4 * ee);
     L.src = take(4 * ee);
     L.tile_cap = ee / 16 + nn + 1;
-    L.tiles = take(8 * L.tile_cap);
+    L.tiles = take(16 * L.tile_cap);
     L.partial = take(4 * (UQ_MAX_BLOCKS + 1));
     L.bstart = take(4 * ((1u << DEG_MAX_BUCKET_BITS) + 4));
     L.isect_partials = take(isect_partials_bytes());
@@ -777,7 +783,7 @@ static IsectArgs isect_args(const RunArgs& r, const Layout& L, uint64_t* csc) {
     ia.inoff = (const uint32_t*)(ws + L.inoff);
     ia.vlist = (const uint32_t*)(ws + L.vlist);
     ia.vbucket = (const uint8_t*)(ws + L.vbucket);
-    ia.tiles = (const uint64_t*)(ws + L.tiles);
+    ia.tiles = (const uint4*)(ws + L.tiles);
     ia.per_edge = r.per_edge_counts;
     ia.per_vertex = (r.per_vertex || r.clustering) ? (uint64_t*)(ws + L.pv) : nullptr;
     ia.per_middle = r.per_middle ? (uint64_t*)(ws + L.pv) : nullptr;
@@ -861,7 +867,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     uint64_t* keysB = (uint64_t*)(ws + L.keysB);
     uint32_t* col = (uint32_t*)(ws + L.col);
     uint32_t* src = (uint32_t*)(ws + L.src);
-    uint64_t* tiles = (uint64_t*)(ws + L.tiles);
+    uint4* tiles = (uint4*)(ws + L.tiles);
     uint32_t* partial = (uint32_t*)(ws + L.partial);
     void* scan_tmp = ws + L.scan_tmp;
     void* radix_tmp = ws + L.radix_tmp;
@@ -1007,8 +1013,8 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     }
     hipLaunchKernelGGL(k_ntiles, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vlist, vbucket, inoff, n, ctrl, tstart);
     scan_exclusive_sum_u32(tstart, tstart, (size_t)n + 1, scan_tmp, s);
-    hipLaunchKernelGGL(k_emit_tiles, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vlist, vbucket, tstart, n, ctrl,
-                       tiles, (uint64_t)L.tile_cap);
+    hipLaunchKernelGGL(k_emit_tiles, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vlist, vbucket, inoff, tstart, n,
+                       ctrl, tiles, (uint64_t)L.tile_cap);
     if (r.per_edge_counts) fill_u32(r.per_edge_counts, 0u, (size_t)E, s);
     if (r.support) fill_u32(r.support, 0u, (size_t)E, s);
     if (r.per_vertex || r.per_middle || r.clustering) fill_u64(pv, 0ull, (size_t)n, s);
