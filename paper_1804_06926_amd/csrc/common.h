@@ -80,6 +80,26 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* scratch, T* total = nu
     return wave_base + inc - v;
 }
 
+// First-pass digit counts of a radix sort, gathered by the kernel that writes
+// the keys: a block of 256 threads writes tile t (RADIX_TILE consecutive keys)
+// and adds each key's first digit here; flush() stores the tile's column of
+// the count table (256 digit rows) and clears the counters.
+struct TileCounts {
+    uint32_t w[4][256];   // one histogram per wave (256 threads)
+    __device__ void clear() {
+        for (int i = threadIdx.x; i < 4 * 256; i += 256) (&w[0][0])[i] = 0;
+    }
+    __device__ void add(uint32_t digit) { atomicAdd(&w[threadIdx.x >> 6][digit], 1u); }
+    // Whole block; barriers.
+    __device__ void flush(uint32_t* counts, uint32_t ntiles, uint32_t tile) {
+        __syncthreads();
+        const uint32_t d = threadIdx.x;
+        counts[(size_t)d * ntiles + tile] = w[0][d] + w[1][d] + w[2][d] + w[3][d];
+        w[0][d] = w[1][d] = w[2][d] = w[3][d] = 0;
+        __syncthreads();
+    }
+};
+
 // Ceiling of log2 for x >= 1 (number of bits needed to hold values < x).
 __host__ __device__ __forceinline__ int bits_for(uint64_t x) {
     int b = 0;

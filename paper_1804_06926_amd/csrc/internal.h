@@ -17,16 +17,26 @@ void scan_exclusive_sum_u32(const uint32_t* in, uint32_t* out, size_t len, void*
 void scan_inclusive_max_u32(const uint32_t* in, uint32_t* out, size_t len, void* temp, hipStream_t s);
 void scan_exclusive_sum_u64(const uint64_t* in, uint64_t* out, size_t len, void* temp, hipStream_t s);
 size_t radix_temp_bytes(size_t cap);
-// Stable LSD sort of keys on bits [bit_lo, bit_hi), 8 bits per pass, optional
-// uint32 payload. The count is read from d_count on the device (nullptr: cap).
-// Returns 1 when the sorted data ended up in the *_alt buffers.
+// Stable LSD sort of keys on bits [bit_lo, bit_hi) in ceil(bits / 8) passes of
+// (nearly) equal digit widths, optional uint32 payload. The count is read from
+// d_count on the device (nullptr: cap). With first_counted, the kernel that
+// wrote the keys has already filled the first pass's per-tile digit counts
+// (radix_first_counts, see TileCounts). Returns 1 when the sorted data ended
+// up in the *_alt buffers.
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s);
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted = false);
 int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s);
-// The 256 per-digit key counts of the last pass of the latest sort with this
-// temp and cap (device memory inside temp).
-const uint32_t* radix_last_digit_totals(const void* temp, size_t cap);
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted = false);
+constexpr uint32_t RADIX_TILE = 2048;   // keys per tile of a sort pass
+struct RadixDigit {
+    int shift;
+    uint32_t mask;
+};
+// The first digit of a sort over [bit_lo, bit_hi).
+RadixDigit radix_first_digit(int bit_lo, int bit_hi);
+// The first pass's count table inside temp: counts[d * ntiles + tile], 256
+// rows, ntiles = ceil(cap / RADIX_TILE).
+uint32_t* radix_first_counts(void* temp);
 
 // ---- control block shared by all stages (device memory, zeroed per call)
 constexpr int NBUCKET = 256;          // degree-pair buckets; 255 = no work

@@ -52,18 +52,41 @@ constexpr unsigned DEG_EP_BLOCKS = 1024;
 
 __global__ __launch_bounds__(NT) void k_endpoints(const int2* __restrict__ edges, uint64_t E, int32_t n,
                                                   uint32_t sentinel, uint32_t* __restrict__ keys, Ctrl* ctrl,
-                                                  uint32_t* __restrict__ nsent) {
+                                                  uint32_t* __restrict__ nsent, uint32_t* __restrict__ counts,
+                                                  uint32_t ntiles, RadixDigit dg) {
+    // tile t = endpoints [t * RADIX_TILE, (t + 1) * RADIX_TILE) = pairs [t * EPT, (t + 1) * EPT);
+    // with counts set, the first digit of the endpoint sort is counted per tile
+    constexpr uint32_t EPT = RADIX_TILE / 2, PER = EPT / NT;
     __shared__ uint32_t red[NT / WAVE];
+    __shared__ TileCounts tc;
+    tc.clear();
+    __syncthreads();
     bool bad = false;
     uint32_t sent = 0;
-    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < E; i += (uint64_t)gridDim.x * NT) {
-        const int2 e = edges[i];
-        const bool in_range = e.x >= 0 && e.x < n && e.y >= 0 && e.y < n;
-        bad |= !in_range;
-        const bool ok = in_range && e.x != e.y;
-        keys[2 * i] = ok ? (uint32_t)e.x : sentinel;
-        keys[2 * i + 1] = ok ? (uint32_t)e.y : sentinel;
-        sent += ok ? 0u : 2u;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        int2 ed[PER];
+#pragma unroll
+        for (uint32_t k = 0; k < PER; ++k) {
+            const uint64_t i = (uint64_t)tile * EPT + k * NT + threadIdx.x;
+            ed[k] = i < E ? edges[i] : make_int2(0, 0);
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < PER; ++k) {
+            const uint64_t i = (uint64_t)tile * EPT + k * NT + threadIdx.x;
+            if (i >= E) continue;
+            const int2 e = ed[k];
+            const bool in_range = e.x >= 0 && e.x < n && e.y >= 0 && e.y < n;
+            bad |= !in_range;
+            const bool ok = in_range && e.x != e.y;
+            const uint32_t a = ok ? (uint32_t)e.x : sentinel, b = ok ? (uint32_t)e.y : sentinel;
+            ((uint2*)keys)[i] = make_uint2(a, b);
+            sent += ok ? 0u : 2u;
+            if (counts) {
+                tc.add((a >> dg.shift) & dg.mask);
+                tc.add((b >> dg.shift) & dg.mask);
+            }
+        }
+        if (counts) tc.flush(counts, ntiles, tile);
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, 1u);
     sent = wave_sum(sent);
@@ -179,15 +202,21 @@ __global__ __launch_bounds__(NT) void k_rank(const uint64_t* __restrict__ sorted
 // rank lookups are random gathers, so the kernel lives on memory-level
 // parallelism.
 constexpr int OR_U = 8;
+static_assert(OR_U * NT == (int)RADIX_TILE, "one sort tile per block step");
 __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, uint64_t E, int32_t n,
                                                const uint32_t* __restrict__ rank, int nb, uint64_t sentinel,
-                                               uint64_t* __restrict__ keys) {
-    const uint64_t stride = (uint64_t)gridDim.x * NT;
-    for (uint64_t i0 = (uint64_t)blockIdx.x * NT + threadIdx.x; i0 < E; i0 += stride * OR_U) {
+                                               uint64_t* __restrict__ keys, uint32_t* __restrict__ counts,
+                                               uint32_t ntiles, RadixDigit dg) {
+    // block step = one tile of the pair sort; its first digit is counted as the keys are made
+    __shared__ TileCounts tc;
+    tc.clear();
+    __syncthreads();
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t i0 = (uint64_t)tile * RADIX_TILE + threadIdx.x;
         int2 ed[OR_U];
 #pragma unroll
         for (int k = 0; k < OR_U; ++k) {
-            const uint64_t i = i0 + k * stride;
+            const uint64_t i = i0 + (uint64_t)k * NT;
             ed[k] = i < E ? edges[i] : make_int2(-1, -1);
         }
         uint32_t ra[OR_U], rb[OR_U];
@@ -200,12 +229,15 @@ __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, u
         }
 #pragma unroll
         for (int k = 0; k < OR_U; ++k) {
-            const uint64_t i = i0 + k * stride;
+            const uint64_t i = i0 + (uint64_t)k * NT;
             if (i < E) {
                 const uint32_t lo = ra[k] < rb[k] ? ra[k] : rb[k], hi = ra[k] < rb[k] ? rb[k] : ra[k];
-                keys[i] = ok[k] ? (((uint64_t)lo << nb) | hi) : sentinel;
+                const uint64_t key = ok[k] ? (((uint64_t)lo << nb) | hi) : sentinel;
+                keys[i] = key;
+                tc.add((uint32_t)(key >> dg.shift) & dg.mask);
             }
         }
+        tc.flush(counts, ntiles, tile);
     }
 }
 
@@ -298,15 +330,19 @@ __global__ __launch_bounds__(NT) void k_unique_write(const uint64_t* __restrict_
 // gathered for that entry later. Packing saves that gather for the others.
 __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ col, const uint32_t* __restrict__ src,
                                                  const uint32_t* __restrict__ off, Ctrl* ctrl, int32_t n,
-                                                 uint64_t* __restrict__ keys, int sh, int lbits) {
+                                                 uint64_t* __restrict__ keys, int sh, int lbits,
+                                                 uint32_t* __restrict__ counts, uint32_t ntiles, RadixDigit dg) {
+    __shared__ TileCounts tc;
+    tc.clear();
+    __syncthreads();
     const uint32_t m = ctrl->m;
     const uint64_t esc = (1ull << lbits) - 1ull;   // escape: length gathered at expansion
-    const uint64_t stride = (uint64_t)gridDim.x * NT;
-    for (uint64_t e0 = (uint64_t)blockIdx.x * NT + threadIdx.x; e0 < m; e0 += stride * OR_U) {
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t e0 = (uint64_t)tile * RADIX_TILE + threadIdx.x;
         uint32_t v[OR_U], u[OR_U];
 #pragma unroll
         for (int k = 0; k < OR_U; ++k) {   // loads of all OR_U edges in flight together
-            const uint64_t e = e0 + k * stride;
+            const uint64_t e = e0 + (uint64_t)k * NT;
             v[k] = e < m ? col[e] : 0u;
             u[k] = e < m ? src[e] : 0u;
         }
@@ -319,7 +355,7 @@ __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ co
         }
 #pragma unroll
         for (int k = 0; k < OR_U; ++k) {
-            const uint64_t e = e0 + k * stride;
+            const uint64_t e = e0 + (uint64_t)k * NT;
             if (e >= m) continue;
             const bool work = (e + 1 < end[k]) && (d1[k] > d0[k]);
             uint64_t low = e;
@@ -327,8 +363,11 @@ __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ co
                 const uint64_t len = work ? end[k] - (e + 1) : 0u;
                 low = (low << lbits) | (len < esc ? len : esc);
             }
-            keys[e] = ((uint64_t)(work ? v[k] : (uint32_t)(n - 1)) << sh) | low;
+            const uint64_t key = ((uint64_t)(work ? v[k] : (uint32_t)(n - 1)) << sh) | low;
+            keys[e] = key;
+            tc.add((uint32_t)(key >> dg.shift) & dg.mask);
         }
+        tc.flush(counts, ntiles, tile);
     }
 }
 
@@ -887,15 +926,21 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     {
         uint32_t* ep = (uint32_t*)keysA;       // 2E uint32 fit in E uint64
         uint32_t* ep_alt = (uint32_t*)keysB;
-        const unsigned eg = grid_for((size_t)E, DEG_EP_BLOCKS);
+        // the endpoint sort's first digit is counted by k_endpoints as it writes the keys
+        const uint32_t ep_tiles = (uint32_t)(((uint64_t)(2 * E) + RADIX_TILE - 1) / RADIX_TILE);
+        const bool ep_sort = !bucketed || vbits > bw;
+        const RadixDigit ep_dg = bucketed ? radix_first_digit(bw, vbits) : radix_first_digit(0, bits_for((uint64_t)n + 1));
+        const unsigned eg = ep_tiles < DEG_EP_BLOCKS ? ep_tiles : DEG_EP_BLOCKS;
         hipLaunchKernelGGL(k_endpoints, dim3(eg), dim3(NT), 0, s, edges, (uint64_t)E, n,
-                           bucketed ? (uint32_t)(n - 1) : (uint32_t)n, ep, ctrl, partial);
+                           bucketed ? (uint32_t)(n - 1) : (uint32_t)n, ep, ctrl, partial,
+                           ep_sort ? radix_first_counts(radix_tmp) : nullptr, ep_tiles, ep_dg);
         if (bucketed) {
             // partition by bits [bw, vbits), then count per bucket
             const uint32_t nb = 1u << (vbits - bw);
             int a0 = 0;
             if (vbits > bw)
-                a0 = radix_sort_u32(ep, ep_alt, nullptr, nullptr, nullptr, (size_t)(2 * E), bw, vbits, radix_tmp, s);
+                a0 = radix_sort_u32(ep, ep_alt, nullptr, nullptr, nullptr, (size_t)(2 * E), bw, vbits, radix_tmp, s,
+                                    true);
             uint32_t* bst = (uint32_t*)(ws + L.bstart);
             hipLaunchKernelGGL(k_bucket_starts, dim3(grid_for((size_t)nb + 1)), dim3(NT), 0, s, a0 ? ep_alt : ep,
                                (uint32_t)(2 * E), bw, nb, bst);
@@ -907,7 +952,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
             hipLaunchKernelGGL(k_drop_sentinels, dim3(1), dim3(NT), 0, s, partial, eg, n, deg);
         } else {
             const int a0 = radix_sort_u32(ep, ep_alt, nullptr, nullptr, nullptr, (size_t)(2 * E), 0,
-                                          bits_for((uint64_t)n + 1), radix_tmp, s);
+                                          bits_for((uint64_t)n + 1), radix_tmp, s, true);
             fill_u32(rowend, 0u, (size_t)n, s);
             hipLaunchKernelGGL(k_endpoint_bounds, dim3(grid_for((size_t)(2 * E))), dim3(NT), 0, s, a0 ? ep_alt : ep,
                                (uint64_t)(2 * E), n, rowend);
@@ -931,11 +976,13 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     // ---- orient
     const int nb = bits_for((uint64_t)n) > 0 ? bits_for((uint64_t)n) : 1;
     const uint64_t sentinel = (2 * nb >= 64) ? ~0ull : ((1ull << (2 * nb)) - 1ull);
-    hipLaunchKernelGGL(k_orient, dim3(grid_for(((size_t)E + OR_U - 1) / OR_U)), dim3(NT), 0, s, edges, (uint64_t)E, n, rank, nb, sentinel,
-                       keysA);
+    const uint32_t e_tiles = (uint32_t)(((uint64_t)E + RADIX_TILE - 1) / RADIX_TILE);
+    hipLaunchKernelGGL(k_orient, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, edges, (uint64_t)E, n,
+                       rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, radix_first_digit(0, 2 * nb));
     mark(3);
-    // ---- sort oriented pairs
-    const int alt = radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)E, 0, 2 * nb, radix_tmp, s);
+    // ---- sort oriented pairs (first digit counted by k_orient)
+    const int alt =
+        radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)E, 0, 2 * nb, radix_tmp, s, true);
     uint64_t* sorted = alt ? keysB : keysA;
     uint64_t* other = alt ? keysA : keysB;
     mark(4);
@@ -965,10 +1012,11 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         // ---- CSC: in-edges with work grouped by v (the sorted pair keys are free now);
         // in-edge groups: ids 0 .. n - 1 (n - 1 = no work)
         const CscPacking pk = csc_packing(E, n);
-        hipLaunchKernelGGL(k_csc_keys, dim3(grid_for(((size_t)E + OR_U - 1) / OR_U)), dim3(NT), 0, s, col, src, off,
-                           ctrl, n, other, pk.sh, pk.lbits);
-        const int alt2 =
-            radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, pk.sh, pk.sh + nbv, radix_tmp, s);
+        hipLaunchKernelGGL(k_csc_keys, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, col, src, off,
+                           ctrl, n, other, pk.sh, pk.lbits, radix_first_counts(radix_tmp), e_tiles,
+                           radix_first_digit(pk.sh, pk.sh + nbv));
+        const int alt2 = radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, pk.sh, pk.sh + nbv,
+                                        radix_tmp, s, true);
         csc = alt2 ? sorted : other;
         fill_u32(rowend, 0u, (size_t)n, s);
         hipLaunchKernelGGL(k_csc_bounds, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, n, rowend, pk.sh);

@@ -3,9 +3,10 @@
 // The radix sort is the CSR builder of the method's "induced subgraph" step
 // (Section 4.2, optimisations for edge list generation): edges are sorted
 // by (source, destination) so every row of the filtered graph is contiguous
-// and ascending. Keys are sorted 8 bits per pass; a pass is a per-tile digit
-// histogram, an exclusive scan of the digit-major histogram, and a stable
-// scatter that ranks equal digits inside each wave with ballots.
+// and ascending. Keys are sorted in ceil(bits / 8) passes of equal digit
+// widths; a pass is a per-tile digit histogram, an exclusive scan of the
+// digit-major histogram, and a stable scatter that ranks equal digits inside
+// each wave with ballots.
 #include "common.h"
 #include "internal.h"
 
@@ -207,6 +208,7 @@ constexpr int RS_WAVES = RS_NT / WAVE;
 constexpr int RS_ITEMS = 8;                     // per lane
 constexpr int RS_TILE = RS_NT * RS_ITEMS;       // 2048 keys per tile
 constexpr int RS_WAVE_SPAN = WAVE * RS_ITEMS;   // 512 keys per wave, striped by lane
+static_assert(RS_TILE == (int)RADIX_TILE, "tile size shared with the key-producing kernels");
 
 __device__ __forceinline__ uint32_t rs_count(const uint32_t* d_count, uint32_t cap) {
     const uint32_t c = d_count ? *d_count : cap;
@@ -393,10 +395,27 @@ size_t radix_temp_bytes(size_t cap) {
            align_up(sizeof(uint32_t) * 256 * (rs_nseg(cap) + 1), 256);
 }
 
+// Digit width of a sort over `bits` bits: the passes an 8-bit digit needs,
+// with the bits spread evenly over them (a narrow last digit would crowd all
+// keys into a few counters of the histogram).
+static int digit_width(int bits) {
+    const int passes = (bits + 7) / 8;
+    return (bits + passes - 1) / passes;
+}
+
+RadixDigit radix_first_digit(int bit_lo, int bit_hi) {
+    const int bits = bit_hi - bit_lo;
+    const int w = bits > 0 ? digit_width(bits) : 0;
+    return {bit_lo, w > 0 ? (uint32_t)((1u << w) - 1u) : 0u};
+}
+
+uint32_t* radix_first_counts(void* temp) { return (uint32_t*)temp; }
+
 template <typename KeyT>
 static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                      size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s) {
+                      size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted) {
     if (cap == 0 || bit_hi <= bit_lo) return 0;
+    const int width = digit_width(bit_hi - bit_lo);
     const uint32_t ntiles = (uint32_t)((cap + RS_TILE - 1) / RS_TILE);
     uint32_t* hist = (uint32_t*)temp;
     void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * ((cap + RS_TILE - 1) / RS_TILE + 1), 256);
@@ -408,11 +427,12 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
     uint32_t* vin = vals;
     uint32_t* vout = vals_alt;
     int passes = 0;
-    for (int shift = bit_lo; shift < bit_hi; shift += 8, ++passes) {
-        const int dbits = bit_hi - shift < 8 ? bit_hi - shift : 8;   // the last digit may be narrower
+    for (int shift = bit_lo; shift < bit_hi; shift += width, ++passes) {
+        const int dbits = bit_hi - shift < width ? bit_hi - shift : width;   // the last digit may be narrower
         const uint32_t dmask = (1u << dbits) - 1u;
-        hipLaunchKernelGGL(k_radix_hist<KeyT>, dim3(ntiles), dim3(RS_NT), 0, s, kin, d_count, (uint32_t)cap, shift,
-                           dmask, hist, ntiles);
+        if (!(first_counted && passes == 0))
+            hipLaunchKernelGGL(k_radix_hist<KeyT>, dim3(ntiles), dim3(RS_NT), 0, s, kin, d_count, (uint32_t)cap,
+                               shift, dmask, hist, ntiles);
         hipLaunchKernelGGL(k_radix_rowscan, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, digit_tot, seg_tot);
         if (nseg > 1)
             hipLaunchKernelGGL(k_radix_rowfix, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, seg_tot, digit_tot);
@@ -429,19 +449,16 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
     return passes & 1;   // 1: result is in keys_alt / vals_alt
 }
 
-const uint32_t* radix_last_digit_totals(const void* temp, size_t cap) {
-    return (const uint32_t*)((const char*)temp +
-                             align_up(sizeof(uint32_t) * 256 * ((cap + RS_TILE - 1) / RS_TILE + 1), 256));
-}
-
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s) {
-    return radix_sort<uint64_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s);
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted) {
+    return radix_sort<uint64_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
+                                first_counted);
 }
 
 int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s) {
-    return radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s);
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted) {
+    return radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
+                                first_counted);
 }
 
 }  // namespace tcx
