@@ -234,10 +234,10 @@ __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, u
                 const uint32_t lo = ra[k] < rb[k] ? ra[k] : rb[k], hi = ra[k] < rb[k] ? rb[k] : ra[k];
                 const uint64_t key = ok[k] ? (((uint64_t)lo << nb) | hi) : sentinel;
                 keys[i] = key;
-                tc.add((uint32_t)(key >> dg.shift) & dg.mask);
+                if (counts) tc.add((uint32_t)(key >> dg.shift) & dg.mask);
             }
         }
-        tc.flush(counts, ntiles, tile);
+        if (counts) tc.flush(counts, ntiles, tile);
     }
 }
 
@@ -365,9 +365,9 @@ __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ co
             }
             const uint64_t key = ((uint64_t)(work ? v[k] : (uint32_t)(n - 1)) << sh) | low;
             keys[e] = key;
-            tc.add((uint32_t)(key >> dg.shift) & dg.mask);
+            if (counts) tc.add((uint32_t)(key >> dg.shift) & dg.mask);
         }
-        tc.flush(counts, ntiles, tile);
+        if (counts) tc.flush(counts, ntiles, tile);
     }
 }
 
