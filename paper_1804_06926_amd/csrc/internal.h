@@ -27,7 +27,7 @@ int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t*
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted = false);
 int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted = false);
-constexpr uint32_t RADIX_TILE = 2048;   // keys per tile of a sort pass
+constexpr uint32_t RADIX_TILE = 4096;   // keys per tile of a sort pass
 struct RadixDigit {
     int shift;
     uint32_t mask;

@@ -202,7 +202,7 @@ __global__ __launch_bounds__(NT) void k_rank(const uint64_t* __restrict__ sorted
 // rank lookups are random gathers, so the kernel lives on memory-level
 // parallelism.
 constexpr int OR_U = 8;
-static_assert(OR_U * NT == (int)RADIX_TILE, "one sort tile per block step");
+static_assert(RADIX_TILE % (OR_U * NT) == 0, "whole rounds per sort tile");
 __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, uint64_t E, int32_t n,
                                                const uint32_t* __restrict__ rank, int nb, uint64_t sentinel,
                                                uint64_t* __restrict__ keys, uint32_t* __restrict__ counts,
@@ -212,7 +212,8 @@ __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, u
     tc.clear();
     __syncthreads();
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint64_t i0 = (uint64_t)tile * RADIX_TILE + threadIdx.x;
+      for (uint32_t r = 0; r < RADIX_TILE; r += OR_U * NT) {
+        const uint64_t i0 = (uint64_t)tile * RADIX_TILE + r + threadIdx.x;
         int2 ed[OR_U];
 #pragma unroll
         for (int k = 0; k < OR_U; ++k) {
@@ -237,6 +238,7 @@ __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, u
                 if (counts) tc.add((uint32_t)(key >> dg.shift) & dg.mask);
             }
         }
+      }
         if (counts) tc.flush(counts, ntiles, tile);
     }
 }
@@ -338,7 +340,8 @@ __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ co
     const uint32_t m = ctrl->m;
     const uint64_t esc = (1ull << lbits) - 1ull;   // escape: length gathered at expansion
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint64_t e0 = (uint64_t)tile * RADIX_TILE + threadIdx.x;
+      for (uint32_t r = 0; r < RADIX_TILE; r += OR_U * NT) {
+        const uint64_t e0 = (uint64_t)tile * RADIX_TILE + r + threadIdx.x;
         uint32_t v[OR_U], u[OR_U];
 #pragma unroll
         for (int k = 0; k < OR_U; ++k) {   // loads of all OR_U edges in flight together
@@ -367,6 +370,7 @@ __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ co
             keys[e] = key;
             if (counts) tc.add((uint32_t)(key >> dg.shift) & dg.mask);
         }
+      }
         if (counts) tc.flush(counts, ntiles, tile);
     }
 }

@@ -205,7 +205,7 @@ void scan_exclusive_sum_u64(const uint64_t* in, uint64_t* out, size_t len, void*
 // ------------------------------------------------------------------ radix sort
 constexpr int RS_NT = 256;
 constexpr int RS_WAVES = RS_NT / WAVE;
-constexpr int RS_ITEMS = 8;                     // per lane
+constexpr int RS_ITEMS = 16;                    // per lane
 constexpr int RS_TILE = RS_NT * RS_ITEMS;       // 2048 keys per tile
 constexpr int RS_WAVE_SPAN = WAVE * RS_ITEMS;   // 512 keys per wave, striped by lane
 static_assert(RS_TILE == (int)RADIX_TILE, "tile size shared with the key-producing kernels");

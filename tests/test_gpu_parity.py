@@ -263,10 +263,10 @@ def test_csr_export_matches_definition(tc):
     np.testing.assert_array_equal(col.cpu().numpy(), r_col)
 
 
-@pytest.mark.parametrize("count,bits", [(c, b) for c in (1, 2047, 2048, 2049, 100003)
+@pytest.mark.parametrize("count,bits", [(c, b) for c in (1, 4095, 4096, 4097, 100003)
                                         for b in ((0, 64), (0, 20), (32, 45), (7, 13))]
-                         # a sort of more than 2^24 keys with a ragged last tile
-                         + [(8 * 1024 * 2048 + 2048 * 5 + 77, (0, 64)), (8 * 1024 * 2048 + 2048 * 5 + 77, (7, 13))])
+                         # more than 8192 tiles of 4096 keys (several digit-row segments), ragged last tile
+                         + [(8 * 1024 * 4096 + 4096 * 5 + 77, (0, 64)), (8 * 1024 * 4096 + 4096 * 5 + 77, (7, 13))])
 def test_radix_sort_is_stable_and_exact(tc, count, bits):
     import torch
     rng = np.random.default_rng(count + bits[0])
