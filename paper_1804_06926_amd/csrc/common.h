@@ -81,7 +81,7 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T* scratch, T* total = nu
 }
 
 // First-pass digit counts of a radix sort, gathered by the kernel that writes
-// the keys: a block of 256 threads writes tile t (RADIX_TILE consecutive keys)
+// the keys: a block of 256 threads writes tile t (the sort's tile of consecutive keys)
 // and adds each key's first digit here; flush() stores the tile's column of
 // the count table (256 digit rows) and clears the counters.
 struct TileCounts {

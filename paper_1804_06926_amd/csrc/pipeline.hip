@@ -53,10 +53,12 @@ constexpr unsigned DEG_EP_BLOCKS = 1024;
 __global__ __launch_bounds__(NT) void k_endpoints(const int2* __restrict__ edges, uint64_t E, int32_t n,
                                                   uint32_t sentinel, uint32_t* __restrict__ keys, Ctrl* ctrl,
                                                   uint32_t* __restrict__ nsent, uint32_t* __restrict__ counts,
-                                                  uint32_t ntiles, RadixDigit dg) {
-    // tile t = endpoints [t * RADIX_TILE, (t + 1) * RADIX_TILE) = pairs [t * EPT, (t + 1) * EPT);
-    // with counts set, the first digit of the endpoint sort is counted per tile
-    constexpr uint32_t EPT = RADIX_TILE / 2, PER = EPT / NT;
+                                                  uint32_t ntiles, uint32_t tile_keys, RadixDigit dg) {
+    // tile t = endpoints [t * tile_keys, (t + 1) * tile_keys) = pairs [t * EPT, (t + 1) * EPT),
+    // in rounds of NT * PER pairs; with counts set, the first digit of the endpoint sort is
+    // counted per tile
+    constexpr uint32_t PER = 4;
+    const uint32_t EPT = tile_keys / 2;
     __shared__ uint32_t red[NT / WAVE];
     __shared__ TileCounts tc;
     tc.clear();
@@ -64,15 +66,16 @@ __global__ __launch_bounds__(NT) void k_endpoints(const int2* __restrict__ edges
     bool bad = false;
     uint32_t sent = 0;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+      for (uint32_t r = 0; r < EPT; r += PER * NT) {
         int2 ed[PER];
 #pragma unroll
         for (uint32_t k = 0; k < PER; ++k) {
-            const uint64_t i = (uint64_t)tile * EPT + k * NT + threadIdx.x;
+            const uint64_t i = (uint64_t)tile * EPT + r + k * NT + threadIdx.x;
             ed[k] = i < E ? edges[i] : make_int2(0, 0);
         }
 #pragma unroll
         for (uint32_t k = 0; k < PER; ++k) {
-            const uint64_t i = (uint64_t)tile * EPT + k * NT + threadIdx.x;
+            const uint64_t i = (uint64_t)tile * EPT + r + k * NT + threadIdx.x;
             if (i >= E) continue;
             const int2 e = ed[k];
             const bool in_range = e.x >= 0 && e.x < n && e.y >= 0 && e.y < n;
@@ -86,6 +89,7 @@ __global__ __launch_bounds__(NT) void k_endpoints(const int2* __restrict__ edges
                 tc.add((b >> dg.shift) & dg.mask);
             }
         }
+      }
         if (counts) tc.flush(counts, ntiles, tile);
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, 1u);
@@ -202,18 +206,18 @@ __global__ __launch_bounds__(NT) void k_rank(const uint64_t* __restrict__ sorted
 // rank lookups are random gathers, so the kernel lives on memory-level
 // parallelism.
 constexpr int OR_U = 8;
-static_assert(RADIX_TILE % (OR_U * NT) == 0, "whole rounds per sort tile");
+// sort tiles (radix_tile_keys) are whole multiples of one round, OR_U * NT keys
 __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, uint64_t E, int32_t n,
                                                const uint32_t* __restrict__ rank, int nb, uint64_t sentinel,
                                                uint64_t* __restrict__ keys, uint32_t* __restrict__ counts,
-                                               uint32_t ntiles, RadixDigit dg) {
+                                               uint32_t ntiles, uint32_t tile_keys, RadixDigit dg) {
     // block step = one tile of the pair sort; its first digit is counted as the keys are made
     __shared__ TileCounts tc;
     tc.clear();
     __syncthreads();
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-      for (uint32_t r = 0; r < RADIX_TILE; r += OR_U * NT) {
-        const uint64_t i0 = (uint64_t)tile * RADIX_TILE + r + threadIdx.x;
+      for (uint32_t r = 0; r < tile_keys; r += OR_U * NT) {
+        const uint64_t i0 = (uint64_t)tile * tile_keys + r + threadIdx.x;
         int2 ed[OR_U];
 #pragma unroll
         for (int k = 0; k < OR_U; ++k) {
@@ -333,15 +337,16 @@ __global__ __launch_bounds__(NT) void k_unique_write(const uint64_t* __restrict_
 __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ col, const uint32_t* __restrict__ src,
                                                  const uint32_t* __restrict__ off, Ctrl* ctrl, int32_t n,
                                                  uint64_t* __restrict__ keys, int sh, int lbits,
-                                                 uint32_t* __restrict__ counts, uint32_t ntiles, RadixDigit dg) {
+                                                 uint32_t* __restrict__ counts, uint32_t ntiles, uint32_t tile_keys,
+                                                 RadixDigit dg) {
     __shared__ TileCounts tc;
     tc.clear();
     __syncthreads();
     const uint32_t m = ctrl->m;
     const uint64_t esc = (1ull << lbits) - 1ull;   // escape: length gathered at expansion
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-      for (uint32_t r = 0; r < RADIX_TILE; r += OR_U * NT) {
-        const uint64_t e0 = (uint64_t)tile * RADIX_TILE + r + threadIdx.x;
+      for (uint32_t r = 0; r < tile_keys; r += OR_U * NT) {
+        const uint64_t e0 = (uint64_t)tile * tile_keys + r + threadIdx.x;
         uint32_t v[OR_U], u[OR_U];
 #pragma unroll
         for (int k = 0; k < OR_U; ++k) {   // loads of all OR_U edges in flight together
@@ -931,13 +936,14 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         uint32_t* ep = (uint32_t*)keysA;       // 2E uint32 fit in E uint64
         uint32_t* ep_alt = (uint32_t*)keysB;
         // the endpoint sort's first digit is counted by k_endpoints as it writes the keys
-        const uint32_t ep_tiles = (uint32_t)(((uint64_t)(2 * E) + RADIX_TILE - 1) / RADIX_TILE);
+        const uint32_t ep_tile = radix_tile_keys((size_t)(2 * E));
+        const uint32_t ep_tiles = (uint32_t)(((uint64_t)(2 * E) + ep_tile - 1) / ep_tile);
         const bool ep_sort = !bucketed || vbits > bw;
         const RadixDigit ep_dg = bucketed ? radix_first_digit(bw, vbits) : radix_first_digit(0, bits_for((uint64_t)n + 1));
         const unsigned eg = ep_tiles < DEG_EP_BLOCKS ? ep_tiles : DEG_EP_BLOCKS;
         hipLaunchKernelGGL(k_endpoints, dim3(eg), dim3(NT), 0, s, edges, (uint64_t)E, n,
                            bucketed ? (uint32_t)(n - 1) : (uint32_t)n, ep, ctrl, partial,
-                           ep_sort ? radix_first_counts(radix_tmp) : nullptr, ep_tiles, ep_dg);
+                           ep_sort ? radix_first_counts(radix_tmp) : nullptr, ep_tiles, ep_tile, ep_dg);
         if (bucketed) {
             // partition by bits [bw, vbits), then count per bucket
             const uint32_t nb = 1u << (vbits - bw);
@@ -980,9 +986,11 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     // ---- orient
     const int nb = bits_for((uint64_t)n) > 0 ? bits_for((uint64_t)n) : 1;
     const uint64_t sentinel = (2 * nb >= 64) ? ~0ull : ((1ull << (2 * nb)) - 1ull);
-    const uint32_t e_tiles = (uint32_t)(((uint64_t)E + RADIX_TILE - 1) / RADIX_TILE);
+    const uint32_t e_tile = radix_tile_keys((size_t)E);
+    const uint32_t e_tiles = (uint32_t)(((uint64_t)E + e_tile - 1) / e_tile);
     hipLaunchKernelGGL(k_orient, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, edges, (uint64_t)E, n,
-                       rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, radix_first_digit(0, 2 * nb));
+                       rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, e_tile,
+                       radix_first_digit(0, 2 * nb));
     mark(3);
     // ---- sort oriented pairs (first digit counted by k_orient)
     const int alt =
@@ -1017,7 +1025,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         // in-edge groups: ids 0 .. n - 1 (n - 1 = no work)
         const CscPacking pk = csc_packing(E, n);
         hipLaunchKernelGGL(k_csc_keys, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, col, src, off,
-                           ctrl, n, other, pk.sh, pk.lbits, radix_first_counts(radix_tmp), e_tiles,
+                           ctrl, n, other, pk.sh, pk.lbits, radix_first_counts(radix_tmp), e_tiles, e_tile,
                            radix_first_digit(pk.sh, pk.sh + nbv));
         const int alt2 = radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, pk.sh, pk.sh + nbv,
                                         radix_tmp, s, true);

@@ -203,12 +203,17 @@ void scan_exclusive_sum_u64(const uint64_t* in, uint64_t* out, size_t len, void*
 }
 
 // ------------------------------------------------------------------ radix sort
+// A tile is RS_NT threads x ITEMS keys: 16 keys per lane (4096-key tiles, longer
+// runs of equal digits for the scatter, half the count table) for sorts of at
+// least 2^22 keys, 8 (2048-key tiles, twice the blocks) below.
 constexpr int RS_NT = 256;
 constexpr int RS_WAVES = RS_NT / WAVE;
-constexpr int RS_ITEMS = 16;                    // per lane
-constexpr int RS_TILE = RS_NT * RS_ITEMS;       // 2048 keys per tile
-constexpr int RS_WAVE_SPAN = WAVE * RS_ITEMS;   // 512 keys per wave, striped by lane
-static_assert(RS_TILE == (int)RADIX_TILE, "tile size shared with the key-producing kernels");
+constexpr int RS_ITEMS_SMALL = 8, RS_ITEMS_LARGE = 16;
+constexpr size_t RS_LARGE_CAP = (size_t)1 << 22;
+
+uint32_t radix_tile_keys(size_t cap) {
+    return (uint32_t)(RS_NT * (cap >= RS_LARGE_CAP ? RS_ITEMS_LARGE : RS_ITEMS_SMALL));
+}
 
 __device__ __forceinline__ uint32_t rs_count(const uint32_t* d_count, uint32_t cap) {
     const uint32_t c = d_count ? *d_count : cap;
@@ -216,11 +221,12 @@ __device__ __forceinline__ uint32_t rs_count(const uint32_t* d_count, uint32_t c
 }
 
 // Per-tile digit counts, written digit-major: hist[d * ntiles + tile].
-template <typename KeyT>
+template <typename KeyT, int RS_ITEMS>
 __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ keys, const uint32_t* d_count,
                                                       uint32_t cap, int shift, uint32_t dmask,
                                                       uint32_t* __restrict__ hist,
                                                       uint32_t ntiles) {
+    constexpr int RS_TILE = RS_NT * RS_ITEMS, RS_WAVE_SPAN = WAVE * RS_ITEMS;   // keys per tile / per wave
     __shared__ uint32_t wcnt[RS_WAVES][256];
     for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
     __syncthreads();
@@ -298,7 +304,7 @@ __global__ __launch_bounds__(RS_NT) void k_radix_rowfix(uint32_t* __restrict__ h
     for (uint32_t i = s0 + threadIdx.x; i < s1; i += RS_NT) row[i] += carry;
 }
 
-template <typename KeyT, bool HAS_VAL>
+template <typename KeyT, bool HAS_VAL, int RS_ITEMS>
 __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const KeyT* __restrict__ kin,
                                                          const uint32_t* __restrict__ vin,
                                                          KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -306,6 +312,7 @@ __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const KeyT* __restrict_
                                                          uint32_t dmask,
                                                          const uint32_t* __restrict__ hist_scan, uint32_t ntiles,
                                                          const uint32_t* __restrict__ digit_tot) {
+    constexpr int RS_TILE = RS_NT * RS_ITEMS, RS_WAVE_SPAN = WAVE * RS_ITEMS;
     __shared__ uint32_t wcnt[RS_WAVES][256];
     __shared__ uint32_t lstart[256];
     __shared__ uint32_t gbase[256];
@@ -383,16 +390,15 @@ __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const KeyT* __restrict_
 }
 
 // Temporary layout: histogram table [256][ntiles + 1] | digit totals [256] (in the
-// scan-temporary area) | segment totals [256][segments].
-static size_t rs_nseg(size_t cap) {
-    const size_t ntiles = (cap + RS_TILE - 1) / RS_TILE;
-    return (ntiles + RS_ROW_SEG - 1) / RS_ROW_SEG;
-}
+// scan-temporary area) | segment totals [256][segments]. Sized for the
+// smaller tiles, whose table is the larger.
+static size_t rs_ntiles(size_t cap, uint32_t tile) { return (cap + tile - 1) / tile; }
+static size_t rs_nseg(size_t ntiles) { return (ntiles + RS_ROW_SEG - 1) / RS_ROW_SEG; }
 
 size_t radix_temp_bytes(size_t cap) {
-    const size_t ntiles = (cap + RS_TILE - 1) / RS_TILE + 1;
-    return align_up(sizeof(uint32_t) * 256 * ntiles, 256) + align_up(scan_temp_bytes(), 256) +
-           align_up(sizeof(uint32_t) * 256 * (rs_nseg(cap) + 1), 256);
+    const size_t ntiles = rs_ntiles(cap, RS_NT * RS_ITEMS_SMALL);
+    return align_up(sizeof(uint32_t) * 256 * (ntiles + 1), 256) + align_up(scan_temp_bytes(), 256) +
+           align_up(sizeof(uint32_t) * 256 * (rs_nseg(ntiles) + 1), 256);
 }
 
 // Digit width of a sort over `bits` bits: the passes an 8-bit digit needs,
@@ -411,17 +417,16 @@ RadixDigit radix_first_digit(int bit_lo, int bit_hi) {
 
 uint32_t* radix_first_counts(void* temp) { return (uint32_t*)temp; }
 
-template <typename KeyT>
+template <typename KeyT, int RS_ITEMS>
 static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                       size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted) {
-    if (cap == 0 || bit_hi <= bit_lo) return 0;
     const int width = digit_width(bit_hi - bit_lo);
-    const uint32_t ntiles = (uint32_t)((cap + RS_TILE - 1) / RS_TILE);
+    const uint32_t ntiles = (uint32_t)rs_ntiles(cap, RS_NT * RS_ITEMS);
     uint32_t* hist = (uint32_t*)temp;
-    void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * ((cap + RS_TILE - 1) / RS_TILE + 1), 256);
+    void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * (ntiles + 1), 256);
     uint32_t* digit_tot = (uint32_t*)scan_tmp;   // 256 digit totals
     uint32_t* seg_tot = (uint32_t*)((char*)scan_tmp + align_up(scan_temp_bytes(), 256));
-    const uint32_t nseg = (uint32_t)rs_nseg(cap);
+    const uint32_t nseg = (uint32_t)rs_nseg(ntiles);
     KeyT* kin = keys;
     KeyT* kout = keys_alt;
     uint32_t* vin = vals;
@@ -431,16 +436,16 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
         const int dbits = bit_hi - shift < width ? bit_hi - shift : width;   // the last digit may be narrower
         const uint32_t dmask = (1u << dbits) - 1u;
         if (!(first_counted && passes == 0))
-            hipLaunchKernelGGL(k_radix_hist<KeyT>, dim3(ntiles), dim3(RS_NT), 0, s, kin, d_count, (uint32_t)cap,
-                               shift, dmask, hist, ntiles);
+            hipLaunchKernelGGL((k_radix_hist<KeyT, RS_ITEMS>), dim3(ntiles), dim3(RS_NT), 0, s, kin, d_count,
+                               (uint32_t)cap, shift, dmask, hist, ntiles);
         hipLaunchKernelGGL(k_radix_rowscan, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, digit_tot, seg_tot);
         if (nseg > 1)
             hipLaunchKernelGGL(k_radix_rowfix, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, seg_tot, digit_tot);
         if (vals) {
-            hipLaunchKernelGGL((k_radix_scatter<KeyT, true>), dim3(ntiles), dim3(RS_NT), 0, s, kin, vin, kout, vout,
+            hipLaunchKernelGGL((k_radix_scatter<KeyT, true, RS_ITEMS>), dim3(ntiles), dim3(RS_NT), 0, s, kin, vin, kout, vout,
                                d_count, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot);
         } else {
-            hipLaunchKernelGGL((k_radix_scatter<KeyT, false>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr, kout,
+            hipLaunchKernelGGL((k_radix_scatter<KeyT, false, RS_ITEMS>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr, kout,
                                nullptr, d_count, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot);
         }
         KeyT* tk = kin; kin = kout; kout = tk;
@@ -449,16 +454,27 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
     return passes & 1;   // 1: result is in keys_alt / vals_alt
 }
 
+template <typename KeyT>
+static int radix_sort_any(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
+                          size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted) {
+    if (cap == 0 || bit_hi <= bit_lo) return 0;
+    if (radix_tile_keys(cap) == RS_NT * RS_ITEMS_LARGE)
+        return radix_sort<KeyT, RS_ITEMS_LARGE>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
+                                                first_counted);
+    return radix_sort<KeyT, RS_ITEMS_SMALL>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
+                                            first_counted);
+}
+
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted) {
-    return radix_sort<uint64_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                first_counted);
+    return radix_sort_any<uint64_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
+                                    first_counted);
 }
 
 int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted) {
-    return radix_sort<uint32_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                first_counted);
+    return radix_sort_any<uint32_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
+                                    first_counted);
 }
 
 }  // namespace tcx

@@ -263,8 +263,10 @@ def test_csr_export_matches_definition(tc):
     np.testing.assert_array_equal(col.cpu().numpy(), r_col)
 
 
-@pytest.mark.parametrize("count,bits", [(c, b) for c in (1, 4095, 4096, 4097, 100003)
+@pytest.mark.parametrize("count,bits", [(c, b) for c in (1, 2047, 2048, 2049, 4097, 100003)
                                         for b in ((0, 64), (0, 20), (32, 45), (7, 13))]
+                         # either side of the switch from 2048- to 4096-key tiles (2^22 keys)
+                         + [((1 << 22) - 1, (0, 20)), ((1 << 22) + 4097, (0, 64))]
                          # more than 8192 tiles of 4096 keys (several digit-row segments), ragged last tile
                          + [(8 * 1024 * 4096 + 4096 * 5 + 77, (0, 64)), (8 * 1024 * 4096 + 4096 * 5 + 77, (7, 13))])
 def test_radix_sort_is_stable_and_exact(tc, count, bits):
