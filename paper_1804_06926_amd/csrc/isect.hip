@@ -60,13 +60,15 @@ __device__ uint32_t load_tile(const IsectArgs& a, uint32_t t, SegsT<N>& S) {
             S.e0[threadIdx.x] = a.inoff[v];
             cnt = a.inoff[v + 1] - a.inoff[v];
         }
-    } else {
-        nseg = 1;
+    } else {   // one vertex: no scan needed
         if (threadIdx.x == 0) {
             S.v[0] = d.x;
             S.e0[0] = d.y;
-            cnt = d.z;
+            S.pref[0] = 0;
+            S.pref[1] = d.z;
         }
+        __syncthreads();
+        return 1;
     }
     uint32_t total;
     const uint32_t excl = block_exclusive_scan<IS_NT>(cnt, S.scratch, &total);
@@ -193,58 +195,61 @@ __device__ __forceinline__ uint32_t wave_first_at_least(const uint32_t* col, uin
 // items [s_pref[k], s_pref[k + 1]) of a flat item range, item q at
 // col[s_base[k] + q] (s_base = start - s_pref, modular). Tails of at least
 // LONG_TAIL items come first, then the shorter non-empty ones; empty tails are
-// left out, so s_pref is strictly increasing. Thread t holds entries t and
-// t + IS_NT (start st_h, length len_h; length 0 past the vertex's entries).
-// Returns the entries kept; nl = long entries, L = total items. Whole block;
-// contains barriers.
+// left out, so s_pref is strictly increasing. Thread t holds entries EH * t ..
+// EH * t + EH - 1 (start st_h, length len_h; length 0 past the vertex's
+// entries) and later owns the table slots with the same indexes, so each
+// phase needs one block scan. Returns the entries kept; nl = long entries,
+// L = total items. Whole block; contains barriers.
 template <bool CNT>
 __device__ __forceinline__ uint32_t entry_table(const uint32_t (&st_h)[EH], const uint32_t (&len_h)[EH],
                                                 uint32_t* s_pref, uint32_t* s_base, uint32_t* s_cnt,
                                                 uint32_t* scratch, uint32_t& nl, uint32_t& L) {
-    uint32_t pos_h[EH];
-    uint32_t cl = 0, cs = 0;   // long and non-empty short entries of the earlier passes
+    uint32_t f = 0;   // long entries in the high half, non-empty short ones in the low half
 #pragma unroll
-    for (int h = 0; h < EH; ++h) {   // both counts in one scan: long in the high half
-        const uint32_t len = len_h[h];
-        const uint32_t f = len >= LONG_TAIL ? 0x10000u : (len ? 1u : 0u);
-        uint32_t total;
-        const uint32_t ex = block_exclusive_scan<IS_NT>(f, scratch, &total);
-        pos_h[h] = len >= LONG_TAIL ? cl + (ex >> 16) : cs + (ex & 0xFFFFu);
-        cl += total >> 16;
-        cs += total & 0xFFFFu;
-    }
+    for (int h = 0; h < EH; ++h) f += len_h[h] >= LONG_TAIL ? 0x10000u : (len_h[h] ? 1u : 0u);
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan<IS_NT>(f, scratch, &total);
+    const uint32_t cl = total >> 16, cs = total & 0xFFFFu;
+    uint32_t pl = ex >> 16, ps = cl + (ex & 0xFFFFu);
 #pragma unroll
     for (int h = 0; h < EH; ++h) {   // lengths and starts in table order
         if (!len_h[h]) continue;
-        const uint32_t pos = len_h[h] >= LONG_TAIL ? pos_h[h] : cl + pos_h[h];
+        const uint32_t pos = len_h[h] >= LONG_TAIL ? pl++ : ps++;
         s_pref[pos] = len_h[h];
         s_base[pos] = st_h[h];
         if (CNT) s_cnt[pos] = 0;
     }
     __syncthreads();
     const uint32_t nt = cl + cs;
-    uint32_t carry = 0;
+    uint32_t len[EH], st[EH], sum = 0;
 #pragma unroll
-    for (int h = 0; h < EH; ++h) {   // in place: each thread rewrites its own slots
-        const uint32_t k = h * IS_NT + threadIdx.x;
-        const uint32_t len = k < nt ? s_pref[k] : 0u;
-        const uint32_t st = k < nt ? s_base[k] : 0u;
-        uint32_t total;
-        const uint32_t excl = block_exclusive_scan<IS_NT>(len, scratch, &total);
-        if (k < nt) {
-            s_pref[k] = carry + excl;
-            s_base[k] = st - (carry + excl);
-        }
-        carry += total;
+    for (int h = 0; h < EH; ++h) {   // this thread's slots, rewritten in place below
+        const uint32_t k = EH * threadIdx.x + (uint32_t)h;
+        len[h] = k < nt ? s_pref[k] : 0u;
+        st[h] = k < nt ? s_base[k] : 0u;
+        sum += len[h];
     }
-    if (threadIdx.x == 0) s_pref[nt] = carry;
+    uint32_t items;
+    uint32_t run = block_exclusive_scan<IS_NT>(sum, scratch, &items);
+#pragma unroll
+    for (int h = 0; h < EH; ++h) {
+        const uint32_t k = EH * threadIdx.x + (uint32_t)h;
+        if (k < nt) {
+            s_pref[k] = run;
+            s_base[k] = st[h] - run;
+        }
+        run += len[h];
+    }
+    if (threadIdx.x == 0) s_pref[nt] = items;
     nl = cl;
-    L = carry;
+    L = items;
     return nt;
 }
 
+// Six blocks of four waves fit a CU by LDS in every mode but the gathering one
+// (44 KB); the register budget is held to the same occupancy (80 VGPRs).
 template <int MODE, bool NARROW>
-__global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* partials) {
+__global__ __launch_bounds__(IS_NT, MODE == BM_GATHER ? 1 : 6) void k_isect_bitmap(IsectArgs a, uint64_t* partials) {
     constexpr bool GATHER = MODE == BM_GATHER;
     constexpr bool CLIP = MODE == BM_CLIP;
     constexpr bool need_cnt = MODE != BM_COUNT && !CLIP;
@@ -269,11 +274,11 @@ __global__ __launch_bounds__(IS_NT) void k_isect_bitmap(IsectArgs a, uint64_t* p
             const uint32_t ne = S.pref[sg + 1] - S.pref[sg];
             const uint32_t b0 = a.off[v], b1 = a.off[v + 1];
             const uint32_t nb = b1 - b0;
-            // the vertex's entries (ne <= CHUNK_MAX = 2 * IS_NT: two per thread)
+            // the vertex's entries (ne <= CHUNK_MAX = EH * IS_NT: EH consecutive ones per thread)
             uint32_t st_h[EH], len_h[EH];
 #pragma unroll
             for (int h = 0; h < EH; ++h) {
-                const uint32_t k = h * IS_NT + threadIdx.x;
+                const uint32_t k = EH * threadIdx.x + (uint32_t)h;
                 st_h[h] = len_h[h] = 0;
                 if (k < ne) {
                     const uint64_t ent = a.csc[e0 + k];   // tail start | tail end << 32
