@@ -233,8 +233,9 @@ tc_status tc_count_triangles_batch(tc_ctx* ctx, const int32_t* d_edges, const in
 
 /*
  * Tile shapes per degree-pair bucket (the autotuner's output): h_chunk[256]
- * in-edges per tile (16..512; 0 = default), h_group[256] lanes per in-edge
- * for merge path and binary search (power of two 1..64; 0 = default).
+ * in-edges per tile (16..2048, at most 512 for buckets the bitmap strategy
+ * serves; values outside are clamped; 0 = default), h_group[256] lanes per
+ * in-edge for merge path and binary search (power of two 1..64; 0 = default).
  * NULL resets to the defaults. Shapes change speed only, never counts.
  */
 tc_status tc_set_tile_shapes(tc_ctx* ctx, const uint16_t* h_chunk, const uint8_t* h_group);

@@ -17,7 +17,7 @@ from . import _lib
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tile_shapes.json")
-CANDIDATES = (32, 64, 128, 256, 512)
+CANDIDATES = (32, 64, 128, 256, 512, 1024, 2048)   # the bitmap kernel caps at 512
 
 
 def device_key(select: int, device: str = "cuda:0") -> str:

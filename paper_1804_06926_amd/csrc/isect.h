@@ -9,6 +9,7 @@
 namespace tcx {
 
 constexpr int CHUNK_MAX = 512;   // in-edges per tile (LDS-resident entry table)
+constexpr int STAGE_MAX = 4096;  // list elements of a tile that merge/bsearch stage in LDS (else read in place)
 
 struct IsectArgs {
     Ctrl* ctrl;                 // control block: tile ranges, tile shapes, the total

@@ -525,11 +525,16 @@ __device__ int heuristic_choice(int b) {
     return KER_MERGE;
 }
 
+constexpr uint32_t EDGE_CHUNK_MAX = 2048;   // in-edges per tile of the edge-centric kernels
+constexpr unsigned long long EDGE_TILES = 4096;
+
 __global__ __launch_bounds__(NBUCKET) void k_select(Ctrl* ctrl, int mode, const uint8_t* __restrict__ learned,
                                                     const uint16_t* __restrict__ chunk_override,
                                                     const uint8_t* __restrict__ group_override, int whole_rows) {
     __shared__ uint32_t s_key[NBUCKET];
+    __shared__ unsigned long long s_in[NKERNEL];   // in-edges per chosen kernel
     const int b = threadIdx.x;
+    if (b < NKERNEL) s_in[b] = 0;
     int ch;
     if (mode == SEL_FORCE_MERGE) ch = KER_MERGE;
     else if (mode == SEL_FORCE_BSEARCH) ch = KER_BSEARCH;
@@ -537,17 +542,33 @@ __global__ __launch_bounds__(NBUCKET) void k_select(Ctrl* ctrl, int mode, const 
     else if (mode == SEL_LEARNED && learned) ch = learned[b] < NKERNEL ? learned[b] : heuristic_choice(b);
     else ch = heuristic_choice(b);
     const int lo = b & 15, li = b >> 4;
-    // tile shape: in-edges per tile and lanes per in-edge
-    // bitmap tiles of vertices with at least 256 in-edges, and of whole-row tails
+    __syncthreads();
+    if (b != BUCKET_NONE && ctrl->bucket_nv[b]) atomicAdd(&s_in[ch], (unsigned long long)ctrl->bucket_in[b]);
+    __syncthreads();
+    // tile shape: in-edges per tile and lanes per in-edge.
+    // Bitmap tiles of vertices with at least 256 in-edges, and of whole-row tails
     // (cut per bitmap window), take the largest chunk: a tile's set-up (entry
     // table, bitmap of the middle list, dependent loads of its descriptors) is
     // then spread over the most in-edges (measured at R-MAT 20: bitmap kernel
-    // 1.24 -> 1.08 ms against 256 in-edges everywhere)
+    // 1.24 -> 1.08 ms against 256 in-edges everywhere).
+    // The edge-centric kernels' tiles of vertices with short lists (fewer than
+    // 64 out-neighbours) grow with the in-edges their launch serves, to about
+    // EDGE_TILES tiles (a few per resident block) between 256 and 2048
+    // in-edges: their per-tile set-up is a chain of dependent loads that the
+    // short lists do not hide (measured: a random geometric graph of 2^23
+    // vertices, merge 6.9 -> 4.4 ms and binary search 5.6 -> 4.4 ms; R-MAT 20,
+    // whose edge-kernel buckets are small, keeps 256; longer lists gained
+    // nothing and lost at R-MAT 24).
     uint32_t chunk = (ch == KER_BITMAP && (whole_rows || li >= 8)) ? (uint32_t)CHUNK_MAX : 256u;
+    if (ch != KER_BITMAP && lo <= 5) {
+        const unsigned long long per = s_in[ch] / EDGE_TILES;
+        chunk = per < 256ull ? 256u : (per > (unsigned long long)EDGE_CHUNK_MAX ? EDGE_CHUNK_MAX : (uint32_t)per);
+    }
     uint32_t group = lo >= 9 ? 64u : (lo >= 3 ? (1u << (lo - 3)) : 1u);
     if (chunk_override && chunk_override[b]) chunk = chunk_override[b];
     if (group_override && group_override[b]) group = group_override[b];
-    if (chunk > (uint32_t)CHUNK_MAX) chunk = CHUNK_MAX;
+    const uint32_t cmax = ch == KER_BITMAP ? (uint32_t)CHUNK_MAX : EDGE_CHUNK_MAX;
+    if (chunk > cmax) chunk = cmax;
     if (chunk < 16u) chunk = 16u;
     if (group > 64u || (group & (group - 1u))) group = 64u;
     if (group < 1u) group = 1u;
@@ -571,8 +592,13 @@ __device__ __forceinline__ uint32_t tile_group(const Ctrl* ctrl, uint32_t b) {
     const uint32_t K = ctrl->chunk[b];
     if (2u * maxin > K) return 1u;
     const uint32_t g = K / maxin;
-    const uint32_t cap = ctrl->choice[b] == KER_BITMAP ? (uint32_t)SEG_MAX_BITMAP : (uint32_t)SEG_MAX;
-    return g > cap ? cap : g;
+    // the edge-centric kernels stage the tile's lists in LDS when they fit:
+    // no more vertices than STAGE_MAX list elements at the bucket's longest
+    const uint32_t lo = b & 15u;
+    const uint32_t stage_cap = lo >= 12 ? 1u : (uint32_t)STAGE_MAX / (2u << lo);
+    const uint32_t cap = ctrl->choice[b] == KER_BITMAP ? (uint32_t)SEG_MAX_BITMAP
+                                                       : (stage_cap < (uint32_t)SEG_MAX ? stage_cap : (uint32_t)SEG_MAX);
+    return g > cap ? cap : (g > 1u ? g : 1u);
 }
 
 __global__ __launch_bounds__(NT) void k_vkeys_slot(const uint8_t* __restrict__ vbucket, int32_t n, const Ctrl* ctrl,
