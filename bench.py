@@ -174,7 +174,9 @@ def batch_bench(args, tc, autotune, sel):
     ms_batch = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
     m = tc.last_stats("cuda:0")["m"]
     print(f"[bench] batched: {ms_batch:.2f} ms/step, union m={m}", file=sys.stderr, flush=True)
-    # the same graphs through 4096 plain calls (one warm pass, then one timed pass)
+    # the same graphs through 4096 plain calls (one warm pass, then one timed pass), with the
+    # default tile shapes (the tuned ones are for the batch's union graph)
+    tc.set_tile_shapes(device="cuda:0")
     sep = np.zeros(nv.size, dtype=np.uint64)
     for rep in range(2):
         torch.cuda.synchronize()

@@ -526,15 +526,13 @@ __device__ int heuristic_choice(int b) {
 }
 
 constexpr uint32_t EDGE_CHUNK_MAX = 2048;   // in-edges per tile of the edge-centric kernels
-constexpr unsigned long long EDGE_TILES = 4096;
+constexpr unsigned long long EDGE_TILES = 512;
 
 __global__ __launch_bounds__(NBUCKET) void k_select(Ctrl* ctrl, int mode, const uint8_t* __restrict__ learned,
                                                     const uint16_t* __restrict__ chunk_override,
                                                     const uint8_t* __restrict__ group_override, int whole_rows) {
     __shared__ uint32_t s_key[NBUCKET];
-    __shared__ unsigned long long s_in[NKERNEL];   // in-edges per chosen kernel
     const int b = threadIdx.x;
-    if (b < NKERNEL) s_in[b] = 0;
     int ch;
     if (mode == SEL_FORCE_MERGE) ch = KER_MERGE;
     else if (mode == SEL_FORCE_BSEARCH) ch = KER_BSEARCH;
@@ -542,9 +540,6 @@ __global__ __launch_bounds__(NBUCKET) void k_select(Ctrl* ctrl, int mode, const 
     else if (mode == SEL_LEARNED && learned) ch = learned[b] < NKERNEL ? learned[b] : heuristic_choice(b);
     else ch = heuristic_choice(b);
     const int lo = b & 15, li = b >> 4;
-    __syncthreads();
-    if (b != BUCKET_NONE && ctrl->bucket_nv[b]) atomicAdd(&s_in[ch], (unsigned long long)ctrl->bucket_in[b]);
-    __syncthreads();
     // tile shape: in-edges per tile and lanes per in-edge.
     // Bitmap tiles of vertices with at least 256 in-edges, and of whole-row tails
     // (cut per bitmap window), take the largest chunk: a tile's set-up (entry
@@ -552,16 +547,17 @@ __global__ __launch_bounds__(NBUCKET) void k_select(Ctrl* ctrl, int mode, const 
     // then spread over the most in-edges (measured at R-MAT 20: bitmap kernel
     // 1.24 -> 1.08 ms against 256 in-edges everywhere).
     // The edge-centric kernels' tiles of vertices with short lists (fewer than
-    // 64 out-neighbours) grow with the in-edges their launch serves, to about
-    // EDGE_TILES tiles (a few per resident block) between 256 and 2048
-    // in-edges: their per-tile set-up is a chain of dependent loads that the
-    // short lists do not hide (measured: a random geometric graph of 2^23
-    // vertices, merge 6.9 -> 4.4 ms and binary search 5.6 -> 4.4 ms; R-MAT 20,
-    // whose edge-kernel buckets are small, keeps 256; longer lists gained
-    // nothing and lost at R-MAT 24).
+    // 64 out-neighbours) grow with the bucket's in-edges, to about EDGE_TILES
+    // tiles per bucket, between 256 and 2048 in-edges: their per-tile set-up is
+    // a chain of dependent loads that the short lists do not hide (measured: a
+    // random geometric graph of 2^23 vertices, merge 6.9 -> 4.4 ms and binary
+    // search 5.6 -> 4.2 ms; R-MAT 20, whose edge-kernel buckets are small,
+    // keeps 256; longer lists gained nothing and lost at R-MAT 24). The shape
+    // depends on the bucket alone, so a bucket timed alone (selector training)
+    // runs as it does among the others.
     uint32_t chunk = (ch == KER_BITMAP && (whole_rows || li >= 8)) ? (uint32_t)CHUNK_MAX : 256u;
     if (ch != KER_BITMAP && lo <= 5) {
-        const unsigned long long per = s_in[ch] / EDGE_TILES;
+        const unsigned long long per = ctrl->bucket_in[b] / EDGE_TILES;
         chunk = per < 256ull ? 256u : (per > (unsigned long long)EDGE_CHUNK_MAX ? EDGE_CHUNK_MAX : (uint32_t)per);
     }
     uint32_t group = lo >= 9 ? 64u : (lo >= 3 ? (1u << (lo - 3)) : 1u);
