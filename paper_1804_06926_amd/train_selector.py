@@ -41,8 +41,10 @@ def training_graphs(quick: bool):
         yield f"chunglu_n{n}_seed{201 + i}", graphgen.chung_lu(n, E, 2.1, seed=201 + i), n
     # mesh-like graphs: without them the network never sees buckets where merge
     # path beats binary search by a wide margin (sizes and seeds distinct from
-    # the held-out random geometric graphs)
-    rsizes = (1 << 15, 1 << 16) if quick else (1 << 17, 1 << 18, 1 << 19)
+    # the held-out random geometric graphs); one large size, since the edge
+    # kernels' tile size, and with it their relative speed, grows with a
+    # bucket's in-edges
+    rsizes = (1 << 15, 1 << 16) if quick else (1 << 17, 1 << 18, 1 << 19, 1 << 21)
     for i, n in enumerate(rsizes):
         for j, deg in enumerate((16.0, 32.0)):
             yield f"rgg_n{n}_d{int(deg)}_seed{301 + 2 * i + j}", graphgen.rgg(n, deg, seed=301 + 2 * i + j), n
