@@ -327,13 +327,16 @@ __global__ __launch_bounds__(NT) void k_unique_write(const uint64_t* __restrict_
 }
 
 // ------------------------------------------------------------------ CSC (in-edges grouped by v)
-// Key of an in-edge e = (u -> v) with work: v in the bits above sh, then e, and
-// (packed form, lbits > 0) the tail length in the low lbits bits; others get
-// v = n - 1 and sort last: the top-ranked vertex has no out-neighbours, so
-// none of its in-edges has work, and ids then need bits_for(n) bits, not
-// bits_for(n + 1) (one pass less when n is a power of two). A length that
-// does not fit the packed field is stored as all ones, and the row end of u is
-// gathered for that entry later. Packing saves that gather for the others.
+// Key of an in-edge e = (u -> v) with a non-empty tail: v in the bits above
+// sh, then e, and (packed form, lbits > 0) the tail length in the low lbits
+// bits; others get v = n - 1 and sort last: the top-ranked vertex has no
+// out-neighbours, so none of its in-edges has work, and ids then need
+// bits_for(n) bits, not bits_for(n + 1) (one pass less when n is a power of
+// two). In-edges of other vertices without out-neighbours keep their group:
+// such a vertex gets no bucket and no tile, so they are never read (testing
+// d+(v) here would cost a random gather per edge). A length that does not fit
+// the packed field is stored as all ones, and the row end of u is gathered for
+// that entry later. Packing saves that gather for the others.
 __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ col, const uint32_t* __restrict__ src,
                                                  const uint32_t* __restrict__ off, Ctrl* ctrl, int32_t n,
                                                  uint64_t* __restrict__ keys, int sh, int lbits,
@@ -354,18 +357,14 @@ __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ co
             v[k] = e < m ? col[e] : 0u;
             u[k] = e < m ? src[e] : 0u;
         }
-        uint32_t end[OR_U], d0[OR_U], d1[OR_U];
+        uint32_t end[OR_U];
 #pragma unroll
-        for (int k = 0; k < OR_U; ++k) {
-            end[k] = off[u[k] + 1];
-            d0[k] = off[v[k]];
-            d1[k] = off[v[k] + 1];
-        }
+        for (int k = 0; k < OR_U; ++k) end[k] = off[u[k] + 1];   // rows ascend with e: near-sequential
 #pragma unroll
         for (int k = 0; k < OR_U; ++k) {
             const uint64_t e = e0 + (uint64_t)k * NT;
             if (e >= m) continue;
-            const bool work = (e + 1 < end[k]) && (d1[k] > d0[k]);
+            const bool work = e + 1 < end[k];   // a non-empty tail
             uint64_t low = e;
             if (lbits > 0) {
                 const uint64_t len = work ? end[k] - (e + 1) : 0u;
