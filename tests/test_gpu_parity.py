@@ -71,6 +71,11 @@ CASES = {
     "dense_12bit": lambda: (graphgen.erdos_renyi(4000, 300_000, seed=13), 4000),
     # ids over 13 bits: a one-bit partition, two buckets counted by several blocks each
     "dense_13bit": lambda: (graphgen.erdos_renyi(6000, 400_000, seed=14), 6000),
+    # short-list buckets of millions of in-edges: edge-centric tiles of up to 2048 in-edges,
+    # vertex groups capped by the LDS stage
+    "rgg_1m": lambda: (graphgen.rgg(1 << 20, avg_degree=16, seed=61), 1 << 20),
+    "uniform_4m": lambda: (np.random.Generator(np.random.PCG64(62)).integers(0, 1 << 18, size=(4 << 20, 2),
+                                                                            dtype=np.int32), 1 << 18),
 }
 
 SELECTS = ["heuristic", "merge", "bsearch", "bitmap"]
