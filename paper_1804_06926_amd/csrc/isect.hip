@@ -20,6 +20,11 @@
 // uw is the tail element's own CSR position, vw the position of w in N+(v)).
 // Tiles are dealt to blocks round-robin (no shared work counter); each block
 // writes its partial count and one reduction adds them in a fixed order.
+// A second pass of the same kernels writes the triangles themselves (listing).
+// The same kernels serve the paper's other formulations (whole neighbour
+// lists; the matrix formulation of Section 3.3): an entry's range is then a
+// whole row that may reach below and above the middle list, and the bitmap
+// kernel cuts it to each window it tests (clipped mode, counts only).
 #include "common.h"
 #include "internal.h"
 #include "isect.h"

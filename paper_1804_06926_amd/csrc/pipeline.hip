@@ -10,13 +10,17 @@
 //   csr       drop repeats and sentinels, emit col/src, row offsets
 //   csc       in-edges (u -> v) with a non-empty tail of row u, grouped by v
 //             (stable radix sort on v), in-offsets from the group boundaries
+//             (the other formulations instead group all in-edges and build the
+//             symmetric adjacency beside the filtered CSR)
 //   bucket    per middle vertex v: (in-edges with work, |N+(v)|) -> bucket
 //   select    choose the intersection strategy and tile shape per bucket
 //   group     order vertices by (strategy, bucket); emit tiles
 //   isect     the three intersection kernels, each over its tile range
 //   finish    map per-vertex / per-edge outputs back to original ids
 // No stage relies on atomics to one address: compaction and grouping go
-// through sorts and scans, so every intermediate array is deterministic.
+// through sorts and scans, so every intermediate array is deterministic. The
+// kernels that write the keys of a sort also take the per-tile digit counts of
+// its first pass (one read of the keys less per sort).
 #include <math.h>
 #include <string.h>
 
