@@ -73,3 +73,29 @@ def test_binding_refuses_host_tensors():
     import paper_1804_06926_amd as tc
     with pytest.raises(TypeError):
         tc.count_triangles(torch.from_numpy(np.zeros((3, 2), np.int32)), 4)
+
+
+def test_formulation_workspace_size_host_checks(lib):
+    """The full-list and matrix forms add the symmetric adjacency (4 (n + 1) + 8 E
+    bytes, each rounded up to 256) to the plain workspace; the filtered and
+    upper-triangle forms need no more than the plain count."""
+    from paper_1804_06926_amd import _lib
+    o = _lib.Options()
+    E, n = 100000, 5000
+    plain, out = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.tc_workspace_size(E, n, ctypes.byref(o), ctypes.byref(plain)) == 0
+    up = lambda x: (x + 255) // 256 * 256
+    for form, extra in ((0, 0), (1, up(4 * (n + 1)) + up(8 * E)), (2, up(4 * (n + 1)) + up(8 * E)), (3, 0)):
+        assert lib.tc_formulation_workspace_size(E, n, ctypes.byref(o), form, ctypes.byref(out)) == 0
+        assert out.value == plain.value + extra, form
+    for bad in (-1, 4):
+        assert lib.tc_formulation_workspace_size(E, n, ctypes.byref(o), bad, ctypes.byref(out)) == 1
+    assert lib.tc_formulation_workspace_size(-1, n, ctypes.byref(o), 1, ctypes.byref(out)) == 1
+    assert lib.tc_formulation_workspace_size((1 << 31) - (1 << 19), n, ctypes.byref(o), 1, ctypes.byref(out)) == 5
+    count = ctypes.c_uint64()
+    assert lib.tc_count_triangles_formulation(None, None, 0, 0, None, 0, None, 1, ctypes.byref(count), None) == 1
+
+
+def test_formulation_binding_names():
+    import paper_1804_06926_amd as tc
+    assert tc.FORMULATIONS == {"filtered": 0, "full": 1, "matrix": 2, "matrix_upper": 3}
