@@ -119,6 +119,11 @@ def main(argv=None):
                  "best_total_ms": float(times.min(axis=1).sum())}
         for k, kn in enumerate(selector.KERNELS):
             entry[f"regret_all_{kn}_ms"] = selector.regret(times, np.full(len(busy), k))
+        # the buckets where either choice misses the fastest strategy
+        entry["misses"] = [{"bucket": int(b), "ms": [round(float(t), 4) for t in times[i]],
+                            "learned": int(learned[i]), "heuristic": int(heur[i])}
+                           for i, b in enumerate(busy)
+                           if learned[i] != np.argmin(times[i]) or heur[i] != np.argmin(times[i])]
         tc.selector_set_params(params)
         t_l, T_l = step_time(tc, d, n, tc.SELECT_LEARNED)
         t_h, T_h = step_time(tc, d, n, tc.SELECT_HEURISTIC)
