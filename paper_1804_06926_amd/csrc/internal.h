@@ -27,8 +27,9 @@ int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t*
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted = false);
 int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted = false);
-// Keys per tile of a sort of cap keys (2048 or 4096; a multiple of 2048).
-uint32_t radix_tile_keys(size_t cap);
+// Keys per tile of a sort of cap keys of key_bytes bytes (2048, 4096 or 8192;
+// a multiple of 2048).
+uint32_t radix_tile_keys(size_t cap, int key_bytes);
 struct RadixDigit {
     int shift;
     uint32_t mask;
@@ -36,7 +37,7 @@ struct RadixDigit {
 // The first digit of a sort over [bit_lo, bit_hi).
 RadixDigit radix_first_digit(int bit_lo, int bit_hi);
 // The first pass's count table inside temp: counts[d * ntiles + tile], 256
-// rows, ntiles = ceil(cap / radix_tile_keys(cap)).
+// rows, ntiles = ceil(cap / radix_tile_keys(cap, key bytes)).
 uint32_t* radix_first_counts(void* temp);
 
 // ---- control block shared by all stages (device memory, zeroed per call)

@@ -961,7 +961,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         uint32_t* ep = (uint32_t*)keysA;       // 2E uint32 fit in E uint64
         uint32_t* ep_alt = (uint32_t*)keysB;
         // the endpoint sort's first digit is counted by k_endpoints as it writes the keys
-        const uint32_t ep_tile = radix_tile_keys((size_t)(2 * E));
+        const uint32_t ep_tile = radix_tile_keys((size_t)(2 * E), 4);
         const uint32_t ep_tiles = (uint32_t)(((uint64_t)(2 * E) + ep_tile - 1) / ep_tile);
         const bool ep_sort = !bucketed || vbits > bw;
         const RadixDigit ep_dg = bucketed ? radix_first_digit(bw, vbits) : radix_first_digit(0, bits_for((uint64_t)n + 1));
@@ -1011,7 +1011,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     // ---- orient
     const int nb = bits_for((uint64_t)n) > 0 ? bits_for((uint64_t)n) : 1;
     const uint64_t sentinel = (2 * nb >= 64) ? ~0ull : ((1ull << (2 * nb)) - 1ull);
-    const uint32_t e_tile = radix_tile_keys((size_t)E);
+    const uint32_t e_tile = radix_tile_keys((size_t)E, 8);
     const uint32_t e_tiles = (uint32_t)(((uint64_t)E + e_tile - 1) / e_tile);
     hipLaunchKernelGGL(k_orient, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, edges, (uint64_t)E, n,
                        rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, e_tile,

@@ -205,14 +205,21 @@ void scan_exclusive_sum_u64(const uint64_t* in, uint64_t* out, size_t len, void*
 // ------------------------------------------------------------------ radix sort
 // A tile is RS_NT threads x ITEMS keys: 16 keys per lane (4096-key tiles, longer
 // runs of equal digits for the scatter, half the count table) for sorts of at
-// least 2^22 keys, 8 (2048-key tiles, twice the blocks) below.
+// least 2^22 keys, 8 (2048-key tiles, twice the blocks) below, and 32 for
+// 64-bit sorts of at least 2^26 keys (8192-key tiles: the scatter's runs of a
+// uniform digit grow from 16 to 32 keys, 256 B; two blocks per CU). Sorts of
+// 32-bit keys keep 4096 there: at two blocks per CU their scatter lost more to
+// latency than it gained in write runs.
 constexpr int RS_NT = 256;
 constexpr int RS_WAVES = RS_NT / WAVE;
-constexpr int RS_ITEMS_SMALL = 8, RS_ITEMS_LARGE = 16;
-constexpr size_t RS_LARGE_CAP = (size_t)1 << 22;
+constexpr int RS_ITEMS_SMALL = 8, RS_ITEMS_LARGE = 16, RS_ITEMS_HUGE = 32;
+constexpr size_t RS_LARGE_CAP = (size_t)1 << 22, RS_HUGE_CAP = (size_t)1 << 26;
 
-uint32_t radix_tile_keys(size_t cap) {
-    return (uint32_t)(RS_NT * (cap >= RS_LARGE_CAP ? RS_ITEMS_LARGE : RS_ITEMS_SMALL));
+uint32_t radix_tile_keys(size_t cap, int key_bytes) {
+    const int items = cap >= RS_HUGE_CAP && key_bytes == 8 ? RS_ITEMS_HUGE
+                      : cap >= RS_LARGE_CAP                ? RS_ITEMS_LARGE
+                                                           : RS_ITEMS_SMALL;
+    return (uint32_t)(RS_NT * items);
 }
 
 __device__ __forceinline__ uint32_t rs_count(const uint32_t* d_count, uint32_t cap) {
@@ -239,10 +246,28 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ k
         const uint32_t i = base + it * WAVE + l;
         dg[it] = i < n ? (uint32_t)(keys[i] >> shift) & dmask : 0u;
     }
-    // counts only (no ranks): one LDS atomic per key into the wave's histogram
+    // counts only (no ranks): one LDS atomic per key into the wave's histogram.
+    // 64-bit keys here hold degree ranks, whose top digit is dominated by the
+    // hubs' in-edges: lanes that share a digit with the wave's first or second
+    // leading lane are added once by that lane, instead of serialising up to 64
+    // atomics on one counter. (32-bit keys are input vertex ids: no such skew by
+    // construction, and the extra ballots would only cost.)
 #pragma unroll
-    for (int it = 0; it < RS_ITEMS; ++it)
-        if (base + it * WAVE + l < n) atomicAdd(&wcnt[w][dg[it]], 1u);
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        uint64_t act = __ballot(base + it * WAVE + l < n);
+        if constexpr (sizeof(KeyT) == 8) {
+#pragma unroll
+            for (int pk = 0; pk < 2; ++pk) {
+                if (!act) break;
+                const int lead = __builtin_ctzll(act);
+                const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)dg[it], lead);
+                const uint64_t m = __ballot(dg[it] == dl) & act;
+                if (l == lead) atomicAdd(&wcnt[w][dl], (uint32_t)__popcll(m));
+                act &= ~m;
+            }
+        }
+        if ((act >> l) & 1u) atomicAdd(&wcnt[w][dg[it]], 1u);
+    }
     __syncthreads();
     const int d = threadIdx.x;
     uint32_t t = 0;
@@ -458,7 +483,11 @@ template <typename KeyT>
 static int radix_sort_any(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                           size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted) {
     if (cap == 0 || bit_hi <= bit_lo) return 0;
-    if (radix_tile_keys(cap) == RS_NT * RS_ITEMS_LARGE)
+    const uint32_t tile = radix_tile_keys(cap, (int)sizeof(KeyT));
+    if (tile == RS_NT * RS_ITEMS_HUGE)
+        return radix_sort<KeyT, RS_ITEMS_HUGE>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
+                                               first_counted);
+    if (tile == RS_NT * RS_ITEMS_LARGE)
         return radix_sort<KeyT, RS_ITEMS_LARGE>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
                                                 first_counted);
     return radix_sort<KeyT, RS_ITEMS_SMALL>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,

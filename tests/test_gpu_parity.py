@@ -273,12 +273,14 @@ def test_csr_export_matches_definition(tc):
                          # either side of the switch from 2048- to 4096-key tiles (2^22 keys)
                          + [((1 << 22) - 1, (0, 20)), ((1 << 22) + 4097, (0, 64))]
                          # more than 8192 tiles of 4096 keys (several digit-row segments), ragged last tile
-                         + [(8 * 1024 * 4096 + 4096 * 5 + 77, (0, 64)), (8 * 1024 * 4096 + 4096 * 5 + 77, (7, 13))])
+                         + [(8 * 1024 * 4096 + 4096 * 5 + 77, (0, 64)), (8 * 1024 * 4096 + 4096 * 5 + 77, (7, 13))]
+                         # 8192-key tiles of 64-bit sorts from 2^26 keys: more than 8192 of them, ragged
+                         + [((1 << 26) + 8192 * 3 + 77, (0, 64))])
 def test_radix_sort_is_stable_and_exact(tc, count, bits):
     import torch
     rng = np.random.default_rng(count + bits[0])
     keys = rng.integers(0, 2**63, count, dtype=np.int64)
-    keys[: count // 3] &= 0xFFFF   # many equal digits
+    keys[: count // 3] &= 0xFFFF   # many equal digits (one dominant digit in the upper passes)
     d = torch.from_numpy(keys.copy()).to("cuda:0")
     tc.radix_sort_u64(d, bits[0], bits[1])
     lo, hi = bits
