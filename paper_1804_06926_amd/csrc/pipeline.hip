@@ -252,7 +252,14 @@ __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, u
 }
 
 // ------------------------------------------------------------------ unique + CSR
+// The sorted pair keys in runs of equal keys: the first of each run is kept,
+// sentinel keys (loops, invalid ids; they sort last) are dropped. Each block
+// owns a chunk of whole 2048-key tiles; in a tile, thread t takes the UQ_ITEMS
+// consecutive keys from t * UQ_ITEMS (four 16-byte loads, in flight together),
+// so a block scans once per tile rather than once per 256 keys.
 constexpr int UQ_MAX_BLOCKS = 1024;
+constexpr int UQ_ITEMS = 8;
+constexpr uint32_t UQ_TILE = NT * UQ_ITEMS;
 
 struct Chunking {
     uint32_t nblk, chunk;
@@ -262,17 +269,46 @@ static Chunking chunking(uint64_t len) {
     uint32_t nblk = (uint32_t)((len + 8191) / 8192);
     if (nblk > (uint32_t)UQ_MAX_BLOCKS) nblk = UQ_MAX_BLOCKS;
     if (nblk < 1) nblk = 1;
-    uint32_t chunk = (uint32_t)((len + nblk - 1) / nblk);
-    chunk = (chunk + NT - 1) / NT * NT;
-    if (chunk == 0) chunk = NT;
+    uint64_t chunk = (len + nblk - 1) / nblk;
+    chunk = (chunk + UQ_TILE - 1) / UQ_TILE * UQ_TILE;
+    if (chunk == 0) chunk = UQ_TILE;
     nblk = (uint32_t)((len + chunk - 1) / chunk);
     if (nblk < 1) nblk = 1;
-    return {nblk, chunk};
+    return {nblk, (uint32_t)chunk};
 }
 
-__device__ __forceinline__ bool keep_key(const uint64_t* keys, uint64_t i, uint64_t sentinel) {
-    const uint64_t k = keys[i];
-    return k != sentinel && (i == 0 || k != keys[i - 1]);
+struct alignas(16) U64x2 {
+    uint64_t a, b;
+};
+
+// Keys i0 .. i0 + UQ_ITEMS - 1 (i0 a multiple of UQ_ITEMS); `fill` past E.
+__device__ __forceinline__ void uq_load(const uint64_t* __restrict__ keys, uint64_t i0, uint64_t E, uint64_t fill,
+                                        uint64_t (&k)[UQ_ITEMS]) {
+    if (i0 + UQ_ITEMS <= E) {
+        const U64x2* p = (const U64x2*)(keys + i0);   // 64-byte aligned
+#pragma unroll
+        for (int q = 0; q < UQ_ITEMS / 2; ++q) {
+            const U64x2 v = p[q];
+            k[2 * q] = v.a;
+            k[2 * q + 1] = v.b;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < UQ_ITEMS; ++j) k[j] = i0 + j < E ? keys[i0 + j] : fill;
+    }
+}
+
+// Bit j: key i0 + j is the first of its run and not the sentinel.
+__device__ __forceinline__ uint32_t uq_keep(const uint64_t* __restrict__ keys, uint64_t i0, uint64_t sentinel,
+                                            const uint64_t (&k)[UQ_ITEMS]) {
+    uint64_t prev = i0 > 0 ? keys[i0 - 1] : ~k[0];
+    uint32_t keep = 0;
+#pragma unroll
+    for (int j = 0; j < UQ_ITEMS; ++j) {
+        keep |= (k[j] != sentinel && k[j] != prev) ? 1u << j : 0u;
+        prev = k[j];
+    }
+    return keep;
 }
 
 __global__ __launch_bounds__(NT) void k_unique_count(const uint64_t* __restrict__ keys, uint64_t E, uint64_t sentinel,
@@ -280,7 +316,13 @@ __global__ __launch_bounds__(NT) void k_unique_count(const uint64_t* __restrict_
     const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
     const uint64_t b1 = b0 + chunk < E ? b0 + chunk : E;
     uint32_t c = 0;
-    for (uint64_t i = b0 + threadIdx.x; i < b1; i += NT) c += keep_key(keys, i, sentinel) ? 1u : 0u;
+    for (uint64_t t0 = b0; t0 < b1; t0 += UQ_TILE) {
+        const uint64_t i0 = t0 + (uint64_t)threadIdx.x * UQ_ITEMS;
+        if (i0 >= b1) continue;
+        uint64_t k[UQ_ITEMS];
+        uq_load(keys, i0, E, sentinel, k);
+        c += (uint32_t)__popc(uq_keep(keys, i0, sentinel, k));
+    }
     c = wave_sum(c);
     __shared__ uint32_t red[NT / WAVE];
     if (lane_id() == 0) red[wave_id()] = c;
@@ -305,26 +347,33 @@ __global__ __launch_bounds__(NT) void k_unique_write(const uint64_t* __restrict_
     const uint64_t lowmask = (1ull << nb) - 1ull;
     uint32_t carry = partial[blockIdx.x];
     if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->m = partial[nblk];
-    for (uint64_t base = b0; base < b1; base += NT) {
-        const uint64_t i = base + threadIdx.x;
-        const bool valid = i < b1 && keys[i] != sentinel;
-        uint64_t key = 0;
+    for (uint64_t t0 = b0; t0 < b1; t0 += UQ_TILE) {   // the same trip count in every thread
+        const uint64_t i0 = t0 + (uint64_t)threadIdx.x * UQ_ITEMS;
+        uint64_t k[UQ_ITEMS];
         uint32_t keep = 0;
-        if (valid) {
-            key = keys[i];
-            keep = (i == 0 || key != keys[i - 1]) ? 1u : 0u;
+        uint64_t next = sentinel;   // the key after this thread's last one
+        if (i0 < b1) {
+            uq_load(keys, i0, E, sentinel, k);
+            keep = uq_keep(keys, i0, sentinel, k);
+            if (i0 + UQ_ITEMS < E) next = keys[i0 + UQ_ITEMS];
         }
         uint32_t total;
-        const uint32_t excl = block_exclusive_scan<NT>(keep, scratch, &total);
-        if (valid) {
-            const uint32_t s = (uint32_t)(key >> nb);
-            const uint32_t pos = carry + excl;
-            if (keep) {
-                col[pos] = (uint32_t)(key & lowmask);
-                src[pos] = s;
+        uint32_t pos = carry + block_exclusive_scan<NT>((uint32_t)__popc(keep), scratch, &total);
+        if (i0 < b1) {
+#pragma unroll
+            for (int j = 0; j < UQ_ITEMS; ++j) {
+                if (k[j] == sentinel) break;   // the sentinels (and the fill past E) come last
+                const uint32_t s = (uint32_t)(k[j] >> nb);
+                const uint32_t kp = (keep >> j) & 1u;
+                if (kp) {
+                    col[pos] = (uint32_t)(k[j] & lowmask);
+                    src[pos] = s;
+                }
+                pos += kp;
+                // the sentinel's row differs from every valid row
+                const uint64_t nx = j + 1 < UQ_ITEMS ? k[j + 1] : next;
+                if ((uint32_t)(nx >> nb) != s) rowend[s] = pos;
             }
-            // the sentinel's row differs from every valid row
-            if (i + 1 == E || (uint32_t)(keys[i + 1] >> nb) != s) rowend[s] = pos + keep;
         }
         carry += total;
     }
