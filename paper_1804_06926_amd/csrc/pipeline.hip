@@ -44,13 +44,16 @@ static unsigned grid_for(size_t n, unsigned cap = 16384) {
 // ------------------------------------------------------------------ degree
 // Input degree = loop-free valid pairs per vertex. Device-wide atomics would
 // serialise on hub vertices, so the 2E endpoints are first partitioned by
-// their high bits (one radix pass for ids of up to 22 bits, two up to 27), and
-// each bucket of 2^bw vertices is then counted in an LDS histogram. Endpoints
+// their high bits (one radix pass for ids of up to 24 bits, two up to 27), and
+// each bucket of 2^bw vertices is then counted in an LDS histogram of up to
+// 2^15 counters (128 KB); a wider bucket is counted in parts, each block
+// reading the whole bucket and counting the ids of its own part. Endpoints
 // of loops and invalid pairs are written as `sentinel`; with sentinel = n - 1
 // each block also records how many it wrote, and they are taken off vertex
 // n - 1 at the end. Wider ids fall back to a full sort of the endpoints
 // (sentinel n, which sorts last) and run boundaries.
-constexpr int DEG_MAX_BW = 14;        // LDS histogram of 2^14 counters (64 KB)
+constexpr int DEG_MAX_BW = 14;        // buckets of 2^14 vertices beyond 24-bit ids (two passes)
+constexpr int DEG_MAX_CW = 15;        // LDS histogram of at most 2^15 counters (128 KB)
 constexpr int DEG_MAX_BUCKET_BITS = 13;   // up to 8192 buckets (ids below 2^27)
 constexpr unsigned DEG_EP_BLOCKS = 1024;
 
@@ -122,41 +125,64 @@ __global__ __launch_bounds__(NT) void k_bucket_starts(const uint32_t* __restrict
     }
 }
 
-// Block (bucket b, split sp) counts its share of bucket b in LDS. One split:
-// plain stores of every count of the bucket; several: atomic adds into the
-// zeroed degree array.
-__global__ __launch_bounds__(NT) void k_bucket_count(const uint32_t* __restrict__ ep,
-                                                     const uint32_t* __restrict__ bstart, int bw, uint32_t splits,
-                                                     int32_t n, uint32_t* __restrict__ deg) {
-    extern __shared__ uint32_t h[];
-    const uint32_t nh = 1u << bw, mask = nh - 1u;
-    const uint32_t b = blockIdx.x / splits, sp = blockIdx.x % splits;
-    for (uint32_t j = threadIdx.x; j < nh; j += NT) h[j] = 0;
+// Block (bucket b, part pt, split sp) counts, in LDS, the ids of part pt (ids
+// whose bits [cw, bw) equal pt, cw = min(bw, CW)) among its share of bucket b.
+// One split: plain stores of every count of the part; several: atomic adds
+// into the zeroed degree array. The 2^15-counter histogram leaves room for one
+// block per CU, so that size runs 1024 threads.
+template <int CW, int NTB>
+__global__ __launch_bounds__(NTB) void k_bucket_count(const uint32_t* __restrict__ ep,
+                                                      const uint32_t* __restrict__ bstart, int bw, uint32_t parts,
+                                                      uint32_t splits, int32_t n, uint32_t* __restrict__ deg) {
+    __shared__ uint32_t h[1u << CW];
+    const int cw = bw < CW ? bw : CW;
+    const uint32_t nh = 1u << cw, hmask = nh - 1u, bmask = (1u << bw) - 1u;
+    const uint32_t b = blockIdx.x / (parts * splits), rem = blockIdx.x % (parts * splits);
+    const uint32_t pt = rem / splits, sp = rem % splits;
+    for (uint32_t j = threadIdx.x; j < nh; j += NTB) h[j] = 0;
     __syncthreads();
     const uint32_t s0 = bstart[b], s1 = bstart[b + 1];
     const uint32_t len = s1 - s0;
     const uint32_t a0 = s0 + (uint32_t)(((uint64_t)len * sp) / splits);
     const uint32_t a1 = s0 + (uint32_t)(((uint64_t)len * (sp + 1)) / splits);
     constexpr int U = 8;
-    for (uint32_t i0 = a0; i0 < a1; i0 += NT * U) {
+    for (uint32_t i0 = a0; i0 < a1; i0 += NTB * U) {
         uint32_t x[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {   // loads in flight together
-            const uint32_t i = i0 + k * NT + threadIdx.x;
+            const uint32_t i = i0 + k * NTB + threadIdx.x;
             x[k] = i < a1 ? ep[i] : 0xFFFFFFFFu;
         }
 #pragma unroll
-        for (int k = 0; k < U; ++k)
-            if (x[k] != 0xFFFFFFFFu) atomicAdd(&h[x[k] & mask], 1u);
+        for (int k = 0; k < U; ++k) {
+            const uint32_t loc = x[k] & bmask;
+            if (x[k] != 0xFFFFFFFFu && (loc >> cw) == pt) atomicAdd(&h[loc & hmask], 1u);
+        }
     }
     __syncthreads();
-    const uint64_t v0 = (uint64_t)b << bw;
-    for (uint32_t j = threadIdx.x; j < nh; j += NT) {
+    const uint64_t v0 = ((uint64_t)b << bw) + ((uint64_t)pt << cw);
+    for (uint32_t j = threadIdx.x; j < nh; j += NTB) {
         const uint64_t v = v0 + j;
         if (v >= (uint64_t)n) break;
         if (splits == 1) deg[v] = h[j];
         else if (h[j]) atomicAdd(&deg[v], h[j]);
     }
+}
+
+static void launch_bucket_count(const uint32_t* ep, const uint32_t* bst, int bw, uint32_t nb, uint32_t splits,
+                                int32_t n, uint32_t* deg, hipStream_t s) {
+    const int cw = bw < DEG_MAX_CW ? bw : DEG_MAX_CW;
+    const uint32_t parts = 1u << (bw - cw);
+    const dim3 grid(nb * parts * splits);
+    if (cw <= 12)
+        hipLaunchKernelGGL((k_bucket_count<12, NT>), grid, dim3(NT), 0, s, ep, bst, bw, parts, splits, n, deg);
+    else if (cw == 13)
+        hipLaunchKernelGGL((k_bucket_count<13, NT>), grid, dim3(NT), 0, s, ep, bst, bw, parts, splits, n, deg);
+    else if (cw == 14)
+        hipLaunchKernelGGL((k_bucket_count<14, NT>), grid, dim3(NT), 0, s, ep, bst, bw, parts, splits, n, deg);
+    else
+        hipLaunchKernelGGL((k_bucket_count<DEG_MAX_CW, 1024>), grid, dim3(1024), 0, s, ep, bst, bw, parts, splits, n,
+                           deg);
 }
 
 // deg[n - 1] -= the sentinel endpoints written by k_endpoints.
@@ -1002,9 +1028,10 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     mark(0);
     // ---- degree: input pairs per vertex, from the sorted endpoints
     fill_u32((uint32_t*)ctrl, 0u, sizeof(Ctrl) / 4, s);
-    // bucket width: one partition pass up to 22-bit ids, two (buckets of 2^14) up to 27 bits
+    // bucket width: one partition pass of at most 8 bits up to 24-bit ids (buckets
+    // of 2^16 vertices counted in two parts at 24 bits), two (buckets of 2^14) up to 27 bits
     const int vbits = bits_for((uint64_t)n);               // vertex ids fit in vbits bits
-    const int bw = vbits <= 20 ? (vbits < 12 ? vbits : 12) : (vbits <= 22 ? vbits - 8 : DEG_MAX_BW);
+    const int bw = vbits <= 20 ? (vbits < 12 ? vbits : 12) : (vbits <= 24 ? vbits - 8 : DEG_MAX_BW);
     const bool bucketed = vbits - bw <= DEG_MAX_BUCKET_BITS;
     {
         uint32_t* ep = (uint32_t*)keysA;       // 2E uint32 fit in E uint64
@@ -1031,8 +1058,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
             uint32_t splits = 1;
             while (nb * splits < 256u && (uint64_t)splits * 65536u < (uint64_t)(2 * E) && splits < 64u) splits *= 2;
             if (splits > 1) fill_u32(deg, 0u, (size_t)n, s);
-            hipLaunchKernelGGL(k_bucket_count, dim3(nb * splits), dim3(NT), sizeof(uint32_t) << bw, s,
-                               a0 ? ep_alt : ep, bst, bw, splits, n, deg);
+            launch_bucket_count(a0 ? ep_alt : ep, bst, bw, nb, splits, n, deg, s);
             hipLaunchKernelGGL(k_drop_sentinels, dim3(1), dim3(NT), 0, s, partial, eg, n, deg);
         } else {
             const int a0 = radix_sort_u32(ep, ep_alt, nullptr, nullptr, nullptr, (size_t)(2 * E), 0,

@@ -65,6 +65,10 @@ CASES = {
     "isolated_tail": lambda: (graphgen.complete(30), 5000),
     # ids over 22 bits: the degree count uses its widest LDS buckets (2^14 vertices)
     "sparse_22bit": lambda: (_dirty(graphgen.chung_lu(4_100_000, 2_000_000, seed=12), 4_100_000, 12), 4_100_000),
+    # ids of 23 bits: one 8-bit partition pass, buckets of 2^15 vertices (128 KB LDS histogram)
+    "sparse_23bit": lambda: (_dirty(graphgen.chung_lu(6_000_000, 1_500_000, seed=17), 6_000_000, 17), 6_000_000),
+    # ids of 24 bits: one 8-bit partition pass, buckets of 2^16 vertices counted in two parts
+    "sparse_24bit": lambda: (_dirty(graphgen.chung_lu(12_000_000, 1_500_000, seed=16), 12_000_000, 16), 12_000_000),
     # ids over 25 bits: two partition passes, buckets of 2^14 vertices
     "sparse_25bit": lambda: (graphgen.chung_lu(20_000_000, 1_500_000, seed=15), 20_000_000),
     # ids over 12 bits: no partition pass, one bucket counted by several blocks
