@@ -282,7 +282,8 @@ __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, u
 // sentinel keys (loops, invalid ids; they sort last) are dropped. Each block
 // owns a chunk of whole 2048-key tiles; in a tile, thread t takes the UQ_ITEMS
 // consecutive keys from t * UQ_ITEMS (four 16-byte loads, in flight together),
-// so a block scans once per tile rather than once per 256 keys.
+// so a block scans once per tile rather than once per 256 keys; the kept keys
+// are compacted in LDS and written out in contiguous runs.
 constexpr int UQ_MAX_BLOCKS = 1024;
 constexpr int UQ_ITEMS = 8;
 constexpr uint32_t UQ_TILE = NT * UQ_ITEMS;
@@ -368,6 +369,7 @@ __global__ __launch_bounds__(NT) void k_unique_write(const uint64_t* __restrict_
                                                      uint32_t nblk, int nb, uint32_t* __restrict__ col,
                                                      uint32_t* __restrict__ src, uint32_t* __restrict__ rowend) {
     __shared__ uint32_t scratch[NT / WAVE];
+    __shared__ uint32_t s_col[UQ_TILE], s_src[UQ_TILE];   // the tile's kept keys, compacted
     const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
     const uint64_t b1 = b0 + chunk < E ? b0 + chunk : E;
     const uint64_t lowmask = (1ull << nb) - 1ull;
@@ -384,7 +386,8 @@ __global__ __launch_bounds__(NT) void k_unique_write(const uint64_t* __restrict_
             if (i0 + UQ_ITEMS < E) next = keys[i0 + UQ_ITEMS];
         }
         uint32_t total;
-        uint32_t pos = carry + block_exclusive_scan<NT>((uint32_t)__popc(keep), scratch, &total);
+        const uint32_t ex = block_exclusive_scan<NT>((uint32_t)__popc(keep), scratch, &total);
+        uint32_t pos = carry + ex, lp = ex;
         if (i0 < b1) {
 #pragma unroll
             for (int j = 0; j < UQ_ITEMS; ++j) {
@@ -392,15 +395,24 @@ __global__ __launch_bounds__(NT) void k_unique_write(const uint64_t* __restrict_
                 const uint32_t s = (uint32_t)(k[j] >> nb);
                 const uint32_t kp = (keep >> j) & 1u;
                 if (kp) {
-                    col[pos] = (uint32_t)(k[j] & lowmask);
-                    src[pos] = s;
+                    s_col[lp] = (uint32_t)(k[j] & lowmask);
+                    s_src[lp] = s;
                 }
                 pos += kp;
+                lp += kp;
                 // the sentinel's row differs from every valid row
                 const uint64_t nx = j + 1 < UQ_ITEMS ? k[j + 1] : next;
                 if ((uint32_t)(nx >> nb) != s) rowend[s] = pos;
             }
         }
+        // the kept keys leave in contiguous runs (a thread's own ones are up to
+        // eight scattered 4-byte stores per lane otherwise)
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < total; q += NT) {
+            col[carry + q] = s_col[q];
+            src[carry + q] = s_src[q];
+        }
+        __syncthreads();
         carry += total;
     }
 }
