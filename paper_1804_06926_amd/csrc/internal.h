@@ -44,6 +44,7 @@ uint32_t* radix_first_counts(void* temp);
 constexpr int NBUCKET = 256;          // degree-pair buckets; 255 = no work
 constexpr int BUCKET_NONE = 255;
 constexpr int NKERNEL = 3;            // 0 merge-path, 1 binary search, 2 LDS bitmap
+constexpr int BM_WINDOW_LOG2 = 17;    // ids covered by one LDS bitmap window
 enum { KER_MERGE = 0, KER_BSEARCH = 1, KER_BITMAP = 2 };
 
 struct Ctrl {
@@ -62,6 +63,7 @@ struct Ctrl {
     uint64_t bucket_in[NBUCKET];      // sum of in-degrees (non-empty tails) per bucket
     uint64_t bucket_out[NBUCKET];     // sum of out-degrees per bucket
     uint64_t bucket_work[NBUCKET];    // sum of d-(v) * d+(v) per bucket
+    uint64_t bucket_win[NBUCKET];     // sum of the bitmap windows spanned by the middle lists per bucket
     uint8_t choice[NBUCKET];          // kernel per bucket
     uint8_t slot[NBUCKET];            // bucket -> position in (kernel, bucket) order
     uint16_t chunk[NBUCKET];          // in-edges per tile, per bucket

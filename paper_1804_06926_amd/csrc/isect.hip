@@ -34,6 +34,7 @@ namespace tcx {
 constexpr int IS_NT = 256;
 constexpr int BM_WORDS = 4096;            // 131072-bit window (16 KiB)
 constexpr uint32_t BM_BITS = BM_WORDS * 32u;
+static_assert(BM_BITS == (1u << BM_WINDOW_LOG2), "the selector's window feature counts these windows");
 constexpr int UNROLL = 8;                 // bitmap kernel: tail loads in flight per lane
 constexpr uint32_t WT_MAX = 1024;         // bitmap kernel: 64-item windows per chunk of the item range
 constexpr uint32_t LONG_TAIL = 64;        // bitmap kernel: tails of at least one window are walked directly

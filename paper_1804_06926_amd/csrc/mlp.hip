@@ -180,11 +180,14 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ master, co
 }
 
 // Bucket features (6 floats): the bucket's two degree classes and the log
-// sizes of its work, from the statistics gathered by the pipeline.
+// sizes of its work, from the statistics gathered by the pipeline: the
+// LDS-bitmap windows its middle lists span (the bitmap strategy's set-up
+// count, which grows with the rank range a list covers and so with the
+// graph's size), in-edges, out-neighbours, and in-edges x out-degree.
 __device__ void bucket_features(const Ctrl* ctrl, int b, float* f) {
     f[0] = (float)(b >> 4) / 14.f;
     f[1] = (float)(b & 15) / 15.f;
-    f[2] = log2f(1.f + (float)ctrl->bucket_nv[b]) / 24.f;
+    f[2] = log2f(1.f + (float)ctrl->bucket_win[b]) / 32.f;
     f[3] = log2f(1.f + (float)ctrl->bucket_in[b]) / 32.f;
     f[4] = log2f(1.f + (float)ctrl->bucket_out[b]) / 32.f;
     f[5] = log2f(1.f + (float)ctrl->bucket_work[b]) / 48.f;

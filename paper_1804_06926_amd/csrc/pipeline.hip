@@ -571,11 +571,18 @@ __device__ __forceinline__ uint32_t bucket_of(uint32_t din, uint32_t dout) {
     return 16u * li + lo;
 }
 
-__global__ __launch_bounds__(NT) void k_vbucket(const uint32_t* __restrict__ off, const uint32_t* __restrict__ inoff,
-                                                int32_t n, uint8_t* __restrict__ vbucket, Ctrl* ctrl) {
+__global__ __launch_bounds__(NT) void k_vbucket(const uint32_t* __restrict__ off, const uint32_t* __restrict__ col,
+                                                const uint32_t* __restrict__ inoff, int32_t n,
+                                                uint8_t* __restrict__ vbucket, Ctrl* ctrl) {
     __shared__ uint32_t s_nv[NBUCKET];
-    __shared__ unsigned long long s_in[NBUCKET], s_out[NBUCKET], s_work[NBUCKET];
-    for (int b = threadIdx.x; b < NBUCKET; b += NT) { s_nv[b] = 0; s_in[b] = 0; s_out[b] = 0; s_work[b] = 0; }
+    __shared__ unsigned long long s_in[NBUCKET], s_out[NBUCKET], s_work[NBUCKET], s_win[NBUCKET];
+    for (int b = threadIdx.x; b < NBUCKET; b += NT) {
+        s_nv[b] = 0;
+        s_in[b] = 0;
+        s_out[b] = 0;
+        s_work[b] = 0;
+        s_win[b] = 0;
+    }
     __syncthreads();
     for (int64_t v = (int64_t)blockIdx.x * NT + threadIdx.x; v < n; v += (int64_t)gridDim.x * NT) {
         const uint32_t din = inoff[v + 1] - inoff[v], dout = off[v + 1] - off[v];
@@ -586,6 +593,10 @@ __global__ __launch_bounds__(NT) void k_vbucket(const uint32_t* __restrict__ off
             atomicAdd(&s_in[b], (unsigned long long)din);
             atomicAdd(&s_out[b], (unsigned long long)dout);
             atomicAdd(&s_work[b], (unsigned long long)din * dout);
+            // windows the bitmap strategy walks for this middle list (first one
+            // aligned down to a word)
+            const uint32_t lo = col[off[v]], hi = col[off[v + 1] - 1];
+            atomicAdd(&s_win[b], (unsigned long long)(((hi - (lo & ~31u)) >> BM_WINDOW_LOG2) + 1u));
         }
     }
     __syncthreads();
@@ -595,6 +606,7 @@ __global__ __launch_bounds__(NT) void k_vbucket(const uint32_t* __restrict__ off
             atomicAdd((unsigned long long*)&ctrl->bucket_in[b], s_in[b]);
             atomicAdd((unsigned long long*)&ctrl->bucket_out[b], s_out[b]);
             atomicAdd((unsigned long long*)&ctrl->bucket_work[b], s_work[b]);
+            atomicAdd((unsigned long long*)&ctrl->bucket_win[b], s_win[b]);
         }
     }
 }
@@ -1169,7 +1181,9 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     }
     mark(6);
     // ---- buckets + selection
-    hipLaunchKernelGGL(k_vbucket, dim3(grid_for((size_t)n, 2048)), dim3(NT), 0, s, moff, inoff, n, vbucket, ctrl);
+    const uint32_t* mcol = (r.formulation == FORM_FULL || r.formulation == FORM_MATRIX) ? sym_col(r, L) : col;
+    hipLaunchKernelGGL(k_vbucket, dim3(grid_for((size_t)n, 2048)), dim3(NT), 0, s, moff, mcol, inoff, n, vbucket,
+                       ctrl);
     const bool learned = r.select == SEL_LEARNED && r.mlp && r.learned;
     if (learned) mlp_select((const MlpCompute*)r.mlp, ctrl, r.learned, s);
     else bucket_features_launch(ctrl, s);

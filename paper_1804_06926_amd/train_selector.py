@@ -10,6 +10,7 @@ per-graph regret of the learned choice, of the heuristic and of every single
 strategy, and the end-to-end step time of the learned and heuristic modes.
 
     python -m paper_1804_06926_amd.train_selector --out selector_weights.json --report report.json
+    python -m paper_1804_06926_amd.train_selector --evaluate selector_weights.json --report report.json
 """
 from __future__ import annotations
 
@@ -73,13 +74,17 @@ def step_time(tc, d, n, select, steps=5):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out", help="where the trained weights go (required unless --evaluate)")
     ap.add_argument("--report", required=True)
     ap.add_argument("--repeats", type=int, default=5)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--quick", action="store_true", help="small graphs (for a smoke run)")
+    ap.add_argument("--evaluate", metavar="WEIGHTS",
+                    help="skip training: evaluate these saved weights on the held-out graphs")
     args = ap.parse_args(argv)
+    if not args.evaluate and not args.out:
+        ap.error("--out is required when training")
 
     import torch
 
@@ -87,6 +92,20 @@ def main(argv=None):
     from paper_1804_06926_amd import selector
 
     t0 = time.time()
+    if args.evaluate:
+        params = selector.load(args.evaluate)
+        report = {"train": {"weights": args.evaluate}}
+    else:
+        params, report = _train(args, tc, selector)
+    _evaluate(args, tc, selector, params, report)
+    report["wall_s"] = time.time() - t0
+    with open(args.report, "w") as f:
+        json.dump(report, f, indent=1)
+    log(f"[selector] report written to {args.report}")
+    return 0
+
+
+def _train(args, tc, selector):
     data = selector.collect(training_graphs(args.quick), repeats=args.repeats, log=log)
     y = selector.make_labels(data["times"], data["bucket"])
     w = selector.sample_weights(data["times"])
@@ -102,7 +121,12 @@ def main(argv=None):
     selector.save(args.out, params, {"trained_on": data["names"], "steps": args.steps, "lr": args.lr,
                                      "repeats": args.repeats})
     log(f"[selector] saved {args.out}; train report {report['train']}")
+    return params, report
 
+
+def _evaluate(args, tc, selector, params, report):
+    import torch
+    tc.selector_set_params(params)   # predict() and the learned mode use the library's parameters
     report["heldout"] = []
     for name, edges, n in heldout_graphs(args.quick):
         log(f"[selector] held-out {name}")
@@ -124,7 +148,6 @@ def main(argv=None):
                             "learned": int(learned[i]), "heuristic": int(heur[i])}
                            for i, b in enumerate(busy)
                            if learned[i] != np.argmin(times[i]) or heur[i] != np.argmin(times[i])]
-        tc.selector_set_params(params)
         t_l, T_l = step_time(tc, d, n, tc.SELECT_LEARNED)
         t_h, T_h = step_time(tc, d, n, tc.SELECT_HEURISTIC)
         assert T_l == T_h, (T_l, T_h)
@@ -132,11 +155,6 @@ def main(argv=None):
         report["heldout"].append(entry)
         log(f"[selector] {entry}")
         del d
-    report["wall_s"] = time.time() - t0
-    with open(args.report, "w") as f:
-        json.dump(report, f, indent=1)
-    log(f"[selector] report written to {args.report}")
-    return 0
 
 
 if __name__ == "__main__":

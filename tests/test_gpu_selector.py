@@ -163,3 +163,30 @@ def test_trained_selector_gains_over_heuristic(tc):
         print(f"{name}: regret learned {r_l:.3f} ms, heuristic {r_h:.3f} ms, best total {best:.3f} ms")
         assert r_l <= r_h + 0.03 * best, (name, r_l, r_h, best)
         assert tc.count_triangles(d, n, select=tc.SELECT_LEARNED) == tc.count_triangles(d, n)
+
+
+def test_window_feature_matches_host_count(tc):
+    """Feature 2 is log2(1 + the LDS-bitmap windows the bucket's middle lists span) / 32,
+    recomputed here from the exported degree-ordered CSR."""
+    import torch
+    n = 1 << 19   # ranks span four 2^17-id windows
+    e = graphgen.rmat(19, 16, seed=9)
+    d = torch.from_numpy(e).cuda()
+    tc.count_triangles(d, n, select=tc.SELECT_HEURISTIC)
+    feat = tc.bucket_features()
+    _, off, col = tc.build_csr(d, n)
+    off = off.cpu().numpy().astype(np.int64)
+    col = col.cpu().numpy().astype(np.int64)
+    dplus = np.diff(off)
+    src = np.repeat(np.arange(n), dplus)
+    tail = off[src + 1] - np.arange(col.size) - 1
+    din = np.bincount(col[tail > 0], minlength=n)
+    v = np.nonzero((din > 0) & (dplus > 0))[0]
+    b = 16 * np.minimum(14, np.floor(np.log2(din[v]))).astype(np.int64) + \
+        np.minimum(15, np.floor(np.log2(dplus[v]))).astype(np.int64)
+    lo, hi = col[off[v]], col[off[v + 1] - 1]
+    win = ((hi - (lo & ~31)) >> 17) + 1
+    assert win.max() > 1
+    tot = np.bincount(b, weights=win, minlength=256)
+    busy = np.nonzero(np.bincount(b, minlength=256))[0]
+    np.testing.assert_allclose(feat[busy, 2], np.log2(1.0 + tot[busy]).astype(np.float32) / 32.0, rtol=1e-5)
