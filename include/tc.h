@@ -301,8 +301,10 @@ tc_status tc_last_stats(const tc_ctx* ctx, tc_stats* out);
  * W1 [32][6], b1 [32], W2 [32][32], b2 [32], W3 [3][32], b3 [3]; logit 0 is
  * merge path, 1 binary search, 2 LDS bitmap.
  * Features of bucket b (float32): floor(log2 d_in)/14, floor(log2 d_out)/15,
- * log2(1+vertices)/24, log2(1+in-edges)/32, log2(1+out-edges)/32,
- * log2(1+sum d_in*d_out)/48.
+ * log2(1+windows)/32, log2(1+in-edges)/32, log2(1+out-edges)/32,
+ * log2(1+sum d_in*d_out)/48, where windows = sum over the bucket's vertices v
+ * of the 2^17-id LDS-bitmap windows spanned by the middle list of v (from its
+ * first element rounded down to a multiple of 32 to its last).
  */
 #define TC_SELECTOR_NUM_PARAMS 1379
 #define TC_SELECTOR_NUM_FEATURES 6
