@@ -329,22 +329,27 @@ __global__ __launch_bounds__(RS_NT) void k_radix_rowfix(uint32_t* __restrict__ h
     for (uint32_t i = s0 + threadIdx.x; i < s1; i += RS_NT) row[i] += carry;
 }
 
-template <typename KeyT, bool HAS_VAL, int RS_ITEMS>
-__global__ __launch_bounds__(RS_NT) void k_radix_scatter(const KeyT* __restrict__ kin,
+// NT_ threads of RS_ITEMS keys each: 8192-key tiles run 512 threads of 16 keys
+// (half the registers per lane of 256 x 32, twice the waves per CU); threads
+// 0..255 own the digits in the per-digit scans.
+template <typename KeyT, bool HAS_VAL, int RS_ITEMS, int NT_ = RS_NT>
+__global__ __launch_bounds__(NT_) void k_radix_scatter(const KeyT* __restrict__ kin,
                                                          const uint32_t* __restrict__ vin,
                                                          KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          const uint32_t* d_count, uint32_t cap, int shift,
                                                          uint32_t dmask,
                                                          const uint32_t* __restrict__ hist_scan, uint32_t ntiles,
                                                          const uint32_t* __restrict__ digit_tot) {
-    constexpr int RS_TILE = RS_NT * RS_ITEMS, RS_WAVE_SPAN = WAVE * RS_ITEMS;
-    __shared__ uint32_t wcnt[RS_WAVES][256];
+    constexpr int NW = NT_ / WAVE;
+    constexpr int RS_TILE = NT_ * RS_ITEMS, RS_WAVE_SPAN = WAVE * RS_ITEMS;
+    static_assert(NT_ >= 256, "a thread per digit");
+    __shared__ uint32_t wcnt[NW][256];
     __shared__ uint32_t lstart[256];
     __shared__ uint32_t gbase[256];
-    __shared__ uint32_t scratch[RS_WAVES];
+    __shared__ uint32_t scratch[NW];
     __shared__ KeyT skey[RS_TILE];
     __shared__ uint32_t sval[HAS_VAL ? RS_TILE : 1];
-    for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < NW * 256; i += NT_) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     const uint32_t n = rs_count(d_count, cap);
     const int w = wave_id(), l = lane_id();
@@ -376,19 +381,22 @@ __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const KeyT* __restrict_
     }
     __syncthreads();
     {
-        const int d = threadIdx.x;
+        const bool own = threadIdx.x < 256;   // threads past the digits add zeros to the scans
+        const int d = own ? (int)threadIdx.x : 0;
         uint32_t run = 0;
+        if (own) {
 #pragma unroll
-        for (int q = 0; q < RS_WAVES; ++q) {
-            const uint32_t c = wcnt[q][d];
-            wcnt[q][d] = run;
-            run += c;
+            for (int q = 0; q < NW; ++q) {
+                const uint32_t c = wcnt[q][d];
+                wcnt[q][d] = run;
+                run += c;
+            }
         }
-        const uint32_t excl = block_exclusive_scan<RS_NT>(run, scratch);
-        lstart[d] = excl;
+        const uint32_t excl = block_exclusive_scan<NT_>(run, scratch);
+        if (own) lstart[d] = excl;
         // digit base = keys with a smaller digit; plus this tile's offset in its digit row
-        const uint32_t dbase = block_exclusive_scan<RS_NT>(digit_tot[d], scratch);
-        gbase[d] = dbase + hist_scan[(size_t)d * ntiles + blockIdx.x];
+        const uint32_t dbase = block_exclusive_scan<NT_>(own ? digit_tot[d] : 0u, scratch);
+        if (own) gbase[d] = dbase + hist_scan[(size_t)d * ntiles + blockIdx.x];
     }
     __syncthreads();
 #pragma unroll
@@ -403,7 +411,7 @@ __global__ __launch_bounds__(RS_NT) void k_radix_scatter(const KeyT* __restrict_
     }
     __syncthreads();
     const uint32_t tile_n = n > tile0 ? (n - tile0 < (uint32_t)RS_TILE ? n - tile0 : (uint32_t)RS_TILE) : 0u;
-    for (uint32_t j = threadIdx.x; j < tile_n; j += RS_NT) {
+    for (uint32_t j = threadIdx.x; j < tile_n; j += NT_) {
         const KeyT key = skey[j];
         const uint32_t d = (uint32_t)(key >> shift) & dmask;
         const uint32_t pos = gbase[d] + (j - lstart[d]);
@@ -466,7 +474,16 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
         hipLaunchKernelGGL(k_radix_rowscan, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, digit_tot, seg_tot);
         if (nseg > 1)
             hipLaunchKernelGGL(k_radix_rowfix, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, seg_tot, digit_tot);
-        if (vals) {
+        if (RS_ITEMS == RS_ITEMS_HUGE) {   // 8192-key tiles: 512 threads of 16 keys
+            if (vals)
+                hipLaunchKernelGGL((k_radix_scatter<KeyT, true, RS_ITEMS / 2, 2 * RS_NT>), dim3(ntiles),
+                                   dim3(2 * RS_NT), 0, s, kin, vin, kout, vout, d_count, (uint32_t)cap, shift, dmask,
+                                   hist, ntiles, digit_tot);
+            else
+                hipLaunchKernelGGL((k_radix_scatter<KeyT, false, RS_ITEMS / 2, 2 * RS_NT>), dim3(ntiles),
+                                   dim3(2 * RS_NT), 0, s, kin, nullptr, kout, nullptr, d_count, (uint32_t)cap, shift,
+                                   dmask, hist, ntiles, digit_tot);
+        } else if (vals) {
             hipLaunchKernelGGL((k_radix_scatter<KeyT, true, RS_ITEMS>), dim3(ntiles), dim3(RS_NT), 0, s, kin, vin, kout, vout,
                                d_count, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot);
         } else {
