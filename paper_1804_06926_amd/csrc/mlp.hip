@@ -193,20 +193,60 @@ __device__ void bucket_features(const Ctrl* ctrl, int b, float* f) {
     f[5] = log2f(1.f + (float)ctrl->bucket_work[b]) / 48.f;
 }
 
-// One thread per bucket: features, forward, argmax (ties to the lower index).
-__global__ __launch_bounds__(NBUCKET) void k_mlp_select(const MlpCompute* __restrict__ cw, Ctrl* ctrl,
-                                                        uint8_t* __restrict__ choice) {
+// SEL_G lanes per bucket: lane j of a group computes hidden units
+// SEL_U * j .. SEL_U * j + SEL_U - 1 of each layer, and output j (j < 3), each
+// as the same ordered dot product plus bias as net_forward, so the logits are
+// bit-identical to it; the other lanes' units arrive by shuffles. Argmax ties
+// go to the lower index.
+constexpr int SEL_G = 8, SEL_U = MLP_H / SEL_G, SEL_NT = 256;
+static_assert(MLP_H % SEL_G == 0 && MLP_OUT <= SEL_G && WAVE % SEL_G == 0, "selection lane layout");
+__global__ __launch_bounds__(SEL_NT) void k_mlp_select(const MlpCompute* __restrict__ cw, Ctrl* ctrl,
+                                                       uint8_t* __restrict__ choice) {
     __shared__ MlpShared S;
     load_net(cw, S);
-    const int b = threadIdx.x;
-    float x[MLP_IN], h1[MLP_H], h2[MLP_H], z[MLP_OUT];
+    const int t = blockIdx.x * SEL_NT + threadIdx.x;
+    const int b = t / SEL_G, j = t % SEL_G;   // NBUCKET * SEL_G threads in all
+    const int lane0 = lane_id() - j;            // the group's first lane
+    float x[MLP_IN];
     bucket_features(ctrl, b, x);
-    for (int i = 0; i < MLP_IN; ++i) ctrl->features[b][i] = x[i];
-    net_forward(S, x, h1, h2, z);
-    int best = 0;
-    for (int o = 1; o < MLP_OUT; ++o)
-        if (z[o] > z[best]) best = o;
-    choice[b] = (uint8_t)best;
+    if (j == 0)
+        for (int i = 0; i < MLP_IN; ++i) ctrl->features[b][i] = x[i];
+    float h1[SEL_U], h2[SEL_U];
+#pragma unroll
+    for (int u = 0; u < SEL_U; ++u) {
+        const int o = SEL_U * j + u;
+        float acc = 0.f;
+        for (int i = 0; i < MLP_IN; ++i) acc = fmaf(S.W1[o * MLP_IN + i], x[i], acc);
+        acc += S.b1[o];
+        h1[u] = acc > 0.f ? acc : 0.f;
+    }
+    float hin[MLP_H];   // all of layer 1, in order
+#pragma unroll
+    for (int i = 0; i < MLP_H; ++i) hin[i] = __shfl(h1[i % SEL_U], lane0 + i / SEL_U, WAVE);
+#pragma unroll
+    for (int u = 0; u < SEL_U; ++u) {
+        const int o = SEL_U * j + u;
+        float acc = 0.f;
+        for (int i = 0; i < MLP_H; ++i) acc = fmaf(S.W2[o * MLP_H + i], hin[i], acc);
+        acc += S.b2[o];
+        h2[u] = acc > 0.f ? acc : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < MLP_H; ++i) hin[i] = __shfl(h2[i % SEL_U], lane0 + i / SEL_U, WAVE);
+    float z = 0.f;
+    if (j < MLP_OUT) {
+        for (int i = 0; i < MLP_H; ++i) z = fmaf(S.W3[j * MLP_H + i], hin[i], z);
+        z += S.b3[j];
+    }
+    float zz[MLP_OUT];
+#pragma unroll
+    for (int o = 0; o < MLP_OUT; ++o) zz[o] = __shfl(z, lane0 + o, WAVE);
+    if (j == 0) {
+        int best = 0;
+        for (int o = 1; o < MLP_OUT; ++o)
+            if (zz[o] > zz[best]) best = o;
+        choice[b] = (uint8_t)best;
+    }
 }
 
 // Features only (heuristic and forced modes), for training data.
@@ -236,7 +276,7 @@ void mlp_adam(float* master, const float* grad, float* m, float* v, float lr, in
                        beta2, eps, c1, c2);
 }
 void mlp_select(const MlpCompute* cw, Ctrl* ctrl, uint8_t* choice, hipStream_t s) {
-    hipLaunchKernelGGL(k_mlp_select, dim3(1), dim3(NBUCKET), 0, s, cw, ctrl, choice);
+    hipLaunchKernelGGL(k_mlp_select, dim3(NBUCKET * SEL_G / SEL_NT), dim3(SEL_NT), 0, s, cw, ctrl, choice);
 }
 void bucket_features_launch(Ctrl* ctrl, hipStream_t s) {
     hipLaunchKernelGGL(k_bucket_features, dim3(1), dim3(NBUCKET), 0, s, ctrl);

@@ -9,7 +9,7 @@ network that picks the strategy:
    every bucket's tiles alone (``profile_buckets``) and reports the bucket
    features.
 2. ``make_labels``: the fastest strategy per bucket by median time; within
-   ``tie`` of the heuristic's time the heuristic's choice is kept.
+   ``tie`` (relative) or ``abs_tie`` (ms) of it the heuristic's choice is kept.
 3. ``train``: full-batch Adam on the GPU with the library's own forward and
    backward kernels (``selector_train_step``); samples are weighted by how
    much time the choice can save.
@@ -83,10 +83,15 @@ def collect(graphs, repeats: int = 5, device: str = "cuda:0", log=None):
             "names": names}
 
 
-def make_labels(times: np.ndarray, buckets: np.ndarray, tie: float = 0.02) -> np.ndarray:
+def make_labels(times: np.ndarray, buckets: np.ndarray, tie: float = 0.02, abs_tie: float = 0.005) -> np.ndarray:
+    """Fastest strategy per bucket; the heuristic's when its time is within `tie`
+    (relative) or `abs_tie` ms of the best. A bucket timed alone costs at least one
+    launch's fixed time (~13 us), and differences of a few microseconds there do not
+    carry over to the bucket's share of the combined launch of its strategy."""
     best = np.argmin(times, axis=1)
     heur = np.array([heuristic_choice(int(b)) for b in buckets])
-    keep = times[np.arange(len(best)), heur] <= (1.0 + tie) * times[np.arange(len(best)), best]
+    t_best = times[np.arange(len(best)), best]
+    keep = times[np.arange(len(best)), heur] <= np.maximum((1.0 + tie) * t_best, t_best + abs_tie)
     return np.where(keep, heur, best).astype(np.int32)
 
 

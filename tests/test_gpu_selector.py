@@ -190,3 +190,24 @@ def test_window_feature_matches_host_count(tc):
     tot = np.bincount(b, weights=win, minlength=256)
     busy = np.nonzero(np.bincount(b, minlength=256))[0]
     np.testing.assert_allclose(feat[busy, 2], np.log2(1.0 + tot[busy]).astype(np.float32) / 32.0, rtol=1e-5)
+
+
+def test_learned_choices_match_forward_argmax(tc):
+    """The selection kernel (eight lanes per bucket) picks, for every bucket, the argmax of
+    the logits the plain forward kernel gives for the same features (same arithmetic order)."""
+    import torch
+    from paper_1804_06926_amd import selector
+    for seed in (5, 11):
+        tc.selector_set_params(mlp.init_params(seed))
+        n = 1 << 16
+        e = graphgen.rmat(16, 16, seed=seed)
+        tc.count_triangles(torch.from_numpy(e).cuda(), n, select=tc.SELECT_LEARNED)
+        st = tc.last_stats()
+        feat = tc.bucket_features()
+        want = selector.predict(feat[:255])
+        np.testing.assert_array_equal(st["bucket_kernel"][:255], want)
+    # the shipped network as well
+    assert selector.load_default()
+    tc.count_triangles(torch.from_numpy(graphgen.rmat(16, 16, seed=4)).cuda(), 1 << 16, select=tc.SELECT_LEARNED)
+    st = tc.last_stats()
+    np.testing.assert_array_equal(st["bucket_kernel"][:255], selector.predict(tc.bucket_features()[:255]))

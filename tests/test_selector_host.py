@@ -23,6 +23,16 @@ def test_labels_keep_heuristic_within_tie():
     assert y.tolist() == [0, 1, 2]
 
 
+def test_labels_keep_heuristic_within_absolute_tie():
+    # small buckets, timed alone: 4 us apart is a tie (5 us tolerance), 6 us is not
+    times = np.array([[0.019, 0.015, 0.12],
+                      [0.025, 0.019, 0.13]])
+    buckets = np.array([0, 0])   # the heuristic's choice: merge path
+    y = selector.make_labels(times, buckets)
+    assert y.tolist() == [0, 1]
+    assert selector.make_labels(times, buckets, abs_tie=0.0).tolist() == [1, 1]
+
+
 def test_sample_weights_and_regret():
     times = np.array([[1.0, 1.0, 1.0], [1.0, 5.0, 9.0]])
     w = selector.sample_weights(times)
