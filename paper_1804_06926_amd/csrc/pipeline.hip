@@ -237,6 +237,10 @@ __global__ __launch_bounds__(NT) void k_rank(const uint64_t* __restrict__ sorted
 // parallelism.
 constexpr int OR_U = 8;
 // sort tiles (radix_tile_keys) are whole multiples of one round, OR_U * NT keys
+// U pairs per thread per step: 16 where the tile is a multiple of 16 * NT
+// (4096- and 8192-key tiles; 0.21 -> 0.20 ms at R-MAT 20, no change at larger
+// sizes, where the gathers' line traffic bounds the kernel), else OR_U.
+template <int U>
 __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, uint64_t E, int32_t n,
                                                const uint32_t* __restrict__ rank, int nb, uint64_t sentinel,
                                                uint64_t* __restrict__ keys, uint32_t* __restrict__ counts,
@@ -246,24 +250,24 @@ __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, u
     tc.clear();
     __syncthreads();
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-      for (uint32_t r = 0; r < tile_keys; r += OR_U * NT) {
+      for (uint32_t r = 0; r < tile_keys; r += U * NT) {
         const uint64_t i0 = (uint64_t)tile * tile_keys + r + threadIdx.x;
-        int2 ed[OR_U];
+        int2 ed[U];
 #pragma unroll
-        for (int k = 0; k < OR_U; ++k) {
+        for (int k = 0; k < U; ++k) {
             const uint64_t i = i0 + (uint64_t)k * NT;
             ed[k] = i < E ? edges[i] : make_int2(-1, -1);
         }
-        uint32_t ra[OR_U], rb[OR_U];
-        bool ok[OR_U];
+        uint32_t ra[U], rb[U];
+        bool ok[U];
 #pragma unroll
-        for (int k = 0; k < OR_U; ++k) {
+        for (int k = 0; k < U; ++k) {
             ok[k] = ed[k].x >= 0 && ed[k].x < n && ed[k].y >= 0 && ed[k].y < n && ed[k].x != ed[k].y;
             ra[k] = rank[ok[k] ? ed[k].x : 0];
             rb[k] = rank[ok[k] ? ed[k].y : 0];
         }
 #pragma unroll
-        for (int k = 0; k < OR_U; ++k) {
+        for (int k = 0; k < U; ++k) {
             const uint64_t i = i0 + (uint64_t)k * NT;
             if (i < E) {
                 const uint32_t lo = ra[k] < rb[k] ? ra[k] : rb[k], hi = ra[k] < rb[k] ? rb[k] : ra[k];
@@ -1112,9 +1116,14 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     const uint64_t sentinel = (2 * nb >= 64) ? ~0ull : ((1ull << (2 * nb)) - 1ull);
     const uint32_t e_tile = radix_tile_keys((size_t)E, 8);
     const uint32_t e_tiles = (uint32_t)(((uint64_t)E + e_tile - 1) / e_tile);
-    hipLaunchKernelGGL(k_orient, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, edges, (uint64_t)E, n,
-                       rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, e_tile,
-                       radix_first_digit(0, 2 * nb));
+    if (e_tile % (16 * NT) == 0)
+        hipLaunchKernelGGL(k_orient<16>, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, edges,
+                           (uint64_t)E, n, rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, e_tile,
+                           radix_first_digit(0, 2 * nb));
+    else
+        hipLaunchKernelGGL(k_orient<OR_U>, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, edges,
+                           (uint64_t)E, n, rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, e_tile,
+                           radix_first_digit(0, 2 * nb));
     mark(3);
     // ---- sort oriented pairs (first digit counted by k_orient)
     const int alt =
