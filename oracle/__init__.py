@@ -52,6 +52,8 @@ def _load():
     vp = ctypes.c_void_p
     lib.oracle_graph_build.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(vp)]
     lib.oracle_graph_build.restype = ctypes.c_int
+    lib.oracle_graph_build_timed.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(vp), vp]
+    lib.oracle_graph_build_timed.restype = ctypes.c_int
     lib.oracle_graph_free.argtypes = [vp]
     lib.oracle_graph_num_edges.argtypes = [vp]
     lib.oracle_graph_num_edges.restype = ctypes.c_int64
@@ -59,6 +61,9 @@ def _load():
     lib.oracle_graph_degrees.argtypes = [vp, vp]
     lib.oracle_count_forward.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
     lib.oracle_count_forward.restype = ctypes.c_uint64
+    lib.oracle_count_forward_timed.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp]
+    lib.oracle_count_forward_timed.restype = ctypes.c_uint64
+    lib.oracle_forward_edge_counts.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
     lib.oracle_vertex_triangles.argtypes = [vp, vp, ctypes.c_int64, vp, ctypes.c_int]
     lib.oracle_oriented_edge_counts.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
     lib.oracle_edge_support.argtypes = [vp, vp, ctypes.c_int]
@@ -84,13 +89,18 @@ class Graph:
         self.threads = threads
         lib = _load()
         h = ctypes.c_void_p()
-        st = lib.oracle_graph_build(e.ctypes.data if e.size else None, e.shape[0], self.n, threads,
-                                    ctypes.byref(h))
+        secs = np.zeros(3, dtype=np.float64)
+        st = lib.oracle_graph_build_timed(e.ctypes.data if e.size else None, e.shape[0], self.n, threads,
+                                          ctypes.byref(h), secs.ctypes.data)
         if st == 2:
             raise VertexRangeError("vertex id outside [0, n)")
         if st != 0:
             raise ValueError("invalid argument")
         self._h = h
+        # wall seconds: canonicalisation (sort + de-duplication), the degrees, and
+        # the symmetric adjacency of the definition-level functions
+        self.build_seconds = (float(secs[0]), float(secs[1]), float(secs[2]))
+        self.count_seconds = None
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -115,11 +125,24 @@ class Graph:
         return out
 
     def count(self, order: int = ORDER_DEG_ID, per_vertex: bool = False):
-        """Forward algorithm. Returns T, or (T, t) with per_vertex."""
+        """Forward algorithm. Returns T, or (T, t) with per_vertex. Afterwards
+        count_seconds = (orientation + out-lists, intersections) wall seconds."""
         t = np.zeros(self.n, dtype=np.uint64) if per_vertex else None
-        T = int(_load().oracle_count_forward(self._h, order, t.ctypes.data if per_vertex and self.n else None,
-                                             self.threads))
+        secs = np.zeros(2, dtype=np.float64)
+        T = int(_load().oracle_count_forward_timed(self._h, order, t.ctypes.data if per_vertex and self.n else None,
+                                                   self.threads, secs.ctypes.data))
+        self.count_seconds = (float(secs[0]), float(secs[1]))
         return (T, t) if per_vertex else T
+
+    def forward_edge_counts(self, degree: str = "simple") -> np.ndarray:
+        """The forward algorithm's per-edge intersection sizes (the list of
+        intersection sizes of Algorithm 2) per canonical edge, uint32 [m]: the same values as
+        oriented_edge_counts, computed by merging out-lists instead of by definition."""
+        out = np.zeros(self.m, dtype=np.uint32)
+        if self.m:
+            _load().oracle_forward_edge_counts(self._h, {"simple": 0, "input": 1}[degree], out.ctypes.data,
+                                               self.threads)
+        return out
 
     def vertex_triangles(self, vs) -> np.ndarray:
         vs = np.ascontiguousarray(vs, dtype=np.int32)

@@ -7,11 +7,14 @@ Three formulations that share nothing with the forward algorithm in
 * ``trace_count``: T = trace(A^3) / 6 and t = diag(A^3) / 2 with int64 matrix
   products (A^3)_vv counts closed walks of length 3 through v, i.e. twice the
   triangles at v.
-* ``matrix_formulation``: the paper's Algorithm 3 (Section 3.3): split A into
-  its strictly lower and strictly upper triangles L and U, B = L U,
-  C = A o B (Hadamard product), T = (1/2) sum C. The printed last line of the
-  algorithm sums A rather than C; the figure caption of the worked example
-  (Figure 4) sums C, which is the reading taken here.
+* ``masked_product``: the matrix formulation of Section 3.3 written as its
+  definition, C = A o (L U) for a vertex order: L keeps the entries A[i, k]
+  with k before i, U the entries A[k, j] with k before j, so (L U)[i, j]
+  counts the common neighbours k of i and j that come before both, and
+  C[i, j] counts them for the edges ij alone; every triangle is seen at its
+  two later edges, once from each end, so T = (1/2) sum C. (The printed last
+  line of Algorithm 3 sums A rather than C; the caption of the worked example,
+  Figure 4, sums C, which is the reading taken here.)
 """
 from __future__ import annotations
 
@@ -56,21 +59,29 @@ def trace_count(edges: np.ndarray, n: int):
     return T2 // 6, (d // 2).astype(np.uint64)
 
 
-def matrix_formulation(A: np.ndarray, permute_by_nnz: bool = False):
-    """Algorithm 3 on a dense adjacency matrix. Returns (T, L, U, B, C).
-
-    With permute_by_nnz, rows and columns are first reordered by increasing
-    number of nonzeros (stable), as the algorithm's first step says; the
-    worked example of Figure 4 is shown without that permutation.
+def masked_product(A: np.ndarray, rank=None):
+    """C = A o (L U) on a dense adjacency matrix, for the vertex order `rank`
+    (rank[v] = position of v; default: id order, where L and U are the strict
+    lower and upper triangles of A). Returns (T, L, U, B, C) with B = L U,
+    all in the original vertex labels, and T = (1/2) sum C.
     """
     A = np.asarray(A, dtype=np.int64)
-    if permute_by_nnz:
-        p = np.argsort(A.sum(axis=1), kind="stable")
-        A = A[np.ix_(p, p)]
-    L = np.tril(A, -1)
-    U = np.triu(A, 1)
+    n = A.shape[0]
+    r = np.arange(n) if rank is None else np.asarray(rank)
+    before = (r[None, :] < r[:, None]).astype(np.int64)   # before[i, k]: k comes before i
+    L = A * before                # L[i, k] = A[i, k] when k is before i
+    U = A * before.T              # U[k, j] = A[k, j] when k is before j
     B = L @ U
     C = A * B
     s = int(C.sum())
     assert s % 2 == 0
     return s // 2, L, U, B, C
+
+
+def nnz_rank(A: np.ndarray) -> np.ndarray:
+    """Position of each vertex when rows are ordered by increasing number of
+    nonzeros, ties by id (the row order Algorithm 3 asks for)."""
+    p = np.argsort(np.asarray(A).sum(axis=1), kind="stable")
+    r = np.empty_like(p)
+    r[p] = np.arange(p.size)
+    return r

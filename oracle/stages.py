@@ -9,10 +9,12 @@ primitives (sort, unique, bincount, lexsort) and no blocking or fusion:
 * ``degree_order``   rank of every vertex in (degree, id) ascending order.
 * ``oriented_csr``   each edge kept once, directed from the lower to the higher
                      rank, as a CSR over ranks with ascending rows.
-* ``edge_tails``     for kept edge e = (u -> v) at position p of row u, the
-                     candidates of the intersection are the entries of row u
-                     after p (they alone exceed v); its length and the length
-                     of row v define the edge's degree-pair bucket.
+* ``middle_buckets`` the dynamic grouping (Section 4.2) by middle vertex: for
+                     kept edge e = (u -> v) at position p of row u, only the
+                     entries of row u after p (its tail) can be common
+                     out-neighbours of u and v; v's in-edges with a non-empty
+                     tail and its out-degree give v's degree-pair bucket.
+* ``bucket_totals``  per-bucket sums of those quantities.
 * ``oriented_counts`` the per-edge intersection sizes, by sets.
 """
 from __future__ import annotations
@@ -69,27 +71,62 @@ def oriented_csr(edges: np.ndarray, n: int, degree: str = "simple"):
     return rank, off, dst, src
 
 
-def edge_tails(off: np.ndarray, col: np.ndarray, src: np.ndarray):
-    """(tail_len, dplus_v) per kept edge in CSR order."""
+NO_BUCKET = 255
+
+
+def _floor_log2(x: np.ndarray) -> np.ndarray:
+    """floor(log2 x) of positive integers, exactly (bit length - 1)."""
+    x = np.asarray(x, dtype=np.int64)
+    out = np.zeros(x.shape, dtype=np.int64)
+    y = x.copy()
+    while np.any(y > 1):
+        big = y > 1
+        out[big] += 1
+        y[big] >>= 1
+    return out
+
+
+def middle_buckets(off: np.ndarray, col: np.ndarray):
+    """(d_in, d_out, bucket) per vertex of the oriented CSR (over ranks).
+
+    d_in(v): kept edges (u -> v) whose tail in row u (the entries after v) is
+    non-empty; d_out(v) = |N+(v)|. A vertex with both positive falls in bucket
+    16 * min(14, floor(log2 d_in)) + min(15, floor(log2 d_out)); every other
+    vertex in NO_BUCKET (255): it has no intersection work as a middle vertex.
+    """
+    off = np.asarray(off, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    n = off.shape[0] - 1
     m = col.shape[0]
-    e = np.arange(m, dtype=np.int64)
-    tail = off[src + 1] - e - 1
-    dplus = np.diff(off)
-    return tail, dplus[col]
+    dout = np.diff(off)
+    src = np.repeat(np.arange(n, dtype=np.int64), dout)
+    tail = off[src + 1] - np.arange(m, dtype=np.int64) - 1   # entries of row u after the edge
+    din = np.bincount(col[tail > 0], minlength=n).astype(np.int64)
+    bucket = np.full(n, NO_BUCKET, dtype=np.int64)
+    busy = (din > 0) & (dout > 0)
+    bucket[busy] = 16 * np.minimum(14, _floor_log2(din[busy])) + np.minimum(15, _floor_log2(dout[busy]))
+    return din, dout, bucket
 
 
-def bucket_of(tail: np.ndarray, dv: np.ndarray) -> np.ndarray:
-    """Degree-pair bucket 16 * l(tail) + l(d+ v), l(x) = min(15, floor(log2 x)); -1 when either is 0."""
-    def lg(x):
-        x = np.asarray(x, dtype=np.int64)
-        out = np.full(x.shape, -1, dtype=np.int64)
-        pos = x > 0
-        out[pos] = np.minimum(15, np.floor(np.log2(x[pos])).astype(np.int64))
-        return out
-    lt, lv = lg(tail), lg(dv)
-    b = 16 * lt + lv
-    b[(lt < 0) | (lv < 0)] = -1
-    return b
+def bucket_totals(off: np.ndarray, col: np.ndarray, window_log2: int = 17):
+    """Per bucket (256 entries, NO_BUCKET excluded from every sum): vertices,
+    sum of d_in, sum of d_out, sum of d_in * d_out, and the bitmap windows of
+    2^window_log2 ids that each middle list N+(v) spans, counted from its first
+    element rounded down to a multiple of 32 to its last."""
+    off = np.asarray(off, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    din, dout, bucket = middle_buckets(off, col)
+    busy = np.nonzero(bucket != NO_BUCKET)[0]
+    b = bucket[busy]
+    lo, hi = col[off[busy]], col[off[busy + 1] - 1]
+    win = ((hi - (lo & ~31)) >> window_log2) + 1
+    out = {}
+    for name, w in (("vertices", np.ones_like(b)), ("in_edges", din[busy]), ("out_edges", dout[busy]),
+                    ("work", din[busy] * dout[busy]), ("windows", win)):
+        acc = np.zeros(256, dtype=np.int64)
+        np.add.at(acc, b, w.astype(np.int64))   # integer sums, no rounding
+        out[name] = acc
+    return out
 
 
 def oriented_counts(off: np.ndarray, col: np.ndarray, src: np.ndarray) -> np.ndarray:

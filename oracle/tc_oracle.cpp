@@ -18,6 +18,10 @@
  *    intersection", Algorithm 2; orientation by degree order, Section 4.2):
  *    keep each edge once, directed along a strict total order of the
  *    vertices, and intersect the two out-neighbour lists of every kept edge.
+ *    oracle_count_forward_timed is the same with the wall time of its two
+ *    stages (orientation + out-lists, intersections) reported.
+ *  - oracle_forward_edge_counts: the per-edge intersection sizes of the
+ *    forward algorithm (Algorithm 2), in canonical pair order.
  *  - oracle_vertex_triangles: t[v] by definition, the number of edges among
  *    the neighbours of v. Written independently of the forward algorithm.
  *  - oracle_oriented_edge_counts: per kept edge (a -> b), the number of
@@ -91,10 +95,18 @@ inline uint64_t merge_count(const int32_t* a, int64_t na, const int32_t* b, int6
 
 extern "C" {
 
-/* Status codes: 0 ok, 1 invalid argument, 2 vertex id outside [0, n). */
-int oracle_graph_build(const int32_t* edges, int64_t num_edges, int32_t n, int threads, void** out) {
+/*
+ * Status codes: 0 ok, 1 invalid argument, 2 vertex id outside [0, n).
+ * seconds (may be NULL) receives wall times: [0] canonicalisation (range
+ * check, loops, sort, de-duplication), [1] the degrees, [2] the symmetric
+ * adjacency (used by the definition-level functions, not by the forward
+ * algorithm).
+ */
+int oracle_graph_build_timed(const int32_t* edges, int64_t num_edges, int32_t n, int threads, void** out,
+                             double* seconds) {
     if (!out || num_edges < 0 || n < 0 || (num_edges > 0 && !edges)) return 1;
     *out = nullptr;
+    const double t0 = omp_get_wtime();
     for (int64_t i = 0; i < 2 * num_edges; ++i)
         if (edges[i] < 0 || edges[i] >= n) return 2;
     Graph* g = new Graph;
@@ -115,9 +127,11 @@ int oracle_graph_build(const int32_t* edges, int64_t num_edges, int32_t n, int t
     __gnu_parallel::sort(g->keys.begin(), g->keys.end());
     g->keys.erase(std::unique(g->keys.begin(), g->keys.end()), g->keys.end());
     g->m = (int64_t)g->keys.size();
+    const double t1 = omp_get_wtime();
     // Degrees and the symmetric adjacency (rows ascending by id).
     g->deg.assign((size_t)n, 0);
     for (uint64_t k : g->keys) { g->deg[k >> 32]++; g->deg[(uint32_t)k]++; }
+    const double t2 = omp_get_wtime();
     g->adj_off.assign((size_t)n + 1, 0);
     for (int32_t v = 0; v < n; ++v) g->adj_off[v + 1] = g->adj_off[v] + g->deg[v];
     g->adj.resize((size_t)(2 * g->m));
@@ -130,8 +144,17 @@ int oracle_graph_build(const int32_t* edges, int64_t num_edges, int32_t n, int t
 #pragma omp parallel for schedule(dynamic, 1024) num_threads(pick_threads(threads))
     for (int32_t v = 0; v < n; ++v)
         std::sort(g->adj.begin() + g->adj_off[v], g->adj.begin() + g->adj_off[v + 1]);
+    if (seconds) {
+        seconds[0] = t1 - t0;
+        seconds[1] = t2 - t1;
+        seconds[2] = omp_get_wtime() - t2;
+    }
     *out = g;
     return 0;
+}
+
+int oracle_graph_build(const int32_t* edges, int64_t num_edges, int32_t n, int threads, void** out) {
+    return oracle_graph_build_timed(edges, num_edges, n, threads, out, nullptr);
 }
 
 void oracle_graph_free(void* h) { delete (Graph*)h; }
@@ -159,11 +182,16 @@ void oracle_graph_degrees(const void* h, int32_t* out) {
  *                 descending, id ascending), 2: plain id order.
  * Every strict total order finds each triangle exactly once, at the edge
  * joining its two smallest vertices, so T and t do not depend on the mode.
- * per_vertex (length n, may be NULL) receives t[v].
+ * per_vertex (length n, may be NULL) receives t[v]: each thread adds its
+ * matches into an array of its own, and the arrays are summed at the end.
+ * seconds (may be NULL): [0] orientation and out-lists, [1] intersections.
  */
-uint64_t oracle_count_forward(const void* h, int order_mode, uint64_t* per_vertex, int threads) {
+uint64_t oracle_count_forward_timed(const void* h, int order_mode, uint64_t* per_vertex, int threads,
+                                    double* seconds) {
     const Graph* g = (const Graph*)h;
     const int32_t n = g->n;
+    const int nth = pick_threads(threads);
+    const double t0 = omp_get_wtime();
     // Form the filtered edge list: each edge once, from the earlier to the later endpoint.
     std::vector<int64_t> off((size_t)n + 1, 0);
     for (uint64_t k : g->keys) {
@@ -179,42 +207,117 @@ uint64_t oracle_count_forward(const void* h, int order_mode, uint64_t* per_verte
         else out_adj[fill[b]++] = a;
     }
     // Out-lists sorted by vertex id (keys are ascending, but sort to be explicit).
-#pragma omp parallel for schedule(dynamic, 1024) num_threads(pick_threads(threads))
+#pragma omp parallel for schedule(dynamic, 1024) num_threads(nth)
     for (int32_t v = 0; v < n; ++v) std::sort(out_adj.begin() + off[v], out_adj.begin() + off[v + 1]);
-    if (per_vertex)
-        for (int32_t v = 0; v < n; ++v) per_vertex[v] = 0;
+    const double t1 = omp_get_wtime();
     // Intersect the two out-lists of every kept edge; reduce the counts.
     uint64_t total = 0;
-#pragma omp parallel for schedule(dynamic, 64) reduction(+ : total) num_threads(pick_threads(threads))
-    for (int32_t u = 0; u < n; ++u) {
-        const int32_t* nu = out_adj.data() + off[u];
-        const int64_t du = off[u + 1] - off[u];
-        for (int64_t p = 0; p < du; ++p) {
-            int32_t v = nu[p];
-            const int32_t* nv = out_adj.data() + off[v];
-            const int64_t dv = off[v + 1] - off[v];
-            if (!per_vertex) {
-                total += merge_count(nu, du, nv, dv);
-                continue;
-            }
-            int64_t i = 0, j = 0;
-            while (i < du && j < dv) {
-                if (nu[i] < nv[j]) ++i;
-                else if (nu[i] > nv[j]) ++j;
-                else {
-                    ++total;
-#pragma omp atomic
-                    per_vertex[u]++;
-#pragma omp atomic
-                    per_vertex[v]++;
-#pragma omp atomic
-                    per_vertex[nu[i]]++;
-                    ++i; ++j;
+    std::vector<std::vector<uint64_t>> local(per_vertex ? (size_t)nth : 0);
+#pragma omp parallel num_threads(nth)
+    {
+        uint64_t* t = nullptr;
+        if (per_vertex) {
+            std::vector<uint64_t>& mine = local[(size_t)omp_get_thread_num()];
+            mine.assign((size_t)n, 0);
+            t = mine.data();
+        }
+#pragma omp for schedule(dynamic, 64) reduction(+ : total)
+        for (int32_t u = 0; u < n; ++u) {
+            const int32_t* nu = out_adj.data() + off[u];
+            const int64_t du = off[u + 1] - off[u];
+            for (int64_t p = 0; p < du; ++p) {
+                int32_t v = nu[p];
+                const int32_t* nv = out_adj.data() + off[v];
+                const int64_t dv = off[v + 1] - off[v];
+                if (!t) {
+                    total += merge_count(nu, du, nv, dv);
+                    continue;
+                }
+                int64_t i = 0, j = 0;
+                while (i < du && j < dv) {
+                    if (nu[i] < nv[j]) ++i;
+                    else if (nu[i] > nv[j]) ++j;
+                    else {
+                        ++total;
+                        t[u]++;
+                        t[v]++;
+                        t[nu[i]]++;
+                        ++i; ++j;
+                    }
                 }
             }
         }
     }
+    if (per_vertex) {
+#pragma omp parallel for schedule(static) num_threads(nth)
+        for (int32_t v = 0; v < n; ++v) {
+            uint64_t s = 0;
+            for (const std::vector<uint64_t>& l : local) s += l[v];
+            per_vertex[v] = s;
+        }
+    }
+    if (seconds) {
+        seconds[0] = t1 - t0;
+        seconds[1] = omp_get_wtime() - t1;
+    }
     return total;
+}
+
+uint64_t oracle_count_forward(const void* h, int order_mode, uint64_t* per_vertex, int threads) {
+    return oracle_count_forward_timed(h, order_mode, per_vertex, threads, nullptr);
+}
+
+/*
+ * The forward algorithm's per-edge intersection sizes (Algorithm 2): for each kept edge
+ * x -> y of the (degree, id) orientation, |N+(x) intersected with N+(y)| by a
+ * two-pointer merge of the two out-lists, written at the index of the edge's
+ * canonical pair (ascending order of oracle_graph_edges). degree_mode 0: the
+ * simple graph's degree; 1: input pairs at the vertex. The definition-level
+ * oracle_oriented_edge_counts gives the same values by another route.
+ */
+void oracle_forward_edge_counts(const void* h, int degree_mode, uint32_t* out, int threads) {
+    const Graph* g = (const Graph*)h;
+    const int32_t n = g->n;
+    struct Out {
+        int32_t w;        // out-neighbour
+        int64_t pair;     // index of the canonical pair
+    };
+    auto before = [&](int32_t a, int32_t b) {
+        return degree_mode ? precedes_input_deg_id(*g, a, b) : precedes_deg_id(*g, a, b);
+    };
+    std::vector<int64_t> off((size_t)n + 1, 0);
+    for (uint64_t k : g->keys) {
+        int32_t a = (int32_t)(k >> 32), b = (int32_t)(uint32_t)k;
+        off[(before(a, b) ? a : b) + 1]++;
+    }
+    for (int32_t v = 0; v < n; ++v) off[v + 1] += off[v];
+    std::vector<Out> lst((size_t)g->m);
+    std::vector<int64_t> fill(off.begin(), off.end() - 1);
+    for (int64_t i = 0; i < g->m; ++i) {
+        int32_t a = (int32_t)(g->keys[i] >> 32), b = (int32_t)(uint32_t)g->keys[i];
+        if (before(a, b)) lst[fill[a]++] = {b, i};
+        else lst[fill[b]++] = {a, i};
+    }
+#pragma omp parallel for schedule(dynamic, 1024) num_threads(pick_threads(threads))
+    for (int32_t v = 0; v < n; ++v)
+        std::sort(lst.begin() + off[v], lst.begin() + off[v + 1], [](const Out& x, const Out& y) { return x.w < y.w; });
+#pragma omp parallel for schedule(dynamic, 64) num_threads(pick_threads(threads))
+    for (int32_t u = 0; u < n; ++u) {
+        const Out* nu = lst.data() + off[u];
+        const int64_t du = off[u + 1] - off[u];
+        for (int64_t p = 0; p < du; ++p) {
+            const Out* nv = lst.data() + off[nu[p].w];
+            const int64_t dv = off[nu[p].w + 1] - off[nu[p].w];
+            uint32_t c = 0;
+            int64_t i = 0, j = 0;
+            while (i < du && j < dv) {
+                if (nu[i].w < nv[j].w) ++i;
+                else if (nu[i].w > nv[j].w) ++j;
+                else { ++c; ++i; ++j; }
+            }
+            out[nu[p].pair] = c;
+        }
+    }
 }
 
 /*

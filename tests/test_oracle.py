@@ -23,7 +23,7 @@ def _count(e, n, **kw):
 # ---------------------------------------------------------------- Figure 4
 def test_fig4_matrix_formulation_reproduces_printed_matrices():
     g = load_golden_matrices("fig4_matrix_example.txt")
-    T, L, U, B, C = dense.matrix_formulation(g["A"])
+    T, L, U, B, C = dense.masked_product(g["A"])
     np.testing.assert_array_equal(L, g["L"])
     np.testing.assert_array_equal(U, g["U"])
     np.testing.assert_array_equal(B, g["B"])
@@ -289,8 +289,82 @@ def test_stage_definitions_on_small_graph():
         row = col[off[u]:off[u + 1]]
         assert np.all(np.diff(row) > 0)
     assert sorted(rank.tolist()) == list(range(n))
-    tail, dv = stages.edge_tails(off, col, src)
-    assert np.all(tail >= 0)
-    b = stages.bucket_of(tail, dv)
-    assert b.max() < 256
-    assert np.all((b < 0) == ((tail == 0) | (dv == 0)))
+    din, dout, b = stages.middle_buckets(off, col)
+    assert b.max() <= stages.NO_BUCKET
+    assert np.all((b == stages.NO_BUCKET) == ((din == 0) | (dout == 0)))
+    np.testing.assert_array_equal(dout, np.diff(off))
+
+
+def test_middle_buckets_k4_by_hand():
+    # K4: all degrees 3, so rank = id; rows 0 -> {1,2,3}, 1 -> {2,3}, 2 -> {3}.
+    # Tails: (0->1): {2,3}; (0->2): {3}; (1->2): {3}; (0->3), (1->3), (2->3): empty.
+    rank, off, col, src = stages.oriented_csr(graphgen.complete(4), 4)
+    din, dout, b = stages.middle_buckets(off, col)
+    assert din.tolist() == [0, 1, 2, 0]
+    assert dout.tolist() == [3, 2, 1, 0]
+    # vertex 1: 16*log2(1) + log2(2) = 1; vertex 2: 16*log2(2) + log2(1) = 16
+    assert b.tolist() == [255, 1, 16, 255]
+
+
+def test_middle_buckets_complete_graph_closed_form():
+    # K_n, rank = id: row v = {v+1 .. n-1}; an in-edge (u -> v) has the tail
+    # {v+1 .. n-1}, non-empty iff v < n - 1; so d_in(v) = v, d_out(v) = n - 1 - v.
+    n = 40
+    rank, off, col, src = stages.oriented_csr(graphgen.complete(n), n)
+    din, dout, b = stages.middle_buckets(off, col)
+    for v in range(n):
+        assert dout[v] == n - 1 - v
+        assert din[v] == (v if v < n - 1 else 0)
+        if 1 <= v <= n - 2:
+            assert b[v] == 16 * int(np.log2(v)) + int(np.log2(n - 1 - v)), v
+        else:
+            assert b[v] == 255
+    tot = stages.bucket_totals(off, col)
+    busy = range(1, n - 1)
+    assert tot["vertices"].sum() == n - 2
+    assert tot["in_edges"].sum() == sum(busy)
+    assert tot["out_edges"].sum() == sum(n - 1 - v for v in busy)
+    assert tot["work"].sum() == sum(v * (n - 1 - v) for v in busy)
+    assert tot["windows"].sum() == n - 2   # every middle list lies inside one 2^17-id window
+    # 8-id windows: N+(v) = {v+1 .. 39} spans ((39 - ((v+1) rounded down to 32)) >> 3) + 1
+    # windows: 5 for v + 1 < 32 (vertices 1..30), 1 for v + 1 >= 32 (vertices 31..38)
+    assert stages.bucket_totals(off, col, window_log2=3)["windows"].sum() == 30 * 5 + 8 * 1
+
+
+def test_middle_buckets_in_degree_cap():
+    # 2^15 vertices u_i joined to both v and w (ids 0 and 1), and v joined to w:
+    # deg(u_i) = 2, deg(v) = deg(w) = 2^15 + 1, v before w by id. Each u_i -> v has the
+    # tail {w}, so d_in(v) = 2^15 and d_out(v) = 1: bucket 16 * min(14, 15) + 0 = 224.
+    k = 1 << 15
+    u = np.arange(2, 2 + k, dtype=np.int32)
+    e = np.concatenate([np.stack([u, np.zeros(k, np.int32)], 1), np.stack([u, np.ones(k, np.int32)], 1),
+                        np.array([[0, 1]], np.int32)])
+    rank, off, col, src = stages.oriented_csr(e, k + 2)
+    din, dout, b = stages.middle_buckets(off, col)
+    rv = rank[0]
+    assert (din[rv], dout[rv], b[rv]) == (k, 1, 224)
+    assert np.count_nonzero(b != 255) == 1
+
+
+def test_forward_edge_counts_match_definition():
+    """The forward algorithm's per-edge intersection sizes equal the definition-level per-edge
+    counts (common neighbours after both endpoints), for both degree readings."""
+    e, n = _rmat_small(12, 31)
+    dirty = np.concatenate([e, e[::3, ::-1], np.array([[5, 5], [7, 7]], np.int32)]).astype(np.int32)
+    for edges, modes in ((e, ("simple", "input")), (dirty, ("simple", "input"))):
+        g = oracle.Graph(edges, n)
+        for mode in modes:
+            f = g.forward_edge_counts(mode)
+            np.testing.assert_array_equal(f, g.oriented_edge_counts(mode))
+            assert int(f.astype(np.int64).sum()) == g.count()
+
+
+def test_forward_per_vertex_thread_private_sums():
+    """t[v] from the forward algorithm (per-thread sums) equals t[v] by definition
+    at 1 and at 8 threads."""
+    e, n = _rmat_small(13, 41)
+    ref = oracle.Graph(e, n, threads=1).vertex_triangles(np.arange(n))
+    for th in (1, 8):
+        T, t = oracle.Graph(e, n, threads=th).count(per_vertex=True)
+        np.testing.assert_array_equal(t, ref)
+        assert int(t.sum()) == 3 * T

@@ -51,7 +51,7 @@ def test_fig4_upper_mask_and_full_sum():
 @pytest.mark.parametrize("seed", range(8))
 def test_rows_match_dense_algorithm_3_in_id_order(seed):
     A, n = _random_graph(seed)
-    _, _, _, _, C = dense.matrix_formulation(A)
+    _, _, _, _, C = dense.masked_product(A)
     s, rs = oracle.Graph(_edges_of(A), n).matrix_sum(order=oracle.ORDER_ID, row_sums=True)
     np.testing.assert_array_equal(rs, C.sum(axis=1))
     assert s == int(C.sum())
@@ -61,11 +61,13 @@ def test_rows_match_dense_algorithm_3_in_id_order(seed):
 @pytest.mark.parametrize("seed", range(8))
 def test_rows_match_dense_algorithm_3_with_nnz_permutation(seed):
     A, n = _random_graph(seed)
-    _, _, _, _, Cp = dense.matrix_formulation(A, permute_by_nnz=True)
-    p = np.argsort(A.sum(axis=1), kind="stable")   # row q of the permuted C is vertex p[q]
+    _, _, _, _, C = dense.masked_product(A, dense.nnz_rank(A))
     s, rs = oracle.Graph(_edges_of(A), n).matrix_sum(order=oracle.ORDER_DEG_ID, row_sums=True)
-    np.testing.assert_array_equal(rs[p], Cp.sum(axis=1))
-    assert s == int(Cp.sum())
+    np.testing.assert_array_equal(rs, C.sum(axis=1))
+    assert s == int(C.sum())
+    # the order changes C, never the count: T = trace(A^3) / 6 in both orders
+    Tt, _ = dense.trace_count(_edges_of(A), n)
+    assert dense.masked_product(A)[0] == dense.masked_product(A, dense.nnz_rank(A))[0] == Tt
 
 
 # ---------------------------------------------------------------- brute force and invariants
