@@ -11,7 +11,7 @@
  *   3. build the filtered CSR (the "induced subgraph" of Section 4.2) with a
  *      device radix sort;
  *   4. intersect the two out-neighbour lists of every kept edge; the sizes
- *      sum to the triangle count (Algorithm 2, Reduce).
+ *      sum to the triangle count (Algorithm 2).
  *
  * Conventions for every entry point
  *   - Pointers prefixed d_ are device pointers on the context's device;
@@ -84,7 +84,7 @@ tc_status tc_workspace_size(int64_t num_edges, int32_t num_vertices, const tc_op
 
 /*
  * Exact triangle count T of the undirected simple graph denoted by the edge
- * list (Algorithm 2: Count = Reduce(IntersectList)).
+ * list (Algorithm 2: the sum of the per-edge intersection sizes).
  *   h_count       out: T (host).
  *   d_per_vertex  out, optional (NULL): uint64[num_vertices], t[v] = number
  *                 of triangles containing v (original ids).
@@ -127,8 +127,8 @@ tc_status tc_clustering(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, 
                         uint64_t* d_per_vertex, uint64_t* h_count, uint64_t* h_wedges, double* h_transitivity);
 
 /*
- * Per-edge intersection sizes (the IntersectList of Algorithm 2). For each
- * kept edge (u -> v), u before v in (degree, id) order, writes
+ * Per-edge intersection sizes (the per-edge list that Algorithm 2 sums). For
+ * each kept edge (u -> v), u before v in (degree, id) order, writes
  *   d_out_edges[i] = {u, v} (original ids) and
  *   d_out_counts[i] = |N+(u) intersected with N+(v)|, the triangles whose two
  *   lowest vertices are u and v.

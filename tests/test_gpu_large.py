@@ -1,12 +1,16 @@
-"""Parity at the full workload sizes: R-MAT scale 24, the random geometric graph on
-2^23 vertices and the batch of 4096 Chung-Lu graphs.
+"""Whole-graph parity at the full workload sizes: R-MAT scale 24 (T above 2^32),
+the random geometric graph on 2^23 vertices and the batch of 4096 Chung-Lu
+graphs.
 
-The oracle cannot count these whole within a test's time, so the GPU outputs
-are checked on samples the oracle computes one by one (t[v] by definition,
-oriented per-edge counts by definition, per-graph counts of sampled graphs) and
-through properties that hold at any size (sum of t[v] = 3T; the three
-strategies agree edge by edge; the batch's counts add up to the union's count).
+Expected values are the oracle's (forward algorithm, Section 3.2 / Algorithm 2),
+written by tests/golden/make_large_golden.py, which calls only the seeded
+generators and the oracle. Vectors too large to store (t[v], the per-edge
+intersection sizes, the kept edges) are compared whole through the SHA-256 of
+their bytes; on a mismatch the test re-runs the oracle to name the first
+differing entries.
 """
+import hashlib
+import json
 import os
 
 import numpy as np
@@ -15,7 +19,9 @@ import pytest
 import graphgen
 import oracle
 
-pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_counts.json")
 
 
 @pytest.fixture(scope="module")
@@ -30,88 +36,119 @@ def tc():
     return paper_1804_06926_amd
 
 
-def _check_large(tc, name, e, n, degree):
+@pytest.fixture(scope="module")
+def gold():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def _sha(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def _canonical(pairs, counts):
+    """GPU per-edge output (original-id pairs in CSR order) in canonical pair order
+    (a << 32 | b, a < b, ascending): (keys uint64, counts uint32) numpy arrays."""
     import torch
-    print(f"[{name}] E={e.shape[0]} n={n}: GPU counts", flush=True)
+    p = pairs.to(torch.int64)
+    key = (torch.minimum(p[:, 0], p[:, 1]) << 32) | torch.maximum(p[:, 0], p[:, 1])
+    del p
+    sk, perm = torch.sort(key)
+    c = counts[perm]
+    return sk.cpu().numpy().astype("<u8"), c.cpu().numpy().astype("<u4")
+
+
+def _modes(tc):
+    from paper_1804_06926_amd import selector
+    modes = [("heuristic", tc.SELECT_HEURISTIC), ("merge", tc.FORCE_MERGE), ("bsearch", tc.FORCE_BSEARCH),
+             ("bitmap", tc.FORCE_BITMAP)]
+    if selector.load_default():
+        modes.insert(1, ("learned", tc.SELECT_LEARNED))
+    return modes
+
+
+def _check_whole(tc, name, e, n, ref):
+    import torch
+    assert e.shape[0] == ref["raw_pairs"]
     d = torch.from_numpy(e).cuda()
-    T = tc.count_triangles(d, n)
-    T2, t = tc.count_triangles(d, n, per_vertex=True)
-    t = t.cpu().numpy().astype(np.uint64)
-    assert T2 == T and int(t.sum()) == 3 * T
-    edges_by_kernel = {}
-    for sel in (tc.FORCE_MERGE, tc.FORCE_BSEARCH, tc.FORCE_BITMAP):
-        print(f"[{name}] per-edge counts, strategy {sel}", flush=True)
-        pairs, counts, T3 = tc.edge_counts(d, n, select=sel)
-        assert T3 == T
-        edges_by_kernel[sel] = (pairs.cpu().numpy(), counts.cpu().numpy())
-    p0, c0 = edges_by_kernel[tc.FORCE_MERGE]
-    for sel in (tc.FORCE_BSEARCH, tc.FORCE_BITMAP):
-        np.testing.assert_array_equal(edges_by_kernel[sel][0], p0)
-        np.testing.assert_array_equal(edges_by_kernel[sel][1], c0)
-    assert int(c0.astype(np.int64).sum()) == T
-    del d
-    print(f"[{name}] oracle graph", flush=True)
-    g = oracle.Graph(e, n)
-    assert g.m == p0.shape[0]
-    rng = np.random.default_rng(2024)
-    deg = g.degrees()
-    top = np.argsort(deg)[-40:]
-    some = rng.choice(np.nonzero(deg > 0)[0], 200, replace=False)
-    low = rng.choice(n, 20, replace=False)
-    vs = np.unique(np.concatenate([top, some, low])).astype(np.int32)
-    print(f"[{name}] oracle t[v] for {vs.size} vertices", flush=True)
-    np.testing.assert_array_equal(g.vertex_triangles(vs), t[vs])
-    idx = rng.choice(p0.shape[0], 3000, replace=False)
-    print(f"[{name}] oracle per-edge counts for {idx.size} edges", flush=True)
-    np.testing.assert_array_equal(g.pair_counts(p0[idx], degree).astype(np.int64), c0[idx].astype(np.int64))
-    return T
+    for mname, sel in _modes(tc):
+        print(f"[{name}] T, selection {mname}", flush=True)
+        assert tc.count_triangles(d, n, select=sel) == ref["triangles"], mname
+    print(f"[{name}] t[v]", flush=True)
+    T, t = tc.count_triangles(d, n, per_vertex=True)
+    assert T == ref["triangles"]
+    t = t.cpu().numpy().astype("<u8")
+    assert int(t.sum()) == ref["t_sum"] == 3 * ref["triangles"]
+    if _sha(t) != ref["t_sha256_u64le"]:
+        _, t_ref = oracle.count_triangles(e, n, per_vertex=True)
+        bad = np.nonzero(t != t_ref)[0]
+        pytest.fail(f"{name}: t[v] differs at {bad.size} vertices, first {bad[:10].tolist()}")
+    print(f"[{name}] per-edge counts, heuristic", flush=True)
+    pairs0, counts0, T0 = tc.edge_counts(d, n)
+    assert T0 == ref["triangles"] and pairs0.shape[0] == ref["m"]
+    keys, c = _canonical(pairs0, counts0)
+    assert _sha(keys) == ref["edge_keys_sha256_u64le"], f"{name}: kept edges differ from the oracle's"
+    assert int(c.astype(np.uint64).sum()) == ref["edge_counts_sum"]
+    if _sha(c) != ref["edge_counts_sha256_u32le"]:
+        c_ref = oracle.Graph(e, n).forward_edge_counts(ref["edge_counts_degree"])
+        bad = np.nonzero(c != c_ref)[0]
+        pytest.fail(f"{name}: per-edge counts differ at {bad.size} edges, first {bad[:10].tolist()}")
+    del keys, c
+    # the CSR (and so the output order) does not depend on the selection: every other
+    # strategy must give the same arrays, entry by entry
+    for mname, sel in _modes(tc)[1:]:
+        print(f"[{name}] per-edge counts, selection {mname}", flush=True)
+        pairs, counts, T1 = tc.edge_counts(d, n, select=sel)
+        assert T1 == ref["triangles"], mname
+        assert torch.equal(pairs, pairs0), mname
+        assert torch.equal(counts, counts0), mname
+        del pairs, counts
 
 
-def test_rmat24_sampled(tc):
-    n = 1 << 24
-    e = graphgen.rmat(24, 16, seed=1)
-    # raw R-MAT draws repeat pairs: the GPU orders by input-pair degree
-    _check_large(tc, "rmat24", e, n, "input")
+def test_rmat24_whole_graph(tc, gold):
+    """R-MAT scale 24 seed 1: T = 10,287,651,446 (above 2^32) and every t[v] and every
+    per-edge count, for every selection mode. The raw draws repeat pairs, so the
+    per-edge counts follow the input-pair degree order (the oracle's "input" reading)."""
+    ref = gold["rmat24"]
+    assert ref["triangles"] > 1 << 32
+    _check_whole(tc, "rmat24", graphgen.rmat(24, 16, seed=1), 1 << 24, ref)
 
 
-def test_rgg23_sampled(tc):
-    n = 1 << 23
-    e = graphgen.rgg(n, 32.0, seed=5)
-    _check_large(tc, "rgg23", e, n, "simple")
+def test_rgg23_whole_graph(tc, gold):
+    """Random geometric graph, 2^23 vertices, average degree 32, seed 5 (held out from
+    selector training): T, every t[v] and every per-edge count, every selection mode."""
+    ref = gold["rgg23"]
+    _check_whole(tc, "rgg23", graphgen.rgg(1 << 23, 32.0, seed=5), 1 << 23, ref)
 
 
-def test_chung_lu_batch_4096_sampled(tc):
+def test_chung_lu_batch_4096_every_graph(tc, gold):
+    """All 4096 per-graph counts of the batch against the oracle's: captured-graph call,
+    its replay, a direct launch, the learned mode, and the shipped autotuned tile shapes."""
     import torch
+    from paper_1804_06926_amd import autotune, selector
+    ref = np.array(gold["clbatch"]["counts"], dtype=np.uint64)
     print("[batch] generating 4096 Chung-Lu graphs", flush=True)
     e, off, nv = graphgen.chung_lu_batch(4096)
+    assert e.shape[0] == gold["clbatch"]["raw_pairs"] and nv.size == ref.size
     d = torch.from_numpy(e).cuda()
-    print(f"[batch] E={e.shape[0]}: batched count", flush=True)
-    got = tc.count_triangles_batch(d, off, nv)
-    again = tc.count_triangles_batch(d, off, nv)   # graph replay
-    np.testing.assert_array_equal(got, again)
-    # the union counted as one graph (vertex ids shifted) gives the sum
-    base = np.zeros(nv.size, dtype=np.int64)
-    np.cumsum(nv[:-1].astype(np.int64), out=base[1:])
-    shift = np.repeat(base, np.diff(off)).astype(np.int32)
-    union = e + shift[:, None]
-    N = int(nv.astype(np.int64).sum())
-    print("[batch] union count", flush=True)
-    T_union = tc.count_triangles(torch.from_numpy(union).cuda(), N)
-    assert int(got.astype(np.int64).sum()) == T_union
-    del union
-    rng = np.random.default_rng(7)
-    sizes = np.diff(off)
-    sample = np.unique(np.concatenate([np.argsort(sizes)[-6:], np.argsort(sizes)[:6],
-                                       rng.choice(nv.size, 36, replace=False)]))
-    print(f"[batch] oracle on {sample.size} graphs", flush=True)
-    for g in sample:
-        ref = oracle.count_triangles(e[off[g]:off[g + 1]], int(nv[g]))
-        assert int(got[g]) == ref, g
+    try:
+        for tuned in (False, True):
+            if tuned:
+                assert autotune.apply_cached(tc.SELECT_HEURISTIC), "no shipped tile shapes for this device"
+            print(f"[batch] tuned tiles={tuned}: captured graph, replay, direct launch", flush=True)
+            np.testing.assert_array_equal(tc.count_triangles_batch(d, off, nv), ref)
+            np.testing.assert_array_equal(tc.count_triangles_batch(d, off, nv), ref)   # replay
+            np.testing.assert_array_equal(tc.count_triangles_batch(d, off, nv, graph=False), ref)
+        if selector.load_default():
+            print("[batch] learned selection", flush=True)
+            np.testing.assert_array_equal(tc.count_triangles_batch(d, off, nv, select=tc.SELECT_LEARNED), ref)
+    finally:
+        tc.set_tile_shapes(None, None)
 
 
 def test_formulations_rmat20_against_oracle(tc):
-    """The benchmark graph (R-MAT 20) through every formulation and strategy:
-    T equal to the oracle's, and the sums 3T (full lists), 2T (sum of C) and T."""
+    """R-MAT 20 through every formulation and strategy: T equal to the oracle's, and
+    the sums 3T (full lists), 2T (sum of C) and T."""
     import torch
     n = 1 << 20
     e = graphgen.rmat(20, 16, seed=1)
@@ -124,15 +161,13 @@ def test_formulations_rmat20_against_oracle(tc):
             assert tc.count_triangles_formulation(d, n, form, select=sel) == (T, k * T)
 
 
-def test_formulations_rmat24_sums(tc):
-    """R-MAT 24 (heuristic selection): every formulation's T equals the filtered
-    count (itself checked on samples above) and the sums are 3T, 2T and T."""
+def test_formulations_rmat24_against_oracle(tc, gold):
+    """R-MAT 24 (heuristic selection): every formulation gives the oracle's T, with the
+    sums 3T, 2T and T."""
     import torch
+    T = gold["rmat24"]["triangles"]
     n = 1 << 24
-    e = graphgen.rmat(24, 16, seed=1)
-    d = torch.from_numpy(e).cuda()
-    print("[rmat24] filtered", flush=True)
-    T = tc.count_triangles(d, n)
-    for form, k in (("full", 3), ("matrix", 2), ("matrix_upper", 1)):
+    d = torch.from_numpy(graphgen.rmat(24, 16, seed=1)).cuda()
+    for form, k in (("filtered", 1), ("full", 3), ("matrix", 2), ("matrix_upper", 1)):
         print(f"[rmat24] formulation={form}", flush=True)
         assert tc.count_triangles_formulation(d, n, form) == (T, k * T)

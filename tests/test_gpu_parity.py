@@ -378,3 +378,64 @@ def test_formulations_empty_and_errors(tc):
         assert ei.value.status == 2
     with pytest.raises(ValueError):
         tc.count_triangles_formulation(dev([[0, 1]]), 2, "dense")
+
+
+# ---------------------------------------------------------------- merge-path diagonal splits
+def _straddles(L, g):
+    """Lane boundaries k (1..g-1) at which the merge-path split of two equal lists of
+    length L falls between the equal pair a_i = b_i. With A = B the merge (A first on
+    ties) is a0 b0 a1 b1 ..., so the boundary at diagonal d = floor(2 L k / g) separates
+    a pair exactly when d is odd."""
+    return {k for k in range(1, g) if ((2 * L * k) // g) % 2 == 1}
+
+
+@pytest.mark.parametrize("n", [130, 4200])
+def test_merge_path_matches_split_at_every_lane_boundary(tc, n):
+    """K_n (all degrees n - 1, so rank = id): every in-edge (u -> v) has the tail
+    {v+1 .. n-1} = N+(v), two equal lists of every length 1 .. n - 2. For each group
+    size g = 2 .. 64 (forced through the tile shapes on every bucket) the host first
+    checks that some list length puts an equal pair across every lane boundary
+    k = 1 .. g - 1; the forced merge-path kernel must then give T = C(n, 3) and every
+    per-edge count c(u -> v) = n - 1 - v. n = 4200 makes the middle lists longer than
+    the kernel's LDS stage, so the unstaged call site is covered as well."""
+    import torch
+    from math import comb
+    e = graphgen.complete(n)
+    d = dev(e)
+    if n <= 200:
+        assert oracle.count_triangles(e, n) == comb(n, 3)
+    try:
+        for g in (1, 2, 4, 8, 16, 32, 64):
+            covered = set().union(*(_straddles(L, g) for L in range(1, n - 1)))
+            assert covered == set(range(1, g)), (g, sorted(set(range(1, g)) - covered))
+            tc.set_tile_shapes(group=np.full(256, g))
+            print(f"K_{n}: merge path, {g} lanes per in-edge", flush=True)
+            assert tc.count_triangles(d, n, select=tc.FORCE_MERGE) == comb(n, 3), g
+            pairs, counts, T = tc.edge_counts(d, n, select=tc.FORCE_MERGE)
+            p = pairs.cpu().numpy()
+            assert np.all(p[:, 0] < p[:, 1])   # rank = id
+            np.testing.assert_array_equal(counts.cpu().numpy(), n - 1 - p[:, 1])
+    finally:
+        tc.set_tile_shapes(None, None)
+
+
+# ---------------------------------------------------------------- dynamic grouping (buckets)
+@pytest.mark.parametrize("case,degree", [("k40", "simple"), ("rmat12_dirty", "input"), ("chung_lu", "simple"),
+                                         ("rgg_16k", "simple"), ("er_4096_32768", "simple")])
+def test_bucket_statistics_match_oracle(tc, case, degree):
+    """Per-bucket vertices, in-edges with work, out-edges and work (the grouping of the
+    middle vertices, Section 4.2) equal the oracle's stage definition on its own
+    degree-ordered CSR."""
+    e, n = CASES[case]()
+    rank, off, col, src = stages.oriented_csr(e, n, degree=degree)
+    ref = stages.bucket_totals(off, col)
+    tc.count_triangles(dev(e), n)
+    st = tc.last_stats()
+    np.testing.assert_array_equal(st["bucket_vertices"][:255].astype(np.int64), ref["vertices"][:255])
+    np.testing.assert_array_equal(st["bucket_in_edges"][:255].astype(np.int64), ref["in_edges"][:255])
+    np.testing.assert_array_equal(st["bucket_out_edges"][:255].astype(np.int64), ref["out_edges"][:255])
+    np.testing.assert_array_equal(st["bucket_work"][:255].astype(np.int64), ref["work"][:255])
+    busy = np.nonzero(ref["vertices"][:255])[0]
+    feat = tc.bucket_features()
+    np.testing.assert_allclose(feat[busy, 2], np.log2(1.0 + ref["windows"][busy]).astype(np.float32) / 32.0,
+                               rtol=1e-6)
