@@ -63,6 +63,8 @@ def _load():
     lib.oracle_count_forward.restype = ctypes.c_uint64
     lib.oracle_count_forward_timed.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp]
     lib.oracle_count_forward_timed.restype = ctypes.c_uint64
+    lib.oracle_count_forward_rows.argtypes = [vp, ctypes.c_int, ctypes.c_int32, vp, ctypes.c_int, vp, vp]
+    lib.oracle_count_forward_rows.restype = ctypes.c_uint64
     lib.oracle_forward_edge_counts.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
     lib.oracle_vertex_triangles.argtypes = [vp, vp, ctypes.c_int64, vp, ctypes.c_int]
     lib.oracle_oriented_edge_counts.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
@@ -133,6 +135,19 @@ class Graph:
                                                    self.threads, secs.ctypes.data))
         self.count_seconds = (float(secs[0]), float(secs[1]))
         return (T, t) if per_vertex else T
+
+    def count_rows(self, row_stride: int, order: int = ORDER_DEG_ID):
+        """The forward algorithm with the intersections of rows u % row_stride == 0 only
+        (a bounded sample for timing). Returns (triangles whose earliest vertex is such a
+        row, kept edges of those rows); count_seconds as in count()."""
+        if row_stride < 1:
+            raise ValueError("row_stride must be >= 1")
+        secs = np.zeros(2, dtype=np.float64)
+        edges = ctypes.c_int64(0)
+        T = int(_load().oracle_count_forward_rows(self._h, order, row_stride, None, self.threads,
+                                                  secs.ctypes.data, ctypes.byref(edges)))
+        self.count_seconds = (float(secs[0]), float(secs[1]))
+        return T, int(edges.value)
 
     def forward_edge_counts(self, degree: str = "simple") -> np.ndarray:
         """The forward algorithm's per-edge intersection sizes (the list of

@@ -19,7 +19,8 @@
  *    keep each edge once, directed along a strict total order of the
  *    vertices, and intersect the two out-neighbour lists of every kept edge.
  *    oracle_count_forward_timed is the same with the wall time of its two
- *    stages (orientation + out-lists, intersections) reported.
+ *    stages (orientation + out-lists, intersections) reported;
+ *    oracle_count_forward_rows restricts the intersections to every k-th row.
  *  - oracle_forward_edge_counts: the per-edge intersection sizes of the
  *    forward algorithm (Algorithm 2), in canonical pair order.
  *  - oracle_vertex_triangles: t[v] by definition, the number of edges among
@@ -185,9 +186,13 @@ void oracle_graph_degrees(const void* h, int32_t* out) {
  * per_vertex (length n, may be NULL) receives t[v]: each thread adds its
  * matches into an array of its own, and the arrays are summed at the end.
  * seconds (may be NULL): [0] orientation and out-lists, [1] intersections.
+ * oracle_count_forward_rows runs the intersections of the rows u with
+ * u % row_stride == 0 only (the CPU baseline's bounded sample; stride 1 is
+ * the whole algorithm): it returns the triangles whose earliest vertex is such
+ * a u, and rows_edges (may be NULL) receives the kept edges of those rows.
  */
-uint64_t oracle_count_forward_timed(const void* h, int order_mode, uint64_t* per_vertex, int threads,
-                                    double* seconds) {
+uint64_t oracle_count_forward_rows(const void* h, int order_mode, int32_t row_stride, uint64_t* per_vertex,
+                                   int threads, double* seconds, int64_t* rows_edges) {
     const Graph* g = (const Graph*)h;
     const int32_t n = g->n;
     const int nth = pick_threads(threads);
@@ -223,6 +228,7 @@ uint64_t oracle_count_forward_timed(const void* h, int order_mode, uint64_t* per
         }
 #pragma omp for schedule(dynamic, 64) reduction(+ : total)
         for (int32_t u = 0; u < n; ++u) {
+            if (u % row_stride != 0) continue;
             const int32_t* nu = out_adj.data() + off[u];
             const int64_t du = off[u + 1] - off[u];
             for (int64_t p = 0; p < du; ++p) {
@@ -260,7 +266,17 @@ uint64_t oracle_count_forward_timed(const void* h, int order_mode, uint64_t* per
         seconds[0] = t1 - t0;
         seconds[1] = omp_get_wtime() - t1;
     }
+    if (rows_edges) {
+        int64_t c = 0;
+        for (int32_t u = 0; u < n; u += row_stride) c += off[u + 1] - off[u];
+        *rows_edges = c;
+    }
     return total;
+}
+
+uint64_t oracle_count_forward_timed(const void* h, int order_mode, uint64_t* per_vertex, int threads,
+                                    double* seconds) {
+    return oracle_count_forward_rows(h, order_mode, 1, per_vertex, threads, seconds, nullptr);
 }
 
 uint64_t oracle_count_forward(const void* h, int order_mode, uint64_t* per_vertex, int threads) {

@@ -368,3 +368,34 @@ def test_forward_per_vertex_thread_private_sums():
         T, t = oracle.Graph(e, n, threads=th).count(per_vertex=True)
         np.testing.assert_array_equal(t, ref)
         assert int(t.sum()) == 3 * T
+
+
+@pytest.mark.parametrize("stride", [1, 2, 3, 7])
+def test_forward_row_sample_counts_triangles_of_sampled_earliest_vertices(stride):
+    """The row-sampled forward count (the CPU baseline's bounded sample) finds exactly the
+    triangles whose earliest vertex in the (degree, id) order is a sampled row, by brute
+    force over triples; its edge total is the out-degrees of the sampled rows."""
+    import itertools
+    e = graphgen.erdos_renyi(36, 220, seed=40 + stride)
+    n = 36
+    g = oracle.Graph(e, n, threads=2)
+    deg = g.degrees()
+    adj = [set() for _ in range(n)]
+    for a, b in g.edges():
+        adj[a].add(b)
+        adj[b].add(a)
+    want = 0
+    for a, b, c in itertools.combinations(range(n), 3):
+        if b in adj[a] and c in adj[a] and c in adj[b]:
+            first = min((a, b, c), key=lambda x: (deg[x], x))
+            want += first % stride == 0
+    out_deg = np.zeros(n, dtype=np.int64)
+    for a, b in g.edges():
+        out_deg[a if (deg[a], a) < (deg[b], b) else b] += 1
+    T, edges = g.count_rows(stride)
+    assert T == want
+    assert edges == int(out_deg[::stride].sum())
+    if stride == 1:
+        assert T == g.count()
+    with pytest.raises(ValueError):
+        g.count_rows(0)
