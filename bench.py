@@ -6,11 +6,19 @@ validate/canonicalise, degree order, orient, radix sort -> CSR, de-duplicate,
 degree-pair buckets, kernel selection, tiles, intersection, reduction, count
 read back to the host. The input edge list is in HBM before timing starts.
 
-Default workload: R-MAT scale 20, edge factor 16 (a, b, c, d = 0.57, 0.19, 0.19,
-0.05), 16,777,216 raw draws over 1,048,576 vertices (random vertex permutation,
-random direction); the counted graph is its symmetrised, loop-free,
-de-duplicated version. Metric: Gedges/s = m / step time, m = unique undirected
-edges (= oriented edges intersected).
+Default workload: R-MAT scale 24, edge factor 16 (a, b, c, d = 0.57, 0.19, 0.19,
+0.05), 268,435,456 raw draws over 16,777,216 vertices (random vertex
+permutation, random direction); the counted graph is its symmetrised,
+loop-free, de-duplicated version. Metric: Gedges/s = m / step time, m = unique
+undirected edges (= oriented edges intersected).
+
+Beside the headline the line carries: the learned selector against the fixed
+thresholds on the same graph (alternating blocks of steps, so the spread of
+the ratio is stated), the latency of one count of an Erdos-Renyi G(4096, 32768)
+graph, the batch of 4096 Chung-Lu graphs in one call against 4096 separate
+calls (first call with graph capture reported apart from replays), and the
+CPU oracle timed on a bounded sample of the same graph at all cores and at one
+thread, stage by stage.
 
 Prints one JSON line (rank 0).
 """
@@ -144,21 +152,114 @@ def formulation_compare(tc, d_edges, n, T, steps, elems):
     return out
 
 
-def cpu_baseline(edges, n, m):
-    """The CPU oracle (forward algorithm, OpenMP) on the same graph, whole."""
+def _threads():
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+
+
+def cpu_oracle_leg(edges, n, threads, stride):
+    """The CPU oracle (forward algorithm, OpenMP) on this graph: canonicalisation,
+    degrees, orientation + out-lists whole; the intersections of every `stride`-th
+    row (by vertex id), scaled by `stride` for the whole graph's estimate."""
     import oracle
-    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    t0 = time.perf_counter()
     g = oracle.Graph(edges, n, threads=threads)
-    T = g.count()
-    dt = time.perf_counter() - t0
-    return {"value": m / dt / 1e9, "unit": "Gedges/s", "cores": threads, "kind": "oracle",
-            "sample": f"whole graph (canonicalise + CSR + count), {dt:.2f} s", "T": T}
+    canon_s, degree_s, adjacency_s = g.build_seconds
+    T_rows, rows_edges = g.count_rows(stride)
+    orient_s, isect_sample_s = g.count_seconds
+    m = g.m
+    isect_s = isect_sample_s * stride
+    total_s = canon_s + degree_s + orient_s + isect_s
+    return {"threads": threads, "row_stride": stride, "m": m,
+            "seconds": {"canonicalise": canon_s, "degrees": degree_s, "orient_csr": orient_s,
+                        "intersect_sample": isect_sample_s, "intersect_estimate": isect_s, "total_estimate": total_s,
+                        "symmetric_adjacency_excluded": adjacency_s},
+            "sample_rows_edges": rows_edges, "sample_triangles": T_rows,
+            "gedges_per_s": m / total_s / 1e9}
 
 
-def batch_bench(args, tc, autotune, sel):
+def cpu_baseline(edges, n, all_stride, one_stride, one_thread=True):
+    """The oracle timed on the host: all cores (the reported value) and one thread."""
+    threads = _threads()
+    allc = cpu_oracle_leg(edges, n, threads, all_stride)
+    def desc(k):
+        if k == 1:
+            return "oracle forward algorithm on the whole graph (canonicalise + CSR + count), single run"
+        return ("oracle forward algorithm on this graph: canonicalise (sort + unique), degrees, "
+                f"orientation + out-lists run whole; intersections of every {k}-th row by vertex id "
+                f"(ids randomly permuted), time x {k}; single run (the whole-graph run exceeds 60 s)")
+    out = {"value": allc["gedges_per_s"], "unit": "Gedges/s", "cores": threads, "kind": "oracle",
+           "sample": desc(all_stride), "stages_s": allc["seconds"], "row_stride": all_stride,
+           "sample_triangles": allc["sample_triangles"]}
+    if one_thread:
+        one = cpu_oracle_leg(edges, n, 1, one_stride)
+        out["one_thread"] = {"value": one["gedges_per_s"], "unit": "Gedges/s", "cores": 1,
+                             "sample": desc(one_stride), "stages_s": one["seconds"],
+                             "row_stride": one_stride}
+    return out
+
+
+def er_latency(tc, sel, calls=200):
+    """One count of Erdos-Renyi G(4096, 32768) (seed 1804): host-synchronised calls
+    back to back; latency-bound (a roofline fraction means nothing at this size)."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import oracle
+    e = graphgen.erdos_renyi(4096, 32768, seed=1804)
+    d = torch.from_numpy(e).to("cuda:0")
+    for _ in range(20):
+        T = tc.count_triangles(d, 4096, select=sel)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(calls):
+        t0 = time.perf_counter()
+        T = tc.count_triangles(d, 4096, select=sel)
+        times.append(time.perf_counter() - t0)
+    us = float(np.median(times) * 1e6)
+    cpu = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        Tc = oracle.count_triangles(e, 4096, threads=1)
+        cpu.append(time.perf_counter() - t0)
+    assert Tc == T, (Tc, T)
+    return {"workload": "er4096", "n": 4096, "m": 32768, "triangles": T, "us_per_count_median": us,
+            "us_per_count_min": float(min(times) * 1e6), "us_per_count_max": float(max(times) * 1e6),
+            "calls": calls, "gedges_per_s": 32768 / (us * 1e-6) / 1e9, "bound": "latency",
+            "roofline": "not meaningful (launch and synchronisation latency)",
+            "cpu_oracle_us_one_thread_median_of_3": float(np.median(cpu) * 1e6)}
+
+
+def learned_compare(tc, d_edges, n, T, steps, blocks=5):
+    """Heuristic and learned selection in alternating blocks of `steps` steps on the
+    same resident graph, counts asserted equal; the ratio of each block pair gives the
+    spread."""
+    import numpy as np
+    import torch
+    for _ in range(2):
+        assert tc.count_triangles(d_edges, n, select=tc.SELECT_LEARNED) == T
+    ms = {"heuristic": [], "learned": []}
+    for _ in range(blocks):
+        for name, sel in (("heuristic", tc.SELECT_HEURISTIC), ("learned", tc.SELECT_LEARNED)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                Tx = tc.count_triangles(d_edges, n, select=sel)
+            torch.cuda.synchronize()
+            ms[name].append((time.perf_counter() - t0) * 1e3 / max(steps, 1))
+            assert Tx == T, (name, Tx, T)
+    ratios = np.array(ms["heuristic"]) / np.array(ms["learned"])
+    return {"ms_per_step_learned": float(np.median(ms["learned"])),
+            "ms_per_step_heuristic": float(np.median(ms["heuristic"])),
+            "speedup": float(np.median(ms["heuristic"]) / np.median(ms["learned"])),
+            "block_ratios": [float(x) for x in ratios], "ratio_min": float(ratios.min()),
+            "ratio_max": float(ratios.max()), "blocks": blocks, "steps_per_block": steps,
+            "triangles_equal": True}
+
+
+def batch_compare(tc, autotune, sel, steps, warmup):
     """4096 Chung-Lu graphs (gamma 2.1, draws log-uniform in [1e3, 1e6], n_g = E_g / 8):
-    one batched call (captured graph replayed) against 4096 separate calls."""
+    one batched call (captured graph replayed) against 4096 separate calls; per-graph
+    counts asserted equal between the two forms."""
     import numpy as np
     import torch
 
@@ -167,16 +268,28 @@ def batch_bench(args, tc, autotune, sel):
     edges, off, nv = graphgen.chung_lu_batch(4096)
     d = torch.from_numpy(edges).to("cuda:0")
     tuned = autotune.apply_cached(sel, "cuda:0")
-    for _ in range(max(args.warmup, 1)):
+    # one direct (uncaptured) call first: the workspace and pinned buffers are allocated there
+    c_direct = tc.count_triangles_batch(d, off, nv, select=sel, graph=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()   # first captured call: capture + instantiate + launch
+    counts = tc.count_triangles_batch(d, off, nv, select=sel)
+    ms_first = (time.perf_counter() - t0) * 1e3
+    assert np.array_equal(c_direct, counts)
+    for _ in range(max(warmup, 1)):
         counts = tc.count_triangles_batch(d, off, nv, select=sel)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         counts = tc.count_triangles_batch(d, off, nv, select=sel)
     torch.cuda.synchronize()
-    ms_batch = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    ms_batch = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+    t0 = time.perf_counter()   # the same batch without capture (kernels launched directly)
+    for _ in range(steps):
+        c_direct = tc.count_triangles_batch(d, off, nv, select=sel, graph=False)
+    ms_direct = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+    assert np.array_equal(c_direct, counts)
     m = tc.last_stats("cuda:0")["m"]
-    print(f"[bench] batched: {ms_batch:.2f} ms/step, union m={m}", file=sys.stderr, flush=True)
+    print(f"[bench] batched: first {ms_first:.1f} ms, replay {ms_batch:.2f} ms, m={m}", file=sys.stderr, flush=True)
     # the same graphs through 4096 plain calls (one warm pass, then one timed pass), with the
     # default tile shapes (the tuned ones are for the batch's union graph)
     tc.set_tile_shapes(device="cuda:0")
@@ -188,7 +301,6 @@ def batch_bench(args, tc, autotune, sel):
             sep[g] = tc.count_triangles(d[off[g]:off[g + 1]], int(nv[g]), select=sel)
         torch.cuda.synchronize()
         ms_sep = (time.perf_counter() - t1) * 1e3
-        print(f"[bench] separate pass {rep}: {ms_sep:.1f} ms", file=sys.stderr, flush=True)
     assert np.array_equal(sep, counts), "batched and separate counts differ"
     # the same 4096 calls queued without host synchronisation (one workspace, one result slot each)
     ws = torch.empty(max(tc.workspace_size(int(off[g + 1] - off[g]), int(nv[g]), sel) for g in range(nv.size)),
@@ -201,24 +313,20 @@ def batch_bench(args, tc, autotune, sel):
             tc.count_triangles_async(d[off[g]:off[g + 1]], int(nv[g]), result=res[g], select=sel, workspace=ws)
         torch.cuda.synchronize()
         ms_async = (time.perf_counter() - t1) * 1e3
-        print(f"[bench] async-queued pass {rep}: {ms_async:.1f} ms", file=sys.stderr, flush=True)
     r = res.cpu().numpy()
     assert np.all(r[:, 1] == 0) and np.array_equal(r[:, 0].astype(np.uint64), counts), "async counts differ"
-    result = {
-        "metric": METRIC, "value": m / (ms_batch * 1e-3) / 1e9, "unit": "Gedges/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batch, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "clbatch", "graphs": int(nv.size), "gamma": 2.1, "draws_loguniform": [1e3, 1e6],
-                   "raw_pairs": int(edges.shape[0]), "n": int(nv.astype(np.int64).sum()), "m": m,
-                   "triangles": int(counts.astype(np.int64).sum()), "select": args.select,
-                   "autotuned_tiles": bool(tuned)},
-        "roofline": None,
-        "batched_vs_separate": {"ms_batched": ms_batch, "ms_separate_4096_calls": ms_sep,
-                                "speedup": ms_sep / ms_batch, "ms_async_queued_4096_calls": ms_async,
-                                "speedup_vs_async": ms_async / ms_batch},
-    }
-    print(json.dumps(result), flush=True)
-    return 0
+    if tuned:
+        tc.set_tile_shapes(device="cuda:0")
+    del d, ws
+    torch.cuda.synchronize()
+    return {"workload": "clbatch", "graphs": int(nv.size), "raw_pairs": int(edges.shape[0]), "m": m,
+            "triangles": int(counts.astype(np.int64).sum()), "autotuned_tiles": bool(tuned),
+            "ms_batched_replay": ms_batch, "ms_batched_first_call_with_capture": ms_first,
+            "ms_batched_without_capture": ms_direct,
+            "ms_separate_4096_calls": ms_sep, "ms_async_queued_4096_calls": ms_async,
+            "speedup": ms_sep / ms_batch, "speedup_first_call": ms_sep / ms_first,
+            "speedup_vs_async": ms_async / ms_batch, "gedges_per_s_batched": m / (ms_batch * 1e-3) / 1e9,
+            "counts_equal": True}
 
 
 def main(argv=None):
@@ -226,12 +334,19 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rmat20", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat24", choices=sorted(WORKLOADS))
     ap.add_argument("--select", default="heuristic", choices=["heuristic", "learned", "merge", "bsearch", "bitmap"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-one-thread", action="store_true", help="CPU baseline at all cores only")
+    ap.add_argument("--cpu-stride", type=int, default=0,
+                    help="CPU baseline: intersect every k-th row at all cores (0: by graph size)")
+    ap.add_argument("--cpu-one-thread-stride", type=int, default=0,
+                    help="CPU baseline: intersect every k-th row at one thread (0: by graph size)")
     ap.add_argument("--no-check", action="store_true", help="skip the oracle equality check")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-selector comparison (profiling runs: one selection mode only)")
+    ap.add_argument("--no-latency", action="store_true", help="skip the ER G(4096, 32768) latency")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-separate comparison")
     ap.add_argument("--formulations", action="store_true",
                     help="also time the full-list and matrix formulations on the same graph")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -242,7 +357,6 @@ def main(argv=None):
               f"(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     import __graft_entry__
@@ -264,7 +378,17 @@ def main(argv=None):
         torch.cuda.synchronize()
         del src, dst
     if args.workload == "clbatch":
-        return batch_bench(args, tc, autotune, sel)
+        b = batch_compare(tc, autotune, sel, args.steps, args.warmup)
+        result = {
+            "metric": METRIC, "value": b["gedges_per_s_batched"], "unit": "Gedges/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["ms_batched_replay"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "clbatch", "graphs": b["graphs"], "gamma": 2.1, "draws_loguniform": [1e3, 1e6],
+                       "raw_pairs": b["raw_pairs"], "m": b["m"], "triangles": b["triangles"],
+                       "select": args.select},
+            "roofline": None, "batched_vs_separate": b}
+        print(json.dumps(result), flush=True)
+        return 0
     print(f"[bench] workload={args.workload} generating", file=sys.stderr, flush=True)
     edges, n, spec = make_graph(args.workload)
     d_edges = torch.from_numpy(edges).to("cuda:0")
@@ -323,37 +447,40 @@ def main(argv=None):
         "roofline": {"bound": "hbm", "kernel": f"k_isect_{dom}", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": counted_traffic(f"k_isect_{dom}", args.workload),
-                     "algorithmic_bytes": kbytes[dom], "avg_launch_ms": dom_ms},
+                     "algorithmic_bytes": kbytes[dom], "avg_launch_ms": dom_ms,
+                     "launch_ms_from": "HIP events at the stage boundaries, K steps after the timed region"},
         "stages_ms": stages,
         "intersect_gedges_per_s": m / (isect_ms * 1e-3) / 1e9 if isect_ms > 0 else None,
         "tail_elements": tail_sum,
-        "effective_gbps_merge_formulation": balg / (isect_ms * 1e-3) / 1e9 if isect_ms > 0 else None,
+        # what a per-edge merge of whole out-lists would read (4(m + S) + 16 m + 8(n + 1)
+        # bytes); this path reads only the tails and each N+(v) once per tile, so this is
+        # a size of work, not a bandwidth
+        "merge_formulation_bytes": balg,
     }
     if have_weights and args.select == "heuristic" and not args.no_learned:
-        # the learned selector against the heuristic on the same graph, counts equal
-        for _ in range(2):
-            T_l = tc.count_triangles(d_edges, n, select=tc.SELECT_LEARNED)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            T_l = tc.count_triangles(d_edges, n, select=tc.SELECT_LEARNED)
-        torch.cuda.synchronize()
-        ms_l = (time.perf_counter() - t1) * 1e3 / max(args.steps, 1)
-        assert T_l == T, (T_l, T)
-        result["learned_vs_heuristic"] = {"ms_per_step_learned": ms_l, "ms_per_step_heuristic": ms_per_step,
-                                          "speedup": ms_per_step / ms_l}
+        print("[bench] learned vs heuristic", file=sys.stderr, flush=True)
+        result["learned_vs_heuristic"] = learned_compare(tc, d_edges, n, T, args.steps)
     if args.formulations and args.select == "heuristic":
         print("[bench] full-list and matrix formulations", file=sys.stderr, flush=True)
         forms = formulation_compare(tc, d_edges, n, T, args.steps, elems)
         forms["filtered"] = {"ms_per_step": ms_per_step, "isect_ms": isect_ms, "sum": T,
                              "streamed_elements": elems["filtered"]}
         result["formulations"] = forms
+    del d_edges
+    torch.cuda.synchronize()
+    if not args.no_latency:
+        print("[bench] ER G(4096, 32768) latency", file=sys.stderr, flush=True)
+        result["er4096_latency"] = er_latency(tc, sel)
+    if not args.no_batch and args.select in ("heuristic", "learned"):
+        result["batched_vs_separate"] = batch_compare(tc, autotune, sel, 3, 1)
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cb = cpu_baseline(edges, n, m)
-        if not args.no_check:
-            assert cb["T"] == T, f"GPU count {T} != oracle {cb['T']}"
-        cb.pop("T")
+        big = m > (1 << 26)
+        all_stride = args.cpu_stride or (4 if big else 1)
+        one_stride = args.cpu_one_thread_stride or (256 if big else 16)
+        print(f"[bench] cpu baseline (oracle), row strides {all_stride} / {one_stride}", file=sys.stderr, flush=True)
+        cb = cpu_baseline(edges, n, all_stride, one_stride, one_thread=not args.no_cpu_one_thread)
+        if all_stride == 1 and not args.no_check:   # the whole graph was counted: same T
+            assert cb["sample_triangles"] == T, f"GPU count {T} != oracle {cb['sample_triangles']}"
         result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
     return 0
