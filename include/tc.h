@@ -331,6 +331,24 @@ tc_status tc_profile_selected(tc_ctx* ctx, const int32_t* d_edges, int64_t num_e
                               void* d_workspace, size_t workspace_bytes, const tc_options* opts, int32_t repeats,
                               float* h_ms);
 
+/*
+ * Timing data for training the selector inside the combined launch: the
+ * pipeline runs up to the tile layout with the caller's choice per bucket,
+ * then the whole intersection stage (the three kernels over their tile
+ * ranges, as a counting call launches them, and the reduction of T) runs
+ * `repeats` (1..64) times. h_choice [256] (host): strategy per degree-pair
+ * bucket (0 merge path, 1 binary search, 2 LDS bitmap; any other value: the
+ * fixed thresholds' choice); h_chunk [256] (host) or NULL: in-edges per tile
+ * per bucket (0: the default rule; clamped as for tc_set_tile_shapes).
+ * h_ms [4] receives the medians, in milliseconds, of the stage (the sum of the
+ * three kernels) and of each kernel; h_count (optional) receives T from the
+ * last repeat. A bucket's cost is read from the change in the stage time when
+ * only its entry changes. Uses the same workspace as tc_count_triangles.
+ */
+tc_status tc_profile_choices(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                             void* d_workspace, size_t workspace_bytes, const uint8_t* h_choice,
+                             const uint16_t* h_chunk, int32_t repeats, float* h_ms, uint64_t* h_count);
+
 /* Load float32 master parameters (host); resets the Adam state and enables
  * TC_SELECT_LEARNED on this context. */
 tc_status tc_selector_set_params(tc_ctx* ctx, const float* h_params);

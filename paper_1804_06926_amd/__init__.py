@@ -30,6 +30,7 @@ from ._lib import (  # noqa: F401
     list_triangles,
     library_path,
     profile_buckets,
+    profile_choices,
     profile_selected,
     radix_sort_u64,
     selector_forward,

@@ -530,6 +530,35 @@ def profile_buckets(edges, num_vertices: int, repeats: int = 5, workspace=None):
     return ms, feat
 
 
+def profile_choices(edges, num_vertices: int, choice, chunk=None, repeats: int = 5, workspace=None):
+    """The intersection stage as a counting call launches it, with the given strategy per
+    bucket (choice uint8 [256]: 0 merge, 1 binary search, 2 bitmap, other = the fixed
+    thresholds' choice) and optional in-edges per tile (chunk uint16 [256], 0 = default).
+    Returns (median ms of the stage, median ms per kernel [3], T)."""
+    import numpy as np
+    e = _edges_arg(edges)
+    ctx, idx = _ctx(e.device)
+    E = e.shape[0]
+    ws = _workspace(idx, workspace_size(E, num_vertices), workspace)
+    ch = np.ascontiguousarray(choice, dtype=np.uint8)
+    if ch.shape != (256,):
+        raise ValueError("choice must have 256 entries")
+    ck = None if chunk is None else np.ascontiguousarray(chunk, dtype=np.uint16)
+    if ck is not None and ck.shape != (256,):
+        raise ValueError("chunk must have 256 entries")
+    ms = np.zeros(4, dtype=np.float32)
+    T = ctypes.c_uint64(0)
+    lib = _load()
+    vp = ctypes.c_void_p
+    lib.tc_profile_choices.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_size_t, vp, vp,
+                                       ctypes.c_int32, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_uint64)]
+    lib.tc_profile_choices.restype = ctypes.c_int
+    _check(lib.tc_profile_choices(ctx, e.data_ptr() if E else None, E, num_vertices, ws.data_ptr(), ws.numel(),
+                                  ch.ctypes.data, ck.ctypes.data if ck is not None else None, repeats, _fptr(ms),
+                                  ctypes.byref(T)), ctx)
+    return float(ms[0]), ms[1:].astype(float), int(T.value)
+
+
 # ---------------------------------------------------------------- batched counting, tile shapes
 F_NO_GRAPH = 0x2
 

@@ -23,6 +23,8 @@ struct tc_ctx {
     int learned_ready = 0;
     uint16_t* d_chunk = nullptr;          // device [256] tile-size overrides (0 = default)
     uint8_t* d_group = nullptr;           // device [256] lanes-per-edge overrides (0 = default)
+    uint8_t* d_given = nullptr;           // device [256] caller-chosen kernels (tc_profile_choices)
+    uint16_t* d_given_chunk = nullptr;    // device [256] caller-chosen tile sizes (tc_profile_choices)
     int grid_override[tcx::NKERNEL] = {0, 0, 0};
     // selector network: float32 master, Adam moments, gradient, bf16 compute copy,
     // and the per-sample training buffers (allocated on first use)
@@ -39,10 +41,9 @@ struct tc_ctx {
     hipStream_t own_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
-    struct {
+    struct {   // sizes and workspace of the captured batch (the edge list is read through the workspace)
         int64_t E, N;
         int32_t G, select;
-        const void* edges;
         const void* ws;
     } graph_key = {};
     uint64_t* h_counts_pinned = nullptr;
@@ -123,7 +124,7 @@ tc_status run(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* w
     ra.select = sel;
     ra.mlp = ctx->learned_ready ? ctx->d_cw : nullptr;
     ra.learned = ctx->d_learned;
-    ra.chunk_override = ctx->d_chunk;
+    if (!ra.chunk_override) ra.chunk_override = ctx->d_chunk;
     ra.group_override = ctx->d_group;
     ra.grid_override = ctx->grid_override;
     ra.events = timing ? ctx->events : nullptr;
@@ -189,6 +190,8 @@ tc_status tc_create(tc_ctx** out, int device, void* hip_stream) {
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_learned, tcx::NBUCKET);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_chunk, sizeof(uint16_t) * tcx::NBUCKET);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_group, tcx::NBUCKET);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_given, tcx::NBUCKET);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_given_chunk, sizeof(uint16_t) * tcx::NBUCKET);
     if (e == hipSuccess) e = hipMemset(ctx->d_chunk, 0, sizeof(uint16_t) * tcx::NBUCKET);
     if (e == hipSuccess) e = hipMemset(ctx->d_group, 0, tcx::NBUCKET);
     const size_t np = sizeof(float) * tcx::MLP_NPARAM;
@@ -216,6 +219,8 @@ tc_status tc_destroy(tc_ctx* ctx) {
         if (ctx->d_learned) (void)hipFree(ctx->d_learned);
         if (ctx->d_chunk) (void)hipFree(ctx->d_chunk);
         if (ctx->d_group) (void)hipFree(ctx->d_group);
+        if (ctx->d_given) (void)hipFree(ctx->d_given);
+        if (ctx->d_given_chunk) (void)hipFree(ctx->d_given_chunk);
         float* bufs[] = {ctx->d_master, ctx->d_adam_m, ctx->d_adam_v, ctx->d_grad, ctx->d_loss, ctx->d_acts};
         for (float* p : bufs)
             if (p) (void)hipFree(p);
@@ -533,9 +538,12 @@ tc_status tc_count_triangles_batch(tc_ctx* ctx, const int32_t* d_edges, const in
         ctx->h_counts_cap = (size_t)num_graphs;
     }
     char* ws = (char*)d_workspace;
-    // graph descriptions go to the device outside any captured graph
-    e = hipMemcpyAsync(ws + B.eoff, h_edge_offsets, sizeof(int64_t) * ((size_t)num_graphs + 1),
-                       hipMemcpyHostToDevice, s);
+    // graph descriptions and the edge list's address go to the device outside any
+    // captured graph (the copies read pageable host memory before they return)
+    e = hipMemcpyAsync(ws + B.eptr, &d_edges, sizeof(void*), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ws + B.eoff, h_edge_offsets, sizeof(int64_t) * ((size_t)num_graphs + 1),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ws + B.voff, voff.data(), sizeof(int64_t) * voff.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -554,7 +562,7 @@ tc_status tc_count_triangles_batch(tc_ctx* ctx, const int32_t* d_edges, const in
     tcx::BatchArgs ba = {d_edges, E, N, num_graphs};
     const bool same = ctx->graph_exec && ctx->graph_key.E == E && ctx->graph_key.N == N &&
                       ctx->graph_key.G == num_graphs && ctx->graph_key.select == sel &&
-                      ctx->graph_key.edges == d_edges && ctx->graph_key.ws == d_workspace;
+                      ctx->graph_key.ws == d_workspace;
     if (capture && !same) {
         if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
         if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
@@ -567,7 +575,7 @@ tc_status tc_count_triangles_batch(tc_ctx* ctx, const int32_t* d_edges, const in
         if (le != hipSuccess) e = le;
         if (e == hipSuccess) e = hipGraphInstantiate(&ctx->graph_exec, ctx->graph, nullptr, nullptr, 0);
         if (e != hipSuccess) return hip_fail(ctx, e, "capture batch");
-        ctx->graph_key = {E, N, num_graphs, sel, d_edges, d_workspace};
+        ctx->graph_key = {E, N, num_graphs, sel, d_workspace};
     }
     if (capture) e = hipGraphLaunch(ctx->graph_exec, s);
     else e = tcx::run_batch(ba, ra);
@@ -667,6 +675,55 @@ tc_status tc_profile_selected(tc_ctx* ctx, const int32_t* d_edges, int64_t num_e
     if (num_edges == 0) return TC_OK;
     return profile_pass(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes,
                         opts ? opts->select : TC_SELECT_HEURISTIC, repeats, h_ms, false, nullptr);
+}
+
+tc_status tc_profile_choices(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                             void* d_workspace, size_t workspace_bytes, const uint8_t* h_choice,
+                             const uint16_t* h_chunk, int32_t repeats, float* h_ms, uint64_t* h_count) {
+    if (!ctx || !h_choice || !h_ms || repeats < 1 || repeats > 64)
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "bad arguments");
+    for (int i = 0; i < 1 + tcx::NKERNEL; ++i) h_ms[i] = 0.f;
+    if (h_count) *h_count = 0;
+    if (num_edges == 0) return TC_OK;
+    DeviceGuard guard(ctx->device);
+    std::vector<uint16_t> chunk(tcx::NBUCKET, 0);
+    if (h_chunk) memcpy(chunk.data(), h_chunk, sizeof(uint16_t) * tcx::NBUCKET);
+    hipError_t e = hipMemcpy(ctx->d_given, h_choice, tcx::NBUCKET, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(ctx->d_given_chunk, chunk.data(), sizeof(uint16_t) * tcx::NBUCKET, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy choices");
+    tc_options o = {};
+    tcx::RunArgs ra = {};
+    ra.stop_before_isect = 1;
+    ra.given = ctx->d_given;
+    ra.chunk_override = ctx->d_given_chunk;
+    tc_status st = run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, &o, ra);
+    if (st != TC_OK) return st;
+    std::vector<float> ms[1 + tcx::NKERNEL];
+    for (int r = 0; r < repeats; ++r) {
+        e = tcx::launch_isect_stage(ra, ctx->events);
+        if (e == hipSuccess) e = hipEventSynchronize(ctx->events[tcx::NKERNEL]);
+        float tot = 0.f;
+        for (int k = 0; k < tcx::NKERNEL && e == hipSuccess; ++k) {
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, ctx->events[k], ctx->events[k + 1]);
+            ms[1 + k].push_back(t);
+            tot += t;
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "profile intersection stage");
+        ms[0].push_back(tot);
+    }
+    for (int i = 0; i < 1 + tcx::NKERNEL; ++i) {
+        std::sort(ms[i].begin(), ms[i].end());
+        h_ms[i] = ms[i][ms[i].size() / 2];
+    }
+    e = hipMemcpyAsync(ctx->h_ctrl, (char*)d_workspace + tcx::make_layout(num_edges, num_vertices).ctrl,
+                       sizeof(tcx::Ctrl), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "read control block");
+    if (ctx->h_ctrl->err) return arg_fail(ctx, TC_ERR_HIP, "internal bound violated");
+    if (h_count) *h_count = ctx->h_ctrl->total;
+    return TC_OK;
 }
 
 static tc_status ensure_acts(tc_ctx* ctx) {

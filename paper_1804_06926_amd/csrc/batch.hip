@@ -17,8 +17,10 @@ constexpr int BT_NT = 256;
 constexpr int BT_EDGES_PER_BLOCK = 4096;
 
 // Local pair -> union pair; ids outside [0, n_g) become (-1, -1), which the
-// pipeline reports as out of range and drops.
-__global__ __launch_bounds__(BT_NT) void k_union_edges(const int2* __restrict__ edges, uint64_t E,
+// pipeline reports as out of range and drops. The caller's edge list is read
+// through a pointer held in the workspace (written before each launch), so a
+// captured graph serves any edge buffer of the same sizes.
+__global__ __launch_bounds__(BT_NT) void k_union_edges(const int2* const* __restrict__ edges_at, uint64_t E,
                                                        const int64_t* __restrict__ eoff, int32_t G,
                                                        const int32_t* __restrict__ nv,
                                                        const int64_t* __restrict__ voff, int2* __restrict__ out) {
@@ -35,6 +37,7 @@ __global__ __launch_bounds__(BT_NT) void k_union_edges(const int2* __restrict__ 
         s_g0 = lo;
     }
     __syncthreads();
+    const int2* __restrict__ edges = *edges_at;
     int32_t g = s_g0;
     const uint64_t c1 = c0 + BT_EDGES_PER_BLOCK < E ? c0 + BT_EDGES_PER_BLOCK : E;
     for (uint64_t i = c0 + threadIdx.x; i < c1; i += BT_NT) {
@@ -73,6 +76,7 @@ BatchLayout make_batch_layout(int64_t E, int64_t N, int32_t G) {
     size_t o = B.pipe.total;
     auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + (bytes ? bytes : 1), 256); return r; };
     B.union_edges = take(8 * (size_t)E);
+    B.eptr = take(sizeof(void*));
     B.eoff = take(8 * ((size_t)G + 1));
     B.voff = take(8 * ((size_t)G + 1));
     B.nv = take(4 * (size_t)G);
@@ -88,7 +92,8 @@ hipError_t run_batch(const BatchArgs& b, RunArgs& r) {
     int2* uedges = (int2*)(ws + B.union_edges);
     const unsigned nblk = (unsigned)((b.E + BT_EDGES_PER_BLOCK - 1) / BT_EDGES_PER_BLOCK);
     if (b.E > 0)
-        hipLaunchKernelGGL(k_union_edges, dim3(nblk), dim3(BT_NT), 0, r.stream, (const int2*)b.edges, (uint64_t)b.E,
+        hipLaunchKernelGGL(k_union_edges, dim3(nblk), dim3(BT_NT), 0, r.stream, (const int2* const*)(ws + B.eptr),
+                           (uint64_t)b.E,
                            (const int64_t*)(ws + B.eoff), b.G, (const int32_t*)(ws + B.nv),
                            (const int64_t*)(ws + B.voff), uedges);
     r.edges = (const int32_t*)uedges;

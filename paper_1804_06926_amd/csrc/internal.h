@@ -30,6 +30,12 @@ int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t*
 // Keys per tile of a sort of cap keys of key_bytes bytes (2048, 4096 or 8192;
 // a multiple of 2048).
 uint32_t radix_tile_keys(size_t cap, int key_bytes);
+// One stable radix pass of 64-bit keys on bits [shift, shift + bits), bits <= 8,
+// from kin to kout (the two must differ); with rank set, the low 32 bits of each
+// key, a vertex id, are replaced by rank[id] as the key moves (0xFFFFFFFF for
+// ids outside [0, n)); the pass's digit must lie in the high half then.
+void radix_pass_u64(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const uint32_t* rank,
+                    int32_t n, void* temp, hipStream_t s);
 struct RadixDigit {
     int shift;
     uint32_t mask;

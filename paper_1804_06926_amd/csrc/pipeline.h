@@ -40,6 +40,8 @@ struct RunArgs {
     int select;
     const void* mlp;                 // device MlpCompute (selector network), or null
     uint8_t* learned;                // device [256] kernel per bucket written by the network
+    const uint8_t* given;            // device [256] kernel per bucket chosen by the caller (values
+                                     // >= NKERNEL: the heuristic's), or null; overrides select
     int stop_before_isect;           // leave after the tiles are laid out (bucket profiling)
     const uint16_t* chunk_override;  // device [256] or null
     const uint8_t* group_override;   // device [256] or null
@@ -76,13 +78,14 @@ void publish_result(const Ctrl* ctrl, uint64_t* result, uint64_t range_status, u
 // ---- batched counting (batch.hip)
 struct BatchLayout {
     Layout pipe;   // the union graph's pipeline workspace comes first
-    size_t union_edges, eoff, voff, nv, middle, counts;
+    size_t union_edges, eptr, eoff, voff, nv, middle, counts;
     size_t total;
 };
 BatchLayout make_batch_layout(int64_t E, int64_t N, int32_t G);
 
 struct BatchArgs {
-    const int32_t* edges;   // device [E][2], graph-local ids, graphs in order
+    const int32_t* edges;   // device [E][2], graph-local ids, graphs in order (its address is
+                            // copied to the workspace's eptr slot before the launch)
     int64_t E;              // total pairs
     int64_t N;              // total vertices
     int32_t G;              // graphs
@@ -102,6 +105,11 @@ size_t list_extra_bytes(int64_t E);
 size_t sym_extra_bytes(int64_t E, int32_t n);
 // After a run with stop_before_isect: one intersection kernel over tiles [t0, t1).
 hipError_t launch_isect_range(const RunArgs& r, int ker, uint32_t t0, uint32_t t1);
+// After a run with stop_before_isect: the whole intersection stage as the pipeline
+// launches it (the three kernels over their tile ranges, then the reduction of T
+// into the control block); ev (null, or 4 events) is recorded before the first
+// kernel and after each.
+hipError_t launch_isect_stage(const RunArgs& r, hipEvent_t* ev);
 int stage_count();
 const char* stage_name(int s);
 

@@ -281,6 +281,58 @@ __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, u
     }
 }
 
+// Orientation of pairs already partitioned on their ids' high bits. Past 2^21
+// vertices the rank table (4 bytes per vertex) outgrows an XCD's 4 MB L2, and two
+// random rank gathers per pair cost two cache lines from beyond it. Instead the
+// pairs pass through two stable radix passes (radix_pass_u64): one on the high
+// bits of the first id, one on the high bits of the second that also replaces the
+// first id by its rank as the pair moves; the blocks of a pass then look up ranks
+// in a few 2^(vbits - 8)-id ranges at a time, which stay in L2. This kernel reads
+// (second id << 32 | rank of the first id), grouped by the second id's high bits,
+// looks up the second rank and writes the oriented key in place.
+constexpr int ORIENT_PART_MIN_BITS = 21;
+template <int U>
+__global__ __launch_bounds__(NT) void k_orient_ranked(uint64_t* __restrict__ keys, uint64_t E, int32_t n,
+                                                      const uint32_t* __restrict__ rank, int nb, uint64_t sentinel,
+                                                      uint32_t* __restrict__ counts, uint32_t ntiles,
+                                                      uint32_t tile_keys, RadixDigit dg) {
+    __shared__ TileCounts tc;
+    tc.clear();
+    __syncthreads();
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+      for (uint32_t r = 0; r < tile_keys; r += U * NT) {
+        const uint64_t i0 = (uint64_t)tile * tile_keys + r + threadIdx.x;
+        uint64_t kk[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const uint64_t i = i0 + (uint64_t)k * NT;
+            kk[k] = i < E ? keys[i] : ~0ull;
+        }
+        uint32_t ra[U], rb[U];
+        bool ok[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int32_t b = (int32_t)(uint32_t)(kk[k] >> 32);
+            ra[k] = (uint32_t)kk[k];
+            ok[k] = ra[k] != 0xFFFFFFFFu && b >= 0 && b < n;
+            rb[k] = rank[ok[k] ? b : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const uint64_t i = i0 + (uint64_t)k * NT;
+            if (i < E) {
+                const bool good = ok[k] && ra[k] != rb[k];   // equal ranks: a self-loop
+                const uint32_t lo = ra[k] < rb[k] ? ra[k] : rb[k], hi = ra[k] < rb[k] ? rb[k] : ra[k];
+                const uint64_t key = good ? (((uint64_t)lo << nb) | hi) : sentinel;
+                keys[i] = key;
+                if (counts) tc.add((uint32_t)(key >> dg.shift) & dg.mask);
+            }
+        }
+      }
+        if (counts) tc.flush(counts, ntiles, tile);
+    }
+}
+
 // ------------------------------------------------------------------ unique + CSR
 // The sorted pair keys in runs of equal keys: the first of each run is kept,
 // sentinel keys (loops, invalid ids; they sort last) are dropped. Each block
@@ -985,6 +1037,21 @@ static uint64_t* csc_of(const RunArgs& r, const Layout& L) {
     return (p2 & 1) ? sorted : other;
 }
 
+hipError_t launch_isect_stage(const RunArgs& r, hipEvent_t* ev) {
+    const Layout L = make_layout(r.E, r.n);
+    const IsectArgs ia = isect_args(r, L, csc_of(r, L));
+    uint64_t* partials = (uint64_t*)((char*)r.ws + L.isect_partials);
+    const int order[NKERNEL] = {KER_MERGE, KER_BSEARCH, KER_BITMAP};
+    if (ev) (void)hipEventRecord(ev[0], r.stream);
+    for (int q = 0; q < NKERNEL; ++q) {
+        const int k = order[q];
+        launch_isect(k, ia, r.grid_override ? r.grid_override[k] : 0, partials, r.stream);
+        if (ev) (void)hipEventRecord(ev[1 + q], r.stream);
+    }
+    launch_reduce_total(partials, ia.ctrl, r.stream);
+    return hipGetLastError();
+}
+
 hipError_t run_list_pass(const RunArgs& r) {
     const Layout L = make_layout(r.E, r.n);
     const IsectArgs ia = isect_args(r, L, csc_of(r, L));
@@ -1116,7 +1183,20 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     const uint64_t sentinel = (2 * nb >= 64) ? ~0ull : ((1ull << (2 * nb)) - 1ull);
     const uint32_t e_tile = radix_tile_keys((size_t)E, 8);
     const uint32_t e_tiles = (uint32_t)(((uint64_t)E + e_tile - 1) / e_tile);
-    if (e_tile % (16 * NT) == 0)
+    if (vbits >= ORIENT_PART_MIN_BITS) {
+        // pairs by their first id's high bits, then by their second's (first id -> rank)
+        const int ob = 8;
+        radix_pass_u64((const uint64_t*)edges, keysB, (size_t)E, vbits - ob, ob, nullptr, n, radix_tmp, s);
+        radix_pass_u64(keysB, keysA, (size_t)E, 32 + vbits - ob, ob, rank, n, radix_tmp, s);
+        if (e_tile % (16 * NT) == 0)
+            hipLaunchKernelGGL(k_orient_ranked<16>, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, keysA,
+                               (uint64_t)E, n, rank, nb, sentinel, radix_first_counts(radix_tmp), e_tiles, e_tile,
+                               radix_first_digit(0, 2 * nb));
+        else
+            hipLaunchKernelGGL(k_orient_ranked<OR_U>, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s,
+                               keysA, (uint64_t)E, n, rank, nb, sentinel, radix_first_counts(radix_tmp), e_tiles,
+                               e_tile, radix_first_digit(0, 2 * nb));
+    } else if (e_tile % (16 * NT) == 0)
         hipLaunchKernelGGL(k_orient<16>, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, edges,
                            (uint64_t)E, n, rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, e_tile,
                            radix_first_digit(0, 2 * nb));
@@ -1193,11 +1273,12 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     const uint32_t* mcol = (r.formulation == FORM_FULL || r.formulation == FORM_MATRIX) ? sym_col(r, L) : col;
     hipLaunchKernelGGL(k_vbucket, dim3(grid_for((size_t)n, 2048)), dim3(NT), 0, s, moff, mcol, inoff, n, vbucket,
                        ctrl);
-    const bool learned = r.select == SEL_LEARNED && r.mlp && r.learned;
+    const bool learned = !r.given && r.select == SEL_LEARNED && r.mlp && r.learned;
     if (learned) mlp_select((const MlpCompute*)r.mlp, ctrl, r.learned, s);
     else bucket_features_launch(ctrl, s);
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(NBUCKET), 0, s, ctrl, r.select, learned ? r.learned : nullptr,
-                       r.chunk_override, r.group_override, r.formulation != FORM_FILTERED ? 1 : 0);
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(NBUCKET), 0, s, ctrl, r.given ? (int)SEL_LEARNED : r.select,
+                       r.given ? r.given : (learned ? r.learned : nullptr), r.chunk_override, r.group_override,
+                       r.formulation != FORM_FILTERED ? 1 : 0);
     mark(7);
     // ---- group: order vertices by (kernel, bucket); tiles
     hipLaunchKernelGGL(k_vkeys_slot, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vbucket, n, ctrl, vkeysA);

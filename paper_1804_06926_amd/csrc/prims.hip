@@ -329,17 +329,36 @@ __global__ __launch_bounds__(RS_NT) void k_radix_rowfix(uint32_t* __restrict__ h
     for (uint32_t i = s0 + threadIdx.x; i < s1; i += RS_NT) row[i] += carry;
 }
 
+// Keys move unchanged.
+struct XfIdentity {
+    template <typename KeyT>
+    __device__ __forceinline__ KeyT operator()(KeyT k) const { return k; }
+};
+// 64-bit keys whose low 32 bits are a vertex id: the id is replaced by its rank
+// (ids outside [0, n): 0xFFFFFFFF) as the key moves; the high half, which holds
+// the digit of the pass, is unchanged.
+struct XfRankLow {
+    const uint32_t* rank;
+    int32_t n;
+    __device__ __forceinline__ uint64_t operator()(uint64_t k) const {
+        const int32_t a = (int32_t)(uint32_t)k;
+        const uint32_t r = (a >= 0 && a < n) ? rank[a] : 0xFFFFFFFFu;
+        return (k & 0xFFFFFFFF00000000ull) | r;
+    }
+};
+
 // NT_ threads of RS_ITEMS keys each: 8192-key tiles run 512 threads of 16 keys
 // (half the registers per lane of 256 x 32, twice the waves per CU); threads
-// 0..255 own the digits in the per-digit scans.
-template <typename KeyT, bool HAS_VAL, int RS_ITEMS, int NT_ = RS_NT>
+// 0..255 own the digits in the per-digit scans. Each key passes through xf as it
+// is loaded (the transform must leave the digit of the pass unchanged).
+template <typename KeyT, bool HAS_VAL, int RS_ITEMS, int NT_ = RS_NT, typename XF = XfIdentity>
 __global__ __launch_bounds__(NT_) void k_radix_scatter(const KeyT* __restrict__ kin,
                                                          const uint32_t* __restrict__ vin,
                                                          KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          const uint32_t* d_count, uint32_t cap, int shift,
                                                          uint32_t dmask,
                                                          const uint32_t* __restrict__ hist_scan, uint32_t ntiles,
-                                                         const uint32_t* __restrict__ digit_tot) {
+                                                         const uint32_t* __restrict__ digit_tot, XF xf = XF()) {
     constexpr int NW = NT_ / WAVE;
     constexpr int RS_TILE = NT_ * RS_ITEMS, RS_WAVE_SPAN = WAVE * RS_ITEMS;
     static_assert(NT_ >= 256, "a thread per digit");
@@ -366,6 +385,9 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter(const KeyT* __restrict__ 
         k[it] = i < n ? kin[i] : KeyT(0);
         if (HAS_VAL) v[it] = i < n ? vin[i] : 0u;
     }
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it)
+        if (base + it * WAVE + l < n) k[it] = xf(k[it]);
 #pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
         const uint32_t i = base + it * WAVE + l;
@@ -509,6 +531,46 @@ static int radix_sort_any(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* 
                                                 first_counted);
     return radix_sort<KeyT, RS_ITEMS_SMALL>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
                                             first_counted);
+}
+
+template <int RS_ITEMS>
+static void radix_pass_relabel(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits,
+                               const uint32_t* rank, int32_t n, void* temp, hipStream_t s) {
+    const uint32_t ntiles = (uint32_t)rs_ntiles(cap, RS_NT * RS_ITEMS);
+    uint32_t* hist = (uint32_t*)temp;
+    void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * (ntiles + 1), 256);
+    uint32_t* digit_tot = (uint32_t*)scan_tmp;
+    uint32_t* seg_tot = (uint32_t*)((char*)scan_tmp + align_up(scan_temp_bytes(), 256));
+    const uint32_t nseg = (uint32_t)rs_nseg(ntiles);
+    const uint32_t dmask = (1u << bits) - 1u;
+    hipLaunchKernelGGL((k_radix_hist<uint64_t, RS_ITEMS>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr,
+                       (uint32_t)cap, shift, dmask, hist, ntiles);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, digit_tot, seg_tot);
+    if (nseg > 1)
+        hipLaunchKernelGGL(k_radix_rowfix, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, seg_tot, digit_tot);
+    constexpr bool HUGE_TILES = RS_ITEMS == RS_ITEMS_HUGE;   // 8192-key tiles: 512 threads of 16 keys
+    constexpr int IT = HUGE_TILES ? RS_ITEMS / 2 : RS_ITEMS;
+    constexpr int NTS = HUGE_TILES ? 2 * RS_NT : RS_NT;
+    if (rank)
+        hipLaunchKernelGGL((k_radix_scatter<uint64_t, false, IT, NTS, XfRankLow>), dim3(ntiles), dim3(NTS), 0, s,
+                           kin, nullptr, kout, nullptr, nullptr, (uint32_t)cap, shift, dmask, hist, ntiles,
+                           digit_tot, XfRankLow{rank, n});
+    else
+        hipLaunchKernelGGL((k_radix_scatter<uint64_t, false, IT, NTS>), dim3(ntiles), dim3(NTS), 0, s, kin, nullptr,
+                           kout, nullptr, nullptr, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot,
+                           XfIdentity());
+}
+
+void radix_pass_u64(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const uint32_t* rank,
+                    int32_t n, void* temp, hipStream_t s) {
+    if (cap == 0 || bits <= 0) return;
+    const uint32_t tile = radix_tile_keys(cap, 8);
+    if (tile == RS_NT * RS_ITEMS_HUGE)
+        radix_pass_relabel<RS_ITEMS_HUGE>(kin, kout, cap, shift, bits, rank, n, temp, s);
+    else if (tile == RS_NT * RS_ITEMS_LARGE)
+        radix_pass_relabel<RS_ITEMS_LARGE>(kin, kout, cap, shift, bits, rank, n, temp, s);
+    else
+        radix_pass_relabel<RS_ITEMS_SMALL>(kin, kout, cap, shift, bits, rank, n, temp, s);
 }
 
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,

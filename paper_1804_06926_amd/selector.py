@@ -83,6 +83,80 @@ def collect(graphs, repeats: int = 5, device: str = "cuda:0", log=None):
             "names": names}
 
 
+def collect_in_launch(graphs, repeats: int = 7, device: str = "cuda:0", log=None, min_tie_ms: float = 0.004):
+    """Time each strategy for each busy bucket inside the combined launch.
+
+    For each graph the whole intersection stage (three kernels over their tile
+    ranges, as a counting call launches them) is timed with the fixed thresholds'
+    choice everywhere, then once per (busy bucket, other strategy) with only that
+    bucket changed. times[i, k] = stage time with bucket i on strategy k (the others
+    on the heuristic's), so times[i, k] - times[i].min() is the time that choice
+    costs in the combined launch. The baseline is re-timed between the changes; the
+    spread of those repeats (noise_ms) sets how large a difference must be to count.
+    graphs: iterable of (name, edges int32 [E, 2] numpy, num_vertices). Returns the
+    dict of collect() plus noise_ms [N] (per bucket, its graph's baseline spread).
+    """
+    import torch
+    feats, times, buckets, gids, names, noise = [], [], [], [], [], []
+    for gi, (name, edges, n) in enumerate(graphs):
+        d = torch.from_numpy(np.ascontiguousarray(edges, dtype=np.int32)).to(device)
+        T = _lib.count_triangles(d, n)
+        st = _lib.last_stats(device)
+        feat = _lib.bucket_features(device)
+        heur = st["bucket_kernel"].astype(int)
+        busy = [b for b in range(255) if st["bucket_vertices"][b] > 0]
+        base = np.full(256, 255, dtype=np.uint8)
+        bases = []
+
+        def stage(choice):
+            ms, _, Tx = _lib.profile_choices(d, n, choice, repeats=repeats)
+            assert Tx == T, (name, Tx, T)
+            return ms
+
+        bases.append(stage(base))
+        rows = []
+        for j, b in enumerate(busy):
+            t = np.zeros(3)
+            for k in range(3):
+                if k == heur[b]:
+                    continue
+                c = base.copy()
+                c[b] = k
+                t[k] = stage(c)
+            rows.append(t)
+            if j % 8 == 7:
+                bases.append(stage(base))
+        bases.append(stage(base))
+        t_base = float(np.median(bases))
+        spread = float(np.max(bases) - np.min(bases))
+        for b, t in zip(busy, rows):
+            t[heur[b]] = t_base
+            feats.append(feat[b])
+            times.append(t)
+            buckets.append(b)
+            gids.append(gi)
+            noise.append(max(spread, min_tie_ms))
+        names.append(name)
+        if log:
+            log(f"[selector] collected {name}: {len(busy)} buckets, stage {t_base:.3f} ms "
+                f"(baseline spread {spread * 1e3:.1f} us over {len(bases)} repeats)")
+        del d
+    return {"features": np.array(feats, dtype=np.float32).reshape(-1, 6),
+            "times": np.array(times, dtype=np.float64).reshape(-1, 3),
+            "bucket": np.array(buckets, dtype=np.int64), "graph": np.array(gids, dtype=np.int64),
+            "names": names, "noise_ms": np.array(noise, dtype=np.float64)}
+
+
+def make_labels_in_launch(times: np.ndarray, buckets: np.ndarray, noise_ms: np.ndarray) -> np.ndarray:
+    """Fastest strategy per bucket in the combined launch; the heuristic's unless
+    another is faster by more than the baseline's repeat spread."""
+    best = np.argmin(times, axis=1)
+    heur = np.array([heuristic_choice(int(b)) for b in buckets])
+    idx = np.arange(len(best))
+    keep = times[idx, heur] - times[idx, best] <= noise_ms
+    return np.where(keep, heur, best).astype(np.int32)
+
+
 def make_labels(times: np.ndarray, buckets: np.ndarray, tie: float = 0.02, abs_tie: float = 0.005) -> np.ndarray:
     """Fastest strategy per bucket; the heuristic's when its time is within `tie`
     (relative) or `abs_tie` ms of the best. A bucket timed alone costs at least one

@@ -1,13 +1,20 @@
 """Train the kernel-selector network on the GPU and evaluate it on held-out graphs.
 
 Training graphs: R-MAT scales 18-22 (edge factor 16) and Chung-Lu graphs
-(power-law exponent 2.1), all seeded apart from the benchmark and test graphs.
+(power-law exponent 2.1), all seeded apart from the benchmark and test graphs;
+with --with-rgg also random geometric graphs of 2^17-2^21 vertices.
 Held-out graphs: R-MAT scale 24 and a random geometric graph on 2^23 vertices
-(average degree 32), plus any others named on the command line.
+(average degree 32).
+
+Labels come from the combined launch (selector.collect_in_launch): the whole
+intersection stage is timed with one bucket's strategy changed at a time, so a
+bucket's label reflects what it costs among the others, not alone (--labels
+isolated takes the older per-bucket launches instead).
 
 Writes the float32 parameters (JSON, see selector.save) and a report with the
 per-graph regret of the learned choice, of the heuristic and of every single
-strategy, and the end-to-end step time of the learned and heuristic modes.
+strategy, and the end-to-end step time of the learned and heuristic modes
+(alternating blocks, with the spread of the per-block ratio).
 
     python -m paper_1804_06926_amd.train_selector --out selector_weights.json --report report.json
     python -m paper_1804_06926_amd.train_selector --evaluate selector_weights.json --report report.json
@@ -31,7 +38,7 @@ def log(msg):
     print(msg, flush=True)
 
 
-def training_graphs(quick: bool):
+def training_graphs(quick: bool, with_rgg: bool = False):
     import graphgen
     scales = (16, 17, 18) if quick else (18, 19, 20, 21, 22)
     for i, s in enumerate(scales):
@@ -40,6 +47,8 @@ def training_graphs(quick: bool):
         ((1 << 17, 8 << 17), (1 << 18, 16 << 18), (1 << 19, 8 << 19), (1 << 20, 16 << 20), (1 << 21, 8 << 21))
     for i, (n, E) in enumerate(sizes):
         yield f"chunglu_n{n}_seed{201 + i}", graphgen.chung_lu(n, E, 2.1, seed=201 + i), n
+    if not with_rgg:
+        return
     # mesh-like graphs: without them the network never sees buckets where merge
     # path beats binary search by a wide margin (sizes and seeds distinct from
     # the held-out random geometric graphs); one large size, since the edge
@@ -61,15 +70,24 @@ def heldout_graphs(quick: bool):
         yield "rgg_2^23", graphgen.rgg(1 << 23, 32.0, seed=5), 1 << 23
 
 
-def step_time(tc, d, n, select, steps=5):
+def step_times(tc, d, n, steps=5, blocks=5):
+    """Learned and heuristic steps in alternating blocks: (median ms learned, median ms
+    heuristic, per-block heuristic/learned ratios, T)."""
     import torch
-    tc.count_triangles(d, n, select=select)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        T = tc.count_triangles(d, n, select=select)
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) * 1e3 / steps, T
+    T = tc.count_triangles(d, n, select=tc.SELECT_HEURISTIC)
+    assert tc.count_triangles(d, n, select=tc.SELECT_LEARNED) == T
+    ms = {tc.SELECT_LEARNED: [], tc.SELECT_HEURISTIC: []}
+    for _ in range(blocks):
+        for sel in (tc.SELECT_HEURISTIC, tc.SELECT_LEARNED):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                Tx = tc.count_triangles(d, n, select=sel)
+            torch.cuda.synchronize()
+            ms[sel].append((time.perf_counter() - t0) * 1e3 / steps)
+            assert Tx == T, (sel, Tx, T)
+    ratios = np.array(ms[tc.SELECT_HEURISTIC]) / np.array(ms[tc.SELECT_LEARNED])
+    return float(np.median(ms[tc.SELECT_LEARNED])), float(np.median(ms[tc.SELECT_HEURISTIC])), ratios, T
 
 
 def main(argv=None):
@@ -80,6 +98,10 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--quick", action="store_true", help="small graphs (for a smoke run)")
+    ap.add_argument("--with-rgg", action="store_true", help="random geometric graphs in the training set too")
+    ap.add_argument("--labels", choices=["in-launch", "isolated"], default="in-launch")
+    ap.add_argument("--no-heldout-profile", action="store_true",
+                    help="held-out graphs: step times only (no per-bucket in-launch regret)")
     ap.add_argument("--evaluate", metavar="WEIGHTS",
                     help="skip training: evaluate these saved weights on the held-out graphs")
     args = ap.parse_args(argv)
@@ -106,8 +128,13 @@ def main(argv=None):
 
 
 def _train(args, tc, selector):
-    data = selector.collect(training_graphs(args.quick), repeats=args.repeats, log=log)
-    y = selector.make_labels(data["times"], data["bucket"])
+    graphs = training_graphs(args.quick, args.with_rgg)
+    if args.labels == "in-launch":
+        data = selector.collect_in_launch(graphs, repeats=args.repeats, log=log)
+        y = selector.make_labels_in_launch(data["times"], data["bucket"], data["noise_ms"])
+    else:
+        data = selector.collect(graphs, repeats=args.repeats, log=log)
+        y = selector.make_labels(data["times"], data["bucket"])
     w = selector.sample_weights(data["times"])
     log(f"[selector] {len(y)} training buckets; label counts {np.bincount(y, minlength=3).tolist()}")
     params, losses = selector.train(data["features"], y, w, steps=args.steps, lr=args.lr, log=log)
@@ -119,7 +146,7 @@ def _train(args, tc, selector):
                             data["times"], np.array([selector.heuristic_choice(int(b)) for b in data["bucket"]])),
                         "graphs": data["names"]}}
     selector.save(args.out, params, {"trained_on": data["names"], "steps": args.steps, "lr": args.lr,
-                                     "repeats": args.repeats})
+                                     "repeats": args.repeats, "labels": args.labels})
     log(f"[selector] saved {args.out}; train report {report['train']}")
     return params, report
 
@@ -131,27 +158,29 @@ def _evaluate(args, tc, selector, params, report):
     for name, edges, n in heldout_graphs(args.quick):
         log(f"[selector] held-out {name}")
         d = torch.from_numpy(edges).cuda()
-        ms, feat = tc.profile_buckets(d, n, repeats=args.repeats)
-        busy = [b for b in range(255) if np.all(ms[:, b] > 0)]
-        times = ms[:, busy].T.astype(np.float64)
-        fx = feat[busy]
-        learned = selector.predict(fx)
-        heur = np.array([selector.heuristic_choice(b) for b in busy])
-        entry = {"graph": name, "buckets": len(busy),
-                 "regret_learned_ms": selector.regret(times, learned),
-                 "regret_heuristic_ms": selector.regret(times, heur),
-                 "best_total_ms": float(times.min(axis=1).sum())}
-        for k, kn in enumerate(selector.KERNELS):
-            entry[f"regret_all_{kn}_ms"] = selector.regret(times, np.full(len(busy), k))
-        # the buckets where either choice misses the fastest strategy
-        entry["misses"] = [{"bucket": int(b), "ms": [round(float(t), 4) for t in times[i]],
-                            "learned": int(learned[i]), "heuristic": int(heur[i])}
-                           for i, b in enumerate(busy)
-                           if learned[i] != np.argmin(times[i]) or heur[i] != np.argmin(times[i])]
-        t_l, T_l = step_time(tc, d, n, tc.SELECT_LEARNED)
-        t_h, T_h = step_time(tc, d, n, tc.SELECT_HEURISTIC)
-        assert T_l == T_h, (T_l, T_h)
-        entry.update({"step_ms_learned": t_l, "step_ms_heuristic": t_h, "triangles": T_l})
+        entry = {"graph": name}
+        if not args.no_heldout_profile:
+            data = selector.collect_in_launch([(name, edges, n)], repeats=args.repeats, log=log)
+            times, busy = data["times"], data["bucket"]
+            tc.selector_set_params(params)
+            learned = selector.predict(data["features"])
+            heur = np.array([selector.heuristic_choice(int(b)) for b in busy])
+            entry.update({"buckets": int(len(busy)),
+                          "stage_ms_heuristic": float(times[0, heur[0]]) if len(busy) else 0.0,
+                          "noise_ms": float(data["noise_ms"][0]) if len(busy) else 0.0,
+                          "regret_learned_ms": selector.regret(times, learned),
+                          "regret_heuristic_ms": selector.regret(times, heur)})
+            for k, kn in enumerate(selector.KERNELS):
+                entry[f"regret_all_{kn}_ms"] = selector.regret(times, np.full(len(busy), k))
+            # the buckets where either choice misses the fastest strategy
+            entry["misses"] = [{"bucket": int(b), "stage_ms": [round(float(t), 4) for t in times[i]],
+                                "learned": int(learned[i]), "heuristic": int(heur[i])}
+                               for i, b in enumerate(busy)
+                               if learned[i] != np.argmin(times[i]) or heur[i] != np.argmin(times[i])]
+        tc.selector_set_params(params)
+        t_l, t_h, ratios, T = step_times(tc, d, n)
+        entry.update({"step_ms_learned": t_l, "step_ms_heuristic": t_h, "speedup": t_h / t_l,
+                      "block_ratios": [float(x) for x in ratios], "triangles": T})
         report["heldout"].append(entry)
         log(f"[selector] {entry}")
         del d

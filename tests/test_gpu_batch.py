@@ -106,3 +106,70 @@ def test_tile_shapes_never_change_counts(tc):
         for s in (tc.SELECT_HEURISTIC, tc.FORCE_MERGE, tc.FORCE_BSEARCH, tc.FORCE_BITMAP):
             assert tc.count_triangles(d, n, select=s) == ref, (K, s)
     tc.set_tile_shapes(None, None)
+
+
+def test_autotuner_end_to_end_on_a_small_batch(tc, tmp_path):
+    """The tile-shape autotuner run for real: tune on the union of a small batch (every
+    busy bucket timed at each candidate size through tc_profile_selected), save the
+    result to a cache file, install it from there, and count the batch with it: every
+    per-graph count equals the oracle's, replayed and launched directly."""
+    import torch
+    from paper_1804_06926_amd import autotune
+    e, off, nv = graphgen.chung_lu_batch(96, 1e3, 5e4, seed=19)
+    ref = _oracle_counts(e, off, nv)
+    base = np.zeros(nv.size, dtype=np.int64)
+    np.cumsum(nv[:-1].astype(np.int64), out=base[1:])
+    union = e + np.repeat(base, np.diff(off)).astype(np.int32)[:, None]
+    N = int(nv.astype(np.int64).sum())
+    du = torch.from_numpy(np.ascontiguousarray(union)).cuda()
+    best, table = autotune.tune(du, N, repeats=2, candidates=(32, 128, 512))
+    busy = np.nonzero(tc.last_stats()["bucket_vertices"][:255])[0]
+    assert busy.size > 0
+    for b in busy:   # every busy bucket was timed at every size and got one of them
+        assert np.all(table[:, b] > 0), b
+        assert best[b] in (32, 128, 512), (b, best[b])
+    assert np.all(best[[b for b in range(256) if b not in set(busy.tolist())]] == 0)
+    cache = str(tmp_path / "shapes.json")
+    key = autotune.device_key(tc.SELECT_HEURISTIC)
+    autotune.save(best, key, cache)
+    np.testing.assert_array_equal(autotune.load(key, cache), best)
+    d = torch.from_numpy(e).cuda()
+    try:
+        assert autotune.apply_cached(tc.SELECT_HEURISTIC, path=cache)
+        np.testing.assert_array_equal(tc.count_triangles_batch(d, off, nv), ref)
+        np.testing.assert_array_equal(tc.count_triangles_batch(d, off, nv), ref)
+        np.testing.assert_array_equal(tc.count_triangles_batch(d, off, nv, graph=False), ref)
+        st = tc.last_stats()
+        for b in busy:   # the tuned sizes are the ones the layout used (bitmap tiles cap at 512)
+            if st["bucket_vertices"][b]:
+                assert st["bucket_chunk"][b] == best[b], (b, st["bucket_chunk"][b], best[b])
+    finally:
+        tc.set_tile_shapes(None, None)
+
+
+def test_captured_graph_serves_other_batches_of_the_same_sizes(tc):
+    """The captured graph is keyed on the batch's totals (pairs, vertices, graphs), the
+    selection and the workspace; the edge list's address and the per-graph offsets
+    reach the device before each launch. Batches with other contents, at another
+    address, and with the same totals split differently between the graphs, replay it
+    and still give the oracle's per-graph counts."""
+    import torch
+    G = 24
+    rng = np.random.default_rng(8)
+    nv = rng.integers(40, 400, size=G).astype(np.int32)
+    E = (nv.astype(np.int64) * rng.integers(3, 9, size=G)).astype(np.int64)
+
+    def batch(nv, E, seed):
+        off = np.zeros(G + 1, dtype=np.int64)
+        np.cumsum(E, out=off[1:])
+        e = np.concatenate([graphgen.chung_lu(int(nv[g]), int(E[g]), seed=seed + g) for g in range(G)])
+        return e.astype(np.int32), off, nv
+
+    # same sizes, other contents; then the same totals split differently
+    nv2, E2 = nv[::-1].copy(), E[::-1].copy()
+    batches = [batch(nv, E, 100), batch(nv, E, 500), batch(nv2, E2, 900), batch(nv, E, 100)]
+    for i, (e, off, n) in enumerate(batches):
+        ref = _oracle_counts(e, off, n)
+        d = torch.from_numpy(e).cuda()   # a new buffer each time
+        np.testing.assert_array_equal(tc.count_triangles_batch(d, off, n, graph=True), ref, err_msg=str(i))
+        del d

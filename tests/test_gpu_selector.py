@@ -211,3 +211,37 @@ def test_learned_choices_match_forward_argmax(tc):
     tc.count_triangles(torch.from_numpy(graphgen.rmat(16, 16, seed=4)).cuda(), 1 << 16, select=tc.SELECT_LEARNED)
     st = tc.last_stats()
     np.testing.assert_array_equal(st["bucket_kernel"][:255], selector.predict(tc.bucket_features()[:255]))
+
+
+def test_profile_choices_applies_the_given_strategies(tc):
+    """tc_profile_choices lays out the tiles with the caller's strategy per bucket
+    (values 3..255 keep the fixed thresholds' choice), times the whole intersection
+    stage, and counts the same T whatever the choice."""
+    import torch
+    from paper_1804_06926_amd import selector
+    n = 1 << 15
+    e = graphgen.rmat(15, 16, seed=21)
+    d = torch.from_numpy(e).cuda()
+    T = oracle.count_triangles(e, n)
+    ms, per, Tx = tc.profile_choices(d, n, np.full(256, 255, np.uint8), repeats=3)
+    assert Tx == T and ms > 0 and np.all(per >= 0) and abs(per.sum() - ms) < 1e-3
+    st = tc.last_stats()
+    busy = np.nonzero(st["bucket_vertices"][:255])[0]
+    for b in range(255):
+        assert st["bucket_kernel"][b] == selector.heuristic_choice(b)
+    rng = np.random.default_rng(5)
+    for trial in range(3):
+        choice = np.full(256, 255, np.uint8)
+        choice[busy] = rng.integers(0, 3, size=busy.size)
+        chunk = np.zeros(256, np.uint16)
+        chunk[busy] = rng.choice([64, 128, 512], size=busy.size)
+        ms, per, Tx = tc.profile_choices(d, n, choice, chunk, repeats=2)
+        assert Tx == T, trial
+        st = tc.last_stats()
+        np.testing.assert_array_equal(st["bucket_kernel"][busy], choice[busy])
+        np.testing.assert_array_equal(st["bucket_chunk"][busy], chunk[busy])
+    # the context's own selection is untouched afterwards
+    assert tc.count_triangles(d, n) == T
+    st = tc.last_stats()
+    for b in range(255):
+        assert st["bucket_kernel"][b] == selector.heuristic_choice(b)
