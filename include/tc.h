@@ -168,6 +168,24 @@ tc_status tc_edge_support(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges
                           int32_t* d_out_edges, uint32_t* d_out_support, int64_t* h_num_out, uint64_t* h_count);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * count as tc_count_triangles_async, with the workspace taken from a fixed
+ * scratch array that the library holds on each GPU for the life of the
+ * process (TC_NOALLOC_SCRATCH_BYTES per GPU; its device address is looked up
+ * once per device by tc_create). The call allocates nothing; inputs and
+ * outputs are the caller's, as for tc_count_triangles_async (d_result uint64[2]
+ * device, d_per_vertex optional). A graph whose tc_workspace_size exceeds
+ * TC_NOALLOC_SCRATCH_BYTES is rejected with TC_ERR_WORKSPACE before anything
+ * is queued. Every call on one GPU uses the same scratch: calls queued on one
+ * stream run one after another, but calls that overlap on one GPU (other
+ * streams, other contexts of that device) race and give undefined results.
+ */
+#define TC_NOALLOC_SCRATCH_BYTES (64u << 20)
+tc_status tc_count_triangles_noalloc(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                                    const tc_options* opts, uint64_t* d_result, uint64_t* d_per_vertex);
+
+/*
  * The paper's other formulations of the same count, for comparison with the
  * filtered one above. All run the same canonicalisation, degree order and
  * filtered CSR, then stream, for every kept edge (u -> v), one list of u

@@ -21,6 +21,8 @@ from ._lib import (  # noqa: F401
     clustering,
     count_triangles,
     count_triangles_async,
+    count_triangles_noalloc,
+    NOALLOC_SCRATCH_BYTES,
     count_triangles_formulation,
     FORMULATIONS,
     count_triangles_batch,

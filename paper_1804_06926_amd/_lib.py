@@ -259,6 +259,36 @@ def count_triangles_async(edges, num_vertices: int, result=None, per_vertex=None
     return result
 
 
+NOALLOC_SCRATCH_BYTES = 64 << 20   # TC_NOALLOC_SCRATCH_BYTES
+
+
+def count_triangles_noalloc(edges, num_vertices: int, result, per_vertex=None, select: int = SELECT_HEURISTIC):
+    """count_triangles_async on the library's fixed per-GPU scratch: neither this call
+    nor the library allocates device memory (the context must exist already: create it
+    with any earlier call on this stream). ``result`` (int64 [2] on the device) is the
+    caller's; graphs whose workspace exceeds NOALLOC_SCRATCH_BYTES raise TCError
+    (status 3) before anything is queued."""
+    torch = _torch()
+    e = _edges_arg(edges)
+    ctx, _ = _ctx(e.device)
+    E = e.shape[0]
+    o = _options(select, False)
+    if result is None or result.dtype != torch.int64 or result.numel() < 2 or not result.is_cuda:
+        raise TypeError("result must be an int64 device tensor with 2 entries")
+    if per_vertex is not None and (per_vertex.dtype != torch.int64 or per_vertex.numel() < num_vertices):
+        raise TypeError("per_vertex must be an int64 tensor with num_vertices entries")
+    lib = _load()
+    vp = ctypes.c_void_p
+    lib.tc_count_triangles_noalloc.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(Options), vp,
+                                               vp]
+    lib.tc_count_triangles_noalloc.restype = ctypes.c_int
+    st = lib.tc_count_triangles_noalloc(ctx, e.data_ptr() if E else None, E, num_vertices, ctypes.byref(o),
+                                        result.data_ptr(),
+                                        per_vertex.data_ptr() if per_vertex is not None and num_vertices else None)
+    _check(st, ctx)
+    return result
+
+
 def clustering(edges, num_vertices: int, per_vertex: bool = False, select: int = SELECT_HEURISTIC, workspace=None):
     """Local clustering coefficients and transitivity.
 

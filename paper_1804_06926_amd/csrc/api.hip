@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -48,9 +49,20 @@ struct tc_ctx {
     } graph_key = {};
     uint64_t* h_counts_pinned = nullptr;
     size_t h_counts_cap = 0;
+    void* d_scratch = nullptr;   // this device's copy of `scratch` (tc_count_triangles_noalloc)
 };
 
+// Fixed scratch of tc_count_triangles_noalloc: the pipeline workspace of graphs
+// up to TC_NOALLOC_SCRATCH_BYTES, one copy per GPU for the life of the process.
+// Host code never uses this name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, in tc_create.
+static __device__ __align__(256) unsigned char scratch[TC_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
 
 struct DeviceGuard {
     int prev = -1;
@@ -201,6 +213,15 @@ tc_status tc_create(tc_ctx** out, int device, void* hip_stream) {
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_grad, np);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_loss, sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_cw, sizeof(tcx::MlpCompute));
+    if (e == hipSuccess && device < kMaxScratchDevices) {   // the fixed scratch's address on this device
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            void* p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e == hipSuccess) g_scratch_ptr[device] = p;
+        }
+        ctx->d_scratch = g_scratch_ptr[device];
+    }
     if (e != hipSuccess) {
         tc_destroy(ctx);
         return TC_ERR_HIP;
@@ -260,6 +281,19 @@ tc_status tc_count_triangles_async(tc_ctx* ctx, const int32_t* d_edges, int64_t 
     tcx::RunArgs ra = {};
     ra.per_vertex = d_per_vertex;
     return run(ctx, d_edges, num_edges, num_vertices, d_workspace, workspace_bytes, opts, ra, d_result);
+}
+
+tc_status tc_count_triangles_noalloc(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, int32_t num_vertices,
+                                    const tc_options* opts, uint64_t* d_result, uint64_t* d_per_vertex) {
+    if (!ctx) return TC_ERR_INVALID_ARG;
+    if (num_edges < 0 || num_vertices < 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "negative size");
+    if (num_edges > kMaxEdges) return arg_fail(ctx, TC_ERR_UNSUPPORTED, "num_edges must be below 2^31 - 2^20");
+    if (tcx::make_layout(num_edges, num_vertices).total > (size_t)TC_NOALLOC_SCRATCH_BYTES)
+        return arg_fail(ctx, TC_ERR_WORKSPACE, "graph needs more workspace than the fixed scratch holds "
+                                               "(tc_workspace_size > TC_NOALLOC_SCRATCH_BYTES)");
+    if (!ctx->d_scratch) return arg_fail(ctx, TC_ERR_UNSUPPORTED, "no fixed scratch on this device");
+    return tc_count_triangles_async(ctx, d_edges, num_edges, num_vertices, ctx->d_scratch,
+                                    (size_t)TC_NOALLOC_SCRATCH_BYTES, opts, d_result, d_per_vertex);
 }
 
 tc_status tc_formulation_workspace_size(int64_t num_edges, int32_t num_vertices, const tc_options* opts,
