@@ -62,8 +62,8 @@ struct Ctrl {
     uint32_t tile_begin[NKERNEL + 1]; // tile range per intersection kernel
     uint32_t m_active;                // in-edges with work (non-empty tail, d+(v) > 0)
     uint32_t pad0;
-    uint32_t tile_next[NKERNEL + 1];  // per intersection kernel: tiles handed out so far (zero between launches)
-    uint32_t tile_done[NKERNEL + 1];  //   and blocks finished (the last one resets both)
+    uint32_t tile_next[NKERNEL + 1];  // per intersection kernel: tiles handed out after the first per block
+                                      // (zeroed before every launch)
     uint64_t wedges;                  // sum over v of C(d(v), 2), simple degree (clustering runs only)
     uint32_t bstart[NBUCKET];         // first / one-past-last position of each bucket
     uint32_t bend[NBUCKET];           //   in the (kernel, bucket)-ordered vertex list

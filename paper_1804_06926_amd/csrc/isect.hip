@@ -18,12 +18,13 @@
 // the per-edge counts c_e, the per-vertex counts t[u], t[v], t[w] and the
 // edge support (triangles per edge: a hit w adds 1 to edges uv, uw and vw;
 // uw is the tail element's own CSR position, vw the position of w in N+(v)).
-// Blocks take tiles in order from a shared counter (one atomic per tile), so a
-// block that drew light tiles takes more: tiles are ordered heaviest bucket
-// first, which makes this a longest-first schedule; the last block to finish
-// resets the counter for the next launch. Each block writes its partial count
-// and one reduction adds them in a fixed order; T does not depend on which
-// block counted which tile (integer sums).
+// Block b starts with tile b; after that the blocks take tiles in order from a
+// shared counter (one atomic per tile), so a block that drew light tiles takes
+// more: tiles are ordered heaviest bucket first, which makes this a
+// longest-first schedule. Blocks without a first tile exit at once (small
+// graphs). The counter is zeroed before each launch (launch_isect callers).
+// Each block writes its partial count and one reduction adds them in a fixed
+// order; T does not depend on which block counted which tile (integer sums).
 // A second pass of the same kernels writes the triangles themselves (listing).
 // The same kernels serve the paper's other formulations (whole neighbour
 // lists; the matrix formulation of Section 3.3): an entry's range is then a
@@ -54,25 +55,14 @@ struct SegsT {
 };
 using Segs = SegsT<SEG_MAX>;
 
-// The next tile for this block: t0 + the shared counter of kernel ker. Called by
-// the whole block (barriers); the value is the same in every thread.
+// The next tile for this block after its first (static) one: t0 + the shared
+// counter of kernel ker, which is zero when the launch starts. Called by the
+// whole block (barriers); the value is the same in every thread.
 __device__ __forceinline__ uint32_t grab_tile(Ctrl* ctrl, int ker, uint32_t t0, uint32_t* s_tile) {
     __syncthreads();   // every thread has read the previous value
     if (threadIdx.x == 0) *s_tile = t0 + atomicAdd(&ctrl->tile_next[ker], 1u);
     __syncthreads();
     return *s_tile;
-}
-
-// After a block's last grab: the last block of the launch to get here resets
-// the counters, so the next launch of the kernel starts from tile t0 again.
-__device__ __forceinline__ void release_tiles(Ctrl* ctrl, int ker) {
-    if (threadIdx.x == 0) {
-        const uint32_t done = atomicAdd(&ctrl->tile_done[ker], 1u);
-        if (done == gridDim.x - 1u) {   // every block has made its final grab
-            atomicExch(&ctrl->tile_next[ker], 0u);
-            atomicExch(&ctrl->tile_done[ker], 0u);
-        }
-    }
 }
 
 // Decode tile t into segments (v, first in-edge, count); returns the count.
@@ -297,8 +287,7 @@ __global__ __launch_bounds__(IS_NT, MODE == BM_GATHER ? 1 : 6) void k_isect_bitm
     uint64_t acc = 0;
     __shared__ uint32_t s_tile;
     const uint32_t t_begin = a.ctrl->tile_begin[KER_BITMAP], t_end = a.ctrl->tile_begin[KER_BITMAP + 1];
-    for (uint32_t t = grab_tile(a.ctrl, KER_BITMAP, t_begin, &s_tile); t < t_end;
-         t = grab_tile(a.ctrl, KER_BITMAP, t_begin, &s_tile)) {
+    for (uint32_t t = t_begin + blockIdx.x; t < t_end; t = grab_tile(a.ctrl, KER_BITMAP, t_begin + gridDim.x, &s_tile)) {
         const uint32_t nseg = load_tile(a, t, S);
         for (uint32_t sg = 0; sg < nseg; ++sg) {
             const uint32_t v = S.v[sg];
@@ -543,7 +532,6 @@ __global__ __launch_bounds__(IS_NT, MODE == BM_GATHER ? 1 : 6) void k_isect_bitm
             __syncthreads();
         }
     }
-    release_tiles(a.ctrl, KER_BITMAP);
     block_partial(acc, partials);
 }
 
@@ -672,7 +660,7 @@ __global__ __launch_bounds__(IS_NT) void k_isect_edges(IsectArgs a, uint64_t* pa
     uint64_t acc = 0;
     __shared__ uint32_t s_tile;
     const uint32_t t_begin = a.ctrl->tile_begin[KER], t_end = a.ctrl->tile_begin[KER + 1];
-    for (uint32_t t = grab_tile(a.ctrl, KER, t_begin, &s_tile); t < t_end; t = grab_tile(a.ctrl, KER, t_begin, &s_tile)) {
+    for (uint32_t t = t_begin + blockIdx.x; t < t_end; t = grab_tile(a.ctrl, KER, t_begin + gridDim.x, &s_tile)) {
         const uint32_t nseg = load_tile(a, t, S);
         const uint32_t v0 = S.v[0];
         // stage the N+(v) lists of all the tile's vertices back to back when they fit
@@ -725,7 +713,6 @@ __global__ __launch_bounds__(IS_NT) void k_isect_edges(IsectArgs a, uint64_t* pa
         }
         __syncthreads();
     }
-    release_tiles(a.ctrl, KER);
     block_partial(acc, partials);
 }
 

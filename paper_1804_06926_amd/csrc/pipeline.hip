@@ -687,6 +687,7 @@ constexpr uint32_t EDGE_CHUNK_MAX = 2048;   // in-edges per tile of the edge-cen
 constexpr unsigned long long EDGE_TILES = 512;
 
 __global__ __launch_bounds__(NBUCKET) void k_select(Ctrl* ctrl, int mode, const uint8_t* __restrict__ learned,
+                                                    const uint8_t* __restrict__ learned_tile,
                                                     const uint16_t* __restrict__ chunk_override,
                                                     const uint8_t* __restrict__ group_override, int whole_rows) {
     __shared__ uint32_t s_key[NBUCKET];
@@ -719,6 +720,9 @@ __global__ __launch_bounds__(NBUCKET) void k_select(Ctrl* ctrl, int mode, const 
         chunk = per < 256ull ? 256u : (per > (unsigned long long)EDGE_CHUNK_MAX ? EDGE_CHUNK_MAX : (uint32_t)per);
     }
     uint32_t group = lo >= 9 ? 64u : (lo >= 3 ? (1u << (lo - 3)) : 1u);
+    // the tile network scales the rule's tile size by 1/2, 1 or 2
+    if (learned_tile && learned_tile[b] == 0) chunk = chunk / 2u;
+    else if (learned_tile && learned_tile[b] == 2) chunk = chunk * 2u;
     if (chunk_override && chunk_override[b]) chunk = chunk_override[b];
     if (group_override && group_override[b]) group = group_override[b];
     const uint32_t cmax = ch == KER_BITMAP ? (uint32_t)CHUNK_MAX : EDGE_CHUNK_MAX;
@@ -914,7 +918,13 @@ __global__ void k_set_tile_range(Ctrl* ctrl, int ker, uint32_t t0, uint32_t t1) 
     if (threadIdx.x == 0) {
         ctrl->tile_begin[ker] = t0;
         ctrl->tile_begin[ker + 1] = t1;
+        ctrl->tile_next[ker] = 0;
     }
+}
+
+// The intersection kernels' shared tile counters, zeroed before a relaunch.
+static void reset_tile_counters(Ctrl* ctrl, hipStream_t s) {
+    fill_u32(ctrl->tile_next, 0u, NKERNEL + 1, s);
 }
 
 // result[0] = T, result[1] = range_status when an id was out of range, else 0.
@@ -1042,6 +1052,7 @@ hipError_t launch_isect_stage(const RunArgs& r, hipEvent_t* ev) {
     const IsectArgs ia = isect_args(r, L, csc_of(r, L));
     uint64_t* partials = (uint64_t*)((char*)r.ws + L.isect_partials);
     const int order[NKERNEL] = {KER_MERGE, KER_BSEARCH, KER_BITMAP};
+    reset_tile_counters(ia.ctrl, r.stream);
     if (ev) (void)hipEventRecord(ev[0], r.stream);
     for (int q = 0; q < NKERNEL; ++q) {
         const int k = order[q];
@@ -1056,6 +1067,7 @@ hipError_t run_list_pass(const RunArgs& r) {
     const Layout L = make_layout(r.E, r.n);
     const IsectArgs ia = isect_args(r, L, csc_of(r, L));
     uint64_t* partials = (uint64_t*)((char*)r.ws + L.isect_partials);
+    reset_tile_counters(ia.ctrl, r.stream);
     for (int k = 0; k < NKERNEL; ++k) launch_isect(k, ia, r.grid_override ? r.grid_override[k] : 0, partials, r.stream);
     return hipGetLastError();
 }
@@ -1081,7 +1093,7 @@ size_t list_extra_bytes(int64_t E) {
 hipError_t launch_isect_range(const RunArgs& r, int ker, uint32_t t0, uint32_t t1) {
     const Layout L = make_layout(r.E, r.n);
     IsectArgs ia = isect_args(r, L, csc_of(r, L));
-    hipLaunchKernelGGL(k_set_tile_range, dim3(1), dim3(64), 0, r.stream, ia.ctrl, ker, t0, t1);
+    hipLaunchKernelGGL(k_set_tile_range, dim3(1), dim3(64), 0, r.stream, ia.ctrl, ker, t0, t1);   // zeroes the counter
     launch_isect(ker, ia, r.grid_override ? r.grid_override[ker] : 0, (uint64_t*)((char*)r.ws + L.isect_partials),
                  r.stream);
     return hipGetLastError();
@@ -1274,11 +1286,13 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     hipLaunchKernelGGL(k_vbucket, dim3(grid_for((size_t)n, 2048)), dim3(NT), 0, s, moff, mcol, inoff, n, vbucket,
                        ctrl);
     const bool learned = !r.given && r.select == SEL_LEARNED && r.mlp && r.learned;
+    const bool learned_tile = learned && r.mlp_tile && r.learned_tile;
     if (learned) mlp_select((const MlpCompute*)r.mlp, ctrl, r.learned, s);
     else bucket_features_launch(ctrl, s);
+    if (learned_tile) mlp_select((const MlpCompute*)r.mlp_tile, ctrl, r.learned_tile, s);
     hipLaunchKernelGGL(k_select, dim3(1), dim3(NBUCKET), 0, s, ctrl, r.given ? (int)SEL_LEARNED : r.select,
-                       r.given ? r.given : (learned ? r.learned : nullptr), r.chunk_override, r.group_override,
-                       r.formulation != FORM_FILTERED ? 1 : 0);
+                       r.given ? r.given : (learned ? r.learned : nullptr), learned_tile ? r.learned_tile : nullptr,
+                       r.chunk_override, r.group_override, r.formulation != FORM_FILTERED ? 1 : 0);
     mark(7);
     // ---- group: order vertices by (kernel, bucket); tiles
     hipLaunchKernelGGL(k_vkeys_slot, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vbucket, n, ctrl, vkeysA);
