@@ -372,6 +372,18 @@ tc_status tc_profile_choices(tc_ctx* ctx, const int32_t* d_edges, int64_t num_ed
 tc_status tc_selector_set_params(tc_ctx* ctx, const float* h_params);
 tc_status tc_selector_get_params(tc_ctx* ctx, float* h_params);
 
+/*
+ * The tile network: the same shape, parameter layout and kernels as the
+ * strategy network above, trained separately. In TC_SELECT_LEARNED mode its
+ * argmax per bucket scales the fixed rule's in-edges per tile by 1/2 (logit 0),
+ * 1 (logit 1) or 2 (logit 2) before the usual clamping (tiles of 16 to 512
+ * in-edges for the bitmap strategy, 2048 for the others); tile sizes set with
+ * tc_set_tile_shapes still take precedence. h_params NULL removes the network
+ * (the rule's tile sizes apply). Tile sizes change the speed, never the count.
+ */
+tc_status tc_selector_set_tile_params(tc_ctx* ctx, const float* h_params);
+tc_status tc_selector_get_tile_params(tc_ctx* ctx, float* h_params);
+
 /* Logits d_logits [batch][3] of features d_x [batch][6] (device arrays). */
 tc_status tc_selector_forward(tc_ctx* ctx, const float* d_x, int32_t batch, float* d_logits);
 

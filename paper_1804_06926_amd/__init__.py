@@ -39,6 +39,8 @@ from ._lib import (  # noqa: F401
     selector_get_params,
     selector_gradient,
     selector_set_params,
+    selector_get_tile_params,
+    selector_set_tile_params,
     selector_train_step,
     set_tile_shapes,
     stage_names,

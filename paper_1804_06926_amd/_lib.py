@@ -457,8 +457,11 @@ def _sel_lib():
     lib.tc_selector_forward.argtypes = [vp, vp, i32, vp]
     lib.tc_selector_gradient.argtypes = [vp, vp, vp, vp, i32, vp, fp]
     lib.tc_selector_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, fp]
+    lib.tc_selector_set_tile_params.argtypes = [vp, fp]
+    lib.tc_selector_get_tile_params.argtypes = [vp, fp]
     for f in ("tc_bucket_features", "tc_profile_buckets", "tc_selector_set_params", "tc_selector_get_params",
-              "tc_selector_forward", "tc_selector_gradient", "tc_selector_train_step"):
+              "tc_selector_forward", "tc_selector_gradient", "tc_selector_train_step",
+              "tc_selector_set_tile_params", "tc_selector_get_tile_params"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -482,6 +485,27 @@ def selector_get_params(device="cuda:0"):
     p = np.empty(SELECTOR_NUM_PARAMS, dtype=np.float32)
     ctx, _ = _ctx(device)
     _check(_sel_lib().tc_selector_get_params(ctx, _fptr(p)), ctx)
+    return p
+
+
+def selector_set_tile_params(params, device="cuda:0") -> None:
+    """Load the tile network's float32 parameters (None removes the network)."""
+    import numpy as np
+    ctx, _ = _ctx(device)
+    if params is None:
+        _check(_sel_lib().tc_selector_set_tile_params(ctx, None), ctx)
+        return
+    p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+    if p.size != SELECTOR_NUM_PARAMS:
+        raise ValueError(f"expected {SELECTOR_NUM_PARAMS} parameters")
+    _check(_sel_lib().tc_selector_set_tile_params(ctx, _fptr(p)), ctx)
+
+
+def selector_get_tile_params(device="cuda:0"):
+    import numpy as np
+    p = np.empty(SELECTOR_NUM_PARAMS, dtype=np.float32)
+    ctx, _ = _ctx(device)
+    _check(_sel_lib().tc_selector_get_tile_params(ctx, _fptr(p)), ctx)
     return p
 
 

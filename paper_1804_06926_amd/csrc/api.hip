@@ -35,6 +35,11 @@ struct tc_ctx {
     float* d_grad = nullptr;
     float* d_loss = nullptr;
     tcx::MlpCompute* d_cw = nullptr;
+    // tile network: float32 master and compute copy, its per-bucket scales
+    float* d_tile_master = nullptr;
+    tcx::MlpCompute* d_cw_tile = nullptr;
+    uint8_t* d_learned_tile = nullptr;
+    int tile_ready = 0;
     float* d_acts = nullptr;
     int adam_step = 0;
     // batched counting: a stream for capture when the context's stream is the
@@ -136,6 +141,8 @@ tc_status run(tc_ctx* ctx, const int32_t* d_edges, int64_t E, int32_t n, void* w
     ra.select = sel;
     ra.mlp = ctx->learned_ready ? ctx->d_cw : nullptr;
     ra.learned = ctx->d_learned;
+    ra.mlp_tile = ctx->tile_ready ? ctx->d_cw_tile : nullptr;
+    ra.learned_tile = ctx->d_learned_tile;
     if (!ra.chunk_override) ra.chunk_override = ctx->d_chunk;
     ra.group_override = ctx->d_group;
     ra.grid_override = ctx->grid_override;
@@ -213,6 +220,9 @@ tc_status tc_create(tc_ctx** out, int device, void* hip_stream) {
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_grad, np);
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_loss, sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_cw, sizeof(tcx::MlpCompute));
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_tile_master, np);
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_cw_tile, sizeof(tcx::MlpCompute));
+    if (e == hipSuccess) e = hipMalloc((void**)&ctx->d_learned_tile, tcx::NBUCKET);
     if (e == hipSuccess && device < kMaxScratchDevices) {   // the fixed scratch's address on this device
         std::lock_guard<std::mutex> lock(g_scratch_mu);
         if (!g_scratch_ptr[device]) {
@@ -246,6 +256,9 @@ tc_status tc_destroy(tc_ctx* ctx) {
         for (float* p : bufs)
             if (p) (void)hipFree(p);
         if (ctx->d_cw) (void)hipFree(ctx->d_cw);
+        if (ctx->d_tile_master) (void)hipFree(ctx->d_tile_master);
+        if (ctx->d_cw_tile) (void)hipFree(ctx->d_cw_tile);
+        if (ctx->d_learned_tile) (void)hipFree(ctx->d_learned_tile);
         if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
         if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
         if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
@@ -590,6 +603,8 @@ tc_status tc_count_triangles_batch(tc_ctx* ctx, const int32_t* d_edges, const in
     ra.select = sel;
     ra.mlp = ctx->learned_ready ? ctx->d_cw : nullptr;
     ra.learned = ctx->d_learned;
+    ra.mlp_tile = ctx->tile_ready ? ctx->d_cw_tile : nullptr;
+    ra.learned_tile = ctx->d_learned_tile;
     ra.chunk_override = ctx->d_chunk;
     ra.group_override = ctx->d_group;
     ra.grid_override = ctx->grid_override;
@@ -795,6 +810,35 @@ tc_status tc_selector_set_params(tc_ctx* ctx, const float* h_params) {
     ctx->adam_step = 0;
     ctx->learned_ready = 1;
     return TC_OK;
+}
+
+tc_status tc_selector_set_tile_params(tc_ctx* ctx, const float* h_params) {
+    if (!ctx) return TC_ERR_INVALID_ARG;
+    if (!h_params) {
+        ctx->tile_ready = 0;
+        return TC_OK;
+    }
+    DeviceGuard guard(ctx->device);
+    hipError_t e = hipMemcpyAsync(ctx->d_tile_master, h_params, sizeof(float) * tcx::MLP_NPARAM,
+                                  hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) {
+        tcx::mlp_cast(ctx->d_tile_master, ctx->d_cw_tile, ctx->stream);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "set tile network parameters");
+    ctx->tile_ready = 1;
+    return TC_OK;
+}
+
+tc_status tc_selector_get_tile_params(tc_ctx* ctx, float* h_params) {
+    if (!ctx || !h_params) return TC_ERR_INVALID_ARG;
+    if (!ctx->tile_ready) return arg_fail(ctx, TC_ERR_INVALID_ARG, "no tile network parameters set");
+    DeviceGuard guard(ctx->device);
+    hipError_t e = hipMemcpyAsync(h_params, ctx->d_tile_master, sizeof(float) * tcx::MLP_NPARAM,
+                                  hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    return e == hipSuccess ? TC_OK : hip_fail(ctx, e, "get tile network parameters");
 }
 
 tc_status tc_selector_get_params(tc_ctx* ctx, float* h_params) {

@@ -40,6 +40,8 @@ struct RunArgs {
     int select;
     const void* mlp;                 // device MlpCompute (selector network), or null
     uint8_t* learned;                // device [256] kernel per bucket written by the network
+    const void* mlp_tile;            // device MlpCompute (tile network), or null
+    uint8_t* learned_tile;           // device [256] tile scale per bucket written by the tile network
     const uint8_t* given;            // device [256] kernel per bucket chosen by the caller (values
                                      // >= NKERNEL: the heuristic's), or null; overrides select
     int stop_before_isect;           // leave after the tiles are laid out (bucket profiling)

@@ -83,18 +83,25 @@ def collect(graphs, repeats: int = 5, device: str = "cuda:0", log=None):
             "names": names}
 
 
-def collect_in_launch(graphs, repeats: int = 7, device: str = "cuda:0", log=None, min_tie_ms: float = 0.004):
-    """Time each strategy for each busy bucket inside the combined launch.
+SCALES = (0.5, 1.0, 2.0)   # the tile network's classes: the rule's tile size times these
+
+
+def collect_in_launch(graphs, repeats: int = 7, device: str = "cuda:0", log=None, min_tie_ms: float = 0.004,
+                      tiles: bool = True):
+    """Time each (strategy, tile size) for each busy bucket inside the combined launch.
 
     For each graph the whole intersection stage (three kernels over their tile
     ranges, as a counting call launches them) is timed with the fixed thresholds'
-    choice everywhere, then once per (busy bucket, other strategy) with only that
-    bucket changed. times[i, k] = stage time with bucket i on strategy k (the others
-    on the heuristic's), so times[i, k] - times[i].min() is the time that choice
-    costs in the combined launch. The baseline is re-timed between the changes; the
-    spread of those repeats (noise_ms) sets how large a difference must be to count.
-    graphs: iterable of (name, edges int32 [E, 2] numpy, num_vertices). Returns the
-    dict of collect() plus noise_ms [N] (per bucket, its graph's baseline spread).
+    choice everywhere, then once per (busy bucket, strategy, tile scale) with only
+    that bucket changed: the strategy, and its tiles at the rule's size for that
+    strategy times 1/2, 1 or 2 (sizes the clamp leaves unchanged are not re-timed).
+    times[i, k, s] = stage time with bucket i on strategy k at scale SCALES[s], the
+    other buckets as the heuristic leaves them, so times[i] - times[i].min() is what
+    each choice costs in the combined launch. The baseline is re-timed between the
+    changes; the spread of those repeats (noise_ms) sets how large a difference must
+    be to count. graphs: iterable of (name, edges int32 [E, 2] numpy, num_vertices).
+    Returns features [N, 6], times [N, 3, 3] (ms; inf where a scale is not
+    available), bucket [N], graph [N], names, noise_ms [N].
     """
     import torch
     feats, times, buckets, gids, names, noise = [], [], [], [], [], []
@@ -108,29 +115,40 @@ def collect_in_launch(graphs, repeats: int = 7, device: str = "cuda:0", log=None
         base = np.full(256, 255, dtype=np.uint8)
         bases = []
 
-        def stage(choice):
-            ms, _, Tx = _lib.profile_choices(d, n, choice, repeats=repeats)
+        def stage(choice, chunk=None):
+            ms, _, Tx = _lib.profile_choices(d, n, choice, chunk, repeats=repeats)
             assert Tx == T, (name, Tx, T)
             return ms
 
         bases.append(stage(base))
         rows = []
         for j, b in enumerate(busy):
-            t = np.zeros(3)
+            t = np.full((3, 3), np.inf)
             for k in range(3):
-                if k == heur[b]:
-                    continue
                 c = base.copy()
                 c[b] = k
-                t[k] = stage(c)
+                if k != heur[b]:
+                    t[k, 1] = stage(c)
+                rule = int(_lib.last_stats(device)["bucket_chunk"][b]) if k != heur[b] else \
+                    int(st["bucket_chunk"][b])
+                if not tiles:
+                    continue
+                cap = 512 if k == 2 else 2048
+                for si, f in ((0, 0.5), (2, 2.0)):
+                    size = min(cap, max(16, int(rule * f)))
+                    if size == rule:
+                        continue
+                    ch = np.zeros(256, dtype=np.uint16)
+                    ch[b] = size
+                    t[k, si] = stage(c, ch)
             rows.append(t)
-            if j % 8 == 7:
+            if j % 4 == 3:
                 bases.append(stage(base))
         bases.append(stage(base))
         t_base = float(np.median(bases))
         spread = float(np.max(bases) - np.min(bases))
         for b, t in zip(busy, rows):
-            t[heur[b]] = t_base
+            t[heur[b], 1] = t_base
             feats.append(feat[b])
             times.append(t)
             buckets.append(b)
@@ -142,19 +160,32 @@ def collect_in_launch(graphs, repeats: int = 7, device: str = "cuda:0", log=None
                 f"(baseline spread {spread * 1e3:.1f} us over {len(bases)} repeats)")
         del d
     return {"features": np.array(feats, dtype=np.float32).reshape(-1, 6),
-            "times": np.array(times, dtype=np.float64).reshape(-1, 3),
+            "times": np.array(times, dtype=np.float64).reshape(-1, 3, 3),
             "bucket": np.array(buckets, dtype=np.int64), "graph": np.array(gids, dtype=np.int64),
             "names": names, "noise_ms": np.array(noise, dtype=np.float64)}
 
 
-def make_labels_in_launch(times: np.ndarray, buckets: np.ndarray, noise_ms: np.ndarray) -> np.ndarray:
-    """Fastest strategy per bucket in the combined launch; the heuristic's unless
-    another is faster by more than the baseline's repeat spread."""
-    best = np.argmin(times, axis=1)
+def make_labels_in_launch(times: np.ndarray, buckets: np.ndarray, noise_ms: np.ndarray):
+    """Fastest (strategy, tile scale) per bucket in the combined launch; the fixed
+    thresholds' (strategy, rule size) unless another is faster by more than the
+    baseline's repeat spread. Returns (strategy labels, scale labels), int32 [N]."""
+    N = times.shape[0]
+    flat = times.reshape(N, 9)
+    best = np.argmin(flat, axis=1)
     heur = np.array([heuristic_choice(int(b)) for b in buckets])
-    idx = np.arange(len(best))
-    keep = times[idx, heur] - times[idx, best] <= noise_ms
-    return np.where(keep, heur, best).astype(np.int32)
+    idx = np.arange(N)
+    keep = flat[idx, heur * 3 + 1] - flat[idx, best] <= noise_ms
+    pick = np.where(keep, heur * 3 + 1, best)
+    return (pick // 3).astype(np.int32), (pick % 3).astype(np.int32)
+
+
+def in_launch_regret(times: np.ndarray, kernels: np.ndarray, scales: np.ndarray) -> float:
+    """Sum over buckets of (stage time with the chosen strategy and scale - the best), ms.
+    A scale that is not available for the chosen strategy counts as the rule's size."""
+    idx = np.arange(times.shape[0])
+    t = times[idx, kernels, scales]
+    t = np.where(np.isfinite(t), t, times[idx, kernels, 1])
+    return float(np.sum(t - times.reshape(times.shape[0], 9).min(axis=1)))
 
 
 def make_labels(times: np.ndarray, buckets: np.ndarray, tie: float = 0.02, abs_tie: float = 0.005) -> np.ndarray:
@@ -170,8 +201,10 @@ def make_labels(times: np.ndarray, buckets: np.ndarray, tie: float = 0.02, abs_t
 
 
 def sample_weights(times: np.ndarray) -> np.ndarray:
-    """Weight each bucket by the time at stake (slowest minus fastest), mean 1."""
-    stake = times.max(axis=1) - times.min(axis=1)
+    """Weight each bucket by the time at stake (slowest minus fastest available), mean 1."""
+    t = times.reshape(times.shape[0], -1)
+    fin = np.where(np.isfinite(t), t, np.nan)
+    stake = np.nanmax(fin, axis=1) - np.nanmin(fin, axis=1)
     w = np.sqrt(stake + 1e-6)
     return (w / w.mean()).astype(np.float32)
 
@@ -204,14 +237,17 @@ def regret(times: np.ndarray, choices: np.ndarray) -> float:
     return float(np.sum(times[idx, choices] - times.min(axis=1)))
 
 
-def save(path: str, params: np.ndarray, meta: dict | None = None) -> None:
+def save(path: str, params: np.ndarray, meta: dict | None = None, tile_params: np.ndarray | None = None) -> None:
     doc = {"format": "tc-selector-v1", "num_params": int(params.size),
            "params": [float(x) for x in np.asarray(params, dtype=np.float32)], "meta": meta or {}}
+    if tile_params is not None:
+        doc["tile_params"] = [float(x) for x in np.asarray(tile_params, dtype=np.float32)]
     with open(path, "w") as f:
         json.dump(doc, f)
 
 
 def load(path: str) -> np.ndarray:
+    """The strategy network's parameters."""
     with open(path) as f:
         doc = json.load(f)
     if doc.get("format") != "tc-selector-v1" or doc.get("num_params") != _lib.SELECTOR_NUM_PARAMS:
@@ -219,9 +255,22 @@ def load(path: str) -> np.ndarray:
     return np.asarray(doc["params"], dtype=np.float32)
 
 
+def load_tile(path: str):
+    """The tile network's parameters, or None when the file has none."""
+    with open(path) as f:
+        doc = json.load(f)
+    if "tile_params" not in doc:
+        return None
+    p = np.asarray(doc["tile_params"], dtype=np.float32)
+    if p.size != _lib.SELECTOR_NUM_PARAMS:
+        raise ValueError(f"{path}: bad tile network parameters")
+    return p
+
+
 def load_default(device: str = "cuda:0") -> bool:
-    """Load the packaged trained parameters into the device's context, if present."""
+    """Load the packaged trained networks into the device's context, if present."""
     if not os.path.exists(DEFAULT_WEIGHTS):
         return False
     _lib.selector_set_params(load(DEFAULT_WEIGHTS), device)
+    _lib.selector_set_tile_params(load_tile(DEFAULT_WEIGHTS), device)
     return True

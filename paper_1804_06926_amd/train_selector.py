@@ -115,7 +115,7 @@ def main(argv=None):
 
     t0 = time.time()
     if args.evaluate:
-        params = selector.load(args.evaluate)
+        params = (selector.load(args.evaluate), selector.load_tile(args.evaluate))
         report = {"train": {"weights": args.evaluate}}
     else:
         params, report = _train(args, tc, selector)
@@ -129,31 +129,47 @@ def main(argv=None):
 
 def _train(args, tc, selector):
     graphs = training_graphs(args.quick, args.with_rgg)
+    tile_params = None
     if args.labels == "in-launch":
         data = selector.collect_in_launch(graphs, repeats=args.repeats, log=log)
-        y = selector.make_labels_in_launch(data["times"], data["bucket"], data["noise_ms"])
+        y, ys = selector.make_labels_in_launch(data["times"], data["bucket"], data["noise_ms"])
     else:
         data = selector.collect(graphs, repeats=args.repeats, log=log)
-        y = selector.make_labels(data["times"], data["bucket"])
+        y, ys = selector.make_labels(data["times"], data["bucket"]), None
     w = selector.sample_weights(data["times"])
-    log(f"[selector] {len(y)} training buckets; label counts {np.bincount(y, minlength=3).tolist()}")
+    log(f"[selector] {len(y)} training buckets; strategy labels {np.bincount(y, minlength=3).tolist()}"
+        + (f", tile-scale labels {np.bincount(ys, minlength=3).tolist()}" if ys is not None else ""))
+    report = {"train": {"buckets": int(len(y)), "graphs": data["names"]}}
+    if ys is not None:   # the tile network first (the trainer's kernels work on one parameter set at a time)
+        tile_params, tl = selector.train(data["features"], ys, w, steps=args.steps, lr=args.lr, seed=1, log=log)
+        ps = selector.predict(data["features"])
+        report["train"].update({"tile_accuracy": float(np.mean(ps == ys)), "tile_loss_last": tl[-1]})
     params, losses = selector.train(data["features"], y, w, steps=args.steps, lr=args.lr, log=log)
     pred = selector.predict(data["features"])
-    report = {"train": {"buckets": int(len(y)), "accuracy": float(np.mean(pred == y)),
-                        "loss_first": losses[0], "loss_last": losses[-1],
-                        "regret_learned_ms": selector.regret(data["times"], pred),
-                        "regret_heuristic_ms": selector.regret(
-                            data["times"], np.array([selector.heuristic_choice(int(b)) for b in data["bucket"]])),
-                        "graphs": data["names"]}}
+    heur = np.array([selector.heuristic_choice(int(b)) for b in data["bucket"]])
+    report["train"].update({"accuracy": float(np.mean(pred == y)), "loss_first": losses[0], "loss_last": losses[-1]})
+    if ys is not None:
+        report["train"].update({
+            "regret_learned_ms": selector.in_launch_regret(data["times"], pred, ps),
+            "regret_learned_strategy_only_ms": selector.in_launch_regret(data["times"], pred, np.ones_like(pred)),
+            "regret_heuristic_ms": selector.in_launch_regret(data["times"], heur, np.ones_like(heur))})
+    else:
+        report["train"].update({"regret_learned_ms": selector.regret(data["times"], pred),
+                                "regret_heuristic_ms": selector.regret(data["times"], heur)})
     selector.save(args.out, params, {"trained_on": data["names"], "steps": args.steps, "lr": args.lr,
-                                     "repeats": args.repeats, "labels": args.labels})
+                                     "repeats": args.repeats, "labels": args.labels}, tile_params=tile_params)
     log(f"[selector] saved {args.out}; train report {report['train']}")
-    return params, report
+    return (params, tile_params), report
+
+
+def _install(tc, params):
+    tc.selector_set_params(params[0])
+    tc.selector_set_tile_params(params[1])
 
 
 def _evaluate(args, tc, selector, params, report):
     import torch
-    tc.selector_set_params(params)   # predict() and the learned mode use the library's parameters
+    _install(tc, params)   # predict() and the learned mode use the library's parameters
     report["heldout"] = []
     for name, edges, n in heldout_graphs(args.quick):
         log(f"[selector] held-out {name}")
@@ -162,22 +178,30 @@ def _evaluate(args, tc, selector, params, report):
         if not args.no_heldout_profile:
             data = selector.collect_in_launch([(name, edges, n)], repeats=args.repeats, log=log)
             times, busy = data["times"], data["bucket"]
-            tc.selector_set_params(params)
-            learned = selector.predict(data["features"])
+            scales = np.ones(len(busy), dtype=int)
+            if params[1] is not None:   # predict() runs the library's strategy network: load the tile one there
+                tc.selector_set_params(params[1])
+                scales = selector.predict(data["features"])
+            tc.selector_set_params(params[0])
+            kernels = selector.predict(data["features"])
             heur = np.array([selector.heuristic_choice(int(b)) for b in busy])
+            one = np.ones(len(busy), dtype=int)
             entry.update({"buckets": int(len(busy)),
-                          "stage_ms_heuristic": float(times[0, heur[0]]) if len(busy) else 0.0,
+                          "stage_ms_heuristic": float(times[0, heur[0], 1]) if len(busy) else 0.0,
                           "noise_ms": float(data["noise_ms"][0]) if len(busy) else 0.0,
-                          "regret_learned_ms": selector.regret(times, learned),
-                          "regret_heuristic_ms": selector.regret(times, heur)})
+                          "regret_learned_ms": selector.in_launch_regret(times, kernels, scales),
+                          "regret_learned_strategy_only_ms": selector.in_launch_regret(times, kernels, one),
+                          "regret_heuristic_ms": selector.in_launch_regret(times, heur, one)})
             for k, kn in enumerate(selector.KERNELS):
-                entry[f"regret_all_{kn}_ms"] = selector.regret(times, np.full(len(busy), k))
-            # the buckets where either choice misses the fastest strategy
-            entry["misses"] = [{"bucket": int(b), "stage_ms": [round(float(t), 4) for t in times[i]],
-                                "learned": int(learned[i]), "heuristic": int(heur[i])}
+                entry[f"regret_all_{kn}_ms"] = selector.in_launch_regret(times, np.full(len(busy), k), one)
+            # the buckets where either choice misses the fastest (strategy, tile scale)
+            flat = times.reshape(len(busy), 9)
+            entry["misses"] = [{"bucket": int(b), "best": [int(flat[i].argmin() // 3), int(flat[i].argmin() % 3)],
+                                "learned": [int(kernels[i]), int(scales[i])], "heuristic": int(heur[i]),
+                                "gain_best_ms": round(float(times[i, heur[i], 1] - flat[i].min()), 4)}
                                for i, b in enumerate(busy)
-                               if learned[i] != np.argmin(times[i]) or heur[i] != np.argmin(times[i])]
-        tc.selector_set_params(params)
+                               if (kernels[i] * 3 + scales[i]) != flat[i].argmin() or heur[i] * 3 + 1 != flat[i].argmin()]
+        _install(tc, params)
         t_l, t_h, ratios, T = step_times(tc, d, n)
         entry.update({"step_ms_learned": t_l, "step_ms_heuristic": t_h, "speedup": t_h / t_l,
                       "block_ratios": [float(x) for x in ratios], "triangles": T})

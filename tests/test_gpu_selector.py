@@ -140,29 +140,38 @@ def test_device_heuristic_matches_host_rule(tc):
 
 
 def test_trained_selector_gains_over_heuristic(tc):
-    """Held-out graphs (an R-MAT scale 21 seed and a random geometric graph, neither
-    used in training): the time the learned choice leaves on the table (its regret
-    against the per-bucket best strategy, from timings taken in this run) is not
-    above the fixed-threshold heuristic's, up to a timing-noise allowance of 3% of
-    the best total; counts are identical in both modes."""
+    """Held-out graphs (R-MAT scale 22 seed 77, and a random geometric graph of 2^20
+    vertices; neither in the training set): every (strategy, tile size) alternative of
+    every busy bucket is timed inside the combined launch, and the time the learned
+    choice leaves on the table (its regret against the per-bucket best) must be below
+    the fixed thresholds' by more than the spread of repeated baseline timings, summed
+    over the graphs; counts are identical in both modes."""
     import torch
     from paper_1804_06926_amd import selector
     if not os.path.exists(selector.DEFAULT_WEIGHTS):
         pytest.skip("no trained selector weights in the package yet")
-    selector.load_default()
-    for name, e, n in (("rmat21", graphgen.rmat(21, 16, seed=77), 1 << 21),
+    params, tile = selector.load(selector.DEFAULT_WEIGHTS), selector.load_tile(selector.DEFAULT_WEIGHTS)
+    r_l = r_h = noise = 0.0
+    for name, e, n in (("rmat22", graphgen.rmat(22, 16, seed=77), 1 << 22),
                        ("rgg20", graphgen.rgg(1 << 20, 32.0, seed=78), 1 << 20)):
+        data = selector.collect_in_launch([(name, e, n)], repeats=5)
+        busy = data["bucket"]
+        scales = np.ones(len(busy), dtype=int)
+        if tile is not None:   # predict() runs the library's strategy network: load the tile one there
+            tc.selector_set_params(tile)
+            scales = selector.predict(data["features"])
+        tc.selector_set_params(params)
+        kernels = selector.predict(data["features"])
+        heur = np.array([selector.heuristic_choice(int(b)) for b in busy])
+        gl = selector.in_launch_regret(data["times"], kernels, scales)
+        gh = selector.in_launch_regret(data["times"], heur, np.ones_like(heur))
+        print(f"{name}: in-launch regret learned {gl:.3f} ms, heuristic {gh:.3f} ms, "
+              f"baseline spread {data['noise_ms'][0]:.3f} ms")
+        r_l, r_h, noise = r_l + gl, r_h + gh, noise + float(data["noise_ms"][0])
+        selector.load_default()
         d = torch.from_numpy(e).cuda()
-        ms, feat = tc.profile_buckets(d, n, repeats=5)
-        busy = [b for b in range(255) if np.all(ms[:, b] > 0)]
-        times = ms[:, busy].T.astype(np.float64)
-        learned = selector.predict(feat[busy])
-        heur = np.array([selector.heuristic_choice(b) for b in busy])
-        r_l, r_h = selector.regret(times, learned), selector.regret(times, heur)
-        best = times.min(axis=1).sum()
-        print(f"{name}: regret learned {r_l:.3f} ms, heuristic {r_h:.3f} ms, best total {best:.3f} ms")
-        assert r_l <= r_h + 0.03 * best, (name, r_l, r_h, best)
         assert tc.count_triangles(d, n, select=tc.SELECT_LEARNED) == tc.count_triangles(d, n)
+    assert r_l + noise < r_h, (r_l, r_h, noise)
 
 
 def test_window_feature_matches_host_count(tc):
@@ -224,7 +233,8 @@ def test_profile_choices_applies_the_given_strategies(tc):
     d = torch.from_numpy(e).cuda()
     T = oracle.count_triangles(e, n)
     ms, per, Tx = tc.profile_choices(d, n, np.full(256, 255, np.uint8), repeats=3)
-    assert Tx == T and ms > 0 and np.all(per >= 0) and abs(per.sum() - ms) < 1e-3
+    # medians of the stage and of each kernel over the repeats: close, not equal
+    assert Tx == T and ms > 0 and np.all(per >= 0) and abs(per.sum() - ms) <= 0.25 * ms
     st = tc.last_stats()
     busy = np.nonzero(st["bucket_vertices"][:255])[0]
     for b in range(255):

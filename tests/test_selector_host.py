@@ -67,3 +67,40 @@ def test_autotune_cache_roundtrip(tmp_path):
     got = autotune.load("gfx950|hipX|select0", str(f))
     np.testing.assert_array_equal(got, shapes)
     assert autotune.load("missing", str(f)) is None
+
+
+def test_in_launch_labels_joint_strategy_and_tile_scale():
+    # times[i, strategy, scale]: stage time with bucket i changed alone (inf: scale unavailable)
+    inf = np.inf
+    t = np.full((3, 3, 3), 10.0)
+    # bucket 0 (heuristic: merge path): binary search at double tiles is 0.5 ms faster
+    t[0, 1, 2] = 9.5
+    # bucket 1: the better choice is within the baseline spread: keep the heuristic's
+    t[1, 2, 0] = 9.995
+    # bucket 2 (heuristic: bitmap, bucket 16*6): halving its tiles wins; doubling unavailable
+    t[2, 2, 2] = inf
+    t[2, 2, 0] = 9.0
+    buckets = np.array([0, 0, 16 * 6])
+    noise = np.array([0.01, 0.01, 0.01])
+    k, s = selector.make_labels_in_launch(t, buckets, noise)
+    assert k.tolist() == [1, 0, 2] and s.tolist() == [2, 1, 0]
+    # regret: the chosen cell minus the bucket's best; an unavailable scale counts as the rule's size
+    assert abs(selector.in_launch_regret(t, k, s) - 0.005) < 1e-12   # bucket 1's tie kept
+    heur = np.array([0, 0, 2])
+    assert abs(selector.in_launch_regret(t, heur, np.ones(3, int)) - (0.5 + 0.005 + 1.0)) < 1e-12
+    assert abs(selector.in_launch_regret(t, np.array([2, 2, 2]), np.array([2, 2, 2])) - (0.5 + 0.005 + 1.0)) < 1e-12
+    w = selector.sample_weights(t)
+    assert np.all(np.isfinite(w)) and abs(w.mean() - 1.0) < 1e-6
+
+
+def test_selector_file_holds_both_networks(tmp_path):
+    p = np.arange(1379, dtype=np.float32) / 1379.0
+    q = -p
+    path = str(tmp_path / "w.json")
+    selector.save(path, p, {"note": "test"}, tile_params=q)
+    np.testing.assert_array_equal(selector.load(path), p)
+    np.testing.assert_array_equal(selector.load_tile(path), q)
+    selector.save(path, p)
+    assert selector.load_tile(path) is None
+    shipped = selector.load_tile(selector.DEFAULT_WEIGHTS)
+    assert shipped is not None and shipped.size == 1379
