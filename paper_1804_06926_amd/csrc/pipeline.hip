@@ -178,8 +178,8 @@ static void launch_bucket_count(const uint32_t* ep, const uint32_t* bst, int bw,
         hipLaunchKernelGGL((k_bucket_count<12, NT>), grid, dim3(NT), 0, s, ep, bst, bw, parts, splits, n, deg);
     else if (cw == 13)
         hipLaunchKernelGGL((k_bucket_count<13, NT>), grid, dim3(NT), 0, s, ep, bst, bw, parts, splits, n, deg);
-    else if (cw == 14)
-        hipLaunchKernelGGL((k_bucket_count<14, NT>), grid, dim3(NT), 0, s, ep, bst, bw, parts, splits, n, deg);
+    else if (cw == 14)   // ids past 24 bits: 2^14 counters (64 KB), 1024 threads (8 blocks ran 2 waves per SIMD)
+        hipLaunchKernelGGL((k_bucket_count<14, 1024>), grid, dim3(1024), 0, s, ep, bst, bw, parts, splits, n, deg);
     else
         hipLaunchKernelGGL((k_bucket_count<DEG_MAX_CW, 1024>), grid, dim3(1024), 0, s, ep, bst, bw, parts, splits, n,
                            deg);

@@ -247,24 +247,24 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ k
         dg[it] = i < n ? (uint32_t)(keys[i] >> shift) & dmask : 0u;
     }
     // counts only (no ranks): one LDS atomic per key into the wave's histogram.
-    // 64-bit keys here hold degree ranks, whose top digit is dominated by the
-    // hubs' in-edges: lanes that share a digit with the wave's first or second
-    // leading lane are added once by that lane, instead of serialising up to 64
-    // atomics on one counter. (32-bit keys are input vertex ids: no such skew by
-    // construction, and the extra ballots would only cost.)
+    // Lanes that share a digit with the wave's first or second leading lane are
+    // added once by that lane, instead of serialising up to 64 atomics on one
+    // counter: 64-bit keys here hold degree ranks, whose top digit is dominated by
+    // the hubs' in-edges, and a 32-bit histogram runs only for the second
+    // partition pass of wide vertex ids (the degree stage past 24 bits), whose
+    // keys the first pass has grouped by their top bits, so neighbouring lanes
+    // often share the next digit too.
 #pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
         uint64_t act = __ballot(base + it * WAVE + l < n);
-        if constexpr (sizeof(KeyT) == 8) {
 #pragma unroll
-            for (int pk = 0; pk < 2; ++pk) {
-                if (!act) break;
-                const int lead = __builtin_ctzll(act);
-                const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)dg[it], lead);
-                const uint64_t m = __ballot(dg[it] == dl) & act;
-                if (l == lead) atomicAdd(&wcnt[w][dl], (uint32_t)__popcll(m));
-                act &= ~m;
-            }
+        for (int pk = 0; pk < 2; ++pk) {
+            if (!act) break;
+            const int lead = __builtin_ctzll(act);
+            const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)dg[it], lead);
+            const uint64_t m = __ballot(dg[it] == dl) & act;
+            if (l == lead) atomicAdd(&wcnt[w][dl], (uint32_t)__popcll(m));
+            act &= ~m;
         }
         if ((act >> l) & 1u) atomicAdd(&wcnt[w][dg[it]], 1u);
     }
