@@ -353,8 +353,8 @@ def main(argv=None):
                     help="also run one device-to-device copy of MIB MiB (calibrates counter-based traffic)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print(f"bench.py: the counter runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(sharding across GPUs is designed, not implemented)", file=sys.stderr)
         return 2
 
     import torch

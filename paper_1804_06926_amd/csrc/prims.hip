@@ -205,18 +205,19 @@ void scan_exclusive_sum_u64(const uint64_t* in, uint64_t* out, size_t len, void*
 // ------------------------------------------------------------------ radix sort
 // A tile is RS_NT threads x ITEMS keys: 16 keys per lane (4096-key tiles, longer
 // runs of equal digits for the scatter, half the count table) for sorts of at
-// least 2^22 keys, 8 (2048-key tiles, twice the blocks) below, and 32 for
-// 64-bit sorts of at least 2^26 keys (8192-key tiles: the scatter's runs of a
-// uniform digit grow from 16 to 32 keys, 256 B; two blocks per CU). Sorts of
-// 32-bit keys keep 4096 there: at two blocks per CU their scatter lost more to
-// latency than it gained in write runs.
+// least 2^22 keys, 8 (2048-key tiles, twice the blocks) below, and 32 for sorts
+// of at least 2^26 keys (8192-key tiles: the scatter's runs of a uniform digit
+// grow from 16 to 32 keys; its blocks run 512 threads of 16 keys, so they keep
+// four waves per SIMD). For the 32-bit endpoint partition of R-MAT 24 (2^29 keys)
+// the 8192-key tiles took the degree stage from 4.00 to 3.79 ms; with 256
+// threads of 32 keys they had lost (two waves per SIMD).
 constexpr int RS_NT = 256;
 constexpr int RS_WAVES = RS_NT / WAVE;
 constexpr int RS_ITEMS_SMALL = 8, RS_ITEMS_LARGE = 16, RS_ITEMS_HUGE = 32;
 constexpr size_t RS_LARGE_CAP = (size_t)1 << 22, RS_HUGE_CAP = (size_t)1 << 26;
 
 uint32_t radix_tile_keys(size_t cap, int key_bytes) {
-    const int items = cap >= RS_HUGE_CAP && key_bytes == 8 ? RS_ITEMS_HUGE
+    const int items = cap >= RS_HUGE_CAP ? RS_ITEMS_HUGE
                       : cap >= RS_LARGE_CAP                ? RS_ITEMS_LARGE
                                                            : RS_ITEMS_SMALL;
     return (uint32_t)(RS_NT * items);
