@@ -30,12 +30,27 @@ int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t*
 // Keys per tile of a sort of cap keys of key_bytes bytes (2048, 4096 or 8192;
 // a multiple of 2048).
 uint32_t radix_tile_keys(size_t cap, int key_bytes);
+// What a radix pass does to each key as it loads it (the orientation's passes):
+//   RX_NONE      nothing;
+//   RX_RANK_LOW  the low 32 bits, a vertex id a, become rank[a] (0xFFFFFFFF for a
+//                outside [0, n)); the pass's digit must lie in the high half;
+//   RX_ORIENT    (b << 32 | rank of a) becomes the oriented pair key
+//                (min rank << nb | max rank), or `sentinel` for a pair with an
+//                invalid id or a loop (equal ranks); digits come from the result.
+enum { RX_NONE = 0, RX_RANK_LOW = 1, RX_ORIENT = 2 };
+struct RadixXf {
+    int kind;
+    const uint32_t* rank;
+    int32_t n;
+    int nb;
+    uint64_t sentinel;
+};
 // One stable radix pass of 64-bit keys on bits [shift, shift + bits), bits <= 8,
-// from kin to kout (the two must differ); with rank set, the low 32 bits of each
-// key, a vertex id, are replaced by rank[id] as the key moves (0xFFFFFFFF for
-// ids outside [0, n)); the pass's digit must lie in the high half then.
-void radix_pass_u64(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const uint32_t* rank,
-                    int32_t n, void* temp, hipStream_t s);
+// from kin to kout (the two must differ), each key transformed as `xf` says.
+void radix_pass_u64(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& xf,
+                    void* temp, hipStream_t s);
+// Digit width of each pass of a sort over `bits` bits (equal widths, at most 8).
+int radix_digit_width(int bits);
 struct RadixDigit {
     int shift;
     uint32_t mask;

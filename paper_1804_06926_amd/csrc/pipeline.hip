@@ -281,57 +281,17 @@ __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, u
     }
 }
 
-// Orientation of pairs already partitioned on their ids' high bits. Past 2^21
-// vertices the rank table (4 bytes per vertex) outgrows an XCD's 4 MB L2, and two
-// random rank gathers per pair cost two cache lines from beyond it. Instead the
-// pairs pass through two stable radix passes (radix_pass_u64): one on the high
-// bits of the first id, one on the high bits of the second that also replaces the
-// first id by its rank as the pair moves; the blocks of a pass then look up ranks
-// in a few 2^(vbits - 8)-id ranges at a time, which stay in L2. This kernel reads
-// (second id << 32 | rank of the first id), grouped by the second id's high bits,
-// looks up the second rank and writes the oriented key in place.
+// Orientation past 2^21 vertices. There the rank table (4 bytes per vertex)
+// outgrows an XCD's 4 MB L2, and two random rank gathers per pair cost two cache
+// lines from beyond it. Instead the pairs pass through two stable radix passes
+// (radix_pass_u64): one on the high bits of the first id, one on the high bits of
+// the second that also replaces the first id by its rank as the pair moves. The
+// first pass of the pair sort then reads (second id << 32 | rank of the first
+// id), grouped by the second id's high bits, looks up the second rank and forms
+// the oriented key as it loads each pair (RX_ORIENT, in its histogram and its
+// scatter alike). The blocks of each pass look up ranks in a few
+// 2^(vbits - 8)-id ranges at a time, which stay in L2.
 constexpr int ORIENT_PART_MIN_BITS = 21;
-template <int U>
-__global__ __launch_bounds__(NT) void k_orient_ranked(uint64_t* __restrict__ keys, uint64_t E, int32_t n,
-                                                      const uint32_t* __restrict__ rank, int nb, uint64_t sentinel,
-                                                      uint32_t* __restrict__ counts, uint32_t ntiles,
-                                                      uint32_t tile_keys, RadixDigit dg) {
-    __shared__ TileCounts tc;
-    tc.clear();
-    __syncthreads();
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-      for (uint32_t r = 0; r < tile_keys; r += U * NT) {
-        const uint64_t i0 = (uint64_t)tile * tile_keys + r + threadIdx.x;
-        uint64_t kk[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const uint64_t i = i0 + (uint64_t)k * NT;
-            kk[k] = i < E ? keys[i] : ~0ull;
-        }
-        uint32_t ra[U], rb[U];
-        bool ok[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int32_t b = (int32_t)(uint32_t)(kk[k] >> 32);
-            ra[k] = (uint32_t)kk[k];
-            ok[k] = ra[k] != 0xFFFFFFFFu && b >= 0 && b < n;
-            rb[k] = rank[ok[k] ? b : 0];
-        }
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const uint64_t i = i0 + (uint64_t)k * NT;
-            if (i < E) {
-                const bool good = ok[k] && ra[k] != rb[k];   // equal ranks: a self-loop
-                const uint32_t lo = ra[k] < rb[k] ? ra[k] : rb[k], hi = ra[k] < rb[k] ? rb[k] : ra[k];
-                const uint64_t key = good ? (((uint64_t)lo << nb) | hi) : sentinel;
-                keys[i] = key;
-                if (counts) tc.add((uint32_t)(key >> dg.shift) & dg.mask);
-            }
-        }
-      }
-        if (counts) tc.flush(counts, ntiles, tile);
-    }
-}
 
 // ------------------------------------------------------------------ unique + CSR
 // The sorted pair keys in runs of equal keys: the first of each run is kept,
@@ -1195,19 +1155,14 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     const uint64_t sentinel = (2 * nb >= 64) ? ~0ull : ((1ull << (2 * nb)) - 1ull);
     const uint32_t e_tile = radix_tile_keys((size_t)E, 8);
     const uint32_t e_tiles = (uint32_t)(((uint64_t)E + e_tile - 1) / e_tile);
-    if (vbits >= ORIENT_PART_MIN_BITS) {
+    const bool part = vbits >= ORIENT_PART_MIN_BITS;
+    if (part) {
         // pairs by their first id's high bits, then by their second's (first id -> rank)
         const int ob = 8;
-        radix_pass_u64((const uint64_t*)edges, keysB, (size_t)E, vbits - ob, ob, nullptr, n, radix_tmp, s);
-        radix_pass_u64(keysB, keysA, (size_t)E, 32 + vbits - ob, ob, rank, n, radix_tmp, s);
-        if (e_tile % (16 * NT) == 0)
-            hipLaunchKernelGGL(k_orient_ranked<16>, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, keysA,
-                               (uint64_t)E, n, rank, nb, sentinel, radix_first_counts(radix_tmp), e_tiles, e_tile,
-                               radix_first_digit(0, 2 * nb));
-        else
-            hipLaunchKernelGGL(k_orient_ranked<OR_U>, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s,
-                               keysA, (uint64_t)E, n, rank, nb, sentinel, radix_first_counts(radix_tmp), e_tiles,
-                               e_tile, radix_first_digit(0, 2 * nb));
+        radix_pass_u64((const uint64_t*)edges, keysB, (size_t)E, vbits - ob, ob, RadixXf{RX_NONE, nullptr, n, 0, 0},
+                       radix_tmp, s);
+        radix_pass_u64(keysB, keysA, (size_t)E, 32 + vbits - ob, ob, RadixXf{RX_RANK_LOW, rank, n, 0, 0}, radix_tmp,
+                       s);
     } else if (e_tile % (16 * NT) == 0)
         hipLaunchKernelGGL(k_orient<16>, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, edges,
                            (uint64_t)E, n, rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, e_tile,
@@ -1217,9 +1172,16 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
                            (uint64_t)E, n, rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, e_tile,
                            radix_first_digit(0, 2 * nb));
     mark(3);
-    // ---- sort oriented pairs (first digit counted by k_orient)
-    const int alt =
-        radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)E, 0, 2 * nb, radix_tmp, s, true);
+    // ---- sort oriented pairs: the first digit counted by k_orient, or, past 2^21
+    // vertices, a first pass that orients each pair as it loads it
+    int alt;
+    if (part) {
+        const int w0 = radix_digit_width(2 * nb);
+        radix_pass_u64(keysA, keysB, (size_t)E, 0, w0, RadixXf{RX_ORIENT, rank, n, nb, sentinel}, radix_tmp, s);
+        alt = 1 - radix_sort_u64(keysB, keysA, nullptr, nullptr, nullptr, (size_t)E, w0, 2 * nb, radix_tmp, s);
+    } else {
+        alt = radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)E, 0, 2 * nb, radix_tmp, s, true);
+    }
     uint64_t* sorted = alt ? keysB : keysA;
     uint64_t* other = alt ? keysA : keysB;
     mark(4);

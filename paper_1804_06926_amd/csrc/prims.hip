@@ -228,12 +228,50 @@ __device__ __forceinline__ uint32_t rs_count(const uint32_t* d_count, uint32_t c
     return c < cap ? c : cap;
 }
 
-// Per-tile digit counts, written digit-major: hist[d * ntiles + tile].
-template <typename KeyT, int RS_ITEMS>
+// Keys move unchanged.
+struct XfIdentity {
+    template <typename KeyT>
+    __device__ __forceinline__ KeyT operator()(KeyT k) const { return k; }
+};
+// 64-bit keys whose low 32 bits are a vertex id: the id is replaced by its rank
+// (ids outside [0, n): 0xFFFFFFFF) as the key moves; the high half, which holds
+// the digit of the pass, is unchanged.
+struct XfRankLow {
+    const uint32_t* rank;
+    int32_t n;
+    __device__ __forceinline__ uint64_t operator()(uint64_t k) const {
+        const int32_t a = (int32_t)(uint32_t)k;
+        const uint32_t r = (a >= 0 && a < n) ? rank[a] : 0xFFFFFFFFu;
+        return (k & 0xFFFFFFFF00000000ull) | r;
+    }
+};
+
+// (b << 32 | rank of a) -> the oriented pair key (min rank << nb | max rank),
+// or the sentinel (an invalid id, or a loop: equal ranks). The rank of b is
+// looked up here; the pass before left the keys grouped by b's high bits.
+struct XfOrient {
+    const uint32_t* rank;
+    int32_t n;
+    int nb;
+    uint64_t sentinel;
+    __device__ __forceinline__ uint64_t operator()(uint64_t k) const {
+        const int32_t b = (int32_t)(uint32_t)(k >> 32);
+        const uint32_t ra = (uint32_t)k;
+        const bool okb = b >= 0 && b < n;
+        const uint32_t rb = rank[okb ? b : 0];
+        const bool good = okb && ra != 0xFFFFFFFFu && ra != rb;
+        const uint32_t lo = ra < rb ? ra : rb, hi = ra < rb ? rb : ra;
+        return good ? (((uint64_t)lo << nb) | hi) : sentinel;
+    }
+};
+
+// Per-tile digit counts, written digit-major: hist[d * ntiles + tile]; digits of
+// the keys as xf transforms them.
+template <typename KeyT, int RS_ITEMS, typename XF = XfIdentity>
 __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ keys, const uint32_t* d_count,
                                                       uint32_t cap, int shift, uint32_t dmask,
                                                       uint32_t* __restrict__ hist,
-                                                      uint32_t ntiles) {
+                                                      uint32_t ntiles, XF xf = XF()) {
     constexpr int RS_TILE = RS_NT * RS_ITEMS, RS_WAVE_SPAN = WAVE * RS_ITEMS;   // keys per tile / per wave
     __shared__ uint32_t wcnt[RS_WAVES][256];
     for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
@@ -242,10 +280,16 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ k
     const int w = wave_id(), l = lane_id();
     const uint32_t base = blockIdx.x * RS_TILE + w * RS_WAVE_SPAN;
     uint32_t dg[RS_ITEMS];
+    KeyT kk[RS_ITEMS];
 #pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
         const uint32_t i = base + it * WAVE + l;
-        dg[it] = i < n ? (uint32_t)(keys[i] >> shift) & dmask : 0u;
+        kk[it] = i < n ? keys[i] : KeyT(0);
+    }
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint32_t i = base + it * WAVE + l;
+        dg[it] = i < n ? (uint32_t)(xf(kk[it]) >> shift) & dmask : 0u;
     }
     // counts only (no ranks): one LDS atomic per key into the wave's histogram.
     // Lanes that share a digit with the wave's first or second leading lane are
@@ -329,24 +373,6 @@ __global__ __launch_bounds__(RS_NT) void k_radix_rowfix(uint32_t* __restrict__ h
     const uint32_t s1 = s0 + RS_ROW_SEG < ntiles ? s0 + RS_ROW_SEG : ntiles;
     for (uint32_t i = s0 + threadIdx.x; i < s1; i += RS_NT) row[i] += carry;
 }
-
-// Keys move unchanged.
-struct XfIdentity {
-    template <typename KeyT>
-    __device__ __forceinline__ KeyT operator()(KeyT k) const { return k; }
-};
-// 64-bit keys whose low 32 bits are a vertex id: the id is replaced by its rank
-// (ids outside [0, n): 0xFFFFFFFF) as the key moves; the high half, which holds
-// the digit of the pass, is unchanged.
-struct XfRankLow {
-    const uint32_t* rank;
-    int32_t n;
-    __device__ __forceinline__ uint64_t operator()(uint64_t k) const {
-        const int32_t a = (int32_t)(uint32_t)k;
-        const uint32_t r = (a >= 0 && a < n) ? rank[a] : 0xFFFFFFFFu;
-        return (k & 0xFFFFFFFF00000000ull) | r;
-    }
-};
 
 // NT_ threads of RS_ITEMS keys each: 8192-key tiles run 512 threads of 16 keys
 // (half the registers per lane of 256 x 32, twice the waves per CU); threads
@@ -534,9 +560,9 @@ static int radix_sort_any(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* 
                                             first_counted);
 }
 
-template <int RS_ITEMS>
-static void radix_pass_relabel(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits,
-                               const uint32_t* rank, int32_t n, void* temp, hipStream_t s) {
+template <int RS_ITEMS, typename XF>
+static void radix_pass_xf(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, XF xf,
+                          bool hist_xf, void* temp, hipStream_t s) {
     const uint32_t ntiles = (uint32_t)rs_ntiles(cap, RS_NT * RS_ITEMS);
     uint32_t* hist = (uint32_t*)temp;
     void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * (ntiles + 1), 256);
@@ -544,35 +570,46 @@ static void radix_pass_relabel(const uint64_t* kin, uint64_t* kout, size_t cap, 
     uint32_t* seg_tot = (uint32_t*)((char*)scan_tmp + align_up(scan_temp_bytes(), 256));
     const uint32_t nseg = (uint32_t)rs_nseg(ntiles);
     const uint32_t dmask = (1u << bits) - 1u;
-    hipLaunchKernelGGL((k_radix_hist<uint64_t, RS_ITEMS>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr,
-                       (uint32_t)cap, shift, dmask, hist, ntiles);
+    if (hist_xf)   // the digit depends on the transformed key
+        hipLaunchKernelGGL((k_radix_hist<uint64_t, RS_ITEMS, XF>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr,
+                           (uint32_t)cap, shift, dmask, hist, ntiles, xf);
+    else
+        hipLaunchKernelGGL((k_radix_hist<uint64_t, RS_ITEMS>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr,
+                           (uint32_t)cap, shift, dmask, hist, ntiles, XfIdentity());
     hipLaunchKernelGGL(k_radix_rowscan, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, digit_tot, seg_tot);
     if (nseg > 1)
         hipLaunchKernelGGL(k_radix_rowfix, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, seg_tot, digit_tot);
     constexpr bool HUGE_TILES = RS_ITEMS == RS_ITEMS_HUGE;   // 8192-key tiles: 512 threads of 16 keys
     constexpr int IT = HUGE_TILES ? RS_ITEMS / 2 : RS_ITEMS;
     constexpr int NTS = HUGE_TILES ? 2 * RS_NT : RS_NT;
-    if (rank)
-        hipLaunchKernelGGL((k_radix_scatter<uint64_t, false, IT, NTS, XfRankLow>), dim3(ntiles), dim3(NTS), 0, s,
-                           kin, nullptr, kout, nullptr, nullptr, (uint32_t)cap, shift, dmask, hist, ntiles,
-                           digit_tot, XfRankLow{rank, n});
-    else
-        hipLaunchKernelGGL((k_radix_scatter<uint64_t, false, IT, NTS>), dim3(ntiles), dim3(NTS), 0, s, kin, nullptr,
-                           kout, nullptr, nullptr, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot,
-                           XfIdentity());
+    hipLaunchKernelGGL((k_radix_scatter<uint64_t, false, IT, NTS, XF>), dim3(ntiles), dim3(NTS), 0, s, kin, nullptr,
+                       kout, nullptr, nullptr, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot, xf);
 }
 
-void radix_pass_u64(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const uint32_t* rank,
-                    int32_t n, void* temp, hipStream_t s) {
+template <int RS_ITEMS>
+static void radix_pass_kind(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& x,
+                            void* temp, hipStream_t s) {
+    if (x.kind == RX_RANK_LOW)   // the digit lies in the untouched high half
+        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfRankLow{x.rank, x.n}, false, temp, s);
+    else if (x.kind == RX_ORIENT)
+        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfOrient{x.rank, x.n, x.nb, x.sentinel}, true, temp, s);
+    else
+        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfIdentity(), false, temp, s);
+}
+
+void radix_pass_u64(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& xf,
+                    void* temp, hipStream_t s) {
     if (cap == 0 || bits <= 0) return;
     const uint32_t tile = radix_tile_keys(cap, 8);
     if (tile == RS_NT * RS_ITEMS_HUGE)
-        radix_pass_relabel<RS_ITEMS_HUGE>(kin, kout, cap, shift, bits, rank, n, temp, s);
+        radix_pass_kind<RS_ITEMS_HUGE>(kin, kout, cap, shift, bits, xf, temp, s);
     else if (tile == RS_NT * RS_ITEMS_LARGE)
-        radix_pass_relabel<RS_ITEMS_LARGE>(kin, kout, cap, shift, bits, rank, n, temp, s);
+        radix_pass_kind<RS_ITEMS_LARGE>(kin, kout, cap, shift, bits, xf, temp, s);
     else
-        radix_pass_relabel<RS_ITEMS_SMALL>(kin, kout, cap, shift, bits, rank, n, temp, s);
+        radix_pass_kind<RS_ITEMS_SMALL>(kin, kout, cap, shift, bits, xf, temp, s);
 }
+
+int radix_digit_width(int bits) { return digit_width(bits); }
 
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted) {
