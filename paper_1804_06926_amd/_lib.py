@@ -67,6 +67,7 @@ def _load():
     lib.tc_radix_sort_workspace_size.argtypes = [i64]
     lib.tc_radix_sort_workspace_size.restype = sz
     lib.tc_radix_sort_u64.argtypes = [vp, vp, vp, i64, i32, i32, vp, sz]
+    lib.tc_sort_runs_u64.argtypes = [vp, vp, vp, i64, i32]
     lib.tc_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
     lib.tc_stage_times.restype = i32
     lib.tc_stage_name.argtypes = [i32]
@@ -76,7 +77,7 @@ def _load():
     for f in ("tc_create", "tc_destroy", "tc_workspace_size", "tc_count_triangles", "tc_count_triangles_async",
               "tc_clustering", "tc_edge_support", "tc_list_workspace_size", "tc_list_triangles",
               "tc_edge_counts",
-              "tc_build_csr", "tc_radix_sort_u64"):
+              "tc_build_csr", "tc_radix_sort_u64", "tc_sort_runs_u64"):
         getattr(lib, f).restype = ctypes.c_int
     _ = u32
     _lib = lib
@@ -411,6 +412,19 @@ def radix_sort_u64(keys, bit_lo: int = 0, bit_hi: int = 64):
     ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=keys.device)
     alt = torch.empty_like(keys)
     st = lib.tc_radix_sort_u64(ctx, keys.data_ptr(), alt.data_ptr(), n, bit_lo, bit_hi, ws.data_ptr(), nbytes)
+    _check(st, ctx)
+    return keys
+
+
+def sort_runs_u64(keys, shift: int):
+    """Sort, in place, each run of equal keys >> shift of a 64-bit CUDA tensor by the whole key
+    (the keys grouped by their high bits beforehand give a sorted tensor)."""
+    torch = _torch()
+    if not (isinstance(keys, torch.Tensor) and keys.is_cuda and keys.element_size() == 8 and keys.is_contiguous()):
+        raise TypeError("keys must be a contiguous 64-bit CUDA tensor")
+    ctx, idx = _ctx(keys.device)
+    tmp = torch.empty_like(keys)
+    st = _load().tc_sort_runs_u64(ctx, keys.data_ptr(), tmp.data_ptr(), keys.numel(), shift)
     _check(st, ctx)
     return keys
 

@@ -503,6 +503,22 @@ tc_status tc_radix_sort_u64(tc_ctx* ctx, uint64_t* d_keys, uint64_t* d_keys_alt,
     return TC_OK;
 }
 
+tc_status tc_sort_runs_u64(tc_ctx* ctx, uint64_t* d_keys, uint64_t* d_tmp, int64_t count, int32_t shift) {
+    if (!ctx) return TC_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    if (count < 0 || shift < 1 || shift > 32) return arg_fail(ctx, TC_ERR_INVALID_ARG, "bad count or shift");
+    if (count > kMaxEdges) return arg_fail(ctx, TC_ERR_UNSUPPORTED, "count must be < 2^31");
+    if (count == 0) return TC_OK;
+    if (!d_keys || !d_tmp) return arg_fail(ctx, TC_ERR_INVALID_ARG, "null pointer");
+    if ((uintptr_t)d_keys % 16 != 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "keys must be 16-byte aligned");
+    DeviceGuard guard(ctx->device);
+    tcx::sort_runs_u64(d_keys, d_tmp, (size_t)count, shift, false, 0ull, ctx->stream);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "run sort");
+    return TC_OK;
+}
+
 tc_status tc_last_stats(const tc_ctx* ctx, tc_stats* out) {
     if (!ctx || !out) return TC_ERR_INVALID_ARG;
     const tcx::Ctrl& c = *ctx->h_ctrl;

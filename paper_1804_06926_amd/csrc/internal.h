@@ -61,6 +61,14 @@ RadixDigit radix_first_digit(int bit_lo, int bit_hi);
 // rows, ntiles = ceil(cap / radix_tile_keys(cap, key bytes)).
 uint32_t* radix_first_counts(void* temp);
 
+// ---- runsort.hip
+// Keys grouped by key >> shift (ascending; 1 <= shift <= 32) are sorted by the
+// whole key inside each run of equal high bits, in place; keys 16-byte aligned,
+// tmp as many keys as keys (scratch for runs longer than 2048). With skip, a
+// run whose first key is skip_key (it must hold only that key) is left alone.
+void sort_runs_u64(uint64_t* keys, uint64_t* tmp, size_t len, int shift, bool skip, uint64_t skip_key,
+                   hipStream_t s);
+
 // ---- control block shared by all stages (device memory, zeroed per call)
 constexpr int NBUCKET = 256;          // degree-pair buckets; 255 = no work
 constexpr int BUCKET_NONE = 255;

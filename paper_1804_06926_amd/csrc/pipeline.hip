@@ -1000,7 +1000,7 @@ static IsectArgs isect_args(const RunArgs& r, const Layout& L, uint64_t* csc) {
 static uint64_t* csc_of(const RunArgs& r, const Layout& L) {
     char* ws = (char*)r.ws;
     const int nb = bits_for((uint64_t)r.n) > 0 ? bits_for((uint64_t)r.n) : 1;
-    const int p1 = (2 * nb + 7) / 8;                   // passes of the pair sort
+    const int p1 = (nb + 7) / 8;                       // radix passes of the pair sort (on the row)
     const int p2 = (bits_for((uint64_t)r.n) + 7) / 8;   // passes of the CSC sort
     uint64_t* sorted = (p1 & 1) ? (uint64_t*)(ws + L.keysB) : (uint64_t*)(ws + L.keysA);
     uint64_t* other = (p1 & 1) ? (uint64_t*)(ws + L.keysA) : (uint64_t*)(ws + L.keysB);
@@ -1166,24 +1166,27 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     } else if (e_tile % (16 * NT) == 0)
         hipLaunchKernelGGL(k_orient<16>, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, edges,
                            (uint64_t)E, n, rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, e_tile,
-                           radix_first_digit(0, 2 * nb));
+                           radix_first_digit(nb, 2 * nb));
     else
         hipLaunchKernelGGL(k_orient<OR_U>, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, edges,
                            (uint64_t)E, n, rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, e_tile,
-                           radix_first_digit(0, 2 * nb));
+                           radix_first_digit(nb, 2 * nb));
     mark(3);
-    // ---- sort oriented pairs: the first digit counted by k_orient, or, past 2^21
-    // vertices, a first pass that orients each pair as it loads it
+    // ---- sort oriented pairs: a stable radix sort on the lower rank (the row; its
+    // first digit counted by k_orient or, past 2^21 vertices, taken by a first pass
+    // that orients each pair as it loads it), then every row sorted on chip by the
+    // higher rank
     int alt;
     if (part) {
-        const int w0 = radix_digit_width(2 * nb);
-        radix_pass_u64(keysA, keysB, (size_t)E, 0, w0, RadixXf{RX_ORIENT, rank, n, nb, sentinel}, radix_tmp, s);
-        alt = 1 - radix_sort_u64(keysB, keysA, nullptr, nullptr, nullptr, (size_t)E, w0, 2 * nb, radix_tmp, s);
+        const int w0 = radix_digit_width(nb);
+        radix_pass_u64(keysA, keysB, (size_t)E, nb, w0, RadixXf{RX_ORIENT, rank, n, nb, sentinel}, radix_tmp, s);
+        alt = 1 - radix_sort_u64(keysB, keysA, nullptr, nullptr, nullptr, (size_t)E, nb + w0, 2 * nb, radix_tmp, s);
     } else {
-        alt = radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)E, 0, 2 * nb, radix_tmp, s, true);
+        alt = radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)E, nb, 2 * nb, radix_tmp, s, true);
     }
     uint64_t* sorted = alt ? keysB : keysA;
     uint64_t* other = alt ? keysA : keysB;
+    sort_runs_u64(sorted, other, (size_t)E, nb, true, sentinel, s);
     mark(4);
     // ---- unique + CSR
     {

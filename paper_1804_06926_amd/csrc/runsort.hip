@@ -1,0 +1,508 @@
+// Sorting runs in place: keys already grouped by their high bits (key >> shift,
+// ascending) are ordered by the whole key inside each run of equal high bits.
+//
+// The pair sort of the CSR build uses it. A stable radix sort on the lower rank
+// of each oriented pair (its row) groups the pairs by row; this pass then orders
+// every row by the higher rank, which the forward algorithm's sorted out-lists
+// need (Section 3.2). Rows are short (the out-degree in (degree, id) order is at
+// most sqrt(2m) on simple input), so one pass over the keys with each row sorted
+// on chip replaces the radix passes over the higher rank's bits.
+//
+// A block takes a tile of SR_TILE positions and sorts the runs that start in it
+// (a run may extend past the tile; the block reads and writes it whole). Other
+// blocks read only the high bits of those positions, which a permutation inside
+// a run leaves unchanged, so the in-place writes race with nothing. The block
+// reads its tile once and keeps the low bits in LDS, with the overflow of its
+// last run. By length:
+//   - up to SR_SHORT: the runs starting in one 64-position window, up to the
+//     first longer one, are sorted together by a bitonic network across the wave
+//     (64 or 128 slots, each holding its run's index in the window above its low
+//     bits, which keeps the runs apart);
+//   - up to SR_MED: one wave, a bitonic network over the low bits held in
+//     registers (the next power of two, up to 32 per lane);
+//   - up to SR_BLOCK: the whole block, the same network over four waves, whose
+//     cross-wave steps exchange through LDS;
+//   - longer (only input with many repeated pairs has such rows): the whole
+//     block, LSD radix passes over the low bits in `tmp` (the run's own range
+//     of it) with the counters in LDS.
+#include "common.h"
+#include "internal.h"
+
+namespace tcx {
+namespace {
+
+constexpr int SR_NT = 256;
+constexpr int SR_NW = SR_NT / WAVE;
+constexpr uint32_t SR_TILE = 4096;                 // positions per block
+constexpr uint32_t SR_PER = SR_TILE / SR_NT;       // consecutive positions per thread in the scan for starts
+constexpr uint32_t SR_WIN = 64;                    // positions per window of short runs
+constexpr uint32_t SR_NWIN = SR_TILE / SR_WIN;
+constexpr uint32_t SR_SHORT = 64;
+constexpr uint32_t SR_MED = 2048;                  // one wave, at most 32 values per lane
+constexpr uint32_t SR_BLOCK = 8192;                // the block, 32 values per lane
+constexpr uint32_t SR_MAXMED = SR_TILE / (SR_SHORT + 1) + 1;   // medium runs that can start in one tile
+constexpr uint32_t SR_MAXLONG = SR_TILE / (SR_MED + 1) + 1;   // runs past SR_MED that can start in one tile
+
+struct SortRunsArgs {
+    uint64_t* keys;
+    uint64_t* tmp;       // as many keys as `keys`: a long run uses its own range of it
+    uint32_t len;
+    int shift;           // 1..32
+    uint32_t skip;       // 1: a run whose first key is skip_key is left alone (it holds only that key)
+    uint64_t skip_key;
+    int passes, dw;      // radix passes over the low shift bits, and the digit width of each
+};
+
+struct alignas(16) Key2 {
+    uint64_t a, b;
+};
+
+// Lanes of `active` whose digit (nbits wide) equals this lane's.
+__device__ __forceinline__ uint64_t match_bits(uint32_t d, uint64_t active, int nbits) {
+    uint64_t peers = active;
+    for (int b = 0; b < nbits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return peers;
+}
+
+// LDS position of tile-relative position p: one word of skew per 64 keeps the
+// strided reads of the register sorts below (lane l, element r at l * P + r)
+// free of bank conflicts.
+__device__ __forceinline__ uint32_t sk(uint32_t p) { return p + (p >> 6); }
+
+// Ascending across the wave, slot = lane.
+template <typename T>
+__device__ __forceinline__ T bitonic64(T x) {
+    const int l = lane_id();
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const T y = __shfl_xor(x, j, WAVE);
+            const bool lt = x < y;
+            x = ((((l & j) == 0) == ((l & k) == 0)) == lt) ? x : y;
+        }
+    }
+    return x;
+}
+
+// Ascending over 128 slots: x0 is slot lane, x1 slot lane + 64.
+template <typename T>
+__device__ __forceinline__ void bitonic128(T& x0, T& x1) {
+    const int l = lane_id();
+#pragma unroll
+    for (int k = 2; k <= 128; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j == 64) {   // k = 128: slots l and l + 64, ascending
+                const T lo = x0 < x1 ? x0 : x1, hi = x0 < x1 ? x1 : x0;
+                x0 = lo;
+                x1 = hi;
+            } else {
+                const bool lower = (l & j) == 0;
+                const T y0 = __shfl_xor(x0, j, WAVE);
+                const T y1 = __shfl_xor(x1, j, WAVE);
+                x0 = ((lower == ((l & k) == 0)) == (x0 < y0)) ? x0 : y0;
+                x1 = ((lower == (((l + 64) & k) == 0)) == (x1 < y1)) ? x1 : y1;
+            }
+        }
+    }
+}
+
+// The short runs of one window, slots [0, S) = tile positions [sp0, sp0 + S),
+// S <= 127: each slot's low bits with the index of its run inside the span
+// above them (T = uint32_t when shift <= 25: at most 127 runs, 7 bits), sorted
+// by a bitonic network; each position keeps its own high bits.
+template <typename T>
+__device__ __forceinline__ void sort_window(uint64_t* keys, const uint32_t* v, const uint16_t* flag, uint32_t sp0,
+                                            uint32_t S, int sh) {
+    const int l = lane_id();
+    const int cs = sizeof(T) == 4 ? sh : 32;
+    const uint64_t lmask = (1ull << sh) - 1ull;
+    const T pad = ~T(0);
+    const uint64_t upto = lanes_below() | (1ull << l);
+    auto start_bit = [&](uint32_t p) -> bool { return (flag[p >> 4] >> (p & 15)) & 1u; };
+    const uint32_t p0 = sp0 + (uint32_t)l, p1 = p0 + 64;
+    const bool ok0 = (uint32_t)l < S, ok1 = (uint32_t)l + 64 < S;
+    const uint64_t o0 = ok0 ? keys[p0] : 0ull;   // the loads of the high bits run under the network
+    const uint64_t o1 = ok1 ? keys[p1] : 0ull;
+    const uint64_t b0 = __ballot(ok0 && start_bit(p0));
+    const T r0 = (T)(__popcll(b0 & upto) - 1);
+    T x0 = ok0 ? (T)((r0 << cs) | (T)v[sk(p0)]) : pad;
+    if (S <= 64) {
+        x0 = bitonic64(x0);
+        if (ok0) keys[p0] = (o0 & ~lmask) | ((uint64_t)x0 & lmask);
+    } else {
+        const uint64_t b1 = __ballot(ok1 && start_bit(p1));
+        const T r1 = (T)(__popcll(b0) + __popcll(b1 & upto) - 1);
+        T x1 = ok1 ? (T)((r1 << cs) | (T)v[sk(p1)]) : pad;
+        bitonic128(x0, x1);
+        keys[p0] = (o0 & ~lmask) | ((uint64_t)x0 & lmask);
+        if (ok1) keys[p1] = (o1 & ~lmask) | ((uint64_t)x1 & lmask);
+    }
+}
+
+__device__ __forceinline__ void cmpx(uint32_t& a, uint32_t& b, bool up) {
+    const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+    a = up ? lo : hi;
+    b = up ? hi : lo;
+}
+
+// Bitonic sorting network over values held P per lane, element e = e0 + r in
+// x[r] (e0 = base + lane * P): compare-exchanges between elements of one lane
+// stay in registers (steps j < P), the others pair lane l with l ^ (j / P).
+// In-lane steps j = P/2 .. 1 of a phase with direction `up`.
+template <int P>
+__device__ __forceinline__ void steps_in_lane(uint32_t (&x)[P], bool up) {
+#pragma unroll
+    for (int j = P / 2; j > 0; j >>= 1)
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+            if ((r ^ j) > r) cmpx(x[r], x[r ^ j], up);
+}
+
+// A cross-lane step: partner lane l ^ lj, the lower lane of a pair keeping the
+// smaller values when `up`.
+template <int P>
+__device__ __forceinline__ void step_across(uint32_t (&x)[P], uint32_t lj, bool up) {
+    const bool keep_lo = ((lane_id() & lj) == 0) == up;
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        const uint32_t y = __shfl_xor(x[r], (int)lj, WAVE);
+        const uint32_t lo = x[r] < y ? x[r] : y, hi = x[r] < y ? y : x[r];
+        x[r] = keep_lo ? lo : hi;
+    }
+}
+
+// Phases k = 2 .. 64P, e0 = base + lane * P (base a multiple of 64P): the
+// wave's 64P elements end up sorted, ascending when bit 64P of base is clear,
+// descending otherwise.
+template <int P>
+__device__ __forceinline__ void bitonic_wave(uint32_t (&x)[P], uint32_t e0) {
+#pragma unroll
+    for (int k = 2; k <= P; k <<= 1)   // bit k of e: r's below P, the lane's at P
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int r = 0; r < P; ++r)
+                if ((r ^ j) > r) cmpx(x[r], x[r ^ j], k < P ? (r & k) == 0 : (e0 & k) == 0);
+    for (uint32_t k = 2 * P; k <= 64u * P; k <<= 1) {
+        const bool up = (e0 & k) == 0;
+        for (uint32_t j = k >> 1; j >= (uint32_t)P; j >>= 1) step_across<P>(x, j / P, up);
+        steps_in_lane<P>(x, up);
+    }
+}
+
+// One wave: the run's low bits v[sk(st) ..] (L of them, L <= 64 * P) sorted in
+// registers and put back in place.
+template <int P>
+__device__ __forceinline__ void wave_sort_run(uint32_t* v, uint32_t st, uint32_t L) {
+    const uint32_t e0 = (uint32_t)lane_id() * P;
+    uint32_t x[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) x[r] = e0 + r < L ? v[sk(st + e0 + r)] : 0xFFFFFFFFu;   // padding sorts last
+    bitonic_wave<P>(x, e0);
+#pragma unroll
+    for (int r = 0; r < P; ++r)
+        if (e0 + r < L) v[sk(st + e0 + r)] = x[r];
+}
+
+// The whole block: N = 256 * P values (v[sk(0) ..], L of them, padded), four
+// waves of 64P; the steps that pair different waves exchange through v.
+template <int P>
+__device__ void block_bitonic(uint32_t* v, uint32_t L) {
+    constexpr uint32_t N = SR_NT * P, WSPAN = 64u * P;
+    const uint32_t e0 = (uint32_t)wave_id() * WSPAN + (uint32_t)lane_id() * P;
+    uint32_t x[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) x[r] = e0 + r < L ? v[sk(e0 + r)] : 0xFFFFFFFFu;
+    bitonic_wave<P>(x, e0);
+    for (uint32_t k = 2 * WSPAN; k <= N; k <<= 1) {
+        const bool up = (e0 & k) == 0;
+        for (uint32_t j = k >> 1; j >= WSPAN; j >>= 1) {
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < P; ++r) v[sk(e0 + r)] = x[r];
+            __syncthreads();
+            const bool keep_lo = ((e0 & j) == 0) == up;
+#pragma unroll
+            for (int r = 0; r < P; ++r) {
+                const uint32_t y = v[sk((e0 + r) ^ j)];
+                const uint32_t lo = x[r] < y ? x[r] : y, hi = x[r] < y ? y : x[r];
+                x[r] = keep_lo ? lo : hi;
+            }
+        }
+        for (uint32_t j = WSPAN / 2; j >= (uint32_t)P; j >>= 1) step_across<P>(x, j / P, up);
+        steps_in_lane<P>(x, up);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < P; ++r)
+        if (e0 + r < L) v[sk(e0 + r)] = x[r];
+    __syncthreads();
+}
+
+// The whole block: the same passes with the values in global memory (tA holds
+// 2L uint32, the run's own range of tmp) and per-wave counters in LDS; each
+// wave owns a contiguous quarter of the run, which keeps the passes stable.
+__device__ void block_sort_run(uint64_t* run, uint32_t* tA, uint32_t L, const SortRunsArgs& a,
+                               uint32_t (*cntw)[256], uint32_t* scan) {
+    const int w = wave_id(), l = lane_id();
+    const int sh = a.shift;
+    const uint64_t hi = (run[0] >> sh) << sh;
+    const uint64_t lmask = (1ull << sh) - 1ull;
+    const uint32_t dmask = (1u << a.dw) - 1u;
+    uint32_t* tB = tA + L;
+    for (uint32_t i = threadIdx.x; i < L; i += SR_NT) tA[i] = (uint32_t)(run[i] & lmask);
+    __threadfence();
+    __syncthreads();
+    const uint32_t Q = (L + SR_NW - 1) / SR_NW;
+    const uint32_t q0 = (uint32_t)w * Q < L ? (uint32_t)w * Q : L;
+    const uint32_t q1 = q0 + Q < L ? q0 + Q : L;
+    uint32_t* cnt = cntw[w];
+    for (int p = 0; p < a.passes; ++p) {
+        const int ps = p * a.dw;
+        const bool last = p + 1 == a.passes;
+        for (int d = l; d < 256; d += WAVE) cnt[d] = 0u;
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t i = q0 + l; i < q1; i += WAVE) atomicAdd(&cnt[(tA[i] >> ps) & dmask], 1u);
+        __syncthreads();
+        {   // thread d: digit d's start for each wave's part
+            const uint32_t d = threadIdx.x;
+            uint32_t c[SR_NW], tot = 0;
+#pragma unroll
+            for (int q = 0; q < SR_NW; ++q) {
+                c[q] = cntw[q][d];
+                tot += c[q];
+            }
+            uint32_t o = block_exclusive_scan<SR_NT>(tot, scan);
+#pragma unroll
+            for (int q = 0; q < SR_NW; ++q) {
+                cntw[q][d] = o;
+                o += c[q];
+            }
+        }
+        __syncthreads();
+        for (uint32_t i0 = q0; i0 < q1; i0 += WAVE) {
+            const uint32_t i = i0 + l;
+            const bool valid = i < q1;
+            const uint32_t v = valid ? tA[i] : 0u;
+            const uint32_t d = (v >> ps) & dmask;
+            const uint64_t peers = match_bits(d, __ballot(valid), a.dw);
+            const uint32_t r = (uint32_t)__popcll(peers & lanes_below());
+            const uint32_t b = cnt[d];
+            __builtin_amdgcn_wave_barrier();
+            if (valid && r == 0) cnt[d] = b + (uint32_t)__popcll(peers);
+            __builtin_amdgcn_wave_barrier();
+            if (valid) {
+                if (last) run[b + r] = hi | v;
+                else tB[b + r] = v;
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        uint32_t* t = tA;
+        tA = tB;
+        tB = t;
+    }
+}
+
+constexpr uint32_t SR_SPAN = SR_TILE + SR_MED;   // the tile and the overflow of its last run
+constexpr uint32_t SR_NFLAG = SR_TILE / 16 + 8;  // run-start bits, 16 positions each (none past the tile)
+constexpr uint32_t SR_LDS = (SR_SPAN > SR_BLOCK ? SR_SPAN : SR_BLOCK) + SR_BLOCK / 64;
+
+__global__ __launch_bounds__(SR_NT, 3) void k_sort_runs(SortRunsArgs a) {
+    __shared__ uint32_t s_v[SR_LDS];                   // low bits of the keys, tile-relative position p at sk(p)
+    __shared__ uint16_t s_bnd[SR_TILE];                 // run starts in the tile, ascending
+    __shared__ uint16_t s_flag[SR_NFLAG];
+    __shared__ uint32_t s_wf[SR_NWIN + 1];              // first run index per window
+    __shared__ uint16_t s_med[SR_MAXMED];
+    __shared__ uint32_t s_long[SR_MAXLONG];
+    __shared__ uint32_t s_scan[SR_NW];
+    __shared__ uint32_t s_nbnd, s_lastend, s_skippos, s_nmed, s_nlong, s_medctr;
+    __shared__ uint32_t s_cnt[SR_NW][256];
+
+    const uint32_t t0 = (gridDim.x - 1 - blockIdx.x) * SR_TILE;   // the last tiles, whose runs are longest, first
+    const uint32_t len = a.len;
+    const int sh = a.shift;
+    const uint64_t lmask = (1ull << sh) - 1ull;
+    const int w = wave_id(), l = lane_id();
+    uint64_t* const keys = a.keys + t0;   // tile-relative
+    if (threadIdx.x == 0) {
+        s_skippos = 0xFFFFFFFFu;
+        s_nmed = 0;
+        s_nlong = 0;
+        s_medctr = 0;
+    }
+    if (threadIdx.x < SR_NFLAG - SR_TILE / 16) s_flag[SR_TILE / 16 + threadIdx.x] = 0;
+    __syncthreads();
+    // ---- run starts: a position whose high bits differ from its predecessor's
+    {
+        const uint32_t p0 = t0 + threadIdx.x * SR_PER;
+        uint64_t k[SR_PER];
+        if (p0 + SR_PER <= len) {
+            const Key2* p = (const Key2*)(a.keys + p0);   // 128-byte aligned
+#pragma unroll
+            for (uint32_t q = 0; q < SR_PER / 2; ++q) {
+                const Key2 v = p[q];
+                k[2 * q] = v.a;
+                k[2 * q + 1] = v.b;
+            }
+        } else {
+#pragma unroll
+            for (uint32_t j = 0; j < SR_PER; ++j) k[j] = p0 + j < len ? a.keys[p0 + j] : 0ull;
+        }
+        uint64_t ph = p0 > 0 && p0 <= len ? a.keys[p0 - 1] >> sh : 0ull;
+        uint32_t flags = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < SR_PER; ++j) {
+            const uint32_t p = p0 + j;
+            s_v[sk(threadIdx.x * SR_PER + j)] = (uint32_t)(k[j] & lmask);
+            if (p < len) {
+                const uint64_t h = k[j] >> sh;
+                if (p == 0 || h != ph) {
+                    flags |= 1u << j;
+                    if (a.skip && k[j] == a.skip_key) s_skippos = p - t0;   // at most one run starts with it
+                }
+                ph = h;
+            }
+        }
+        s_flag[threadIdx.x] = (uint16_t)flags;
+        uint32_t total;
+        uint32_t o = block_exclusive_scan<SR_NT>((uint32_t)__popc(flags), s_scan, &total);
+        if ((threadIdx.x & 3) == 0) s_wf[threadIdx.x >> 2] = o;
+        if (threadIdx.x == 0) {
+            s_wf[SR_NWIN] = total;
+            s_nbnd = total;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < SR_PER; ++j)
+            if ((flags >> j) & 1u) s_bnd[o++] = (uint16_t)(threadIdx.x * SR_PER + j);
+    }
+    __syncthreads();
+    const uint32_t nbnd = s_nbnd;
+    if (nbnd == 0) return;   // the whole tile lies in a run that starts earlier
+    // ---- where the tile's last run ends: a 64-way search past the tile
+    if (w == 0) {
+        const uint64_t hl = keys[s_bnd[nbnd - 1]] >> sh;
+        uint32_t lo = t0 + SR_TILE < len ? t0 + SR_TILE : len;   // [last start, lo) lies in the run
+        uint32_t hi = len;                                      // [hi, len) does not
+        while (lo < hi) {
+            const uint32_t step = (hi - lo + WAVE - 1) / WAVE;
+            const uint32_t q = lo + (uint32_t)l * step;
+            const bool in = q < hi && (a.keys[q] >> sh) == hl;
+            const uint32_t c = (uint32_t)__popcll(__ballot(in));   // the probes in the run are a prefix
+            if (c == 0) {
+                hi = lo;
+            } else {
+                const uint32_t nlo = lo + (c - 1) * step + 1;
+                const uint32_t qc = lo + c * step;
+                if (c < (uint32_t)WAVE && qc < hi) hi = qc;
+                lo = nlo;
+            }
+            lo = __builtin_amdgcn_readfirstlane(lo);
+            hi = __builtin_amdgcn_readfirstlane(hi);
+        }
+        if (l == 0) s_lastend = lo - t0;
+    }
+    __syncthreads();
+    const uint32_t lastend = s_lastend, skippos = s_skippos;
+    auto run_end = [&](uint32_t i) -> uint32_t { return i + 1 < nbnd ? (uint32_t)s_bnd[i + 1] : lastend; };
+    {   // the last run's positions past the tile, when it is sorted in LDS
+        const uint32_t st = s_bnd[nbnd - 1];
+        if (lastend > SR_TILE && lastend - st <= SR_MED && st != skippos)
+            for (uint32_t p = SR_TILE + threadIdx.x; p < lastend; p += SR_NT) s_v[sk(p)] = (uint32_t)(keys[p] & lmask);
+    }
+    // ---- medium and long runs
+    for (uint32_t i = threadIdx.x; i < nbnd; i += SR_NT) {
+        const uint32_t st = s_bnd[i];
+        const uint32_t L = run_end(i) - st;
+        if (st == skippos || L <= SR_SHORT) continue;
+        if (L <= SR_MED) s_med[atomicAdd(&s_nmed, 1u)] = (uint16_t)i;
+        else s_long[atomicAdd(&s_nlong, 1u)] = i;
+    }
+    __syncthreads();
+    // ---- short runs, window by window
+    for (uint32_t win = w; win < SR_NWIN; win += SR_NW) {
+        const uint32_t r0 = s_wf[win], r1 = s_wf[win + 1];
+        if (r0 == r1) continue;
+        const uint32_t r = r0 + l;
+        const bool has = r < r1;
+        uint32_t L = 0;
+        bool bad = false;
+        if (has) {
+            const uint32_t st = s_bnd[r];
+            L = run_end(r) - st;
+            bad = L > SR_SHORT || st == skippos;
+        }
+        const uint64_t mb = __ballot(bad);
+        const uint32_t cut = mb ? (uint32_t)__ffsll((unsigned long long)mb) - 1u : r1 - r0;
+        if (cut == 0 || __ballot(has && (uint32_t)l < cut && L >= 2) == 0) continue;
+        const uint32_t sp0 = s_bnd[r0];
+        const uint32_t S = run_end(r0 + cut - 1) - sp0;   // at most 127
+        if (sh <= 25) sort_window<uint32_t>(keys, s_v, s_flag, sp0, S, sh);
+        else sort_window<uint64_t>(keys, s_v, s_flag, sp0, S, sh);
+    }
+    // ---- medium runs, one wave each: a register sort of the next power of two
+    {
+        const uint32_t nmed = s_nmed;
+        for (;;) {
+            uint32_t idx = 0;
+            if (l == 0) idx = atomicAdd(&s_medctr, 1u);
+            idx = __builtin_amdgcn_readfirstlane(idx);
+            if (idx >= nmed) break;
+            const uint32_t i = s_med[idx];
+            const uint32_t st = s_bnd[i], L = run_end(i) - st;
+            const uint64_t hi = (keys[st] >> sh) << sh;
+            if (L <= 128) wave_sort_run<2>(s_v, st, L);
+            else if (L <= 256) wave_sort_run<4>(s_v, st, L);
+            else if (L <= 512) wave_sort_run<8>(s_v, st, L);
+            else if (L <= 1024) wave_sort_run<16>(s_v, st, L);
+            else wave_sort_run<32>(s_v, st, L);
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t p = l; p < L; p += WAVE) keys[st + p] = hi | s_v[sk(st + p)];
+        }
+    }
+    // ---- long runs, the whole block: a network over LDS up to SR_BLOCK, else radix passes in tmp
+    __syncthreads();
+    const uint32_t nlong = s_nlong;
+    for (uint32_t q = 0; q < nlong; ++q) {
+        const uint32_t i = s_long[q];
+        const uint32_t st = s_bnd[i], L = run_end(i) - st;
+        uint64_t* run = keys + st;
+        if (L <= SR_BLOCK) {
+            const uint64_t hi = (run[0] >> sh) << sh;
+            for (uint32_t p = threadIdx.x; p < L; p += SR_NT) s_v[sk(p)] = (uint32_t)(run[p] & lmask);
+            __syncthreads();
+            if (L <= SR_BLOCK / 2) block_bitonic<SR_BLOCK / 2 / SR_NT>(s_v, L);
+            else block_bitonic<SR_BLOCK / SR_NT>(s_v, L);
+            for (uint32_t p = threadIdx.x; p < L; p += SR_NT) run[p] = hi | s_v[sk(p)];
+            __syncthreads();
+        } else {
+            block_sort_run(run, (uint32_t*)(a.tmp + t0 + st), L, a, s_cnt, s_scan);
+        }
+    }
+}
+
+}  // namespace
+
+void sort_runs_u64(uint64_t* keys, uint64_t* tmp, size_t len, int shift, bool skip, uint64_t skip_key,
+                   hipStream_t s) {
+    if (len == 0) return;
+    SortRunsArgs a;
+    a.keys = keys;
+    a.tmp = tmp;
+    a.len = (uint32_t)len;
+    a.shift = shift;
+    a.skip = skip ? 1u : 0u;
+    a.skip_key = skip_key;
+    a.passes = (shift + 7) / 8;
+    a.dw = (shift + a.passes - 1) / a.passes;
+    const uint32_t grid = (uint32_t)((len + SR_TILE - 1) / SR_TILE);
+    hipLaunchKernelGGL(k_sort_runs, dim3(grid), dim3(SR_NT), 0, s, a);
+}
+
+}  // namespace tcx

@@ -294,6 +294,42 @@ def test_radix_sort_is_stable_and_exact(tc, count, bits):
     np.testing.assert_array_equal(d.cpu().numpy(), ref)
 
 
+def _run_lengths(kind, rng):
+    if kind == "singletons":
+        return [1] * 5000
+    if kind == "short":
+        return rng.integers(1, 65, 3000).tolist()
+    if kind == "windows":        # spans of short runs past 64 slots
+        return rng.integers(1, 130, 1500).tolist()
+    if kind == "edges":          # either side of every length class
+        return [64, 65, 2048, 2049, 1, 2, 127, 128, 4095, 4096, 4097, 63, 1, 8192, 3]
+    if kind == "huge":           # one run over many tiles, between short ones
+        return rng.integers(1, 40, 200).tolist() + [300_000] + rng.integers(1, 300, 200).tolist()
+    if kind == "powerlaw":       # row lengths like a degree-ordered R-MAT out-list
+        return np.minimum((rng.pareto(1.2, 120_000) * 4 + 1).astype(np.int64), 5000).tolist()
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("shift,kind", [(24, "singletons"), (24, "short"), (24, "windows"), (24, "edges"),
+                                        (20, "huge"), (24, "powerlaw"), (32, "powerlaw"), (7, "windows"),
+                                        (1, "edges"), (13, "short"), (24, "one")])
+def test_sort_runs_sorts_every_run(tc, shift, kind):
+    """tc_sort_runs_u64 on keys grouped by their high bits gives np.sort of them (runs of every length
+    class, duplicates inside runs, ragged last tile)."""
+    import torch
+    rng = np.random.default_rng(shift * 7 + len(kind))
+    lens = np.asarray([1] if kind == "one" else _run_lengths(kind, rng), dtype=np.int64)
+    high = np.cumsum(rng.integers(1, 4, lens.size)).astype(np.uint64)
+    hv = np.repeat(high, lens)
+    low = rng.integers(0, 1 << shift, hv.size, dtype=np.uint64)
+    few = np.repeat(rng.random(lens.size) < 0.3, lens)   # some runs with many repeated keys
+    low[few] %= np.uint64(5)
+    keys = (hv << np.uint64(shift)) | low
+    d = torch.from_numpy(keys.view(np.int64).copy()).to("cuda:0")
+    tc.sort_runs_u64(d, shift)
+    np.testing.assert_array_equal(d.cpu().numpy().view(np.uint64), np.sort(keys))
+
+
 def test_per_edge_counts_clean_input_simple_degree(tc):
     """Without repeated pairs, input degree and simple degree coincide."""
     n = 1 << 12
