@@ -68,131 +68,175 @@ __device__ __forceinline__ uint64_t match_bits(uint32_t d, uint64_t active, int 
     return peers;
 }
 
-// LDS position of tile-relative position p: one word of skew per 64 keeps the
-// strided reads of the register sorts below (lane l, element r at l * P + r)
-// free of bank conflicts.
-__device__ __forceinline__ uint32_t sk(uint32_t p) { return p + (p >> 6); }
-
-// Ascending across the wave, slot = lane.
-template <typename T>
-__device__ __forceinline__ T bitonic64(T x) {
-    const int l = lane_id();
-#pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const T y = __shfl_xor(x, j, WAVE);
-            const bool lt = x < y;
-            x = ((((l & j) == 0) == ((l & k) == 0)) == lt) ? x : y;
-        }
-    }
-    return x;
+// ---- lane exchanges without LDS: DPP moves inside 16-lane rows, the gfx950
+// permlane swaps across rows.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
 }
 
-// Ascending over 128 slots: x0 is slot lane, x1 slot lane + 64.
-template <typename T>
-__device__ __forceinline__ void bitonic128(T& x0, T& x1) {
-    const int l = lane_id();
-#pragma unroll
-    for (int k = 2; k <= 128; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j == 64) {   // k = 128: slots l and l + 64, ascending
-                const T lo = x0 < x1 ? x0 : x1, hi = x0 < x1 ? x1 : x0;
-                x0 = lo;
-                x1 = hi;
-            } else {
-                const bool lower = (l & j) == 0;
-                const T y0 = __shfl_xor(x0, j, WAVE);
-                const T y1 = __shfl_xor(x1, j, WAVE);
-                x0 = ((lower == ((l & k) == 0)) == (x0 < y0)) ? x0 : y0;
-                x1 = ((lower == (((l + 64) & k) == 0)) == (x1 < y1)) ? x1 : y1;
-            }
-        }
-    }
-}
-
-// The short runs of one window, slots [0, S) = tile positions [sp0, sp0 + S),
-// S <= 127: each slot's low bits with the index of its run inside the span
-// above them (T = uint32_t when shift <= 25: at most 127 runs, 7 bits), sorted
-// by a bitonic network; each position keeps its own high bits.
-template <typename T>
-__device__ __forceinline__ void sort_window(uint64_t* keys, const uint32_t* v, const uint16_t* flag, uint32_t sp0,
-                                            uint32_t S, int sh) {
-    const int l = lane_id();
-    const int cs = sizeof(T) == 4 ? sh : 32;
-    const uint64_t lmask = (1ull << sh) - 1ull;
-    const T pad = ~T(0);
-    const uint64_t upto = lanes_below() | (1ull << l);
-    auto start_bit = [&](uint32_t p) -> bool { return (flag[p >> 4] >> (p & 15)) & 1u; };
-    const uint32_t p0 = sp0 + (uint32_t)l, p1 = p0 + 64;
-    const bool ok0 = (uint32_t)l < S, ok1 = (uint32_t)l + 64 < S;
-    const uint64_t o0 = ok0 ? keys[p0] : 0ull;   // the loads of the high bits run under the network
-    const uint64_t o1 = ok1 ? keys[p1] : 0ull;
-    const uint64_t b0 = __ballot(ok0 && start_bit(p0));
-    const T r0 = (T)(__popcll(b0 & upto) - 1);
-    T x0 = ok0 ? (T)((r0 << cs) | (T)v[sk(p0)]) : pad;
-    if (S <= 64) {
-        x0 = bitonic64(x0);
-        if (ok0) keys[p0] = (o0 & ~lmask) | ((uint64_t)x0 & lmask);
+// {a, b} = this lane's value and lane l ^ M's, in either order (what a
+// compare-exchange needs): M = 16 and 32 by the permlane swaps, which leave the
+// two in their two outputs; M < 16 by DPP (quad permutations for 1 and 2, a
+// half-row mirror then a quad reversal for 4, a row rotation by 8 for 8).
+template <int M>
+__device__ __forceinline__ void lane_pair(uint32_t x, uint32_t& a, uint32_t& b) {
+    if constexpr (M == 16 || M == 32) {
+        const auto p = M == 16 ? __builtin_amdgcn_permlane16_swap(x, x, false, false)
+                               : __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        a = p[0];
+        b = p[1];
     } else {
-        const uint64_t b1 = __ballot(ok1 && start_bit(p1));
-        const T r1 = (T)(__popcll(b0) + __popcll(b1 & upto) - 1);
-        T x1 = ok1 ? (T)((r1 << cs) | (T)v[sk(p1)]) : pad;
-        bitonic128(x0, x1);
-        keys[p0] = (o0 & ~lmask) | ((uint64_t)x0 & lmask);
-        if (ok1) keys[p1] = (o1 & ~lmask) | ((uint64_t)x1 & lmask);
+        static_assert(M == 1 || M == 2 || M == 4 || M == 8, "lane partner");
+        a = x;
+        if constexpr (M == 1) b = dpp_mov<0xB1>(x);
+        else if constexpr (M == 2) b = dpp_mov<0x4E>(x);
+        else if constexpr (M == 4) b = dpp_mov<0x1B>(dpp_mov<0x141>(x));
+        else b = dpp_mov<0x128>(x);
     }
 }
 
-__device__ __forceinline__ void cmpx(uint32_t& a, uint32_t& b, bool up) {
-    const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-    a = up ? lo : hi;
-    b = up ? hi : lo;
-}
-
-// Bitonic sorting network over values held P per lane, element e = e0 + r in
-// x[r] (e0 = base + lane * P): compare-exchanges between elements of one lane
-// stay in registers (steps j < P), the others pair lane l with l ^ (j / P).
-// In-lane steps j = P/2 .. 1 of a phase with direction `up`.
-template <int P>
-__device__ __forceinline__ void steps_in_lane(uint32_t (&x)[P], bool up) {
-#pragma unroll
-    for (int j = P / 2; j > 0; j >>= 1)
-#pragma unroll
-        for (int r = 0; r < P; ++r)
-            if ((r ^ j) > r) cmpx(x[r], x[r ^ j], up);
-}
-
-// A cross-lane step: partner lane l ^ lj, the lower lane of a pair keeping the
-// smaller values when `up`.
-template <int P>
-__device__ __forceinline__ void step_across(uint32_t (&x)[P], uint32_t lj, bool up) {
-    const bool keep_lo = ((lane_id() & lj) == 0) == up;
-#pragma unroll
-    for (int r = 0; r < P; ++r) {
-        const uint32_t y = __shfl_xor(x[r], (int)lj, WAVE);
-        const uint32_t lo = x[r] < y ? x[r] : y, hi = x[r] < y ? y : x[r];
-        x[r] = keep_lo ? lo : hi;
+// The value of lane l ^ M, M = 2^t - 1 (the mirror partners of the flip steps):
+// quad reversals and row mirrors by DPP; 16 and 32 added by a permlane swap and
+// a select of the output that holds the partner.
+template <int M>
+__device__ __forceinline__ uint32_t lane_mirror(uint32_t x) {
+    if constexpr (M == 1) return dpp_mov<0xB1>(x);
+    else if constexpr (M == 3) return dpp_mov<0x1B>(x);
+    else if constexpr (M == 7) return dpp_mov<0x141>(x);
+    else if constexpr (M == 15) return dpp_mov<0x140>(x);
+    else if constexpr (M == 31) {
+        const auto p = __builtin_amdgcn_permlane16_swap(dpp_mov<0x140>(x), dpp_mov<0x140>(x), false, false);
+        return (lane_id() & 16) ? p[0] : p[1];
+    } else {
+        static_assert(M == 63, "mirror partner");
+        const uint32_t y = lane_mirror<31>(x);
+        const auto p = __builtin_amdgcn_permlane32_swap(y, y, false, false);
+        return (lane_id() & 32) ? p[0] : p[1];
     }
 }
 
-// Phases k = 2 .. 64P, e0 = base + lane * P (base a multiple of 64P): the
-// wave's 64P elements end up sorted, ascending when bit 64P of base is clear,
-// descending otherwise.
-template <int P>
-__device__ __forceinline__ void bitonic_wave(uint32_t (&x)[P], uint32_t e0) {
-#pragma unroll
-    for (int k = 2; k <= P; k <<= 1)   // bit k of e: r's below P, the lane's at P
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1)
+// The same on 64-bit values, one half at a time (both halves come from the same lane).
+template <int M>
+__device__ __forceinline__ void lane_pair(uint64_t x, uint64_t& a, uint64_t& b) {
+    uint32_t al, bl, ah, bh;
+    lane_pair<M>((uint32_t)x, al, bl);
+    lane_pair<M>((uint32_t)(x >> 32), ah, bh);
+    a = ((uint64_t)ah << 32) | al;
+    b = ((uint64_t)bh << 32) | bl;
+}
+
+template <int M>
+__device__ __forceinline__ uint64_t lane_mirror(uint64_t x) {
+    return ((uint64_t)lane_mirror<M>((uint32_t)(x >> 32)) << 32) | lane_mirror<M>((uint32_t)x);
+}
+
+template <typename T>
+__device__ __forceinline__ void ce(T& a, T& b) {   // ascending compare-exchange
+    const T lo = a < b ? a : b, hi = a < b ? b : a;
+    a = lo;
+    b = hi;
+}
+
+// ---- bitonic sorting networks in registers, all compare-exchanges ascending
+// (each phase k starts with a flip step that pairs e with e ^ (k - 1), then
+// halves with e ^ j, j = k/4 .. 1). A wave holds 64P values, P per lane,
+// element e = lane * P + r in x[r]: pairs inside a lane are two registers,
+// pairs across lanes one DPP or permlane exchange.
+template <typename T, int P, int J>
+__device__ __forceinline__ void half_clean(T (&x)[P]) {
+    if constexpr (J >= 1) {
+        if constexpr (J < P) {
 #pragma unroll
             for (int r = 0; r < P; ++r)
-                if ((r ^ j) > r) cmpx(x[r], x[r ^ j], k < P ? (r & k) == 0 : (e0 & k) == 0);
-    for (uint32_t k = 2 * P; k <= 64u * P; k <<= 1) {
-        const bool up = (e0 & k) == 0;
-        for (uint32_t j = k >> 1; j >= (uint32_t)P; j >>= 1) step_across<P>(x, j / P, up);
-        steps_in_lane<P>(x, up);
+                if ((r & J) == 0) ce(x[r], x[r | J]);
+        } else {
+            constexpr int M = J / P;
+            const bool lower = (lane_id() & M) == 0;
+#pragma unroll
+            for (int r = 0; r < P; ++r) {
+                T a, b;
+                lane_pair<M>(x[r], a, b);
+                x[r] = (a < b) == lower ? a : b;
+            }
+        }
+        half_clean<T, P, J / 2>(x);
+    }
+}
+
+template <typename T, int P, int K>
+__device__ __forceinline__ void flip(T (&x)[P]) {
+    if constexpr (K <= P) {
+#pragma unroll
+        for (int r = 0; r < P; ++r)
+            if ((r & (K / 2)) == 0) ce(x[r], x[r ^ (K - 1)]);
+    } else {   // partner: lane l ^ (K/P - 1), register P - 1 - r
+        const bool lower = (lane_id() & (K / (2 * P))) == 0;
+        T y[P];
+#pragma unroll
+        for (int r = 0; r < P; ++r) y[r] = lane_mirror<K / P - 1>(x[P - 1 - r]);
+#pragma unroll
+        for (int r = 0; r < P; ++r) x[r] = (x[r] < y[r]) == lower ? x[r] : y[r];
+    }
+}
+
+// Phases K .. KMAX (KMAX <= 64P): after phase 64P the wave's values ascend.
+template <typename T, int P, int K, int KMAX>
+__device__ __forceinline__ void sort_phases(T (&x)[P]) {
+    if constexpr (K <= KMAX) {
+        flip<T, P, K>(x);
+        half_clean<T, P, K / 4>(x);
+        sort_phases<T, P, K * 2, KMAX>(x);
+    }
+}
+
+template <typename T, int P>
+__device__ __forceinline__ void sort_wave(T (&x)[P]) {
+    sort_phases<T, P, 2, 64 * P>(x);
+}
+
+// LDS position of tile-relative position p: one word of skew per 64 keeps the
+// strided reads of the register sorts (lane l, element r at l * P + r) free of
+// bank conflicts.
+__device__ __forceinline__ uint32_t sk(uint32_t p) { return p + (p >> 6); }
+
+// The short runs of one window, slots [0, S) = tile positions [sp0, sp0 + S),
+// S <= 127, P slots per lane (1 or 2): each slot's low bits with the index of
+// its run inside the span above them (T = uint32_t when shift <= 25: at most
+// 127 runs, 7 bits), sorted by the network; each position keeps its own high
+// bits.
+template <typename T, int P>
+__device__ __forceinline__ void sort_window(uint64_t* keys, const uint32_t* v, const uint16_t* flag, uint32_t sp0,
+                                            uint32_t S, int sh) {
+    const uint32_t l = (uint32_t)lane_id();
+    const int cs = sizeof(T) == 4 ? sh : 32;
+    const uint64_t lmask = (1ull << sh) - 1ull;
+    const uint64_t below = lanes_below();
+    uint64_t o[P];
+    T x[P];
+    uint32_t before = 0;   // run starts in this lane's earlier slots
+    bool st[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        const uint32_t s = l * P + r, p = sp0 + s;
+        o[r] = s < S ? keys[p] : 0ull;   // the high bits: loads in flight under the network
+        st[r] = s < S && ((flag[p >> 4] >> (p & 15)) & 1u);
+    }
+    uint32_t prior = 0;    // run starts in the slots of the lanes below
+#pragma unroll
+    for (int r = 0; r < P; ++r) prior += (uint32_t)__popcll(__ballot(st[r]) & below);
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        const uint32_t s = l * P + r;
+        before += st[r] ? 1u : 0u;
+        const T ri = (T)(prior + before - 1u);   // slot 0 starts a run
+        x[r] = s < S ? (T)((ri << cs) | (T)v[sk(sp0 + s)]) : ~T(0);
+    }
+    sort_wave<T, P>(x);
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+        const uint32_t s = l * P + r;
+        if (s < S) keys[sp0 + s] = (o[r] & ~lmask) | ((uint64_t)x[r] & lmask);
     }
 }
 
@@ -204,39 +248,37 @@ __device__ __forceinline__ void wave_sort_run(uint32_t* v, uint32_t st, uint32_t
     uint32_t x[P];
 #pragma unroll
     for (int r = 0; r < P; ++r) x[r] = e0 + r < L ? v[sk(st + e0 + r)] : 0xFFFFFFFFu;   // padding sorts last
-    bitonic_wave<P>(x, e0);
+    sort_wave<uint32_t, P>(x);
 #pragma unroll
     for (int r = 0; r < P; ++r)
         if (e0 + r < L) v[sk(st + e0 + r)] = x[r];
 }
 
 // The whole block: N = 256 * P values (v[sk(0) ..], L of them, padded), four
-// waves of 64P; the steps that pair different waves exchange through v.
+// waves of 64P each sorted in registers; the steps that pair different waves
+// exchange through v.
 template <int P>
 __device__ void block_bitonic(uint32_t* v, uint32_t L) {
-    constexpr uint32_t N = SR_NT * P, WSPAN = 64u * P;
+    constexpr uint32_t N = 256u * P, WSPAN = 64u * P;
     const uint32_t e0 = (uint32_t)wave_id() * WSPAN + (uint32_t)lane_id() * P;
     uint32_t x[P];
 #pragma unroll
     for (int r = 0; r < P; ++r) x[r] = e0 + r < L ? v[sk(e0 + r)] : 0xFFFFFFFFu;
-    bitonic_wave<P>(x, e0);
+    sort_wave<uint32_t, P>(x);
     for (uint32_t k = 2 * WSPAN; k <= N; k <<= 1) {
-        const bool up = (e0 & k) == 0;
-        for (uint32_t j = k >> 1; j >= WSPAN; j >>= 1) {
+        for (uint32_t j = k - 1; j >= WSPAN; j = (j == k - 1) ? k / 4 : j / 2) {   // the flip, then halving
             __syncthreads();
 #pragma unroll
             for (int r = 0; r < P; ++r) v[sk(e0 + r)] = x[r];
             __syncthreads();
-            const bool keep_lo = ((e0 & j) == 0) == up;
+            const bool lower = (e0 & (j == k - 1 ? k / 2 : j)) == 0;
 #pragma unroll
             for (int r = 0; r < P; ++r) {
                 const uint32_t y = v[sk((e0 + r) ^ j)];
-                const uint32_t lo = x[r] < y ? x[r] : y, hi = x[r] < y ? y : x[r];
-                x[r] = keep_lo ? lo : hi;
+                x[r] = (x[r] < y) == lower ? x[r] : y;
             }
         }
-        for (uint32_t j = WSPAN / 2; j >= (uint32_t)P; j >>= 1) step_across<P>(x, j / P, up);
-        steps_in_lane<P>(x, up);
+        half_clean<uint32_t, P, 32 * P>(x);
     }
     __syncthreads();
 #pragma unroll
@@ -443,8 +485,13 @@ __global__ __launch_bounds__(SR_NT, 3) void k_sort_runs(SortRunsArgs a) {
         if (cut == 0 || __ballot(has && (uint32_t)l < cut && L >= 2) == 0) continue;
         const uint32_t sp0 = s_bnd[r0];
         const uint32_t S = run_end(r0 + cut - 1) - sp0;   // at most 127
-        if (sh <= 25) sort_window<uint32_t>(keys, s_v, s_flag, sp0, S, sh);
-        else sort_window<uint64_t>(keys, s_v, s_flag, sp0, S, sh);
+        if (sh <= 25) {
+            if (S <= 64) sort_window<uint32_t, 1>(keys, s_v, s_flag, sp0, S, sh);
+            else sort_window<uint32_t, 2>(keys, s_v, s_flag, sp0, S, sh);
+        } else {
+            if (S <= 64) sort_window<uint64_t, 1>(keys, s_v, s_flag, sp0, S, sh);
+            else sort_window<uint64_t, 2>(keys, s_v, s_flag, sp0, S, sh);
+        }
     }
     // ---- medium runs, one wave each: a register sort of the next power of two
     {
