@@ -512,7 +512,7 @@ tc_status tc_sort_runs_u64(tc_ctx* ctx, uint64_t* d_keys, uint64_t* d_tmp, int64
     if (!d_keys || !d_tmp) return arg_fail(ctx, TC_ERR_INVALID_ARG, "null pointer");
     if ((uintptr_t)d_keys % 16 != 0) return arg_fail(ctx, TC_ERR_INVALID_ARG, "keys must be 16-byte aligned");
     DeviceGuard guard(ctx->device);
-    tcx::sort_runs_u64(d_keys, d_tmp, (size_t)count, shift, false, 0ull, ctx->stream);
+    tcx::sort_runs_u64(d_keys, d_tmp, (size_t)count, shift, false, 0ull, nullptr, 0u, ctx->stream);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "run sort");

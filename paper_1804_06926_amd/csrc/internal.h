@@ -64,10 +64,12 @@ uint32_t* radix_first_counts(void* temp);
 // ---- runsort.hip
 // Keys grouped by key >> shift (ascending; 1 <= shift <= 32) are sorted by the
 // whole key inside each run of equal high bits, in place; keys 16-byte aligned,
-// tmp as many keys as keys (scratch for runs longer than 2048). With skip, a
+// tmp as many keys as keys (scratch for runs longer than 8192). With skip, a
 // run whose first key is skip_key (it must hold only that key) is left alone.
+// With kept non-null, kept[p / chunk] += the keys at positions p that differ
+// from the key before them, over the runs sorted (kept must start at zero).
 void sort_runs_u64(uint64_t* keys, uint64_t* tmp, size_t len, int shift, bool skip, uint64_t skip_key,
-                   hipStream_t s);
+                   uint32_t* kept, uint32_t chunk, hipStream_t s);
 
 // ---- control block shared by all stages (device memory, zeroed per call)
 constexpr int NBUCKET = 256;          // degree-pair buckets; 255 = no work

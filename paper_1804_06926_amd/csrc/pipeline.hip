@@ -296,10 +296,11 @@ constexpr int ORIENT_PART_MIN_BITS = 21;
 // ------------------------------------------------------------------ unique + CSR
 // The sorted pair keys in runs of equal keys: the first of each run is kept,
 // sentinel keys (loops, invalid ids; they sort last) are dropped. Each block
-// owns a chunk of whole 2048-key tiles; in a tile, thread t takes the UQ_ITEMS
-// consecutive keys from t * UQ_ITEMS (four 16-byte loads, in flight together),
-// so a block scans once per tile rather than once per 256 keys; the kept keys
-// are compacted in LDS and written out in contiguous runs.
+// owns a chunk of whole 2048-key tiles, whose kept keys the row sort has
+// counted; in a tile, thread t takes the UQ_ITEMS consecutive keys from
+// t * UQ_ITEMS (four 16-byte loads, in flight together), so a block scans once
+// per tile rather than once per 256 keys; the kept keys are compacted in LDS
+// and written out in contiguous runs.
 constexpr int UQ_MAX_BLOCKS = 1024;
 constexpr int UQ_ITEMS = 8;
 constexpr uint32_t UQ_TILE = NT * UQ_ITEMS;
@@ -352,30 +353,6 @@ __device__ __forceinline__ uint32_t uq_keep(const uint64_t* __restrict__ keys, u
         prev = k[j];
     }
     return keep;
-}
-
-__global__ __launch_bounds__(NT) void k_unique_count(const uint64_t* __restrict__ keys, uint64_t E, uint64_t sentinel,
-                                                     uint32_t chunk, uint32_t* __restrict__ partial, uint32_t nblk) {
-    const uint64_t b0 = (uint64_t)blockIdx.x * chunk;
-    const uint64_t b1 = b0 + chunk < E ? b0 + chunk : E;
-    uint32_t c = 0;
-    for (uint64_t t0 = b0; t0 < b1; t0 += UQ_TILE) {
-        const uint64_t i0 = t0 + (uint64_t)threadIdx.x * UQ_ITEMS;
-        if (i0 >= b1) continue;
-        uint64_t k[UQ_ITEMS];
-        uq_load(keys, i0, E, sentinel, k);
-        c += (uint32_t)__popc(uq_keep(keys, i0, sentinel, k));
-    }
-    c = wave_sum(c);
-    __shared__ uint32_t red[NT / WAVE];
-    if (lane_id() == 0) red[wave_id()] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t s = 0;
-        for (int k = 0; k < NT / WAVE; ++k) s += red[k];
-        partial[blockIdx.x] = s;
-        if (blockIdx.x == 0) partial[nblk] = 0;
-    }
 }
 
 // Keeps the first of every run of equal keys; rowend[s] = number of kept keys
@@ -1186,13 +1163,14 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     }
     uint64_t* sorted = alt ? keysB : keysA;
     uint64_t* other = alt ? keysA : keysB;
-    sort_runs_u64(sorted, other, (size_t)E, nb, true, sentinel, s);
+    // the row sort also counts the kept (first of equal) keys per chunk of the unique pass
+    const Chunking uc = chunking((uint64_t)E);
+    fill_u32(partial, 0u, (size_t)uc.nblk + 1, s);
+    sort_runs_u64(sorted, other, (size_t)E, nb, true, sentinel, partial, uc.chunk, s);
     mark(4);
     // ---- unique + CSR
     {
-        const Chunking c = chunking((uint64_t)E);
-        hipLaunchKernelGGL(k_unique_count, dim3(c.nblk), dim3(NT), 0, s, sorted, (uint64_t)E, sentinel, c.chunk,
-                           partial, c.nblk);
+        const Chunking c = uc;
         scan_exclusive_sum_u32(partial, partial, (size_t)c.nblk + 1, scan_tmp, s);
         fill_u32(rowend, 0u, (size_t)n, s);
         hipLaunchKernelGGL(k_unique_write, dim3(c.nblk), dim3(NT), 0, s, sorted, (uint64_t)E, sentinel, ctrl, c.chunk,

@@ -51,6 +51,8 @@ struct SortRunsArgs {
     uint32_t skip;       // 1: a run whose first key is skip_key is left alone (it holds only that key)
     uint64_t skip_key;
     int passes, dw;      // radix passes over the low shift bits, and the digit width of each
+    uint32_t* kept;      // non-null: per chunk of positions, += the keys that differ from their predecessor
+    uint32_t chunk;      //   (the first of each run of equal keys; runs left alone are not counted)
 };
 
 struct alignas(16) Key2 {
@@ -206,8 +208,8 @@ __device__ __forceinline__ uint32_t sk(uint32_t p) { return p + (p >> 6); }
 // 127 runs, 7 bits), sorted by the network; each position keeps its own high
 // bits.
 template <typename T, int P>
-__device__ __forceinline__ void sort_window(uint64_t* keys, const uint32_t* v, const uint16_t* flag, uint32_t sp0,
-                                            uint32_t S, int sh) {
+__device__ __forceinline__ uint32_t sort_window(uint64_t* keys, const uint32_t* v, const uint16_t* flag,
+                                                uint32_t sp0, uint32_t S, int sh) {
     const uint32_t l = (uint32_t)lane_id();
     const int cs = sizeof(T) == 4 ? sh : 32;
     const uint64_t lmask = (1ull << sh) - 1ull;
@@ -233,11 +235,18 @@ __device__ __forceinline__ void sort_window(uint64_t* keys, const uint32_t* v, c
         x[r] = s < S ? (T)((ri << cs) | (T)v[sk(sp0 + s)]) : ~T(0);
     }
     sort_wave<T, P>(x);
+    // the slots whose value differs from the slot before (the run index is part
+    // of it), counted across the wave
+    T prev = __shfl_up(x[P - 1], 1, WAVE);
+    uint32_t kept = 0;
 #pragma unroll
     for (int r = 0; r < P; ++r) {
         const uint32_t s = l * P + r;
         if (s < S) keys[sp0 + s] = (o[r] & ~lmask) | ((uint64_t)x[r] & lmask);
+        kept += (uint32_t)__popcll(__ballot(s < S && (s == 0 || x[r] != prev)));
+        prev = x[r];
     }
+    return kept;
 }
 
 // One wave: the run's low bits v[sk(st) ..] (L of them, L <= 64 * P) sorted in
@@ -366,8 +375,25 @@ __global__ __launch_bounds__(SR_NT, 3) void k_sort_runs(SortRunsArgs a) {
     __shared__ uint32_t s_scan[SR_NW];
     __shared__ uint32_t s_nbnd, s_lastend, s_skippos, s_nmed, s_nlong, s_medctr;
     __shared__ uint32_t s_cnt[SR_NW][256];
+    __shared__ uint32_t s_kept[8];                      // kept keys per chunk c0 .. c0 + 7
 
     const uint32_t t0 = (gridDim.x - 1 - blockIdx.x) * SR_TILE;   // the last tiles, whose runs are longest, first
+    const uint32_t c0 = a.kept ? t0 / a.chunk : 0u;
+    // kept keys at tile-relative position rel (cnt of them, all in rel's chunk)
+    auto add_kept = [&](uint32_t rel, uint32_t cnt) {
+        const uint32_t c = (t0 + rel) / a.chunk - c0;
+        if (c < 8) atomicAdd(&s_kept[c], cnt);
+        else atomicAdd(&a.kept[c0 + c], cnt);
+    };
+    // a wave's kept keys over positions [rel0, rel0 + len), tot of them (uniform): one add
+    // when they share a chunk, else one per position (kept_at says which)
+    auto wave_kept = [&](uint32_t rel0, uint32_t len, uint32_t tot, auto kept_at) {
+        if ((t0 + rel0) / a.chunk == (t0 + rel0 + len - 1) / a.chunk) {
+            if (lane_id() == 0 && tot) add_kept(rel0, tot);
+        } else {
+            kept_at();
+        }
+    };
     const uint32_t len = a.len;
     const int sh = a.shift;
     const uint64_t lmask = (1ull << sh) - 1ull;
@@ -380,6 +406,7 @@ __global__ __launch_bounds__(SR_NT, 3) void k_sort_runs(SortRunsArgs a) {
         s_medctr = 0;
     }
     if (threadIdx.x < SR_NFLAG - SR_TILE / 16) s_flag[SR_TILE / 16 + threadIdx.x] = 0;
+    if (threadIdx.x < 8) s_kept[threadIdx.x] = 0;
     __syncthreads();
     // ---- run starts: a position whose high bits differ from its predecessor's
     {
@@ -482,16 +509,31 @@ __global__ __launch_bounds__(SR_NT, 3) void k_sort_runs(SortRunsArgs a) {
         }
         const uint64_t mb = __ballot(bad);
         const uint32_t cut = mb ? (uint32_t)__ffsll((unsigned long long)mb) - 1u : r1 - r0;
-        if (cut == 0 || __ballot(has && (uint32_t)l < cut && L >= 2) == 0) continue;
+        if (cut == 0) continue;
         const uint32_t sp0 = s_bnd[r0];
-        const uint32_t S = run_end(r0 + cut - 1) - sp0;   // at most 127
-        if (sh <= 25) {
-            if (S <= 64) sort_window<uint32_t, 1>(keys, s_v, s_flag, sp0, S, sh);
-            else sort_window<uint32_t, 2>(keys, s_v, s_flag, sp0, S, sh);
-        } else {
-            if (S <= 64) sort_window<uint64_t, 1>(keys, s_v, s_flag, sp0, S, sh);
-            else sort_window<uint64_t, 2>(keys, s_v, s_flag, sp0, S, sh);
+        if (__ballot(has && (uint32_t)l < cut && L >= 2) == 0) {   // single keys only: nothing to sort
+            if (a.kept)
+                wave_kept(sp0, cut, cut, [&] {
+                    if ((uint32_t)l < cut) add_kept(sp0 + l, 1u);
+                });
+            continue;
         }
+        const uint32_t S = run_end(r0 + cut - 1) - sp0;   // at most 127
+        uint32_t kept;
+        if (sh <= 25) {
+            if (S <= 64) kept = sort_window<uint32_t, 1>(keys, s_v, s_flag, sp0, S, sh);
+            else kept = sort_window<uint32_t, 2>(keys, s_v, s_flag, sp0, S, sh);
+        } else {
+            if (S <= 64) kept = sort_window<uint64_t, 1>(keys, s_v, s_flag, sp0, S, sh);
+            else kept = sort_window<uint64_t, 2>(keys, s_v, s_flag, sp0, S, sh);
+        }
+        if (a.kept)
+            wave_kept(sp0, S, kept, [&] {   // a chunk boundary inside the span: position by position
+                for (uint32_t q = l; q < S; q += WAVE) {
+                    const uint64_t k = keys[sp0 + q];
+                    if (q == 0 || k != keys[sp0 + q - 1]) add_kept(sp0 + q, 1u);
+                }
+            });
     }
     // ---- medium runs, one wave each: a register sort of the next power of two
     {
@@ -510,7 +552,18 @@ __global__ __launch_bounds__(SR_NT, 3) void k_sort_runs(SortRunsArgs a) {
             else if (L <= 1024) wave_sort_run<16>(s_v, st, L);
             else wave_sort_run<32>(s_v, st, L);
             __builtin_amdgcn_wave_barrier();
-            for (uint32_t p = l; p < L; p += WAVE) keys[st + p] = hi | s_v[sk(st + p)];
+            uint32_t kept = 0;
+            for (uint32_t p0 = 0; p0 < L; p0 += WAVE) {
+                const uint32_t p = p0 + l;
+                const uint32_t v = p < L ? s_v[sk(st + p)] : 0u;
+                if (p < L) keys[st + p] = hi | v;
+                if (a.kept) kept += (uint32_t)__popcll(__ballot(p < L && (p == 0 || v != s_v[sk(st + p - 1)])));
+            }
+            if (a.kept)
+                wave_kept(st, L, kept, [&] {
+                    for (uint32_t p = l; p < L; p += WAVE)
+                        if (p == 0 || s_v[sk(st + p)] != s_v[sk(st + p - 1)]) add_kept(st + p, 1u);
+                });
         }
     }
     // ---- long runs, the whole block: a network over LDS up to SR_BLOCK, else radix passes in tmp
@@ -526,18 +579,29 @@ __global__ __launch_bounds__(SR_NT, 3) void k_sort_runs(SortRunsArgs a) {
             __syncthreads();
             if (L <= SR_BLOCK / 2) block_bitonic<SR_BLOCK / 2 / SR_NT>(s_v, L);
             else block_bitonic<SR_BLOCK / SR_NT>(s_v, L);
-            for (uint32_t p = threadIdx.x; p < L; p += SR_NT) run[p] = hi | s_v[sk(p)];
+            for (uint32_t p = threadIdx.x; p < L; p += SR_NT) {
+                const uint32_t v = s_v[sk(p)];
+                run[p] = hi | v;
+                if (a.kept && (p == 0 || v != s_v[sk(p - 1)])) add_kept(st + p, 1u);
+            }
             __syncthreads();
         } else {
             block_sort_run(run, (uint32_t*)(a.tmp + t0 + st), L, a, s_cnt, s_scan);
+            if (a.kept)
+                for (uint32_t p = threadIdx.x; p < L; p += SR_NT)
+                    if (p == 0 || run[p] != run[p - 1]) add_kept(st + p, 1u);
         }
+    }
+    if (a.kept) {
+        __syncthreads();
+        if (threadIdx.x < 8 && s_kept[threadIdx.x]) atomicAdd(&a.kept[c0 + threadIdx.x], s_kept[threadIdx.x]);
     }
 }
 
 }  // namespace
 
 void sort_runs_u64(uint64_t* keys, uint64_t* tmp, size_t len, int shift, bool skip, uint64_t skip_key,
-                   hipStream_t s) {
+                   uint32_t* kept, uint32_t chunk, hipStream_t s) {
     if (len == 0) return;
     SortRunsArgs a;
     a.keys = keys;
@@ -548,6 +612,8 @@ void sort_runs_u64(uint64_t* keys, uint64_t* tmp, size_t len, int shift, bool sk
     a.skip_key = skip_key;
     a.passes = (shift + 7) / 8;
     a.dw = (shift + a.passes - 1) / a.passes;
+    a.kept = kept;
+    a.chunk = chunk > 0 ? chunk : 1u;
     const uint32_t grid = (uint32_t)((len + SR_TILE - 1) / SR_TILE);
     hipLaunchKernelGGL(k_sort_runs, dim3(grid), dim3(SR_NT), 0, s, a);
 }
