@@ -463,39 +463,64 @@ __global__ __launch_bounds__(NT) void k_csc_keys(const uint32_t* __restrict__ co
     }
 }
 
-// inend[v] = one past the last in-edge of v in the sorted order; m_active.
-__global__ __launch_bounds__(NT) void k_csc_bounds(const uint64_t* __restrict__ keys, Ctrl* ctrl, int32_t n,
-                                                   uint32_t* __restrict__ inend, int sh) {
-    const uint32_t m = ctrl->m;
-    const uint32_t last = (uint32_t)(n - 1);   // the group of in-edges without work
-    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < m; i += (uint64_t)gridDim.x * NT) {
-        const uint32_t v = (uint32_t)(keys[i] >> sh);
-        const uint32_t vn = i + 1 < m ? (uint32_t)(keys[i + 1] >> sh) : last;
-        if (v < last && vn != v) {
-            inend[v] = (uint32_t)(i + 1);
-            if (vn == last) ctrl->m_active = (uint32_t)(i + 1);
-        }
+// One pass over the sorted in-edge keys: inend[v] = one past the last in-edge
+// of v and m_active from the group boundaries, and each key with work written
+// to out (the other buffer: neighbours' keys are still being read) as the tail
+// range of its edge e, start (e + 1) | end << 32, so a kernel reads it in one
+// load. Packed keys carry the length; otherwise the row end of u is gathered.
+// Thread t takes keys 2t and 2t + 1 (16-byte loads and stores, coalesced
+// across the wave) and reads the key after them.
+__device__ __forceinline__ uint64_t csc_range(uint64_t key, uint64_t emask, uint64_t lmask, int lbits,
+                                              const uint32_t* __restrict__ src, const uint32_t* __restrict__ off) {
+    uint32_t e, end;
+    if (lbits > 0) {
+        e = (uint32_t)((key >> lbits) & emask);
+        const uint64_t len = key & lmask;
+        end = len != lmask ? e + 1u + (uint32_t)len : off[src[e] + 1];
+    } else {
+        e = (uint32_t)key;
+        end = off[src[e] + 1];
     }
+    return (uint64_t)(e + 1u) | ((uint64_t)end << 32);
 }
 
-// In place, after the bounds are known: each key becomes the tail range of its
-// edge e, start (e + 1) | end << 32, so a kernel reads it in one load. Packed
-// keys carry the length; otherwise the row end of u is gathered.
-__global__ __launch_bounds__(NT) void k_csc_expand(uint64_t* __restrict__ csc, const Ctrl* ctrl,
+__global__ __launch_bounds__(NT) void k_csc_finish(const uint64_t* __restrict__ keys, uint64_t* __restrict__ out,
+                                                   Ctrl* ctrl, int32_t n, uint32_t* __restrict__ inend, int sh,
                                                    const uint32_t* __restrict__ src,
                                                    const uint32_t* __restrict__ off, int ebits, int lbits) {
-    const uint32_t ma = ctrl->m_active;
+    const uint32_t m = ctrl->m;
+    const uint32_t last = (uint32_t)(n - 1);   // the group of in-edges without work
     const uint64_t emask = (1ull << ebits) - 1ull, lmask = (1ull << lbits) - 1ull;
-    for (uint64_t i = (uint64_t)blockIdx.x * NT + threadIdx.x; i < ma; i += (uint64_t)gridDim.x * NT) {
-        const uint64_t key = csc[i];
-        if (lbits > 0) {
-            const uint32_t e = (uint32_t)((key >> lbits) & emask);
-            const uint64_t len = key & lmask;
-            const uint32_t end = len != lmask ? e + 1u + (uint32_t)len : off[src[e] + 1];
-            csc[i] = (uint64_t)(e + 1u) | ((uint64_t)end << 32);
+    const uint64_t none = (uint64_t)last << sh;
+    for (uint64_t i0 = ((uint64_t)blockIdx.x * NT + threadIdx.x) * 2; i0 < m; i0 += (uint64_t)gridDim.x * NT * 2) {
+        uint64_t k0, k1;
+        if (i0 + 2 <= m) {
+            const U64x2 v = *(const U64x2*)(keys + i0);   // 16-byte aligned
+            k0 = v.a;
+            k1 = v.b;
         } else {
-            const uint32_t e = (uint32_t)key;
-            csc[i] = (uint64_t)(e + 1u) | ((uint64_t)off[src[e] + 1] << 32);
+            k0 = keys[i0];
+            k1 = none;
+        }
+        const uint64_t k2 = i0 + 2 < m ? keys[i0 + 2] : none;
+        const uint32_t v0 = (uint32_t)(k0 >> sh), v1 = (uint32_t)(k1 >> sh), v2 = (uint32_t)(k2 >> sh);
+        if (v0 < last && v1 != v0) {
+            inend[v0] = (uint32_t)(i0 + 1);
+            if (v1 == last) ctrl->m_active = (uint32_t)(i0 + 1);
+        }
+        if (i0 + 1 < m && v1 < last && v2 != v1) {
+            inend[v1] = (uint32_t)(i0 + 2);
+            if (v2 == last) ctrl->m_active = (uint32_t)(i0 + 2);
+        }
+        const uint64_t r0 = v0 < last ? csc_range(k0, emask, lmask, lbits, src, off) : 0ull;
+        const uint64_t r1 = v1 < last ? csc_range(k1, emask, lmask, lbits, src, off) : 0ull;
+        if (i0 + 2 <= m) {
+            U64x2 w;
+            w.a = r0;
+            w.b = r1;
+            *(U64x2*)(out + i0) = w;
+        } else {
+            out[i0] = r0;
         }
     }
 }
@@ -973,7 +998,8 @@ static IsectArgs isect_args(const RunArgs& r, const Layout& L, uint64_t* csc) {
     return ia;
 }
 
-// Where the CSC array ended up (it depends on the parity of the sort passes).
+// Where the CSC array ended up (it depends on the parity of the sort passes;
+// the filtered form's tail ranges are written to the buffer its sort left free).
 static uint64_t* csc_of(const RunArgs& r, const Layout& L) {
     char* ws = (char*)r.ws;
     const int nb = bits_for((uint64_t)r.n) > 0 ? bits_for((uint64_t)r.n) : 1;
@@ -981,7 +1007,8 @@ static uint64_t* csc_of(const RunArgs& r, const Layout& L) {
     const int p2 = (bits_for((uint64_t)r.n) + 7) / 8;   // passes of the CSC sort
     uint64_t* sorted = (p1 & 1) ? (uint64_t*)(ws + L.keysB) : (uint64_t*)(ws + L.keysA);
     uint64_t* other = (p1 & 1) ? (uint64_t*)(ws + L.keysA) : (uint64_t*)(ws + L.keysB);
-    return (p2 & 1) ? sorted : other;
+    const bool keys_in_sorted = (p2 & 1) != 0;
+    return keys_in_sorted == (r.formulation == FORM_FILTERED) ? other : sorted;
 }
 
 hipError_t launch_isect_stage(const RunArgs& r, hipEvent_t* ev) {
@@ -1197,13 +1224,14 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
                            radix_first_digit(pk.sh, pk.sh + nbv));
         const int alt2 = radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, pk.sh, pk.sh + nbv,
                                         radix_tmp, s, true);
-        csc = alt2 ? sorted : other;
+        // bounds and tail ranges in one pass, into the buffer the sort left free
+        const uint64_t* ckeys = alt2 ? sorted : other;
+        csc = alt2 ? other : sorted;
         fill_u32(rowend, 0u, (size_t)n, s);
-        hipLaunchKernelGGL(k_csc_bounds, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, n, rowend, pk.sh);
+        hipLaunchKernelGGL(k_csc_finish, dim3(grid_for(((size_t)E + 1) / 2)), dim3(NT), 0, s, ckeys,
+                           csc, ctrl, n, rowend, pk.sh, src, off, pk.ebits, pk.lbits);
         fill_u32(inoff, 0u, 1, s);
         scan_inclusive_max_u32(rowend, inoff + 1, (size_t)n, scan_tmp, s);
-        hipLaunchKernelGGL(k_csc_expand, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, src, off, pk.ebits,
-                           pk.lbits);
     } else {
         // ---- all in-edges grouped by v; the symmetric adjacency; the streamed ranges
         const int sh = bits_for((uint64_t)E) > 0 ? bits_for((uint64_t)E) : 1;
