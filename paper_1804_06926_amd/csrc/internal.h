@@ -47,8 +47,11 @@ struct RadixXf {
 };
 // One stable radix pass of 64-bit keys on bits [shift, shift + bits), bits <= 8,
 // from kin to kout (the two must differ), each key transformed as `xf` says.
+// counted: the per-tile digit counts, already taken by an earlier kernel
+// (counts[d * ntiles + tile], tiles of radix_tile_keys(cap, 8) keys; the pass
+// turns them into offsets in place); nullptr: the pass counts them itself.
 void radix_pass_u64(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& xf,
-                    void* temp, hipStream_t s);
+                    void* temp, hipStream_t s, uint32_t* counted = nullptr);
 // Digit width of each pass of a sort over `bits` bits (equal widths, at most 8).
 int radix_digit_width(int bits);
 struct RadixDigit {

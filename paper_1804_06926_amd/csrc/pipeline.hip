@@ -60,19 +60,25 @@ constexpr unsigned DEG_EP_BLOCKS = 1024;
 __global__ __launch_bounds__(NT) void k_endpoints(const int2* __restrict__ edges, uint64_t E, int32_t n,
                                                   uint32_t sentinel, uint32_t* __restrict__ keys, Ctrl* ctrl,
                                                   uint32_t* __restrict__ nsent, uint32_t* __restrict__ counts,
-                                                  uint32_t ntiles, uint32_t tile_keys, RadixDigit dg) {
+                                                  uint32_t ntiles, uint32_t tile_keys, RadixDigit dg,
+                                                  uint32_t* __restrict__ pcounts, uint32_t pf, RadixDigit pdg) {
     // tile t = endpoints [t * tile_keys, (t + 1) * tile_keys) = pairs [t * EPT, (t + 1) * EPT),
     // in rounds of NT * PER pairs; with counts set, the first digit of the endpoint sort is
-    // counted per tile
+    // counted per tile. With pcounts set, the digit pdg of the first id is counted too, per
+    // tile of pf endpoint tiles: the first pass of the orientation's pair partition, whose
+    // tiles hold pf * EPT pairs.
     constexpr uint32_t PER = 4;
     const uint32_t EPT = tile_keys / 2;
+    const uint32_t pntiles = (ntiles + pf - 1) / pf;
     __shared__ uint32_t red[NT / WAVE];
-    __shared__ TileCounts tc;
+    __shared__ TileCounts tc, tp;
     tc.clear();
+    if (pcounts) tp.clear();
     __syncthreads();
     bool bad = false;
     uint32_t sent = 0;
-    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (uint32_t pt = blockIdx.x; pt < pntiles; pt += gridDim.x) {
+     for (uint32_t tile = pt * pf; tile < (pt + 1) * pf && tile < ntiles; ++tile) {
       for (uint32_t r = 0; r < EPT; r += PER * NT) {
         int2 ed[PER];
 #pragma unroll
@@ -95,9 +101,12 @@ __global__ __launch_bounds__(NT) void k_endpoints(const int2* __restrict__ edges
                 tc.add((a >> dg.shift) & dg.mask);
                 tc.add((b >> dg.shift) & dg.mask);
             }
+            if (pcounts) tp.add(((uint32_t)e.x >> pdg.shift) & pdg.mask);
         }
       }
         if (counts) tc.flush(counts, ntiles, tile);
+     }
+        if (pcounts) tp.flush(pcounts, pntiles, pt);
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, 1u);
     sent = wave_sum(sent);
@@ -292,6 +301,7 @@ __global__ __launch_bounds__(NT) void k_orient(const int2* __restrict__ edges, u
 // scatter alike). The blocks of each pass look up ranks in a few
 // 2^(vbits - 8)-id ranges at a time, which stay in L2.
 constexpr int ORIENT_PART_MIN_BITS = 21;
+constexpr int ORIENT_PART_BITS = 8;   // digit of each partition pass
 
 // ------------------------------------------------------------------ unique + CSR
 // The sorted pair keys in runs of equal keys: the first of each run is kept,
@@ -1102,6 +1112,9 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     // bucket width: one partition pass of at most 8 bits up to 24-bit ids (buckets
     // of 2^16 vertices counted in two parts at 24 bits), two (buckets of 2^14) up to 27 bits
     const int vbits = bits_for((uint64_t)n);               // vertex ids fit in vbits bits
+    const bool orient_part = vbits >= ORIENT_PART_MIN_BITS;
+    uint32_t* p1_counts = nullptr;   // the orientation's first partition pass, counted by k_endpoints
+    uint32_t p1_f = 1;
     const int bw = vbits <= 20 ? (vbits < 12 ? vbits : 12) : (vbits <= 24 ? vbits - 8 : DEG_MAX_BW);
     const bool bucketed = vbits - bw <= DEG_MAX_BUCKET_BITS;
     {
@@ -1112,10 +1125,22 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         const uint32_t ep_tiles = (uint32_t)(((uint64_t)(2 * E) + ep_tile - 1) / ep_tile);
         const bool ep_sort = !bucketed || vbits > bw;
         const RadixDigit ep_dg = bucketed ? radix_first_digit(bw, vbits) : radix_first_digit(0, bits_for((uint64_t)n + 1));
-        const unsigned eg = ep_tiles < DEG_EP_BLOCKS ? ep_tiles : DEG_EP_BLOCKS;
+        // past 2^21 vertices the orientation's first partition pass (pairs by the high bits
+        // of the first id) takes its digit counts from here too, kept in the column array
+        // until then; its tiles hold one or two endpoint tiles' pairs
+        const uint32_t pt_pairs = radix_tile_keys((size_t)E, 8);
+        const uint64_t pt_tiles = ((uint64_t)E + pt_pairs - 1) / pt_pairs;
+        if (orient_part && pt_pairs % (ep_tile / 2) == 0 && pt_pairs / (ep_tile / 2) <= 2 &&
+            256u * (pt_tiles + 1) <= (uint64_t)E) {   // the count table fits the column array
+            p1_counts = col;
+            p1_f = pt_pairs / (ep_tile / 2);
+        }
+        const uint32_t p1_tiles = (ep_tiles + p1_f - 1) / p1_f;
+        const unsigned eg = p1_tiles < DEG_EP_BLOCKS ? p1_tiles : DEG_EP_BLOCKS;
         hipLaunchKernelGGL(k_endpoints, dim3(eg), dim3(NT), 0, s, edges, (uint64_t)E, n,
                            bucketed ? (uint32_t)(n - 1) : (uint32_t)n, ep, ctrl, partial,
-                           ep_sort ? radix_first_counts(radix_tmp) : nullptr, ep_tiles, ep_tile, ep_dg);
+                           ep_sort ? radix_first_counts(radix_tmp) : nullptr, ep_tiles, ep_tile, ep_dg, p1_counts,
+                           p1_f, RadixDigit{vbits - ORIENT_PART_BITS, (1u << ORIENT_PART_BITS) - 1u});
         if (bucketed) {
             // partition by bits [bw, vbits), then count per bucket
             const uint32_t nb = 1u << (vbits - bw);
@@ -1159,12 +1184,12 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     const uint64_t sentinel = (2 * nb >= 64) ? ~0ull : ((1ull << (2 * nb)) - 1ull);
     const uint32_t e_tile = radix_tile_keys((size_t)E, 8);
     const uint32_t e_tiles = (uint32_t)(((uint64_t)E + e_tile - 1) / e_tile);
-    const bool part = vbits >= ORIENT_PART_MIN_BITS;
+    const bool part = orient_part;
     if (part) {
         // pairs by their first id's high bits, then by their second's (first id -> rank)
-        const int ob = 8;
+        const int ob = ORIENT_PART_BITS;
         radix_pass_u64((const uint64_t*)edges, keysB, (size_t)E, vbits - ob, ob, RadixXf{RX_NONE, nullptr, n, 0, 0},
-                       radix_tmp, s);
+                       radix_tmp, s, p1_counts);
         radix_pass_u64(keysB, keysA, (size_t)E, 32 + vbits - ob, ob, RadixXf{RX_RANK_LOW, rank, n, 0, 0}, radix_tmp,
                        s);
     } else if (e_tile % (16 * NT) == 0)

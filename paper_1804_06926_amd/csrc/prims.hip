@@ -562,15 +562,17 @@ static int radix_sort_any(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* 
 
 template <int RS_ITEMS, typename XF>
 static void radix_pass_xf(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, XF xf,
-                          bool hist_xf, void* temp, hipStream_t s) {
+                          bool hist_xf, uint32_t* counted, void* temp, hipStream_t s) {
     const uint32_t ntiles = (uint32_t)rs_ntiles(cap, RS_NT * RS_ITEMS);
-    uint32_t* hist = (uint32_t*)temp;
+    uint32_t* hist = counted ? counted : (uint32_t*)temp;
     void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * (ntiles + 1), 256);
     uint32_t* digit_tot = (uint32_t*)scan_tmp;
     uint32_t* seg_tot = (uint32_t*)((char*)scan_tmp + align_up(scan_temp_bytes(), 256));
     const uint32_t nseg = (uint32_t)rs_nseg(ntiles);
     const uint32_t dmask = (1u << bits) - 1u;
-    if (hist_xf)   // the digit depends on the transformed key
+    if (counted)   // the kernel that wrote or read the keys before has counted the digits
+        ;
+    else if (hist_xf)   // the digit depends on the transformed key
         hipLaunchKernelGGL((k_radix_hist<uint64_t, RS_ITEMS, XF>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr,
                            (uint32_t)cap, shift, dmask, hist, ntiles, xf);
     else
@@ -588,25 +590,26 @@ static void radix_pass_xf(const uint64_t* kin, uint64_t* kout, size_t cap, int s
 
 template <int RS_ITEMS>
 static void radix_pass_kind(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& x,
-                            void* temp, hipStream_t s) {
+                            uint32_t* counted, void* temp, hipStream_t s) {
     if (x.kind == RX_RANK_LOW)   // the digit lies in the untouched high half
-        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfRankLow{x.rank, x.n}, false, temp, s);
+        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfRankLow{x.rank, x.n}, false, counted, temp, s);
     else if (x.kind == RX_ORIENT)
-        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfOrient{x.rank, x.n, x.nb, x.sentinel}, true, temp, s);
+        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfOrient{x.rank, x.n, x.nb, x.sentinel}, true, counted,
+                                temp, s);
     else
-        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfIdentity(), false, temp, s);
+        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfIdentity(), false, counted, temp, s);
 }
 
 void radix_pass_u64(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& xf,
-                    void* temp, hipStream_t s) {
+                    void* temp, hipStream_t s, uint32_t* counted) {
     if (cap == 0 || bits <= 0) return;
     const uint32_t tile = radix_tile_keys(cap, 8);
     if (tile == RS_NT * RS_ITEMS_HUGE)
-        radix_pass_kind<RS_ITEMS_HUGE>(kin, kout, cap, shift, bits, xf, temp, s);
+        radix_pass_kind<RS_ITEMS_HUGE>(kin, kout, cap, shift, bits, xf, counted, temp, s);
     else if (tile == RS_NT * RS_ITEMS_LARGE)
-        radix_pass_kind<RS_ITEMS_LARGE>(kin, kout, cap, shift, bits, xf, temp, s);
+        radix_pass_kind<RS_ITEMS_LARGE>(kin, kout, cap, shift, bits, xf, counted, temp, s);
     else
-        radix_pass_kind<RS_ITEMS_SMALL>(kin, kout, cap, shift, bits, xf, temp, s);
+        radix_pass_kind<RS_ITEMS_SMALL>(kin, kout, cap, shift, bits, xf, counted, temp, s);
 }
 
 int radix_digit_width(int bits) { return digit_width(bits); }
