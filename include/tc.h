@@ -289,11 +289,11 @@ tc_status tc_radix_sort_u64(tc_ctx* ctx, uint64_t* d_keys, uint64_t* d_keys_alt,
  * in place, so a pair list sorted by row leaves with each row sorted by column
  * (the sorted out-lists of Section 3.2). Runs of up to 64 keys are sorted
  * together by a network across a wave, up to 2048 by one wave's registers, up
- * to 8192 by a whole block, longer ones by a whole block's radix passes in
+ * to 4096 by a whole block, longer ones by a whole block's radix passes in
  * d_tmp. Any key order is safe (runs are the maximal stretches of equal high
  * bits); only grouped input yields a sorted array.
  *   d_keys  count uint64 keys, 16-byte aligned, device; sorted in place.
- *   d_tmp   caller scratch of count uint64, device (runs longer than 8192).
+ *   d_tmp   caller scratch of count uint64, device (runs longer than 4096).
  *   shift   1..32.
  * Errors: TC_ERR_INVALID_ARG (null or misaligned pointer, bad shift or count),
  * TC_ERR_UNSUPPORTED (count >= 2^31); the call synchronises its stream.

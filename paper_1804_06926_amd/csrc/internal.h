@@ -67,7 +67,7 @@ uint32_t* radix_first_counts(void* temp);
 // ---- runsort.hip
 // Keys grouped by key >> shift (ascending; 1 <= shift <= 32) are sorted by the
 // whole key inside each run of equal high bits, in place; keys 16-byte aligned,
-// tmp as many keys as keys (scratch for runs longer than 8192). With skip, a
+// tmp as many keys as keys (scratch for runs longer than 4096). With skip, a
 // run whose first key is skip_key (it must hold only that key) is left alone.
 // With kept non-null, kept[p / chunk] += the keys at positions p that differ
 // from the key before them, over the runs sorted (kept must start at zero).

@@ -39,7 +39,7 @@ constexpr uint32_t SR_WIN = 64;                    // positions per window of sh
 constexpr uint32_t SR_NWIN = SR_TILE / SR_WIN;
 constexpr uint32_t SR_SHORT = 64;
 constexpr uint32_t SR_MED = 2048;                  // one wave, at most 32 values per lane
-constexpr uint32_t SR_BLOCK = 8192;                // the block, 32 values per lane
+constexpr uint32_t SR_BLOCK = 4096;                // the block, 16 values per lane
 constexpr uint32_t SR_MAXMED = SR_TILE / (SR_SHORT + 1) + 1;   // medium runs that can start in one tile
 constexpr uint32_t SR_MAXLONG = SR_TILE / (SR_MED + 1) + 1;   // runs past SR_MED that can start in one tile
 
@@ -200,7 +200,7 @@ __device__ __forceinline__ void sort_wave(T (&x)[P]) {
 // LDS position of tile-relative position p: one word of skew per 64 keeps the
 // strided reads of the register sorts (lane l, element r at l * P + r) free of
 // bank conflicts.
-__device__ __forceinline__ uint32_t sk(uint32_t p) { return p + (p >> 6); }
+__host__ __device__ constexpr uint32_t sk(uint32_t p) { return p + (p >> 6); }
 
 // The short runs of one window, slots [0, S) = tile positions [sp0, sp0 + S),
 // S <= 127, P slots per lane (1 or 2): each slot's low bits with the index of
@@ -363,9 +363,14 @@ __device__ void block_sort_run(uint64_t* run, uint32_t* tA, uint32_t L, const So
 
 constexpr uint32_t SR_SPAN = SR_TILE + SR_MED;   // the tile and the overflow of its last run
 constexpr uint32_t SR_NFLAG = SR_TILE / 16 + 8;  // run-start bits, 16 positions each (none past the tile)
-constexpr uint32_t SR_LDS = (SR_SPAN > SR_BLOCK ? SR_SPAN : SR_BLOCK) + SR_BLOCK / 64;
+// s_v holds tile-relative positions 0 .. SR_SPAN - 1 (the tile, then the overflow of
+// its last row) and, for the long rows, block network elements 0 .. SR_BLOCK - 1, each at
+// its skewed index sk(p)
+constexpr uint32_t SR_VMAX = SR_SPAN > SR_BLOCK ? SR_SPAN : SR_BLOCK;
+constexpr uint32_t SR_LDS = sk(SR_VMAX - 1) + 1;
+static_assert(sk(SR_SPAN - 1) < SR_LDS && sk(SR_BLOCK - 1) < SR_LDS, "skewed LDS index past the array");
 
-__global__ __launch_bounds__(SR_NT, 3) void k_sort_runs(SortRunsArgs a) {
+__global__ __launch_bounds__(SR_NT, 4) void k_sort_runs(SortRunsArgs a) {
     __shared__ uint32_t s_v[SR_LDS];                   // low bits of the keys, tile-relative position p at sk(p)
     __shared__ uint16_t s_bnd[SR_TILE];                 // run starts in the tile, ascending
     __shared__ uint16_t s_flag[SR_NFLAG];

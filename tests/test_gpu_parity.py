@@ -305,6 +305,8 @@ def _run_lengths(kind, rng):
         return [64, 65, 2048, 2049, 1, 2, 127, 128, 4095, 4096, 4097, 63, 1, 8192, 3]
     if kind == "huge":           # one run over many tiles, between short ones
         return rng.integers(1, 40, 200).tolist() + [300_000] + rng.integers(1, 300, 200).tolist()
+    if kind == "overflow":       # a 2048-key run from the last position of a tile: its overflow
+        return ([1] * 4095 + [2048]) * 3 + [2000, 1, 2048]   # reaches the end of the block's LDS span
     if kind == "powerlaw":       # row lengths like a degree-ordered R-MAT out-list
         return np.minimum((rng.pareto(1.2, 120_000) * 4 + 1).astype(np.int64), 5000).tolist()
     raise ValueError(kind)
@@ -312,7 +314,8 @@ def _run_lengths(kind, rng):
 
 @pytest.mark.parametrize("shift,kind", [(24, "singletons"), (24, "short"), (24, "windows"), (24, "edges"),
                                         (20, "huge"), (24, "powerlaw"), (32, "powerlaw"), (7, "windows"),
-                                        (1, "edges"), (13, "short"), (24, "one")])
+                                        (1, "edges"), (13, "short"), (24, "one"), (24, "overflow"),
+                                        (32, "overflow")])
 def test_sort_runs_sorts_every_run(tc, shift, kind):
     """tc_sort_runs_u64 on keys grouped by their high bits gives np.sort of them (runs of every length
     class, duplicates inside runs, ragged last tile)."""
