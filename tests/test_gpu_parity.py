@@ -48,8 +48,21 @@ def _dirty(e, n, seed):
     return graphgen.shuffle_edges(np.concatenate([e, dup, loops]).astype(np.int32), seed)
 
 
+def _repeated(e, n, seed):
+    """Three pairs repeated 1500, 3000 and 10000 times: after orientation their rows hold that
+    many keys, so the row sort takes its one-wave, whole-block and radix paths."""
+    rng = np.random.default_rng(seed)
+    pick = e[e[:, 0] != e[:, 1]][rng.integers(0, e.shape[0] // 2, 3)]
+    reps = [np.repeat(pick[k:k + 1], c, axis=0) for k, c in enumerate((1500, 3000, 10000))]
+    return graphgen.shuffle_edges(np.concatenate([e] + reps).astype(np.int32), seed)
+
+
 CASES = {
     "fig4": _fig4,
+    "repeated_rows": lambda: (_repeated(graphgen.rmat(12, 16, seed=5), 4096, 5), 4096),
+    # the same past 2^21 vertices (orientation by partition passes)
+    "repeated_rows_22bit": lambda: (_repeated(graphgen.chung_lu(4_100_000, 1_000_000, seed=18), 4_100_000, 18),
+                                    4_100_000),
     "k5": lambda: (graphgen.complete(5), 5),
     "k40": lambda: (graphgen.complete(40), 40),
     "bipartite": lambda: (graphgen.complete_bipartite(17, 23), 40),
