@@ -402,6 +402,20 @@ tc_status tc_selector_get_params(tc_ctx* ctx, float* h_params);
 tc_status tc_selector_set_tile_params(tc_ctx* ctx, const float* h_params);
 tc_status tc_selector_get_tile_params(tc_ctx* ctx, float* h_params);
 
+/*
+ * Selector parameter files: JSON {"format": "tc-selector-v1", "num_params":
+ * TC_SELECTOR_NUM_PARAMS, "params": [...], "meta": {...}, "tile_params":
+ * [...]} (tile_params optional), the format the training driver writes.
+ * tc_selector_load installs both networks (as tc_selector_set_params and
+ * tc_selector_set_tile_params; no tile_params removes the tile network);
+ * tc_selector_save writes the context's current parameters (floats printed
+ * with 9 significant digits, which float32 values survive exactly).
+ * Errors: TC_ERR_INVALID_ARG for a null argument, a file that cannot be opened,
+ * read or written, or one that is not in this format (tc_last_error says which).
+ */
+tc_status tc_selector_load(tc_ctx* ctx, const char* path);
+tc_status tc_selector_save(tc_ctx* ctx, const char* path);
+
 /* Logits d_logits [batch][3] of features d_x [batch][6] (device arrays). */
 tc_status tc_selector_forward(tc_ctx* ctx, const float* d_x, int32_t batch, float* d_logits);
 

@@ -38,6 +38,8 @@ from ._lib import (  # noqa: F401
     sort_runs_u64,
     selector_forward,
     selector_get_params,
+    selector_load,
+    selector_save,
     selector_gradient,
     selector_set_params,
     selector_get_tile_params,

@@ -473,9 +473,12 @@ def _sel_lib():
     lib.tc_selector_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, fp]
     lib.tc_selector_set_tile_params.argtypes = [vp, fp]
     lib.tc_selector_get_tile_params.argtypes = [vp, fp]
+    lib.tc_selector_load.argtypes = [vp, ctypes.c_char_p]
+    lib.tc_selector_save.argtypes = [vp, ctypes.c_char_p]
     for f in ("tc_bucket_features", "tc_profile_buckets", "tc_selector_set_params", "tc_selector_get_params",
               "tc_selector_forward", "tc_selector_gradient", "tc_selector_train_step",
-              "tc_selector_set_tile_params", "tc_selector_get_tile_params"):
+              "tc_selector_set_tile_params", "tc_selector_get_tile_params", "tc_selector_load",
+              "tc_selector_save"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -492,6 +495,18 @@ def selector_set_params(params, device="cuda:0") -> None:
         raise ValueError(f"expected {SELECTOR_NUM_PARAMS} parameters")
     ctx, _ = _ctx(device)
     _check(_sel_lib().tc_selector_set_params(ctx, _fptr(p)), ctx)
+
+
+def selector_load(path, device="cuda:0") -> None:
+    """Install both networks from a selector parameter file (the library's own JSON reader)."""
+    ctx, _ = _ctx(device)
+    _check(_sel_lib().tc_selector_load(ctx, os.fsencode(path)), ctx)
+
+
+def selector_save(path, device="cuda:0") -> None:
+    """Write the context's selector parameters to a file in the same format."""
+    ctx, _ = _ctx(device)
+    _check(_sel_lib().tc_selector_save(ctx, os.fsencode(path)), ctx)
 
 
 def selector_get_params(device="cuda:0"):

@@ -1,5 +1,6 @@
 // C ABI of the library (declared in include/tc.h).
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -865,6 +866,92 @@ tc_status tc_selector_get_params(tc_ctx* ctx, float* h_params) {
                                   ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     return e == hipSuccess ? TC_OK : hip_fail(ctx, e, "get selector parameters");
+}
+
+// ---- selector parameter files
+namespace {
+// The numbers of the array after "key": in text (the first such key).
+bool json_floats(const std::string& text, const char* key, std::vector<float>& out) {
+    const std::string k = std::string("\"") + key + "\"";
+    size_t p = text.find(k);
+    if (p == std::string::npos) return false;
+    p = text.find_first_not_of(" \t\r\n", p + k.size());
+    if (p == std::string::npos || text[p] != ':') return false;
+    p = text.find_first_not_of(" \t\r\n", p + 1);
+    if (p == std::string::npos || text[p] != '[') return false;
+    out.clear();
+    const char* base = text.c_str();
+    ++p;
+    for (;;) {
+        p = text.find_first_not_of(" \t\r\n", p);
+        if (p == std::string::npos) return false;
+        if (text[p] == ']') return true;
+        char* end = nullptr;
+        const float v = strtof(base + p, &end);
+        if (end == base + p) return false;
+        out.push_back(v);
+        p = text.find_first_not_of(" \t\r\n", (size_t)(end - base));
+        if (p == std::string::npos) return false;
+        if (text[p] == ',') ++p;
+        else if (text[p] != ']') return false;
+    }
+}
+
+bool write_floats(FILE* f, const char* key, const std::vector<float>& v) {
+    if (fprintf(f, "\"%s\": [", key) < 0) return false;
+    for (size_t i = 0; i < v.size(); ++i)
+        if (fprintf(f, i ? ", %.9g" : "%.9g", (double)v[i]) < 0) return false;
+    return fprintf(f, "]") >= 0;
+}
+}  // namespace
+
+tc_status tc_selector_load(tc_ctx* ctx, const char* path) {
+    if (!ctx) return TC_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    if (!path) return arg_fail(ctx, TC_ERR_INVALID_ARG, "null path");
+    FILE* f = fopen(path, "rb");
+    if (!f) return arg_fail(ctx, TC_ERR_INVALID_ARG, "cannot open the selector parameter file");
+    std::string text;
+    char buf[65536];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    const bool read_ok = !ferror(f);
+    fclose(f);
+    if (!read_ok) return arg_fail(ctx, TC_ERR_INVALID_ARG, "cannot read the selector parameter file");
+    if (text.find("\"tc-selector-v1\"") == std::string::npos)
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "not a tc-selector-v1 parameter file");
+    std::vector<float> p, t;
+    if (!json_floats(text, "params", p) || p.size() != (size_t)tcx::MLP_NPARAM)
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "params: not TC_SELECTOR_NUM_PARAMS numbers");
+    const bool has_tile = text.find("\"tile_params\"") != std::string::npos;
+    if (has_tile && (!json_floats(text, "tile_params", t) || t.size() != (size_t)tcx::MLP_NPARAM))
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "tile_params: not TC_SELECTOR_NUM_PARAMS numbers");
+    const tc_status st = tc_selector_set_params(ctx, p.data());
+    if (st != TC_OK) return st;
+    return tc_selector_set_tile_params(ctx, has_tile ? t.data() : nullptr);
+}
+
+tc_status tc_selector_save(tc_ctx* ctx, const char* path) {
+    if (!ctx) return TC_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    if (!path) return arg_fail(ctx, TC_ERR_INVALID_ARG, "null path");
+    std::vector<float> p(tcx::MLP_NPARAM), t;
+    tc_status st = tc_selector_get_params(ctx, p.data());
+    if (st != TC_OK) return st;
+    if (ctx->tile_ready) {
+        t.resize(tcx::MLP_NPARAM);
+        st = tc_selector_get_tile_params(ctx, t.data());
+        if (st != TC_OK) return st;
+    }
+    FILE* f = fopen(path, "wb");
+    if (!f) return arg_fail(ctx, TC_ERR_INVALID_ARG, "cannot open the file for writing");
+    bool ok = fprintf(f, "{\"format\": \"tc-selector-v1\", \"num_params\": %d, ", (int)tcx::MLP_NPARAM) >= 0;
+    ok = ok && write_floats(f, "params", p) && fprintf(f, ", \"meta\": {}") >= 0;
+    if (ok && !t.empty()) ok = fprintf(f, ", ") >= 0 && write_floats(f, "tile_params", t);
+    ok = ok && fprintf(f, "}\n") >= 0;
+    ok = (fclose(f) == 0) && ok;
+    if (!ok) return arg_fail(ctx, TC_ERR_INVALID_ARG, "cannot write the selector parameter file");
+    return TC_OK;
 }
 
 tc_status tc_selector_forward(tc_ctx* ctx, const float* d_x, int32_t batch, float* d_logits) {

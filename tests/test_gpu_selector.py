@@ -255,3 +255,25 @@ def test_profile_choices_applies_the_given_strategies(tc):
     st = tc.last_stats()
     for b in range(255):
         assert st["bucket_kernel"][b] == selector.heuristic_choice(b)
+
+
+def test_selector_file_load_and_save(tc, tmp_path):
+    """tc_selector_load reads the shipped parameter file into exactly the float32 parameters the
+    Python reader gives, for both networks; tc_selector_save writes a file that reads back the
+    same; a file with the wrong number of parameters is rejected."""
+    from paper_1804_06926_amd import selector
+    path = selector.DEFAULT_WEIGHTS
+    tc.selector_load(path)
+    np.testing.assert_array_equal(tc.selector_get_params(), selector.load(path))
+    np.testing.assert_array_equal(tc.selector_get_tile_params(), selector.load_tile(path))
+    out = tmp_path / "saved.json"
+    tc.selector_save(str(out))
+    np.testing.assert_array_equal(selector.load(str(out)), selector.load(path))
+    np.testing.assert_array_equal(selector.load_tile(str(out)), selector.load_tile(path))
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"format": "tc-selector-v1", "num_params": 1379, "params": [1.0, 2.0]}')
+    with pytest.raises(tc.TCError):
+        tc.selector_load(str(bad))
+    with pytest.raises(tc.TCError):
+        tc.selector_load(str(tmp_path / "missing.json"))
+    tc.selector_load(path)   # leave the shipped networks installed
