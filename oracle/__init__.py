@@ -50,6 +50,8 @@ def _load():
         build()
     lib = ctypes.CDLL(_SO)
     vp = ctypes.c_void_p
+    lib.tc_oracle_count.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int]
+    lib.tc_oracle_count.restype = ctypes.c_uint64
     lib.oracle_graph_build.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(vp)]
     lib.oracle_graph_build.restype = ctypes.c_int
     lib.oracle_graph_build_timed.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(vp), vp]
@@ -210,6 +212,17 @@ class Graph:
         if self.m:
             _load().oracle_edge_support(self._h, out.ctypes.data, self.threads)
         return out
+
+
+def tc_oracle_count(edges: np.ndarray, n: int, per_vertex: bool = False, threads: int = 0):
+    """The one-call C entry (edge list to T, and t[v] with per_vertex); None for invalid input."""
+    e = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    t = np.zeros(max(n, 0), dtype=np.uint64) if per_vertex else None
+    T = int(_load().tc_oracle_count(e.ctypes.data if e.size else None, e.shape[0], n,
+                                    t.ctypes.data if per_vertex and n > 0 else None, threads))
+    if T == (1 << 64) - 1:
+        return None
+    return (T, t) if per_vertex else T
 
 
 def count_triangles(edges: np.ndarray, n: int, per_vertex: bool = False, threads: int = 0,

@@ -284,6 +284,22 @@ uint64_t oracle_count_forward(const void* h, int order_mode, uint64_t* per_verte
 }
 
 /*
+ * One call from the edge list to T (Section 3.2, Algorithm 2): canonicalise,
+ * orient by (degree, id), count by the forward algorithm. h_per_vertex (may
+ * be NULL) receives t[v] for v in [0, num_vertices). A null or negative
+ * argument, or an id outside [0, num_vertices), returns UINT64_MAX and writes
+ * nothing. threads <= 0: all cores.
+ */
+uint64_t tc_oracle_count(const int32_t* h_edges, int64_t num_edges, int32_t num_vertices, uint64_t* h_per_vertex,
+                         int threads) {
+    void* h = nullptr;
+    if (oracle_graph_build(h_edges, num_edges, num_vertices, threads, &h) != 0) return UINT64_MAX;
+    const uint64_t T = oracle_count_forward(h, 0, h_per_vertex, threads);
+    oracle_graph_free(h);
+    return T;
+}
+
+/*
  * The forward algorithm's per-edge intersection sizes (Algorithm 2): for each kept edge
  * x -> y of the (degree, id) orientation, |N+(x) intersected with N+(y)| by a
  * two-pointer merge of the two out-lists, written at the index of the edge's

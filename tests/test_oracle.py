@@ -399,3 +399,16 @@ def test_forward_row_sample_counts_triangles_of_sampled_earliest_vertices(stride
         assert T == g.count()
     with pytest.raises(ValueError):
         g.count_rows(0)
+
+
+def test_one_call_entry_matches_the_graph_path():
+    """tc_oracle_count (edge list to T in one C call) gives the closed form on K_n and the same T
+    and t[v] as the graph path on dirty R-MAT input; an id out of range is refused."""
+    assert oracle.tc_oracle_count(graphgen.complete(12), 12) == 220   # C(12, 3)
+    e = graphgen.rmat(11, 8, seed=9)
+    e = np.concatenate([e, e[:100, ::-1], np.array([[3, 3], [5, 5]], np.int32)])
+    T, t = oracle.tc_oracle_count(e, 2048, per_vertex=True)
+    T2, t2 = oracle.count_triangles(e, 2048, per_vertex=True)
+    assert T == T2 and np.array_equal(t, t2)
+    assert oracle.tc_oracle_count(np.array([[0, 5]], np.int32), 5) is None
+    assert oracle.tc_oracle_count(np.zeros((0, 2), np.int32), 0) == 0
