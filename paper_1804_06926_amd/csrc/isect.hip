@@ -652,7 +652,7 @@ __device__ __forceinline__ uint32_t isect_edge(const IsectArgs& a, const uint32_
 }
 
 template <bool MERGE>
-__global__ __launch_bounds__(IS_NT) void k_isect_edges(IsectArgs a, uint64_t* partials) {
+__global__ __launch_bounds__(IS_NT, MERGE ? 7 : 6) void k_isect_edges(IsectArgs a, uint64_t* partials) {
     __shared__ uint32_t sb[STAGE_MAX];
     __shared__ uint32_t s_boff[SEG_MAX + 1];
     __shared__ Segs S;
@@ -689,13 +689,26 @@ __global__ __launch_bounds__(IS_NT) void k_isect_edges(IsectArgs a, uint64_t* pa
         const uint32_t ngroups = IS_NT / g;
         const uint32_t ne = S.pref[nseg];
         const uint32_t rounds = (ne + ngroups - 1) / ngroups;
+        // each round's in-edge entry (tail start | end << 32) is loaded one round ahead,
+        // so that its latency overlaps the intersection before it
+        uint32_t sg_next = 0;
+        uint64_t ent_next = 0;
+        if (gi < ne) {
+            sg_next = nseg == 1 ? 0u : find_seg(S, nseg, gi);
+            ent_next = a.csc[S.e0[sg_next] + (gi - S.pref[sg_next])];
+        }
         for (uint32_t r = 0; r < rounds; ++r) {
             const uint32_t q = r * ngroups + gi;
+            const uint32_t sg = sg_next;
+            const uint64_t ent = ent_next;
+            const uint32_t qn = q + ngroups;
+            if (qn < ne) {
+                sg_next = nseg == 1 ? 0u : find_seg(S, nseg, qn);
+                ent_next = a.csc[S.e0[sg_next] + (qn - S.pref[sg_next])];
+            }
             uint32_t c = 0, e = 0, v = 0;
             if (q < ne) {
-                const uint32_t sg = nseg == 1 ? 0u : find_seg(S, nseg, q);
                 v = S.v[sg];
-                const uint64_t ent = a.csc[S.e0[sg] + (q - S.pref[sg])];   // tail start | end << 32
                 const uint32_t s = (uint32_t)ent, end = (uint32_t)(ent >> 32);
                 e = s - 1u;
                 const uint32_t nb = s_boff[sg + 1] - s_boff[sg];
