@@ -283,6 +283,24 @@ tc_status tc_radix_sort_u64(tc_ctx* ctx, uint64_t* d_keys, uint64_t* d_keys_alt,
                             int32_t bit_hi, void* d_workspace, size_t workspace_bytes);
 
 /*
+ * One radix pass of the CSR builder (step 3) that only partitions: the count
+ * uint64 keys of d_in are written to d_out grouped by their digit
+ * (key >> shift) & (2^bits - 1), digits ascending, keys of one digit in no
+ * particular order (ranks come from atomics, so the order can change from
+ * call to call). It is the form the builder uses where the order inside a
+ * digit is free: the first pass of a sort whose equal keys are identical or
+ * re-sorted later, and the grouping passes.
+ *   d_in, d_out  count uint64 each, device, distinct buffers.
+ *   shift, bits  0 <= shift, 1 <= bits <= 8, shift + bits <= 64.
+ *   d_workspace  at least tc_radix_sort_workspace_size(count) bytes.
+ * Errors: TC_ERR_INVALID_ARG (null or equal pointers, bad shift or bits),
+ * TC_ERR_UNSUPPORTED (count >= 2^31), TC_ERR_WORKSPACE; the call synchronises
+ * its stream.
+ */
+tc_status tc_radix_partition_u64(tc_ctx* ctx, const uint64_t* d_in, uint64_t* d_out, int64_t count, int32_t shift,
+                                 int32_t bits, void* d_workspace, size_t workspace_bytes);
+
+/*
  * The second half of the CSR builder's pair sort (step 3), exposed for reuse:
  * the keys, already grouped by their high bits (key >> shift, runs of equal
  * high bits in ascending order), are sorted by the whole key inside every run,

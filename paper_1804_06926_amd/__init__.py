@@ -35,6 +35,7 @@ from ._lib import (  # noqa: F401
     profile_choices,
     profile_selected,
     radix_sort_u64,
+    radix_partition_u64,
     sort_runs_u64,
     selector_forward,
     selector_get_params,

@@ -67,6 +67,7 @@ def _load():
     lib.tc_radix_sort_workspace_size.argtypes = [i64]
     lib.tc_radix_sort_workspace_size.restype = sz
     lib.tc_radix_sort_u64.argtypes = [vp, vp, vp, i64, i32, i32, vp, sz]
+    lib.tc_radix_partition_u64.argtypes = [vp, vp, vp, i64, i32, i32, vp, sz]
     lib.tc_sort_runs_u64.argtypes = [vp, vp, vp, i64, i32]
     lib.tc_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i32]
     lib.tc_stage_times.restype = i32
@@ -77,7 +78,7 @@ def _load():
     for f in ("tc_create", "tc_destroy", "tc_workspace_size", "tc_count_triangles", "tc_count_triangles_async",
               "tc_clustering", "tc_edge_support", "tc_list_workspace_size", "tc_list_triangles",
               "tc_edge_counts",
-              "tc_build_csr", "tc_radix_sort_u64", "tc_sort_runs_u64"):
+              "tc_build_csr", "tc_radix_sort_u64", "tc_radix_partition_u64", "tc_sort_runs_u64"):
         getattr(lib, f).restype = ctypes.c_int
     _ = u32
     _lib = lib
@@ -414,6 +415,23 @@ def radix_sort_u64(keys, bit_lo: int = 0, bit_hi: int = 64):
     st = lib.tc_radix_sort_u64(ctx, keys.data_ptr(), alt.data_ptr(), n, bit_lo, bit_hi, ws.data_ptr(), nbytes)
     _check(st, ctx)
     return keys
+
+
+def radix_partition_u64(keys, shift: int, bits: int):
+    """One partitioning radix pass of a 64-bit CUDA tensor: a new tensor holding the keys grouped
+    by digit (key >> shift) & (2**bits - 1), digits ascending, order inside a digit arbitrary."""
+    torch = _torch()
+    if not (isinstance(keys, torch.Tensor) and keys.is_cuda and keys.element_size() == 8 and keys.is_contiguous()):
+        raise TypeError("keys must be a contiguous 64-bit CUDA tensor")
+    ctx, idx = _ctx(keys.device)
+    n = keys.numel()
+    lib = _load()
+    nbytes = int(lib.tc_radix_sort_workspace_size(n))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=keys.device)
+    out = torch.empty_like(keys)
+    st = lib.tc_radix_partition_u64(ctx, keys.data_ptr(), out.data_ptr(), n, shift, bits, ws.data_ptr(), nbytes)
+    _check(st, ctx)
+    return out
 
 
 def sort_runs_u64(keys, shift: int):

@@ -504,6 +504,27 @@ tc_status tc_radix_sort_u64(tc_ctx* ctx, uint64_t* d_keys, uint64_t* d_keys_alt,
     return TC_OK;
 }
 
+tc_status tc_radix_partition_u64(tc_ctx* ctx, const uint64_t* d_in, uint64_t* d_out, int64_t count, int32_t shift,
+                                 int32_t bits, void* d_workspace, size_t workspace_bytes) {
+    if (!ctx) return TC_ERR_INVALID_ARG;
+    ctx->last_error.clear();
+    if (count < 0 || shift < 0 || bits < 1 || bits > 8 || shift + bits > 64)
+        return arg_fail(ctx, TC_ERR_INVALID_ARG, "bad count, shift or bits");
+    if (count > kMaxEdges) return arg_fail(ctx, TC_ERR_UNSUPPORTED, "count must be < 2^31");
+    if (count == 0) return TC_OK;
+    if (!d_in || !d_out || !d_workspace) return arg_fail(ctx, TC_ERR_INVALID_ARG, "null pointer");
+    if ((const void*)d_in == (const void*)d_out) return arg_fail(ctx, TC_ERR_INVALID_ARG, "d_in and d_out must differ");
+    if (workspace_bytes < tcx::radix_temp_bytes((size_t)count))
+        return arg_fail(ctx, TC_ERR_WORKSPACE, "workspace too small");
+    DeviceGuard guard(ctx->device);
+    tcx::radix_pass_u64(d_in, d_out, (size_t)count, shift, bits, tcx::RadixXf{tcx::RX_NONE, nullptr, 0, 0, 0},
+                        d_workspace, ctx->stream, nullptr, false);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "radix partition");
+    return TC_OK;
+}
+
 tc_status tc_sort_runs_u64(tc_ctx* ctx, uint64_t* d_keys, uint64_t* d_tmp, int64_t count, int32_t shift) {
     if (!ctx) return TC_ERR_INVALID_ARG;
     ctx->last_error.clear();

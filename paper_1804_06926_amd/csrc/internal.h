@@ -21,12 +21,17 @@ size_t radix_temp_bytes(size_t cap);
 // (nearly) equal digit widths, optional uint32 payload. The count is read from
 // d_count on the device (nullptr: cap). With first_counted, the kernel that
 // wrote the keys has already filled the first pass's per-tile digit counts
-// (radix_first_counts, see TileCounts). Returns 1 when the sorted data ended
-// up in the *_alt buffers.
+// (radix_first_counts, see TileCounts). With first_unstable, the first pass
+// only partitions (ranks by LDS atomics): the keys come out sorted on
+// [bit_lo, bit_hi), but keys equal on those bits in no particular order, so
+// use it where that order is free (the whole key sorted, or a grouping).
+// Returns 1 when the sorted data ended up in the *_alt buffers.
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted = false);
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted = false,
+                   bool first_unstable = false);
 int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted = false);
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted = false,
+                   bool first_unstable = false);
 // Keys per tile of a sort of cap keys of key_bytes bytes (2048, 4096 or 8192;
 // a multiple of 2048).
 uint32_t radix_tile_keys(size_t cap, int key_bytes);
@@ -41,17 +46,19 @@ enum { RX_NONE = 0, RX_RANK_LOW = 1, RX_ORIENT = 2 };
 struct RadixXf {
     int kind;
     const uint32_t* rank;
-    int32_t n;
+    int32_t n;   // >= 1 for RX_RANK_LOW and RX_ORIENT (lanes past the end read rank[0])
     int nb;
     uint64_t sentinel;
 };
-// One stable radix pass of 64-bit keys on bits [shift, shift + bits), bits <= 8,
-// from kin to kout (the two must differ), each key transformed as `xf` says.
+// One radix pass of 64-bit keys on bits [shift, shift + bits), bits <= 8, from
+// kin to kout (the two must differ), each key transformed as `xf` says.
 // counted: the per-tile digit counts, already taken by an earlier kernel
 // (counts[d * ntiles + tile], tiles of radix_tile_keys(cap, 8) keys; the pass
 // turns them into offsets in place); nullptr: the pass counts them itself.
+// stable: keys of equal digit keep their input order; otherwise their order
+// is arbitrary (a partition).
 void radix_pass_u64(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& xf,
-                    void* temp, hipStream_t s, uint32_t* counted = nullptr);
+                    void* temp, hipStream_t s, uint32_t* counted, bool stable);
 // Digit width of each pass of a sort over `bits` bits (equal widths, at most 8).
 int radix_digit_width(int bits);
 struct RadixDigit {

@@ -1147,7 +1147,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
             int a0 = 0;
             if (vbits > bw)
                 a0 = radix_sort_u32(ep, ep_alt, nullptr, nullptr, nullptr, (size_t)(2 * E), bw, vbits, radix_tmp, s,
-                                    true);
+                                    true, true);   // a grouping: the order inside a bucket is free
             uint32_t* bst = (uint32_t*)(ws + L.bstart);
             hipLaunchKernelGGL(k_bucket_starts, dim3(grid_for((size_t)nb + 1)), dim3(NT), 0, s, a0 ? ep_alt : ep,
                                (uint32_t)(2 * E), bw, nb, bst);
@@ -1158,7 +1158,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
             hipLaunchKernelGGL(k_drop_sentinels, dim3(1), dim3(NT), 0, s, partial, eg, n, deg);
         } else {
             const int a0 = radix_sort_u32(ep, ep_alt, nullptr, nullptr, nullptr, (size_t)(2 * E), 0,
-                                          bits_for((uint64_t)n + 1), radix_tmp, s, true);
+                                          bits_for((uint64_t)n + 1), radix_tmp, s, true, true);   // whole keys
             fill_u32(rowend, 0u, (size_t)n, s);
             hipLaunchKernelGGL(k_endpoint_bounds, dim3(grid_for((size_t)(2 * E))), dim3(NT), 0, s, a0 ? ep_alt : ep,
                                (uint64_t)(2 * E), n, rowend);
@@ -1186,12 +1186,13 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     const uint32_t e_tiles = (uint32_t)(((uint64_t)E + e_tile - 1) / e_tile);
     const bool part = orient_part;
     if (part) {
-        // pairs by their first id's high bits, then by their second's (first id -> rank)
+        // pairs by their first id's high bits, then by their second's (first id -> rank);
+        // both passes only group the pairs for locality of the rank lookups
         const int ob = ORIENT_PART_BITS;
         radix_pass_u64((const uint64_t*)edges, keysB, (size_t)E, vbits - ob, ob, RadixXf{RX_NONE, nullptr, n, 0, 0},
-                       radix_tmp, s, p1_counts);
+                       radix_tmp, s, p1_counts, false);
         radix_pass_u64(keysB, keysA, (size_t)E, 32 + vbits - ob, ob, RadixXf{RX_RANK_LOW, rank, n, 0, 0}, radix_tmp,
-                       s);
+                       s, nullptr, false);
     } else if (e_tile % (16 * NT) == 0)
         hipLaunchKernelGGL(k_orient<16>, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, edges,
                            (uint64_t)E, n, rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, e_tile,
@@ -1201,17 +1202,20 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
                            (uint64_t)E, n, rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, e_tile,
                            radix_first_digit(nb, 2 * nb));
     mark(3);
-    // ---- sort oriented pairs: a stable radix sort on the lower rank (the row; its
-    // first digit counted by k_orient or, past 2^21 vertices, taken by a first pass
-    // that orients each pair as it loads it), then every row sorted on chip by the
-    // higher rank
+    // ---- sort oriented pairs: a radix sort on the lower rank (the row; its first
+    // digit counted by k_orient or, past 2^21 vertices, taken by a first pass that
+    // orients each pair as it loads it), then every row sorted on chip by the
+    // higher rank. The row sort fixes the order inside a row, so the first pass
+    // only partitions; the later ones are stable.
     int alt;
     if (part) {
         const int w0 = radix_digit_width(nb);
-        radix_pass_u64(keysA, keysB, (size_t)E, nb, w0, RadixXf{RX_ORIENT, rank, n, nb, sentinel}, radix_tmp, s);
+        radix_pass_u64(keysA, keysB, (size_t)E, nb, w0, RadixXf{RX_ORIENT, rank, n, nb, sentinel}, radix_tmp, s,
+                       nullptr, false);
         alt = 1 - radix_sort_u64(keysB, keysA, nullptr, nullptr, nullptr, (size_t)E, nb + w0, 2 * nb, radix_tmp, s);
     } else {
-        alt = radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)E, nb, 2 * nb, radix_tmp, s, true);
+        alt = radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)E, nb, 2 * nb, radix_tmp, s, true,
+                             true);
     }
     uint64_t* sorted = alt ? keysB : keysA;
     uint64_t* other = alt ? keysA : keysB;
@@ -1242,13 +1246,15 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     const uint32_t* moff = off;   // offsets of the middle lists
     if (r.formulation == FORM_FILTERED) {
         // ---- CSC: in-edges with work grouped by v (the sorted pair keys are free now);
-        // in-edge groups: ids 0 .. n - 1 (n - 1 = no work)
+        // in-edge groups: ids 0 .. n - 1 (n - 1 = no work). Each in-edge carries its
+        // own edge index and tail, so the order inside a group is free: the
+        // sort's first pass only partitions.
         const CscPacking pk = csc_packing(E, n);
         hipLaunchKernelGGL(k_csc_keys, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, col, src, off,
                            ctrl, n, other, pk.sh, pk.lbits, radix_first_counts(radix_tmp), e_tiles, e_tile,
                            radix_first_digit(pk.sh, pk.sh + nbv));
         const int alt2 = radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, pk.sh, pk.sh + nbv,
-                                        radix_tmp, s, true);
+                                        radix_tmp, s, true, true);
         // bounds and tail ranges in one pass, into the buffer the sort left free
         const uint64_t* ckeys = alt2 ? sorted : other;
         csc = alt2 ? other : sorted;

@@ -238,11 +238,12 @@ struct XfIdentity {
 // the digit of the pass, is unchanged.
 struct XfRankLow {
     const uint32_t* rank;
-    int32_t n;
+    int32_t n;   // >= 1: an id out of range reads rank[0] and discards it (no branch around the gather)
     __device__ __forceinline__ uint64_t operator()(uint64_t k) const {
         const int32_t a = (int32_t)(uint32_t)k;
-        const uint32_t r = (a >= 0 && a < n) ? rank[a] : 0xFFFFFFFFu;
-        return (k & 0xFFFFFFFF00000000ull) | r;
+        const bool ok = a >= 0 && a < n;
+        const uint32_t r = rank[ok ? a : 0];
+        return (k & 0xFFFFFFFF00000000ull) | (ok ? r : 0xFFFFFFFFu);
     }
 };
 
@@ -287,9 +288,10 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ k
         kk[it] = i < n ? keys[i] : KeyT(0);
     }
 #pragma unroll
-    for (int it = 0; it < RS_ITEMS; ++it) {
+    for (int it = 0; it < RS_ITEMS; ++it) {   // every lane transforms (no branch around the gathers)
         const uint32_t i = base + it * WAVE + l;
-        dg[it] = i < n ? (uint32_t)(xf(kk[it]) >> shift) & dmask : 0u;
+        const uint32_t dd = (uint32_t)(xf(kk[it]) >> shift) & dmask;
+        dg[it] = i < n ? dd : 0u;
     }
     // counts only (no ranks): one LDS atomic per key into the wave's histogram.
     // Lanes that share a digit with the wave's first or second leading lane are
@@ -378,24 +380,45 @@ __global__ __launch_bounds__(RS_NT) void k_radix_rowfix(uint32_t* __restrict__ h
 // (half the registers per lane of 256 x 32, twice the waves per CU); threads
 // 0..255 own the digits in the per-digit scans. Each key passes through xf as it
 // is loaded (the transform must leave the digit of the pass unchanged).
-template <typename KeyT, bool HAS_VAL, int RS_ITEMS, int NT_ = RS_NT, typename XF = XfIdentity>
+// RANK says how a key gets its rank among the wave's keys of its digit:
+//   RANK_MATCH   stable: the lanes of equal digit found by 8 ballots (VALU);
+//   RANK_MASK    stable: each lane sets its bit in a 64-bit LDS mask of its
+//                digit, reads the mask back and the lowest lane clears it; the
+//                LDS applies one wave's instructions in order, so the read sees
+//                exactly this instruction's lanes of that digit (few VALU
+//                operations, one LDS round trip per key);
+//   RANK_ATOMIC  the order inside a digit is whatever the LDS adds give, and
+//                the pass only partitions: for a pass whose later users never
+//                look at that order (the first pass of an LSD sort whose
+//                equal-key order is free, a grouping). One add per key, all of
+//                a thread's adds in flight together.
+// The masks use the key tile's LDS, free until the ranks are known.
+enum { RANK_MATCH = 0, RANK_MASK = 1, RANK_ATOMIC = 2 };
+
+template <typename KeyT, bool HAS_VAL, int RS_ITEMS, int NT_ = RS_NT, typename XF = XfIdentity, int RANK = RANK_MATCH>
 __global__ __launch_bounds__(NT_) void k_radix_scatter(const KeyT* __restrict__ kin,
                                                          const uint32_t* __restrict__ vin,
                                                          KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          const uint32_t* d_count, uint32_t cap, int shift,
                                                          uint32_t dmask,
                                                          const uint32_t* __restrict__ hist_scan, uint32_t ntiles,
-                                                         const uint32_t* __restrict__ digit_tot, XF xf = XF()) {
+                                                         const uint32_t* __restrict__ digit_tot, XF xf) {
     constexpr int NW = NT_ / WAVE;
     constexpr int RS_TILE = NT_ * RS_ITEMS, RS_WAVE_SPAN = WAVE * RS_ITEMS;
     static_assert(NT_ >= 256, "a thread per digit");
     __shared__ uint32_t wcnt[NW][256];
-    __shared__ uint32_t lstart[256];
-    __shared__ uint32_t gbase[256];
+    __shared__ uint32_t gofs[256];
     __shared__ uint32_t scratch[NW];
-    __shared__ KeyT skey[RS_TILE];
+    __shared__ __align__(16) KeyT skey[RS_TILE];
     __shared__ uint32_t sval[HAS_VAL ? RS_TILE : 1];
-    for (int i = threadIdx.x; i < NW * 256; i += NT_) (&wcnt[0][0])[i] = 0;
+    constexpr bool MASK_IN_TILE = sizeof(KeyT) * RS_TILE >= sizeof(uint64_t) * 256 * NW;
+    __shared__ uint64_t mask_own[RANK == RANK_MASK && !MASK_IN_TILE ? NW : 1][RANK == RANK_MASK ? 256 : 1];
+    uint64_t (*wmask)[256] = MASK_IN_TILE ? reinterpret_cast<uint64_t (*)[256]>(skey)
+                                          : reinterpret_cast<uint64_t (*)[256]>(mask_own);
+    for (int i = threadIdx.x; i < NW * 256; i += NT_) {
+        (&wcnt[0][0])[i] = 0;
+        if (RANK == RANK_MASK) (&wmask[0][0])[i] = 0ull;
+    }
     __syncthreads();
     const uint32_t n = rs_count(d_count, cap);
     const int w = wave_id(), l = lane_id();
@@ -412,24 +435,53 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter(const KeyT* __restrict__ 
         k[it] = i < n ? kin[i] : KeyT(0);
         if (HAS_VAL) v[it] = i < n ? vin[i] : 0u;
     }
+    // every lane transforms, lanes past the end their zero key, so that no branch
+    // separates the gathers of a transform: all of them are in flight together
 #pragma unroll
-    for (int it = 0; it < RS_ITEMS; ++it)
-        if (base + it * WAVE + l < n) k[it] = xf(k[it]);
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint64_t t = xf(k[it]);
+        k[it] = base + it * WAVE + l < n ? t : k[it];
+    }
 #pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
         const uint32_t i = base + it * WAVE + l;
         const bool valid = i < n;
         const uint32_t d = (uint32_t)(k[it] >> shift) & dmask;
-        const uint64_t peers = match_digit8(d, __ballot(valid));
-        const uint32_t r = (uint32_t)__popcll(peers & lanes_below());
-        const uint32_t prev = wcnt[w][d];
-        __builtin_amdgcn_wave_barrier();
-        if (valid && r == 0) wcnt[w][d] = prev + (uint32_t)__popcll(peers);
-        __builtin_amdgcn_wave_barrier();
-        loc[it] = d | ((prev + r) << 8);
+        if (RANK != RANK_ATOMIC) {
+            uint64_t peers;
+            if (RANK == RANK_MATCH) {
+                peers = match_digit8(d, __ballot(valid));
+            } else {
+                if (valid) atomicOr((unsigned long long*)&wmask[w][d], 1ull << l);
+                __builtin_amdgcn_wave_barrier();
+                peers = valid ? wmask[w][d] : 0ull;
+                __builtin_amdgcn_wave_barrier();
+            }
+            const uint32_t r = (uint32_t)__popcll(peers & lanes_below());
+            const uint32_t prev = wcnt[w][d];
+            __builtin_amdgcn_wave_barrier();
+            if (valid && r == 0) {
+                wcnt[w][d] = prev + (uint32_t)__popcll(peers);
+                if (RANK == RANK_MASK) wmask[w][d] = 0ull;
+            }
+            __builtin_amdgcn_wave_barrier();
+            loc[it] = d | ((prev + r) << 8);
+        } else {
+            // one LDS atomic per key, none waited on before the next key's: the
+            // ranks of one digit are the counter's successive values in whatever
+            // order the LDS applies the adds (equal digits in one wave serialise
+            // there, at worst 64 adds on one address per instruction)
+            // (lanes past the end add 0 to digit 0's counter: no branch, so no
+            // wait between the atomics)
+            const uint32_t r = atomicAdd(&wcnt[w][valid ? d : 0u], valid ? 1u : 0u);
+            loc[it] = d | (r << 8);
+        }
     }
     __syncthreads();
     {
+        // wcnt[q][d] becomes the tile position of wave q's first key of digit d,
+        // gofs[d] the output position of the tile's first key of digit d minus
+        // its tile position: one LDS lookup per key in each phase below
         const bool own = threadIdx.x < 256;   // threads past the digits add zeros to the scans
         const int d = own ? (int)threadIdx.x : 0;
         uint32_t run = 0;
@@ -442,31 +494,47 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter(const KeyT* __restrict__ 
             }
         }
         const uint32_t excl = block_exclusive_scan<NT_>(run, scratch);
-        if (own) lstart[d] = excl;
         // digit base = keys with a smaller digit; plus this tile's offset in its digit row
         const uint32_t dbase = block_exclusive_scan<NT_>(own ? digit_tot[d] : 0u, scratch);
-        if (own) gbase[d] = dbase + hist_scan[(size_t)d * ntiles + blockIdx.x];
+        if (own) {
+#pragma unroll
+            for (int q = 0; q < NW; ++q) wcnt[q][d] += excl;
+            gofs[d] = dbase + hist_scan[(size_t)d * ntiles + blockIdx.x] - excl;
+        }
     }
     __syncthreads();
+    {
+        uint32_t pb[RS_ITEMS];   // all lookups in flight before the first write
 #pragma unroll
-    for (int it = 0; it < RS_ITEMS; ++it) {
-        const uint32_t i = base + it * WAVE + l;
-        if (i < n) {
-            const uint32_t d = loc[it] & 255u;
-            const uint32_t p = lstart[d] + wcnt[w][d] + (loc[it] >> 8);
-            skey[p] = k[it];
-            if (HAS_VAL) sval[p] = v[it];
+        for (int it = 0; it < RS_ITEMS; ++it) pb[it] = wcnt[w][loc[it] & 255u];
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it) {
+            if (base + it * WAVE + l < n) {
+                const uint32_t p = pb[it] + (loc[it] >> 8);
+                skey[p] = k[it];
+                if (HAS_VAL) sval[p] = v[it];
+            }
         }
     }
     __syncthreads();
     const uint32_t tile_n = n > tile0 ? (n - tile0 < (uint32_t)RS_TILE ? n - tile0 : (uint32_t)RS_TILE) : 0u;
-    for (uint32_t j = threadIdx.x; j < tile_n; j += NT_) {
-        const KeyT key = skey[j];
-        const uint32_t d = (uint32_t)(key >> shift) & dmask;
-        const uint32_t pos = gbase[d] + (j - lstart[d]);
-        if (pos < n) {   // always true when the histogram scan is consistent
-            kout[pos] = key;
-            if (HAS_VAL) vout[pos] = sval[j];
+    {
+        // thread t writes tile positions t, t + NT_, ...: consecutive threads,
+        // consecutive positions, so each digit's run goes out coalesced
+        KeyT key[RS_ITEMS];
+        uint32_t go[RS_ITEMS];
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it) key[it] = skey[it * NT_ + threadIdx.x];   // in the tile's LDS
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it) go[it] = gofs[(uint32_t)(key[it] >> shift) & dmask];
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it) {
+            const uint32_t j = it * NT_ + threadIdx.x;
+            const uint32_t pos = go[it] + j;
+            if (j < tile_n && pos < n) {   // pos < n: always, when the histogram scan is consistent
+                kout[pos] = key[it];
+                if (HAS_VAL) vout[pos] = sval[j];
+            }
         }
     }
 }
@@ -499,9 +567,42 @@ RadixDigit radix_first_digit(int bit_lo, int bit_hi) {
 
 uint32_t* radix_first_counts(void* temp) { return (uint32_t*)temp; }
 
+// The ranking of a pass: lane masks for 32-bit keys (twice the keys per byte
+// moved, so the 8-ballot match costs twice as much per byte there); for
+// 64-bit keys the match when stable, the LDS adds when not.
+template <typename KeyT>
+constexpr int rank_for(bool stable) {
+    return sizeof(KeyT) == 4 ? RANK_MASK : (stable ? RANK_MATCH : RANK_ATOMIC);
+}
+
+template <typename KeyT, int RS_ITEMS, int RANK>
+static void scatter_launch(const KeyT* kin, const uint32_t* vin, KeyT* kout, uint32_t* vout, const uint32_t* d_count,
+                           size_t cap, int shift, uint32_t dmask, const uint32_t* hist, uint32_t ntiles,
+                           const uint32_t* digit_tot, hipStream_t s) {
+    if (RS_ITEMS == RS_ITEMS_HUGE) {   // 8192-key tiles: 512 threads of 16 keys
+        if (vin)
+            hipLaunchKernelGGL((k_radix_scatter<KeyT, true, RS_ITEMS / 2, 2 * RS_NT, XfIdentity, RANK>), dim3(ntiles),
+                               dim3(2 * RS_NT), 0, s, kin, vin, kout, vout, d_count, (uint32_t)cap, shift, dmask,
+                               hist, ntiles, digit_tot, XfIdentity());
+        else
+            hipLaunchKernelGGL((k_radix_scatter<KeyT, false, RS_ITEMS / 2, 2 * RS_NT, XfIdentity, RANK>),
+                               dim3(ntiles), dim3(2 * RS_NT), 0, s, kin, nullptr, kout, nullptr, d_count,
+                               (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot, XfIdentity());
+    } else if (vin) {
+        hipLaunchKernelGGL((k_radix_scatter<KeyT, true, RS_ITEMS, RS_NT, XfIdentity, RANK>), dim3(ntiles), dim3(RS_NT),
+                           0, s, kin, vin, kout, vout, d_count, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot,
+                           XfIdentity());
+    } else {
+        hipLaunchKernelGGL((k_radix_scatter<KeyT, false, RS_ITEMS, RS_NT, XfIdentity, RANK>), dim3(ntiles),
+                           dim3(RS_NT), 0, s, kin, nullptr, kout, nullptr, d_count, (uint32_t)cap, shift, dmask, hist,
+                           ntiles, digit_tot, XfIdentity());
+    }
+}
+
 template <typename KeyT, int RS_ITEMS>
 static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                      size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted) {
+                      size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted,
+                      bool first_unstable) {
     const int width = digit_width(bit_hi - bit_lo);
     const uint32_t ntiles = (uint32_t)rs_ntiles(cap, RS_NT * RS_ITEMS);
     uint32_t* hist = (uint32_t*)temp;
@@ -523,22 +624,12 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
         hipLaunchKernelGGL(k_radix_rowscan, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, digit_tot, seg_tot);
         if (nseg > 1)
             hipLaunchKernelGGL(k_radix_rowfix, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, seg_tot, digit_tot);
-        if (RS_ITEMS == RS_ITEMS_HUGE) {   // 8192-key tiles: 512 threads of 16 keys
-            if (vals)
-                hipLaunchKernelGGL((k_radix_scatter<KeyT, true, RS_ITEMS / 2, 2 * RS_NT>), dim3(ntiles),
-                                   dim3(2 * RS_NT), 0, s, kin, vin, kout, vout, d_count, (uint32_t)cap, shift, dmask,
-                                   hist, ntiles, digit_tot);
-            else
-                hipLaunchKernelGGL((k_radix_scatter<KeyT, false, RS_ITEMS / 2, 2 * RS_NT>), dim3(ntiles),
-                                   dim3(2 * RS_NT), 0, s, kin, nullptr, kout, nullptr, d_count, (uint32_t)cap, shift,
-                                   dmask, hist, ntiles, digit_tot);
-        } else if (vals) {
-            hipLaunchKernelGGL((k_radix_scatter<KeyT, true, RS_ITEMS>), dim3(ntiles), dim3(RS_NT), 0, s, kin, vin, kout, vout,
-                               d_count, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot);
-        } else {
-            hipLaunchKernelGGL((k_radix_scatter<KeyT, false, RS_ITEMS>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr, kout,
-                               nullptr, d_count, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot);
-        }
+        if (first_unstable && passes == 0)
+            scatter_launch<KeyT, RS_ITEMS, rank_for<KeyT>(false)>(kin, vals ? vin : nullptr, kout, vout, d_count, cap,
+                                                                  shift, dmask, hist, ntiles, digit_tot, s);
+        else
+            scatter_launch<KeyT, RS_ITEMS, rank_for<KeyT>(true)>(kin, vals ? vin : nullptr, kout, vout, d_count, cap,
+                                                                 shift, dmask, hist, ntiles, digit_tot, s);
         KeyT* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
     }
@@ -547,22 +638,23 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
 
 template <typename KeyT>
 static int radix_sort_any(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                          size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted) {
+                          size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted,
+                          bool first_unstable) {
     if (cap == 0 || bit_hi <= bit_lo) return 0;
     const uint32_t tile = radix_tile_keys(cap, (int)sizeof(KeyT));
     if (tile == RS_NT * RS_ITEMS_HUGE)
         return radix_sort<KeyT, RS_ITEMS_HUGE>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                               first_counted);
+                                               first_counted, first_unstable);
     if (tile == RS_NT * RS_ITEMS_LARGE)
         return radix_sort<KeyT, RS_ITEMS_LARGE>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                                first_counted);
+                                                first_counted, first_unstable);
     return radix_sort<KeyT, RS_ITEMS_SMALL>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                            first_counted);
+                                            first_counted, first_unstable);
 }
 
 template <int RS_ITEMS, typename XF>
 static void radix_pass_xf(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, XF xf,
-                          bool hist_xf, uint32_t* counted, void* temp, hipStream_t s) {
+                          bool hist_xf, uint32_t* counted, bool stable, void* temp, hipStream_t s) {
     const uint32_t ntiles = (uint32_t)rs_ntiles(cap, RS_NT * RS_ITEMS);
     uint32_t* hist = counted ? counted : (uint32_t*)temp;
     void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * (ntiles + 1), 256);
@@ -584,46 +676,54 @@ static void radix_pass_xf(const uint64_t* kin, uint64_t* kout, size_t cap, int s
     constexpr bool HUGE_TILES = RS_ITEMS == RS_ITEMS_HUGE;   // 8192-key tiles: 512 threads of 16 keys
     constexpr int IT = HUGE_TILES ? RS_ITEMS / 2 : RS_ITEMS;
     constexpr int NTS = HUGE_TILES ? 2 * RS_NT : RS_NT;
-    hipLaunchKernelGGL((k_radix_scatter<uint64_t, false, IT, NTS, XF>), dim3(ntiles), dim3(NTS), 0, s, kin, nullptr,
-                       kout, nullptr, nullptr, (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot, xf);
+    if (stable)
+        hipLaunchKernelGGL((k_radix_scatter<uint64_t, false, IT, NTS, XF, rank_for<uint64_t>(true)>), dim3(ntiles),
+                           dim3(NTS), 0, s, kin, nullptr, kout, nullptr, nullptr, (uint32_t)cap, shift, dmask, hist,
+                           ntiles, digit_tot, xf);
+    else
+        hipLaunchKernelGGL((k_radix_scatter<uint64_t, false, IT, NTS, XF, rank_for<uint64_t>(false)>), dim3(ntiles),
+                           dim3(NTS), 0, s, kin, nullptr, kout, nullptr, nullptr, (uint32_t)cap, shift, dmask, hist,
+                           ntiles, digit_tot, xf);
 }
 
 template <int RS_ITEMS>
 static void radix_pass_kind(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& x,
-                            uint32_t* counted, void* temp, hipStream_t s) {
+                            uint32_t* counted, bool stable, void* temp, hipStream_t s) {
     if (x.kind == RX_RANK_LOW)   // the digit lies in the untouched high half
-        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfRankLow{x.rank, x.n}, false, counted, temp, s);
+        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfRankLow{x.rank, x.n}, false, counted, stable, temp, s);
     else if (x.kind == RX_ORIENT)
         radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfOrient{x.rank, x.n, x.nb, x.sentinel}, true, counted,
-                                temp, s);
+                                stable, temp, s);
     else
-        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfIdentity(), false, counted, temp, s);
+        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfIdentity(), false, counted, stable, temp, s);
 }
 
 void radix_pass_u64(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& xf,
-                    void* temp, hipStream_t s, uint32_t* counted) {
+                    void* temp, hipStream_t s, uint32_t* counted, bool stable) {
     if (cap == 0 || bits <= 0) return;
     const uint32_t tile = radix_tile_keys(cap, 8);
     if (tile == RS_NT * RS_ITEMS_HUGE)
-        radix_pass_kind<RS_ITEMS_HUGE>(kin, kout, cap, shift, bits, xf, counted, temp, s);
+        radix_pass_kind<RS_ITEMS_HUGE>(kin, kout, cap, shift, bits, xf, counted, stable, temp, s);
     else if (tile == RS_NT * RS_ITEMS_LARGE)
-        radix_pass_kind<RS_ITEMS_LARGE>(kin, kout, cap, shift, bits, xf, counted, temp, s);
+        radix_pass_kind<RS_ITEMS_LARGE>(kin, kout, cap, shift, bits, xf, counted, stable, temp, s);
     else
-        radix_pass_kind<RS_ITEMS_SMALL>(kin, kout, cap, shift, bits, xf, counted, temp, s);
+        radix_pass_kind<RS_ITEMS_SMALL>(kin, kout, cap, shift, bits, xf, counted, stable, temp, s);
 }
 
 int radix_digit_width(int bits) { return digit_width(bits); }
 
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted) {
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted,
+                   bool first_unstable) {
     return radix_sort_any<uint64_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                    first_counted);
+                                    first_counted, first_unstable);
 }
 
 int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
-                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted) {
+                   size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted,
+                   bool first_unstable) {
     return radix_sort_any<uint32_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                    first_counted);
+                                    first_counted, first_unstable);
 }
 
 }  // namespace tcx

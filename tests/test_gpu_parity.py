@@ -307,6 +307,44 @@ def test_radix_sort_is_stable_and_exact(tc, count, bits):
     np.testing.assert_array_equal(d.cpu().numpy(), ref)
 
 
+@pytest.mark.parametrize("count,shift,bits,dist",
+                         [(c, sh, b, "mixed") for c in (1, 2047, 2049, 100003) for sh, b in ((0, 8), (7, 6), (56, 8), (3, 1))]
+                         + [(100003, 32, 8, "equal"), (4097, 0, 8, "equal"), (100003, 40, 8, "skewed"),
+                            # 4096-key tiles (from 2^22 keys) and 8192-key tiles (from 2^26), ragged last tiles
+                            ((1 << 22) + 4097, 24, 8, "mixed"), ((1 << 26) + 8192 * 3 + 77, 0, 8, "mixed"),
+                            ((1 << 26) + 8192 * 3 + 77, 40, 8, "skewed")])
+def test_radix_partition_groups_by_digit(tc, count, shift, bits, dist):
+    """tc_radix_partition_u64 (the builder's partitioning pass, ranks by LDS atomics): the output is a
+    permutation of the input whose digits never decrease, so every key lies in its digit's group,
+    the groups in ascending order; what is unique (the digit sequence and the multiset) is
+    compared with a sort on the CPU, the order inside a group is not."""
+    import torch
+    rng = np.random.default_rng(count + 31 * shift + bits)
+    keys = rng.integers(0, 2**63, count, dtype=np.int64) * 2 + rng.integers(0, 2, count)
+    if dist == "mixed":
+        keys[: count // 3] &= 0xFFFF   # a third with high digits zero
+    elif dist == "equal":
+        keys[:] = keys[0]              # every lane of every wave on one counter
+    elif dist == "skewed":             # nine in ten keys on one digit, the rest spread
+        keys[rng.random(count) < 0.9] &= ~np.int64(((1 << bits) - 1) << shift)
+    out = tc.radix_partition_u64(torch.from_numpy(keys.copy()).to("cuda:0"), shift, bits).cpu().numpy()
+    u, o = keys.view(np.uint64), out.view(np.uint64)
+    mask = np.uint64((1 << bits) - 1)
+    np.testing.assert_array_equal(np.sort((o >> np.uint64(shift)) & mask), (o >> np.uint64(shift)) & mask)
+    np.testing.assert_array_equal(np.sort((u >> np.uint64(shift)) & mask), (o >> np.uint64(shift)) & mask)
+    np.testing.assert_array_equal(np.sort(o), np.sort(u))
+
+
+def test_radix_partition_rejects_bad_arguments(tc):
+    import torch
+    k = torch.zeros(16, dtype=torch.int64, device="cuda:0")
+    for shift, bits in ((0, 0), (0, 9), (60, 8), (-1, 4)):
+        with pytest.raises(tc.TCError) as ei:
+            tc.radix_partition_u64(k, shift, bits)
+        assert ei.value.status == 1   # TC_ERR_INVALID_ARG
+    assert tc.radix_partition_u64(k[:0], 0, 8).numel() == 0
+
+
 def _run_lengths(kind, rng):
     if kind == "singletons":
         return [1] * 5000
