@@ -276,7 +276,10 @@ tc_status tc_build_csr(tc_ctx* ctx, const int32_t* d_edges, int64_t num_edges, i
  * reuse: stable ascending sort of `count` uint64 keys on bits [bit_lo,
  * bit_hi), 8 bits per pass. d_keys holds the input and receives the result;
  * d_keys_alt is caller scratch of the same size. Workspace: at least
- * tc_radix_sort_workspace_size(count) bytes.
+ * tc_radix_sort_workspace_size(count) bytes. From 2^26 keys, sorts of two to
+ * four passes take the passes after the first in one kernel each, whose tiles
+ * wait (boundedly) for the tiles before them; TC_ERR_HIP if such a wait ever
+ * runs out (an internal bound, not a property of the keys).
  */
 size_t tc_radix_sort_workspace_size(int64_t count);
 tc_status tc_radix_sort_u64(tc_ctx* ctx, uint64_t* d_keys, uint64_t* d_keys_alt, int64_t count, int32_t bit_lo,

@@ -494,13 +494,21 @@ tc_status tc_radix_sort_u64(tc_ctx* ctx, uint64_t* d_keys, uint64_t* d_keys_alt,
     if (workspace_bytes < tcx::radix_temp_bytes((size_t)count))
         return arg_fail(ctx, TC_ERR_WORKSPACE, "workspace too small");
     DeviceGuard guard(ctx->device);
+    uint32_t* d_err = tcx::radix_err_word(d_workspace, (size_t)count);
+    tcx::fill_u32(d_err, 0u, 1, ctx->stream);
     const int alt = tcx::radix_sort_u64(d_keys, d_keys_alt, nullptr, nullptr, nullptr, (size_t)count, bit_lo, bit_hi,
-                                        d_workspace, ctx->stream);
+                                        d_workspace, ctx->stream, false, false, d_err);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess && alt)
         e = hipMemcpyAsync(d_keys, d_keys_alt, sizeof(uint64_t) * (size_t)count, hipMemcpyDeviceToDevice, ctx->stream);
+    uint32_t h_err = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h_err, d_err, sizeof(h_err), hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "radix sort");
+    if (h_err) {   // a look-back wait ran out (an internal bound; never in a correct run)
+        ctx->last_error = "radix sort: a look-back wait ran out";
+        return TC_ERR_HIP;
+    }
     return TC_OK;
 }
 

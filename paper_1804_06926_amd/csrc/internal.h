@@ -9,6 +9,7 @@ namespace tcx {
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+
 // ---- prims.hip
 void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 void fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
@@ -25,13 +26,21 @@ size_t radix_temp_bytes(size_t cap);
 // only partitions (ranks by LDS atomics): the keys come out sorted on
 // [bit_lo, bit_hi), but keys equal on those bits in no particular order, so
 // use it where that order is free (the whole key sorted, or a grouping).
+// Sorts of 2^26 keys or more without payload take their passes after the first
+// in one kernel each (decoupled look-back, no histogram pass); a wait there
+// that runs out sets bit 1 of *err (nullptr: radix_err_word(temp, cap)).
 // Returns 1 when the sorted data ended up in the *_alt buffers.
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted = false,
-                   bool first_unstable = false);
+                   bool first_unstable = false, uint32_t* err = nullptr);
 int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted = false,
-                   bool first_unstable = false);
+                   bool first_unstable = false, uint32_t* err = nullptr);
+// The word in a sort's temporary (cap keys) where its look-back passes report
+// a wait that ran out (bit 1).
+uint32_t* radix_err_word(void* temp, size_t cap);
+
+
 // Keys per tile of a sort of cap keys of key_bytes bytes (2048, 4096 or 8192;
 // a multiple of 2048).
 uint32_t radix_tile_keys(size_t cap, int key_bytes);

@@ -1147,7 +1147,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
             int a0 = 0;
             if (vbits > bw)
                 a0 = radix_sort_u32(ep, ep_alt, nullptr, nullptr, nullptr, (size_t)(2 * E), bw, vbits, radix_tmp, s,
-                                    true, true);   // a grouping: the order inside a bucket is free
+                                    true, true, &ctrl->err);   // a grouping: the order inside a bucket is free
             uint32_t* bst = (uint32_t*)(ws + L.bstart);
             hipLaunchKernelGGL(k_bucket_starts, dim3(grid_for((size_t)nb + 1)), dim3(NT), 0, s, a0 ? ep_alt : ep,
                                (uint32_t)(2 * E), bw, nb, bst);
@@ -1158,7 +1158,8 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
             hipLaunchKernelGGL(k_drop_sentinels, dim3(1), dim3(NT), 0, s, partial, eg, n, deg);
         } else {
             const int a0 = radix_sort_u32(ep, ep_alt, nullptr, nullptr, nullptr, (size_t)(2 * E), 0,
-                                          bits_for((uint64_t)n + 1), radix_tmp, s, true, true);   // whole keys
+                                          bits_for((uint64_t)n + 1), radix_tmp, s, true, true,
+                                          &ctrl->err);   // whole keys
             fill_u32(rowend, 0u, (size_t)n, s);
             hipLaunchKernelGGL(k_endpoint_bounds, dim3(grid_for((size_t)(2 * E))), dim3(NT), 0, s, a0 ? ep_alt : ep,
                                (uint64_t)(2 * E), n, rowend);
@@ -1175,7 +1176,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     {
         const int dbits = bits_for((uint64_t)2 * (uint64_t)E + 1);
         const int alt = radix_sort_u64(vkeysA, vkeysB, nullptr, nullptr, nullptr, (size_t)n, 32, 32 + dbits,
-                                       radix_tmp, s);
+                                       radix_tmp, s, false, false, &ctrl->err);
         hipLaunchKernelGGL(k_rank, dim3(grid_for((size_t)n)), dim3(NT), 0, s, alt ? vkeysB : vkeysA, n, rank, inv);
     }
     mark(2);
@@ -1212,10 +1213,11 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         const int w0 = radix_digit_width(nb);
         radix_pass_u64(keysA, keysB, (size_t)E, nb, w0, RadixXf{RX_ORIENT, rank, n, nb, sentinel}, radix_tmp, s,
                        nullptr, false);
-        alt = 1 - radix_sort_u64(keysB, keysA, nullptr, nullptr, nullptr, (size_t)E, nb + w0, 2 * nb, radix_tmp, s);
+        alt = 1 - radix_sort_u64(keysB, keysA, nullptr, nullptr, nullptr, (size_t)E, nb + w0, 2 * nb, radix_tmp, s,
+                                 false, false, &ctrl->err);
     } else {
         alt = radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)E, nb, 2 * nb, radix_tmp, s, true,
-                             true);
+                             true, &ctrl->err);
     }
     uint64_t* sorted = alt ? keysB : keysA;
     uint64_t* other = alt ? keysA : keysB;
@@ -1254,7 +1256,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
                            ctrl, n, other, pk.sh, pk.lbits, radix_first_counts(radix_tmp), e_tiles, e_tile,
                            radix_first_digit(pk.sh, pk.sh + nbv));
         const int alt2 = radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, pk.sh, pk.sh + nbv,
-                                        radix_tmp, s, true, true);
+                                        radix_tmp, s, true, true, &ctrl->err);
         // bounds and tail ranges in one pass, into the buffer the sort left free
         const uint64_t* ckeys = alt2 ? sorted : other;
         csc = alt2 ? other : sorted;
@@ -1268,7 +1270,8 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         const int sh = bits_for((uint64_t)E) > 0 ? bits_for((uint64_t)E) : 1;
         hipLaunchKernelGGL(k_sym_keys, dim3(grid_for((size_t)E)), dim3(NT), 0, s, col, ctrl, other, sh);
         const int alt2 =
-            radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, sh, sh + nbv, radix_tmp, s);
+            radix_sort_u64(other, sorted, nullptr, nullptr, &ctrl->m, (size_t)E, sh, sh + nbv, radix_tmp, s, false,
+                           false, &ctrl->err);
         csc = alt2 ? sorted : other;
         fill_u32(rowend, 0u, (size_t)n, s);
         hipLaunchKernelGGL(k_sym_bounds, dim3(grid_for((size_t)E)), dim3(NT), 0, s, csc, ctrl, rowend, sh);
@@ -1299,7 +1302,8 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     // ---- group: order vertices by (kernel, bucket); tiles
     hipLaunchKernelGGL(k_vkeys_slot, dim3(grid_for((size_t)n)), dim3(NT), 0, s, vbucket, n, ctrl, vkeysA);
     {
-        const int a3 = radix_sort_u64(vkeysA, vkeysB, nullptr, nullptr, nullptr, (size_t)n, 32, 40, radix_tmp, s);
+        const int a3 = radix_sort_u64(vkeysA, vkeysB, nullptr, nullptr, nullptr, (size_t)n, 32, 40, radix_tmp, s,
+                                      false, false, &ctrl->err);
         hipLaunchKernelGGL(k_vpos, dim3(grid_for((size_t)n)), dim3(NT), 0, s, a3 ? vkeysB : vkeysA, n, vbucket, ctrl,
                            vlist);
     }

@@ -266,6 +266,29 @@ struct XfOrient {
     }
 };
 
+// Global digit counts for the later passes of a sort that look back (no
+// histogram pass of their own): the first pass, which reads every key anyway,
+// adds for digit q (bits [shift + q * bits, min(that + bits, hi)),
+// q < n <= LB_MAX_MORE) the count of each value into tot[q * 256 + d].
+constexpr int LB_MAX_MORE = 3;
+struct MoreTot {
+    uint32_t* tot;
+    int n, shift, bits, hi;
+};
+__device__ __forceinline__ void more_add(uint32_t (*mcnt)[256], const MoreTot& more, uint64_t key) {
+    for (int q = 0; q < more.n; ++q) {
+        const int sh = more.shift + q * more.bits;
+        const int wb = more.hi - sh < more.bits ? more.hi - sh : more.bits;
+        atomicAdd(&mcnt[q][(uint32_t)(key >> sh) & ((1u << wb) - 1u)], 1u);
+    }
+}
+__device__ __forceinline__ void more_flush(uint32_t (*mcnt)[256], const MoreTot& more) {
+    for (int i = threadIdx.x; i < more.n * 256; i += blockDim.x) {
+        const uint32_t c = (&mcnt[0][0])[i];
+        if (c) atomicAdd(&more.tot[i], c);
+    }
+}
+
 // Per-tile digit counts, written digit-major: hist[d * ntiles + tile]; digits of
 // the keys as xf transforms them.
 template <typename KeyT, int RS_ITEMS, typename XF = XfIdentity>
@@ -293,27 +316,24 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ k
         const uint32_t dd = (uint32_t)(xf(kk[it]) >> shift) & dmask;
         dg[it] = i < n ? dd : 0u;
     }
-    // counts only (no ranks): one LDS atomic per key into the wave's histogram.
-    // Lanes that share a digit with the wave's first or second leading lane are
-    // added once by that lane, instead of serialising up to 64 atomics on one
-    // counter: 64-bit keys here hold degree ranks, whose top digit is dominated by
-    // the hubs' in-edges, and a 32-bit histogram runs only for the second
-    // partition pass of wide vertex ids (the degree stage past 24 bits), whose
-    // keys the first pass has grouped by their top bits, so neighbouring lanes
-    // often share the next digit too.
+    // counts only (no ranks): one LDS add per key into the wave's histogram, none
+    // waited on. A wave whose valid keys all share one digit (sorted stretches:
+    // 64-bit keys here hold degree ranks, whose top digit the hubs' in-edges
+    // dominate, and a 32-bit histogram runs for the second partition pass of
+    // wide vertex ids, whose keys the first pass grouped by their top bits)
+    // adds its count once from lane 0 instead of 64 adds on one counter. The
+    // test is uniform (valid lanes are a prefix of the wave), so it costs a few
+    // scalar operations per key, not a leader search.
 #pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
-        uint64_t act = __ballot(base + it * WAVE + l < n);
-#pragma unroll
-        for (int pk = 0; pk < 2; ++pk) {
-            if (!act) break;
-            const int lead = __builtin_ctzll(act);
-            const uint32_t dl = (uint32_t)__builtin_amdgcn_readlane((int)dg[it], lead);
-            const uint64_t m = __ballot(dg[it] == dl) & act;
-            if (l == lead) atomicAdd(&wcnt[w][dl], (uint32_t)__popcll(m));
-            act &= ~m;
+        const uint64_t act = __ballot(base + it * WAVE + l < n);
+        const uint32_t d0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)dg[it]);
+        const uint64_t same = __ballot(dg[it] == d0) & act;
+        if (same == act) {
+            if (l == 0 && act) atomicAdd(&wcnt[w][d0], (uint32_t)__popcll(act));
+        } else if ((act >> l) & 1u) {
+            atomicAdd(&wcnt[w][dg[it]], 1u);
         }
-        if ((act >> l) & 1u) atomicAdd(&wcnt[w][dg[it]], 1u);
     }
     __syncthreads();
     const int d = threadIdx.x;
@@ -395,14 +415,16 @@ __global__ __launch_bounds__(RS_NT) void k_radix_rowfix(uint32_t* __restrict__ h
 // The masks use the key tile's LDS, free until the ranks are known.
 enum { RANK_MATCH = 0, RANK_MASK = 1, RANK_ATOMIC = 2 };
 
-template <typename KeyT, bool HAS_VAL, int RS_ITEMS, int NT_ = RS_NT, typename XF = XfIdentity, int RANK = RANK_MATCH>
+template <typename KeyT, bool HAS_VAL, int RS_ITEMS, int NT_ = RS_NT, typename XF = XfIdentity, int RANK = RANK_MATCH,
+          bool TOT = false>
 __global__ __launch_bounds__(NT_) void k_radix_scatter(const KeyT* __restrict__ kin,
                                                          const uint32_t* __restrict__ vin,
                                                          KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
                                                          const uint32_t* d_count, uint32_t cap, int shift,
                                                          uint32_t dmask,
                                                          const uint32_t* __restrict__ hist_scan, uint32_t ntiles,
-                                                         const uint32_t* __restrict__ digit_tot, XF xf) {
+                                                         const uint32_t* __restrict__ digit_tot, XF xf,
+                                                         MoreTot more = MoreTot{nullptr, 0, 0, 0, 0}) {
     constexpr int NW = NT_ / WAVE;
     constexpr int RS_TILE = NT_ * RS_ITEMS, RS_WAVE_SPAN = WAVE * RS_ITEMS;
     static_assert(NT_ >= 256, "a thread per digit");
@@ -415,10 +437,13 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter(const KeyT* __restrict__ 
     __shared__ uint64_t mask_own[RANK == RANK_MASK && !MASK_IN_TILE ? NW : 1][RANK == RANK_MASK ? 256 : 1];
     uint64_t (*wmask)[256] = MASK_IN_TILE ? reinterpret_cast<uint64_t (*)[256]>(skey)
                                           : reinterpret_cast<uint64_t (*)[256]>(mask_own);
+    __shared__ uint32_t mcnt[TOT ? LB_MAX_MORE : 1][256];   // TOT: the later digits' counts
     for (int i = threadIdx.x; i < NW * 256; i += NT_) {
         (&wcnt[0][0])[i] = 0;
         if (RANK == RANK_MASK) (&wmask[0][0])[i] = 0ull;
     }
+    if (TOT)
+        for (int i = threadIdx.x; i < more.n * 256; i += NT_) (&mcnt[0][0])[i] = 0;
     __syncthreads();
     const uint32_t n = rs_count(d_count, cap);
     const int w = wave_id(), l = lane_id();
@@ -536,6 +561,160 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter(const KeyT* __restrict__ 
                 if (HAS_VAL) vout[pos] = sval[j];
             }
         }
+        if (TOT) {
+#pragma unroll
+            for (int it = 0; it < RS_ITEMS; ++it)
+                if (it * NT_ + threadIdx.x < tile_n) more_add(mcnt, more, (uint64_t)key[it]);
+        }
+    }
+    if (TOT) {
+        __syncthreads();
+        more_flush(mcnt, more);
+    }
+}
+
+// A later pass of a large sort in one kernel: the per-tile digit offsets come
+// from the tiles before it (decoupled look-back) instead of a count table
+// built by a histogram pass. Tiles are taken in order from a counter, so a
+// tile only ever waits for tiles that a running block holds. Each tile
+// publishes, per digit, its count (flag 1) as soon as it has ranked its keys,
+// then walks back over the tiles before it, adding counts until it meets a
+// running total (flag 2), and publishes its own running total. status holds one
+// 64-bit word per (tile, digit), zeroed before the pass: flag in bits 63..62,
+// value in bits 31..0. digit_tot: the pass's global digit counts. The waits
+// are bounded: a wait that runs past LB_SPIN polls sets bit 1 of *err and the
+// keys go out clamped in place (wrong order, no access out of bounds).
+constexpr uint32_t LB_SPIN = 1u << 16;
+template <typename KeyT, int RS_ITEMS, int NT_, int RANK>
+__global__ __launch_bounds__(NT_) void k_radix_scatter_lb(const KeyT* __restrict__ kin, KeyT* __restrict__ kout,
+                                                            const uint32_t* d_count, uint32_t cap, int shift,
+                                                            uint32_t dmask, const uint32_t* __restrict__ digit_tot,
+                                                            uint64_t* status, uint32_t* tile_ctr, uint32_t* err) {
+    constexpr int NW = NT_ / WAVE;
+    constexpr int RS_TILE = NT_ * RS_ITEMS, RS_WAVE_SPAN = WAVE * RS_ITEMS;
+    static_assert(NT_ >= 256, "a thread per digit");
+    __shared__ uint32_t wcnt[NW][256];
+    __shared__ uint32_t gofs[256];
+    __shared__ uint32_t scratch[NW];
+    __shared__ uint32_t s_tile;
+    __shared__ __align__(16) KeyT skey[RS_TILE];
+    constexpr bool MASK_IN_TILE = sizeof(KeyT) * RS_TILE >= sizeof(uint64_t) * 256 * NW;
+    __shared__ uint64_t mask_own[RANK == RANK_MASK && !MASK_IN_TILE ? NW : 1][RANK == RANK_MASK ? 256 : 1];
+    uint64_t (*wmask)[256] = MASK_IN_TILE ? reinterpret_cast<uint64_t (*)[256]>(skey)
+                                          : reinterpret_cast<uint64_t (*)[256]>(mask_own);
+    const uint32_t n = rs_count(d_count, cap);
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    for (int i = threadIdx.x; i < NW * 256; i += NT_) {
+        (&wcnt[0][0])[i] = 0;
+        if (RANK == RANK_MASK) (&wmask[0][0])[i] = 0ull;
+    }
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t tile0 = tile * RS_TILE;
+    if (tile0 >= n) return;   // empty: every tile after it is empty too, and none waits on it
+    const int w = wave_id(), l = lane_id();
+    const uint32_t base = tile0 + w * RS_WAVE_SPAN;
+    KeyT k[RS_ITEMS];
+    uint32_t loc[RS_ITEMS];
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint32_t i = base + it * WAVE + l;
+        k[it] = i < n ? kin[i] : KeyT(0);
+    }
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint32_t i = base + it * WAVE + l;
+        const bool valid = i < n;
+        const uint32_t d = (uint32_t)(k[it] >> shift) & dmask;
+        uint64_t peers;
+        if (RANK == RANK_MATCH) {
+            peers = match_digit8(d, __ballot(valid));
+        } else {
+            if (valid) atomicOr((unsigned long long*)&wmask[w][d], 1ull << l);
+            __builtin_amdgcn_wave_barrier();
+            peers = valid ? wmask[w][d] : 0ull;
+            __builtin_amdgcn_wave_barrier();
+        }
+        const uint32_t r = (uint32_t)__popcll(peers & lanes_below());
+        const uint32_t prev = wcnt[w][d];
+        __builtin_amdgcn_wave_barrier();
+        if (valid && r == 0) {
+            wcnt[w][d] = prev + (uint32_t)__popcll(peers);
+            if (RANK == RANK_MASK) wmask[w][d] = 0ull;
+        }
+        __builtin_amdgcn_wave_barrier();
+        loc[it] = d | ((prev + r) << 8);
+    }
+    __syncthreads();
+    {
+        const bool own = threadIdx.x < 256;
+        const int d = own ? (int)threadIdx.x : 0;
+        uint32_t run = 0;
+        if (own) {
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                const uint32_t c = wcnt[q][d];
+                wcnt[q][d] = run;
+                run += c;
+            }
+        }
+        uint64_t* st = status + (size_t)tile * 256 + d;
+        if (own)   // this tile's count, for the tiles after it
+            __hip_atomic_store(st, (tile == 0 ? (2ull << 62) : (1ull << 62)) | run, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t before = 0;   // keys of digit d in the tiles before this one
+        if (own && tile > 0) {
+            uint32_t j = tile - 1, spins = 0;
+            for (;;) {
+                const uint64_t v = __hip_atomic_load(status + (size_t)j * 256 + d, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t f = (uint32_t)(v >> 62);
+                if (f == 0) {
+                    if (++spins > LB_SPIN) {
+                        atomicOr(err, 2u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                before += (uint32_t)v;
+                if (f == 2 || j == 0) break;
+                --j;
+            }
+            __hip_atomic_store(st, (2ull << 62) | (before + run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const uint32_t excl = block_exclusive_scan<NT_>(run, scratch);
+        const uint32_t dbase = block_exclusive_scan<NT_>(own ? digit_tot[d] : 0u, scratch);
+        if (own) {
+#pragma unroll
+            for (int q = 0; q < NW; ++q) wcnt[q][d] += excl;
+            gofs[d] = dbase + before - excl;
+        }
+    }
+    __syncthreads();
+    {
+        uint32_t pb[RS_ITEMS];
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it) pb[it] = wcnt[w][loc[it] & 255u];
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it)
+            if (base + it * WAVE + l < n) skey[pb[it] + (loc[it] >> 8)] = k[it];
+    }
+    __syncthreads();
+    const uint32_t tile_n = n - tile0 < (uint32_t)RS_TILE ? n - tile0 : (uint32_t)RS_TILE;
+    {
+        KeyT key[RS_ITEMS];
+        uint32_t go[RS_ITEMS];
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it) key[it] = skey[it * NT_ + threadIdx.x];
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it) go[it] = gofs[(uint32_t)(key[it] >> shift) & dmask];
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it) {
+            const uint32_t j = it * NT_ + threadIdx.x;
+            const uint32_t pos = go[it] + j;
+            if (j < tile_n) kout[pos < n ? pos : n - 1] = key[it];
+        }
     }
 }
 
@@ -545,11 +724,22 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter(const KeyT* __restrict__ 
 static size_t rs_ntiles(size_t cap, uint32_t tile) { return (cap + tile - 1) / tile; }
 static size_t rs_nseg(size_t ntiles) { return (ntiles + RS_ROW_SEG - 1) / RS_ROW_SEG; }
 
-size_t radix_temp_bytes(size_t cap) {
+// Look-back region (end of the temporary): per pass p of a sort, its digit
+// totals [LB_PASSES][256] and its tile counter [LB_PASSES]; an error word.
+constexpr int LB_PASSES = LB_MAX_MORE + 1;
+constexpr size_t LB_WORDS = LB_PASSES * 256 + LB_PASSES + 1;
+static size_t rs_lb_offset(size_t cap) {
     const size_t ntiles = rs_ntiles(cap, RS_NT * RS_ITEMS_SMALL);
     return align_up(sizeof(uint32_t) * 256 * (ntiles + 1), 256) + align_up(scan_temp_bytes(), 256) +
            align_up(sizeof(uint32_t) * 256 * (rs_nseg(ntiles) + 1), 256);
 }
+
+size_t radix_temp_bytes(size_t cap) { return rs_lb_offset(cap) + align_up(sizeof(uint32_t) * LB_WORDS, 256); }
+
+uint32_t* radix_err_word(void* temp, size_t cap) {
+    return (uint32_t*)((char*)temp + rs_lb_offset(cap)) + LB_PASSES * 256 + LB_PASSES;
+}
+
 
 // Digit width of a sort over `bits` bits: the passes an 8-bit digit needs,
 // with the bits spread evenly over them (a narrow last digit would crowd all
@@ -602,8 +792,18 @@ static void scatter_launch(const KeyT* kin, const uint32_t* vin, KeyT* kout, uin
 template <typename KeyT, int RS_ITEMS>
 static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                       size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted,
-                      bool first_unstable) {
+                      bool first_unstable, uint32_t* err) {
     const int width = digit_width(bit_hi - bit_lo);
+    const int npasses = (bit_hi - bit_lo + width - 1) / width;
+    // 8192-key tiles, keys only, several passes: the passes after the first look
+    // back (no histogram pass); the first pass counts their digits
+    constexpr bool HUGE_TILES = RS_ITEMS == RS_ITEMS_HUGE;
+    const bool lookback = HUGE_TILES && !vals && npasses >= 2 && npasses - 1 <= LB_MAX_MORE;
+    uint32_t* lb = (uint32_t*)((char*)temp + rs_lb_offset(cap));   // totals | tile counters | error word
+    if (lookback) {
+        fill_u32(lb, 0u, LB_PASSES * 256 + LB_PASSES, s);
+        if (!err) err = lb + LB_PASSES * 256 + LB_PASSES;
+    }
     const uint32_t ntiles = (uint32_t)rs_ntiles(cap, RS_NT * RS_ITEMS);
     uint32_t* hist = (uint32_t*)temp;
     void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * (ntiles + 1), 256);
@@ -618,13 +818,43 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
     for (int shift = bit_lo; shift < bit_hi; shift += width, ++passes) {
         const int dbits = bit_hi - shift < width ? bit_hi - shift : width;   // the last digit may be narrower
         const uint32_t dmask = (1u << dbits) - 1u;
+        if constexpr (HUGE_TILES) {
+            if (lookback && passes > 0) {
+                uint64_t* status = (uint64_t*)temp;   // the count table's room: ntiles * 256 words fit
+                fill_u64(status, 0ull, (size_t)ntiles * 256, s);
+                constexpr int IT = RS_ITEMS / 2, NTS = 2 * RS_NT;
+                hipLaunchKernelGGL((k_radix_scatter_lb<KeyT, IT, NTS, rank_for<KeyT>(true)>), dim3(ntiles), dim3(NTS),
+                                   0, s, kin, kout, d_count, (uint32_t)cap, shift, dmask, lb + passes * 256,
+                                   status, lb + LB_PASSES * 256 + passes, err);
+                KeyT* tk = kin; kin = kout; kout = tk;
+                continue;
+            }
+        }
         if (!(first_counted && passes == 0))
             hipLaunchKernelGGL((k_radix_hist<KeyT, RS_ITEMS>), dim3(ntiles), dim3(RS_NT), 0, s, kin, d_count,
                                (uint32_t)cap, shift, dmask, hist, ntiles);
         hipLaunchKernelGGL(k_radix_rowscan, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, digit_tot, seg_tot);
         if (nseg > 1)
             hipLaunchKernelGGL(k_radix_rowfix, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, seg_tot, digit_tot);
-        if (first_unstable && passes == 0)
+        bool done = false;
+        if constexpr (HUGE_TILES) {
+            if (lookback) {   // the first pass: 8192-key tiles, keys only
+                constexpr int IT = RS_ITEMS / 2, NTS = 2 * RS_NT;
+                const MoreTot more{lb + 256, npasses - 1, shift + width, width, bit_hi};
+                if (first_unstable)
+                    hipLaunchKernelGGL((k_radix_scatter<KeyT, false, IT, NTS, XfIdentity, rank_for<KeyT>(false), true>),
+                                       dim3(ntiles), dim3(NTS), 0, s, kin, nullptr, kout, nullptr, d_count,
+                                       (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot, XfIdentity(), more);
+                else
+                    hipLaunchKernelGGL((k_radix_scatter<KeyT, false, IT, NTS, XfIdentity, rank_for<KeyT>(true), true>),
+                                       dim3(ntiles), dim3(NTS), 0, s, kin, nullptr, kout, nullptr, d_count,
+                                       (uint32_t)cap, shift, dmask, hist, ntiles, digit_tot, XfIdentity(), more);
+                done = true;
+            }
+        }
+        if (done)
+            ;
+        else if (first_unstable && passes == 0)
             scatter_launch<KeyT, RS_ITEMS, rank_for<KeyT>(false)>(kin, vals ? vin : nullptr, kout, vout, d_count, cap,
                                                                   shift, dmask, hist, ntiles, digit_tot, s);
         else
@@ -639,17 +869,17 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
 template <typename KeyT>
 static int radix_sort_any(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                           size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted,
-                          bool first_unstable) {
+                          bool first_unstable, uint32_t* err) {
     if (cap == 0 || bit_hi <= bit_lo) return 0;
     const uint32_t tile = radix_tile_keys(cap, (int)sizeof(KeyT));
     if (tile == RS_NT * RS_ITEMS_HUGE)
         return radix_sort<KeyT, RS_ITEMS_HUGE>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                               first_counted, first_unstable);
+                                               first_counted, first_unstable, err);
     if (tile == RS_NT * RS_ITEMS_LARGE)
         return radix_sort<KeyT, RS_ITEMS_LARGE>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                                first_counted, first_unstable);
+                                                first_counted, first_unstable, err);
     return radix_sort<KeyT, RS_ITEMS_SMALL>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                            first_counted, first_unstable);
+                                            first_counted, first_unstable, err);
 }
 
 template <int RS_ITEMS, typename XF>
@@ -690,7 +920,8 @@ template <int RS_ITEMS>
 static void radix_pass_kind(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& x,
                             uint32_t* counted, bool stable, void* temp, hipStream_t s) {
     if (x.kind == RX_RANK_LOW)   // the digit lies in the untouched high half
-        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfRankLow{x.rank, x.n}, false, counted, stable, temp, s);
+        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfRankLow{x.rank, x.n}, false, counted, stable, temp,
+                                s);
     else if (x.kind == RX_ORIENT)
         radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfOrient{x.rank, x.n, x.nb, x.sentinel}, true, counted,
                                 stable, temp, s);
@@ -714,16 +945,16 @@ int radix_digit_width(int bits) { return digit_width(bits); }
 
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted,
-                   bool first_unstable) {
+                   bool first_unstable, uint32_t* err) {
     return radix_sort_any<uint64_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                    first_counted, first_unstable);
+                                    first_counted, first_unstable, err);
 }
 
 int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted,
-                   bool first_unstable) {
+                   bool first_unstable, uint32_t* err) {
     return radix_sort_any<uint32_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                    first_counted, first_unstable);
+                                    first_counted, first_unstable, err);
 }
 
 }  // namespace tcx

@@ -292,7 +292,11 @@ def test_csr_export_matches_definition(tc):
                          # more than 8192 tiles of 4096 keys (several digit-row segments), ragged last tile
                          + [(8 * 1024 * 4096 + 4096 * 5 + 77, (0, 64)), (8 * 1024 * 4096 + 4096 * 5 + 77, (7, 13))]
                          # 8192-key tiles of 64-bit sorts from 2^26 keys: more than 8192 of them, ragged
-                         + [((1 << 26) + 8192 * 3 + 77, (0, 64))])
+                         + [((1 << 26) + 8192 * 3 + 77, (0, 64))]
+                         # two to four passes at that size: the passes after the first look back
+                         # over the tiles before them instead of reading a count table
+                         + [((1 << 26) + 8192 * 3 + 77, (0, 32)), ((1 << 26) + 8192 * 3 + 77, (7, 29)),
+                            ((1 << 26) + 5, (40, 56))])
 def test_radix_sort_is_stable_and_exact(tc, count, bits):
     import torch
     rng = np.random.default_rng(count + bits[0])
