@@ -275,17 +275,24 @@ struct MoreTot {
     uint32_t* tot;
     int n, shift, bits, hi;
 };
-__device__ __forceinline__ void more_add(uint32_t (*mcnt)[256], const MoreTot& more, uint64_t key) {
+// The counts go to LDS counters cnt[(q * 256 + d) * copies + c], lane l adding
+// to copy c = l % copies: the later digits of rank keys are skewed (the hubs'
+// ranks), and the copies, in different banks, split the lanes of a wave that
+// share a digit over several addresses.
+__device__ __forceinline__ void more_add(uint32_t* cnt, int copies, const MoreTot& more, uint64_t key) {
+    const uint32_t c = (uint32_t)lane_id() & (uint32_t)(copies - 1);
     for (int q = 0; q < more.n; ++q) {
         const int sh = more.shift + q * more.bits;
         const int wb = more.hi - sh < more.bits ? more.hi - sh : more.bits;
-        atomicAdd(&mcnt[q][(uint32_t)(key >> sh) & ((1u << wb) - 1u)], 1u);
+        const uint32_t d = (uint32_t)(key >> sh) & ((1u << wb) - 1u);
+        atomicAdd(&cnt[(q * 256 + d) * copies + c], 1u);
     }
 }
-__device__ __forceinline__ void more_flush(uint32_t (*mcnt)[256], const MoreTot& more) {
+__device__ __forceinline__ void more_flush(const uint32_t* cnt, int copies, const MoreTot& more) {
     for (int i = threadIdx.x; i < more.n * 256; i += blockDim.x) {
-        const uint32_t c = (&mcnt[0][0])[i];
-        if (c) atomicAdd(&more.tot[i], c);
+        uint32_t t = 0;
+        for (int c = 0; c < copies; ++c) t += cnt[i * copies + c];
+        if (t) atomicAdd(&more.tot[i], t);
     }
 }
 
@@ -437,13 +444,10 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter(const KeyT* __restrict__ 
     __shared__ uint64_t mask_own[RANK == RANK_MASK && !MASK_IN_TILE ? NW : 1][RANK == RANK_MASK ? 256 : 1];
     uint64_t (*wmask)[256] = MASK_IN_TILE ? reinterpret_cast<uint64_t (*)[256]>(skey)
                                           : reinterpret_cast<uint64_t (*)[256]>(mask_own);
-    __shared__ uint32_t mcnt[TOT ? LB_MAX_MORE : 1][256];   // TOT: the later digits' counts
     for (int i = threadIdx.x; i < NW * 256; i += NT_) {
         (&wcnt[0][0])[i] = 0;
         if (RANK == RANK_MASK) (&wmask[0][0])[i] = 0ull;
     }
-    if (TOT)
-        for (int i = threadIdx.x; i < more.n * 256; i += NT_) (&mcnt[0][0])[i] = 0;
     __syncthreads();
     const uint32_t n = rs_count(d_count, cap);
     const int w = wave_id(), l = lane_id();
@@ -542,6 +546,14 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter(const KeyT* __restrict__ 
         }
     }
     __syncthreads();
+    // TOT: the later digits are counted in wcnt, free once the keys sit in LDS,
+    // in as many copies as fit
+    static_assert(!TOT || NW * 256 >= LB_MAX_MORE * 256 * 2, "two copies of the counts fit the wave counters");
+    const int copies = !TOT ? 1 : more.n <= 1 ? 8 : more.n == 2 ? 4 : 2;
+    if (TOT) {
+        for (int i = threadIdx.x; i < NW * 256; i += NT_) (&wcnt[0][0])[i] = 0;
+        __syncthreads();
+    }
     const uint32_t tile_n = n > tile0 ? (n - tile0 < (uint32_t)RS_TILE ? n - tile0 : (uint32_t)RS_TILE) : 0u;
     {
         // thread t writes tile positions t, t + NT_, ...: consecutive threads,
@@ -564,12 +576,12 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter(const KeyT* __restrict__ 
         if (TOT) {
 #pragma unroll
             for (int it = 0; it < RS_ITEMS; ++it)
-                if (it * NT_ + threadIdx.x < tile_n) more_add(mcnt, more, (uint64_t)key[it]);
+                if (it * NT_ + threadIdx.x < tile_n) more_add(&wcnt[0][0], copies, more, (uint64_t)key[it]);
         }
     }
     if (TOT) {
         __syncthreads();
-        more_flush(mcnt, more);
+        more_flush(&wcnt[0][0], copies, more);
     }
 }
 
