@@ -625,6 +625,8 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter_lb(const KeyT* __restrict
     const uint32_t tile0 = tile * RS_TILE;
     if (tile0 >= n) return;   // empty: every tile after it is empty too, and none waits on it
     const int w = wave_id(), l = lane_id();
+    const bool own = threadIdx.x < 256;
+    const int dd = own ? (int)threadIdx.x : 0;
     const uint32_t base = tile0 + w * RS_WAVE_SPAN;
     KeyT k[RS_ITEMS];
     uint32_t loc[RS_ITEMS];
@@ -633,6 +635,8 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter_lb(const KeyT* __restrict
         const uint32_t i = base + it * WAVE + l;
         k[it] = i < n ? kin[i] : KeyT(0);
     }
+    // keys with a smaller digit (the same for every tile), while the keys load
+    const uint32_t dbase = block_exclusive_scan<NT_>(own ? digit_tot[dd] : 0u, scratch);
 #pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
         const uint32_t i = base + it * WAVE + l;
@@ -658,27 +662,43 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter_lb(const KeyT* __restrict
         loc[it] = d | ((prev + r) << 8);
     }
     __syncthreads();
+    uint32_t run = 0, excl;   // thread d: the tile's keys of digit d, and of the digits below d
+    uint64_t* st = status + (size_t)tile * 256 + dd;
     {
-        const bool own = threadIdx.x < 256;
-        const int d = own ? (int)threadIdx.x : 0;
-        uint32_t run = 0;
         if (own) {
 #pragma unroll
             for (int q = 0; q < NW; ++q) {
-                const uint32_t c = wcnt[q][d];
-                wcnt[q][d] = run;
+                const uint32_t c = wcnt[q][dd];
+                wcnt[q][dd] = run;
                 run += c;
             }
-        }
-        uint64_t* st = status + (size_t)tile * 256 + d;
-        if (own)   // this tile's count, for the tiles after it
+            // this tile's count, for the tiles after it, as early as it is known
             __hip_atomic_store(st, (tile == 0 ? (2ull << 62) : (1ull << 62)) | run, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t before = 0;   // keys of digit d in the tiles before this one
-        if (own && tile > 0) {
+        }
+        excl = block_exclusive_scan<NT_>(run, scratch);
+        if (own) {
+#pragma unroll
+            for (int q = 0; q < NW; ++q) wcnt[q][dd] += excl;
+        }
+    }
+    __syncthreads();
+    {   // the keys into LDS in digit order: needs only the positions inside the tile
+        uint32_t pb[RS_ITEMS];
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it) pb[it] = wcnt[w][loc[it] & 255u];
+#pragma unroll
+        for (int it = 0; it < RS_ITEMS; ++it)
+            if (base + it * WAVE + l < n) skey[pb[it] + (loc[it] >> 8)] = k[it];
+    }
+    // then the look-back, by which time the tiles before have had the LDS pass
+    // too to publish their totals
+    if (own) {
+        uint32_t before = 0;   // keys of digit dd in the tiles before this one
+        if (tile > 0) {
             uint32_t j = tile - 1, spins = 0;
             for (;;) {
-                const uint64_t v = __hip_atomic_load(status + (size_t)j * 256 + d, __ATOMIC_RELAXED,
+                const uint64_t v = __hip_atomic_load(status + (size_t)j * 256 + dd, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t f = (uint32_t)(v >> 62);
                 if (f == 0) {
@@ -695,22 +715,7 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter_lb(const KeyT* __restrict
             }
             __hip_atomic_store(st, (2ull << 62) | (before + run), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        const uint32_t excl = block_exclusive_scan<NT_>(run, scratch);
-        const uint32_t dbase = block_exclusive_scan<NT_>(own ? digit_tot[d] : 0u, scratch);
-        if (own) {
-#pragma unroll
-            for (int q = 0; q < NW; ++q) wcnt[q][d] += excl;
-            gofs[d] = dbase + before - excl;
-        }
-    }
-    __syncthreads();
-    {
-        uint32_t pb[RS_ITEMS];
-#pragma unroll
-        for (int it = 0; it < RS_ITEMS; ++it) pb[it] = wcnt[w][loc[it] & 255u];
-#pragma unroll
-        for (int it = 0; it < RS_ITEMS; ++it)
-            if (base + it * WAVE + l < n) skey[pb[it] + (loc[it] >> 8)] = k[it];
+        gofs[dd] = dbase + before - excl;
     }
     __syncthreads();
     const uint32_t tile_n = n - tile0 < (uint32_t)RS_TILE ? n - tile0 : (uint32_t)RS_TILE;
