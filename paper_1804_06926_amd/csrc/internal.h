@@ -10,6 +10,16 @@ namespace tcx {
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 
+// Global digit counts for the passes of a later sort, taken by a kernel that
+// reads every key anyway, so that those passes look back with no histogram
+// pass of their own: digit q (bits [shift + q * bits, min(that + bits, hi)),
+// q < n <= LB_MAX_MORE), count of value d in tot[q * 256 + d].
+constexpr int LB_MAX_MORE = 3;
+struct MoreTot {
+    uint32_t* tot;
+    int n, shift, bits, hi;
+};
+
 // ---- prims.hip
 void fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 void fill_u64(uint64_t* p, uint64_t v, size_t n, hipStream_t s);
@@ -28,17 +38,22 @@ size_t radix_temp_bytes(size_t cap);
 // use it where that order is free (the whole key sorted, or a grouping).
 // Sorts of 2^26 keys or more without payload take their passes after the first
 // in one kernel each (decoupled look-back, no histogram pass); a wait there
-// that runs out sets bit 1 of *err (nullptr: radix_err_word(temp, cap)).
-// Returns 1 when the sorted data ended up in the *_alt buffers.
+// that runs out sets bit 1 of *err (nullptr: radix_err_word(temp, cap)). With
+// totals_given, an earlier kernel has counted radix_sort_totals(...) and every
+// pass looks back. Returns 1 when the sorted data ended up in the *_alt buffers.
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted = false,
-                   bool first_unstable = false, uint32_t* err = nullptr);
+                   bool first_unstable = false, uint32_t* err = nullptr, bool totals_given = false);
 int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted = false,
                    bool first_unstable = false, uint32_t* err = nullptr);
 // The word in a sort's temporary (cap keys) where its look-back passes report
 // a wait that ran out (bit 1).
 uint32_t* radix_err_word(void* temp, size_t cap);
+// The counts a sort of cap keys of key_bytes bytes on [bit_lo, bit_hi), in
+// temporary temp, takes with totals_given; n == 0 when that sort cannot look
+// back on all its passes (then nothing needs counting).
+MoreTot radix_sort_totals(void* temp, size_t cap, int key_bytes, int bit_lo, int bit_hi);
 
 
 // Keys per tile of a sort of cap keys of key_bytes bytes (2048, 4096 or 8192;
@@ -66,8 +81,11 @@ struct RadixXf {
 // turns them into offsets in place); nullptr: the pass counts them itself.
 // stable: keys of equal digit keep their input order; otherwise their order
 // is arbitrary (a partition).
+// more (n > 0): the pass's histogram kernel also takes these global counts
+// (zeroing them first); ignored when the counts come from `counted`.
 void radix_pass_u64(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& xf,
-                    void* temp, hipStream_t s, uint32_t* counted, bool stable);
+                    void* temp, hipStream_t s, uint32_t* counted, bool stable,
+                    const MoreTot& more = MoreTot{nullptr, 0, 0, 0, 0});
 // Digit width of each pass of a sort over `bits` bits (equal widths, at most 8).
 int radix_digit_width(int bits);
 struct RadixDigit {

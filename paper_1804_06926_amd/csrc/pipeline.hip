@@ -1210,11 +1210,14 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     // only partitions; the later ones are stable.
     int alt;
     if (part) {
+        // the orienting pass's histogram also counts the digits of the passes after
+        // it, so that those look back with no histogram pass of their own
         const int w0 = radix_digit_width(nb);
+        const MoreTot rest = radix_sort_totals(radix_tmp, (size_t)E, 8, nb + w0, 2 * nb);
         radix_pass_u64(keysA, keysB, (size_t)E, nb, w0, RadixXf{RX_ORIENT, rank, n, nb, sentinel}, radix_tmp, s,
-                       nullptr, false);
+                       nullptr, false, rest);
         alt = 1 - radix_sort_u64(keysB, keysA, nullptr, nullptr, nullptr, (size_t)E, nb + w0, 2 * nb, radix_tmp, s,
-                                 false, false, &ctrl->err);
+                                 false, false, &ctrl->err, rest.n > 0);
     } else {
         alt = radix_sort_u64(keysA, keysB, nullptr, nullptr, nullptr, (size_t)E, nb, 2 * nb, radix_tmp, s, true,
                              true, &ctrl->err);

@@ -266,16 +266,9 @@ struct XfOrient {
     }
 };
 
-// Global digit counts for the later passes of a sort that look back (no
-// histogram pass of their own): the first pass, which reads every key anyway,
-// adds for digit q (bits [shift + q * bits, min(that + bits, hi)),
-// q < n <= LB_MAX_MORE) the count of each value into tot[q * 256 + d].
-constexpr int LB_MAX_MORE = 3;
-struct MoreTot {
-    uint32_t* tot;
-    int n, shift, bits, hi;
-};
-// The counts go to LDS counters cnt[(q * 256 + d) * copies + c], lane l adding
+// Global digit counts for the passes of a sort that look back (no histogram
+// pass of their own; MoreTot): a kernel that reads every key anyway (the
+// sort's first pass, or an earlier pass's histogram) adds them. The counts go to LDS counters cnt[(q * 256 + d) * copies + c], lane l adding
 // to copy c = l % copies: the later digits of rank keys are skewed (the hubs'
 // ranks), and the copies, in different banks, split the lanes of a wave that
 // share a digit over several addresses.
@@ -298,14 +291,21 @@ __device__ __forceinline__ void more_flush(const uint32_t* cnt, int copies, cons
 
 // Per-tile digit counts, written digit-major: hist[d * ntiles + tile]; digits of
 // the keys as xf transforms them.
-template <typename KeyT, int RS_ITEMS, typename XF = XfIdentity>
+// TOT: also the global counts of a later sort's digits (MoreTot), in four
+// copies of LDS counters.
+template <typename KeyT, int RS_ITEMS, typename XF = XfIdentity, bool TOT = false>
 __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ keys, const uint32_t* d_count,
                                                       uint32_t cap, int shift, uint32_t dmask,
                                                       uint32_t* __restrict__ hist,
-                                                      uint32_t ntiles, XF xf = XF()) {
+                                                      uint32_t ntiles, XF xf = XF(),
+                                                      MoreTot more = MoreTot{nullptr, 0, 0, 0, 0}) {
     constexpr int RS_TILE = RS_NT * RS_ITEMS, RS_WAVE_SPAN = WAVE * RS_ITEMS;   // keys per tile / per wave
+    constexpr int COPIES = 4;
     __shared__ uint32_t wcnt[RS_WAVES][256];
+    __shared__ uint32_t mcnt[TOT ? LB_MAX_MORE * 256 * COPIES : 1];
     for (int i = threadIdx.x; i < RS_WAVES * 256; i += RS_NT) (&wcnt[0][0])[i] = 0;
+    if (TOT)
+        for (int i = threadIdx.x; i < more.n * 256 * COPIES; i += RS_NT) mcnt[i] = 0;
     __syncthreads();
     const uint32_t n = rs_count(d_count, cap);
     const int w = wave_id(), l = lane_id();
@@ -320,8 +320,10 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ k
 #pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {   // every lane transforms (no branch around the gathers)
         const uint32_t i = base + it * WAVE + l;
-        const uint32_t dd = (uint32_t)(xf(kk[it]) >> shift) & dmask;
+        const KeyT t = xf(kk[it]);
+        const uint32_t dd = (uint32_t)(t >> shift) & dmask;
         dg[it] = i < n ? dd : 0u;
+        if (TOT && i < n) more_add(mcnt, COPIES, more, (uint64_t)t);
     }
     // counts only (no ranks): one LDS add per key into the wave's histogram, none
     // waited on. A wave whose valid keys all share one digit (sorted stretches:
@@ -348,6 +350,7 @@ __global__ __launch_bounds__(RS_NT) void k_radix_hist(const KeyT* __restrict__ k
 #pragma unroll
     for (int k = 0; k < RS_WAVES; ++k) t += wcnt[k][d];
     hist[(size_t)d * ntiles + blockIdx.x] = t;
+    if (TOT) more_flush(mcnt, COPIES, more);
 }
 
 // Block (d, s): exclusive scan, in place, of segment s (RS_ROW_SEG tile counts)
@@ -766,6 +769,15 @@ static int digit_width(int bits) {
     return (bits + passes - 1) / passes;
 }
 
+MoreTot radix_sort_totals(void* temp, size_t cap, int key_bytes, int bit_lo, int bit_hi) {
+    const int bits = bit_hi - bit_lo;
+    if (bits <= 0 || radix_tile_keys(cap, key_bytes) != (uint32_t)(RS_NT * RS_ITEMS_HUGE)) return {nullptr, 0, 0, 0, 0};
+    const int width = digit_width(bits);
+    const int np = (bits + width - 1) / width;
+    if (np > LB_MAX_MORE) return {nullptr, 0, 0, 0, 0};
+    return {(uint32_t*)((char*)temp + rs_lb_offset(cap)), np, bit_lo, width, bit_hi};
+}
+
 RadixDigit radix_first_digit(int bit_lo, int bit_hi) {
     const int bits = bit_hi - bit_lo;
     const int w = bits > 0 ? digit_width(bits) : 0;
@@ -809,16 +821,19 @@ static void scatter_launch(const KeyT* kin, const uint32_t* vin, KeyT* kout, uin
 template <typename KeyT, int RS_ITEMS>
 static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                       size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted,
-                      bool first_unstable, uint32_t* err) {
+                      bool first_unstable, uint32_t* err, bool totals_given) {
     const int width = digit_width(bit_hi - bit_lo);
     const int npasses = (bit_hi - bit_lo + width - 1) / width;
     // 8192-key tiles, keys only, several passes: the passes after the first look
-    // back (no histogram pass); the first pass counts their digits
+    // back (no histogram pass); the first pass counts their digits. With the
+    // totals given (counted by an earlier kernel), every pass looks back.
     constexpr bool HUGE_TILES = RS_ITEMS == RS_ITEMS_HUGE;
-    const bool lookback = HUGE_TILES && !vals && npasses >= 2 && npasses - 1 <= LB_MAX_MORE;
+    const bool all_lb = totals_given && HUGE_TILES && !vals && npasses <= LB_MAX_MORE;
+    const bool lookback = all_lb || (HUGE_TILES && !vals && npasses >= 2 && npasses - 1 <= LB_MAX_MORE);
     uint32_t* lb = (uint32_t*)((char*)temp + rs_lb_offset(cap));   // totals | tile counters | error word
     if (lookback) {
-        fill_u32(lb, 0u, LB_PASSES * 256 + LB_PASSES, s);
+        if (all_lb) fill_u32(lb + LB_PASSES * 256, 0u, LB_PASSES, s);   // the counters; the totals are given
+        else fill_u32(lb, 0u, LB_PASSES * 256 + LB_PASSES, s);
         if (!err) err = lb + LB_PASSES * 256 + LB_PASSES;
     }
     const uint32_t ntiles = (uint32_t)rs_ntiles(cap, RS_NT * RS_ITEMS);
@@ -836,7 +851,7 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
         const int dbits = bit_hi - shift < width ? bit_hi - shift : width;   // the last digit may be narrower
         const uint32_t dmask = (1u << dbits) - 1u;
         if constexpr (HUGE_TILES) {
-            if (lookback && passes > 0) {
+            if (lookback && (passes > 0 || all_lb)) {
                 uint64_t* status = (uint64_t*)temp;   // the count table's room: ntiles * 256 words fit
                 fill_u64(status, 0ull, (size_t)ntiles * 256, s);
                 constexpr int IT = RS_ITEMS / 2, NTS = 2 * RS_NT;
@@ -886,22 +901,23 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
 template <typename KeyT>
 static int radix_sort_any(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                           size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted,
-                          bool first_unstable, uint32_t* err) {
+                          bool first_unstable, uint32_t* err, bool totals_given) {
     if (cap == 0 || bit_hi <= bit_lo) return 0;
     const uint32_t tile = radix_tile_keys(cap, (int)sizeof(KeyT));
     if (tile == RS_NT * RS_ITEMS_HUGE)
         return radix_sort<KeyT, RS_ITEMS_HUGE>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                               first_counted, first_unstable, err);
+                                               first_counted, first_unstable, err, totals_given);
     if (tile == RS_NT * RS_ITEMS_LARGE)
         return radix_sort<KeyT, RS_ITEMS_LARGE>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                                first_counted, first_unstable, err);
+                                                first_counted, first_unstable, err, totals_given);
     return radix_sort<KeyT, RS_ITEMS_SMALL>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                            first_counted, first_unstable, err);
+                                            first_counted, first_unstable, err, totals_given);
 }
 
 template <int RS_ITEMS, typename XF>
 static void radix_pass_xf(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, XF xf,
-                          bool hist_xf, uint32_t* counted, bool stable, void* temp, hipStream_t s) {
+                          bool hist_xf, uint32_t* counted, bool stable, const MoreTot& more, void* temp,
+                          hipStream_t s) {
     const uint32_t ntiles = (uint32_t)rs_ntiles(cap, RS_NT * RS_ITEMS);
     uint32_t* hist = counted ? counted : (uint32_t*)temp;
     void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * (ntiles + 1), 256);
@@ -911,7 +927,11 @@ static void radix_pass_xf(const uint64_t* kin, uint64_t* kout, size_t cap, int s
     const uint32_t dmask = (1u << bits) - 1u;
     if (counted)   // the kernel that wrote or read the keys before has counted the digits
         ;
-    else if (hist_xf)   // the digit depends on the transformed key
+    else if (more.n > 0) {   // also the global counts for a later sort
+        fill_u32(more.tot, 0u, (size_t)more.n * 256, s);
+        hipLaunchKernelGGL((k_radix_hist<uint64_t, RS_ITEMS, XF, true>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr,
+                           (uint32_t)cap, shift, dmask, hist, ntiles, xf, more);
+    } else if (hist_xf)   // the digit depends on the transformed key
         hipLaunchKernelGGL((k_radix_hist<uint64_t, RS_ITEMS, XF>), dim3(ntiles), dim3(RS_NT), 0, s, kin, nullptr,
                            (uint32_t)cap, shift, dmask, hist, ntiles, xf);
     else
@@ -935,43 +955,43 @@ static void radix_pass_xf(const uint64_t* kin, uint64_t* kout, size_t cap, int s
 
 template <int RS_ITEMS>
 static void radix_pass_kind(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& x,
-                            uint32_t* counted, bool stable, void* temp, hipStream_t s) {
+                            uint32_t* counted, bool stable, const MoreTot& more, void* temp, hipStream_t s) {
     if (x.kind == RX_RANK_LOW)   // the digit lies in the untouched high half
-        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfRankLow{x.rank, x.n}, false, counted, stable, temp,
-                                s);
+        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfRankLow{x.rank, x.n}, false, counted, stable, more,
+                                temp, s);
     else if (x.kind == RX_ORIENT)
         radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfOrient{x.rank, x.n, x.nb, x.sentinel}, true, counted,
-                                stable, temp, s);
+                                stable, more, temp, s);
     else
-        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfIdentity(), false, counted, stable, temp, s);
+        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfIdentity(), false, counted, stable, more, temp, s);
 }
 
 void radix_pass_u64(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& xf,
-                    void* temp, hipStream_t s, uint32_t* counted, bool stable) {
+                    void* temp, hipStream_t s, uint32_t* counted, bool stable, const MoreTot& more) {
     if (cap == 0 || bits <= 0) return;
     const uint32_t tile = radix_tile_keys(cap, 8);
     if (tile == RS_NT * RS_ITEMS_HUGE)
-        radix_pass_kind<RS_ITEMS_HUGE>(kin, kout, cap, shift, bits, xf, counted, stable, temp, s);
+        radix_pass_kind<RS_ITEMS_HUGE>(kin, kout, cap, shift, bits, xf, counted, stable, more, temp, s);
     else if (tile == RS_NT * RS_ITEMS_LARGE)
-        radix_pass_kind<RS_ITEMS_LARGE>(kin, kout, cap, shift, bits, xf, counted, stable, temp, s);
+        radix_pass_kind<RS_ITEMS_LARGE>(kin, kout, cap, shift, bits, xf, counted, stable, more, temp, s);
     else
-        radix_pass_kind<RS_ITEMS_SMALL>(kin, kout, cap, shift, bits, xf, counted, stable, temp, s);
+        radix_pass_kind<RS_ITEMS_SMALL>(kin, kout, cap, shift, bits, xf, counted, stable, more, temp, s);
 }
 
 int radix_digit_width(int bits) { return digit_width(bits); }
 
 int radix_sort_u64(uint64_t* keys, uint64_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted,
-                   bool first_unstable, uint32_t* err) {
+                   bool first_unstable, uint32_t* err, bool totals_given) {
     return radix_sort_any<uint64_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                    first_counted, first_unstable, err);
+                                    first_counted, first_unstable, err, totals_given);
 }
 
 int radix_sort_u32(uint32_t* keys, uint32_t* keys_alt, uint32_t* vals, uint32_t* vals_alt, const uint32_t* d_count,
                    size_t cap, int bit_lo, int bit_hi, void* temp, hipStream_t s, bool first_counted,
                    bool first_unstable, uint32_t* err) {
     return radix_sort_any<uint32_t>(keys, keys_alt, vals, vals_alt, d_count, cap, bit_lo, bit_hi, temp, s,
-                                    first_counted, first_unstable, err);
+                                    first_counted, first_unstable, err, false);
 }
 
 }  // namespace tcx
