@@ -83,9 +83,14 @@ struct RadixXf {
 // is arbitrary (a partition).
 // more (n > 0): the pass's histogram kernel also takes these global counts
 // (zeroing them first); ignored when the counts come from `counted`.
+// lb_tot: the global counts of this pass's digit (256), taken by an earlier
+// kernel; with 8192-key tiles (2^26 keys or more) the pass then runs as one
+// look-back kernel with no histogram (a wait that runs out sets bit 1 of *err;
+// nullptr: radix_err_word(temp, cap)); otherwise it is ignored.
 void radix_pass_u64(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& xf,
                     void* temp, hipStream_t s, uint32_t* counted, bool stable,
-                    const MoreTot& more = MoreTot{nullptr, 0, 0, 0, 0});
+                    const MoreTot& more = MoreTot{nullptr, 0, 0, 0, 0}, const uint32_t* lb_tot = nullptr,
+                    uint32_t* err = nullptr);
 // Digit width of each pass of a sort over `bits` bits (equal widths, at most 8).
 int radix_digit_width(int bits);
 struct RadixDigit {

@@ -24,7 +24,7 @@ constexpr int NSTAGE = 12;
 
 struct Layout {
     size_t ctrl, deg, rank, inv, vbucket, vlist, tstart, off, inoff, rowend, pv;
-    size_t vkeysA, vkeysB, keysA, keysB, col, src, tiles, partial, bstart, isect_partials, scan_tmp, radix_tmp;
+    size_t vkeysA, vkeysB, keysA, keysB, col, src, tiles, partial, bstart, isect_partials, scan_tmp, lb_aux, radix_tmp;
     size_t tile_cap;
     size_t total;
 };

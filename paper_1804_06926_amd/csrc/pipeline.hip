@@ -61,19 +61,23 @@ __global__ __launch_bounds__(NT) void k_endpoints(const int2* __restrict__ edges
                                                   uint32_t sentinel, uint32_t* __restrict__ keys, Ctrl* ctrl,
                                                   uint32_t* __restrict__ nsent, uint32_t* __restrict__ counts,
                                                   uint32_t ntiles, uint32_t tile_keys, RadixDigit dg,
-                                                  uint32_t* __restrict__ pcounts, uint32_t pf, RadixDigit pdg) {
+                                                  uint32_t* __restrict__ pcounts, uint32_t pf, RadixDigit pdg,
+                                                  uint32_t* __restrict__ p2tot) {
     // tile t = endpoints [t * tile_keys, (t + 1) * tile_keys) = pairs [t * EPT, (t + 1) * EPT),
     // in rounds of NT * PER pairs; with counts set, the first digit of the endpoint sort is
     // counted per tile. With pcounts set, the digit pdg of the first id is counted too, per
     // tile of pf endpoint tiles: the first pass of the orientation's pair partition, whose
-    // tiles hold pf * EPT pairs.
+    // tiles hold pf * EPT pairs. With p2tot set, the same digit of the second id is counted
+    // over all pairs (added into p2tot[256]): the digit totals of that partition's second
+    // pass, which then takes its offsets by look-back.
     constexpr uint32_t PER = 4;
     const uint32_t EPT = tile_keys / 2;
     const uint32_t pntiles = (ntiles + pf - 1) / pf;
     __shared__ uint32_t red[NT / WAVE];
-    __shared__ TileCounts tc, tp;
+    __shared__ TileCounts tc, tp, tq;
     tc.clear();
     if (pcounts) tp.clear();
+    if (p2tot) tq.clear();
     __syncthreads();
     bool bad = false;
     uint32_t sent = 0;
@@ -102,11 +106,17 @@ __global__ __launch_bounds__(NT) void k_endpoints(const int2* __restrict__ edges
                 tc.add((b >> dg.shift) & dg.mask);
             }
             if (pcounts) tp.add(((uint32_t)e.x >> pdg.shift) & pdg.mask);
+            if (p2tot) tq.add(((uint32_t)e.y >> pdg.shift) & pdg.mask);
         }
       }
         if (counts) tc.flush(counts, ntiles, tile);
      }
         if (pcounts) tp.flush(pcounts, pntiles, pt);
+    }
+    if (p2tot) {
+        __syncthreads();
+        const uint32_t t = tq.w[0][threadIdx.x] + tq.w[1][threadIdx.x] + tq.w[2][threadIdx.x] + tq.w[3][threadIdx.x];
+        if (t) atomicAdd(&p2tot[threadIdx.x], t);
     }
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctrl->err, 1u);
     sent = wave_sum(sent);
@@ -962,6 +972,7 @@ Layout make_layout(int64_t E, int32_t n) {
     L.bstart = take(4 * ((1u << DEG_MAX_BUCKET_BITS) + 4));
     L.isect_partials = take(isect_partials_bytes());
     L.scan_tmp = take(scan_temp_bytes());
+    L.lb_aux = take(4 * 256);
     L.radix_tmp = take(radix_temp_bytes(2 * ee > nn ? 2 * ee : nn));
     L.total = o;
     return L;
@@ -1115,6 +1126,10 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
     const bool orient_part = vbits >= ORIENT_PART_MIN_BITS;
     uint32_t* p1_counts = nullptr;   // the orientation's first partition pass, counted by k_endpoints
     uint32_t p1_f = 1;
+    // and the digit totals of its second pass, which with 8192-key tiles (2^26 pairs or more)
+    // then looks back instead of running a histogram pass
+    uint32_t* p2_tot =
+        orient_part && radix_tile_keys((size_t)E, 8) == 8192u ? (uint32_t*)(ws + L.lb_aux) : nullptr;
     const int bw = vbits <= 20 ? (vbits < 12 ? vbits : 12) : (vbits <= 24 ? vbits - 8 : DEG_MAX_BW);
     const bool bucketed = vbits - bw <= DEG_MAX_BUCKET_BITS;
     {
@@ -1137,10 +1152,11 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         }
         const uint32_t p1_tiles = (ep_tiles + p1_f - 1) / p1_f;
         const unsigned eg = p1_tiles < DEG_EP_BLOCKS ? p1_tiles : DEG_EP_BLOCKS;
+        if (p2_tot) fill_u32(p2_tot, 0u, 256, s);
         hipLaunchKernelGGL(k_endpoints, dim3(eg), dim3(NT), 0, s, edges, (uint64_t)E, n,
                            bucketed ? (uint32_t)(n - 1) : (uint32_t)n, ep, ctrl, partial,
                            ep_sort ? radix_first_counts(radix_tmp) : nullptr, ep_tiles, ep_tile, ep_dg, p1_counts,
-                           p1_f, RadixDigit{vbits - ORIENT_PART_BITS, (1u << ORIENT_PART_BITS) - 1u});
+                           p1_f, RadixDigit{vbits - ORIENT_PART_BITS, (1u << ORIENT_PART_BITS) - 1u}, p2_tot);
         if (bucketed) {
             // partition by bits [bw, vbits), then count per bucket
             const uint32_t nb = 1u << (vbits - bw);
@@ -1193,7 +1209,7 @@ hipError_t run_pipeline(const RunArgs& r, RunResult* out) {
         radix_pass_u64((const uint64_t*)edges, keysB, (size_t)E, vbits - ob, ob, RadixXf{RX_NONE, nullptr, n, 0, 0},
                        radix_tmp, s, p1_counts, false);
         radix_pass_u64(keysB, keysA, (size_t)E, 32 + vbits - ob, ob, RadixXf{RX_RANK_LOW, rank, n, 0, 0}, radix_tmp,
-                       s, nullptr, false);
+                       s, nullptr, false, MoreTot{nullptr, 0, 0, 0, 0}, p2_tot, &ctrl->err);
     } else if (e_tile % (16 * NT) == 0)
         hipLaunchKernelGGL(k_orient<16>, dim3(e_tiles < 16384u ? e_tiles : 16384u), dim3(NT), 0, s, edges,
                            (uint64_t)E, n, rank, nb, sentinel, keysA, radix_first_counts(radix_tmp), e_tiles, e_tile,

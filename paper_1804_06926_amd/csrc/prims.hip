@@ -268,10 +268,11 @@ struct XfOrient {
 
 // Global digit counts for the passes of a sort that look back (no histogram
 // pass of their own; MoreTot): a kernel that reads every key anyway (the
-// sort's first pass, or an earlier pass's histogram) adds them. The counts go to LDS counters cnt[(q * 256 + d) * copies + c], lane l adding
-// to copy c = l % copies: the later digits of rank keys are skewed (the hubs'
-// ranks), and the copies, in different banks, split the lanes of a wave that
-// share a digit over several addresses.
+// sort's first pass, or an earlier pass's histogram) adds them. The counts go
+// to LDS counters cnt[(q * 256 + d) * copies + c], lane l adding to copy
+// c = l % copies: the later digits of rank keys are skewed (the hubs' ranks),
+// and the copies, in different banks, split the lanes of a wave that share a
+// digit over several addresses.
 __device__ __forceinline__ void more_add(uint32_t* cnt, int copies, const MoreTot& more, uint64_t key) {
     const uint32_t c = (uint32_t)lane_id() & (uint32_t)(copies - 1);
     for (int q = 0; q < more.n; ++q) {
@@ -600,11 +601,12 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter(const KeyT* __restrict__ 
 // are bounded: a wait that runs past LB_SPIN polls sets bit 1 of *err and the
 // keys go out clamped in place (wrong order, no access out of bounds).
 constexpr uint32_t LB_SPIN = 1u << 16;
-template <typename KeyT, int RS_ITEMS, int NT_, int RANK>
+template <typename KeyT, int RS_ITEMS, int NT_, int RANK, typename XF = XfIdentity>
 __global__ __launch_bounds__(NT_) void k_radix_scatter_lb(const KeyT* __restrict__ kin, KeyT* __restrict__ kout,
                                                             const uint32_t* d_count, uint32_t cap, int shift,
                                                             uint32_t dmask, const uint32_t* __restrict__ digit_tot,
-                                                            uint64_t* status, uint32_t* tile_ctr, uint32_t* err) {
+                                                            uint64_t* status, uint32_t* tile_ctr, uint32_t* err,
+                                                            XF xf = XF()) {
     constexpr int NW = NT_ / WAVE;
     constexpr int RS_TILE = NT_ * RS_ITEMS, RS_WAVE_SPAN = WAVE * RS_ITEMS;
     static_assert(NT_ >= 256, "a thread per digit");
@@ -641,10 +643,19 @@ __global__ __launch_bounds__(NT_) void k_radix_scatter_lb(const KeyT* __restrict
     // keys with a smaller digit (the same for every tile), while the keys load
     const uint32_t dbase = block_exclusive_scan<NT_>(own ? digit_tot[dd] : 0u, scratch);
 #pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {   // no branch around a transform's gathers
+        const KeyT t = xf(k[it]);
+        k[it] = base + it * WAVE + l < n ? t : k[it];
+    }
+#pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
         const uint32_t i = base + it * WAVE + l;
         const bool valid = i < n;
         const uint32_t d = (uint32_t)(k[it] >> shift) & dmask;
+        if (RANK == RANK_ATOMIC) {   // a partition: ranks from LDS adds
+            loc[it] = d | (atomicAdd(&wcnt[w][valid ? d : 0u], valid ? 1u : 0u) << 8);
+            continue;
+        }
         uint64_t peers;
         if (RANK == RANK_MATCH) {
             peers = match_digit8(d, __ballot(valid));
@@ -916,9 +927,29 @@ static int radix_sort_any(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* 
 
 template <int RS_ITEMS, typename XF>
 static void radix_pass_xf(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, XF xf,
-                          bool hist_xf, uint32_t* counted, bool stable, const MoreTot& more, void* temp,
-                          hipStream_t s) {
+                          bool hist_xf, uint32_t* counted, bool stable, const MoreTot& more,
+                          const uint32_t* lb_tot, uint32_t* err, void* temp, hipStream_t s) {
     const uint32_t ntiles = (uint32_t)rs_ntiles(cap, RS_NT * RS_ITEMS);
+    if constexpr (RS_ITEMS == RS_ITEMS_HUGE) {
+        if (lb_tot) {   // the digit totals are given: one look-back kernel, no histogram
+            uint32_t* lb = (uint32_t*)((char*)temp + rs_lb_offset(cap));
+            uint32_t* ctr = lb + LB_PASSES * 256 + (LB_PASSES - 1);   // the last pass slot's counter
+            if (!err) err = lb + LB_PASSES * 256 + LB_PASSES;
+            uint64_t* status = (uint64_t*)temp;
+            fill_u64(status, 0ull, (size_t)ntiles * 256, s);
+            fill_u32(ctr, 0u, 1, s);
+            constexpr int IT = RS_ITEMS / 2, NTS = 2 * RS_NT;
+            const uint32_t dmask = (1u << bits) - 1u;
+            if (stable)
+                hipLaunchKernelGGL((k_radix_scatter_lb<uint64_t, IT, NTS, rank_for<uint64_t>(true), XF>), dim3(ntiles),
+                                   dim3(NTS), 0, s, kin, kout, nullptr, (uint32_t)cap, shift, dmask, lb_tot, status,
+                                   ctr, err, xf);
+            else
+                hipLaunchKernelGGL((k_radix_scatter_lb<uint64_t, IT, NTS, RANK_ATOMIC, XF>), dim3(ntiles), dim3(NTS), 0,
+                                   s, kin, kout, nullptr, (uint32_t)cap, shift, dmask, lb_tot, status, ctr, err, xf);
+            return;
+        }
+    }
     uint32_t* hist = counted ? counted : (uint32_t*)temp;
     void* scan_tmp = (char*)temp + align_up(sizeof(uint32_t) * 256 * (ntiles + 1), 256);
     uint32_t* digit_tot = (uint32_t*)scan_tmp;
@@ -955,27 +986,30 @@ static void radix_pass_xf(const uint64_t* kin, uint64_t* kout, size_t cap, int s
 
 template <int RS_ITEMS>
 static void radix_pass_kind(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& x,
-                            uint32_t* counted, bool stable, const MoreTot& more, void* temp, hipStream_t s) {
+                            uint32_t* counted, bool stable, const MoreTot& more, const uint32_t* lb_tot,
+                            uint32_t* err, void* temp, hipStream_t s) {
     if (x.kind == RX_RANK_LOW)   // the digit lies in the untouched high half
         radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfRankLow{x.rank, x.n}, false, counted, stable, more,
-                                temp, s);
+                                lb_tot, err, temp, s);
     else if (x.kind == RX_ORIENT)
         radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfOrient{x.rank, x.n, x.nb, x.sentinel}, true, counted,
-                                stable, more, temp, s);
+                                stable, more, lb_tot, err, temp, s);
     else
-        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfIdentity(), false, counted, stable, more, temp, s);
+        radix_pass_xf<RS_ITEMS>(kin, kout, cap, shift, bits, XfIdentity(), false, counted, stable, more, lb_tot, err,
+                                temp, s);
 }
 
 void radix_pass_u64(const uint64_t* kin, uint64_t* kout, size_t cap, int shift, int bits, const RadixXf& xf,
-                    void* temp, hipStream_t s, uint32_t* counted, bool stable, const MoreTot& more) {
+                    void* temp, hipStream_t s, uint32_t* counted, bool stable, const MoreTot& more,
+                    const uint32_t* lb_tot, uint32_t* err) {
     if (cap == 0 || bits <= 0) return;
     const uint32_t tile = radix_tile_keys(cap, 8);
     if (tile == RS_NT * RS_ITEMS_HUGE)
-        radix_pass_kind<RS_ITEMS_HUGE>(kin, kout, cap, shift, bits, xf, counted, stable, more, temp, s);
+        radix_pass_kind<RS_ITEMS_HUGE>(kin, kout, cap, shift, bits, xf, counted, stable, more, lb_tot, err, temp, s);
     else if (tile == RS_NT * RS_ITEMS_LARGE)
-        radix_pass_kind<RS_ITEMS_LARGE>(kin, kout, cap, shift, bits, xf, counted, stable, more, temp, s);
+        radix_pass_kind<RS_ITEMS_LARGE>(kin, kout, cap, shift, bits, xf, counted, stable, more, lb_tot, err, temp, s);
     else
-        radix_pass_kind<RS_ITEMS_SMALL>(kin, kout, cap, shift, bits, xf, counted, stable, more, temp, s);
+        radix_pass_kind<RS_ITEMS_SMALL>(kin, kout, cap, shift, bits, xf, counted, stable, more, lb_tot, err, temp, s);
 }
 
 int radix_digit_width(int bits) { return digit_width(bits); }
