@@ -36,7 +36,7 @@ size_t radix_temp_bytes(size_t cap);
 // only partitions (ranks by LDS atomics): the keys come out sorted on
 // [bit_lo, bit_hi), but keys equal on those bits in no particular order, so
 // use it where that order is free (the whole key sorted, or a grouping).
-// Sorts of 2^26 keys or more without payload take their passes after the first
+// 64-bit sorts of 2^26 keys or more without payload take their passes after the first
 // in one kernel each (decoupled look-back, no histogram pass); a wait there
 // that runs out sets bit 1 of *err (nullptr: radix_err_word(temp, cap)). With
 // totals_given, an earlier kernel has counted radix_sort_totals(...) and every

@@ -835,12 +835,14 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
                       bool first_unstable, uint32_t* err, bool totals_given) {
     const int width = digit_width(bit_hi - bit_lo);
     const int npasses = (bit_hi - bit_lo + width - 1) / width;
-    // 8192-key tiles, keys only, several passes: the passes after the first look
-    // back (no histogram pass); the first pass counts their digits. With the
-    // totals given (counted by an earlier kernel), every pass looks back.
-    constexpr bool HUGE_TILES = RS_ITEMS == RS_ITEMS_HUGE;
-    const bool all_lb = totals_given && HUGE_TILES && !vals && npasses <= LB_MAX_MORE;
-    const bool lookback = all_lb || (HUGE_TILES && !vals && npasses >= 2 && npasses - 1 <= LB_MAX_MORE);
+    // 8192-key tiles, 64-bit keys only, several passes: the passes after the first
+    // look back (no histogram pass); the first pass counts their digits. With the
+    // totals given (counted by an earlier kernel), every pass looks back. (The one
+    // 32-bit sort this large with several passes, the endpoint sort of ids wider
+    // than 27 bits, keeps its histogram passes.)
+    constexpr bool LB_TILES = RS_ITEMS == RS_ITEMS_HUGE && sizeof(KeyT) == 8;
+    const bool all_lb = totals_given && LB_TILES && !vals && npasses <= LB_MAX_MORE;
+    const bool lookback = all_lb || (LB_TILES && !vals && npasses >= 2 && npasses - 1 <= LB_MAX_MORE);
     uint32_t* lb = (uint32_t*)((char*)temp + rs_lb_offset(cap));   // totals | tile counters | error word
     if (lookback) {
         if (all_lb) fill_u32(lb + LB_PASSES * 256, 0u, LB_PASSES, s);   // the counters; the totals are given
@@ -861,7 +863,7 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
     for (int shift = bit_lo; shift < bit_hi; shift += width, ++passes) {
         const int dbits = bit_hi - shift < width ? bit_hi - shift : width;   // the last digit may be narrower
         const uint32_t dmask = (1u << dbits) - 1u;
-        if constexpr (HUGE_TILES) {
+        if constexpr (LB_TILES) {
             if (lookback && (passes > 0 || all_lb)) {
                 uint64_t* status = (uint64_t*)temp;   // the count table's room: ntiles * 256 words fit
                 fill_u64(status, 0ull, (size_t)ntiles * 256, s);
@@ -880,7 +882,7 @@ static int radix_sort(KeyT* keys, KeyT* keys_alt, uint32_t* vals, uint32_t* vals
         if (nseg > 1)
             hipLaunchKernelGGL(k_radix_rowfix, dim3(256, nseg), dim3(RS_NT), 0, s, hist, ntiles, seg_tot, digit_tot);
         bool done = false;
-        if constexpr (HUGE_TILES) {
+        if constexpr (LB_TILES) {
             if (lookback) {   // the first pass: 8192-key tiles, keys only
                 constexpr int IT = RS_ITEMS / 2, NTS = 2 * RS_NT;
                 const MoreTot more{lb + 256, npasses - 1, shift + width, width, bit_hi};
